@@ -1,0 +1,212 @@
+"""Workload builders: the paper's 2D piston, 1D-reducible parallel plates and
+the 3D sphere above an indented plate, at the sizes the benchmarks use.
+
+Every builder returns a :class:`Workload` holding rasterized per-component
+material ids.  Geometry follows the paper's examples (Sec. III A piston of
+Fig. 1/3; Sec. III E sphere over an indented plate, Fig. 9) with the sizes of
+the benchmark configurations:
+
+* piston: two PEC blocks 1.0 x 0.5 separated by a gap a = 1.0, between
+  sidewall slabs; ``h`` is the total vertical clearance (h/2 above and below
+  each block).  The stress surface S is the right block grown by a margin of
+  min(2, floor(g/2)) pixels, g being the smallest block-to-object gap.
+* sphere-plate: a PEC plate whose top face carries a hemispherical
+  indentation, a dielectric sphere above it, immersed in a fluid; periodic
+  x/y, PML along z.
+"""
+from __future__ import annotations
+
+import math
+from typing import List
+
+import numpy as np
+
+from .geometry import PEC, PMC, Box, Sphere, Workload, rasterize
+
+BIG = 1e30
+
+
+def _margin(min_gap_px: int) -> int:
+    return int(min(2, min_gap_px // 2))
+
+
+def piston2d(nx: int, ny: int, slab_px: int, block_w: int, block_h: int, gap: int,
+             block_y0: int, res: float, sidewall: str = "pec", n_harm: int = 16,
+             **opts) -> Workload:
+    """2D piston on an nx x ny grid (pixel units).
+
+    Sidewall slabs occupy y in [0, slab_px] and [ny - slab_px, ny]; blocks
+    are PEC, the left one ending at x = (nx - gap)//2 and the right one
+    starting gap pixels later; both span y in [block_y0, block_y0 + block_h].
+    ``sidewall`` is "pec", "pmc" or "mu5" (a magnetic slab with mu = 5).
+    """
+    eps = [1.0, PEC, 1.0]
+    mu = [1.0, 1.0, 1.0]
+    side_id = 2
+    if sidewall == "pec":
+        side_id = 1
+    elif sidewall == "pmc":
+        mu[2] = PMC
+    elif sidewall == "mu5":
+        mu[2] = 5.0
+    else:
+        raise ValueError(sidewall)
+    left_hi = (nx - gap) // 2
+    left_lo = left_hi - block_w
+    right_lo = left_hi + gap
+    right_hi = right_lo + block_w
+    y0, y1 = block_y0, block_y0 + block_h
+    prims = [
+        Box((-BIG, -BIG, -BIG), (BIG, slab_px, BIG), side_id),
+        Box((-BIG, ny - slab_px, -BIG), (BIG, BIG, BIG), side_id),
+        Box((left_lo, y0, -BIG), (left_hi, y1, BIG), 1),
+        Box((right_lo, y0, -BIG), (right_hi, y1, BIG), 1),
+    ]
+    ids = rasterize((nx, ny, 1), prims)
+    gap_below = y0 - slab_px
+    gap_above = (ny - slab_px) - y1
+    gap_right = nx - right_hi
+    m = _margin(min(gap, gap_below, gap_above, gap_right))
+    kw = dict(sigma=1.0, courant=0.5, n_steps=1000, pol="TM", kernel="zinv2d",
+              precision="fp64")
+    kw.update(opts)
+    return Workload(
+        name=kw.pop("name", f"piston2d_{nx}x{ny}"), ndim=2, shape=(nx, ny, 1), res=float(res),
+        bc=("pec", "pec", "periodic"), pml_cells=(0, 0, 0), eps=eps, mu=mu,
+        comp_ids=ids, s_lo=(right_lo - m, y0 - m, 0), s_hi=(right_hi + m, y1 + m, 1),
+        n_harm=int(n_harm), force_axis=0,
+        meta=dict(margin=m, blocks=((left_lo, left_hi), (right_lo, right_hi)), block_y=(y0, y1),
+                  slab_px=slab_px, sidewall=sidewall),
+        **kw,
+    )
+
+
+def piston2d_units(res: int, width_u: float, height_u: float, h_u: float,
+                   sidewall: str = "pec", **kw) -> Workload:
+    """Piston with slabs filling everything outside the interior strip of
+    height block_h + h, centred vertically (the reading used for the 2D
+    benchmark configurations)."""
+    nx = int(round(width_u * res))
+    ny = int(round(height_u * res))
+    block_w = int(round(1.0 * res))
+    block_h = int(round(0.5 * res))
+    gap = int(round(1.0 * res))
+    h_px = int(round(h_u * res))
+    interior = block_h + h_px
+    slab = (ny - interior) // 2
+    y0 = slab + h_px // 2
+    return piston2d(nx, ny, slab, block_w, block_h, gap, y0, res, sidewall=sidewall, **kw)
+
+
+def c1_piston_tm_fp64(**over) -> Workload:
+    """2D TM, FP64: res 20, 80x40, h = 0.5, 16 harmonics, 2000 steps."""
+    kw = dict(pol="TM", precision="fp64", n_steps=2000, kernel="zinv2d", n_harm=16,
+              name="c1_piston_tm_fp64_80x40")
+    kw.update(over)
+    return piston2d_units(20, 4.0, 2.0, 0.5, **kw)
+
+
+def c2_piston_tetm_fp32(**over) -> Workload:
+    """2D TE+TM, FP32 fields: res 40, 400x200, h = 0.5, 40 harmonics, 10000 steps."""
+    kw = dict(pol="TM+TE", precision="fp32", n_steps=10000, kernel="zinv2d", n_harm=40,
+              name="c2_piston_tetm_fp32_400x200")
+    kw.update(over)
+    return piston2d_units(40, 10.0, 5.0, 0.5, **kw)
+
+
+def c3_uneven_set(sidewall: str = "pec", n_inst: int = 24, res: int = 40, **over) -> List[Workload]:
+    """24 pistons with total clearance h in linspace(0.1, 2.0), grid height
+    round(res*(2+h)) (84..160 px at res 40), 0.75-unit sidewall slabs."""
+    out = []
+    for h in np.linspace(0.1, 2.0, n_inst):
+        ny = int(round(res * (2.0 + h)))
+        slab = int(round(0.75 * res))
+        block_h = int(round(0.5 * res))
+        clear = ny - 2 * slab - block_h
+        y0 = slab + clear // 2
+        kw = dict(pol="TM+TE", precision="fp32", n_steps=10000, kernel="zinv2d", n_harm=40,
+                  name=f"c3_{sidewall}_h{h:.3f}_400x{ny}")
+        kw.update(over)
+        w = piston2d(int(round(10 * res)), ny, slab, int(round(res)), block_h, int(round(res)), y0,
+                     res, sidewall=sidewall, **kw)
+        w.meta["h"] = float(h)
+        out.append(w)
+    return out
+
+
+def parallel_plates_1d(res: int, a_u: float, d_u: float, b_u: float, margin: int = 2,
+                       ny: int = 1, **opts) -> Workload:
+    """A PEC slab of thickness d between PEC walls at distances a (left) and
+    b (right), translation invariant along y (periodic, ny cells).  S is two
+    full-width lines, one in each gap."""
+    a = int(round(a_u * res))
+    d = int(round(d_u * res))
+    b = int(round(b_u * res))
+    nx = a + d + b
+    eps = [1.0, PEC]
+    mu = [1.0, 1.0]
+    prims = [Box((a, -BIG, -BIG), (a + d, BIG, BIG), 1)]
+    ids = rasterize((nx, ny, 1), prims)
+    kw = dict(sigma=1.0, courant=0.5, n_steps=2000, pol="TM", kernel="zinv2d",
+              precision="fp64")
+    kw.update(opts)
+    return Workload(
+        name=kw.pop("name", f"plates_{nx}x{ny}"), ndim=2, shape=(nx, ny, 1), res=float(res),
+        bc=("pec", "periodic", "periodic"), pml_cells=(0, 0, 0), eps=eps, mu=mu, comp_ids=ids,
+        s_lo=(a - margin, 0, 0), s_hi=(a + d + margin, ny, 1), n_harm=max(1, ny), force_axis=0,
+        meta=dict(a_px=a, d_px=d, b_px=b),
+        **kw,
+    )
+
+
+def sphere_plate3d(n: int, h_u: float, eps_sphere: float = 2.1, eps_fluid: float = 1.8,
+                   pml: int = 16, n_harm: int = 8, margin: int = 2, r_u: float = 0.5,
+                   R_u: float = 1.0, plate_u: float = 1.5, dx_u: float = 0.0, **opts) -> Workload:
+    """Sphere (radius r) of eps_sphere in a fluid above a PEC plate whose top
+    (at z = plate_u) carries a hemispherical indentation of radius R centred
+    on the x/y axis.  The cubic cell spans 4.0 units (res = n/4), periodic in
+    x/y with PML at both z ends.  h is the gap between the sphere's bottom
+    and the bottom of the indentation; dx shifts the sphere along x."""
+    res = n / 4.0
+    c = n / 2.0
+    top = plate_u * res
+    zc = (plate_u - R_u + h_u + r_u) * res
+    xc = c + dx_u * res
+    r = r_u * res
+    eps = [eps_fluid, PEC, eps_sphere]
+    mu = [1.0, 1.0, 1.0]
+    prims = [
+        Box((-BIG, -BIG, -BIG), (BIG, BIG, top), 1),
+        Sphere((c, c, top), R_u * res, 0),
+        Sphere((xc, c, zc), r, 2),
+    ]
+    ids = rasterize((n, n, n), prims)
+    lo = (int(math.floor(xc - r)) - margin, int(math.floor(c - r)) - margin, int(math.floor(zc - r)) - margin)
+    hi = (int(math.ceil(xc + r)) + margin, int(math.ceil(c + r)) + margin, int(math.ceil(zc + r)) + margin)
+    kw = dict(sigma=1.0, courant=0.5, n_steps=6000, pol="3D", kernel="general", precision="fp32")
+    kw.update(opts)
+    return Workload(
+        name=kw.pop("name", f"sphere_plate_{n}^3_h{h_u:.2f}"), ndim=3, shape=(n, n, n), res=float(res),
+        bc=("periodic", "periodic", "pml"), pml_cells=(0, 0, pml), eps=eps, mu=mu, comp_ids=ids,
+        s_lo=lo, s_hi=hi, n_harm=int(n_harm), force_axis=2,
+        meta=dict(h=h_u, center=(xc, c, zc), r=r),
+        **kw,
+    )
+
+
+def c4_sphere_plate(**over) -> Workload:
+    """3D FP32: 192^3, res 48, sphere r=0.5 eps 2.1 in fluid eps 1.8 at
+    gap 0.45 over an indented PEC plate; 8x8 harmonics; 6000 steps."""
+    kw = dict(name="c4_sphere_plate_192^3")
+    kw.update(over)
+    return sphere_plate3d(192, 0.45, **kw)
+
+
+def small_cases():
+    """Small workloads the oracle finishes in seconds (parity test sizes)."""
+    return {
+        "piston_tm_small": piston2d_units(10, 4.0, 2.0, 0.6, pol="TM", n_steps=300, n_harm=6,
+                                          name="piston_tm_small"),
+        "piston_te_small": piston2d_units(10, 4.0, 2.0, 0.6, pol="TE", n_steps=300, n_harm=6,
+                                          name="piston_te_small"),
+    }
