@@ -1,0 +1,219 @@
+/*
+ * casimir_fdtd.h - C ABI of the MI355X (gfx950) time-domain Casimir-force
+ * library.
+ *
+ * The library computes the Casimir force on an object by the time-domain
+ * stress-tensor method of McCauley, Rodriguez, Joannopoulos and Johnson,
+ * "Casimir forces in the time domain: Applications":
+ *
+ *   - one Yee-grid FDTD run per harmonic current source on the stress
+ *     surface S (Sec. II, the harmonic expansion of the surface delta
+ *     function; Sec. III A, the per-face cosine basis f_n),
+ *   - with a uniform artificial conductivity sigma that makes the response
+ *     decay (Sec. II),
+ *   - recording the stress-tensor field correlations Gamma on S at every
+ *     step and integrating them in time against the kernel g(-t)
+ *     (Sec. II, eq. time-force; Appendix A, the closed forms of g).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns cf_status (CF_OK == 0) and never throws or
+ *     aborts on bad input; cf_last_error() returns a thread-local message
+ *     describing the most recent failure on the calling thread.
+ *   - Units: hbar = c = eps_0 = mu_0 = 1.  Lengths are in units of the
+ *     geometry (1/res per cell); time step dt = courant / res.
+ *   - Arrays passed in are host memory, read during the call and copied;
+ *     the caller keeps ownership.  Output arrays are host memory allocated
+ *     by the caller, with their lengths passed; a length shorter than
+ *     required gives CF_E_ARG and writes nothing.
+ *   - Device memory: a solve needs cf_workspace_size() bytes of device
+ *     memory.  The caller may pass its own allocation (e.g. a PyTorch tensor)
+ *     as `workspace`; with workspace == NULL the library allocates and frees
+ *     it itself.  Work is issued on opts->stream (a hipStream_t; NULL = the
+ *     default stream) and the call returns after the results are on the
+ *     host.
+ *   - Results are deterministic: identical inputs and options give
+ *     bitwise-identical outputs.
+ */
+#ifndef CASIMIR_FDTD_H
+#define CASIMIR_FDTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CF_OK = 0,
+    CF_E_ARG = 1,         /* invalid argument, shape or length                  */
+    CF_E_CFL = 2,         /* courant number above the Yee stability limit       */
+    CF_E_SURFACE = 3,     /* S leaves the grid or does not lie in one uniform medium */
+    CF_E_BUDGET = 4,      /* workspace smaller than required / budget exceeded  */
+    CF_E_NONFINITE = 5,   /* a force accumulator became NaN or infinite          */
+    CF_E_DEVICE = 6,      /* HIP runtime error                                   */
+    CF_E_CANCELLED = 7,   /* request cancelled before completion                 */
+    CF_E_UNSUPPORTED = 8  /* option combination not implemented                  */
+} cf_status;
+
+/* Boundary per axis (both ends of the axis). */
+enum { CF_BC_PEC = 0, CF_BC_PERIODIC = 1, CF_BC_PML = 2 };
+/* Polarizations: 2D runs take CF_POL_TM, CF_POL_TE or both OR-ed; 3D runs CF_POL_3D. */
+enum { CF_POL_TM = 1, CF_POL_TE = 2, CF_POL_3D = 4 };
+/* Time kernel (Appendix A): general, or the 2D cross-section of a z-invariant
+ * perfect-conductor system (Appendix A.2). */
+enum { CF_KERNEL_GENERAL = 0, CF_KERNEL_ZINV2D = 1 };
+/* Field precision.  The surface projection and the g-weighted time
+ * accumulation are always FP64 (compensated). */
+enum { CF_FP64 = 0, CF_FP32 = 1 };
+/* Execution path: all channels advanced together (batched), or one channel
+ * at a time with three kernel launches per time step (plain). */
+enum { CF_PATH_BATCHED = 0, CF_PATH_PLAIN = 1 };
+
+/* Component order of every per-component array: Ex, Ey, Ez, Hx, Hy, Hz. */
+enum { CF_EX = 0, CF_EY, CF_EZ, CF_HX, CF_HY, CF_HZ };
+
+typedef struct cf_grid {
+    int ndim;          /* 2 or 3                                                   */
+    int n[3];          /* cells nx, ny, nz (nz == 1 when ndim == 2)               */
+    double res;        /* cells per unit length                                    */
+    int bc[3];         /* CF_BC_* per axis; 2D problems ignore bc[2]               */
+    int pml_cells[3];  /* PML thickness in cells at each end of a CF_BC_PML axis   */
+} cf_grid;
+
+/*
+ * Materials (Sec. III A uses PEC (eps = -inf) and PMC (mu = -inf) walls;
+ * Sec. III E uses dielectrics).  comp_id[c] is a host array of
+ * n[2]*n[1]*n[0] bytes (index (k*ny + j)*nx + i) giving the material of Yee
+ * component c at cell (i, j, k); component c of a cell sits at the standard
+ * Yee position (E_a half a cell along a, H_a half a cell along both other
+ * axes).  NULL means id 0 everywhere.  eps[id] == -INFINITY marks a perfect
+ * electric conductor (E held at 0), mu[id] == -INFINITY a perfect magnetic
+ * conductor (H held at 0).  n_materials <= 254.
+ */
+typedef struct cf_materials {
+    int n_materials;
+    const double* eps;
+    const double* mu;
+    const uint8_t* comp_id[6];
+} cf_materials;
+
+/*
+ * Stress surface S (Sec. III: a rectangle / box with a cosine basis on each
+ * face).  lo/hi are integer cell coordinates of the box corners.  Each face
+ * is sampled at cell midpoints along its tangential axes; an axis spanned
+ * completely while periodic has no faces.  n_harm cosine harmonics are used
+ * per tangential axis (clamped per face to its sample count: the discrete
+ * cosine basis has no more orthonormal members).  S must lie at least one
+ * cell inside one uniform, non-conducting medium, else CF_E_SURFACE.
+ */
+typedef struct cf_surface {
+    int lo[3];
+    int hi[3];
+    int n_harm;
+    int force_axis;    /* 0, 1 or 2 */
+} cf_surface;
+
+/* CF_FLAG_KEEP_GAMMA keeps Gamma_c(t_m) for the gamma/trace outputs.
+ * CF_FLAG_TIME_STENCIL brackets sampled launches of the field-update
+ * kernel with HIP events on the solve's stream and reports their average
+ * duration (cf_result.stencil_ms_avg); the stepping loop is otherwise
+ * unchanged. */
+enum { CF_FLAG_KEEP_GAMMA = 1, CF_FLAG_TIME_STENCIL = 2 };
+
+typedef struct cf_opts {
+    double sigma;       /* uniform conductivity (decay rate), >= 0            */
+    double courant;     /* dt * res; must be below 1/sqrt(ndim) / max speed   */
+    int n_steps;        /* time steps T (samples at t_m = m dt, m = 1..T)     */
+    int pol;            /* CF_POL_* (bitmask for 2D)                          */
+    int kernel;         /* CF_KERNEL_*                                        */
+    int precision;      /* CF_FP64 or CF_FP32                                 */
+    int path;           /* CF_PATH_*                                          */
+    int flags;          /* CF_FLAG_*                                          */
+    const int* channel_subset;  /* optional: run only these channel indices  */
+    int n_subset;               /* length of channel_subset (0 = all)         */
+    void* stream;       /* hipStream_t, or NULL for the default stream        */
+} cf_opts;
+
+typedef struct cf_info {
+    int n_channels;        /* channels of the full problem                     */
+    int n_faces;
+    int per_harmonic_len;  /* entries of cf_result.per_harmonic                */
+    int n_comp;            /* field components per channel (3 in 2D, 6 in 3D) */
+    size_t workspace_bytes;
+    double eps_s, mu_s;    /* medium S lies in                                 */
+} cf_info;
+
+/*
+ * Outputs.  force is F along force_axis (per unit z-length for 2D runs).
+ * per_harmonic[k] is the contribution of harmonic label k (n in 2D,
+ * m*n_harm + n in 3D; Fig. 5), per_face[f] of face f = 2*axis + (side > 0),
+ * per_channel[c] = sum_m dt K(t_m) Gamma_c(t_m) (unsigned, without 1/pi),
+ * gamma[m*C + c] = Gamma_c(t_{m+1}) (needs CF_FLAG_KEEP_GAMMA) and
+ * trace[m] = F after m+1 steps (Fig. 12; needs CF_FLAG_KEEP_GAMMA).
+ * Optional arrays may be NULL.  With a channel subset, per_channel and gamma
+ * follow the subset order and force/per_* sum over the subset only.
+ */
+typedef struct cf_result {
+    double force;
+    double* per_harmonic; int per_harmonic_len;
+    double* per_face;     int per_face_len;
+    double* per_channel;  int per_channel_len;
+    double* gamma;        long long gamma_len;
+    double* trace;        int trace_len;
+    int n_channels_run;
+    double cell_updates;  /* channels * cells * steps advanced               */
+    double device_ms;     /* time of the stepping loop on the stream         */
+    double stencil_ms_avg;       /* mean duration of one field-update launch (CF_FLAG_TIME_STENCIL) */
+    int stencil_samples;         /* launches timed                                                  */
+    int stencil_launches;        /* field-update launches in the solve                              */
+    double stencil_alg_bytes;    /* algorithmic HBM bytes of one field-update launch:               */
+                                 /* one read + one write of the state it advances                   */
+    double stencil_cell_updates; /* cell-updates one field-update launch performs                   */
+} cf_result;
+
+typedef struct cf_problem cf_problem;
+
+/* Build a problem: copies the inputs, rasterizes walls, builds S, the
+ * per-face cosine basis and the interpolation tables.  *out receives a
+ * handle to free with cf_problem_destroy.  CF_E_ARG on bad shapes/ids,
+ * CF_E_SURFACE when S is invalid. */
+cf_status cf_problem_create(const cf_grid* grid, const cf_materials* mats,
+                            const cf_surface* surf, cf_problem** out);
+cf_status cf_problem_destroy(cf_problem* p);
+
+/* Sizes and medium for a solve with these options (no device work). */
+cf_status cf_problem_info(const cf_problem* p, const cf_opts* opts, cf_info* out);
+
+/* Channel table (Sec. II, the stress-tensor components as separate runs):
+ * for channel c, face index, harmonic label, kind (0 = E-current source,
+ * 1 = H-current source), source and measured component (CF_EX..CF_HZ) and
+ * sign (outward-normal side times stress coefficient).  Arrays of length
+ * >= n (n = cf_info.n_channels); NULL arrays are skipped. */
+cf_status cf_channel_table(const cf_problem* p, const cf_opts* opts, int n, int* face,
+                           int* label, int* kind, int* src, int* meas, double* sign);
+
+/* Validation: CFL limit, surface placement, option ranges (no device work). */
+cf_status cf_validate(const cf_problem* p, const cf_opts* opts);
+
+/* Device bytes a solve with these options needs. */
+cf_status cf_workspace_size(const cf_problem* p, const cf_opts* opts, size_t* bytes);
+
+/* Blocking force solve (Sec. II algorithm) on opts->stream.  workspace is a
+ * device pointer of ws_bytes >= cf_workspace_size() bytes, or NULL. */
+cf_status cf_solve(cf_problem* p, const cf_opts* opts, void* workspace, size_t ws_bytes,
+                   cf_result* out);
+
+/* The time kernel K(t_m) = 2 pi Im g(-t_m), t_m = m dt for m = 1..n
+ * (Appendix A, general and z-invariant forms), written to out[m-1]. Host
+ * only. */
+cf_status cf_kernel_table(int kernel, double sigma, double dt, int n, double* out);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char* cf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CASIMIR_FDTD_H */

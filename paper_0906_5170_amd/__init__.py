@@ -1,0 +1,289 @@
+"""Python binding of the MI355X Casimir-force FDTD library (libcasimir_fdtd.so).
+
+Argument marshalling only: every step of the force solve runs in the HIP
+library behind the C ABI of include/casimir_fdtd.h.  PyTorch provides the
+device workspace (a uint8 tensor) and the stream.  Loading fails loudly when
+the built library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcasimir_fdtd.so")
+
+COMPONENTS = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
+BC = {"pec": 0, "periodic": 1, "pml": 2}
+POL = {"TM": 1, "TE": 2, "TM+TE": 3, "3D": 4}
+KERNEL = {"general": 0, "zinv2d": 1}
+PRECISION = {"fp64": 0, "fp32": 1}
+PATH = {"batched": 0, "plain": 1}
+FLAG_KEEP_GAMMA = 1
+FLAG_TIME_STENCIL = 2
+STATUS = {0: "CF_OK", 1: "CF_E_ARG", 2: "CF_E_CFL", 3: "CF_E_SURFACE", 4: "CF_E_BUDGET",
+          5: "CF_E_NONFINITE", 6: "CF_E_DEVICE", 7: "CF_E_CANCELLED", 8: "CF_E_UNSUPPORTED"}
+
+
+class CfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class _Grid(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("res", C.c_double), ("bc", C.c_int * 3),
+                ("pml_cells", C.c_int * 3)]
+
+
+class _Materials(C.Structure):
+    _fields_ = [("n_materials", C.c_int), ("eps", C.POINTER(C.c_double)),
+                ("mu", C.POINTER(C.c_double)), ("comp_id", C.c_void_p * 6)]
+
+
+class _Surface(C.Structure):
+    _fields_ = [("lo", C.c_int * 3), ("hi", C.c_int * 3), ("n_harm", C.c_int),
+                ("force_axis", C.c_int)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("courant", C.c_double), ("n_steps", C.c_int),
+                ("pol", C.c_int), ("kernel", C.c_int), ("precision", C.c_int), ("path", C.c_int),
+                ("flags", C.c_int), ("channel_subset", C.POINTER(C.c_int)), ("n_subset", C.c_int),
+                ("stream", C.c_void_p)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("n_channels", C.c_int), ("n_faces", C.c_int), ("per_harmonic_len", C.c_int),
+                ("n_comp", C.c_int), ("workspace_bytes", C.c_size_t), ("eps_s", C.c_double),
+                ("mu_s", C.c_double)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("force", C.c_double),
+                ("per_harmonic", C.POINTER(C.c_double)), ("per_harmonic_len", C.c_int),
+                ("per_face", C.POINTER(C.c_double)), ("per_face_len", C.c_int),
+                ("per_channel", C.POINTER(C.c_double)), ("per_channel_len", C.c_int),
+                ("gamma", C.POINTER(C.c_double)), ("gamma_len", C.c_longlong),
+                ("trace", C.POINTER(C.c_double)), ("trace_len", C.c_int),
+                ("n_channels_run", C.c_int), ("cell_updates", C.c_double),
+                ("device_ms", C.c_double), ("stencil_ms_avg", C.c_double),
+                ("stencil_samples", C.c_int), ("stencil_launches", C.c_int),
+                ("stencil_alg_bytes", C.c_double), ("stencil_cell_updates", C.c_double)]
+
+
+_lib = None
+
+EXPORTS = ("cf_problem_create", "cf_problem_destroy", "cf_problem_info", "cf_channel_table",
+           "cf_validate", "cf_workspace_size", "cf_solve", "cf_kernel_table", "cf_last_error")
+
+
+def load():
+    """Load the built HIP library (raises if it has not been built).
+
+    PyTorch is imported first: its HIP runtime has the same soname
+    (libamdhip64.so.7) as the one the library links, so the dynamic linker
+    binds the library to PyTorch's already loaded runtime and the process
+    holds a single HIP runtime (device memory and streams from PyTorch are
+    then valid inside the library)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    import torch  # noqa: F401  (see docstring)
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    lib.cf_last_error.restype = C.c_char_p
+    lib.cf_problem_create.argtypes = [C.POINTER(_Grid), C.POINTER(_Materials), C.POINTER(_Surface),
+                                      C.POINTER(P)]
+    lib.cf_problem_destroy.argtypes = [P]
+    lib.cf_problem_info.argtypes = [P, C.POINTER(_Opts), C.POINTER(_Info)]
+    lib.cf_channel_table.argtypes = [P, C.POINTER(_Opts), C.c_int] + [C.c_void_p] * 6
+    lib.cf_validate.argtypes = [P, C.POINTER(_Opts)]
+    lib.cf_workspace_size.argtypes = [P, C.POINTER(_Opts), C.POINTER(C.c_size_t)]
+    lib.cf_solve.argtypes = [P, C.POINTER(_Opts), C.c_void_p, C.c_size_t, C.POINTER(_Result)]
+    lib.cf_kernel_table.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_double)]
+    for name in EXPORTS:
+        getattr(lib, name).restype = C.c_int if name != "cf_last_error" else C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != 0:
+        raise CfError(code, load().cf_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def kernel_table(kernel: str, sigma: float, dt: float, n: int) -> np.ndarray:
+    out = np.zeros(n)
+    _check(load().cf_kernel_table(KERNEL[kernel], float(sigma), float(dt), int(n), _dptr(out)))
+    return out
+
+
+class Problem:
+    """A force-solve problem: grid, per-component materials and the stress
+    surface.  Inputs are copied by the library at construction."""
+
+    def __init__(self, ndim: int, shape: Sequence[int], res: float, bc: Sequence[str],
+                 eps: Sequence[float], mu: Sequence[float], comp_ids: Dict[str, np.ndarray],
+                 s_lo: Sequence[int], s_hi: Sequence[int], n_harm: int, force_axis: int,
+                 pml_cells: Sequence[int] = (0, 0, 0)):
+        lib = load()
+        g = _Grid()
+        g.ndim = int(ndim)
+        for a in range(3):
+            g.n[a] = int(shape[a])
+            g.bc[a] = BC[bc[a]]
+            g.pml_cells[a] = int(pml_cells[a])
+        g.res = float(res)
+        self._eps = np.ascontiguousarray(eps, dtype=np.float64)
+        self._mu = np.ascontiguousarray(mu, dtype=np.float64)
+        m = _Materials()
+        m.n_materials = len(self._eps)
+        m.eps = _dptr(self._eps)
+        m.mu = _dptr(self._mu)
+        self._ids = []
+        for k, name in enumerate(COMPONENTS):
+            arr = comp_ids.get(name)
+            if arr is None:
+                m.comp_id[k] = None
+                continue
+            arr = np.ascontiguousarray(arr, dtype=np.uint8)
+            if arr.size != int(shape[0]) * int(shape[1]) * int(shape[2]):
+                raise ValueError(f"{name} id grid has {arr.size} cells")
+            self._ids.append(arr)
+            m.comp_id[k] = arr.ctypes.data
+        s = _Surface()
+        for a in range(3):
+            s.lo[a] = int(s_lo[a])
+            s.hi[a] = int(s_hi[a])
+        s.n_harm = int(n_harm)
+        s.force_axis = int(force_axis)
+        h = C.c_void_p()
+        _check(lib.cf_problem_create(C.byref(g), C.byref(m), C.byref(s), C.byref(h)))
+        self._h = h
+        self.ndim = ndim
+        self.shape = tuple(int(v) for v in shape)
+        self.res = float(res)
+        self._ids = None
+
+    @classmethod
+    def from_workload(cls, wl) -> "Problem":
+        return cls(wl.ndim, wl.shape, wl.res, wl.bc, wl.eps, wl.mu, wl.comp_ids, wl.s_lo, wl.s_hi,
+                   wl.n_harm, wl.force_axis, wl.pml_cells)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value is not None and _lib is not None:
+            _lib.cf_problem_destroy(h)
+            self._h = None
+
+    @property
+    def n_cells(self) -> int:
+        return self.shape[0] * self.shape[1] * self.shape[2]
+
+    def _opts(self, sigma=1.0, courant=0.5, n_steps=1000, pol="TM", kernel="zinv2d",
+              precision="fp64", path="batched", keep_gamma=False, channel_subset=None, stream=None,
+              time_stencil=False):
+        o = _Opts()
+        o.sigma = float(sigma)
+        o.courant = float(courant)
+        o.n_steps = int(n_steps)
+        o.pol = POL[pol]
+        o.kernel = KERNEL[kernel]
+        o.precision = PRECISION[precision]
+        o.path = PATH[path]
+        o.flags = (FLAG_KEEP_GAMMA if keep_gamma else 0) | (FLAG_TIME_STENCIL if time_stencil else 0)
+        if channel_subset is not None:
+            sub = np.ascontiguousarray(channel_subset, dtype=np.int32)
+            o.channel_subset = sub.ctypes.data_as(C.POINTER(C.c_int))
+            o.n_subset = len(sub)
+            self._subset_keep = sub
+        else:
+            o.channel_subset = None
+            o.n_subset = 0
+        o.stream = stream
+        return o
+
+    def info(self, **opts) -> dict:
+        o = self._opts(**opts)
+        inf = _Info()
+        _check(load().cf_problem_info(self._h, C.byref(o), C.byref(inf)))
+        return dict(n_channels=inf.n_channels, n_faces=inf.n_faces,
+                    per_harmonic_len=inf.per_harmonic_len, n_comp=inf.n_comp,
+                    workspace_bytes=int(inf.workspace_bytes), eps_s=inf.eps_s, mu_s=inf.mu_s)
+
+    def validate(self, **opts):
+        o = self._opts(**opts)
+        _check(load().cf_validate(self._h, C.byref(o)))
+
+    def channel_table(self, **opts) -> dict:
+        n = self.info(**opts)["n_channels"]
+        o = self._opts(**opts)
+        face, label, kind, src, meas = (np.zeros(n, np.int32) for _ in range(5))
+        sign = np.zeros(n)
+        _check(load().cf_channel_table(self._h, C.byref(o), n, face.ctypes.data, label.ctypes.data,
+                                       kind.ctypes.data, src.ctypes.data, meas.ctypes.data,
+                                       sign.ctypes.data))
+        return dict(face=face, label=label, kind=kind, src=src, meas=meas, sign=sign)
+
+    def solve(self, workspace=None, **opts) -> dict:
+        """Run the force solve on the GPU.  workspace: optional torch uint8
+        CUDA tensor of at least info()['workspace_bytes'] bytes."""
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("cf solve needs a ROCm GPU")
+        stream = torch.cuda.current_stream()
+        opts = dict(opts)
+        opts["stream"] = C.c_void_p(stream.cuda_stream)
+        info = self.info(**{k: v for k, v in opts.items() if k != "stream"})
+        nbytes = info["workspace_bytes"]
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        if workspace.numel() < nbytes:
+            raise ValueError("workspace too small")
+        o = self._opts(**opts)
+        C_run = o.n_subset if o.n_subset > 0 else info["n_channels"]
+        T = int(opts.get("n_steps", 1000))
+        ph = np.zeros(max(1, info["per_harmonic_len"]))
+        pf = np.zeros(6)
+        pc = np.zeros(C_run)
+        r = _Result()
+        r.per_harmonic, r.per_harmonic_len = _dptr(ph), len(ph)
+        r.per_face, r.per_face_len = _dptr(pf), 6
+        r.per_channel, r.per_channel_len = _dptr(pc), C_run
+        gam = tr = None
+        if opts.get("keep_gamma"):
+            gam = np.zeros(T * C_run)
+            tr = np.zeros(T)
+            r.gamma, r.gamma_len = _dptr(gam), gam.size
+            r.trace, r.trace_len = _dptr(tr), T
+        _check(load().cf_solve(self._h, C.byref(o), C.c_void_p(workspace.data_ptr()), nbytes, C.byref(r)))
+        out = dict(force=r.force, per_harmonic=ph[:info["per_harmonic_len"]], per_face=pf,
+                   per_channel=pc, n_channels=r.n_channels_run, cell_updates=r.cell_updates,
+                   device_ms=r.device_ms, stencil_ms_avg=r.stencil_ms_avg,
+                   stencil_samples=r.stencil_samples, stencil_launches=r.stencil_launches,
+                   stencil_alg_bytes=r.stencil_alg_bytes,
+                   stencil_cell_updates=r.stencil_cell_updates)
+        if gam is not None:
+            out["gamma"] = gam.reshape(T, C_run)
+            out["trace"] = tr
+        return out
+
+
+def solve_workload(wl, **over) -> dict:
+    """Solve a casimir_inputs.Workload with its own run options."""
+    p = Problem.from_workload(wl)
+    opts = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol=wl.pol,
+                kernel=wl.kernel, precision=wl.precision)
+    opts.update(over)
+    return p.solve(**opts)

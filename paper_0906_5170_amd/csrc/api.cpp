@@ -1,0 +1,514 @@
+// C ABI of the Casimir FDTD library: problem handles, validation, workspace
+// layout, table upload, the batched and plain stepping loops and the final
+// reduction of the per-channel FP64 accumulators into the force.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/casimir_fdtd.h"
+#include "device.hpp"
+#include "plan.hpp"
+
+struct cf_problem {
+    cf::Problem p;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+cf_status fail(cf_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define CF_HIP(expr)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(CF_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Device workspace layout of one solve.
+struct Layout {
+    size_t ids, lut, ktab, chans, slots, gidx, gw, uidx, uoff, usamp, uw, basis, acc, gamma,
+        fields, total;
+    int n_field_slots;
+};
+
+struct Staged {
+    std::vector<cf::Channel> chans;       // channels run, in output order
+    std::vector<cf::ChanDev> dev;          // one descriptor per channel run
+    std::vector<int> slots_tm, slots_te, slots_3d, slots_all;
+    std::vector<int32_t> gidx, uidx, uoff, usamp;
+    std::vector<double> gw, uw, basis;
+    int max_uniq = 0;
+    int n_field_slots = 0;
+    int ncomp = 3;
+};
+
+std::vector<cf::Channel> selected_channels(const cf::Problem& p, const cf_opts& o, std::string* err) {
+    std::vector<cf::Channel> all = cf::channel_table(p, o.pol);
+    if (o.n_subset <= 0 || !o.channel_subset) return all;
+    std::vector<cf::Channel> out;
+    for (int k = 0; k < o.n_subset; ++k) {
+        int c = o.channel_subset[k];
+        if (c < 0 || c >= (int)all.size()) {
+            *err = "channel_subset index out of range";
+            return {};
+        }
+        out.push_back(all[c]);
+    }
+    return out;
+}
+
+// Build host copies of every table a solve uploads.
+void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel>& chans, Staged& st) {
+    st.chans = chans;
+    st.ncomp = cf::n_comp_for(p.grid.ndim);
+    // concatenated gather / scatter tables for every (face, comp) pair used
+    std::vector<int> g_goff(p.gathers.size(), -1), g_uoff(p.gathers.size(), -1);
+    auto add_gather = [&](int gi) {
+        if (g_goff[gi] >= 0) return;
+        const cf::Gather& g = p.gathers[gi];
+        g_goff[gi] = (int)st.gidx.size();
+        st.gidx.insert(st.gidx.end(), g.idx.begin(), g.idx.end());
+        st.gw.insert(st.gw.end(), g.w.begin(), g.w.end());
+        g_uoff[gi] = (int)st.uidx.size();
+        const int base = (int)st.usamp.size();
+        st.uidx.insert(st.uidx.end(), g.uidx.begin(), g.uidx.end());
+        // uoff is stored per distinct point with one trailing entry per gather
+        // (offsets global into usamp/uw); the extra entry keeps [u, u+1] valid.
+        for (size_t k = 0; k + 1 < g.uoff.size(); ++k) st.uoff.push_back(base + g.uoff[k]);
+        st.uoff.push_back(base + g.uoff.back());
+        st.uidx.push_back(0);   // pad so uidx and uoff stay index-aligned
+        st.usamp.insert(st.usamp.end(), g.usamp.begin(), g.usamp.end());
+        st.uw.insert(st.uw.end(), g.uw.begin(), g.uw.end());
+    };
+    std::vector<int> basis_face_off(p.faces.size());
+    for (size_t f = 0; f < p.faces.size(); ++f) {
+        basis_face_off[f] = (int)st.basis.size();
+        st.basis.insert(st.basis.end(), p.basis[f].begin(), p.basis[f].end());
+    }
+    const bool plain = o.path == CF_PATH_PLAIN;
+    st.n_field_slots = plain ? 1 : (int)chans.size();
+    const double res = p.grid.res;
+    for (size_t c = 0; c < chans.size(); ++c) {
+        const cf::Channel& ch = chans[c];
+        int gm = p.gather_of.at({ch.face, ch.meas});
+        int gs = p.gather_of.at({ch.face, ch.src});
+        add_gather(gm);
+        add_gather(gs);
+        cf::ChanDev d{};
+        d.field_off = plain ? 0 : (int64_t)c * st.ncomp * p.ncell;
+        d.src_off = d.field_off + (int64_t)cf::comp_slot(ch.pol, ch.src) * p.ncell;
+        d.meas_off = d.field_off + (int64_t)cf::comp_slot(ch.pol, ch.meas) * p.ncell;
+        d.kind = ch.kind;
+        d.nsamp = p.gathers[gm].nsamp;
+        d.P = p.gathers[gm].P;
+        d.g_off = g_goff[gm];
+        d.u_off = g_uoff[gs];
+        d.n_uniq = (int)p.gathers[gs].uidx.size();
+        d.basis_off = basis_face_off[ch.face] + ch.row * p.faces[ch.face].nsamp;
+        d.kick_scale = -res / (ch.kind == 0 ? p.eps_s : p.mu_s);
+        st.max_uniq = std::max(st.max_uniq, d.n_uniq);
+        st.dev.push_back(d);
+        st.slots_all.push_back((int)c);
+        if (ch.pol == CF_POL_TM) st.slots_tm.push_back((int)c);
+        else if (ch.pol == CF_POL_TE) st.slots_te.push_back((int)c);
+        else st.slots_3d.push_back((int)c);
+    }
+}
+
+Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    const size_t fsz = o.precision == CF_FP64 ? 8 : 4;
+    const size_t C = st.chans.size();
+    L.ids = take((size_t)cf::kNumComp * p.ncell);
+    L.lut = take(2 * cf::kNumComp * 256 * 2 * fsz);
+    L.ktab = take((size_t)o.n_steps * 8);
+    L.chans = take(C * sizeof(cf::ChanDev));
+    L.slots = take((C + 2) * 3 * sizeof(int));
+    L.gidx = take(st.gidx.size() * 4 + 4);
+    L.gw = take(st.gw.size() * 8 + 8);
+    L.uidx = take(st.uidx.size() * 4 + 4);
+    L.uoff = take(st.uoff.size() * 4 + 4);
+    L.usamp = take(st.usamp.size() * 4 + 4);
+    L.uw = take(st.uw.size() * 8 + 8);
+    L.basis = take(st.basis.size() * 8 + 8);
+    L.acc = take(C * 2 * 8);
+    L.gamma = (o.flags & CF_FLAG_KEEP_GAMMA) ? take((size_t)o.n_steps * C * 8) : off;
+    L.fields = take((size_t)st.n_field_slots * st.ncomp * p.ncell * fsz);
+    L.total = off;
+    L.n_field_slots = st.n_field_slots;
+    return L;
+}
+
+struct StencilTiming {
+    double ms_avg = 0;
+    int samples = 0;
+    int launches = 0;
+};
+
+template <typename T>
+cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, const Layout& L,
+                    char* ws, hipStream_t s, std::vector<double>& acc_out, std::vector<double>& gamma_out,
+                    double* device_ms, StencilTiming* timing) {
+    const size_t C = st.chans.size();
+    // ---- upload tables --------------------------------------------------
+    std::vector<uint8_t> ids((size_t)cf::kNumComp * p.ncell);
+    for (int c = 0; c < cf::kNumComp; ++c)
+        std::memcpy(ids.data() + (size_t)c * p.ncell, p.ids[c].data(), p.ncell);
+    std::vector<double> lut64 = cf::coefficient_lut(p, o.sigma, o.courant);
+    std::vector<T> lut(lut64.begin(), lut64.end());
+    std::vector<double> ktab(o.n_steps);
+    cf::kernel_table(o.kernel, o.sigma, o.courant / p.grid.res, o.n_steps, ktab.data());
+    std::vector<int> slots;
+    slots.insert(slots.end(), st.slots_tm.begin(), st.slots_tm.end());
+    slots.insert(slots.end(), st.slots_te.begin(), st.slots_te.end());
+    slots.insert(slots.end(), st.slots_3d.begin(), st.slots_3d.end());
+    slots.insert(slots.end(), st.slots_all.begin(), st.slots_all.end());
+    auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    CF_HIP(up(L.ids, ids.data(), ids.size()));
+    CF_HIP(up(L.lut, lut.data(), lut.size() * sizeof(T)));
+    CF_HIP(up(L.ktab, ktab.data(), ktab.size() * 8));
+    CF_HIP(up(L.chans, st.dev.data(), st.dev.size() * sizeof(cf::ChanDev)));
+    CF_HIP(up(L.slots, slots.data(), slots.size() * sizeof(int)));
+    CF_HIP(up(L.gidx, st.gidx.data(), st.gidx.size() * 4));
+    CF_HIP(up(L.gw, st.gw.data(), st.gw.size() * 8));
+    CF_HIP(up(L.uidx, st.uidx.data(), st.uidx.size() * 4));
+    CF_HIP(up(L.uoff, st.uoff.data(), st.uoff.size() * 4));
+    CF_HIP(up(L.usamp, st.usamp.data(), st.usamp.size() * 4));
+    CF_HIP(up(L.uw, st.uw.data(), st.uw.size() * 8));
+    CF_HIP(up(L.basis, st.basis.data(), st.basis.size() * 8));
+    CF_HIP(hipMemsetAsync(ws + L.acc, 0, C * 2 * 8, s));
+    const bool keep_gamma = (o.flags & CF_FLAG_KEEP_GAMMA) != 0;
+    if (keep_gamma) CF_HIP(hipMemsetAsync(ws + L.gamma, 0, (size_t)o.n_steps * C * 8, s));
+
+    T* fields = reinterpret_cast<T*>(ws + L.fields);
+    const cf::ChanDev* dch = reinterpret_cast<const cf::ChanDev*>(ws + L.chans);
+    const int* dslots = reinterpret_cast<const int*>(ws + L.slots);
+    const int n_tm = (int)st.slots_tm.size(), n_te = (int)st.slots_te.size(),
+              n_3d = (int)st.slots_3d.size();
+    const int* s_tm = dslots;
+    const int* s_te = dslots + n_tm;
+    const int* s_all = dslots + n_tm + n_te + n_3d;
+    const T* dlut = reinterpret_cast<const T*>(ws + L.lut);
+    const double* dk = reinterpret_cast<const double*>(ws + L.ktab);
+    double* dacc = reinterpret_cast<double*>(ws + L.acc);
+    double* dgam = keep_gamma ? reinterpret_cast<double*>(ws + L.gamma) : nullptr;
+    cf::SurfTables tabs;
+    tabs.gidx = reinterpret_cast<const int32_t*>(ws + L.gidx);
+    tabs.gw = reinterpret_cast<const double*>(ws + L.gw);
+    tabs.uidx = reinterpret_cast<const int32_t*>(ws + L.uidx);
+    tabs.uoff = reinterpret_cast<const int32_t*>(ws + L.uoff);
+    tabs.usamp = reinterpret_cast<const int32_t*>(ws + L.usamp);
+    tabs.uw = reinterpret_cast<const double*>(ws + L.uw);
+    tabs.basis = reinterpret_cast<const double*>(ws + L.basis);
+    cf::Grid2D g{};
+    g.nx = p.nx;
+    g.ny = p.ny;
+    g.ncell = p.ncell;
+    g.perx = p.grid.bc[0] == CF_BC_PERIODIC;
+    g.pery = p.grid.bc[1] == CF_BC_PERIODIC;
+    for (int c = 0; c < cf::kNumComp; ++c)
+        g.ids[c] = reinterpret_cast<const uint8_t*>(ws + L.ids) + (size_t)c * p.ncell;
+    const double dt = o.courant / p.grid.res;
+    const double dA = std::pow(1.0 / p.grid.res, p.grid.ndim - 1);
+    const size_t field_bytes = (size_t)L.n_field_slots * st.ncomp * p.ncell * sizeof(T);
+
+    hipEvent_t e0, e1;
+    CF_HIP(hipEventCreate(&e0));
+    CF_HIP(hipEventCreate(&e1));
+    // sampled timing of the field-update launches (batched path)
+    const bool time_it = (o.flags & CF_FLAG_TIME_STENCIL) && o.path == CF_PATH_BATCHED;
+    const int stride = std::max(1, o.n_steps / 200);
+    std::vector<hipEvent_t> tev;
+    if (time_it) {
+        tev.resize(2 * ((o.n_steps + stride - 1) / stride));
+        for (auto& e : tev) CF_HIP(hipEventCreate(&e));
+    }
+    int tk = 0;
+    cf_status status = CF_OK;
+    hipError_t err = hipSuccess;
+#define STEP_OK(expr)                \
+    do {                             \
+        err = (expr);                \
+        if (err != hipSuccess) goto done; \
+    } while (0)
+    STEP_OK(hipEventRecord(e0, s));
+    if (o.path == CF_PATH_BATCHED) {
+        STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
+        STEP_OK(cf::launch_kick<T>(fields, dch, s_all, (int)C, st.max_uniq, tabs, s));
+        STEP_OK(cf::launch_h2d<T>(CF_POL_TM, 1, fields, dch, s_tm, n_tm, g, dlut, s));
+        STEP_OK(cf::launch_h2d<T>(CF_POL_TE, 1, fields, dch, s_te, n_te, g, dlut, s));
+        STEP_OK(cf::launch_e2d<T>(CF_POL_TM, 1, fields, dch, s_tm, n_tm, g, dlut, s));
+        STEP_OK(cf::launch_e2d<T>(CF_POL_TE, 1, fields, dch, s_te, n_te, g, dlut, s));
+        for (int m = 0; m < o.n_steps; ++m) {
+            const bool sample = time_it && m % stride == 0;
+            if (sample) STEP_OK(hipEventRecord(tev[2 * tk], s));
+            STEP_OK(cf::launch_h2d<T>(CF_POL_TM, 0, fields, dch, s_tm, n_tm, g, dlut, s));
+            STEP_OK(cf::launch_h2d<T>(CF_POL_TE, 0, fields, dch, s_te, n_te, g, dlut, s));
+            STEP_OK(cf::launch_e2d<T>(CF_POL_TM, 0, fields, dch, s_tm, n_tm, g, dlut, s));
+            STEP_OK(cf::launch_e2d<T>(CF_POL_TE, 0, fields, dch, s_te, n_te, g, dlut, s));
+            if (sample) STEP_OK(hipEventRecord(tev[2 * tk++ + 1], s));
+            STEP_OK(cf::launch_surface<T>(fields, dch, s_all, (int)C, tabs, dk, m, dt, dA, dacc, dgam,
+                                          (int)C, s));
+        }
+    } else {
+        // plain: one channel at a time in a single field block
+        for (size_t c = 0; c < C; ++c) {
+            const int* one = s_all + c;
+            const int pol = st.chans[c].pol;
+            STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
+            STEP_OK(cf::launch_kick<T>(fields, dch, one, 1, st.max_uniq, tabs, s));
+            STEP_OK(cf::launch_h2d<T>(pol, 1, fields, dch, one, 1, g, dlut, s));
+            STEP_OK(cf::launch_e2d<T>(pol, 1, fields, dch, one, 1, g, dlut, s));
+            for (int m = 0; m < o.n_steps; ++m) {
+                STEP_OK(cf::launch_h2d<T>(pol, 0, fields, dch, one, 1, g, dlut, s));
+                STEP_OK(cf::launch_e2d<T>(pol, 0, fields, dch, one, 1, g, dlut, s));
+                STEP_OK(cf::launch_surface<T>(fields, dch, one, 1, tabs, dk, m, dt, dA, dacc, dgam,
+                                              (int)C, s));
+            }
+        }
+    }
+    STEP_OK(hipEventRecord(e1, s));
+    STEP_OK(hipEventSynchronize(e1));
+    {
+        float ms = 0;
+        STEP_OK(hipEventElapsedTime(&ms, e0, e1));
+        *device_ms = ms;
+    }
+    if (time_it) {
+        double tot = 0;
+        for (int k = 0; k < tk; ++k) {
+            float ms = 0;
+            STEP_OK(hipEventElapsedTime(&ms, tev[2 * k], tev[2 * k + 1]));
+            tot += ms;
+        }
+        timing->samples = tk;
+        timing->ms_avg = tk ? tot / tk : 0.0;
+        timing->launches = o.n_steps;
+    }
+    acc_out.assign(C * 2, 0.0);
+    STEP_OK(hipMemcpy(acc_out.data(), ws + L.acc, C * 2 * 8, hipMemcpyDeviceToHost));
+    if (keep_gamma) {
+        gamma_out.assign((size_t)o.n_steps * C, 0.0);
+        STEP_OK(hipMemcpy(gamma_out.data(), ws + L.gamma, gamma_out.size() * 8, hipMemcpyDeviceToHost));
+    }
+done:
+#undef STEP_OK
+    // host staging vectors die with this frame: drain the stream first
+    if (err != hipSuccess) (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (auto& e : tev) (void)hipEventDestroy(e);
+    if (err != hipSuccess) status = fail(CF_E_DEVICE, std::string("device step failed: ") + hipGetErrorString(err));
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cf_last_error(void) { return g_err.c_str(); }
+
+cf_status cf_problem_create(const cf_grid* grid, const cf_materials* mats, const cf_surface* surf,
+                            cf_problem** out) {
+    if (!grid || !mats || !surf || !out) return fail(CF_E_ARG, "null argument");
+    *out = nullptr;
+    std::unique_ptr<cf_problem> h(new (std::nothrow) cf_problem);
+    if (!h) return fail(CF_E_ARG, "out of host memory");
+    std::string err = cf::build_problem(*grid, *mats, *surf, h->p);
+    if (!err.empty()) {
+        bool surface = err.find("surface") != std::string::npos;
+        return fail(surface ? CF_E_SURFACE : CF_E_ARG, err);
+    }
+    *out = h.release();
+    g_err.clear();
+    return CF_OK;
+}
+
+cf_status cf_problem_destroy(cf_problem* p) {
+    delete p;
+    return CF_OK;
+}
+
+cf_status cf_validate(const cf_problem* h, const cf_opts* o) {
+    if (!h || !o) return fail(CF_E_ARG, "null argument");
+    cf_status code;
+    std::string err = cf::validate_opts(h->p, *o, &code);
+    if (!err.empty()) return fail(code, err);
+    if (o->n_subset > 0) {
+        std::string e2;
+        auto ch = selected_channels(h->p, *o, &e2);
+        if (!e2.empty()) return fail(CF_E_ARG, e2);
+    }
+    return CF_OK;
+}
+
+cf_status cf_problem_info(const cf_problem* h, const cf_opts* o, cf_info* out) {
+    cf_status st = cf_validate(h, o);
+    if (st != CF_OK) return st;
+    if (!out) return fail(CF_E_ARG, "null argument");
+    const cf::Problem& p = h->p;
+    std::string e2;
+    auto all = cf::channel_table(p, o->pol);
+    auto chans = selected_channels(p, *o, &e2);
+    Staged sg;
+    stage(p, *o, chans, sg);
+    Layout L = layout_for(p, *o, sg);
+    out->n_channels = (int)all.size();
+    out->n_faces = (int)p.faces.size();
+    int lab = 0;
+    for (auto& v : p.labels)
+        for (int l : v) lab = std::max(lab, l + 1);
+    out->per_harmonic_len = lab;
+    out->n_comp = cf::n_comp_for(p.grid.ndim);
+    out->workspace_bytes = L.total;
+    out->eps_s = p.eps_s;
+    out->mu_s = p.mu_s;
+    return CF_OK;
+}
+
+cf_status cf_channel_table(const cf_problem* h, const cf_opts* o, int n, int* face, int* label,
+                           int* kind, int* src, int* meas, double* sign) {
+    cf_status st = cf_validate(h, o);
+    if (st != CF_OK) return st;
+    auto all = cf::channel_table(h->p, o->pol);
+    if (n < (int)all.size()) return fail(CF_E_ARG, "channel arrays too short");
+    for (size_t c = 0; c < all.size(); ++c) {
+        if (face) face[c] = h->p.faces[all[c].face].index;
+        if (label) label[c] = all[c].label;
+        if (kind) kind[c] = all[c].kind;
+        if (src) src[c] = all[c].src;
+        if (meas) meas[c] = all[c].meas;
+        if (sign) sign[c] = all[c].sign;
+    }
+    return CF_OK;
+}
+
+cf_status cf_workspace_size(const cf_problem* h, const cf_opts* o, size_t* bytes) {
+    cf_info info;
+    cf_status st = cf_problem_info(h, o, &info);
+    if (st != CF_OK) return st;
+    if (!bytes) return fail(CF_E_ARG, "null argument");
+    *bytes = info.workspace_bytes;
+    return CF_OK;
+}
+
+cf_status cf_kernel_table(int kernel, double sigma, double dt, int n, double* out) {
+    if (!out || n < 0 || !(dt > 0) || !(sigma >= 0)) return fail(CF_E_ARG, "bad kernel table arguments");
+    if (kernel != CF_KERNEL_GENERAL && kernel != CF_KERNEL_ZINV2D) return fail(CF_E_ARG, "unknown kernel");
+    cf::kernel_table(kernel, sigma, dt, n, out);
+    return CF_OK;
+}
+
+cf_status cf_solve(cf_problem* h, const cf_opts* o, void* workspace, size_t ws_bytes, cf_result* out) {
+    cf_status st = cf_validate(h, o);
+    if (st != CF_OK) return st;
+    if (!out) return fail(CF_E_ARG, "null result");
+    const cf::Problem& p = h->p;
+    if (p.grid.ndim != 2) return fail(CF_E_UNSUPPORTED, "3D solve not available in this build");
+    std::string e2;
+    auto chans = selected_channels(p, *o, &e2);
+    if (!e2.empty()) return fail(CF_E_ARG, e2);
+    const size_t C = chans.size();
+    int lab = 0;
+    for (auto& v : p.labels)
+        for (int l : v) lab = std::max(lab, l + 1);
+    const bool keep_gamma = (o->flags & CF_FLAG_KEEP_GAMMA) != 0;
+    if (out->per_harmonic && out->per_harmonic_len < lab) return fail(CF_E_ARG, "per_harmonic too short");
+    if (out->per_face && out->per_face_len < 2 * p.grid.ndim) return fail(CF_E_ARG, "per_face too short");
+    if (out->per_channel && out->per_channel_len < (int)C) return fail(CF_E_ARG, "per_channel too short");
+    if (out->gamma && (!keep_gamma || out->gamma_len < (long long)o->n_steps * (long long)C))
+        return fail(CF_E_ARG, "gamma needs CF_FLAG_KEEP_GAMMA and n_steps*channels entries");
+    if (out->trace && (!keep_gamma || out->trace_len < o->n_steps))
+        return fail(CF_E_ARG, "trace needs CF_FLAG_KEEP_GAMMA and n_steps entries");
+    Staged sg;
+    stage(p, *o, chans, sg);
+    Layout L = layout_for(p, *o, sg);
+    char* ws = static_cast<char*>(workspace);
+    void* owned = nullptr;
+    if (!ws) {
+        CF_HIP(hipMalloc(&owned, L.total));
+        ws = static_cast<char*>(owned);
+    } else if (ws_bytes < L.total) {
+        return fail(CF_E_BUDGET, "workspace smaller than cf_workspace_size()");
+    }
+    hipStream_t s = static_cast<hipStream_t>(o->stream);
+    std::vector<double> acc, gam;
+    double ms = 0;
+    StencilTiming tim;
+    cf_status rs = o->precision == CF_FP64 ? run_solve<double>(p, *o, sg, L, ws, s, acc, gam, &ms, &tim)
+                                           : run_solve<float>(p, *o, sg, L, ws, s, acc, gam, &ms, &tim);
+    if (owned) hipFree(owned);
+    if (rs != CF_OK) return rs;
+    // ---- reduction (host, FP64, channel order) -------------------------
+    std::vector<double> a(C);
+    bool finite = true;
+    for (size_t c = 0; c < C; ++c) {
+        a[c] = acc[2 * c] + acc[2 * c + 1];
+        finite = finite && std::isfinite(a[c]);
+    }
+    double F = 0;
+    for (size_t c = 0; c < C; ++c) F += chans[c].sign * a[c];
+    out->force = F / M_PI;
+    if (out->per_harmonic) {
+        std::fill(out->per_harmonic, out->per_harmonic + out->per_harmonic_len, 0.0);
+        for (size_t c = 0; c < C; ++c) out->per_harmonic[chans[c].label] += chans[c].sign * a[c] / M_PI;
+    }
+    if (out->per_face) {
+        std::fill(out->per_face, out->per_face + out->per_face_len, 0.0);
+        for (size_t c = 0; c < C; ++c)
+            out->per_face[p.faces[chans[c].face].index] += chans[c].sign * a[c] / M_PI;
+    }
+    if (out->per_channel)
+        for (size_t c = 0; c < C; ++c) out->per_channel[c] = a[c];
+    if (out->gamma) std::copy(gam.begin(), gam.end(), out->gamma);
+    if (out->trace) {
+        std::vector<double> ktab(o->n_steps);
+        const double dt = o->courant / p.grid.res;
+        cf::kernel_table(o->kernel, o->sigma, dt, o->n_steps, ktab.data());
+        double run = 0;
+        for (int m = 0; m < o->n_steps; ++m) {
+            double s = 0;
+            for (size_t c = 0; c < C; ++c) s += chans[c].sign * gam[(size_t)m * C + c];
+            run += dt * ktab[m] * s / M_PI;
+            out->trace[m] = run;
+        }
+    }
+    out->n_channels_run = (int)C;
+    out->cell_updates = (double)C * (double)p.ncell * (double)o->n_steps;
+    out->device_ms = ms;
+    out->stencil_ms_avg = tim.ms_avg;
+    out->stencil_samples = tim.samples;
+    out->stencil_launches = tim.launches;
+    {
+        const double fsz = o->precision == CF_FP64 ? 8.0 : 4.0;
+        const int ncomp = cf::n_comp_for(p.grid.ndim);
+        out->stencil_cell_updates = (double)C * (double)p.ncell;
+        out->stencil_alg_bytes = 2.0 * ncomp * fsz * out->stencil_cell_updates;
+    }
+    if (!finite) return fail(CF_E_NONFINITE, "a force accumulator is not finite");
+    g_err.clear();
+    return CF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+// Device-side tables and kernel launchers shared by the HIP sources and the
+// C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cf {
+
+// Per-channel descriptor on the device.  Offsets are element offsets into
+// the field array (fields), the gather tables (gidx/gw), the scatter tables
+// (uidx/uoff) and the basis table.
+struct ChanDev {
+    int64_t field_off;   // first element of the channel's field block
+    int64_t src_off;     // field_off + slot(src) * ncell
+    int64_t meas_off;    // field_off + slot(meas) * ncell
+    int32_t kind;        // 0 E-current source, 1 H-current source
+    int32_t nsamp;       // samples on the channel's face
+    int32_t P;           // interpolation points per sample of the measured component
+    int32_t g_off;       // gather table offset (measured component), entries = nsamp*P
+    int32_t u_off;       // scatter table: first distinct point (source component)
+    int32_t n_uniq;      // number of distinct source points
+    int32_t basis_off;   // first basis value of the channel's row
+    int32_t pad;
+    double kick_scale;   // -res / (eps_S or mu_S)
+};
+
+// Grid and table pointers of one launch.
+struct Grid2D {
+    int nx, ny;
+    int64_t ncell;
+    int perx, pery;
+    const uint8_t* ids[6];   // per-component material ids
+};
+
+struct SurfTables {
+    const int32_t* gidx;
+    const double* gw;
+    const int32_t* uidx;
+    const int32_t* uoff;     // CSR offsets, global
+    const int32_t* usamp;    // global sample index into the basis row
+    const double* uw;
+    const double* basis;
+};
+
+// 2D launchers.  `slots` lists the channel descriptors to advance (one
+// thread-block row per slot).  pol is CF_POL_TM or CF_POL_TE.  mode 0 =
+// regular step half, mode 1 = consistent start (H half for E-kind
+// channels, E half for H-kind channels).
+template <typename T>
+hipError_t launch_h2d(int pol, int mode, T* fields, const ChanDev* ch, const int* slots, int nslots,
+                      const Grid2D& g, const T* lut, hipStream_t s);
+template <typename T>
+hipError_t launch_e2d(int pol, int mode, T* fields, const ChanDev* ch, const int* slots, int nslots,
+                      const Grid2D& g, const T* lut, hipStream_t s);
+
+template <typename T>
+hipError_t launch_kick(T* fields, const ChanDev* ch, const int* slots, int nslots, int max_uniq,
+                       const SurfTables& t, hipStream_t s);
+
+// Surface projection + g-weighted accumulation for step m (0-based sample
+// index into ktab).  acc holds (sum, compensation) per channel descriptor.
+// gamma, when non-null, receives Gamma at gamma[m * gamma_stride + slot].
+template <typename T>
+hipError_t launch_surface(const T* fields, const ChanDev* ch, const int* slots, int nslots,
+                          const SurfTables& t, const double* ktab, int m, double dt, double dA,
+                          double* acc, double* gamma, int gamma_stride, hipStream_t s);
+
+}  // namespace cf

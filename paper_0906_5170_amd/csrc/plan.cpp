@@ -1,0 +1,461 @@
+// Host planning: walls, stress surface, interpolation, cosine basis,
+// channel table, update coefficients and the time kernel.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <set>
+
+namespace cf {
+
+// E_a: half a cell along a.  H_a: half a cell along both other axes.
+const int kOffset2[kNumComp][3] = {
+    {1, 0, 0}, {0, 1, 0}, {0, 0, 1},   // Ex Ey Ez
+    {0, 1, 1}, {1, 0, 1}, {1, 1, 0},   // Hx Hy Hz
+};
+
+static bool is_e(int comp) { return comp < 3; }
+
+void pol_components(int pol, std::vector<int>& e, std::vector<int>& h) {
+    e.clear();
+    h.clear();
+    if (pol == CF_POL_TM) {
+        e = {CF_EZ};
+        h = {CF_HX, CF_HY};
+    } else if (pol == CF_POL_TE) {
+        e = {CF_EX, CF_EY};
+        h = {CF_HZ};
+    } else {
+        e = {CF_EX, CF_EY, CF_EZ};
+        h = {CF_HX, CF_HY, CF_HZ};
+    }
+}
+
+// Field block of a channel: TM (Ez, Hx, Hy), TE (Ex, Ey, Hz), 3D (Ex..Hz).
+int comp_slot(int pol, int comp) {
+    if (pol == CF_POL_TM) return comp == CF_EZ ? 0 : comp == CF_HX ? 1 : comp == CF_HY ? 2 : -1;
+    if (pol == CF_POL_TE) return comp == CF_EX ? 0 : comp == CF_EY ? 1 : comp == CF_HZ ? 2 : -1;
+    return comp;
+}
+
+int n_comp_for(int ndim) { return ndim == 2 ? 3 : 6; }
+
+static bool spans_periodic(const Problem& p, int a) {
+    return p.grid.bc[a] == CF_BC_PERIODIC && p.surf.lo[a] == 0 && p.surf.hi[a] == p.grid.n[a];
+}
+
+// Points along one axis for a sample at doubled coordinate s2 and a
+// component with doubled offset o2: one point (weight 1) when they coincide,
+// else the two neighbours with weight 1/2.
+static bool axis_points(int s2, int o2, int n, bool periodic, int* i, double* w, int* np) {
+    int d = s2 - o2;
+    if ((d % 2 + 2) % 2 == 0) {
+        i[0] = d / 2;
+        w[0] = 1.0;
+        *np = 1;
+    } else {
+        i[0] = (d - 1) / 2;
+        i[1] = (d + 1) / 2;
+        w[0] = w[1] = 0.5;
+        *np = 2;
+    }
+    for (int k = 0; k < *np; ++k) {
+        if (periodic) {
+            i[k] = ((i[k] % n) + n) % n;
+        } else if (i[k] < 0 || i[k] >= n) {
+            return false;
+        }
+    }
+    return true;
+}
+
+static std::string make_gather(const Problem& p, int fi, int comp, Gather& g) {
+    const Face& f = p.faces[fi];
+    g.face = fi;
+    g.comp = comp;
+    g.nsamp = f.nsamp;
+    g.P = 0;
+    g.idx.clear();
+    g.w.clear();
+    for (int s = 0; s < f.nsamp; ++s) {
+        int t[2] = {0, 0};
+        if (f.ntang == 1) {
+            t[0] = s;
+        } else {
+            t[0] = s / f.count[1];
+            t[1] = s % f.count[1];
+        }
+        int pi[3][2];
+        double pw[3][2];
+        int pn[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            if (ax >= p.grid.ndim) {
+                pi[ax][0] = 0;
+                pw[ax][0] = 1.0;
+                pn[ax] = 1;
+                continue;
+            }
+            int s2;
+            if (ax == f.axis) {
+                s2 = 2 * f.plane;
+            } else {
+                int k = (f.tang[0] == ax) ? 0 : 1;
+                s2 = 2 * (f.start[k] + t[k]) + 1;
+            }
+            if (!axis_points(s2, kOffset2[comp][ax], p.grid.n[ax], p.grid.bc[ax] == CF_BC_PERIODIC,
+                             pi[ax], pw[ax], &pn[ax]))
+                return "stress surface stencil leaves the grid";
+        }
+        int count = 0;
+        for (int a = 0; a < pn[0]; ++a)
+            for (int b = 0; b < pn[1]; ++b)
+                for (int c = 0; c < pn[2]; ++c) {
+                    int64_t flat = ((int64_t)pi[2][c] * p.ny + pi[1][b]) * p.nx + pi[0][a];
+                    g.idx.push_back((int32_t)flat);
+                    g.w.push_back(pw[0][a] * pw[1][b] * pw[2][c]);
+                    ++count;
+                }
+        if (s == 0) g.P = count;
+        if (count != g.P) return "non-uniform interpolation stencil";
+    }
+    // adjoint (scatter) form, distinct points in ascending order
+    std::map<int32_t, std::vector<std::pair<int32_t, double>>> by_point;
+    for (int s = 0; s < g.nsamp; ++s)
+        for (int q = 0; q < g.P; ++q) by_point[g.idx[s * g.P + q]].push_back({s, g.w[s * g.P + q]});
+    g.uidx.clear();
+    g.uoff.assign(1, 0);
+    g.usamp.clear();
+    g.uw.clear();
+    for (auto& kv : by_point) {
+        g.uidx.push_back(kv.first);
+        for (auto& sw : kv.second) {
+            g.usamp.push_back(sw.first);
+            g.uw.push_back(sw.second);
+        }
+        g.uoff.push_back((int32_t)g.usamp.size());
+    }
+    return "";
+}
+
+// Cosine basis on N midpoints of a face of length L = N dx:
+// f_0 = sqrt(1/L), f_n = sqrt(2/L) cos(n pi (i + 1/2) / N).
+static std::vector<double> cosine_rows(int N, int nh, double dx) {
+    int rows = std::min(nh, N);
+    std::vector<double> b((size_t)rows * N);
+    double L = N * dx;
+    for (int n = 0; n < rows; ++n) {
+        double c = std::sqrt((n == 0 ? 1.0 : 2.0) / L);
+        for (int i = 0; i < N; ++i) b[(size_t)n * N + i] = c * std::cos(M_PI * n * (i + 0.5) / N);
+    }
+    return b;
+}
+
+std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surface& s,
+                          Problem& p) {
+    if (g.ndim != 2 && g.ndim != 3) return "ndim must be 2 or 3";
+    for (int a = 0; a < 3; ++a)
+        if (g.n[a] < 1) return "grid sizes must be positive";
+    if (g.ndim == 2 && g.n[2] != 1) return "2D grids need n[2] == 1";
+    if (!(g.res > 0)) return "res must be positive";
+    int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    if (ncell >= (int64_t)1 << 31) return "grid too large for 32-bit cell indices";
+    for (int a = 0; a < g.ndim; ++a) {
+        if (g.bc[a] < CF_BC_PEC || g.bc[a] > CF_BC_PML) return "unknown boundary";
+        if (g.bc[a] == CF_BC_PML && (g.pml_cells[a] < 1 || 2 * g.pml_cells[a] >= g.n[a]))
+            return "PML thickness out of range";
+    }
+    if (m.n_materials < 1 || m.n_materials > 254 || !m.eps || !m.mu) return "bad material table";
+    p.grid = g;
+    if (g.ndim == 2) {
+        p.grid.bc[2] = CF_BC_PERIODIC;
+        p.grid.pml_cells[2] = 0;
+    }
+    p.nx = g.n[0];
+    p.ny = g.n[1];
+    p.nz = g.n[2];
+    p.ncell = ncell;
+    p.nmat = m.n_materials;
+    p.eps.assign(m.eps, m.eps + m.n_materials);
+    p.mu.assign(m.mu, m.mu + m.n_materials);
+    for (int i = 0; i < p.nmat; ++i) {
+        bool pec = std::isinf(p.eps[i]) && p.eps[i] < 0;
+        bool pmc = std::isinf(p.mu[i]) && p.mu[i] < 0;
+        if (!pec && !(p.eps[i] > 0 && std::isfinite(p.eps[i]))) return "eps must be > 0 or -inf";
+        if (!pmc && !(p.mu[i] > 0 && std::isfinite(p.mu[i]))) return "mu must be > 0 or -inf";
+    }
+    for (int c = 0; c < kNumComp; ++c) {
+        if (m.comp_id[c]) {
+            p.ids[c].assign(m.comp_id[c], m.comp_id[c] + ncell);
+            for (uint8_t v : p.ids[c])
+                if (v >= p.nmat) return "material id out of range";
+        } else {
+            p.ids[c].assign(ncell, 0);
+        }
+    }
+    // E components lying on a PEC(-backed) wall: integer coordinate 0 along
+    // a non-periodic axis.
+    for (int c = 0; c < 3; ++c)
+        for (int a = 0; a < p.grid.ndim; ++a) {
+            if (p.grid.bc[a] == CF_BC_PERIODIC || kOffset2[c][a] != 0) continue;
+            for (int k = 0; k < p.nz; ++k)
+                for (int j = 0; j < p.ny; ++j)
+                    for (int i = 0; i < p.nx; ++i) {
+                        int coord = a == 0 ? i : a == 1 ? j : k;
+                        if (coord == 0) p.ids[c][((int64_t)k * p.ny + j) * p.nx + i] = kWallId;
+                    }
+        }
+    // stress surface
+    p.surf = s;
+    if (s.force_axis < 0 || s.force_axis >= g.ndim) return "force_axis out of range";
+    if (s.n_harm < 1) return "n_harm must be >= 1";
+    p.faces.clear();
+    for (int a = 0; a < g.ndim; ++a) {
+        if (s.lo[a] >= s.hi[a]) return "surface box is empty";
+        if (spans_periodic(p, a)) continue;
+        Face f{};
+        f.axis = a;
+        f.ntang = 0;
+        f.nsamp = 1;
+        for (int b = 0; b < g.ndim; ++b) {
+            if (b == a) continue;
+            f.tang[f.ntang] = b;
+            f.start[f.ntang] = s.lo[b];
+            f.count[f.ntang] = s.hi[b] - s.lo[b];
+            f.nsamp *= f.count[f.ntang];
+            ++f.ntang;
+        }
+        for (int side : {-1, +1}) {
+            f.side = side;
+            f.plane = side < 0 ? s.lo[a] : s.hi[a];
+            f.index = 2 * a + (side > 0);
+            p.faces.push_back(f);
+        }
+    }
+    if (p.faces.empty()) return "surface has no faces";
+    double dx = 1.0 / g.res;
+    p.basis.clear();
+    p.labels.clear();
+    p.nrows.clear();
+    for (const Face& f : p.faces) {
+        if (f.ntang == 1) {
+            auto b = cosine_rows(f.count[0], s.n_harm, dx);
+            int rows = (int)(b.size() / f.count[0]);
+            std::vector<int> lab(rows);
+            for (int r = 0; r < rows; ++r) lab[r] = r;
+            p.basis.push_back(b);
+            p.labels.push_back(lab);
+            p.nrows.push_back(rows);
+        } else {
+            auto bu = cosine_rows(f.count[0], s.n_harm, dx);
+            auto bv = cosine_rows(f.count[1], s.n_harm, dx);
+            int ru = (int)(bu.size() / f.count[0]), rv = (int)(bv.size() / f.count[1]);
+            std::vector<double> b((size_t)ru * rv * f.nsamp);
+            std::vector<int> lab;
+            for (int mm = 0; mm < ru; ++mm)
+                for (int nn = 0; nn < rv; ++nn) {
+                    size_t row = (size_t)mm * rv + nn;
+                    for (int i0 = 0; i0 < f.count[0]; ++i0)
+                        for (int i1 = 0; i1 < f.count[1]; ++i1)
+                            b[row * f.nsamp + (size_t)i0 * f.count[1] + i1] =
+                                bu[(size_t)mm * f.count[0] + i0] * bv[(size_t)nn * f.count[1] + i1];
+                    lab.push_back(mm * s.n_harm + nn);
+                }
+            p.basis.push_back(b);
+            p.labels.push_back(lab);
+            p.nrows.push_back(ru * rv);
+        }
+    }
+    // interpolation tables for every (face, component)
+    p.gathers.clear();
+    p.gather_of.clear();
+    std::set<double> e_vals, h_vals;
+    for (int fi = 0; fi < (int)p.faces.size(); ++fi)
+        for (int c = 0; c < kNumComp; ++c) {
+            Gather gt;
+            std::string err = make_gather(p, fi, c, gt);
+            if (!err.empty()) return err;
+            for (int32_t ix : gt.idx) {
+                int id = p.ids[c][ix];
+                if (is_e(c)) {
+                    e_vals.insert(id == kWallId ? -INFINITY : p.eps[id]);
+                } else {
+                    h_vals.insert(p.mu[id]);
+                }
+            }
+            p.gather_of[{fi, c}] = (int)p.gathers.size();
+            p.gathers.push_back(std::move(gt));
+        }
+    if (e_vals.size() != 1 || h_vals.size() != 1)
+        return "stress surface does not lie in one uniform medium";
+    p.eps_s = *e_vals.begin();
+    p.mu_s = *h_vals.begin();
+    if (!(std::isfinite(p.eps_s) && p.eps_s > 0 && std::isfinite(p.mu_s) && p.mu_s > 0))
+        return "stress surface touches a conductor";
+    return "";
+}
+
+std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
+    *code = CF_E_ARG;
+    if (!(o.sigma >= 0) || !std::isfinite(o.sigma)) return "sigma must be >= 0";
+    if (!(o.courant > 0)) return "courant must be > 0";
+    if (o.n_steps < 1) return "n_steps must be >= 1";
+    if (o.precision != CF_FP64 && o.precision != CF_FP32) return "unknown precision";
+    if (o.path != CF_PATH_BATCHED && o.path != CF_PATH_PLAIN) return "unknown path";
+    if (o.kernel != CF_KERNEL_GENERAL && o.kernel != CF_KERNEL_ZINV2D) return "unknown kernel";
+    if (p.grid.ndim == 2) {
+        if (o.pol < 1 || o.pol > 3) return "2D runs take CF_POL_TM and/or CF_POL_TE";
+    } else {
+        if (o.pol != CF_POL_3D) return "3D runs take CF_POL_3D";
+        if (o.kernel == CF_KERNEL_ZINV2D) {
+            *code = CF_E_UNSUPPORTED;
+            return "the z-invariant kernel applies to 2D runs only";
+        }
+    }
+    if (p.grid.ndim == 2) {
+        for (int a = 0; a < 2; ++a)
+            if (p.grid.bc[a] == CF_BC_PML) {
+                *code = CF_E_UNSUPPORTED;
+                return "PML is implemented for 3D grids";
+            }
+    } else {
+        if (p.grid.bc[0] == CF_BC_PML || p.grid.bc[1] == CF_BC_PML) {
+            *code = CF_E_UNSUPPORTED;
+            return "3D PML is implemented along z only";
+        }
+    }
+    // Yee stability: dt * v_max * sqrt(ndim) / dx < 1
+    double emin = INFINITY;
+    for (int i = 0; i < p.nmat; ++i) {
+        double e = std::isfinite(p.eps[i]) ? p.eps[i] : INFINITY;
+        double m = std::isfinite(p.mu[i]) ? p.mu[i] : INFINITY;
+        emin = std::min(emin, e * m);
+    }
+    if (!std::isfinite(emin)) emin = 1.0;
+    double vmax = 1.0 / std::sqrt(emin);
+    if (o.courant * vmax * std::sqrt((double)p.grid.ndim) >= 1.0) {
+        *code = CF_E_CFL;
+        return "courant number above the Yee stability limit";
+    }
+    *code = CF_OK;
+    return "";
+}
+
+// Stress-tensor channels for force axis d and a face with normal a
+// (Minkowski tensor with the medium's eps_S, mu_S):
+//   a == d: E(k->k) eps_S (delta_kd - 1/2), H(k->k) mu_S (delta_kd - 1/2)
+//   a != d: E(a->d) eps_S and H(a->d) mu_S when both components exist.
+std::vector<Channel> channel_table(const Problem& p, int pol_mask) {
+    std::vector<Channel> out;
+    const int d = p.surf.force_axis;
+    std::vector<int> pols;
+    if (p.grid.ndim == 3) {
+        pols = {CF_POL_3D};
+    } else {
+        if (pol_mask & CF_POL_TM) pols.push_back(CF_POL_TM);
+        if (pol_mask & CF_POL_TE) pols.push_back(CF_POL_TE);
+    }
+    for (int pol : pols) {
+        std::vector<int> e, h;
+        pol_components(pol, e, h);
+        auto has = [](const std::vector<int>& v, int c) {
+            return std::find(v.begin(), v.end(), c) != v.end();
+        };
+        for (int fi = 0; fi < (int)p.faces.size(); ++fi) {
+            const Face& f = p.faces[fi];
+            const int a = f.axis;
+            struct Spec { int kind, src, meas; double coef; };
+            std::vector<Spec> specs;
+            if (a == d) {
+                for (int c : e) specs.push_back({0, c, c, p.eps_s * ((c == d ? 1.0 : 0.0) - 0.5)});
+                for (int c : h) specs.push_back({1, c, c, p.mu_s * ((c - 3 == d ? 1.0 : 0.0) - 0.5)});
+            } else {
+                if (has(e, a) && has(e, d)) specs.push_back({0, a, d, p.eps_s});
+                if (has(h, 3 + a) && has(h, 3 + d)) specs.push_back({1, 3 + a, 3 + d, p.mu_s});
+            }
+            for (int r = 0; r < p.nrows[fi]; ++r)
+                for (const Spec& sp : specs) {
+                    Channel ch;
+                    ch.face = fi;
+                    ch.row = r;
+                    ch.label = p.labels[fi][r];
+                    ch.kind = sp.kind;
+                    ch.pol = pol;
+                    ch.src = sp.src;
+                    ch.meas = sp.meas;
+                    ch.sign = (double)f.side * sp.coef;
+                    out.push_back(ch);
+                }
+        }
+    }
+    return out;
+}
+
+// Time-centred conductivity: a lossy component of a channel's kind gets
+// a = (1 - r)/(1 + r), b = S_c/(eps or mu)/(1 + r), r = sigma dt / 2; the
+// other field of the run is lossless (a = 1, b = S_c/(eps or mu)).  A
+// conductor (PEC for E, PMC for H, or a wall E component) gets a = b = 0.
+std::vector<double> coefficient_lut(const Problem& p, double sigma, double courant) {
+    std::vector<double> lut(2 * kNumComp * 256 * 2, 0.0);
+    const double dt = courant / p.grid.res;
+    const double r = 0.5 * sigma * dt;
+    const double la = (1.0 - r) / (1.0 + r), lb = 1.0 / (1.0 + r);
+    for (int kind = 0; kind < 2; ++kind)
+        for (int c = 0; c < kNumComp; ++c)
+            for (int id = 0; id < 256; ++id) {
+                double a = 0, b = 0;
+                bool valid = id < p.nmat || (id == kWallId && is_e(c));
+                if (valid) {
+                    double v;
+                    if (is_e(c)) v = id == kWallId ? -INFINITY : p.eps[id];
+                    else v = p.mu[id];
+                    if (std::isfinite(v)) {
+                        bool lossy = (kind == 0) == is_e(c);
+                        a = lossy ? la : 1.0;
+                        b = lossy ? courant / v * lb : courant / v;
+                    }
+                }
+                size_t at = ((size_t)(kind * kNumComp + c) * 256 + id) * 2;
+                lut[at] = a;
+                lut[at + 1] = b;
+            }
+    return lut;
+}
+
+// K(t) = 2 pi Im g(-t).  General form: the Laplace integral
+// int_0^inf (k + s/2) sqrt(1 + s/k) e^{-k t} dk, which the substitution
+// k + s/2 = (s/2) cosh u turns into (s^2/4) int_0^inf cosh u (cosh u + 1)
+// e^{-x (cosh u - 1)} du with x = s t / 2; the integrand is entire and
+// decays double-exponentially, so the trapezoidal rule in u converges
+// geometrically.  Near u = 0 the integrand behaves like exp(-x u^2 / 2), so
+// the step is min(1/8, 1/(2 sqrt(x))): both bounds keep the aliasing error
+// below exp(-70).
+// z-invariant 2D form: 1/t^3 + 3 s/(4 t^2) + s^2/(4 t).
+static double k_general(double t, double s) {
+    if (s == 0.0) return 1.0 / (t * t);
+    const double x = 0.5 * s * t;
+    const double h = std::min(0.125, 0.5 / std::sqrt(x));
+    double sum = 0.5 * 2.0;   // u = 0: cosh 0 (cosh 0 + 1) = 2, half weight
+    for (int k = 1;; ++k) {
+        double u = k * h;
+        double c = std::cosh(u);
+        double arg = x * (c - 1.0);
+        double term = c * (c + 1.0) * std::exp(-arg);
+        sum += term;
+        if (arg > 50.0 && term < 1e-18 * sum) break;
+        if (k > 100000) break;
+    }
+    return 0.25 * s * s * h * sum;
+}
+
+void kernel_table(int kernel, double sigma, double dt, int n, double* out) {
+    for (int m = 1; m <= n; ++m) {
+        double t = m * dt;
+        if (kernel == CF_KERNEL_ZINV2D)
+            out[m - 1] = 1.0 / (t * t * t) + 0.75 * sigma / (t * t) + 0.25 * sigma * sigma / t;
+        else
+            out[m - 1] = k_general(t, sigma);
+    }
+}
+
+}  // namespace cf

@@ -1,0 +1,94 @@
+// Host-side problem description and solve planning.
+//
+// A cf_problem holds the copied inputs plus everything derived from them that
+// does not depend on the run options: wall-marked material ids, the faces of
+// the stress surface S, the interpolation (gather) tables of every
+// (face, component) pair, the per-face cosine basis and the medium S lies in.
+// A SolvePlan adds what depends on the options: the channel table, the
+// coefficient look-up tables and the time kernel samples.
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/casimir_fdtd.h"
+
+namespace cf {
+
+constexpr int kWallId = 255;        // E components on a PEC(-backed) wall
+constexpr int kNumComp = 6;          // Ex Ey Ez Hx Hy Hz
+
+// doubled Yee offsets (x, y, z) of each component
+extern const int kOffset2[kNumComp][3];
+
+struct Face {
+    int index;        // 2*axis + (side > 0)
+    int axis;         // normal axis
+    int side;         // -1 / +1
+    int plane;        // integer coordinate of the plane
+    int ntang;        // tangential axes (1 in 2D, 2 in 3D)
+    int tang[2];
+    int start[2];
+    int count[2];
+    int nsamp;
+};
+
+// Interpolation W of one component on one face: for sample s, points
+// idx[s*P + p] with weights w[s*P + p].  The adjoint (scatter) form lists the
+// distinct grid points with the (sample, weight) pairs that touch them.
+struct Gather {
+    int face, comp, P, nsamp;
+    std::vector<int32_t> idx;
+    std::vector<double> w;
+    std::vector<int32_t> uidx;    // distinct grid points
+    std::vector<int32_t> uoff;    // CSR offsets into usamp/uw (size uidx+1)
+    std::vector<int32_t> usamp;
+    std::vector<double> uw;
+};
+
+struct Channel {
+    int face, row, label;
+    int kind;        // 0: E-current source, 1: H-current source
+    int pol;         // CF_POL_TM / CF_POL_TE / CF_POL_3D
+    int src, meas;   // component ids
+    double sign;
+};
+
+struct Problem {
+    cf_grid grid{};
+    int nx = 0, ny = 0, nz = 0;
+    int64_t ncell = 0;
+    int nmat = 0;
+    std::vector<double> eps, mu;
+    std::vector<uint8_t> ids[kNumComp];
+    cf_surface surf{};
+    std::vector<Face> faces;
+    std::vector<std::vector<double>> basis;   // per face: rows x nsamp
+    std::vector<std::vector<int>> labels;     // per face: label per row
+    std::vector<int> nrows;
+    std::map<std::pair<int, int>, int> gather_of;   // (face, comp) -> gathers index
+    std::vector<Gather> gathers;
+    double eps_s = 0, mu_s = 0;
+};
+
+// Components of each polarization: (E list, H list) as component ids.
+void pol_components(int pol, std::vector<int>& e, std::vector<int>& h);
+// Slot position of component `comp` inside a channel's field block.
+int comp_slot(int pol, int comp);
+int n_comp_for(int ndim);
+
+std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surface& s,
+                          Problem& p);   // returns "" or an error message
+std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code);
+std::vector<Channel> channel_table(const Problem& p, int pol_mask);
+
+// coefficient tables: lut[(kind*6 + comp)*256 + id] = (a, b)
+std::vector<double> coefficient_lut(const Problem& p, double sigma, double courant);
+
+// K(t_m), m = 1..n
+void kernel_table(int kernel, double sigma, double dt, int n, double* out);
+
+}  // namespace cf

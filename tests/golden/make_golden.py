@@ -1,0 +1,50 @@
+"""Write oracle results used as stored expected values by the GPU tests.
+
+Calls only the CPU oracle (oracle/) on the synthetic workloads of
+casimir_inputs; no value comes from the HIP library.
+
+    python tests/golden/make_golden.py c2      # 2D TE+TM piston, 400x200, T=10000
+    python tests/golden/make_golden.py c1      # 2D TM piston, 80x40, T=2000
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from casimir_inputs import c1_piston_tm_fp64, c2_piston_tetm_fp32  # noqa: E402
+
+CASES = {
+    "c1": ("c1_piston_tm_oracle.json", c1_piston_tm_fp64),
+    "c2": ("c2_piston_tetm_oracle.json", c2_piston_tetm_fp32),
+}
+
+
+def main(which, workers=8):
+    fname, make = CASES[which]
+    wl = make()
+    t0 = time.time()
+    r = oracle.solve(wl, workers=workers, chunk=16)
+    out = dict(
+        workload=wl.name, shape=list(wl.shape), n_steps=wl.n_steps, sigma=wl.sigma,
+        courant=wl.courant, kernel=wl.kernel, pol=wl.pol, n_harm=wl.n_harm,
+        force=r.force,
+        per_channel=[float(v) for v in r.acc],
+        sign=[float(v) for v in r.sign],
+        per_harmonic={str(k): v for k, v in sorted(r.per_harmonic.items())},
+        per_face={str(k): v for k, v in sorted(r.per_face.items())},
+        oracle_seconds=time.time() - t0,
+        workers=workers,
+        source="oracle.solve (FP64 NumPy), written by tests/golden/make_golden.py",
+    )
+    with open(os.path.join(HERE, fname), "w") as f:
+        json.dump(out, f, indent=1)
+    print(which, r.force, f"{time.time() - t0:.1f}s")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1])

@@ -1,0 +1,192 @@
+"""GPU parity of the HIP library against the FP64 oracle (2D).
+
+Tolerances:
+* FP64 fields: the GPU evaluates the same operations as the oracle up to
+  rounding order and fused multiply-adds (a few ulp per update).  The force
+  is a signed sum of per-channel terms that cancel strongly (the early-time
+  self response cancels between opposite faces), so rounding is bounded by
+  the summed magnitude of the terms, sum_c |sign_c acc_c| / pi, not by |F|.
+  The bar is 1e-9 of that magnitude for the force, the per-face and the
+  per-harmonic sums, and 1e-9 of the largest channel per channel.
+* FP32 fields with FP64 surface and time accumulation: on the benchmark-size
+  pistons the force must match the FP64 oracle to 1e-4 relative to |F| (the
+  target accuracy of the precision extension); on the small cases, whose
+  forces are tiny differences of large terms, to 1e-5 of the term magnitude.
+
+Every case prints its name before running so a failure on the box is named.
+Oracle results of the two benchmark-size pistons come from golden files
+written by tests/golden/make_golden.py (oracle only); small cases run the
+oracle in-process (single process: no worker pool is forked after the GPU
+is initialised).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from casimir_inputs import c1_piston_tm_fp64, c2_piston_tetm_fp32, parallel_plates_1d
+from casimir_inputs.configs import piston2d
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def announce(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+def run(cf, wl, **over):
+    opts = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol=wl.pol,
+                kernel=wl.kernel, precision=wl.precision)
+    opts.update(over)
+    return cf.Problem.from_workload(wl).solve(**opts)
+
+
+class Golden:
+    """Oracle result read from a golden file (same fields as OracleResult)."""
+
+    def __init__(self, d):
+        self.force = d["force"]
+        self.acc = np.array(d["per_channel"])
+        self.sign = np.array(d["sign"])
+        self.per_face = {int(k): v for k, v in d["per_face"].items()}
+        self.per_harmonic = {int(k): v for k, v in d["per_harmonic"].items()}
+        self.channels = d["per_channel"]
+
+
+def golden(name):
+    path = os.path.join(HERE, "golden", name)
+    if not os.path.exists(path):
+        pytest.skip(f"golden oracle result {name} not generated")
+    return Golden(json.load(open(path)))
+
+
+def compare(gpu, ref, rtol_force, rtol_chan, force_vs="terms"):
+    scale = np.max(np.abs(ref.acc))
+    terms = float(np.sum(np.abs(ref.sign * ref.acc)) / np.pi)
+    if force_vs == "terms":
+        assert abs(gpu["force"] - ref.force) <= rtol_force * terms
+    else:
+        assert gpu["force"] == pytest.approx(ref.force, rel=rtol_force)
+    np.testing.assert_allclose(gpu["per_channel"], ref.acc, rtol=0, atol=rtol_chan * scale)
+    fscale = terms
+    for f, v in ref.per_face.items():
+        assert abs(gpu["per_face"][f] - v) <= rtol_chan * fscale
+    for k, v in ref.per_harmonic.items():
+        assert abs(gpu["per_harmonic"][k] - v) <= rtol_chan * fscale
+
+
+@pytest.fixture(scope="module")
+def c1_ref():
+    return golden("c1_piston_tm_oracle.json")
+
+
+def test_c1_fp64_batched(cf, c1_ref):
+    announce("c1 fp64 batched 80x40 TM T=2000")
+    g = run(cf, c1_piston_tm_fp64())
+    assert g["n_channels"] == len(c1_ref.channels) == 116
+    compare(g, c1_ref, 1e-9, 1e-9)
+    assert g["force"] == pytest.approx(c1_ref.force, rel=1e-9)
+
+
+def test_c1_fp64_plain_bitwise_equals_batched(cf):
+    announce("c1 fp64 plain vs batched, 12-channel subset")
+    wl = c1_piston_tm_fp64()
+    sub = list(range(0, 116, 10))
+    a = run(cf, wl, channel_subset=sub)
+    b = run(cf, wl, channel_subset=sub, path="plain")
+    np.testing.assert_array_equal(a["per_channel"], b["per_channel"])
+    assert a["force"] == b["force"]
+
+
+def test_c1_fp32_within_1e4(cf, c1_ref):
+    announce("c1 fp32 fields, fp64 accumulation")
+    g = run(cf, c1_piston_tm_fp64(), precision="fp32")
+    rel = abs(g["force"] / c1_ref.force - 1)
+    print(f"c1 fp32 force rel err {rel:.3e}")
+    assert rel <= 1e-4
+
+
+def test_deterministic(cf):
+    announce("c1 fp32 determinism, two runs")
+    wl = c1_piston_tm_fp64(n_steps=400)
+    a = run(cf, wl, precision="fp32")
+    b = run(cf, wl, precision="fp32")
+    np.testing.assert_array_equal(a["per_channel"], b["per_channel"])
+
+
+SMALL = {
+    "te_pec": lambda: piston2d(40, 24, 4, 10, 5, 10, 7, 10.0, pol="TE", n_steps=500, n_harm=40),
+    "tmte_pec": lambda: piston2d(40, 24, 4, 10, 5, 10, 7, 10.0, pol="TM+TE", n_steps=300, n_harm=8),
+    "tmte_pmc": lambda: piston2d(40, 24, 4, 10, 5, 10, 7, 10.0, pol="TM+TE", n_steps=300, n_harm=8,
+                                 sidewall="pmc"),
+    "tmte_mu5": lambda: piston2d(40, 24, 4, 10, 5, 10, 7, 10.0, pol="TM+TE", n_steps=300, n_harm=8,
+                                 sidewall="mu5"),
+    "plates_periodic_faces": lambda: parallel_plates_1d(10, 1.0, 0.5, 1.5, ny=6, pol="TM+TE",
+                                                        n_steps=400),
+    "x_periodic": lambda: piston2d(40, 24, 4, 10, 5, 10, 7, 10.0, pol="TM+TE", n_steps=300,
+                                   n_harm=8).replace(bc=("periodic", "pec", "periodic")),
+    "one_harmonic_one_step": lambda: piston2d(40, 24, 4, 10, 5, 10, 7, 10.0, pol="TM+TE", n_steps=1,
+                                              n_harm=1),
+    "general_kernel_sigma2": lambda: piston2d(40, 24, 4, 10, 5, 10, 7, 10.0, pol="TM+TE", n_steps=250,
+                                              n_harm=6, kernel="general", sigma=2.0),
+    "ragged_61x37": lambda: piston2d(61, 37, 5, 13, 7, 11, 14, 10.0, pol="TM+TE", n_steps=200,
+                                     n_harm=50),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SMALL))
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_small_cases(cf, name, precision):
+    announce(f"small {name} {precision}")
+    wl = SMALL[name]()
+    ref = oracle.solve(wl)
+    g = run(cf, wl, precision=precision)
+    if precision == "fp64":
+        compare(g, ref, 1e-9, 1e-9)
+    else:
+        compare(g, ref, 1e-5, 1e-5)
+
+
+def test_gamma_and_trace(cf):
+    announce("gamma and trace, small TM+TE")
+    wl = SMALL["tmte_pec"]()
+    ref = oracle.solve(wl, keep_gamma=True)
+    g = run(cf, wl, keep_gamma=True)
+    scale = np.max(np.abs(ref.gamma))
+    np.testing.assert_allclose(g["gamma"], ref.gamma, rtol=0, atol=1e-10 * scale)
+    np.testing.assert_allclose(g["trace"], ref.trace, rtol=0, atol=1e-9 * np.max(np.abs(ref.trace)))
+
+
+def test_subset_equals_full(cf):
+    announce("channel subset equals full run entries")
+    wl = SMALL["tmte_pec"]()
+    full = run(cf, wl, precision="fp32")
+    sub = [3, 0, 17, len(full["per_channel"]) - 1]
+    part = run(cf, wl, precision="fp32", channel_subset=sub)
+    np.testing.assert_array_equal(part["per_channel"], full["per_channel"][sub])
+
+
+def test_error_surface_on_device_path(cf):
+    announce("invalid options raise before any launch")
+    wl = SMALL["tmte_pec"]()
+    p = cf.Problem.from_workload(wl)
+    with pytest.raises(cf.CfError):
+        p.solve(pol="TM", courant=0.9, n_steps=10)
+    with pytest.raises(cf.CfError):
+        p.solve(pol="TM", n_steps=10, channel_subset=[10 ** 6])
+
+
+def test_c2_full_size_bench_configuration(cf):
+    """400x200 TE+TM, 448 channels, T = 10000, FP32 fields, batched: the
+    launch configuration the benchmark times, against the full FP64 oracle
+    run stored by tests/golden/make_golden.py."""
+    ref = golden("c2_piston_tetm_oracle.json")
+    announce("c2 full size fp32 batched 400x200 TE+TM T=10000")
+    g = run(cf, c2_piston_tetm_fp32())
+    rel = abs(g["force"] / ref.force - 1)
+    print(f"c2 fp32 force {g['force']:.12e} oracle {ref.force:.12e} rel {rel:.3e}")
+    assert rel <= 1e-4
+    np.testing.assert_allclose(g["per_channel"], ref.acc, rtol=0, atol=1e-5 * np.max(np.abs(ref.acc)))

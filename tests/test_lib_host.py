@@ -1,0 +1,108 @@
+"""Host-side checks of the HIP library through its C ABI (no GPU needed).
+
+* the shared library loads and exports every function include/casimir_fdtd.h
+  declares;
+* its time-kernel table (its own quadrature) matches the oracle's closed form;
+* its channel table (faces, labels, kinds, components, signs) is the
+  oracle's, channel for channel;
+* validation rejects CFL violations, surfaces outside a uniform medium and
+  unsupported option combinations with the documented status codes.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from casimir_inputs import c1_piston_tm_fp64, c2_piston_tetm_fp32, c4_sphere_plate, parallel_plates_1d
+from casimir_inputs.configs import piston2d
+from oracle.force import setup as oracle_setup
+from oracle.kernels import kernel_table as oracle_ktab
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COMP_ID = {"Ex": 0, "Ey": 1, "Ez": 2, "Hx": 3, "Hy": 4, "Hz": 5}
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "casimir_fdtd.h")).read()
+    return sorted(set(re.findall(r"^(?:cf_status|const char\*)\s+(cf_\w+)\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol(cf):
+    lib = cf.load()
+    names = declared_functions()
+    assert "cf_solve" in names and len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("kernel", ["general", "zinv2d"])
+@pytest.mark.parametrize("sigma,dt,n", [(1.0, 0.0125, 10000), (1.0, 0.025, 2000), (10.0, 0.01, 3000),
+                                        (0.0, 0.02, 500), (0.3, 0.5, 400)])
+def test_kernel_table_matches_oracle(cf, kernel, sigma, dt, n):
+    mine = cf.kernel_table(kernel, sigma, dt, n)
+    ref = oracle_ktab(kernel, sigma, dt, n)
+    np.testing.assert_allclose(mine, ref, rtol=2e-14, atol=0)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: c1_piston_tm_fp64(),
+    lambda: c2_piston_tetm_fp32(),
+    lambda: parallel_plates_1d(10, 1.0, 0.5, 1.5, ny=6, pol="TM+TE"),
+    lambda: c4_sphere_plate(n_harm=3),
+])
+def test_channel_table_matches_oracle(cf, make):
+    wl = make()
+    p = cf.Problem.from_workload(wl)
+    tab = p.channel_table(pol=wl.pol, kernel=wl.kernel)
+    faces, bases, eps_s, mu_s, chans = oracle_setup(wl)
+    assert len(chans) == len(tab["face"])
+    for c, ch in enumerate(chans):
+        assert tab["face"][c] == faces[ch.face].index
+        assert tab["label"][c] == ch.label
+        assert tab["kind"][c] == (0 if ch.kind == "E" else 1)
+        assert tab["src"][c] == COMP_ID[ch.src] and tab["meas"][c] == COMP_ID[ch.meas]
+        assert tab["sign"][c] == pytest.approx(ch.sign, rel=1e-15)
+    info = p.info(pol=wl.pol, kernel=wl.kernel)
+    assert info["eps_s"] == eps_s and info["mu_s"] == mu_s
+
+
+def test_c2_channel_count_and_workspace(cf):
+    wl = c2_piston_tetm_fp32()
+    p = cf.Problem.from_workload(wl)
+    info = p.info(pol="TM+TE", kernel="zinv2d", precision="fp32", n_steps=10000)
+    # faces: x-faces 24 samples (clamped from 40 harmonics), y-faces 44 samples
+    assert info["n_channels"] == 2 * (2 * 24 * 3 + 2 * 40 * 1)
+    assert info["workspace_bytes"] >= info["n_channels"] * 3 * 400 * 200 * 4
+
+
+def test_validation_errors(cf):
+    wl = c1_piston_tm_fp64()
+    p = cf.Problem.from_workload(wl)
+    p.validate(pol="TM", courant=0.5)
+    with pytest.raises(cf.CfError) as e:
+        p.validate(pol="TM", courant=0.75)       # 2D Yee limit 1/sqrt(2)
+    assert e.value.status == "CF_E_CFL"
+    with pytest.raises(cf.CfError) as e:
+        p.validate(pol="3D")
+    assert e.value.status == "CF_E_ARG"
+    # S placed on the block's surface
+    bad = wl.replace(s_lo=(50, 15, 0), s_hi=(70, 25, 1))
+    with pytest.raises(cf.CfError) as e:
+        cf.Problem.from_workload(bad)
+    assert e.value.status == "CF_E_SURFACE"
+    # S leaving the grid
+    bad = wl.replace(s_lo=(0, 13, 0), s_hi=(72, 27, 1))
+    with pytest.raises(cf.CfError) as e:
+        cf.Problem.from_workload(bad)
+    assert e.value.status == "CF_E_SURFACE"
+
+
+def test_invalid_material_ids_rejected(cf):
+    wl = c1_piston_tm_fp64()
+    ids = dict(wl.comp_ids)
+    ids["Ez"] = ids["Ez"].copy()
+    ids["Ez"][0, 0, 0] = 9
+    with pytest.raises(cf.CfError) as e:
+        cf.Problem.from_workload(wl.replace(comp_ids=ids))
+    assert e.value.status == "CF_E_ARG"
