@@ -118,8 +118,10 @@ typedef struct cf_surface {
  * CF_FLAG_TIME_STENCIL brackets sampled launches of the field-update
  * kernel with HIP events on the solve's stream and reports their average
  * duration (cf_result.stencil_ms_avg); the stepping loop is otherwise
- * unchanged. */
-enum { CF_FLAG_KEEP_GAMMA = 1, CF_FLAG_TIME_STENCIL = 2 };
+ * unchanged.
+ * CF_FLAG_SPLIT makes the batched path use one launch per half step instead
+ * of the fused multi-step kernel (same arithmetic, bitwise-equal results). */
+enum { CF_FLAG_KEEP_GAMMA = 1, CF_FLAG_TIME_STENCIL = 2, CF_FLAG_SPLIT = 4 };
 
 typedef struct cf_opts {
     double sigma;       /* uniform conductivity (decay rate), >= 0            */
@@ -170,6 +172,7 @@ typedef struct cf_result {
     double stencil_alg_bytes;    /* algorithmic HBM bytes of one field-update launch:               */
                                  /* one read + one write of the state it advances                   */
     double stencil_cell_updates; /* cell-updates one field-update launch performs                   */
+    int fused;                   /* 1 when the fused multi-step kernel advanced the fields          */
 } cf_result;
 
 typedef struct cf_problem cf_problem;

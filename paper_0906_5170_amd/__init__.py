@@ -24,6 +24,7 @@ PRECISION = {"fp64": 0, "fp32": 1}
 PATH = {"batched": 0, "plain": 1}
 FLAG_KEEP_GAMMA = 1
 FLAG_TIME_STENCIL = 2
+FLAG_SPLIT = 4
 STATUS = {0: "CF_OK", 1: "CF_E_ARG", 2: "CF_E_CFL", 3: "CF_E_SURFACE", 4: "CF_E_BUDGET",
           5: "CF_E_NONFINITE", 6: "CF_E_DEVICE", 7: "CF_E_CANCELLED", 8: "CF_E_UNSUPPORTED"}
 
@@ -73,7 +74,8 @@ class _Result(C.Structure):
                 ("n_channels_run", C.c_int), ("cell_updates", C.c_double),
                 ("device_ms", C.c_double), ("stencil_ms_avg", C.c_double),
                 ("stencil_samples", C.c_int), ("stencil_launches", C.c_int),
-                ("stencil_alg_bytes", C.c_double), ("stencil_cell_updates", C.c_double)]
+                ("stencil_alg_bytes", C.c_double), ("stencil_cell_updates", C.c_double),
+                ("fused", C.c_int)]
 
 
 _lib = None
@@ -193,7 +195,7 @@ class Problem:
 
     def _opts(self, sigma=1.0, courant=0.5, n_steps=1000, pol="TM", kernel="zinv2d",
               precision="fp64", path="batched", keep_gamma=False, channel_subset=None, stream=None,
-              time_stencil=False):
+              time_stencil=False, split=False):
         o = _Opts()
         o.sigma = float(sigma)
         o.courant = float(courant)
@@ -202,7 +204,8 @@ class Problem:
         o.kernel = KERNEL[kernel]
         o.precision = PRECISION[precision]
         o.path = PATH[path]
-        o.flags = (FLAG_KEEP_GAMMA if keep_gamma else 0) | (FLAG_TIME_STENCIL if time_stencil else 0)
+        o.flags = ((FLAG_KEEP_GAMMA if keep_gamma else 0) | (FLAG_TIME_STENCIL if time_stencil else 0)
+                   | (FLAG_SPLIT if split else 0))
         if channel_subset is not None:
             sub = np.ascontiguousarray(channel_subset, dtype=np.int32)
             o.channel_subset = sub.ctypes.data_as(C.POINTER(C.c_int))
@@ -273,7 +276,7 @@ class Problem:
                    device_ms=r.device_ms, stencil_ms_avg=r.stencil_ms_avg,
                    stencil_samples=r.stencil_samples, stencil_launches=r.stencil_launches,
                    stencil_alg_bytes=r.stencil_alg_bytes,
-                   stencil_cell_updates=r.stencil_cell_updates)
+                   stencil_cell_updates=r.stencil_cell_updates, fused=bool(r.fused))
         if gam is not None:
             out["gamma"] = gam.reshape(T, C_run)
             out["trace"] = tr

@@ -21,7 +21,7 @@ ARCH = os.environ.get("CF_OFFLOAD_ARCH", "gfx950")
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-ffp-contract=fast", "-Wall", "-Wno-unused-result",
+    "-ffp-contract=off", "-Wall", "-Wno-unused-result",
     "-I", os.path.join(ROOT, "include"),
 ]
 

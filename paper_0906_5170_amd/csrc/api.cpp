@@ -39,11 +39,19 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Device workspace layout of one solve.
 struct Layout {
     size_t ids, lut, ktab, chans, slots, gidx, gw, uidx, uoff, usamp, uw, basis, acc, gamma,
-        fields, total;
+        fields, fields2, total;
     int n_field_slots;
 };
 
+// Tiling of the fused kernel: shifted so that every measured surface stencil
+// point of every channel lies in one tile (the surface tile).
+struct TBPlan {
+    bool ok = false;
+    int base_x = 0, base_y = 0, ntx = 0, nty = 0, stile = -1;
+};
+
 struct Staged {
+    TBPlan tb;
     std::vector<cf::Channel> chans;       // channels run, in output order
     std::vector<cf::ChanDev> dev;          // one descriptor per channel run
     std::vector<int> slots_tm, slots_te, slots_3d, slots_all;
@@ -53,6 +61,8 @@ struct Staged {
     int n_field_slots = 0;
     int ncomp = 3;
 };
+
+TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, cf::TBShape sh);
 
 std::vector<cf::Channel> selected_channels(const cf::Problem& p, const cf_opts& o, std::string* err) {
     std::vector<cf::Channel> all = cf::channel_table(p, o.pol);
@@ -117,6 +127,7 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         d.u_off = g_uoff[gs];
         d.n_uniq = (int)p.gathers[gs].uidx.size();
         d.basis_off = basis_face_off[ch.face] + ch.row * p.faces[ch.face].nsamp;
+        d.meas_slot = cf::comp_slot(ch.pol, ch.meas);
         d.kick_scale = -res / (ch.kind == 0 ? p.eps_s : p.mu_s);
         st.max_uniq = std::max(st.max_uniq, d.n_uniq);
         st.dev.push_back(d);
@@ -125,6 +136,45 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         else if (ch.pol == CF_POL_TE) st.slots_te.push_back((int)c);
         else st.slots_3d.push_back((int)c);
     }
+    if (!plain && p.grid.ndim == 2 && !(o.flags & CF_FLAG_SPLIT)) {
+        const cf::TBShape sh = o.precision == CF_FP64 ? cf::tb_shape<double>() : cf::tb_shape<float>();
+        st.tb = plan_tiles(p, chans, sh);
+    }
+}
+
+// Place the tile grid along one axis so that [lo, hi] sits in one tile of
+// width w: returns false when it cannot.
+static bool place_axis(int lo, int hi, int n, int w, int* base, int* ntiles, int* stile) {
+    const int span = hi - lo + 1;
+    if (span > w) return false;
+    const int X0 = lo - (w - span) / 2;
+    const int r = ((X0 % w) + w) % w;
+    *base = r == 0 ? 0 : r - w;
+    *ntiles = (n - *base + w - 1) / w;
+    *stile = (X0 - *base) / w;
+    return true;
+}
+
+TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, cf::TBShape sh) {
+    TBPlan t;
+    if (p.grid.ndim != 2 || chans.empty()) return t;
+    int xmin = p.nx, xmax = -1, ymin = p.ny, ymax = -1;
+    for (const auto& ch : chans) {
+        const cf::Gather& g = p.gathers[p.gather_of.at({ch.face, ch.meas})];
+        for (int32_t idx : g.idx) {
+            const int x = idx % p.nx, y = idx / p.nx;
+            xmin = std::min(xmin, x);
+            xmax = std::max(xmax, x);
+            ymin = std::min(ymin, y);
+            ymax = std::max(ymax, y);
+        }
+    }
+    int sx, sy;
+    if (!place_axis(xmin, xmax, p.nx, sh.tx, &t.base_x, &t.ntx, &sx)) return t;
+    if (!place_axis(ymin, ymax, p.ny, sh.ty, &t.base_y, &t.nty, &sy)) return t;
+    t.stile = sy * t.ntx + sx;
+    t.ok = true;
+    return t;
 }
 
 Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
@@ -152,13 +202,14 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.acc = take(C * 2 * 8);
     L.gamma = (o.flags & CF_FLAG_KEEP_GAMMA) ? take((size_t)o.n_steps * C * 8) : off;
     L.fields = take((size_t)st.n_field_slots * st.ncomp * p.ncell * fsz);
+    L.fields2 = st.tb.ok ? take((size_t)st.n_field_slots * st.ncomp * p.ncell * fsz) : off;
     L.total = off;
     L.n_field_slots = st.n_field_slots;
     return L;
 }
 
 struct StencilTiming {
-    double ms_avg = 0;
+    double ms_total = 0, bytes_total = 0, cu_total = 0;
     int samples = 0;
     int launches = 0;
 };
@@ -241,7 +292,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     const int stride = std::max(1, o.n_steps / 200);
     std::vector<hipEvent_t> tev;
     if (time_it) {
-        tev.resize(2 * ((o.n_steps + stride - 1) / stride));
+        tev.resize(2 * 256);
         for (auto& e : tev) CF_HIP(hipEventCreate(&e));
     }
     int tk = 0;
@@ -260,16 +311,73 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
         STEP_OK(cf::launch_h2d<T>(CF_POL_TE, 1, fields, dch, s_te, n_te, g, dlut, s));
         STEP_OK(cf::launch_e2d<T>(CF_POL_TM, 1, fields, dch, s_tm, n_tm, g, dlut, s));
         STEP_OK(cf::launch_e2d<T>(CF_POL_TE, 1, fields, dch, s_te, n_te, g, dlut, s));
-        for (int m = 0; m < o.n_steps; ++m) {
-            const bool sample = time_it && m % stride == 0;
-            if (sample) STEP_OK(hipEventRecord(tev[2 * tk], s));
-            STEP_OK(cf::launch_h2d<T>(CF_POL_TM, 0, fields, dch, s_tm, n_tm, g, dlut, s));
-            STEP_OK(cf::launch_h2d<T>(CF_POL_TE, 0, fields, dch, s_te, n_te, g, dlut, s));
-            STEP_OK(cf::launch_e2d<T>(CF_POL_TM, 0, fields, dch, s_tm, n_tm, g, dlut, s));
-            STEP_OK(cf::launch_e2d<T>(CF_POL_TE, 0, fields, dch, s_te, n_te, g, dlut, s));
-            if (sample) STEP_OK(hipEventRecord(tev[2 * tk++ + 1], s));
-            STEP_OK(cf::launch_surface<T>(fields, dch, s_all, (int)C, tabs, dk, m, dt, dA, dacc, dgam,
-                                          (int)C, s));
+        const double state_bytes = 2.0 * st.ncomp * sizeof(T);   // read + write of a cell's state
+        if (st.tb.ok) {
+            cf::TBGrid tg{};
+            tg.nx = p.nx;
+            tg.ny = p.ny;
+            tg.ncell = p.ncell;
+            tg.perx = g.perx;
+            tg.pery = g.pery;
+            for (int c = 0; c < cf::kNumComp; ++c) tg.ids[c] = g.ids[c];
+            tg.base_x = st.tb.base_x;
+            tg.base_y = st.tb.base_y;
+            tg.ntx = st.tb.ntx;
+            tg.nty = st.tb.nty;
+            tg.stile = st.tb.stile;
+            tg.dt = dt;
+            tg.dA = dA;
+            tg.ktab = dk;
+            tg.acc = dacc;
+            tg.gamma = dgam;
+            tg.gamma_stride = (int)C;
+            const int kh = cf::tb_shape<T>().kh;
+            T* A = fields;
+            T* B = reinterpret_cast<T*>(ws + L.fields2);
+            const int n_launch = 2 * ((o.n_steps + kh - 1) / kh);
+            const int lstride = std::max(1, n_launch / 200);
+            int launch = 0;
+            for (int m = 0; m < o.n_steps; m += kh) {
+                const int ks = std::min(kh, o.n_steps - m);
+                for (int pol : {CF_POL_TM, CF_POL_TE}) {
+                    const int n = pol == CF_POL_TM ? n_tm : n_te;
+                    if (n == 0) continue;
+                    tg.nslots = n;
+                    const bool sample = time_it && launch % lstride == 0 && tk < (int)tev.size() / 2;
+                    if (sample) STEP_OK(hipEventRecord(tev[2 * tk], s));
+                    STEP_OK(cf::launch_tb2d<T>(pol, A, B, dch, pol == CF_POL_TM ? s_tm : s_te, tg, tabs,
+                                               dlut, ks, m, s));
+                    if (sample) {
+                        STEP_OK(hipEventRecord(tev[2 * tk + 1], s));
+                        const double cu = (double)n * p.ncell * ks;
+                        timing->cu_total += cu;
+                        timing->bytes_total += cu * state_bytes;
+                        ++tk;
+                    }
+                    ++launch;
+                }
+                std::swap(A, B);
+            }
+            timing->launches = launch;
+        } else {
+            for (int m = 0; m < o.n_steps; ++m) {
+                const bool sample = time_it && m % stride == 0 && tk < (int)tev.size() / 2;
+                if (sample) STEP_OK(hipEventRecord(tev[2 * tk], s));
+                STEP_OK(cf::launch_h2d<T>(CF_POL_TM, 0, fields, dch, s_tm, n_tm, g, dlut, s));
+                STEP_OK(cf::launch_h2d<T>(CF_POL_TE, 0, fields, dch, s_te, n_te, g, dlut, s));
+                STEP_OK(cf::launch_e2d<T>(CF_POL_TM, 0, fields, dch, s_tm, n_tm, g, dlut, s));
+                STEP_OK(cf::launch_e2d<T>(CF_POL_TE, 0, fields, dch, s_te, n_te, g, dlut, s));
+                if (sample) {
+                    STEP_OK(hipEventRecord(tev[2 * tk + 1], s));
+                    const double cu = (double)C * p.ncell;
+                    timing->cu_total += cu;
+                    timing->bytes_total += cu * state_bytes;
+                    ++tk;
+                }
+                STEP_OK(cf::launch_surface<T>(fields, dch, s_all, (int)C, tabs, dk, m, dt, dA, dacc, dgam,
+                                              (int)C, s));
+            }
+            timing->launches = o.n_steps;
         }
     } else {
         // plain: one channel at a time in a single field block
@@ -303,8 +411,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             tot += ms;
         }
         timing->samples = tk;
-        timing->ms_avg = tk ? tot / tk : 0.0;
-        timing->launches = o.n_steps;
+        timing->ms_total = tot;
     }
     acc_out.assign(C * 2, 0.0);
     STEP_OK(hipMemcpy(acc_out.data(), ws + L.acc, C * 2 * 8, hipMemcpyDeviceToHost));
@@ -497,15 +604,12 @@ cf_status cf_solve(cf_problem* h, const cf_opts* o, void* workspace, size_t ws_b
     out->n_channels_run = (int)C;
     out->cell_updates = (double)C * (double)p.ncell * (double)o->n_steps;
     out->device_ms = ms;
-    out->stencil_ms_avg = tim.ms_avg;
     out->stencil_samples = tim.samples;
     out->stencil_launches = tim.launches;
-    {
-        const double fsz = o->precision == CF_FP64 ? 8.0 : 4.0;
-        const int ncomp = cf::n_comp_for(p.grid.ndim);
-        out->stencil_cell_updates = (double)C * (double)p.ncell;
-        out->stencil_alg_bytes = 2.0 * ncomp * fsz * out->stencil_cell_updates;
-    }
+    out->stencil_ms_avg = tim.samples ? tim.ms_total / tim.samples : 0.0;
+    out->stencil_alg_bytes = tim.samples ? tim.bytes_total / tim.samples : 0.0;
+    out->stencil_cell_updates = tim.samples ? tim.cu_total / tim.samples : 0.0;
+    out->fused = sg.tb.ok ? 1 : 0;
     if (!finite) return fail(CF_E_NONFINITE, "a force accumulator is not finite");
     g_err.clear();
     return CF_OK;

@@ -22,9 +22,13 @@ struct ChanDev {
     int32_t u_off;       // scatter table: first distinct point (source component)
     int32_t n_uniq;      // number of distinct source points
     int32_t basis_off;   // first basis value of the channel's row
-    int32_t pad;
+    int32_t meas_slot;   // slot of the measured component in the field block
     double kick_scale;   // -res / (eps_S or mu_S)
 };
+
+// Material id of cells outside a non-periodic grid inside a fused tile's
+// halo: every coefficient table maps it to a = b = 0.
+constexpr int kNullId = 254;
 
 // Grid and table pointers of one launch.
 struct Grid2D {
@@ -33,6 +37,30 @@ struct Grid2D {
     int perx, pery;
     const uint8_t* ids[6];   // per-component material ids
 };
+
+// Fused temporal-blocked launch over a set of channels (2D).
+struct TBGrid {
+    int nx, ny;
+    int64_t ncell;
+    int perx, pery;
+    const uint8_t* ids[6];
+    int base_x, base_y;    // first cell of tile 0 (<= 0)
+    int ntx, nty;          // tiles per axis
+    int stile;             // tile (ty * ntx + tx) holding every surface stencil point
+    int nslots;            // channels listed in `slots`
+    double dt, dA;
+    const double* ktab;
+    double* acc;
+    double* gamma;
+    int gamma_stride;
+};
+
+// Tile interior (tx x ty cells) and halo / maximum steps per launch.
+struct TBShape {
+    int tx, ty, kh;
+};
+template <typename T>
+TBShape tb_shape();
 
 struct SurfTables {
     const int32_t* gidx;
@@ -66,5 +94,13 @@ template <typename T>
 hipError_t launch_surface(const T* fields, const ChanDev* ch, const int* slots, int nslots,
                           const SurfTables& t, const double* ktab, int m, double dt, double dA,
                           double* acc, double* gamma, int gamma_stride, hipStream_t s);
+
+// Fused launch: `ksteps` (<= tb_shape<T>().kh) full time steps of every
+// listed channel of polarization pol, reading src and writing dst; measures
+// Gamma at steps m0 .. m0 + ksteps - 1 in the surface tile.
+template <typename T>
+hipError_t launch_tb2d(int pol, const T* src, T* dst, const ChanDev* ch, const int* slots,
+                       const TBGrid& g, const SurfTables& t, const T* lut, int ksteps, int m0,
+                       hipStream_t s);
 
 }  // namespace cf

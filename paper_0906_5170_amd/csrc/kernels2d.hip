@@ -1,21 +1,20 @@
-// 2D Yee kernels for gfx950: TM (Ez, Hx, Hy) and TE (Ex, Ey, Hz) half-step
-// updates with the uniform conductivity sigma carried by the per-kind
-// coefficient tables, the delta(t) kick, and the surface projection with
-// the FP64 compensated g-weighted time accumulation.
+// 2D Yee kernels for gfx950: TM (Ez, Hx, Hy) and TE (Ex, Ey, Hz) updates
+// with the uniform conductivity sigma carried by per-kind coefficient tables,
+// the delta(t) kick, the surface projection with the FP64 compensated
+// g-weighted time accumulation, and the fused temporal-blocked step kernel.
 //
 // Layout: a channel's field block is 3 components x (ny x nx) cells, x
-// fastest.  A 64 x 4 thread block covers 64 consecutive x cells of 4 rows,
-// so every wavefront reads and writes 64 contiguous elements per component
-// (coalesced 256 B / 512 B for FP32 / FP64).  Channels run along grid.y.
-//
-// Update forms (undivided differences; a, b from the channel kind's table):
+// fastest.  Update forms (undivided differences; a, b from the channel
+// kind's table):
 //   TM  Hx <- a Hx - b (Ez[j+1] - Ez[j])        Hy <- a Hy - b (Ez[i] - Ez[i+1])
 //       Ez <- a Ez + b ((Hy[i] - Hy[i-1]) - (Hx[j] - Hx[j-1]))
 //   TE  Hz <- a Hz - b ((Ey[i+1] - Ey[i]) - (Ex[j+1] - Ex[j]))
 //       Ex <- a Ex + b (Hz[j] - Hz[j-1])         Ey <- a Ey - b (Hz[i] - Hz[i-1])
 // A neighbour beyond the grid reads as 0 on a PEC wall and wraps on a
-// periodic one.  The consistent start writes the partner field of the
-// kicked one as +b/2 times the same curl.
+// periodic one.  Every kernel evaluates these forms through the same inline
+// helpers with explicit fused multiply-adds (the library is built without
+// automatic contraction), so the split, fused and plain paths produce
+// bitwise-identical fields.
 #include "../../include/casimir_fdtd.h"
 #include "device.hpp"
 
@@ -25,11 +24,55 @@ namespace {
 
 constexpr int BX = 64;
 constexpr int BY = 4;
+constexpr int NT = 256;   // threads of the surface and fused kernels
+
+template <typename T>
+__device__ __forceinline__ T yee_sub(T a, T x, T b, T d) { return fma(a, x, -(b * d)); }
+template <typename T>
+__device__ __forceinline__ T yee_add(T a, T x, T b, T d) { return fma(a, x, b * d); }
+template <typename T>
+__device__ __forceinline__ T yee_half(T b, T d) { return (T(0.5) * b) * d; }
 
 template <typename T>
 __device__ __forceinline__ const T* lut_ab(const T* lut, int kind, int comp, int id) {
     return lut + (((kind * 6 + comp) << 8) + id) * 2;
 }
+
+__device__ __forceinline__ void neumaier(double& sum, double& comp, double term) {
+    const double nt = sum + term;
+    if (fabs(sum) >= fabs(term))
+        comp += (sum - nt) + term;
+    else
+        comp += (term - nt) + sum;
+    sum = nt;
+}
+
+// Gamma sum of one channel by a block of NT threads: thread t takes samples
+// t, t+NT, ...; sum_p w X in FP64 per sample, weighted by f_n(s); then a
+// fixed-order reduction over the wave and over the NT/64 waves.  The total is
+// returned in thread 0.  `fetch(idx)` reads the measured component at flat
+// grid index idx.
+template <typename Fetch>
+__device__ double block_surface_sum(const ChanDev& d, const SurfTables& t, Fetch fetch, double* red) {
+    double s = 0.0;
+    const int n = threadIdx.x < NT ? d.nsamp : 0;   // larger blocks: the first NT threads sum
+    for (int i = threadIdx.x; i < n; i += NT) {
+        const int32_t* gi = t.gidx + d.g_off + (int64_t)i * d.P;
+        const double* gw = t.gw + d.g_off + (int64_t)i * d.P;
+        double v = 0.0;
+        for (int p = 0; p < d.P; ++p) v += gw[p] * fetch(gi[p]);
+        s += t.basis[d.basis_off + i] * v;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0 && threadIdx.x < NT) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double tot = 0.0;
+    if (threadIdx.x == 0) tot = ((red[0] + red[1]) + red[2]) + red[3];
+    return tot;
+}
+
+// ---------------------------------------------------------------------------
+// split half-step kernels (one launch per half step for a batch of channels)
 
 template <typename T, int POL, int MODE>
 __global__ __launch_bounds__(BX* BY) void k_h2d(T* __restrict__ fields, const ChanDev* __restrict__ ch,
@@ -54,11 +97,11 @@ __global__ __launch_bounds__(BX* BY) void k_h2d(T* __restrict__ fields, const Ch
         const T* lx = lut_ab(lut, d.kind, CF_HX, g.ids[CF_HX][c]);
         const T* ly = lut_ab(lut, d.kind, CF_HY, g.ids[CF_HY][c]);
         if (MODE == 0) {
-            Hx[c] = lx[0] * Hx[c] - lx[1] * (ezu - ez);
-            Hy[c] = ly[0] * Hy[c] - ly[1] * (ez - ezr);
+            Hx[c] = yee_sub(lx[0], Hx[c], lx[1], ezu - ez);
+            Hy[c] = yee_sub(ly[0], Hy[c], ly[1], ez - ezr);
         } else {
-            Hx[c] = T(0.5) * lx[1] * (ezu - ez);
-            Hy[c] = T(0.5) * ly[1] * (ez - ezr);
+            Hx[c] = yee_half(lx[1], ezu - ez);
+            Hy[c] = yee_half(ly[1], ez - ezr);
         }
     } else {
         const T* Ex = base;
@@ -70,9 +113,9 @@ __global__ __launch_bounds__(BX* BY) void k_h2d(T* __restrict__ fields, const Ch
         const T curl = (eyr - ey) - (exu - ex);
         const T* lz = lut_ab(lut, d.kind, CF_HZ, g.ids[CF_HZ][c]);
         if (MODE == 0) {
-            Hz[c] = lz[0] * Hz[c] - lz[1] * curl;
+            Hz[c] = yee_sub(lz[0], Hz[c], lz[1], curl);
         } else {
-            Hz[c] = T(0.5) * lz[1] * curl;
+            Hz[c] = yee_half(lz[1], curl);
         }
     }
 }
@@ -99,9 +142,9 @@ __global__ __launch_bounds__(BX* BY) void k_e2d(T* __restrict__ fields, const Ch
         const T curl = (hy - hyl) - (hx - hxd);
         const T* lz = lut_ab(lut, d.kind, CF_EZ, g.ids[CF_EZ][c]);
         if (MODE == 0) {
-            Ez[c] = lz[0] * Ez[c] + lz[1] * curl;
+            Ez[c] = yee_add(lz[0], Ez[c], lz[1], curl);
         } else {
-            Ez[c] = T(0.5) * lz[1] * curl;
+            Ez[c] = yee_half(lz[1], curl);
         }
     } else {
         T* Ex = base;
@@ -113,11 +156,11 @@ __global__ __launch_bounds__(BX* BY) void k_e2d(T* __restrict__ fields, const Ch
         const T* lx = lut_ab(lut, d.kind, CF_EX, g.ids[CF_EX][c]);
         const T* ly = lut_ab(lut, d.kind, CF_EY, g.ids[CF_EY][c]);
         if (MODE == 0) {
-            Ex[c] = lx[0] * Ex[c] + lx[1] * (hz - hzd);
-            Ey[c] = ly[0] * Ey[c] - ly[1] * (hz - hzl);
+            Ex[c] = yee_add(lx[0], Ex[c], lx[1], hz - hzd);
+            Ey[c] = yee_sub(ly[0], Ey[c], ly[1], hz - hzl);
         } else {
-            Ex[c] = T(0.5) * lx[1] * (hz - hzd);
-            Ey[c] = T(-0.5) * ly[1] * (hz - hzl);
+            Ex[c] = yee_half(lx[1], hz - hzd);
+            Ey[c] = -yee_half(ly[1], hz - hzl);
         }
     }
 }
@@ -136,39 +179,262 @@ __global__ void k_kick(T* __restrict__ fields, const ChanDev* __restrict__ ch, c
     }
 }
 
-// One wavefront per channel: Gamma = dA sum_s f_n(s) sum_p w_sp X[idx_sp] in
-// FP64, reduced across the wave in a fixed order, then the Neumaier update of
-// (sum, comp) += dt K(t_m) Gamma.
+// One block per channel: Gamma = dA sum_s f_n(s) sum_p w_sp X[idx_sp] (FP64),
+// then the Neumaier update of (sum, comp) += dt K(t_m) Gamma.
 template <typename T>
-__global__ __launch_bounds__(64) void k_surface(const T* __restrict__ fields, const ChanDev* __restrict__ ch,
+__global__ __launch_bounds__(NT) void k_surface(const T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                 const int* __restrict__ slots, SurfTables t,
                                                 const double* __restrict__ ktab, int m, double dt,
                                                 double dA, double* __restrict__ acc,
                                                 double* __restrict__ gamma, int gamma_stride) {
+    __shared__ double red[NT / 64];
     const int slot = slots[blockIdx.x];
     const ChanDev d = ch[slot];
     const T* X = fields + d.meas_off;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < d.nsamp; i += 64) {
-        const int32_t* gi = t.gidx + d.g_off + (int64_t)i * d.P;
-        const double* gw = t.gw + d.g_off + (int64_t)i * d.P;
-        double v = 0.0;
-        for (int p = 0; p < d.P; ++p) v += gw[p] * (double)X[gi[p]];
-        s += t.basis[d.basis_off + i] * v;
-    }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    const double s = block_surface_sum(d, t, [&](int32_t idx) { return (double)X[idx]; }, red);
     if (threadIdx.x == 0) {
         const double G = dA * s;
-        const double term = dt * ktab[m] * G;
         double sum = acc[2 * slot], comp = acc[2 * slot + 1];
-        const double nt = sum + term;
-        if (fabs(sum) >= fabs(term))
-            comp += (sum - nt) + term;
-        else
-            comp += (term - nt) + sum;
-        acc[2 * slot] = nt;
+        neumaier(sum, comp, (dt * ktab[m]) * G);
+        acc[2 * slot] = sum;
         acc[2 * slot + 1] = comp;
         if (gamma) gamma[(int64_t)m * gamma_stride + slot] = G;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fused temporal-blocked kernel, register-blocked
+//
+// Block b works on one tile of channel slots[k].  Its region is 64 columns
+// (one per lane) by W*B rows (wave w of W holds rows w*B .. w*B+B-1 of every
+// column in registers); the tile proper is the region minus a KH-cell halo on
+// every side.  The block loads the region, takes `ksteps` <= KH full time
+// steps and writes the tile's cells to dst.  After step s the fields are
+// exact on the region shrunk by s cells on every side, so the tile stays
+// exact for KH steps; the shrinking rim holds finite stale values that are
+// never written back.
+//
+// Neighbours: along x a lane takes its neighbour lane's value with a DPP
+// wave shift (no memory); along y rows of one wave are registers and the
+// rows at a wave boundary go through a one-row LDS exchange per half step.
+// Barriers per step: one after the E-row writes, one after the H-row writes
+// (plus two around the surface staging in the surface tile).
+// Coefficients come from the channel kind's table in LDS, indexed by the
+// per-cell material ids held packed in registers.  Cells outside a
+// non-periodic grid carry the null material (a = b = 0) and stay 0.
+//
+// The tiling is shifted so that every surface stencil point lies in one
+// tile (g.stile); that tile's block stages the measured component in LDS
+// after every step, forms Gamma with the shared block reduction, and
+// carries the channel's compensated accumulator through the launch.
+//
+// Block order: b % 8 selects the XCD a block is dispatched to, so
+// k = 8 * (q / ntile) + b % 8 with q = b / 8 keeps all tiles of a channel
+// on one XCD (halo re-reads hit that XCD's L2).
+
+template <typename T>
+struct Pair {
+    T a, b;
+};
+
+// Value of v held by lane l+1 (DPP wave_shl:1); lane 63 keeps its own.
+__device__ __forceinline__ float from_next(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+// Value of v held by lane l-1 (DPP wave_shr:1); lane 0 keeps its own.
+__device__ __forceinline__ float from_prev(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_next(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_prev(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+}
+
+template <typename T, int POL, int RBW, int B, int KH>
+__global__ __launch_bounds__(64 * RBW) __attribute__((amdgpu_waves_per_eu(4)))
+void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __restrict__ ch,
+            const int* __restrict__ slots, TBGrid g, SurfTables t, const T* __restrict__ lut, int ksteps,
+            int m0) {
+    constexpr int RH = RBW * B;
+    constexpr int NTB = 64 * RBW;
+    constexpr int TX = 64 - 2 * KH, TY = RH - 2 * KH;
+    constexpr int C0 = POL == CF_POL_TM ? CF_EZ : CF_EX;
+    constexpr int C1 = POL == CF_POL_TM ? CF_HX : CF_EY;
+    constexpr int C2 = POL == CF_POL_TM ? CF_HY : CF_HZ;
+    __shared__ Pair<T> L[3][256];
+    // wave-boundary rows: E rows (read by the wave below) and H rows (read by
+    // the wave above) in separate buffers, so each write is separated from
+    // the previous reads of the same buffer by the other half step's barrier
+    __shared__ T xe[RBW][64];
+    __shared__ T xh[RBW][64];
+    __shared__ T stage[RH * 64];     // measured component (surface tile only)
+    __shared__ double red[RBW];
+
+    const int b = blockIdx.x;
+    const int ntile = g.ntx * g.nty;
+    const int q = b >> 3;
+    const int tile = q % ntile;
+    const int k = (q / ntile) * 8 + (b & 7);
+    if (k >= g.nslots) return;
+    const int slot = slots[k];
+    const ChanDev d = ch[slot];
+    const int tx = tile % g.ntx, ty = tile / g.ntx;
+    const int rx0 = g.base_x + tx * TX - KH, ry0 = g.base_y + ty * TY - KH;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+
+    for (int i = tid; i < 3 * 256; i += NTB) {
+        const int s = i >> 8, id = i & 255;
+        const int comp = s == 0 ? C0 : (s == 1 ? C1 : C2);
+        const T* p = lut_ab(lut, d.kind, comp, id);
+        L[s][id].a = p[0];
+        L[s][id].b = p[1];
+    }
+
+    T f0[B], f1[B], f2[B];
+    uint32_t m0p[(B + 3) / 4], m1p[(B + 3) / 4], m2p[(B + 3) / 4];
+#pragma unroll
+    for (int r = 0; r < (B + 3) / 4; ++r) m0p[r] = m1p[r] = m2p[r] = 0;
+    {
+        const T* S = src + d.field_off;
+        int gx = rx0 + lane;
+        bool inx = true;
+        if (gx < 0 || gx >= g.nx) {
+            if (g.perx) gx = ((gx % g.nx) + g.nx) % g.nx;
+            else inx = false;
+        }
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            int gy = ry0 + w * B + r;
+            bool in = inx;
+            if (gy < 0 || gy >= g.ny) {
+                if (g.pery) gy = ((gy % g.ny) + g.ny) % g.ny;
+                else in = false;
+            }
+            uint32_t i0 = kNullId, i1 = kNullId, i2 = kNullId;
+            if (in) {
+                const int64_t gi = (int64_t)gy * g.nx + gx;
+                f0[r] = S[gi];
+                f1[r] = S[g.ncell + gi];
+                f2[r] = S[2 * g.ncell + gi];
+                i0 = g.ids[C0][gi];
+                i1 = g.ids[C1][gi];
+                i2 = g.ids[C2][gi];
+            } else {
+                f0[r] = T(0);
+                f1[r] = T(0);
+                f2[r] = T(0);
+            }
+            m0p[r >> 2] |= i0 << (8 * (r & 3));
+            m1p[r >> 2] |= i1 << (8 * (r & 3));
+            m2p[r >> 2] |= i2 << (8 * (r & 3));
+        }
+    }
+    const bool stile = tile == g.stile;
+    double acc_s = 0.0, acc_c = 0.0;
+    if (stile && tid == 0) {
+        acc_s = g.acc[2 * slot];
+        acc_c = g.acc[2 * slot + 1];
+    }
+    __syncthreads();
+
+#define CF_ID(p, r) ((p[(r) >> 2] >> (8 * ((r) & 3))) & 255u)
+    for (int step = 0; step < ksteps; ++step) {
+        // ---- H half: needs the E row above the wave's band ----
+        xe[w][lane] = f0[0];
+        __syncthreads();
+        const T e_above = w + 1 < RBW ? xe[w + 1][lane] : f0[B - 1];
+        if (POL == CF_POL_TM) {
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                const T ez = f0[r];
+                const T ezr = from_next(ez);
+                const T ezu = r + 1 < B ? f0[r + 1] : e_above;
+                const Pair<T> cx = L[1][CF_ID(m1p, r)], cy = L[2][CF_ID(m2p, r)];
+                f1[r] = yee_sub(cx.a, f1[r], cx.b, ezu - ez);
+                f2[r] = yee_sub(cy.a, f2[r], cy.b, ez - ezr);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                const T ex = f0[r], ey = f1[r];
+                const T eyr = from_next(ey);
+                const T exu = r + 1 < B ? f0[r + 1] : e_above;
+                const Pair<T> cz = L[2][CF_ID(m2p, r)];
+                f2[r] = yee_sub(cz.a, f2[r], cz.b, (eyr - ey) - (exu - ex));
+            }
+        }
+        // ---- E half: needs the H row below the wave's band ----
+        xh[w][lane] = POL == CF_POL_TM ? f1[B - 1] : f2[B - 1];
+        __syncthreads();
+        const T h_below = w > 0 ? xh[w - 1][lane] : (POL == CF_POL_TM ? f1[0] : f2[0]);
+        if (POL == CF_POL_TM) {
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                const T hx = f1[r], hy = f2[r];
+                const T hyl = from_prev(hy);
+                const T hxd = r > 0 ? f1[r - 1] : h_below;
+                const T curl = (hy - hyl) - (hx - hxd);
+                const Pair<T> cz = L[0][CF_ID(m0p, r)];
+                f0[r] = yee_add(cz.a, f0[r], cz.b, curl);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                const T hz = f2[r];
+                const T hzl = from_prev(hz);
+                const T hzd = r > 0 ? f2[r - 1] : h_below;
+                const Pair<T> cx = L[0][CF_ID(m0p, r)], cy = L[1][CF_ID(m1p, r)];
+                f0[r] = yee_add(cx.a, f0[r], cx.b, hz - hzd);
+                f1[r] = yee_sub(cy.a, f1[r], cy.b, hz - hzl);
+            }
+        }
+        if (stile) {
+            const int ms = d.meas_slot;
+#pragma unroll
+            for (int r = 0; r < B; ++r)
+                stage[(w * B + r) * 64 + lane] = ms == 0 ? f0[r] : (ms == 1 ? f1[r] : f2[r]);
+            __syncthreads();
+            const double s = block_surface_sum(
+                d, t,
+                [&](int32_t idx) {
+                    const int gx = idx % g.nx, gy = idx / g.nx;
+                    return (double)stage[(gy - ry0) * 64 + (gx - rx0)];
+                },
+                red);
+            if (tid == 0) {
+                const double G = g.dA * s;
+                const int m = m0 + step;
+                neumaier(acc_s, acc_c, (g.dt * g.ktab[m]) * G);
+                if (g.gamma) g.gamma[(int64_t)m * g.gamma_stride + slot] = G;
+            }
+            __syncthreads();
+        }
+    }
+#undef CF_ID
+    if (stile && tid == 0) {
+        g.acc[2 * slot] = acc_s;
+        g.acc[2 * slot + 1] = acc_c;
+    }
+    T* D = dst + d.field_off;
+    const int gx = rx0 + lane;
+    if (lane >= KH && lane < KH + TX && gx >= 0 && gx < g.nx) {
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            const int ry = w * B + r;
+            const int gy = ry0 + ry;
+            if (ry < KH || ry >= KH + TY || gy < 0 || gy >= g.ny) continue;
+            const int64_t gi = (int64_t)gy * g.nx + gx;
+            D[gi] = f0[r];
+            D[g.ncell + gi] = f1[r];
+            D[2 * g.ncell + gi] = f2[r];
+        }
     }
 }
 
@@ -178,6 +444,14 @@ inline dim3 grid2d(const Grid2D& g, int nslots) {
 }
 
 }  // namespace
+
+// register blocking: W waves of B rows, halo KH (tile = (64 - 2 KH) x (W B - 2 KH))
+constexpr int kRbF32W = 8, kRbF32B = 8, kRbF32K = 8;
+constexpr int kRbF64W = 8, kRbF64B = 4, kRbF64K = 4;
+template <>
+TBShape tb_shape<float>() { return TBShape{64 - 2 * kRbF32K, kRbF32W * kRbF32B - 2 * kRbF32K, kRbF32K}; }
+template <>
+TBShape tb_shape<double>() { return TBShape{64 - 2 * kRbF64K, kRbF64W * kRbF64B - 2 * kRbF64K, kRbF64K}; }
 
 template <typename T>
 hipError_t launch_h2d(int pol, int mode, T* fields, const ChanDev* ch, const int* slots, int nslots,
@@ -223,8 +497,28 @@ hipError_t launch_surface(const T* fields, const ChanDev* ch, const int* slots, 
                           const SurfTables& t, const double* ktab, int m, double dt, double dA,
                           double* acc, double* gamma, int gamma_stride, hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_surface<T>), dim3(nslots), dim3(64), 0, s, fields, ch, slots, t, ktab, m,
+    hipLaunchKernelGGL((k_surface<T>), dim3(nslots), dim3(NT), 0, s, fields, ch, slots, t, ktab, m,
                        dt, dA, acc, gamma, gamma_stride);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tb2d(int pol, const T* src, T* dst, const ChanDev* ch, const int* slots,
+                       const TBGrid& g, const SurfTables& t, const T* lut, int ksteps, int m0,
+                       hipStream_t s) {
+    if (g.nslots <= 0) return hipSuccess;
+    const TBShape sh = tb_shape<T>();
+    if (ksteps < 1 || ksteps > sh.kh) return hipErrorInvalidValue;
+    const int groups = (g.nslots + 7) / 8;
+    constexpr bool f32 = sizeof(T) == 4;
+    constexpr int W = f32 ? kRbF32W : kRbF64W, B = f32 ? kRbF32B : kRbF64B, KH = f32 ? kRbF32K : kRbF64K;
+    dim3 grid(8 * groups * g.ntx * g.nty), block(64 * W);
+    if (pol == CF_POL_TM)
+        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TM, W, B, KH>), grid, block, 0, s, src, dst, ch, slots, g, t,
+                           lut, ksteps, m0);
+    else
+        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TE, W, B, KH>), grid, block, 0, s, src, dst, ch, slots, g, t,
+                           lut, ksteps, m0);
     return hipGetLastError();
 }
 
@@ -237,7 +531,9 @@ hipError_t launch_surface(const T* fields, const ChanDev* ch, const int* slots, 
                                        hipStream_t);                                                    \
     template hipError_t launch_surface<T>(const T*, const ChanDev*, const int*, int, const SurfTables&, \
                                           const double*, int, double, double, double*, double*, int,    \
-                                          hipStream_t);
+                                          hipStream_t);                                                 \
+    template hipError_t launch_tb2d<T>(int, const T*, T*, const ChanDev*, const int*, const TBGrid&,    \
+                                       const SurfTables&, const T*, int, int, hipStream_t);
 CF_INSTANTIATE(float)
 CF_INSTANTIATE(double)
 #undef CF_INSTANTIATE

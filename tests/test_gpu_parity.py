@@ -87,6 +87,7 @@ def test_c1_fp64_batched(cf, c1_ref):
     announce("c1 fp64 batched 80x40 TM T=2000")
     g = run(cf, c1_piston_tm_fp64())
     assert g["n_channels"] == len(c1_ref.channels) == 116
+    assert g["fused"]
     compare(g, c1_ref, 1e-9, 1e-9)
     assert g["force"] == pytest.approx(c1_ref.force, rel=1e-9)
 
@@ -99,6 +100,22 @@ def test_c1_fp64_plain_bitwise_equals_batched(cf):
     b = run(cf, wl, channel_subset=sub, path="plain")
     np.testing.assert_array_equal(a["per_channel"], b["per_channel"])
     assert a["force"] == b["force"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_bitwise_equals_split(cf, precision):
+    announce(f"fused multi-step kernel vs split half-step kernels, {precision}")
+    wl = SMALL["tmte_pec"]().replace(n_steps=203)       # ragged last time block
+    a = run(cf, wl, precision=precision)
+    b = run(cf, wl, precision=precision, split=True)
+    assert a["fused"] and not b["fused"]
+    np.testing.assert_array_equal(a["per_channel"], b["per_channel"])
+    c2 = c2_piston_tetm_fp32(n_steps=37)
+    sub = [0, 5, 100, 223, 224, 300, 447]
+    a = run(cf, c2, channel_subset=sub)
+    b = run(cf, c2, channel_subset=sub, split=True)
+    assert a["fused"]
+    np.testing.assert_array_equal(a["per_channel"], b["per_channel"])
 
 
 def test_c1_fp32_within_1e4(cf, c1_ref):
@@ -115,6 +132,21 @@ def test_deterministic(cf):
     a = run(cf, wl, precision="fp32")
     b = run(cf, wl, precision="fp32")
     np.testing.assert_array_equal(a["per_channel"], b["per_channel"])
+
+
+def test_deterministic_full_size_and_equal_to_split(cf):
+    """All 448 channels at 400x200 (the benchmark launch configuration, T cut
+    to 1200): three fused runs are bitwise identical and equal the split
+    half-step kernels (a race between the waves of a fused block shows up
+    here as run-to-run differences)."""
+    announce("c2 400x200 all channels T=1200: fused x3 vs split")
+    wl = c2_piston_tetm_fp32(n_steps=1200)
+    runs = [run(cf, wl) for _ in range(3)]
+    assert all(r["fused"] for r in runs)
+    for r in runs[1:]:
+        np.testing.assert_array_equal(r["per_channel"], runs[0]["per_channel"])
+    ref = run(cf, wl, split=True)
+    np.testing.assert_array_equal(ref["per_channel"], runs[0]["per_channel"])
 
 
 SMALL = {
