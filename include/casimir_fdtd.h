@@ -135,6 +135,10 @@ typedef struct cf_opts {
     const int* channel_subset;  /* optional: run only these channel indices  */
     int n_subset;               /* length of channel_subset (0 = all)         */
     void* stream;       /* hipStream_t, or NULL for the default stream        */
+    int max_resident;   /* channels whose fields are on the device at once;   */
+                        /* the channels run in consecutive waves of this many */
+                        /* (0 = all at once).  Bounds the workspace of large  */
+                        /* 3D problems; results do not depend on it.          */
 } cf_opts;
 
 typedef struct cf_info {

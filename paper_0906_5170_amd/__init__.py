@@ -55,7 +55,7 @@ class _Opts(C.Structure):
     _fields_ = [("sigma", C.c_double), ("courant", C.c_double), ("n_steps", C.c_int),
                 ("pol", C.c_int), ("kernel", C.c_int), ("precision", C.c_int), ("path", C.c_int),
                 ("flags", C.c_int), ("channel_subset", C.POINTER(C.c_int)), ("n_subset", C.c_int),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("max_resident", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -195,7 +195,7 @@ class Problem:
 
     def _opts(self, sigma=1.0, courant=0.5, n_steps=1000, pol="TM", kernel="zinv2d",
               precision="fp64", path="batched", keep_gamma=False, channel_subset=None, stream=None,
-              time_stencil=False, split=False):
+              time_stencil=False, split=False, max_resident=0):
         o = _Opts()
         o.sigma = float(sigma)
         o.courant = float(courant)
@@ -215,6 +215,7 @@ class Problem:
             o.channel_subset = None
             o.n_subset = 0
         o.stream = stream
+        o.max_resident = int(max_resident)
         return o
 
     def info(self, **opts) -> dict:

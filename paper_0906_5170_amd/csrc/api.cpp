@@ -38,9 +38,8 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Device workspace layout of one solve.
 struct Layout {
-    size_t ids, lut, ktab, chans, slots, gidx, gw, uidx, uoff, usamp, uw, basis, acc, gamma,
-        fields, fields2, total;
-    int n_field_slots;
+    size_t ids, lut, ktab, pml, chans, slots, gidx, gw, uidx, uoff, usamp, uw, basis, acc, gamma,
+        fields, fields2, psi, total;
 };
 
 // Tiling of the fused kernel: shifted so that every measured surface stencil
@@ -50,16 +49,24 @@ struct TBPlan {
     int base_x = 0, base_y = 0, ntx = 0, nty = 0, stile = -1;
 };
 
+// One wave of resident channels: index lists (into the channel table) per
+// polarization and in channel order.
+struct Wave {
+    int tm_off, n_tm, te_off, n_te, d3_off, n_3d, all_off, n_all;
+};
+
 struct Staged {
     TBPlan tb;
     std::vector<cf::Channel> chans;       // channels run, in output order
     std::vector<cf::ChanDev> dev;          // one descriptor per channel run
-    std::vector<int> slots_tm, slots_te, slots_3d, slots_all;
+    std::vector<int> slot_lists;           // concatenated per-wave lists
+    std::vector<Wave> waves;
     std::vector<int32_t> gidx, uidx, uoff, usamp;
     std::vector<double> gw, uw, basis;
     int max_uniq = 0;
-    int n_field_slots = 0;
+    int resident = 0;                      // field blocks on the device
     int ncomp = 3;
+    int64_t psi_comp = 0;                  // values per psi component (3D CPML)
 };
 
 TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, cf::TBShape sh);
@@ -79,10 +86,17 @@ std::vector<cf::Channel> selected_channels(const cf::Problem& p, const cf_opts& 
     return out;
 }
 
-// Build host copies of every table a solve uploads.
+// Build host copies of every table a solve uploads.  Channels run in waves
+// of `resident` consecutive channels; channel c uses field block c % resident.
 void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel>& chans, Staged& st) {
     st.chans = chans;
     st.ncomp = cf::n_comp_for(p.grid.ndim);
+    const int C = (int)chans.size();
+    const bool plain = o.path == CF_PATH_PLAIN;
+    st.resident = plain ? 1 : (o.max_resident > 0 ? std::min(o.max_resident, C) : C);
+    st.resident = std::max(st.resident, 1);
+    const int P = p.grid.ndim == 3 && p.grid.bc[2] == CF_BC_PML ? p.grid.pml_cells[2] : 0;
+    st.psi_comp = (int64_t)2 * P * p.nx * p.ny;
     // concatenated gather / scatter tables for every (face, comp) pair used
     std::vector<int> g_goff(p.gathers.size(), -1), g_uoff(p.gathers.size(), -1);
     auto add_gather = [&](int gi) {
@@ -94,11 +108,10 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         g_uoff[gi] = (int)st.uidx.size();
         const int base = (int)st.usamp.size();
         st.uidx.insert(st.uidx.end(), g.uidx.begin(), g.uidx.end());
-        // uoff is stored per distinct point with one trailing entry per gather
-        // (offsets global into usamp/uw); the extra entry keeps [u, u+1] valid.
-        for (size_t k = 0; k + 1 < g.uoff.size(); ++k) st.uoff.push_back(base + g.uoff[k]);
-        st.uoff.push_back(base + g.uoff.back());
-        st.uidx.push_back(0);   // pad so uidx and uoff stay index-aligned
+        // uoff holds one entry per distinct point plus a trailing one, offsets
+        // global into usamp/uw; uidx gets a pad entry to stay index-aligned.
+        for (size_t k = 0; k < g.uoff.size(); ++k) st.uoff.push_back(base + g.uoff[k]);
+        st.uidx.push_back(0);
         st.usamp.insert(st.usamp.end(), g.usamp.begin(), g.usamp.end());
         st.uw.insert(st.uw.end(), g.uw.begin(), g.uw.end());
     };
@@ -107,17 +120,17 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         basis_face_off[f] = (int)st.basis.size();
         st.basis.insert(st.basis.end(), p.basis[f].begin(), p.basis[f].end());
     }
-    const bool plain = o.path == CF_PATH_PLAIN;
-    st.n_field_slots = plain ? 1 : (int)chans.size();
     const double res = p.grid.res;
-    for (size_t c = 0; c < chans.size(); ++c) {
+    for (int c = 0; c < C; ++c) {
         const cf::Channel& ch = chans[c];
         int gm = p.gather_of.at({ch.face, ch.meas});
         int gs = p.gather_of.at({ch.face, ch.src});
         add_gather(gm);
         add_gather(gs);
+        const int blk = c % st.resident;
         cf::ChanDev d{};
-        d.field_off = plain ? 0 : (int64_t)c * st.ncomp * p.ncell;
+        d.field_off = (int64_t)blk * st.ncomp * p.ncell;
+        d.psi_off = (int64_t)blk * 4 * st.psi_comp;
         d.src_off = d.field_off + (int64_t)cf::comp_slot(ch.pol, ch.src) * p.ncell;
         d.meas_off = d.field_off + (int64_t)cf::comp_slot(ch.pol, ch.meas) * p.ncell;
         d.kind = ch.kind;
@@ -131,10 +144,21 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         d.kick_scale = -res / (ch.kind == 0 ? p.eps_s : p.mu_s);
         st.max_uniq = std::max(st.max_uniq, d.n_uniq);
         st.dev.push_back(d);
-        st.slots_all.push_back((int)c);
-        if (ch.pol == CF_POL_TM) st.slots_tm.push_back((int)c);
-        else if (ch.pol == CF_POL_TE) st.slots_te.push_back((int)c);
-        else st.slots_3d.push_back((int)c);
+    }
+    for (int w0 = 0; w0 < C; w0 += st.resident) {
+        const int w1 = std::min(C, w0 + st.resident);
+        Wave w{};
+        auto add = [&](int pol, int* off, int* n) {
+            *off = (int)st.slot_lists.size();
+            for (int c = w0; c < w1; ++c)
+                if (pol == 0 || chans[c].pol == pol) st.slot_lists.push_back(c);
+            *n = (int)st.slot_lists.size() - *off;
+        };
+        add(CF_POL_TM, &w.tm_off, &w.n_tm);
+        add(CF_POL_TE, &w.te_off, &w.n_te);
+        add(CF_POL_3D, &w.d3_off, &w.n_3d);
+        add(0, &w.all_off, &w.n_all);
+        st.waves.push_back(w);
     }
     if (!plain && p.grid.ndim == 2 && !(o.flags & CF_FLAG_SPLIT)) {
         const cf::TBShape sh = o.precision == CF_FP64 ? cf::tb_shape<double>() : cf::tb_shape<float>();
@@ -187,11 +211,13 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     };
     const size_t fsz = o.precision == CF_FP64 ? 8 : 4;
     const size_t C = st.chans.size();
+    const size_t block = (size_t)st.resident * st.ncomp * p.ncell * fsz;
     L.ids = take((size_t)cf::kNumComp * p.ncell);
     L.lut = take(2 * cf::kNumComp * 256 * 2 * fsz);
     L.ktab = take((size_t)o.n_steps * 8);
+    L.pml = take((size_t)4 * p.nz * 8);
     L.chans = take(C * sizeof(cf::ChanDev));
-    L.slots = take((C + 2) * 3 * sizeof(int));
+    L.slots = take(st.slot_lists.size() * sizeof(int) + 4);
     L.gidx = take(st.gidx.size() * 4 + 4);
     L.gw = take(st.gw.size() * 8 + 8);
     L.uidx = take(st.uidx.size() * 4 + 4);
@@ -201,10 +227,10 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.basis = take(st.basis.size() * 8 + 8);
     L.acc = take(C * 2 * 8);
     L.gamma = (o.flags & CF_FLAG_KEEP_GAMMA) ? take((size_t)o.n_steps * C * 8) : off;
-    L.fields = take((size_t)st.n_field_slots * st.ncomp * p.ncell * fsz);
-    L.fields2 = st.tb.ok ? take((size_t)st.n_field_slots * st.ncomp * p.ncell * fsz) : off;
+    L.fields = take(block);
+    L.fields2 = st.tb.ok ? take(block) : off;
+    L.psi = st.psi_comp > 0 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
     L.total = off;
-    L.n_field_slots = st.n_field_slots;
     return L;
 }
 
@@ -212,6 +238,27 @@ struct StencilTiming {
     double ms_total = 0, bytes_total = 0, cu_total = 0;
     int samples = 0;
     int launches = 0;
+};
+
+// Sampled HIP-event timing of field-update launches on the solve's stream.
+struct Sampler {
+    std::vector<hipEvent_t> ev;
+    int taken = 0, seen = 0, stride = 1;
+    double bytes = 0, cu = 0;
+    bool on = false;
+    bool begin(hipStream_t s) {
+        const bool take = on && seen % stride == 0 && taken < (int)ev.size() / 2;
+        if (take) (void)hipEventRecord(ev[2 * taken], s);
+        return take;
+    }
+    void end(bool take, hipStream_t s, double launch_cu, double launch_bytes) {
+        ++seen;
+        if (!take) return;
+        (void)hipEventRecord(ev[2 * taken + 1], s);
+        ++taken;
+        cu += launch_cu;
+        bytes += launch_bytes;
+    }
 };
 
 template <typename T>
@@ -227,11 +274,12 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     std::vector<T> lut(lut64.begin(), lut64.end());
     std::vector<double> ktab(o.n_steps);
     cf::kernel_table(o.kernel, o.sigma, o.courant / p.grid.res, o.n_steps, ktab.data());
-    std::vector<int> slots;
-    slots.insert(slots.end(), st.slots_tm.begin(), st.slots_tm.end());
-    slots.insert(slots.end(), st.slots_te.begin(), st.slots_te.end());
-    slots.insert(slots.end(), st.slots_3d.begin(), st.slots_3d.end());
-    slots.insert(slots.end(), st.slots_all.begin(), st.slots_all.end());
+    std::vector<double> bh, chh, be, ce, pml;
+    cf::pml_tables(p, o.courant, bh, chh, be, ce);
+    pml.insert(pml.end(), bh.begin(), bh.end());
+    pml.insert(pml.end(), chh.begin(), chh.end());
+    pml.insert(pml.end(), be.begin(), be.end());
+    pml.insert(pml.end(), ce.begin(), ce.end());
     auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
         if (!bytes) return hipSuccess;
         return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, s);
@@ -239,8 +287,9 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     CF_HIP(up(L.ids, ids.data(), ids.size()));
     CF_HIP(up(L.lut, lut.data(), lut.size() * sizeof(T)));
     CF_HIP(up(L.ktab, ktab.data(), ktab.size() * 8));
+    CF_HIP(up(L.pml, pml.data(), pml.size() * 8));
     CF_HIP(up(L.chans, st.dev.data(), st.dev.size() * sizeof(cf::ChanDev)));
-    CF_HIP(up(L.slots, slots.data(), slots.size() * sizeof(int)));
+    CF_HIP(up(L.slots, st.slot_lists.data(), st.slot_lists.size() * sizeof(int)));
     CF_HIP(up(L.gidx, st.gidx.data(), st.gidx.size() * 4));
     CF_HIP(up(L.gw, st.gw.data(), st.gw.size() * 8));
     CF_HIP(up(L.uidx, st.uidx.data(), st.uidx.size() * 4));
@@ -253,15 +302,12 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     if (keep_gamma) CF_HIP(hipMemsetAsync(ws + L.gamma, 0, (size_t)o.n_steps * C * 8, s));
 
     T* fields = reinterpret_cast<T*>(ws + L.fields);
+    T* psi = st.psi_comp > 0 ? reinterpret_cast<T*>(ws + L.psi) : nullptr;
     const cf::ChanDev* dch = reinterpret_cast<const cf::ChanDev*>(ws + L.chans);
     const int* dslots = reinterpret_cast<const int*>(ws + L.slots);
-    const int n_tm = (int)st.slots_tm.size(), n_te = (int)st.slots_te.size(),
-              n_3d = (int)st.slots_3d.size();
-    const int* s_tm = dslots;
-    const int* s_te = dslots + n_tm;
-    const int* s_all = dslots + n_tm + n_te + n_3d;
     const T* dlut = reinterpret_cast<const T*>(ws + L.lut);
     const double* dk = reinterpret_cast<const double*>(ws + L.ktab);
+    const double* dpml = reinterpret_cast<const double*>(ws + L.pml);
     double* dacc = reinterpret_cast<double*>(ws + L.acc);
     double* dgam = keep_gamma ? reinterpret_cast<double*>(ws + L.gamma) : nullptr;
     cf::SurfTables tabs;
@@ -272,46 +318,100 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     tabs.usamp = reinterpret_cast<const int32_t*>(ws + L.usamp);
     tabs.uw = reinterpret_cast<const double*>(ws + L.uw);
     tabs.basis = reinterpret_cast<const double*>(ws + L.basis);
+    const uint8_t* dids = reinterpret_cast<const uint8_t*>(ws + L.ids);
     cf::Grid2D g{};
     g.nx = p.nx;
     g.ny = p.ny;
     g.ncell = p.ncell;
     g.perx = p.grid.bc[0] == CF_BC_PERIODIC;
     g.pery = p.grid.bc[1] == CF_BC_PERIODIC;
-    for (int c = 0; c < cf::kNumComp; ++c)
-        g.ids[c] = reinterpret_cast<const uint8_t*>(ws + L.ids) + (size_t)c * p.ncell;
+    for (int c = 0; c < cf::kNumComp; ++c) g.ids[c] = dids + (size_t)c * p.ncell;
+    cf::Grid3D g3{};
+    g3.nx = p.nx;
+    g3.ny = p.ny;
+    g3.nz = p.nz;
+    g3.ncell = p.ncell;
+    for (int a = 0; a < 3; ++a) g3.per[a] = p.grid.bc[a] == CF_BC_PERIODIC;
+    for (int c = 0; c < cf::kNumComp; ++c) g3.ids[c] = g.ids[c];
+    g3.pml = p.grid.ndim == 3 && p.grid.bc[2] == CF_BC_PML ? p.grid.pml_cells[2] : 0;
+    g3.psi_comp = st.psi_comp;
+    g3.pml_bh = dpml;
+    g3.pml_ch = dpml + p.nz;
+    g3.pml_be = dpml + 2 * p.nz;
+    g3.pml_ce = dpml + 3 * p.nz;
     const double dt = o.courant / p.grid.res;
     const double dA = std::pow(1.0 / p.grid.res, p.grid.ndim - 1);
-    const size_t field_bytes = (size_t)L.n_field_slots * st.ncomp * p.ncell * sizeof(T);
+    const size_t field_bytes = (size_t)st.resident * st.ncomp * p.ncell * sizeof(T);
+    const size_t psi_bytes = (size_t)st.resident * 4 * st.psi_comp * sizeof(T);
+    const double state_bytes = 2.0 * st.ncomp * sizeof(T);   // read + write of a cell's state
+    const bool three = p.grid.ndim == 3;
 
     hipEvent_t e0, e1;
     CF_HIP(hipEventCreate(&e0));
     CF_HIP(hipEventCreate(&e1));
-    // sampled timing of the field-update launches (batched path)
-    const bool time_it = (o.flags & CF_FLAG_TIME_STENCIL) && o.path == CF_PATH_BATCHED;
-    const int stride = std::max(1, o.n_steps / 200);
-    std::vector<hipEvent_t> tev;
-    if (time_it) {
-        tev.resize(2 * 256);
-        for (auto& e : tev) CF_HIP(hipEventCreate(&e));
+    Sampler smp;
+    smp.on = (o.flags & CF_FLAG_TIME_STENCIL) != 0;
+    if (smp.on) {
+        smp.ev.resize(2 * 256);
+        for (auto& e : smp.ev) CF_HIP(hipEventCreate(&e));
+        const int kh = st.tb.ok ? cf::tb_shape<T>().kh : 1;
+        const int per_wave = st.tb.ok ? 2 * ((o.n_steps + kh - 1) / kh) : o.n_steps;
+        smp.stride = std::max(1, per_wave * (int)st.waves.size() / 200);
     }
-    int tk = 0;
-    cf_status status = CF_OK;
     hipError_t err = hipSuccess;
-#define STEP_OK(expr)                \
-    do {                             \
-        err = (expr);                \
+#define STEP_OK(expr)                     \
+    do {                                  \
+        err = (expr);                     \
         if (err != hipSuccess) goto done; \
     } while (0)
     STEP_OK(hipEventRecord(e0, s));
-    if (o.path == CF_PATH_BATCHED) {
+    for (const Wave& w : st.waves) {
+        const int* s_tm = dslots + w.tm_off;
+        const int* s_te = dslots + w.te_off;
+        const int* s_3d = dslots + w.d3_off;
+        const int* s_all = dslots + w.all_off;
+        if (o.path == CF_PATH_PLAIN) {
+            // plain: one channel at a time, three launches per step
+            for (int k = 0; k < w.n_all; ++k) {
+                const int* one = s_all + k;
+                const int pol = st.chans[st.slot_lists[w.all_off + k]].pol;
+                STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
+                if (psi) STEP_OK(hipMemsetAsync(psi, 0, psi_bytes, s));
+                STEP_OK(cf::launch_kick<T>(fields, dch, one, 1, st.max_uniq, tabs, s));
+                if (three) {
+                    STEP_OK(cf::launch_h3d<T>(1, fields, psi, dch, one, 1, g3, dlut, s));
+                    STEP_OK(cf::launch_e3d<T>(1, fields, psi, dch, one, 1, g3, dlut, s));
+                } else {
+                    STEP_OK(cf::launch_h2d<T>(pol, 1, fields, dch, one, 1, g, dlut, s));
+                    STEP_OK(cf::launch_e2d<T>(pol, 1, fields, dch, one, 1, g, dlut, s));
+                }
+                for (int m = 0; m < o.n_steps; ++m) {
+                    if (three) {
+                        STEP_OK(cf::launch_h3d<T>(0, fields, psi, dch, one, 1, g3, dlut, s));
+                        STEP_OK(cf::launch_e3d<T>(0, fields, psi, dch, one, 1, g3, dlut, s));
+                    } else {
+                        STEP_OK(cf::launch_h2d<T>(pol, 0, fields, dch, one, 1, g, dlut, s));
+                        STEP_OK(cf::launch_e2d<T>(pol, 0, fields, dch, one, 1, g, dlut, s));
+                    }
+                    STEP_OK(cf::launch_surface<T>(fields, dch, one, 1, tabs, dk, m, dt, dA, dacc, dgam,
+                                                  (int)C, s));
+                }
+            }
+            continue;
+        }
+        // batched: kick and consistent start for the whole wave
         STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
-        STEP_OK(cf::launch_kick<T>(fields, dch, s_all, (int)C, st.max_uniq, tabs, s));
-        STEP_OK(cf::launch_h2d<T>(CF_POL_TM, 1, fields, dch, s_tm, n_tm, g, dlut, s));
-        STEP_OK(cf::launch_h2d<T>(CF_POL_TE, 1, fields, dch, s_te, n_te, g, dlut, s));
-        STEP_OK(cf::launch_e2d<T>(CF_POL_TM, 1, fields, dch, s_tm, n_tm, g, dlut, s));
-        STEP_OK(cf::launch_e2d<T>(CF_POL_TE, 1, fields, dch, s_te, n_te, g, dlut, s));
-        const double state_bytes = 2.0 * st.ncomp * sizeof(T);   // read + write of a cell's state
+        if (psi) STEP_OK(hipMemsetAsync(psi, 0, psi_bytes, s));
+        STEP_OK(cf::launch_kick<T>(fields, dch, s_all, w.n_all, st.max_uniq, tabs, s));
+        if (three) {
+            STEP_OK(cf::launch_h3d<T>(1, fields, psi, dch, s_3d, w.n_3d, g3, dlut, s));
+            STEP_OK(cf::launch_e3d<T>(1, fields, psi, dch, s_3d, w.n_3d, g3, dlut, s));
+        } else {
+            STEP_OK(cf::launch_h2d<T>(CF_POL_TM, 1, fields, dch, s_tm, w.n_tm, g, dlut, s));
+            STEP_OK(cf::launch_h2d<T>(CF_POL_TE, 1, fields, dch, s_te, w.n_te, g, dlut, s));
+            STEP_OK(cf::launch_e2d<T>(CF_POL_TM, 1, fields, dch, s_tm, w.n_tm, g, dlut, s));
+            STEP_OK(cf::launch_e2d<T>(CF_POL_TE, 1, fields, dch, s_te, w.n_te, g, dlut, s));
+        }
         if (st.tb.ok) {
             cf::TBGrid tg{};
             tg.nx = p.nx;
@@ -334,64 +434,35 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             const int kh = cf::tb_shape<T>().kh;
             T* A = fields;
             T* B = reinterpret_cast<T*>(ws + L.fields2);
-            const int n_launch = 2 * ((o.n_steps + kh - 1) / kh);
-            const int lstride = std::max(1, n_launch / 200);
-            int launch = 0;
             for (int m = 0; m < o.n_steps; m += kh) {
                 const int ks = std::min(kh, o.n_steps - m);
                 for (int pol : {CF_POL_TM, CF_POL_TE}) {
-                    const int n = pol == CF_POL_TM ? n_tm : n_te;
+                    const int n = pol == CF_POL_TM ? w.n_tm : w.n_te;
                     if (n == 0) continue;
                     tg.nslots = n;
-                    const bool sample = time_it && launch % lstride == 0 && tk < (int)tev.size() / 2;
-                    if (sample) STEP_OK(hipEventRecord(tev[2 * tk], s));
+                    const bool take = smp.begin(s);
                     STEP_OK(cf::launch_tb2d<T>(pol, A, B, dch, pol == CF_POL_TM ? s_tm : s_te, tg, tabs,
                                                dlut, ks, m, s));
-                    if (sample) {
-                        STEP_OK(hipEventRecord(tev[2 * tk + 1], s));
-                        const double cu = (double)n * p.ncell * ks;
-                        timing->cu_total += cu;
-                        timing->bytes_total += cu * state_bytes;
-                        ++tk;
-                    }
-                    ++launch;
+                    const double cu = (double)n * p.ncell * ks;
+                    smp.end(take, s, cu, cu * state_bytes);
                 }
                 std::swap(A, B);
             }
-            timing->launches = launch;
         } else {
             for (int m = 0; m < o.n_steps; ++m) {
-                const bool sample = time_it && m % stride == 0 && tk < (int)tev.size() / 2;
-                if (sample) STEP_OK(hipEventRecord(tev[2 * tk], s));
-                STEP_OK(cf::launch_h2d<T>(CF_POL_TM, 0, fields, dch, s_tm, n_tm, g, dlut, s));
-                STEP_OK(cf::launch_h2d<T>(CF_POL_TE, 0, fields, dch, s_te, n_te, g, dlut, s));
-                STEP_OK(cf::launch_e2d<T>(CF_POL_TM, 0, fields, dch, s_tm, n_tm, g, dlut, s));
-                STEP_OK(cf::launch_e2d<T>(CF_POL_TE, 0, fields, dch, s_te, n_te, g, dlut, s));
-                if (sample) {
-                    STEP_OK(hipEventRecord(tev[2 * tk + 1], s));
-                    const double cu = (double)C * p.ncell;
-                    timing->cu_total += cu;
-                    timing->bytes_total += cu * state_bytes;
-                    ++tk;
+                const bool take = smp.begin(s);
+                if (three) {
+                    STEP_OK(cf::launch_h3d<T>(0, fields, psi, dch, s_3d, w.n_3d, g3, dlut, s));
+                    STEP_OK(cf::launch_e3d<T>(0, fields, psi, dch, s_3d, w.n_3d, g3, dlut, s));
+                } else {
+                    STEP_OK(cf::launch_h2d<T>(CF_POL_TM, 0, fields, dch, s_tm, w.n_tm, g, dlut, s));
+                    STEP_OK(cf::launch_h2d<T>(CF_POL_TE, 0, fields, dch, s_te, w.n_te, g, dlut, s));
+                    STEP_OK(cf::launch_e2d<T>(CF_POL_TM, 0, fields, dch, s_tm, w.n_tm, g, dlut, s));
+                    STEP_OK(cf::launch_e2d<T>(CF_POL_TE, 0, fields, dch, s_te, w.n_te, g, dlut, s));
                 }
-                STEP_OK(cf::launch_surface<T>(fields, dch, s_all, (int)C, tabs, dk, m, dt, dA, dacc, dgam,
-                                              (int)C, s));
-            }
-            timing->launches = o.n_steps;
-        }
-    } else {
-        // plain: one channel at a time in a single field block
-        for (size_t c = 0; c < C; ++c) {
-            const int* one = s_all + c;
-            const int pol = st.chans[c].pol;
-            STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
-            STEP_OK(cf::launch_kick<T>(fields, dch, one, 1, st.max_uniq, tabs, s));
-            STEP_OK(cf::launch_h2d<T>(pol, 1, fields, dch, one, 1, g, dlut, s));
-            STEP_OK(cf::launch_e2d<T>(pol, 1, fields, dch, one, 1, g, dlut, s));
-            for (int m = 0; m < o.n_steps; ++m) {
-                STEP_OK(cf::launch_h2d<T>(pol, 0, fields, dch, one, 1, g, dlut, s));
-                STEP_OK(cf::launch_e2d<T>(pol, 0, fields, dch, one, 1, g, dlut, s));
-                STEP_OK(cf::launch_surface<T>(fields, dch, one, 1, tabs, dk, m, dt, dA, dacc, dgam,
+                const double cu = (double)w.n_all * p.ncell;
+                smp.end(take, s, cu, cu * state_bytes);
+                STEP_OK(cf::launch_surface<T>(fields, dch, s_all, w.n_all, tabs, dk, m, dt, dA, dacc, dgam,
                                               (int)C, s));
             }
         }
@@ -403,15 +474,18 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
         STEP_OK(hipEventElapsedTime(&ms, e0, e1));
         *device_ms = ms;
     }
-    if (time_it) {
+    if (smp.on) {
         double tot = 0;
-        for (int k = 0; k < tk; ++k) {
+        for (int k = 0; k < smp.taken; ++k) {
             float ms = 0;
-            STEP_OK(hipEventElapsedTime(&ms, tev[2 * k], tev[2 * k + 1]));
+            STEP_OK(hipEventElapsedTime(&ms, smp.ev[2 * k], smp.ev[2 * k + 1]));
             tot += ms;
         }
-        timing->samples = tk;
+        timing->samples = smp.taken;
         timing->ms_total = tot;
+        timing->bytes_total = smp.bytes;
+        timing->cu_total = smp.cu;
+        timing->launches = smp.seen;
     }
     acc_out.assign(C * 2, 0.0);
     STEP_OK(hipMemcpy(acc_out.data(), ws + L.acc, C * 2 * 8, hipMemcpyDeviceToHost));
@@ -425,9 +499,10 @@ done:
     if (err != hipSuccess) (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    for (auto& e : tev) (void)hipEventDestroy(e);
-    if (err != hipSuccess) status = fail(CF_E_DEVICE, std::string("device step failed: ") + hipGetErrorString(err));
-    return status;
+    for (auto& e : smp.ev) (void)hipEventDestroy(e);
+    if (err != hipSuccess)
+        return fail(CF_E_DEVICE, std::string("device step failed: ") + hipGetErrorString(err));
+    return CF_OK;
 }
 
 }  // namespace
@@ -532,7 +607,6 @@ cf_status cf_solve(cf_problem* h, const cf_opts* o, void* workspace, size_t ws_b
     if (st != CF_OK) return st;
     if (!out) return fail(CF_E_ARG, "null result");
     const cf::Problem& p = h->p;
-    if (p.grid.ndim != 2) return fail(CF_E_UNSUPPORTED, "3D solve not available in this build");
     std::string e2;
     auto chans = selected_channels(p, *o, &e2);
     if (!e2.empty()) return fail(CF_E_ARG, e2);

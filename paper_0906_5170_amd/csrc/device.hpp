@@ -13,6 +13,7 @@ namespace cf {
 // (uidx/uoff) and the basis table.
 struct ChanDev {
     int64_t field_off;   // first element of the channel's field block
+    int64_t psi_off;     // first element of the channel's CPML block (3D)
     int64_t src_off;     // field_off + slot(src) * ncell
     int64_t meas_off;    // field_off + slot(meas) * ncell
     int32_t kind;        // 0 E-current source, 1 H-current source
@@ -62,6 +63,23 @@ struct TBShape {
 template <typename T>
 TBShape tb_shape();
 
+// 3D launch geometry.  The CPML along z has `pml` layers at each end; the
+// psi block of a channel is 4 components (Hx dz Ey, Hy dz Ex, Ex dz Hy,
+// Ey dz Hx) of psi_comp = 2 * pml * ny * nx values each.  pml_bh/pml_ch
+// (pml_be/pml_ce) hold b and c at the z positions of H_x, H_y (E_x, E_y).
+struct Grid3D {
+    int nx, ny, nz;
+    int64_t ncell;
+    int per[3];
+    const uint8_t* ids[6];
+    int pml;
+    int64_t psi_comp;
+    const double* pml_bh;
+    const double* pml_ch;
+    const double* pml_be;
+    const double* pml_ce;
+};
+
 struct SurfTables {
     const int32_t* gidx;
     const double* gw;
@@ -94,6 +112,13 @@ template <typename T>
 hipError_t launch_surface(const T* fields, const ChanDev* ch, const int* slots, int nslots,
                           const SurfTables& t, const double* ktab, int m, double dt, double dA,
                           double* acc, double* gamma, int gamma_stride, hipStream_t s);
+
+template <typename T>
+hipError_t launch_h3d(int mode, T* fields, T* psi, const ChanDev* ch, const int* slots, int nslots,
+                      const Grid3D& g, const T* lut, hipStream_t s);
+template <typename T>
+hipError_t launch_e3d(int mode, T* fields, T* psi, const ChanDev* ch, const int* slots, int nslots,
+                      const Grid3D& g, const T* lut, hipStream_t s);
 
 // Fused launch: `ksteps` (<= tb_shape<T>().kh) full time steps of every
 // listed channel of polarization pol, reading src and writing dst; measures

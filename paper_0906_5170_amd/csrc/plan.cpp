@@ -448,6 +448,36 @@ static double k_general(double t, double s) {
     return 0.25 * s * s * h * sum;
 }
 
+// CPML profile (Roden-Gedney with kappa = 1, alpha = 0): in the layers of
+// P cells at both ends of z, sigma_p(z) = sigma_max (depth / P)^3 with
+// depth the distance in cells from the layer's inner face and
+// sigma_max = -(3 + 1) ln(1e-8) / (2 P dx); b = exp(-sigma_p dt), c = b - 1.
+void pml_tables(const Problem& p, double courant, std::vector<double>& bh, std::vector<double>& ch,
+                std::vector<double>& be, std::vector<double>& ce) {
+    const int nz = p.nz, P = p.grid.bc[2] == CF_BC_PML ? p.grid.pml_cells[2] : 0;
+    bh.assign(nz, 1.0);
+    ch.assign(nz, 0.0);
+    be.assign(nz, 1.0);
+    ce.assign(nz, 0.0);
+    if (P <= 0) return;
+    const double dx = 1.0 / p.grid.res, dt = courant * dx;
+    const double smax = -(3.0 + 1.0) * std::log(1e-8) / (2.0 * P * dx);
+    for (int k = 0; k < nz; ++k)
+        for (int half = 0; half < 2; ++half) {
+            const double z = k + 0.5 * half;
+            const double depth = std::max(std::max(P - z, z - (nz - P)), 0.0);
+            const double sg = smax * std::pow(depth / P, 3);
+            const double b = std::exp(-sg * dt);
+            if (half) {
+                bh[k] = b;
+                ch[k] = b - 1.0;
+            } else {
+                be[k] = b;
+                ce[k] = b - 1.0;
+            }
+        }
+}
+
 void kernel_table(int kernel, double sigma, double dt, int n, double* out) {
     for (int m = 1; m <= n; ++m) {
         double t = m * dt;

@@ -91,4 +91,8 @@ std::vector<double> coefficient_lut(const Problem& p, double sigma, double coura
 // K(t_m), m = 1..n
 void kernel_table(int kernel, double sigma, double dt, int n, double* out);
 
+// CPML along z: b, c at the z positions of H_x/H_y (k + 1/2) and E_x/E_y (k).
+void pml_tables(const Problem& p, double courant, std::vector<double>& bh, std::vector<double>& ch,
+                std::vector<double>& be, std::vector<double>& ce);
+
 }  // namespace cf

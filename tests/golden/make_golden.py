@@ -5,6 +5,7 @@ casimir_inputs; no value comes from the HIP library.
 
     python tests/golden/make_golden.py c2      # 2D TE+TM piston, 400x200, T=10000
     python tests/golden/make_golden.py c1      # 2D TM piston, 80x40, T=2000
+    python tests/golden/make_golden.py c4s     # 3D sphere-plate 192^3: 5 channels, 24 steps
 """
 import json
 import os
@@ -16,12 +17,30 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
-from casimir_inputs import c1_piston_tm_fp64, c2_piston_tetm_fp32  # noqa: E402
+from casimir_inputs import c1_piston_tm_fp64, c2_piston_tetm_fp32, c4_sphere_plate  # noqa: E402
 
 CASES = {
     "c1": ("c1_piston_tm_oracle.json", c1_piston_tm_fp64),
     "c2": ("c2_piston_tetm_oracle.json", c2_piston_tetm_fp32),
 }
+# 3D sample: channels on x-, z-lo and z-hi faces, E and H kinds, several harmonics
+C4_SUBSET = [1, 512, 571, 898, 1279]
+C4_STEPS = 24
+
+
+def c4_sample(workers=5):
+    wl = c4_sphere_plate()
+    t0 = time.time()
+    r = oracle.solve(wl, n_steps=C4_STEPS, channel_subset=C4_SUBSET, workers=workers, chunk=1,
+                     keep_gamma=True)
+    out = dict(workload=wl.name, shape=list(wl.shape), n_steps=C4_STEPS, subset=C4_SUBSET,
+               gamma=[[float(v) for v in row] for row in r.gamma],
+               per_channel=[float(v) for v in r.acc], sign=[float(v) for v in r.sign],
+               oracle_seconds=time.time() - t0,
+               source="oracle.solve (FP64 NumPy), written by tests/golden/make_golden.py")
+    with open(os.path.join(HERE, "c4_sphere_plate_sample_oracle.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("c4s", f"{time.time() - t0:.1f}s")
 
 
 def main(which, workers=8):
@@ -47,4 +66,7 @@ def main(which, workers=8):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1])
+    if sys.argv[1] == "c4s":
+        c4_sample()
+    else:
+        main(sys.argv[1])
