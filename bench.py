@@ -57,6 +57,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--n-steps", type=int, default=None, help="override T (testing only)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB (a plain copy kernel of known size, "
+                         "the reference for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the channel-parallel "
@@ -79,6 +82,15 @@ def main():
     wl = c2_piston_tetm_fp32()
     if args.n_steps:
         wl = wl.replace(n_steps=args.n_steps)
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * 2**20 // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
+        del a, b
     prob = cf.Problem.from_workload(wl)
     opts = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol=wl.pol,
                 kernel=wl.kernel, precision="fp32")
@@ -110,10 +122,12 @@ def main():
     achieved = rt["stencil_alg_bytes"] / avg_s / 1e9 if avg_s > 0 else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-                "kernel": "2D field update (H and E halves) of all channels, one time step",
+                "kernel": "k_rb2d: fused register-blocked 2D update of all TM (or TE) channels, "
+                          "steps_per_launch time steps per launch",
                 "avg_launch_ms": rt["stencil_ms_avg"], "launches_timed": rt["stencil_samples"],
                 "alg_bytes_per_launch": rt["stencil_alg_bytes"],
-                "alg_bytes_per_cell_update": rt["stencil_alg_bytes"] / rt["stencil_cell_updates"]}
+                "alg_bytes_per_cell_update": rt["stencil_alg_bytes"] / rt["stencil_cell_updates"],
+                "tile_variant": rt["tile_variant"], "steps_per_launch": rt["tile_halo"]}
 
     out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
@@ -127,6 +141,23 @@ def main():
            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                           "n": len(lat)},
            "force": r["force"], "roofline": roofline}
+
+    # every fused-kernel variant on the same solve (T = 1000), the autotuner's
+    # search space; all variants give bitwise-identical results
+    sweep = []
+    for v in range(1, 32):
+        try:
+            rv = prob.solve(workspace=ws, tile_variant=v, **dict(opts, n_steps=1000))
+        except cf.CfError:
+            break
+        if not rv["fused"] or rv["tile_variant"] != v:
+            break
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rv = prob.solve(workspace=ws, tile_variant=v, **dict(opts, n_steps=1000))
+        sweep.append({"variant": v, "steps_per_launch": rv["tile_halo"],
+                      "ms_per_1000_steps": (time.perf_counter() - t1) * 1e3})
+    out["tile_sweep"] = sweep
 
     gold = os.path.join(ROOT, "tests", "golden", "c2_piston_tetm_oracle.json")
     if os.path.exists(gold) and not args.n_steps:

@@ -139,6 +139,10 @@ typedef struct cf_opts {
                         /* the channels run in consecutive waves of this many */
                         /* (0 = all at once).  Bounds the workspace of large  */
                         /* 3D problems; results do not depend on it.          */
+    int tile_variant;   /* fused 2D kernel tile shape: 0 = autotune (timed on */
+                        /* the solve's own data, cached per shape in the      */
+                        /* process and in $CF_AUTOTUNE_CACHE when set),       */
+                        /* k >= 1 = variant k-1.  Results do not depend on it. */
 } cf_opts;
 
 typedef struct cf_info {
@@ -177,6 +181,8 @@ typedef struct cf_result {
                                  /* one read + one write of the state it advances                   */
     double stencil_cell_updates; /* cell-updates one field-update launch performs                   */
     int fused;                   /* 1 when the fused multi-step kernel advanced the fields          */
+    int tile_variant;            /* fused kernel variant used (1-based), 0 if not fused             */
+    int tile_halo;               /* steps per fused launch of that variant                          */
 } cf_result;
 
 typedef struct cf_problem cf_problem;

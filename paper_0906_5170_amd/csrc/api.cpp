@@ -5,8 +5,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -56,7 +62,10 @@ struct Wave {
 };
 
 struct Staged {
-    TBPlan tb;
+    TBPlan tb;                             // plan of the chosen variant
+    int variant = -1;                      // chosen fused variant (-1: not fused)
+    std::vector<TBPlan> plans;             // plan per fused variant
+    std::vector<cf::TBShape> shapes;
     std::vector<cf::Channel> chans;       // channels run, in output order
     std::vector<cf::ChanDev> dev;          // one descriptor per channel run
     std::vector<int> slot_lists;           // concatenated per-wave lists
@@ -161,8 +170,64 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         st.waves.push_back(w);
     }
     if (!plain && p.grid.ndim == 2 && !(o.flags & CF_FLAG_SPLIT)) {
-        const cf::TBShape sh = o.precision == CF_FP64 ? cf::tb_shape<double>() : cf::tb_shape<float>();
-        st.tb = plan_tiles(p, chans, sh);
+        cf::TBShape sh[cf::kMaxVariants];
+        const int nv = o.precision == CF_FP64 ? cf::tb_variants<double>(sh, cf::kMaxVariants)
+                                              : cf::tb_variants<float>(sh, cf::kMaxVariants);
+        for (int v = 0; v < nv; ++v) {
+            st.shapes.push_back(sh[v]);
+            st.plans.push_back(plan_tiles(p, chans, sh[v]));
+        }
+        if (o.tile_variant >= 1 && o.tile_variant <= nv && st.plans[o.tile_variant - 1].ok) {
+            st.variant = o.tile_variant - 1;
+        } else {
+            for (int v = 0; v < nv; ++v)
+                if (st.plans[v].ok) {
+                    st.variant = v;   // provisional: the autotuner may replace it
+                    break;
+                }
+        }
+        if (st.variant >= 0) st.tb = st.plans[st.variant];
+    }
+}
+
+// ---- autotuner cache: "key variant" lines ---------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const cf::Problem& p, const cf_opts& o, int n_tm, int n_te) {
+    std::ostringstream k;
+    k << "2d fp" << (o.precision == CF_FP64 ? 64 : 32) << " " << p.nx << "x" << p.ny << " tm" << n_tm << " te"
+      << n_te;
+    return k.str();
+}
+
+bool tune_lookup(const std::string& key, int* v) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) {
+        g_tune_loaded = true;
+        if (const char* path = std::getenv("CF_AUTOTUNE_CACHE")) {
+            std::ifstream f(path);
+            std::string line;
+            while (std::getline(f, line)) {
+                const size_t at = line.rfind(' ');
+                if (at == std::string::npos) continue;
+                g_tune[line.substr(0, at)] = std::atoi(line.c_str() + at + 1);
+            }
+        }
+    }
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *v = it->second;
+    return true;
+}
+
+void tune_store(const std::string& key, int v) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = v;
+    if (const char* path = std::getenv("CF_AUTOTUNE_CACHE")) {
+        std::ofstream f(path, std::ios::app);
+        f << key << " " << v << "\n";
     }
 }
 
@@ -228,7 +293,7 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.acc = take(C * 2 * 8);
     L.gamma = (o.flags & CF_FLAG_KEEP_GAMMA) ? take((size_t)o.n_steps * C * 8) : off;
     L.fields = take(block);
-    L.fields2 = st.tb.ok ? take(block) : off;
+    L.fields2 = st.variant >= 0 ? take(block) : off;
     L.psi = st.psi_comp > 0 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
     L.total = off;
     return L;
@@ -238,6 +303,7 @@ struct StencilTiming {
     double ms_total = 0, bytes_total = 0, cu_total = 0;
     int samples = 0;
     int launches = 0;
+    int variant = -1;
 };
 
 // Sampled HIP-event timing of field-update launches on the solve's stream.
@@ -354,16 +420,86 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     if (smp.on) {
         smp.ev.resize(2 * 256);
         for (auto& e : smp.ev) CF_HIP(hipEventCreate(&e));
-        const int kh = st.tb.ok ? cf::tb_shape<T>().kh : 1;
-        const int per_wave = st.tb.ok ? 2 * ((o.n_steps + kh - 1) / kh) : o.n_steps;
+        const int kh = st.variant >= 0 ? st.shapes[st.variant].kh : 1;
+        const int per_wave = st.variant >= 0 ? 2 * ((o.n_steps + kh - 1) / kh) : o.n_steps;
         smp.stride = std::max(1, per_wave * (int)st.waves.size() / 200);
     }
+    auto make_tg = [&](const TBPlan& pl) {
+        cf::TBGrid tg{};
+        tg.nx = p.nx;
+        tg.ny = p.ny;
+        tg.ncell = p.ncell;
+        tg.perx = g.perx;
+        tg.pery = g.pery;
+        for (int c = 0; c < cf::kNumComp; ++c) tg.ids[c] = g.ids[c];
+        tg.base_x = pl.base_x;
+        tg.base_y = pl.base_y;
+        tg.ntx = pl.ntx;
+        tg.nty = pl.nty;
+        tg.stile = pl.stile;
+        tg.dt = dt;
+        tg.dA = dA;
+        tg.ktab = dk;
+        tg.acc = dacc;
+        tg.gamma = dgam;
+        tg.gamma_stride = (int)C;
+        return tg;
+    };
+    int variant = st.variant;
     hipError_t err = hipSuccess;
 #define STEP_OK(expr)                     \
     do {                                  \
         err = (expr);                     \
         if (err != hipSuccess) goto done; \
     } while (0)
+    if (variant >= 0 && o.tile_variant == 0 && !st.waves.empty()) {
+        // autotune: time every applicable variant on this solve's own buffers
+        // (fields, accumulators and Gamma are reset before the real run)
+        const Wave& w = st.waves[0];
+        const bool tm = w.n_tm >= w.n_te;
+        const int n = tm ? w.n_tm : w.n_te;
+        const int* sl = dslots + (tm ? w.tm_off : w.te_off);
+        const std::string key = tune_key(p, o, w.n_tm, w.n_te);
+        int cached;
+        if (tune_lookup(key, &cached) && cached >= 0 && cached < (int)st.plans.size() && st.plans[cached].ok) {
+            variant = cached;
+        } else if (n > 0) {
+            double best = 1e300;
+            hipEvent_t t0, t1;
+            STEP_OK(hipEventCreate(&t0));
+            STEP_OK(hipEventCreate(&t1));
+            for (int v = 0; v < (int)st.plans.size(); ++v) {
+                if (!st.plans[v].ok) continue;
+                cf::TBGrid tg = make_tg(st.plans[v]);
+                tg.nslots = n;
+                tg.gamma = nullptr;
+                const int kh = st.shapes[v].kh;
+                T* A = fields;
+                T* B = reinterpret_cast<T*>(ws + L.fields2);
+                STEP_OK(cf::launch_tb2d<T>(v, tm ? CF_POL_TM : CF_POL_TE, A, B, dch, sl, tg, tabs, dlut, kh, 0, s));
+                STEP_OK(hipEventRecord(t0, s));
+                for (int r = 0; r < 3; ++r) {
+                    STEP_OK(cf::launch_tb2d<T>(v, tm ? CF_POL_TM : CF_POL_TE, A, B, dch, sl, tg, tabs, dlut, kh,
+                                               0, s));
+                    std::swap(A, B);
+                }
+                STEP_OK(hipEventRecord(t1, s));
+                STEP_OK(hipEventSynchronize(t1));
+                float ms = 0;
+                STEP_OK(hipEventElapsedTime(&ms, t0, t1));
+                const double per_cu = ms / (3.0 * n * (double)p.ncell * kh);
+                if (per_cu < best) {
+                    best = per_cu;
+                    variant = v;
+                }
+            }
+            (void)hipEventDestroy(t0);
+            (void)hipEventDestroy(t1);
+            tune_store(key, variant);
+        }
+        STEP_OK(hipMemsetAsync(ws + L.acc, 0, C * 2 * 8, s));
+    }
+    timing->variant = variant;
     STEP_OK(hipEventRecord(e0, s));
     for (const Wave& w : st.waves) {
         const int* s_tm = dslots + w.tm_off;
@@ -412,26 +548,9 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             STEP_OK(cf::launch_e2d<T>(CF_POL_TM, 1, fields, dch, s_tm, w.n_tm, g, dlut, s));
             STEP_OK(cf::launch_e2d<T>(CF_POL_TE, 1, fields, dch, s_te, w.n_te, g, dlut, s));
         }
-        if (st.tb.ok) {
-            cf::TBGrid tg{};
-            tg.nx = p.nx;
-            tg.ny = p.ny;
-            tg.ncell = p.ncell;
-            tg.perx = g.perx;
-            tg.pery = g.pery;
-            for (int c = 0; c < cf::kNumComp; ++c) tg.ids[c] = g.ids[c];
-            tg.base_x = st.tb.base_x;
-            tg.base_y = st.tb.base_y;
-            tg.ntx = st.tb.ntx;
-            tg.nty = st.tb.nty;
-            tg.stile = st.tb.stile;
-            tg.dt = dt;
-            tg.dA = dA;
-            tg.ktab = dk;
-            tg.acc = dacc;
-            tg.gamma = dgam;
-            tg.gamma_stride = (int)C;
-            const int kh = cf::tb_shape<T>().kh;
+        if (variant >= 0) {
+            cf::TBGrid tg = make_tg(st.plans[variant]);
+            const int kh = st.shapes[variant].kh;
             T* A = fields;
             T* B = reinterpret_cast<T*>(ws + L.fields2);
             for (int m = 0; m < o.n_steps; m += kh) {
@@ -441,8 +560,8 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
                     if (n == 0) continue;
                     tg.nslots = n;
                     const bool take = smp.begin(s);
-                    STEP_OK(cf::launch_tb2d<T>(pol, A, B, dch, pol == CF_POL_TM ? s_tm : s_te, tg, tabs,
-                                               dlut, ks, m, s));
+                    STEP_OK(cf::launch_tb2d<T>(variant, pol, A, B, dch, pol == CF_POL_TM ? s_tm : s_te, tg,
+                                               tabs, dlut, ks, m, s));
                     const double cu = (double)n * p.ncell * ks;
                     smp.end(take, s, cu, cu * state_bytes);
                 }
@@ -683,7 +802,9 @@ cf_status cf_solve(cf_problem* h, const cf_opts* o, void* workspace, size_t ws_b
     out->stencil_ms_avg = tim.samples ? tim.ms_total / tim.samples : 0.0;
     out->stencil_alg_bytes = tim.samples ? tim.bytes_total / tim.samples : 0.0;
     out->stencil_cell_updates = tim.samples ? tim.cu_total / tim.samples : 0.0;
-    out->fused = sg.tb.ok ? 1 : 0;
+    out->fused = tim.variant >= 0 ? 1 : 0;
+    out->tile_variant = tim.variant + 1;
+    out->tile_halo = tim.variant >= 0 ? sg.shapes[tim.variant].kh : 0;
     if (!finite) return fail(CF_E_NONFINITE, "a force accumulator is not finite");
     g_err.clear();
     return CF_OK;

@@ -56,12 +56,14 @@ struct TBGrid {
     int gamma_stride;
 };
 
-// Tile interior (tx x ty cells) and halo / maximum steps per launch.
+// Tile interior (tx x ty cells) and halo / maximum steps per launch of the
+// fused kernel's variants (index = variant).
 struct TBShape {
     int tx, ty, kh;
 };
+constexpr int kMaxVariants = 8;
 template <typename T>
-TBShape tb_shape();
+int tb_variants(TBShape* out, int max);
 
 // 3D launch geometry.  The CPML along z has `pml` layers at each end; the
 // psi block of a channel is 4 components (Hx dz Ey, Hy dz Ex, Ex dz Hy,
@@ -124,7 +126,7 @@ hipError_t launch_e3d(int mode, T* fields, T* psi, const ChanDev* ch, const int*
 // listed channel of polarization pol, reading src and writing dst; measures
 // Gamma at steps m0 .. m0 + ksteps - 1 in the surface tile.
 template <typename T>
-hipError_t launch_tb2d(int pol, const T* src, T* dst, const ChanDev* ch, const int* slots,
+hipError_t launch_tb2d(int variant, int pol, const T* src, T* dst, const ChanDev* ch, const int* slots,
                        const TBGrid& g, const SurfTables& t, const T* lut, int ksteps, int m0,
                        hipStream_t s);
 

@@ -237,27 +237,28 @@ struct Pair {
     T a, b;
 };
 
-// Value of v held by lane l+1 (DPP wave_shl:1); lane 63 keeps its own.
+// Value of v held by lane l+1 (DPP wave_shl:1) / lane l-1 (wave_shr:1).  The
+// lane with no neighbour (63 / 0) reads 0 (bound_ctrl); it lies in the rim
+// that is never written back.
 __device__ __forceinline__ float from_next(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
-// Value of v held by lane l-1 (DPP wave_shr:1); lane 0 keeps its own.
 __device__ __forceinline__ float from_prev(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double from_next(double v) {
     const int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
-                            __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+    return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x130, 0xf, 0xf, true),
+                            __builtin_amdgcn_mov_dpp(lo, 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double from_prev(double v) {
     const int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
-                            __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+    return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x138, 0xf, 0xf, true),
+                            __builtin_amdgcn_mov_dpp(lo, 0x138, 0xf, 0xf, true));
 }
 
-template <typename T, int POL, int RBW, int B, int KH>
-__global__ __launch_bounds__(64 * RBW) __attribute__((amdgpu_waves_per_eu(4)))
+template <typename T, int POL, int RBW, int B, int KH, bool CREG>
+__global__ __launch_bounds__(64 * RBW) __attribute__((amdgpu_waves_per_eu(CREG ? 3 : 4)))
 void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __restrict__ ch,
             const int* __restrict__ slots, TBGrid g, SurfTables t, const T* __restrict__ lut, int ksteps,
             int m0) {
@@ -345,6 +346,18 @@ void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __res
     __syncthreads();
 
 #define CF_ID(p, r) ((p[(r) >> 2] >> (8 * ((r) & 3))) & 255u)
+    // CREG: each cell's (a, b) pairs are constant over the launch and can be
+    // held in registers instead of being looked up in LDS every step.
+    Pair<T> k0[CREG ? B : 1], k1[CREG ? B : 1], k2[CREG ? B : 1];
+    if constexpr (CREG) {
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            k0[r] = L[0][CF_ID(m0p, r)];
+            k1[r] = L[1][CF_ID(m1p, r)];
+            k2[r] = L[2][CF_ID(m2p, r)];
+        }
+    }
+#define CF_K(s, r) (CREG ? k##s[(CREG ? (r) : 0)] : L[s][CF_ID(m##s##p, r)])
     for (int step = 0; step < ksteps; ++step) {
         // ---- H half: needs the E row above the wave's band ----
         xe[w][lane] = f0[0];
@@ -356,7 +369,7 @@ void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __res
                 const T ez = f0[r];
                 const T ezr = from_next(ez);
                 const T ezu = r + 1 < B ? f0[r + 1] : e_above;
-                const Pair<T> cx = L[1][CF_ID(m1p, r)], cy = L[2][CF_ID(m2p, r)];
+                const Pair<T> cx = CF_K(1, r), cy = CF_K(2, r);
                 f1[r] = yee_sub(cx.a, f1[r], cx.b, ezu - ez);
                 f2[r] = yee_sub(cy.a, f2[r], cy.b, ez - ezr);
             }
@@ -366,7 +379,7 @@ void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __res
                 const T ex = f0[r], ey = f1[r];
                 const T eyr = from_next(ey);
                 const T exu = r + 1 < B ? f0[r + 1] : e_above;
-                const Pair<T> cz = L[2][CF_ID(m2p, r)];
+                const Pair<T> cz = CF_K(2, r);
                 f2[r] = yee_sub(cz.a, f2[r], cz.b, (eyr - ey) - (exu - ex));
             }
         }
@@ -381,7 +394,7 @@ void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __res
                 const T hyl = from_prev(hy);
                 const T hxd = r > 0 ? f1[r - 1] : h_below;
                 const T curl = (hy - hyl) - (hx - hxd);
-                const Pair<T> cz = L[0][CF_ID(m0p, r)];
+                const Pair<T> cz = CF_K(0, r);
                 f0[r] = yee_add(cz.a, f0[r], cz.b, curl);
             }
         } else {
@@ -390,7 +403,7 @@ void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __res
                 const T hz = f2[r];
                 const T hzl = from_prev(hz);
                 const T hzd = r > 0 ? f2[r - 1] : h_below;
-                const Pair<T> cx = L[0][CF_ID(m0p, r)], cy = L[1][CF_ID(m1p, r)];
+                const Pair<T> cx = CF_K(0, r), cy = CF_K(1, r);
                 f0[r] = yee_add(cx.a, f0[r], cx.b, hz - hzd);
                 f1[r] = yee_sub(cy.a, f1[r], cy.b, hz - hzl);
             }
@@ -417,6 +430,7 @@ void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __res
             __syncthreads();
         }
     }
+#undef CF_K
 #undef CF_ID
     if (stile && tid == 0) {
         g.acc[2 * slot] = acc_s;
@@ -445,13 +459,36 @@ inline dim3 grid2d(const Grid2D& g, int nslots) {
 
 }  // namespace
 
-// register blocking: W waves of B rows, halo KH (tile = (64 - 2 KH) x (W B - 2 KH))
-constexpr int kRbF32W = 8, kRbF32B = 8, kRbF32K = 8;
-constexpr int kRbF64W = 8, kRbF64B = 4, kRbF64K = 4;
-template <>
-TBShape tb_shape<float>() { return TBShape{64 - 2 * kRbF32K, kRbF32W * kRbF32B - 2 * kRbF32K, kRbF32K}; }
-template <>
-TBShape tb_shape<double>() { return TBShape{64 - 2 * kRbF64K, kRbF64W * kRbF64B - 2 * kRbF64K, kRbF64K}; }
+// Register-blocking variants: W waves of B rows and halo KH give a tile of
+// (64 - 2 KH) x (W B - 2 KH) cells and at most KH steps per launch.  All
+// variants evaluate the same arithmetic; the autotuner picks among them.
+struct RbVariant {
+    int W, B, KH;
+    bool creg;   // coefficients held in registers over the launch
+};
+constexpr RbVariant kRbF32[] = {{8, 8, 8, false}, {8, 8, 6, false}, {8, 8, 4, false}, {16, 4, 8, false},
+                                {8, 8, 8, true},  {16, 4, 8, true},  {8, 8, 6, true}};
+constexpr RbVariant kRbF64[] = {{8, 4, 4, false}, {8, 4, 2, false}, {16, 4, 4, false}, {16, 4, 4, true}};
+
+template <typename T>
+static const RbVariant* rb_table(int* n) {
+    if (sizeof(T) == 4) {
+        *n = sizeof(kRbF32) / sizeof(kRbF32[0]);
+        return kRbF32;
+    }
+    *n = sizeof(kRbF64) / sizeof(kRbF64[0]);
+    return kRbF64;
+}
+
+template <typename T>
+int tb_variants(TBShape* out, int max) {
+    int n;
+    const RbVariant* v = rb_table<T>(&n);
+    for (int i = 0; i < n && i < max; ++i) out[i] = TBShape{64 - 2 * v[i].KH, v[i].W * v[i].B - 2 * v[i].KH, v[i].KH};
+    return n;
+}
+template int tb_variants<float>(TBShape*, int);
+template int tb_variants<double>(TBShape*, int);
 
 template <typename T>
 hipError_t launch_h2d(int pol, int mode, T* fields, const ChanDev* ch, const int* slots, int nslots,
@@ -502,23 +539,47 @@ hipError_t launch_surface(const T* fields, const ChanDev* ch, const int* slots, 
     return hipGetLastError();
 }
 
+template <typename T, int W, int B, int KH, bool CREG>
+static void rb_launch(int pol, dim3 grid, hipStream_t s, const T* src, T* dst, const ChanDev* ch,
+                      const int* slots, const TBGrid& g, const SurfTables& t, const T* lut, int ksteps, int m0) {
+    dim3 block(64 * W);
+    if (pol == CF_POL_TM)
+        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TM, W, B, KH, CREG>), grid, block, 0, s, src, dst, ch, slots, g,
+                           t, lut, ksteps, m0);
+    else
+        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TE, W, B, KH, CREG>), grid, block, 0, s, src, dst, ch, slots, g,
+                           t, lut, ksteps, m0);
+}
+
 template <typename T>
-hipError_t launch_tb2d(int pol, const T* src, T* dst, const ChanDev* ch, const int* slots,
+hipError_t launch_tb2d(int variant, int pol, const T* src, T* dst, const ChanDev* ch, const int* slots,
                        const TBGrid& g, const SurfTables& t, const T* lut, int ksteps, int m0,
                        hipStream_t s) {
     if (g.nslots <= 0) return hipSuccess;
-    const TBShape sh = tb_shape<T>();
-    if (ksteps < 1 || ksteps > sh.kh) return hipErrorInvalidValue;
+    int n;
+    const RbVariant* v = rb_table<T>(&n);
+    if (variant < 0 || variant >= n) return hipErrorInvalidValue;
+    if (ksteps < 1 || ksteps > v[variant].KH) return hipErrorInvalidValue;
     const int groups = (g.nslots + 7) / 8;
-    constexpr bool f32 = sizeof(T) == 4;
-    constexpr int W = f32 ? kRbF32W : kRbF64W, B = f32 ? kRbF32B : kRbF64B, KH = f32 ? kRbF32K : kRbF64K;
-    dim3 grid(8 * groups * g.ntx * g.nty), block(64 * W);
-    if (pol == CF_POL_TM)
-        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TM, W, B, KH>), grid, block, 0, s, src, dst, ch, slots, g, t,
-                           lut, ksteps, m0);
-    else
-        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TE, W, B, KH>), grid, block, 0, s, src, dst, ch, slots, g, t,
-                           lut, ksteps, m0);
+    dim3 grid(8 * groups * g.ntx * g.nty);
+    if constexpr (sizeof(T) == 4) {
+        switch (variant) {
+            case 0: rb_launch<T, 8, 8, 8, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
+            case 1: rb_launch<T, 8, 8, 6, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
+            case 2: rb_launch<T, 8, 8, 4, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
+            case 3: rb_launch<T, 16, 4, 8, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
+            case 4: rb_launch<T, 8, 8, 8, true>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
+            case 5: rb_launch<T, 16, 4, 8, true>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
+            default: rb_launch<T, 8, 8, 6, true>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
+        }
+    } else {
+        switch (variant) {
+            case 0: rb_launch<T, 8, 4, 4, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
+            case 1: rb_launch<T, 8, 4, 2, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
+            case 2: rb_launch<T, 16, 4, 4, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
+            default: rb_launch<T, 16, 4, 4, true>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
+        }
+    }
     return hipGetLastError();
 }
 
@@ -532,7 +593,7 @@ hipError_t launch_tb2d(int pol, const T* src, T* dst, const ChanDev* ch, const i
     template hipError_t launch_surface<T>(const T*, const ChanDev*, const int*, int, const SurfTables&, \
                                           const double*, int, double, double, double*, double*, int,    \
                                           hipStream_t);                                                 \
-    template hipError_t launch_tb2d<T>(int, const T*, T*, const ChanDev*, const int*, const TBGrid&,    \
+    template hipError_t launch_tb2d<T>(int, int, const T*, T*, const ChanDev*, const int*, const TBGrid&, \
                                        const SurfTables&, const T*, int, int, hipStream_t);
 CF_INSTANTIATE(float)
 CF_INSTANTIATE(double)

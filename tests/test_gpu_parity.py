@@ -118,6 +118,20 @@ def test_fused_bitwise_equals_split(cf, precision):
     np.testing.assert_array_equal(a["per_channel"], b["per_channel"])
 
 
+@pytest.mark.parametrize("precision,nvar", [("fp32", 7), ("fp64", 4)])
+def test_every_tile_variant_bitwise_equals_split(cf, precision, nvar):
+    announce(f"fused tile variants 1..{nvar} vs split, {precision}")
+    wl = SMALL["ragged_61x37"]().replace(n_steps=53)
+    ref = run(cf, wl, precision=precision, split=True)
+    for v in range(1, nvar + 1):
+        r = run(cf, wl, precision=precision, tile_variant=v)
+        assert r["fused"] and r["tile_variant"] == v
+        np.testing.assert_array_equal(r["per_channel"], ref["per_channel"])
+    auto = run(cf, wl, precision=precision)
+    assert auto["fused"] and 1 <= auto["tile_variant"] <= nvar
+    np.testing.assert_array_equal(auto["per_channel"], ref["per_channel"])
+
+
 def test_c1_fp32_within_1e4(cf, c1_ref):
     announce("c1 fp32 fields, fp64 accumulation")
     g = run(cf, c1_piston_tm_fp64(), precision="fp32")
