@@ -56,6 +56,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--n-steps", type=int, default=None, help="override T (testing only)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB (a plain copy kernel of known size, "
@@ -158,6 +159,32 @@ def main():
         sweep.append({"variant": v, "steps_per_launch": rv["tile_halo"],
                       "ms_per_1000_steps": (time.perf_counter() - t1) * 1e3})
     out["tile_sweep"] = sweep
+
+    if not args.no_batch:
+        # batching extension: the 24-clearance uneven piston set (h in [0.1, 2],
+        # grid heights 84..160) in one batched launch sequence vs one problem
+        # after another (each fused), T = 1000 steps
+        from casimir_inputs import c3_uneven_set
+        set_wl = [w.replace(n_steps=1000) for w in c3_uneven_set()]
+        probs = [cf.Problem.from_workload(w) for w in set_wl]
+        bo = dict(opts, n_steps=1000)
+        cf.batch_solve(probs, **bo)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rb = cf.batch_solve(probs, **bo)
+        tb = time.perf_counter() - t1
+        cu = sum(r["cell_updates"] for r in rb)
+        for p_ in probs:
+            p_.solve(**bo)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for p_ in probs:
+            p_.solve(**bo)
+        ts = time.perf_counter() - t1
+        out["batched_uneven"] = {"workload": "24 TE+TM pistons, h = linspace(0.1, 2.0), 400 x (84..160), "
+                                             f"{sum(r['n_channels'] for r in rb)} channels, T=1000, FP32",
+                                 "value": cu / tb, "unit": "cell-updates/s", "ms": tb * 1e3,
+                                 "sequential_ms": ts * 1e3, "speedup_vs_sequential": ts / tb}
 
     gold = os.path.join(ROOT, "tests", "golden", "c2_piston_tetm_oracle.json")
     if os.path.exists(gold) and not args.n_steps:

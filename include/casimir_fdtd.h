@@ -217,6 +217,19 @@ cf_status cf_workspace_size(const cf_problem* p, const cf_opts* opts, size_t* by
 cf_status cf_solve(cf_problem* p, const cf_opts* opts, void* workspace, size_t ws_bytes,
                    cf_result* out);
 
+/* Batched solve: n problems (for instance a sweep of sidewall separations)
+ * with the same options, advanced together.  2D problems whose stress
+ * surfaces fit the fused kernel's tiles share one fused launch sequence:
+ * every launch advances the channels of all of them (each problem keeps its
+ * own grid, materials, surface and coefficient table).  Any other problem is
+ * solved on its own as by cf_solve.  outs[i] receives problem i's result;
+ * channel_subset, max_resident and CF_FLAG_KEEP_GAMMA are not used.
+ * workspace is NULL (allocated internally) or a device buffer of at least
+ * cf_batch_workspace_size() bytes. */
+cf_status cf_batch_workspace_size(cf_problem* const* probs, int n, const cf_opts* opts, size_t* bytes);
+cf_status cf_batch_solve(cf_problem* const* probs, int n, const cf_opts* opts, void* workspace,
+                         size_t ws_bytes, cf_result* outs);
+
 /* The time kernel K(t_m) = 2 pi Im g(-t_m), t_m = m dt for m = 1..n
  * (Appendix A, general and z-invariant forms), written to out[m-1]. Host
  * only. */

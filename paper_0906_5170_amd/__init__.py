@@ -81,7 +81,8 @@ class _Result(C.Structure):
 _lib = None
 
 EXPORTS = ("cf_problem_create", "cf_problem_destroy", "cf_problem_info", "cf_channel_table",
-           "cf_validate", "cf_workspace_size", "cf_solve", "cf_kernel_table", "cf_last_error")
+           "cf_validate", "cf_workspace_size", "cf_solve", "cf_kernel_table", "cf_last_error",
+           "cf_batch_workspace_size", "cf_batch_solve")
 
 
 def load():
@@ -110,6 +111,10 @@ def load():
     lib.cf_workspace_size.argtypes = [P, C.POINTER(_Opts), C.POINTER(C.c_size_t)]
     lib.cf_solve.argtypes = [P, C.POINTER(_Opts), C.c_void_p, C.c_size_t, C.POINTER(_Result)]
     lib.cf_kernel_table.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_double)]
+    lib.cf_batch_workspace_size.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(_Opts),
+                                            C.POINTER(C.c_size_t)]
+    lib.cf_batch_solve.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(_Opts), C.c_void_p, C.c_size_t,
+                                   C.POINTER(_Result)]
     for name in EXPORTS:
         getattr(lib, name).restype = C.c_int if name != "cf_last_error" else C.c_char_p
     _lib = lib
@@ -284,6 +289,50 @@ class Problem:
             out["gamma"] = gam.reshape(T, C_run)
             out["trace"] = tr
         return out
+
+
+def batch_solve(problems: Sequence["Problem"], workspace=None, **opts):
+    """Solve several problems with the same options in one batched launch
+    sequence (see cf_batch_solve).  Returns one result dict per problem."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("cf batch solve needs a ROCm GPU")
+    lib = load()
+    opts = dict(opts)
+    opts.pop("keep_gamma", None)
+    opts.pop("channel_subset", None)
+    stream = torch.cuda.current_stream()
+    o = problems[0]._opts(stream=C.c_void_p(stream.cuda_stream), **opts)
+    n = len(problems)
+    hs = (C.c_void_p * n)(*[p._h.value for p in problems])
+    nbytes = C.c_size_t()
+    _check(lib.cf_batch_workspace_size(hs, n, C.byref(o), C.byref(nbytes)))
+    if workspace is None:
+        workspace = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+    if workspace.numel() < nbytes.value:
+        raise ValueError("workspace too small")
+    results = (_Result * n)()
+    keep = []
+    for k, p in enumerate(problems):
+        inf = p.info(**opts)
+        ph = np.zeros(max(1, inf["per_harmonic_len"]))
+        pf = np.zeros(6)
+        pc = np.zeros(inf["n_channels"])
+        keep.append((ph, pf, pc, inf))
+        r = results[k]
+        r.per_harmonic, r.per_harmonic_len = _dptr(ph), len(ph)
+        r.per_face, r.per_face_len = _dptr(pf), 6
+        r.per_channel, r.per_channel_len = _dptr(pc), len(pc)
+    _check(lib.cf_batch_solve(hs, n, C.byref(o), C.c_void_p(workspace.data_ptr()), nbytes.value, results))
+    out = []
+    for k in range(n):
+        r = results[k]
+        ph, pf, pc, inf = keep[k]
+        out.append(dict(force=r.force, per_harmonic=ph[:inf["per_harmonic_len"]], per_face=pf,
+                        per_channel=pc, n_channels=r.n_channels_run, cell_updates=r.cell_updates,
+                        device_ms=r.device_ms, fused=bool(r.fused), tile_variant=r.tile_variant,
+                        tile_halo=r.tile_halo))
+    return out
 
 
 def solve_workload(wl, **over) -> dict:

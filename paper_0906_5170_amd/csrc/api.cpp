@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <fstream>
 #include <map>
 #include <memory>
@@ -45,7 +46,8 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Device workspace layout of one solve.
 struct Layout {
     size_t ids, lut, ktab, pml, chans, slots, gidx, gw, uidx, uoff, usamp, uw, basis, acc, gamma,
-        fields, fields2, psi, total;
+        fields, fields2, psi, inst, work, total;
+    size_t work_items;    // capacity of one work list
 };
 
 // Tiling of the fused kernel: shifted so that every measured surface stencil
@@ -143,6 +145,8 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         d.src_off = d.field_off + (int64_t)cf::comp_slot(ch.pol, ch.src) * p.ncell;
         d.meas_off = d.field_off + (int64_t)cf::comp_slot(ch.pol, ch.meas) * p.ncell;
         d.kind = ch.kind;
+        d.inst = 0;
+        d.pol = ch.pol;
         d.nsamp = p.gathers[gm].nsamp;
         d.P = p.gathers[gm].P;
         d.g_off = g_goff[gm];
@@ -266,6 +270,30 @@ TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, c
     return t;
 }
 
+// Work list of a fused launch: channel `slots[k]` contributes ntiles[k]
+// tiles.  Each channel is assigned whole to the XCD queue with the fewest
+// tiles so far; block b = 8 i + x takes item i of queue x, so every tile of
+// a channel runs on XCD x (blocks are dispatched to XCDs round-robin).
+std::vector<cf::WorkItem> make_work(const std::vector<int>& slots, const std::vector<int>& ntiles) {
+    std::vector<std::vector<cf::WorkItem>> q(8);
+    std::vector<long> load(8, 0);
+    for (size_t k = 0; k < slots.size(); ++k) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        for (int t = 0; t < ntiles[k]; ++t) q[x].push_back({slots[k], t});
+        load[x] += ntiles[k];
+    }
+    size_t len = 0;
+    for (auto& v : q) len = std::max(len, v.size());
+    std::vector<cf::WorkItem> out(8 * len, cf::WorkItem{-1, 0});
+    for (int x = 0; x < 8; ++x)
+        for (size_t i = 0; i < q[x].size(); ++i) out[8 * i + x] = q[x][i];
+    return out;
+}
+
+size_t work_capacity(int resident, int max_tiles) {
+    return (size_t)8 * ((size_t)resident * max_tiles / 8 + max_tiles + 1);
+}
+
 Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     Layout L{};
     size_t off = 0;
@@ -295,6 +323,12 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.fields = take(block);
     L.fields2 = st.variant >= 0 ? take(block) : off;
     L.psi = st.psi_comp > 0 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
+    int max_tiles = 0;
+    for (const TBPlan& pl : st.plans)
+        if (pl.ok) max_tiles = std::max(max_tiles, pl.ntx * pl.nty);
+    L.work_items = max_tiles ? work_capacity(st.resident, max_tiles) : 0;
+    L.inst = take(sizeof(cf::InstDev));
+    L.work = take(2 * L.work_items * sizeof(cf::WorkItem) + 8);
     L.total = off;
     return L;
 }
@@ -424,26 +458,47 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
         const int per_wave = st.variant >= 0 ? 2 * ((o.n_steps + kh - 1) / kh) : o.n_steps;
         smp.stride = std::max(1, per_wave * (int)st.waves.size() / 200);
     }
-    auto make_tg = [&](const TBPlan& pl) {
-        cf::TBGrid tg{};
-        tg.nx = p.nx;
-        tg.ny = p.ny;
-        tg.ncell = p.ncell;
-        tg.perx = g.perx;
-        tg.pery = g.pery;
-        for (int c = 0; c < cf::kNumComp; ++c) tg.ids[c] = g.ids[c];
-        tg.base_x = pl.base_x;
-        tg.base_y = pl.base_y;
-        tg.ntx = pl.ntx;
-        tg.nty = pl.nty;
-        tg.stile = pl.stile;
-        tg.dt = dt;
-        tg.dA = dA;
-        tg.ktab = dk;
-        tg.acc = dacc;
-        tg.gamma = dgam;
-        tg.gamma_stride = (int)C;
-        return tg;
+    auto make_inst = [&](const TBPlan& pl, bool with_gamma) {
+        cf::InstDev I{};
+        I.nx = p.nx;
+        I.ny = p.ny;
+        I.ncell = p.ncell;
+        I.perx = g.perx;
+        I.pery = g.pery;
+        for (int c = 0; c < cf::kNumComp; ++c) I.ids[c] = g.ids[c];
+        I.lut = dlut;
+        I.base_x = pl.base_x;
+        I.base_y = pl.base_y;
+        I.ntx = pl.ntx;
+        I.nty = pl.nty;
+        I.stile = pl.stile;
+        I.start = 0;
+        I.nsteps = o.n_steps;
+        I.dt = dt;
+        I.dA = dA;
+        I.ktab = dk;
+        I.gamma = with_gamma ? dgam : nullptr;
+        I.gamma_stride = (int64_t)C;
+        return I;
+    };
+    cf::InstDev* dinst = reinterpret_cast<cf::InstDev*>(ws + L.inst);
+    cf::WorkItem* dwork = reinterpret_cast<cf::WorkItem*>(ws + L.work);
+    // sources of asynchronous uploads: kept (at stable addresses) until the
+    // stream has drained
+    std::deque<std::vector<cf::WorkItem>> host_work;
+    std::deque<cf::InstDev> host_inst;
+    // work list of one wave's channels of one polarization for plan pl
+    auto upload_work = [&](const int* list, int n, const TBPlan& pl, size_t slot_off, int* nwork) -> hipError_t {
+        std::vector<int> sl(list, list + n), nt(n, pl.ntx * pl.nty);
+        host_work.push_back(make_work(sl, nt));
+        *nwork = (int)host_work.back().size();
+        if ((size_t)*nwork > L.work_items) return hipErrorInvalidValue;
+        return hipMemcpyAsync(dwork + slot_off, host_work.back().data(), *nwork * sizeof(cf::WorkItem),
+                              hipMemcpyHostToDevice, s);
+    };
+    auto upload_inst = [&](const cf::InstDev& I) -> hipError_t {
+        host_inst.push_back(I);
+        return hipMemcpyAsync(dinst, &host_inst.back(), sizeof(cf::InstDev), hipMemcpyHostToDevice, s);
     };
     int variant = st.variant;
     hipError_t err = hipSuccess;
@@ -458,7 +513,6 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
         const Wave& w = st.waves[0];
         const bool tm = w.n_tm >= w.n_te;
         const int n = tm ? w.n_tm : w.n_te;
-        const int* sl = dslots + (tm ? w.tm_off : w.te_off);
         const std::string key = tune_key(p, o, w.n_tm, w.n_te);
         int cached;
         if (tune_lookup(key, &cached) && cached >= 0 && cached < (int)st.plans.size() && st.plans[cached].ok) {
@@ -470,17 +524,17 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             STEP_OK(hipEventCreate(&t1));
             for (int v = 0; v < (int)st.plans.size(); ++v) {
                 if (!st.plans[v].ok) continue;
-                cf::TBGrid tg = make_tg(st.plans[v]);
-                tg.nslots = n;
-                tg.gamma = nullptr;
                 const int kh = st.shapes[v].kh;
+                int nw = 0;
+                STEP_OK(upload_inst(make_inst(st.plans[v], false)));
+                STEP_OK(upload_work(st.slot_lists.data() + (tm ? w.tm_off : w.te_off), n, st.plans[v], 0, &nw));
                 T* A = fields;
                 T* B = reinterpret_cast<T*>(ws + L.fields2);
-                STEP_OK(cf::launch_tb2d<T>(v, tm ? CF_POL_TM : CF_POL_TE, A, B, dch, sl, tg, tabs, dlut, kh, 0, s));
+                const int pol = tm ? CF_POL_TM : CF_POL_TE;
+                STEP_OK(cf::launch_tb2d<T>(v, pol, A, B, dch, dwork, nw, dinst, tabs, dacc, kh, 0, s));
                 STEP_OK(hipEventRecord(t0, s));
                 for (int r = 0; r < 3; ++r) {
-                    STEP_OK(cf::launch_tb2d<T>(v, tm ? CF_POL_TM : CF_POL_TE, A, B, dch, sl, tg, tabs, dlut, kh,
-                                               0, s));
+                    STEP_OK(cf::launch_tb2d<T>(v, pol, A, B, dch, dwork, nw, dinst, tabs, dacc, kh, 0, s));
                     std::swap(A, B);
                 }
                 STEP_OK(hipEventRecord(t1, s));
@@ -549,8 +603,12 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             STEP_OK(cf::launch_e2d<T>(CF_POL_TE, 1, fields, dch, s_te, w.n_te, g, dlut, s));
         }
         if (variant >= 0) {
-            cf::TBGrid tg = make_tg(st.plans[variant]);
+            const TBPlan& pl = st.plans[variant];
             const int kh = st.shapes[variant].kh;
+            int nw_tm = 0, nw_te = 0;
+            STEP_OK(upload_inst(make_inst(pl, true)));
+            STEP_OK(upload_work(st.slot_lists.data() + w.tm_off, w.n_tm, pl, 0, &nw_tm));
+            STEP_OK(upload_work(st.slot_lists.data() + w.te_off, w.n_te, pl, L.work_items, &nw_te));
             T* A = fields;
             T* B = reinterpret_cast<T*>(ws + L.fields2);
             for (int m = 0; m < o.n_steps; m += kh) {
@@ -558,10 +616,10 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
                 for (int pol : {CF_POL_TM, CF_POL_TE}) {
                     const int n = pol == CF_POL_TM ? w.n_tm : w.n_te;
                     if (n == 0) continue;
-                    tg.nslots = n;
                     const bool take = smp.begin(s);
-                    STEP_OK(cf::launch_tb2d<T>(variant, pol, A, B, dch, pol == CF_POL_TM ? s_tm : s_te, tg,
-                                               tabs, dlut, ks, m, s));
+                    STEP_OK(cf::launch_tb2d<T>(variant, pol, A, B, dch,
+                                               pol == CF_POL_TM ? dwork : dwork + L.work_items,
+                                               pol == CF_POL_TM ? nw_tm : nw_te, dinst, tabs, dacc, kh, m, s));
                     const double cu = (double)n * p.ncell * ks;
                     smp.end(take, s, cu, cu * state_bytes);
                 }
@@ -621,6 +679,417 @@ done:
     for (auto& e : smp.ev) (void)hipEventDestroy(e);
     if (err != hipSuccess)
         return fail(CF_E_DEVICE, std::string("device step failed: ") + hipGetErrorString(err));
+    return CF_OK;
+}
+
+// Host reduction (FP64, channel order): F = (1/pi) sum_c sign_c acc_c and
+// the per-harmonic / per-face / per-channel / trace outputs.  Returns false
+// when an accumulator is not finite.
+bool fill_result(const cf::Problem& p, const std::vector<cf::Channel>& chans, const std::vector<double>& acc,
+                 const std::vector<double>& gam, const cf_opts& o, double ms, const StencilTiming& tim,
+                 const Staged& sg, cf_result* out) {
+    const size_t C = chans.size();
+    std::vector<double> a(C);
+    bool finite = true;
+    for (size_t c = 0; c < C; ++c) {
+        a[c] = acc[2 * c] + acc[2 * c + 1];
+        finite = finite && std::isfinite(a[c]);
+    }
+    double F = 0;
+    for (size_t c = 0; c < C; ++c) F += chans[c].sign * a[c];
+    out->force = F / M_PI;
+    if (out->per_harmonic) {
+        std::fill(out->per_harmonic, out->per_harmonic + out->per_harmonic_len, 0.0);
+        for (size_t c = 0; c < C; ++c) out->per_harmonic[chans[c].label] += chans[c].sign * a[c] / M_PI;
+    }
+    if (out->per_face) {
+        std::fill(out->per_face, out->per_face + out->per_face_len, 0.0);
+        for (size_t c = 0; c < C; ++c)
+            out->per_face[p.faces[chans[c].face].index] += chans[c].sign * a[c] / M_PI;
+    }
+    if (out->per_channel)
+        for (size_t c = 0; c < C; ++c) out->per_channel[c] = a[c];
+    if (out->gamma && !gam.empty()) std::copy(gam.begin(), gam.end(), out->gamma);
+    if (out->trace && !gam.empty()) {
+        std::vector<double> ktab(o.n_steps);
+        const double dt = o.courant / p.grid.res;
+        cf::kernel_table(o.kernel, o.sigma, dt, o.n_steps, ktab.data());
+        double run = 0;
+        for (int m = 0; m < o.n_steps; ++m) {
+            double s = 0;
+            for (size_t c = 0; c < C; ++c) s += chans[c].sign * gam[(size_t)m * C + c];
+            run += dt * ktab[m] * s / M_PI;
+            out->trace[m] = run;
+        }
+    }
+    out->n_channels_run = (int)C;
+    out->cell_updates = (double)C * (double)p.ncell * (double)o.n_steps;
+    out->device_ms = ms;
+    out->stencil_samples = tim.samples;
+    out->stencil_launches = tim.launches;
+    out->stencil_ms_avg = tim.samples ? tim.ms_total / tim.samples : 0.0;
+    out->stencil_alg_bytes = tim.samples ? tim.bytes_total / tim.samples : 0.0;
+    out->stencil_cell_updates = tim.samples ? tim.cu_total / tim.samples : 0.0;
+    out->fused = tim.variant >= 0 ? 1 : 0;
+    out->tile_variant = tim.variant + 1;
+    out->tile_halo = tim.variant >= 0 && tim.variant < (int)sg.shapes.size() ? sg.shapes[tim.variant].kh : 0;
+    return finite;
+}
+
+// ---------------------------------------------------------------------------
+// Batched solve: several 2D problems advanced by one fused launch sequence.
+
+struct BatchPlan {
+    std::vector<const cf::Problem*> probs;
+    std::vector<std::vector<cf::Channel>> chans;
+    std::vector<Staged> st;
+    std::vector<int> base;                 // first global channel slot per instance
+    std::vector<cf::ChanDev> dev;          // all channels, global slots
+    std::vector<int32_t> gidx, uidx, uoff, usamp;
+    std::vector<double> gw, uw, basis;
+    std::vector<int> all, tm, te;          // global slot lists
+    std::vector<int> inst_tm_off, inst_tm_n, inst_te_off, inst_te_n;   // per instance, into `lists`
+    std::vector<int> lists;                // all | tm | te | per-instance tm | per-instance te
+    std::vector<size_t> ids_off, lut_off, ktab_off, field_off;
+    size_t ids_bytes = 0, lut_bytes = 0, ktab_bytes = 0, field_elems = 0, work_items = 0;
+    std::vector<int> variants_ok;          // variants every instance can use
+    int max_uniq = 0;
+    int C = 0;
+};
+
+std::string plan_batch(cf_problem* const* probs, int n, const cf_opts& o, BatchPlan& B) {
+    cf_opts oo = o;
+    oo.n_subset = 0;
+    oo.channel_subset = nullptr;
+    oo.max_resident = 0;
+    oo.path = CF_PATH_BATCHED;
+    oo.flags &= ~CF_FLAG_KEEP_GAMMA;
+    const size_t fsz = o.precision == CF_FP64 ? 8 : 4;
+    int nvar = -1;
+    for (int i = 0; i < n; ++i) {
+        const cf::Problem& p = probs[i]->p;
+        B.probs.push_back(&p);
+        B.chans.push_back(cf::channel_table(p, o.pol));
+        B.st.emplace_back();
+        stage(p, oo, B.chans.back(), B.st.back());
+        const Staged& st = B.st.back();
+        if (nvar < 0) nvar = (int)st.plans.size();
+        if ((int)st.plans.size() != nvar) nvar = 0;
+    }
+    for (int v = 0; v < nvar; ++v) {
+        bool ok = true;
+        for (auto& st : B.st) ok = ok && st.plans[v].ok;
+        if (ok) B.variants_ok.push_back(v);
+    }
+    if (B.variants_ok.empty()) return "no fused tile shape fits every problem";
+    for (int i = 0; i < n; ++i) {
+        const cf::Problem& p = *B.probs[i];
+        const Staged& st = B.st[i];
+        const int Ci = (int)B.chans[i].size();
+        B.base.push_back(B.C);
+        B.ids_off.push_back(B.ids_bytes);
+        B.ids_bytes = align_up(B.ids_bytes + (size_t)cf::kNumComp * p.ncell, 256);
+        B.lut_off.push_back(B.lut_bytes);
+        B.lut_bytes = align_up(B.lut_bytes + 2 * cf::kNumComp * 256 * 2 * fsz, 256);
+        B.ktab_off.push_back(B.ktab_bytes);
+        B.ktab_bytes = align_up(B.ktab_bytes + (size_t)o.n_steps * 8, 256);
+        B.field_off.push_back(B.field_elems);
+        const int G = (int)B.gidx.size(), U = (int)B.uidx.size(), S = (int)B.usamp.size(),
+                  Bo = (int)B.basis.size();
+        B.gidx.insert(B.gidx.end(), st.gidx.begin(), st.gidx.end());
+        B.gw.insert(B.gw.end(), st.gw.begin(), st.gw.end());
+        B.uidx.insert(B.uidx.end(), st.uidx.begin(), st.uidx.end());
+        for (int32_t v : st.uoff) B.uoff.push_back(v + S);
+        B.usamp.insert(B.usamp.end(), st.usamp.begin(), st.usamp.end());
+        B.uw.insert(B.uw.end(), st.uw.begin(), st.uw.end());
+        B.basis.insert(B.basis.end(), st.basis.begin(), st.basis.end());
+        for (int c = 0; c < Ci; ++c) {
+            cf::ChanDev d = st.dev[c];
+            d.field_off += (int64_t)B.field_elems;
+            d.src_off += (int64_t)B.field_elems;
+            d.meas_off += (int64_t)B.field_elems;
+            d.g_off += G;
+            d.u_off += U;
+            d.basis_off += Bo;
+            d.inst = i;
+            B.dev.push_back(d);
+            const int slot = B.C + c;
+            B.all.push_back(slot);
+            (B.chans[i][c].pol == CF_POL_TM ? B.tm : B.te).push_back(slot);
+        }
+        B.max_uniq = std::max(B.max_uniq, st.max_uniq);
+        B.field_elems += (size_t)Ci * st.ncomp * p.ncell;
+        B.C += Ci;
+    }
+    B.lists = B.all;
+    B.lists.insert(B.lists.end(), B.tm.begin(), B.tm.end());
+    B.lists.insert(B.lists.end(), B.te.begin(), B.te.end());
+    for (int i = 0; i < n; ++i) {
+        const int Ci = (int)B.chans[i].size();
+        B.inst_tm_off.push_back((int)B.lists.size());
+        for (int c = 0; c < Ci; ++c)
+            if (B.chans[i][c].pol == CF_POL_TM) B.lists.push_back(B.base[i] + c);
+        B.inst_tm_n.push_back((int)B.lists.size() - B.inst_tm_off.back());
+        B.inst_te_off.push_back((int)B.lists.size());
+        for (int c = 0; c < Ci; ++c)
+            if (B.chans[i][c].pol == CF_POL_TE) B.lists.push_back(B.base[i] + c);
+        B.inst_te_n.push_back((int)B.lists.size() - B.inst_te_off.back());
+    }
+    // work-list capacity for the largest variant
+    size_t cap = 0;
+    for (int v : B.variants_ok) {
+        long tiles = 0;
+        int tmax = 0;
+        for (int i = 0; i < n; ++i) {
+            const int t = B.st[i].plans[v].ntx * B.st[i].plans[v].nty;
+            tiles += (long)t * (long)B.chans[i].size();
+            tmax = std::max(tmax, t);
+        }
+        cap = std::max(cap, (size_t)(8 * (tiles / 8 + 2 * tmax + 1)));
+    }
+    B.work_items = cap;
+    return "";
+}
+
+struct BatchLayout {
+    size_t ids, lut, ktab, chans, lists, gidx, gw, uidx, uoff, usamp, uw, basis, acc, inst, work, fA, fB,
+        total;
+};
+
+BatchLayout batch_layout(const BatchPlan& B, const cf_opts& o) {
+    BatchLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    const size_t fsz = o.precision == CF_FP64 ? 8 : 4;
+    L.ids = take(B.ids_bytes);
+    L.lut = take(B.lut_bytes);
+    L.ktab = take(B.ktab_bytes);
+    L.chans = take(B.dev.size() * sizeof(cf::ChanDev));
+    L.lists = take(B.lists.size() * sizeof(int) + 4);
+    L.gidx = take(B.gidx.size() * 4 + 4);
+    L.gw = take(B.gw.size() * 8 + 8);
+    L.uidx = take(B.uidx.size() * 4 + 4);
+    L.uoff = take(B.uoff.size() * 4 + 4);
+    L.usamp = take(B.usamp.size() * 4 + 4);
+    L.uw = take(B.uw.size() * 8 + 8);
+    L.basis = take(B.basis.size() * 8 + 8);
+    L.acc = take((size_t)B.C * 2 * 8);
+    L.inst = take(B.probs.size() * sizeof(cf::InstDev));
+    L.work = take(2 * B.work_items * sizeof(cf::WorkItem) + 8);
+    L.fA = take(B.field_elems * fsz);
+    L.fB = take(B.field_elems * fsz);
+    L.total = off;
+    return L;
+}
+
+template <typename T>
+cf_status run_batch(const BatchPlan& B, const BatchLayout& L, const cf_opts& o, char* ws, hipStream_t s,
+                    std::vector<double>& acc_out, double* device_ms, StencilTiming* timing) {
+    const int n = (int)B.probs.size();
+    std::deque<std::vector<uint8_t>> keep8;
+    std::deque<std::vector<T>> keepT;
+    std::deque<std::vector<double>> keepD;
+    std::deque<std::vector<cf::WorkItem>> keepW;
+    std::deque<std::vector<cf::InstDev>> keepI;
+    auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    for (int i = 0; i < n; ++i) {
+        const cf::Problem& p = *B.probs[i];
+        keep8.emplace_back((size_t)cf::kNumComp * p.ncell);
+        for (int c = 0; c < cf::kNumComp; ++c)
+            std::memcpy(keep8.back().data() + (size_t)c * p.ncell, p.ids[c].data(), p.ncell);
+        CF_HIP(up(L.ids + B.ids_off[i], keep8.back().data(), keep8.back().size()));
+        std::vector<double> l64 = cf::coefficient_lut(p, o.sigma, o.courant);
+        keepT.emplace_back(l64.begin(), l64.end());
+        CF_HIP(up(L.lut + B.lut_off[i], keepT.back().data(), keepT.back().size() * sizeof(T)));
+        keepD.emplace_back(o.n_steps);
+        cf::kernel_table(o.kernel, o.sigma, o.courant / p.grid.res, o.n_steps, keepD.back().data());
+        CF_HIP(up(L.ktab + B.ktab_off[i], keepD.back().data(), (size_t)o.n_steps * 8));
+    }
+    CF_HIP(up(L.chans, B.dev.data(), B.dev.size() * sizeof(cf::ChanDev)));
+    CF_HIP(up(L.lists, B.lists.data(), B.lists.size() * sizeof(int)));
+    CF_HIP(up(L.gidx, B.gidx.data(), B.gidx.size() * 4));
+    CF_HIP(up(L.gw, B.gw.data(), B.gw.size() * 8));
+    CF_HIP(up(L.uidx, B.uidx.data(), B.uidx.size() * 4));
+    CF_HIP(up(L.uoff, B.uoff.data(), B.uoff.size() * 4));
+    CF_HIP(up(L.usamp, B.usamp.data(), B.usamp.size() * 4));
+    CF_HIP(up(L.uw, B.uw.data(), B.uw.size() * 8));
+    CF_HIP(up(L.basis, B.basis.data(), B.basis.size() * 8));
+
+    const cf::ChanDev* dch = reinterpret_cast<const cf::ChanDev*>(ws + L.chans);
+    const int* dl = reinterpret_cast<const int*>(ws + L.lists);
+    double* dacc = reinterpret_cast<double*>(ws + L.acc);
+    cf::InstDev* dinst = reinterpret_cast<cf::InstDev*>(ws + L.inst);
+    cf::WorkItem* dwork = reinterpret_cast<cf::WorkItem*>(ws + L.work);
+    T* A = reinterpret_cast<T*>(ws + L.fA);
+    T* Bf = reinterpret_cast<T*>(ws + L.fB);
+    cf::SurfTables tabs;
+    tabs.gidx = reinterpret_cast<const int32_t*>(ws + L.gidx);
+    tabs.gw = reinterpret_cast<const double*>(ws + L.gw);
+    tabs.uidx = reinterpret_cast<const int32_t*>(ws + L.uidx);
+    tabs.uoff = reinterpret_cast<const int32_t*>(ws + L.uoff);
+    tabs.usamp = reinterpret_cast<const int32_t*>(ws + L.usamp);
+    tabs.uw = reinterpret_cast<const double*>(ws + L.uw);
+    tabs.basis = reinterpret_cast<const double*>(ws + L.basis);
+    auto grid_of = [&](int i) {
+        const cf::Problem& p = *B.probs[i];
+        cf::Grid2D g{};
+        g.nx = p.nx;
+        g.ny = p.ny;
+        g.ncell = p.ncell;
+        g.perx = p.grid.bc[0] == CF_BC_PERIODIC;
+        g.pery = p.grid.bc[1] == CF_BC_PERIODIC;
+        for (int c = 0; c < cf::kNumComp; ++c)
+            g.ids[c] = reinterpret_cast<const uint8_t*>(ws + L.ids + B.ids_off[i]) + (size_t)c * p.ncell;
+        return g;
+    };
+    auto insts_for = [&](int v) {
+        std::vector<cf::InstDev> I(n);
+        for (int i = 0; i < n; ++i) {
+            const cf::Problem& p = *B.probs[i];
+            const TBPlan& pl = B.st[i].plans[v];
+            const cf::Grid2D g = grid_of(i);
+            cf::InstDev& d = I[i];
+            d.nx = p.nx;
+            d.ny = p.ny;
+            d.ncell = p.ncell;
+            d.perx = g.perx;
+            d.pery = g.pery;
+            for (int c = 0; c < cf::kNumComp; ++c) d.ids[c] = g.ids[c];
+            d.lut = ws + L.lut + B.lut_off[i];
+            d.base_x = pl.base_x;
+            d.base_y = pl.base_y;
+            d.ntx = pl.ntx;
+            d.nty = pl.nty;
+            d.stile = pl.stile;
+            d.start = 0;
+            d.nsteps = o.n_steps;
+            d.dt = o.courant / p.grid.res;
+            d.dA = std::pow(1.0 / p.grid.res, p.grid.ndim - 1);
+            d.ktab = reinterpret_cast<const double*>(ws + L.ktab + B.ktab_off[i]);
+            d.gamma = nullptr;
+            d.gamma_stride = B.C;
+        }
+        return I;
+    };
+    auto work_for = [&](int v, const std::vector<int>& slots) {
+        std::vector<int> nt;
+        for (int sl : slots) {
+            const int i = B.dev[sl].inst;
+            nt.push_back(B.st[i].plans[v].ntx * B.st[i].plans[v].nty);
+        }
+        return make_work(slots, nt);
+    };
+    const int n_tm = (int)B.tm.size(), n_te = (int)B.te.size();
+    hipError_t err = hipSuccess;
+    hipEvent_t e0, e1;
+    CF_HIP(hipEventCreate(&e0));
+    CF_HIP(hipEventCreate(&e1));
+    int variant = B.variants_ok[0];
+    const size_t fbytes = B.field_elems * sizeof(T);
+#define BSTEP(expr)                        \
+    do {                                   \
+        err = (expr);                      \
+        if (err != hipSuccess) goto bdone; \
+    } while (0)
+    if (o.tile_variant >= 1) {
+        variant = -1;
+        for (int v : B.variants_ok)
+            if (v == o.tile_variant - 1) variant = v;
+        if (variant < 0) variant = B.variants_ok[0];
+    } else if (B.variants_ok.size() > 1) {
+        std::ostringstream k;
+        k << "batch fp" << (sizeof(T) == 8 ? 64 : 32) << " n" << n << " ch" << B.C << " cells" << B.field_elems;
+        int cached;
+        if (tune_lookup(k.str(), &cached) &&
+            std::find(B.variants_ok.begin(), B.variants_ok.end(), cached) != B.variants_ok.end()) {
+            variant = cached;
+        } else {
+            double best = 1e300;
+            for (int v : B.variants_ok) {
+                keepI.push_back(insts_for(v));
+                BSTEP(up(L.inst, keepI.back().data(), n * sizeof(cf::InstDev)));
+                const std::vector<int>& sl = n_tm >= n_te ? B.tm : B.te;
+                keepW.push_back(work_for(v, sl));
+                BSTEP(up(L.work, keepW.back().data(), keepW.back().size() * sizeof(cf::WorkItem)));
+                const int kh = B.st[0].shapes[v].kh, nw = (int)keepW.back().size();
+                const int pol = n_tm >= n_te ? CF_POL_TM : CF_POL_TE;
+                BSTEP(cf::launch_tb2d<T>(v, pol, A, Bf, dch, dwork, nw, dinst, tabs, dacc, kh, 0, s));
+                BSTEP(hipEventRecord(e0, s));
+                for (int r = 0; r < 2; ++r)
+                    BSTEP(cf::launch_tb2d<T>(v, pol, r ? Bf : A, r ? A : Bf, dch, dwork, nw, dinst, tabs, dacc,
+                                             kh, 0, s));
+                BSTEP(hipEventRecord(e1, s));
+                BSTEP(hipEventSynchronize(e1));
+                float ms = 0;
+                BSTEP(hipEventElapsedTime(&ms, e0, e1));
+                const double per = ms / (2.0 * kh);
+                if (per < best) {
+                    best = per;
+                    variant = v;
+                }
+            }
+            tune_store(k.str(), variant);
+        }
+    }
+    timing->variant = variant;
+    {
+        const int kh = B.st[0].shapes[variant].kh;
+        keepI.push_back(insts_for(variant));
+        BSTEP(up(L.inst, keepI.back().data(), n * sizeof(cf::InstDev)));
+        keepW.push_back(work_for(variant, B.tm));
+        const int nw_tm = (int)keepW.back().size();
+        BSTEP(up(L.work, keepW.back().data(), nw_tm * sizeof(cf::WorkItem)));
+        keepW.push_back(work_for(variant, B.te));
+        const int nw_te = (int)keepW.back().size();
+        BSTEP(up(L.work + B.work_items * sizeof(cf::WorkItem), keepW.back().data(), nw_te * sizeof(cf::WorkItem)));
+        BSTEP(hipMemsetAsync(dacc, 0, (size_t)B.C * 2 * 8, s));
+        BSTEP(hipMemsetAsync(A, 0, fbytes, s));
+        BSTEP(hipEventRecord(e0, s));
+        BSTEP(cf::launch_kick<T>(A, dch, dl, B.C, B.max_uniq, tabs, s));
+        for (int i = 0; i < n; ++i) {
+            const cf::Grid2D g = grid_of(i);
+            const T* lut = reinterpret_cast<const T*>(ws + L.lut + B.lut_off[i]);
+            const int* tm = dl + B.inst_tm_off[i];
+            const int* te = dl + B.inst_te_off[i];
+            BSTEP(cf::launch_h2d<T>(CF_POL_TM, 1, A, dch, tm, B.inst_tm_n[i], g, lut, s));
+            BSTEP(cf::launch_h2d<T>(CF_POL_TE, 1, A, dch, te, B.inst_te_n[i], g, lut, s));
+            BSTEP(cf::launch_e2d<T>(CF_POL_TM, 1, A, dch, tm, B.inst_tm_n[i], g, lut, s));
+            BSTEP(cf::launch_e2d<T>(CF_POL_TE, 1, A, dch, te, B.inst_te_n[i], g, lut, s));
+        }
+        T* X = A;
+        T* Y = Bf;
+        int launches = 0;
+        for (int m = 0; m < o.n_steps; m += kh) {
+            if (n_tm) BSTEP(cf::launch_tb2d<T>(variant, CF_POL_TM, X, Y, dch, dwork, nw_tm, dinst, tabs, dacc, kh, m, s));
+            if (n_te)
+                BSTEP(cf::launch_tb2d<T>(variant, CF_POL_TE, X, Y, dch, dwork + B.work_items, nw_te, dinst, tabs,
+                                         dacc, kh, m, s));
+            launches += (n_tm > 0) + (n_te > 0);
+            std::swap(X, Y);
+        }
+        timing->launches = launches;
+        BSTEP(hipEventRecord(e1, s));
+        BSTEP(hipEventSynchronize(e1));
+        float ms = 0;
+        BSTEP(hipEventElapsedTime(&ms, e0, e1));
+        *device_ms = ms;
+    }
+    acc_out.assign((size_t)B.C * 2, 0.0);
+    BSTEP(hipMemcpy(acc_out.data(), dacc, (size_t)B.C * 2 * 8, hipMemcpyDeviceToHost));
+bdone:
+#undef BSTEP
+    if (err != hipSuccess) (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess)
+        return fail(CF_E_DEVICE, std::string("batched device step failed: ") + hipGetErrorString(err));
     return CF_OK;
 }
 
@@ -760,52 +1229,93 @@ cf_status cf_solve(cf_problem* h, const cf_opts* o, void* workspace, size_t ws_b
                                            : run_solve<float>(p, *o, sg, L, ws, s, acc, gam, &ms, &tim);
     if (owned) hipFree(owned);
     if (rs != CF_OK) return rs;
-    // ---- reduction (host, FP64, channel order) -------------------------
-    std::vector<double> a(C);
-    bool finite = true;
-    for (size_t c = 0; c < C; ++c) {
-        a[c] = acc[2 * c] + acc[2 * c + 1];
-        finite = finite && std::isfinite(a[c]);
+    const bool finite = fill_result(p, chans, acc, gam, *o, ms, tim, sg, out);
+    if (!finite) return fail(CF_E_NONFINITE, "a force accumulator is not finite");
+    g_err.clear();
+    return CF_OK;
+}
+
+
+cf_status cf_batch_workspace_size(cf_problem* const* probs, int n, const cf_opts* o, size_t* bytes) {
+    if (!probs || n < 1 || !o || !bytes) return fail(CF_E_ARG, "bad batch arguments");
+    size_t solo = 0;
+    std::vector<cf_problem*> fused;
+    for (int i = 0; i < n; ++i) {
+        cf_status st = cf_validate(probs[i], o);
+        if (st != CF_OK) return st;
+        if (probs[i]->p.grid.ndim == 2) fused.push_back(probs[i]);
+        size_t b = 0;
+        cf_opts oo = *o;
+        oo.n_subset = 0;
+        oo.channel_subset = nullptr;
+        st = cf_workspace_size(probs[i], &oo, &b);
+        if (st != CF_OK) return st;
+        solo = std::max(solo, b);
     }
-    double F = 0;
-    for (size_t c = 0; c < C; ++c) F += chans[c].sign * a[c];
-    out->force = F / M_PI;
-    if (out->per_harmonic) {
-        std::fill(out->per_harmonic, out->per_harmonic + out->per_harmonic_len, 0.0);
-        for (size_t c = 0; c < C; ++c) out->per_harmonic[chans[c].label] += chans[c].sign * a[c] / M_PI;
+    size_t fb = 0;
+    if (!fused.empty()) {
+        BatchPlan B;
+        if (plan_batch(fused.data(), (int)fused.size(), *o, B).empty()) fb = batch_layout(B, *o).total;
     }
-    if (out->per_face) {
-        std::fill(out->per_face, out->per_face + out->per_face_len, 0.0);
-        for (size_t c = 0; c < C; ++c)
-            out->per_face[p.faces[chans[c].face].index] += chans[c].sign * a[c] / M_PI;
+    *bytes = std::max(solo, fb);
+    return CF_OK;
+}
+
+cf_status cf_batch_solve(cf_problem* const* probs, int n, const cf_opts* o, void* workspace, size_t ws_bytes,
+                         cf_result* outs) {
+    if (!probs || n < 1 || !o || !outs) return fail(CF_E_ARG, "bad batch arguments");
+    cf_opts oo = *o;
+    oo.n_subset = 0;
+    oo.channel_subset = nullptr;
+    oo.flags &= ~CF_FLAG_KEEP_GAMMA;
+    for (int i = 0; i < n; ++i) {
+        cf_status st = cf_validate(probs[i], &oo);
+        if (st != CF_OK) return st;
     }
-    if (out->per_channel)
-        for (size_t c = 0; c < C; ++c) out->per_channel[c] = a[c];
-    if (out->gamma) std::copy(gam.begin(), gam.end(), out->gamma);
-    if (out->trace) {
-        std::vector<double> ktab(o->n_steps);
-        const double dt = o->courant / p.grid.res;
-        cf::kernel_table(o->kernel, o->sigma, dt, o->n_steps, ktab.data());
-        double run = 0;
-        for (int m = 0; m < o->n_steps; ++m) {
-            double s = 0;
-            for (size_t c = 0; c < C; ++c) s += chans[c].sign * gam[(size_t)m * C + c];
-            run += dt * ktab[m] * s / M_PI;
-            out->trace[m] = run;
+    // 2D problems share one fused sequence when every one fits a common tile
+    std::vector<int> fused_idx;
+    if (!(o->flags & CF_FLAG_SPLIT))
+        for (int i = 0; i < n; ++i)
+            if (probs[i]->p.grid.ndim == 2) fused_idx.push_back(i);
+    BatchPlan B;
+    if (fused_idx.size() >= 1) {
+        std::vector<cf_problem*> fp;
+        for (int i : fused_idx) fp.push_back(probs[i]);
+        if (!plan_batch(fp.data(), (int)fp.size(), oo, B).empty()) fused_idx.clear();
+    }
+    std::vector<bool> done(n, false);
+    if (!fused_idx.empty()) {
+        BatchLayout L = batch_layout(B, oo);
+        char* ws = static_cast<char*>(workspace);
+        void* owned = nullptr;
+        if (!ws) {
+            CF_HIP(hipMalloc(&owned, L.total));
+            ws = static_cast<char*>(owned);
+        } else if (ws_bytes < L.total) {
+            return fail(CF_E_BUDGET, "workspace smaller than cf_batch_workspace_size()");
+        }
+        hipStream_t s = static_cast<hipStream_t>(o->stream);
+        std::vector<double> acc;
+        double ms = 0;
+        StencilTiming tim;
+        cf_status rs = o->precision == CF_FP64 ? run_batch<double>(B, L, oo, ws, s, acc, &ms, &tim)
+                                               : run_batch<float>(B, L, oo, ws, s, acc, &ms, &tim);
+        if (owned) (void)hipFree(owned);
+        if (rs != CF_OK) return rs;
+        for (size_t k = 0; k < fused_idx.size(); ++k) {
+            const int i = fused_idx[k];
+            const size_t Ci = B.chans[k].size();
+            std::vector<double> ai(acc.begin() + 2 * (size_t)B.base[k], acc.begin() + 2 * ((size_t)B.base[k] + Ci));
+            const bool finite = fill_result(*B.probs[k], B.chans[k], ai, {}, oo, ms, tim, B.st[k], &outs[i]);
+            if (!finite) return fail(CF_E_NONFINITE, "a force accumulator is not finite");
+            done[i] = true;
         }
     }
-    out->n_channels_run = (int)C;
-    out->cell_updates = (double)C * (double)p.ncell * (double)o->n_steps;
-    out->device_ms = ms;
-    out->stencil_samples = tim.samples;
-    out->stencil_launches = tim.launches;
-    out->stencil_ms_avg = tim.samples ? tim.ms_total / tim.samples : 0.0;
-    out->stencil_alg_bytes = tim.samples ? tim.bytes_total / tim.samples : 0.0;
-    out->stencil_cell_updates = tim.samples ? tim.cu_total / tim.samples : 0.0;
-    out->fused = tim.variant >= 0 ? 1 : 0;
-    out->tile_variant = tim.variant + 1;
-    out->tile_halo = tim.variant >= 0 ? sg.shapes[tim.variant].kh : 0;
-    if (!finite) return fail(CF_E_NONFINITE, "a force accumulator is not finite");
+    for (int i = 0; i < n; ++i) {
+        if (done[i]) continue;
+        cf_status st = cf_solve(probs[i], &oo, workspace, ws_bytes, &outs[i]);
+        if (st != CF_OK) return st;
+    }
     g_err.clear();
     return CF_OK;
 }

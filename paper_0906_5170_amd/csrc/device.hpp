@@ -14,6 +14,8 @@ namespace cf {
 struct ChanDev {
     int64_t field_off;   // first element of the channel's field block
     int64_t psi_off;     // first element of the channel's CPML block (3D)
+    int32_t inst;        // instance of a fused launch
+    int32_t pol;         // CF_POL_TM / CF_POL_TE / CF_POL_3D
     int64_t src_off;     // field_off + slot(src) * ncell
     int64_t meas_off;    // field_off + slot(meas) * ncell
     int32_t kind;        // 0 E-current source, 1 H-current source
@@ -39,21 +41,31 @@ struct Grid2D {
     const uint8_t* ids[6];   // per-component material ids
 };
 
-// Fused temporal-blocked launch over a set of channels (2D).
-struct TBGrid {
+// One problem instance of a fused (2D) launch.  Several instances with
+// different grids, materials and surfaces can share one launch; each has its
+// own time origin `start` on the launch clock and its own step count.
+struct InstDev {
     int nx, ny;
     int64_t ncell;
     int perx, pery;
     const uint8_t* ids[6];
+    const void* lut;       // coefficient table (field precision)
     int base_x, base_y;    // first cell of tile 0 (<= 0)
     int ntx, nty;          // tiles per axis
     int stile;             // tile (ty * ntx + tx) holding every surface stencil point
-    int nslots;            // channels listed in `slots`
+    int start;             // launch-clock step at which this instance's step 0 runs
+    int nsteps;            // time steps of this instance
+    int pad;
     double dt, dA;
-    const double* ktab;
-    double* acc;
-    double* gamma;
-    int gamma_stride;
+    const double* ktab;    // K(t_m) of this instance
+    double* gamma;         // optional Gamma rows (stride gamma_stride, column = channel slot)
+    int64_t gamma_stride;
+};
+
+// Work item of a fused launch: channel descriptor `slot`, tile `tile` of its
+// instance.  slot < 0 is padding.
+struct WorkItem {
+    int slot, tile;
 };
 
 // Tile interior (tx x ty cells) and halo / maximum steps per launch of the
@@ -122,12 +134,13 @@ template <typename T>
 hipError_t launch_e3d(int mode, T* fields, T* psi, const ChanDev* ch, const int* slots, int nslots,
                       const Grid3D& g, const T* lut, hipStream_t s);
 
-// Fused launch: `ksteps` (<= tb_shape<T>().kh) full time steps of every
-// listed channel of polarization pol, reading src and writing dst; measures
-// Gamma at steps m0 .. m0 + ksteps - 1 in the surface tile.
+// Fused launch over a work list of nwork items, all of polarization pol:
+// every item advances its channel by min(kmax, remaining steps of its
+// instance) steps starting at launch-clock step m, reading src and writing
+// dst.  acc holds the (sum, compensation) pairs of all channel slots.
 template <typename T>
-hipError_t launch_tb2d(int variant, int pol, const T* src, T* dst, const ChanDev* ch, const int* slots,
-                       const TBGrid& g, const SurfTables& t, const T* lut, int ksteps, int m0,
+hipError_t launch_tb2d(int variant, int pol, const T* src, T* dst, const ChanDev* ch, const WorkItem* work,
+                       int nwork, const InstDev* inst, const SurfTables& t, double* acc, int kmax, int m,
                        hipStream_t s);
 
 }  // namespace cf

@@ -228,9 +228,10 @@ __global__ __launch_bounds__(NT) void k_surface(const T* __restrict__ fields, co
 // after every step, forms Gamma with the shared block reduction, and
 // carries the channel's compensated accumulator through the launch.
 //
-// Block order: b % 8 selects the XCD a block is dispatched to, so
-// k = 8 * (q / ntile) + b % 8 with q = b / 8 keeps all tiles of a channel
-// on one XCD (halo re-reads hit that XCD's L2).
+// Work: block b takes item work[b] = (channel slot, tile).  The host lays
+// the list out so that b % 8, the XCD a block is dispatched to, is the same
+// for every tile of a channel (halo re-reads hit that XCD's L2).  Instances
+// (problems) of one launch have their own grids, tables and time origin.
 
 template <typename T>
 struct Pair {
@@ -260,8 +261,8 @@ __device__ __forceinline__ double from_prev(double v) {
 template <typename T, int POL, int RBW, int B, int KH, bool CREG>
 __global__ __launch_bounds__(64 * RBW) __attribute__((amdgpu_waves_per_eu(CREG ? 3 : 4)))
 void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __restrict__ ch,
-            const int* __restrict__ slots, TBGrid g, SurfTables t, const T* __restrict__ lut, int ksteps,
-            int m0) {
+            const WorkItem* __restrict__ work, const InstDev* __restrict__ insts, SurfTables t,
+            double* __restrict__ acc, int kmax, int mclock) {
     constexpr int RH = RBW * B;
     constexpr int NTB = 64 * RBW;
     constexpr int TX = 64 - 2 * KH, TY = RH - 2 * KH;
@@ -277,14 +278,15 @@ void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __res
     __shared__ T stage[RH * 64];     // measured component (surface tile only)
     __shared__ double red[RBW];
 
-    const int b = blockIdx.x;
-    const int ntile = g.ntx * g.nty;
-    const int q = b >> 3;
-    const int tile = q % ntile;
-    const int k = (q / ntile) * 8 + (b & 7);
-    if (k >= g.nslots) return;
-    const int slot = slots[k];
+    const WorkItem wi = work[blockIdx.x];
+    if (wi.slot < 0) return;
+    const int slot = wi.slot, tile = wi.tile;
     const ChanDev d = ch[slot];
+    const InstDev g = insts[d.inst];
+    const int m0 = mclock - g.start;                      // instance's own step
+    const int ksteps = min(kmax, g.nsteps - m0);
+    if (m0 < 0 || ksteps <= 0) return;                    // not started / finished
+    const T* __restrict__ lut = static_cast<const T*>(g.lut);
     const int tx = tile % g.ntx, ty = tile / g.ntx;
     const int rx0 = g.base_x + tx * TX - KH, ry0 = g.base_y + ty * TY - KH;
     const int tid = threadIdx.x;
@@ -340,8 +342,8 @@ void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __res
     const bool stile = tile == g.stile;
     double acc_s = 0.0, acc_c = 0.0;
     if (stile && tid == 0) {
-        acc_s = g.acc[2 * slot];
-        acc_c = g.acc[2 * slot + 1];
+        acc_s = acc[2 * slot];
+        acc_c = acc[2 * slot + 1];
     }
     __syncthreads();
 
@@ -433,8 +435,8 @@ void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __res
 #undef CF_K
 #undef CF_ID
     if (stile && tid == 0) {
-        g.acc[2 * slot] = acc_s;
-        g.acc[2 * slot + 1] = acc_c;
+        acc[2 * slot] = acc_s;
+        acc[2 * slot + 1] = acc_c;
     }
     T* D = dst + d.field_off;
     const int gx = rx0 + lane;
@@ -540,46 +542,47 @@ hipError_t launch_surface(const T* fields, const ChanDev* ch, const int* slots, 
 }
 
 template <typename T, int W, int B, int KH, bool CREG>
-static void rb_launch(int pol, dim3 grid, hipStream_t s, const T* src, T* dst, const ChanDev* ch,
-                      const int* slots, const TBGrid& g, const SurfTables& t, const T* lut, int ksteps, int m0) {
-    dim3 block(64 * W);
+static void rb_launch(int pol, int nwork, hipStream_t s, const T* src, T* dst, const ChanDev* ch,
+                      const WorkItem* work, const InstDev* inst, const SurfTables& t, double* acc, int kmax,
+                      int m) {
+    dim3 grid(nwork), block(64 * W);
     if (pol == CF_POL_TM)
-        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TM, W, B, KH, CREG>), grid, block, 0, s, src, dst, ch, slots, g,
-                           t, lut, ksteps, m0);
+        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TM, W, B, KH, CREG>), grid, block, 0, s, src, dst, ch, work, inst,
+                           t, acc, kmax, m);
     else
-        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TE, W, B, KH, CREG>), grid, block, 0, s, src, dst, ch, slots, g,
-                           t, lut, ksteps, m0);
+        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TE, W, B, KH, CREG>), grid, block, 0, s, src, dst, ch, work, inst,
+                           t, acc, kmax, m);
 }
 
 template <typename T>
-hipError_t launch_tb2d(int variant, int pol, const T* src, T* dst, const ChanDev* ch, const int* slots,
-                       const TBGrid& g, const SurfTables& t, const T* lut, int ksteps, int m0,
+hipError_t launch_tb2d(int variant, int pol, const T* src, T* dst, const ChanDev* ch, const WorkItem* work,
+                       int nwork, const InstDev* inst, const SurfTables& t, double* acc, int kmax, int m,
                        hipStream_t s) {
-    if (g.nslots <= 0) return hipSuccess;
+    if (nwork <= 0) return hipSuccess;
     int n;
     const RbVariant* v = rb_table<T>(&n);
     if (variant < 0 || variant >= n) return hipErrorInvalidValue;
-    if (ksteps < 1 || ksteps > v[variant].KH) return hipErrorInvalidValue;
-    const int groups = (g.nslots + 7) / 8;
-    dim3 grid(8 * groups * g.ntx * g.nty);
+    if (kmax < 1 || kmax > v[variant].KH) return hipErrorInvalidValue;
+#define CF_RB(W, B, KH, CR) rb_launch<T, W, B, KH, CR>(pol, nwork, s, src, dst, ch, work, inst, t, acc, kmax, m)
     if constexpr (sizeof(T) == 4) {
         switch (variant) {
-            case 0: rb_launch<T, 8, 8, 8, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
-            case 1: rb_launch<T, 8, 8, 6, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
-            case 2: rb_launch<T, 8, 8, 4, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
-            case 3: rb_launch<T, 16, 4, 8, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
-            case 4: rb_launch<T, 8, 8, 8, true>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
-            case 5: rb_launch<T, 16, 4, 8, true>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
-            default: rb_launch<T, 8, 8, 6, true>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
+            case 0: CF_RB(8, 8, 8, false); break;
+            case 1: CF_RB(8, 8, 6, false); break;
+            case 2: CF_RB(8, 8, 4, false); break;
+            case 3: CF_RB(16, 4, 8, false); break;
+            case 4: CF_RB(8, 8, 8, true); break;
+            case 5: CF_RB(16, 4, 8, true); break;
+            default: CF_RB(8, 8, 6, true); break;
         }
     } else {
         switch (variant) {
-            case 0: rb_launch<T, 8, 4, 4, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
-            case 1: rb_launch<T, 8, 4, 2, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
-            case 2: rb_launch<T, 16, 4, 4, false>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
-            default: rb_launch<T, 16, 4, 4, true>(pol, grid, s, src, dst, ch, slots, g, t, lut, ksteps, m0); break;
+            case 0: CF_RB(8, 4, 4, false); break;
+            case 1: CF_RB(8, 4, 2, false); break;
+            case 2: CF_RB(16, 4, 4, false); break;
+            default: CF_RB(16, 4, 4, true); break;
         }
     }
+#undef CF_RB
     return hipGetLastError();
 }
 
@@ -593,8 +596,8 @@ hipError_t launch_tb2d(int variant, int pol, const T* src, T* dst, const ChanDev
     template hipError_t launch_surface<T>(const T*, const ChanDev*, const int*, int, const SurfTables&, \
                                           const double*, int, double, double, double*, double*, int,    \
                                           hipStream_t);                                                 \
-    template hipError_t launch_tb2d<T>(int, int, const T*, T*, const ChanDev*, const int*, const TBGrid&, \
-                                       const SurfTables&, const T*, int, int, hipStream_t);
+    template hipError_t launch_tb2d<T>(int, int, const T*, T*, const ChanDev*, const WorkItem*, int,      \
+                                       const InstDev*, const SurfTables&, double*, int, int, hipStream_t);
 CF_INSTANTIATE(float)
 CF_INSTANTIATE(double)
 #undef CF_INSTANTIATE
