@@ -147,6 +147,7 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         d.kind = ch.kind;
         d.inst = 0;
         d.pol = ch.pol;
+        d.local = c;
         d.nsamp = p.gathers[gm].nsamp;
         d.P = p.gathers[gm].P;
         d.g_off = g_goff[gm];
@@ -460,6 +461,9 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     }
     auto make_inst = [&](const TBPlan& pl, bool with_gamma) {
         cf::InstDev I{};
+        I.fa = fields;
+        I.fb = ws + L.fields2;
+        I.acc = dacc;
         I.nx = p.nx;
         I.ny = p.ny;
         I.ncell = p.ncell;
@@ -479,6 +483,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
         I.ktab = dk;
         I.gamma = with_gamma ? dgam : nullptr;
         I.gamma_stride = (int64_t)C;
+        I.t = tabs;
         return I;
     };
     cf::InstDev* dinst = reinterpret_cast<cf::InstDev*>(ws + L.inst);
@@ -528,15 +533,10 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
                 int nw = 0;
                 STEP_OK(upload_inst(make_inst(st.plans[v], false)));
                 STEP_OK(upload_work(st.slot_lists.data() + (tm ? w.tm_off : w.te_off), n, st.plans[v], 0, &nw));
-                T* A = fields;
-                T* B = reinterpret_cast<T*>(ws + L.fields2);
                 const int pol = tm ? CF_POL_TM : CF_POL_TE;
-                STEP_OK(cf::launch_tb2d<T>(v, pol, A, B, dch, dwork, nw, dinst, tabs, dacc, kh, 0, s));
+                STEP_OK(cf::launch_tb2d<T>(v, pol, dch, dwork, nw, dinst, kh, 0, 0, s));
                 STEP_OK(hipEventRecord(t0, s));
-                for (int r = 0; r < 3; ++r) {
-                    STEP_OK(cf::launch_tb2d<T>(v, pol, A, B, dch, dwork, nw, dinst, tabs, dacc, kh, 0, s));
-                    std::swap(A, B);
-                }
+                for (int r = 0; r < 3; ++r) STEP_OK(cf::launch_tb2d<T>(v, pol, dch, dwork, nw, dinst, kh, 0, r & 1, s));
                 STEP_OK(hipEventRecord(t1, s));
                 STEP_OK(hipEventSynchronize(t1));
                 float ms = 0;
@@ -609,21 +609,19 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             STEP_OK(upload_inst(make_inst(pl, true)));
             STEP_OK(upload_work(st.slot_lists.data() + w.tm_off, w.n_tm, pl, 0, &nw_tm));
             STEP_OK(upload_work(st.slot_lists.data() + w.te_off, w.n_te, pl, L.work_items, &nw_te));
-            T* A = fields;
-            T* B = reinterpret_cast<T*>(ws + L.fields2);
+            int parity = 0;
             for (int m = 0; m < o.n_steps; m += kh) {
                 const int ks = std::min(kh, o.n_steps - m);
                 for (int pol : {CF_POL_TM, CF_POL_TE}) {
                     const int n = pol == CF_POL_TM ? w.n_tm : w.n_te;
                     if (n == 0) continue;
                     const bool take = smp.begin(s);
-                    STEP_OK(cf::launch_tb2d<T>(variant, pol, A, B, dch,
-                                               pol == CF_POL_TM ? dwork : dwork + L.work_items,
-                                               pol == CF_POL_TM ? nw_tm : nw_te, dinst, tabs, dacc, kh, m, s));
+                    STEP_OK(cf::launch_tb2d<T>(variant, pol, dch, pol == CF_POL_TM ? dwork : dwork + L.work_items,
+                                               pol == CF_POL_TM ? nw_tm : nw_te, dinst, kh, m, parity, s));
                     const double cu = (double)n * p.ncell * ks;
                     smp.end(take, s, cu, cu * state_bytes);
                 }
-                std::swap(A, B);
+                parity ^= 1;
             }
         } else {
             for (int m = 0; m < o.n_steps; ++m) {
@@ -808,6 +806,7 @@ std::string plan_batch(cf_problem* const* probs, int n, const cf_opts& o, BatchP
             d.field_off += (int64_t)B.field_elems;
             d.src_off += (int64_t)B.field_elems;
             d.meas_off += (int64_t)B.field_elems;
+            d.local = B.C + c;   // the batch keeps one accumulator array and one field array
             d.g_off += G;
             d.u_off += U;
             d.basis_off += Bo;
@@ -956,6 +955,9 @@ cf_status run_batch(const BatchPlan& B, const BatchLayout& L, const cf_opts& o, 
             const TBPlan& pl = B.st[i].plans[v];
             const cf::Grid2D g = grid_of(i);
             cf::InstDev& d = I[i];
+            d.fa = A;
+            d.fb = Bf;
+            d.acc = dacc;
             d.nx = p.nx;
             d.ny = p.ny;
             d.ncell = p.ncell;
@@ -975,6 +977,7 @@ cf_status run_batch(const BatchPlan& B, const BatchLayout& L, const cf_opts& o, 
             d.ktab = reinterpret_cast<const double*>(ws + L.ktab + B.ktab_off[i]);
             d.gamma = nullptr;
             d.gamma_stride = B.C;
+            d.t = tabs;
         }
         return I;
     };
@@ -1020,11 +1023,9 @@ cf_status run_batch(const BatchPlan& B, const BatchLayout& L, const cf_opts& o, 
                 BSTEP(up(L.work, keepW.back().data(), keepW.back().size() * sizeof(cf::WorkItem)));
                 const int kh = B.st[0].shapes[v].kh, nw = (int)keepW.back().size();
                 const int pol = n_tm >= n_te ? CF_POL_TM : CF_POL_TE;
-                BSTEP(cf::launch_tb2d<T>(v, pol, A, Bf, dch, dwork, nw, dinst, tabs, dacc, kh, 0, s));
+                BSTEP(cf::launch_tb2d<T>(v, pol, dch, dwork, nw, dinst, kh, 0, 0, s));
                 BSTEP(hipEventRecord(e0, s));
-                for (int r = 0; r < 2; ++r)
-                    BSTEP(cf::launch_tb2d<T>(v, pol, r ? Bf : A, r ? A : Bf, dch, dwork, nw, dinst, tabs, dacc,
-                                             kh, 0, s));
+                for (int r = 0; r < 2; ++r) BSTEP(cf::launch_tb2d<T>(v, pol, dch, dwork, nw, dinst, kh, 0, r, s));
                 BSTEP(hipEventRecord(e1, s));
                 BSTEP(hipEventSynchronize(e1));
                 float ms = 0;
@@ -1063,16 +1064,14 @@ cf_status run_batch(const BatchPlan& B, const BatchLayout& L, const cf_opts& o, 
             BSTEP(cf::launch_e2d<T>(CF_POL_TM, 1, A, dch, tm, B.inst_tm_n[i], g, lut, s));
             BSTEP(cf::launch_e2d<T>(CF_POL_TE, 1, A, dch, te, B.inst_te_n[i], g, lut, s));
         }
-        T* X = A;
-        T* Y = Bf;
-        int launches = 0;
+        int launches = 0, parity = 0;
         for (int m = 0; m < o.n_steps; m += kh) {
-            if (n_tm) BSTEP(cf::launch_tb2d<T>(variant, CF_POL_TM, X, Y, dch, dwork, nw_tm, dinst, tabs, dacc, kh, m, s));
+            if (n_tm) BSTEP(cf::launch_tb2d<T>(variant, CF_POL_TM, dch, dwork, nw_tm, dinst, kh, m, parity, s));
             if (n_te)
-                BSTEP(cf::launch_tb2d<T>(variant, CF_POL_TE, X, Y, dch, dwork + B.work_items, nw_te, dinst, tabs,
-                                         dacc, kh, m, s));
+                BSTEP(cf::launch_tb2d<T>(variant, CF_POL_TE, dch, dwork + B.work_items, nw_te, dinst, kh, m, parity,
+                                         s));
             launches += (n_tm > 0) + (n_te > 0);
-            std::swap(X, Y);
+            parity ^= 1;
         }
         timing->launches = launches;
         BSTEP(hipEventRecord(e1, s));

@@ -16,6 +16,8 @@ struct ChanDev {
     int64_t psi_off;     // first element of the channel's CPML block (3D)
     int32_t inst;        // instance of a fused launch
     int32_t pol;         // CF_POL_TM / CF_POL_TE / CF_POL_3D
+    int32_t local;       // channel index within its instance (accumulator, Gamma column)
+    int32_t pad2;
     int64_t src_off;     // field_off + slot(src) * ncell
     int64_t meas_off;    // field_off + slot(meas) * ncell
     int32_t kind;        // 0 E-current source, 1 H-current source
@@ -41,10 +43,23 @@ struct Grid2D {
     const uint8_t* ids[6];   // per-component material ids
 };
 
+struct SurfTables {
+    const int32_t* gidx;
+    const double* gw;
+    const int32_t* uidx;
+    const int32_t* uoff;     // CSR offsets, global
+    const int32_t* usamp;    // global sample index into the basis row
+    const double* uw;
+    const double* basis;
+};
+
 // One problem instance of a fused (2D) launch.  Several instances with
 // different grids, materials and surfaces can share one launch; each has its
 // own time origin `start` on the launch clock and its own step count.
 struct InstDev {
+    void* fa;              // field buffers of this instance (ping-pong): a launch
+    void* fb;              // with parity 0 reads fa and writes fb, parity 1 the reverse
+    double* acc;           // (sum, compensation) per channel, indexed by ChanDev.local
     int nx, ny;
     int64_t ncell;
     int perx, pery;
@@ -58,8 +73,9 @@ struct InstDev {
     int pad;
     double dt, dA;
     const double* ktab;    // K(t_m) of this instance
-    double* gamma;         // optional Gamma rows (stride gamma_stride, column = channel slot)
+    double* gamma;         // optional Gamma rows (stride gamma_stride, column = ChanDev.local)
     int64_t gamma_stride;
+    SurfTables t;          // surface tables the instance's channel offsets refer to
 };
 
 // Work item of a fused launch: channel descriptor `slot`, tile `tile` of its
@@ -94,15 +110,7 @@ struct Grid3D {
     const double* pml_ce;
 };
 
-struct SurfTables {
-    const int32_t* gidx;
-    const double* gw;
-    const int32_t* uidx;
-    const int32_t* uoff;     // CSR offsets, global
-    const int32_t* usamp;    // global sample index into the basis row
-    const double* uw;
-    const double* basis;
-};
+
 
 // 2D launchers.  `slots` lists the channel descriptors to advance (one
 // thread-block row per slot).  pol is CF_POL_TM or CF_POL_TE.  mode 0 =
@@ -136,11 +144,10 @@ hipError_t launch_e3d(int mode, T* fields, T* psi, const ChanDev* ch, const int*
 
 // Fused launch over a work list of nwork items, all of polarization pol:
 // every item advances its channel by min(kmax, remaining steps of its
-// instance) steps starting at launch-clock step m, reading src and writing
-// dst.  acc holds the (sum, compensation) pairs of all channel slots.
+// instance) steps starting at launch-clock step m, between its instance's
+// two field buffers in the direction given by parity.
 template <typename T>
-hipError_t launch_tb2d(int variant, int pol, const T* src, T* dst, const ChanDev* ch, const WorkItem* work,
-                       int nwork, const InstDev* inst, const SurfTables& t, double* acc, int kmax, int m,
-                       hipStream_t s);
+hipError_t launch_tb2d(int variant, int pol, const ChanDev* ch, const WorkItem* work, int nwork,
+                       const InstDev* inst, int kmax, int m, int parity, hipStream_t s);
 
 }  // namespace cf

@@ -260,9 +260,8 @@ __device__ __forceinline__ double from_prev(double v) {
 
 template <typename T, int POL, int RBW, int B, int KH, bool CREG>
 __global__ __launch_bounds__(64 * RBW) __attribute__((amdgpu_waves_per_eu(CREG ? 3 : 4)))
-void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __restrict__ ch,
-            const WorkItem* __restrict__ work, const InstDev* __restrict__ insts, SurfTables t,
-            double* __restrict__ acc, int kmax, int mclock) {
+void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
+            const InstDev* __restrict__ insts, int kmax, int mclock, int parity) {
     constexpr int RH = RBW * B;
     constexpr int NTB = 64 * RBW;
     constexpr int TX = 64 - 2 * KH, TY = RH - 2 * KH;
@@ -283,10 +282,14 @@ void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __res
     const int slot = wi.slot, tile = wi.tile;
     const ChanDev d = ch[slot];
     const InstDev g = insts[d.inst];
+    const SurfTables& t = g.t;
     const int m0 = mclock - g.start;                      // instance's own step
     const int ksteps = min(kmax, g.nsteps - m0);
     if (m0 < 0 || ksteps <= 0) return;                    // not started / finished
     const T* __restrict__ lut = static_cast<const T*>(g.lut);
+    const T* __restrict__ src = static_cast<const T*>(parity ? g.fb : g.fa);
+    T* __restrict__ dst = static_cast<T*>(parity ? g.fa : g.fb);
+    double* __restrict__ acc = g.acc + 2 * d.local;
     const int tx = tile % g.ntx, ty = tile / g.ntx;
     const int rx0 = g.base_x + tx * TX - KH, ry0 = g.base_y + ty * TY - KH;
     const int tid = threadIdx.x;
@@ -342,8 +345,8 @@ void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __res
     const bool stile = tile == g.stile;
     double acc_s = 0.0, acc_c = 0.0;
     if (stile && tid == 0) {
-        acc_s = acc[2 * slot];
-        acc_c = acc[2 * slot + 1];
+        acc_s = acc[0];
+        acc_c = acc[1];
     }
     __syncthreads();
 
@@ -427,7 +430,7 @@ void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __res
                 const double G = g.dA * s;
                 const int m = m0 + step;
                 neumaier(acc_s, acc_c, (g.dt * g.ktab[m]) * G);
-                if (g.gamma) g.gamma[(int64_t)m * g.gamma_stride + slot] = G;
+                if (g.gamma) g.gamma[(int64_t)m * g.gamma_stride + d.local] = G;
             }
             __syncthreads();
         }
@@ -435,8 +438,8 @@ void k_rb2d(const T* __restrict__ src, T* __restrict__ dst, const ChanDev* __res
 #undef CF_K
 #undef CF_ID
     if (stile && tid == 0) {
-        acc[2 * slot] = acc_s;
-        acc[2 * slot + 1] = acc_c;
+        acc[0] = acc_s;
+        acc[1] = acc_c;
     }
     T* D = dst + d.field_off;
     const int gx = rx0 + lane;
@@ -542,28 +545,26 @@ hipError_t launch_surface(const T* fields, const ChanDev* ch, const int* slots, 
 }
 
 template <typename T, int W, int B, int KH, bool CREG>
-static void rb_launch(int pol, int nwork, hipStream_t s, const T* src, T* dst, const ChanDev* ch,
-                      const WorkItem* work, const InstDev* inst, const SurfTables& t, double* acc, int kmax,
-                      int m) {
+static void rb_launch(int pol, int nwork, hipStream_t s, const ChanDev* ch, const WorkItem* work,
+                      const InstDev* inst, int kmax, int m, int parity) {
     dim3 grid(nwork), block(64 * W);
     if (pol == CF_POL_TM)
-        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TM, W, B, KH, CREG>), grid, block, 0, s, src, dst, ch, work, inst,
-                           t, acc, kmax, m);
+        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TM, W, B, KH, CREG>), grid, block, 0, s, ch, work, inst, kmax, m,
+                           parity);
     else
-        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TE, W, B, KH, CREG>), grid, block, 0, s, src, dst, ch, work, inst,
-                           t, acc, kmax, m);
+        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TE, W, B, KH, CREG>), grid, block, 0, s, ch, work, inst, kmax, m,
+                           parity);
 }
 
 template <typename T>
-hipError_t launch_tb2d(int variant, int pol, const T* src, T* dst, const ChanDev* ch, const WorkItem* work,
-                       int nwork, const InstDev* inst, const SurfTables& t, double* acc, int kmax, int m,
-                       hipStream_t s) {
+hipError_t launch_tb2d(int variant, int pol, const ChanDev* ch, const WorkItem* work, int nwork,
+                       const InstDev* inst, int kmax, int m, int parity, hipStream_t s) {
     if (nwork <= 0) return hipSuccess;
     int n;
     const RbVariant* v = rb_table<T>(&n);
     if (variant < 0 || variant >= n) return hipErrorInvalidValue;
     if (kmax < 1 || kmax > v[variant].KH) return hipErrorInvalidValue;
-#define CF_RB(W, B, KH, CR) rb_launch<T, W, B, KH, CR>(pol, nwork, s, src, dst, ch, work, inst, t, acc, kmax, m)
+#define CF_RB(W, B, KH, CR) rb_launch<T, W, B, KH, CR>(pol, nwork, s, ch, work, inst, kmax, m, parity)
     if constexpr (sizeof(T) == 4) {
         switch (variant) {
             case 0: CF_RB(8, 8, 8, false); break;
@@ -596,8 +597,8 @@ hipError_t launch_tb2d(int variant, int pol, const T* src, T* dst, const ChanDev
     template hipError_t launch_surface<T>(const T*, const ChanDev*, const int*, int, const SurfTables&, \
                                           const double*, int, double, double, double*, double*, int,    \
                                           hipStream_t);                                                 \
-    template hipError_t launch_tb2d<T>(int, int, const T*, T*, const ChanDev*, const WorkItem*, int,      \
-                                       const InstDev*, const SurfTables&, double*, int, int, hipStream_t);
+    template hipError_t launch_tb2d<T>(int, int, const ChanDev*, const WorkItem*, int, const InstDev*,    \
+                                       int, int, int, hipStream_t);
 CF_INSTANTIATE(float)
 CF_INSTANTIATE(double)
 #undef CF_INSTANTIATE
