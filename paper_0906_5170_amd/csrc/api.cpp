@@ -20,12 +20,13 @@
 #include "../../include/casimir_fdtd.h"
 #include "device.hpp"
 #include "plan.hpp"
+#include "solver.hpp"
 
 struct cf_problem {
     cf::Problem p;
 };
 
-namespace {
+namespace cfi {
 
 thread_local std::string g_err;
 
@@ -33,6 +34,8 @@ cf_status fail(cf_status code, const std::string& msg) {
     g_err = msg;
     return code;
 }
+
+void clear_error() { g_err.clear(); }
 
 #define CF_HIP(expr)                                                                  \
     do {                                                                              \
@@ -43,6 +46,10 @@ cf_status fail(cf_status code, const std::string& msg) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
 // Device workspace layout of one solve.
 struct Layout {
     size_t ids, lut, ktab, pml, chans, slots, gidx, gw, uidx, uoff, usamp, uw, basis, acc, gamma,
@@ -50,35 +57,8 @@ struct Layout {
     size_t work_items;    // capacity of one work list
 };
 
-// Tiling of the fused kernel: shifted so that every measured surface stencil
-// point of every channel lies in one tile (the surface tile).
-struct TBPlan {
-    bool ok = false;
-    int base_x = 0, base_y = 0, ntx = 0, nty = 0, stile = -1;
-};
 
-// One wave of resident channels: index lists (into the channel table) per
-// polarization and in channel order.
-struct Wave {
-    int tm_off, n_tm, te_off, n_te, d3_off, n_3d, all_off, n_all;
-};
 
-struct Staged {
-    TBPlan tb;                             // plan of the chosen variant
-    int variant = -1;                      // chosen fused variant (-1: not fused)
-    std::vector<TBPlan> plans;             // plan per fused variant
-    std::vector<cf::TBShape> shapes;
-    std::vector<cf::Channel> chans;       // channels run, in output order
-    std::vector<cf::ChanDev> dev;          // one descriptor per channel run
-    std::vector<int> slot_lists;           // concatenated per-wave lists
-    std::vector<Wave> waves;
-    std::vector<int32_t> gidx, uidx, uoff, usamp;
-    std::vector<double> gw, uw, basis;
-    int max_uniq = 0;
-    int resident = 0;                      // field blocks on the device
-    int ncomp = 3;
-    int64_t psi_comp = 0;                  // values per psi component (3D CPML)
-};
 
 TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, cf::TBShape sh);
 
@@ -196,9 +176,6 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
 }
 
 // ---- autotuner cache: "key variant" lines ---------------------------------
-std::mutex g_tune_mu;
-std::map<std::string, int> g_tune;
-bool g_tune_loaded = false;
 
 std::string tune_key(const cf::Problem& p, const cf_opts& o, int n_tm, int n_te) {
     std::ostringstream k;
@@ -334,12 +311,6 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     return L;
 }
 
-struct StencilTiming {
-    double ms_total = 0, bytes_total = 0, cu_total = 0;
-    int samples = 0;
-    int launches = 0;
-    int variant = -1;
-};
 
 // Sampled HIP-event timing of field-update launches on the solve's stream.
 struct Sampler {
@@ -1092,7 +1063,9 @@ bdone:
     return CF_OK;
 }
 
-}  // namespace
+}  // namespace cfi
+
+using namespace cfi;
 
 extern "C" {
 

@@ -1,0 +1,65 @@
+// Host structures shared by the solve, batch and serving code of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/casimir_fdtd.h"
+#include "device.hpp"
+#include "plan.hpp"
+
+namespace cfi {
+
+cf_status fail(cf_status code, const std::string& msg);
+void clear_error();
+size_t align_up(size_t v, size_t a);
+
+// Tiling of the fused kernel: shifted so that every measured surface stencil
+// point of every channel lies in one tile (the surface tile).
+struct TBPlan {
+    bool ok = false;
+    int base_x = 0, base_y = 0, ntx = 0, nty = 0, stile = -1;
+};
+
+// One wave of resident channels: index lists (into the channel table) per
+// polarization and in channel order.
+struct Wave {
+    int tm_off, n_tm, te_off, n_te, d3_off, n_3d, all_off, n_all;
+};
+
+struct Staged {
+    TBPlan tb;                             // plan of the chosen variant
+    int variant = -1;                      // chosen fused variant (-1: not fused)
+    std::vector<TBPlan> plans;             // plan per fused variant
+    std::vector<cf::TBShape> shapes;
+    std::vector<cf::Channel> chans;       // channels run, in output order
+    std::vector<cf::ChanDev> dev;          // one descriptor per channel run
+    std::vector<int> slot_lists;           // concatenated per-wave lists
+    std::vector<Wave> waves;
+    std::vector<int32_t> gidx, uidx, uoff, usamp;
+    std::vector<double> gw, uw, basis;
+    int max_uniq = 0;
+    int resident = 0;                      // field blocks on the device
+    int ncomp = 3;
+    int64_t psi_comp = 0;                  // values per psi component (3D CPML)
+};
+
+struct StencilTiming {
+    double ms_total = 0, bytes_total = 0, cu_total = 0;
+    int samples = 0;
+    int launches = 0;
+    int variant = -1;
+};
+
+// Stage the tables of one problem for the given channels and options.
+void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel>& chans, Staged& st);
+// XCD-balanced work list (see api.cpp).
+std::vector<cf::WorkItem> make_work(const std::vector<int>& slots, const std::vector<int>& ntiles);
+// Host reduction of accumulators into a cf_result; false if not finite.
+bool fill_result(const cf::Problem& p, const std::vector<cf::Channel>& chans, const std::vector<double>& acc,
+                 const std::vector<double>& gam, const cf_opts& o, double ms, const StencilTiming& tim,
+                 const Staged& sg, cf_result* out);
+
+}  // namespace cfi
