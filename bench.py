@@ -9,6 +9,12 @@ against K(t); the force is reduced on the host.  Inputs (material grids,
 tables) are uploaded inside each solve; the timed work is the whole solve.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain]
+                    [--no-batch] [--no-serve] [--serve-n N] [--serve-mixed]
+
+Beside the headline line it measures the 3D path on the 192^3 sphere-plate
+cell (a channel sample), the batched uneven piston set, and the serving
+scheduler on a seeded stream of piston requests (saturated, then Poisson
+arrivals at 0.7 of the measured capacity).
 
 Prints one JSON line.  Only one GPU is used; --gpus > 1 is refused.
 """
@@ -25,6 +31,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Yee cell-updates/s + force-solve p50/p99 latency, batched FP32 vs plain"
 HBM_PEAK_GBS = 8000.0
+
+
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_k_rb2d_piston2d_400x200_tetm_fp32.json")
+
+
+def kernel_source_hash():
+    """sha256 over the sources of the 2D kernels (the counters of a traffic
+    record only hold for the code they were taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels2d.hip", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_0906_5170_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(variant):
+    """HBM bytes per launch of the fused kernel from the committed counter
+    record (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a
+    plain copy of known size), or None when the record does not match the
+    current kernel source or variant."""
+    if not os.path.exists(TRAFFIC_RECORD):
+        return None, "no counter record"
+    rec = json.load(open(TRAFFIC_RECORD))
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None, "kernel source changed since the counters were taken"
+    if rec.get("tile_variant") != variant:
+        return None, f"counters taken on variant {rec.get('tile_variant')}, not {variant}"
+    return rec["hbm_bytes_per_launch"], rec.get("command", "")
 
 
 def log(msg):
@@ -49,6 +84,155 @@ def cpu_baseline(wl, n_channels=16, n_steps=3000):
                       f"({cu:.3e} cell-updates, {dt:.1f} s, FP64 NumPy, one process per channel)"}
 
 
+def bench_3d(cf, torch, n_chan=64, n_steps=200):
+    """3D FP32 path on the 192^3 sphere-over-indented-plate cell (16-cell z
+    CPML): a sample of n_chan of its 1280 channels, spread over faces, kinds
+    and harmonics, for n_steps steps, all resident at once."""
+    from casimir_inputs import c4_sphere_plate
+    wl = c4_sphere_plate()
+    p = cf.Problem.from_workload(wl)
+    o = dict(sigma=wl.sigma, courant=wl.courant, n_steps=n_steps, pol=wl.pol, kernel=wl.kernel,
+             precision="fp32")
+    C = p.info(**o)["n_channels"]
+    sub = np.linspace(0, C - 1, n_chan).astype(int).tolist()
+    p.solve(channel_subset=sub, **dict(o, n_steps=10))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r = p.solve(channel_subset=sub, time_stencil=True, **o)
+    dt = time.perf_counter() - t1
+    ceiling = HBM_PEAK_GBS * 1e9 / 48.0       # 48 B per 3D FP32 cell-update
+    rate = r["cell_updates"] / dt
+    step_rate = r["stencil_cell_updates"] / (r["stencil_ms_avg"] * 1e-3) if r["stencil_ms_avg"] else None
+    log(f"[bench] 3d: {rate:.3e} cell-updates/s over the solve, stencil {step_rate:.3e}")
+    return {"workload": f"sphere over indented plate 192^3 res 48, z CPML 16, {n_chan} of {C} channels "
+                        f"x {n_steps} steps, FP32 fields", "value": rate, "unit": "cell-updates/s",
+            "stencil_cell_updates_per_s": step_rate,
+            "stencil_frac_of_hbm_ceiling": step_rate / ceiling if step_rate else None,
+            "hbm_ceiling_cell_updates_per_s": ceiling,
+            "projected_full_solve_s": 1280 * wl.n_cells * wl.n_steps / rate}
+
+
+def _serve(cf, srv_budget, reqs, probs, opts_list, lam_times=True):
+    """Submit requests at their arrival times (or all at once) and wait for
+    all; returns per-request (kind, submit, admit, done, cell-updates)."""
+    rows = []
+    with cf.Server(srv_budget) as srv:
+        t0 = time.perf_counter()
+        tickets = []
+        for q, p, o in zip(reqs, probs, opts_list):
+            if lam_times:
+                delay = q.t_arrive - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+            try:
+                tickets.append((q, srv.submit(p, **o)))
+            except cf.CfError as e:
+                tickets.append((q, None))
+                log(f"[bench] serve: request {q.index} rejected: {e}")
+        for q, t in tickets:
+            if t is None:
+                rows.append(dict(kind=q.kind, rejected=True))
+                continue
+            r = srv.wait(t, timeout=-1)
+            ts, ta, td = srv.times(t)
+            rows.append(dict(kind=q.kind, submit=ts, admit=ta, done=td, cu=r["cell_updates"],
+                             fused=r["fused"], rejected=False))
+            srv.release(t)
+    return rows
+
+
+def _summary(rows):
+    ok = [r for r in rows if not r["rejected"]]
+    lat = np.array([r["done"] - r["submit"] for r in ok])
+    wait = np.array([r["admit"] - r["submit"] for r in ok])
+    span = max(r["done"] for r in ok) - min(r["submit"] for r in ok)
+    out = {"n": len(ok), "rejected": len(rows) - len(ok),
+           "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+           "mean_queue_wait_s": float(wait.mean()), "span_s": span,
+           "cell_updates_per_s": sum(r["cu"] for r in ok) / span,
+           "fused_requests": sum(1 for r in ok if r["fused"])}
+    for kind in sorted({r["kind"] for r in ok}):
+        lk = np.array([r["done"] - r["submit"] for r in ok if r["kind"] == kind])
+        out[f"{kind}_p50_s"] = float(np.percentile(lk, 50))
+        out[f"{kind}_p99_s"] = float(np.percentile(lk, 99))
+    return out
+
+
+def bench_serving(cf, torch, args, rate_3d):
+    """Serving on the seeded piston class of the mixed request stream: every
+    request is a complete force solve (2D TE+TM piston, clearance
+    h ~ U[0.1, 2], resolution ~ U{20..60}, T = 250 res, FP32).  First all
+    requests at once (saturation: the server's capacity), then the same
+    requests arriving as a Poisson stream at 0.7 of that capacity (the
+    load-matched stream whose latency percentiles are the headline)."""
+    from casimir_inputs.streams import mixed_stream, rescale_arrivals
+    budget = int(min(torch.cuda.get_device_properties(0).total_memory * 0.6, 160 * 2**30))
+    reqs, wls, probs = [], [], []
+    for q in mixed_stream(2 * args.serve_n, lam=4.0, seed=0, kinds=["2d"]):
+        w = q.workload()
+        try:
+            p_ = cf.Problem.from_workload(w)
+        except cf.CfError:          # no room for S between block and sidewall
+            continue
+        reqs.append(q)
+        wls.append(w)
+        probs.append(p_)
+        if len(reqs) == args.serve_n:
+            break
+    opts = [dict(sigma=w.sigma, courant=w.courant, n_steps=w.n_steps, pol=w.pol, kernel=w.kernel,
+                 precision="fp32") for w in wls]
+    log(f"[bench] serve: {len(reqs)} piston requests, saturated pass ...")
+    sat = _summary(_serve(cf, budget, reqs, probs, opts, lam_times=False))
+    cap = sat["n"] / sat["span_s"]                       # requests per second at saturation
+    lam = 0.7 * cap
+    log(f"[bench] serve: capacity {cap:.2f} req/s; Poisson pass at {lam:.2f} req/s ...")
+    matched = _summary(_serve(cf, budget, rescale_arrivals(reqs, lam), probs, opts))
+    res = {"stream": f"piston class of the seeded mixed stream (seed 0), {len(reqs)} requests: "
+                     "clearance h ~ U[0.1,2], res ~ U{20..60}, T = 250 res, 40 harmonics/face, TE+TM, FP32",
+           "budget_bytes": budget, "saturated": sat, "capacity_req_per_s": cap,
+           "load_matched": dict(matched, lam_req_per_s=lam, load=0.7)}
+    # the literal mixed stream (4 req/s, 70 % pistons / 30 % 3D cells): offered
+    # load against capacity from the measured per-class rates
+    if rate_3d:
+        lit = mixed_stream(200, lam=4.0, seed=0)
+        rate_2d = sat["cell_updates_per_s"]
+        svc, infeasible = [], 0
+        for q in lit:
+            if q.kind == "2d":
+                w = q.workload()
+                try:
+                    c = cf.Problem.from_workload(w).info(**opts[0])["n_channels"]
+                except cf.CfError:
+                    infeasible += 1
+                    continue
+                svc.append(c * w.n_cells * w.n_steps / rate_2d)
+            else:
+                n = q.params["n"]
+                svc.append(1280 * n ** 3 * (125 * n // 4) / rate_3d)
+        res["literal_stream"] = {"lam_req_per_s": 4.0, "n": len(lit), "infeasible_2d": infeasible,
+                                 "mean_service_s_estimated": float(np.mean(svc)),
+                                 "offered_load_x_capacity": 4.0 * float(np.mean(svc)),
+                                 "note": "service times from the measured saturated piston rate and the "
+                                         "3D sample rate; the stream is far beyond one GPU's capacity, "
+                                         "so its backlog grows without bound"}
+    if args.serve_mixed:
+        mreq, mp, mo = [], [], []
+        for q in mixed_stream(args.serve_mixed, lam=4.0, seed=0):
+            w = q.workload()
+            try:
+                p_ = cf.Problem.from_workload(w)
+            except cf.CfError:      # S does not fit (3D: gap below the indentation limit)
+                continue
+            mreq.append(q)
+            mp.append(p_)
+            mo.append(dict(sigma=w.sigma, courant=w.courant, n_steps=w.n_steps, pol=w.pol,
+                           kernel=w.kernel, precision="fp32"))
+        log(f"[bench] serve: mixed stream of {len(mreq)} requests at 4 req/s ...")
+        res["mixed_literal"] = _summary(_serve(cf, budget, mreq, mp, mo))
+    log(f"[bench] serve: p50 {matched['p50_s']:.3f} s p99 {matched['p99_s']:.3f} s")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,11 +241,24 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the headline solve and its stencil timing (for counter runs)")
+    ap.add_argument("--tile-variant", type=int, default=0,
+                    help="fused kernel variant for the headline solve (0: autotuned)")
+    ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--serve-n", type=int, default=24, help="requests in the served piston stream")
+    ap.add_argument("--serve-mixed", type=int, default=0,
+                    help="also serve this many requests of the mixed 2D/3D stream (long: 3D requests "
+                         "take tens of seconds each)")
     ap.add_argument("--n-steps", type=int, default=None, help="override T (testing only)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB (a plain copy kernel of known size, "
                          "the reference for HBM counter scaling)")
     args = ap.parse_args()
+    if args.main_only:
+        args.no_cpu = args.no_plain = args.no_batch = args.no_serve = args.no_3d = args.no_sweep = True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the channel-parallel "
               "multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
@@ -94,7 +291,7 @@ def main():
         del a, b
     prob = cf.Problem.from_workload(wl)
     opts = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol=wl.pol,
-                kernel=wl.kernel, precision="fp32")
+                kernel=wl.kernel, precision="fp32", tile_variant=args.tile_variant)
     info = prob.info(**opts)
     ws = torch.empty(info["workspace_bytes"], dtype=torch.uint8, device="cuda")
     log(f"[bench] {wl.name}: {info['n_channels']} channels, {wl.n_cells} cells, T={wl.n_steps}, "
@@ -121,8 +318,10 @@ def main():
     rt = prob.solve(workspace=ws, time_stencil=True, **opts)
     avg_s = rt["stencil_ms_avg"] * 1e-3
     achieved = rt["stencil_alg_bytes"] / avg_s / 1e9 if avg_s > 0 else None
+    traffic, traffic_note = measured_traffic(rt["tile_variant"])
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "traffic_note": traffic_note,
                 "kernel": "k_rb2d: fused register-blocked 2D update of all TM (or TE) channels, "
                           "steps_per_launch time steps per launch",
                 "avg_launch_ms": rt["stencil_ms_avg"], "launches_timed": rt["stencil_samples"],
@@ -146,16 +345,16 @@ def main():
     # every fused-kernel variant on the same solve (T = 1000), the autotuner's
     # search space; all variants give bitwise-identical results
     sweep = []
-    for v in range(1, 32):
+    for v in (range(1, 32) if not args.no_sweep else ()):
         try:
-            rv = prob.solve(workspace=ws, tile_variant=v, **dict(opts, n_steps=1000))
+            rv = prob.solve(workspace=ws, **dict(opts, n_steps=1000, tile_variant=v))
         except cf.CfError:
             break
         if not rv["fused"] or rv["tile_variant"] != v:
             break
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        rv = prob.solve(workspace=ws, tile_variant=v, **dict(opts, n_steps=1000))
+        rv = prob.solve(workspace=ws, **dict(opts, n_steps=1000, tile_variant=v))
         sweep.append({"variant": v, "steps_per_launch": rv["tile_halo"],
                       "ms_per_1000_steps": (time.perf_counter() - t1) * 1e3})
     out["tile_sweep"] = sweep
@@ -185,6 +384,13 @@ def main():
                                              f"{sum(r['n_channels'] for r in rb)} channels, T=1000, FP32",
                                  "value": cu / tb, "unit": "cell-updates/s", "ms": tb * 1e3,
                                  "sequential_ms": ts * 1e3, "speedup_vs_sequential": ts / tb}
+
+    rate_3d = None
+    if not args.no_3d:
+        out["c4_3d"] = bench_3d(cf, torch)
+        rate_3d = out["c4_3d"]["value"]
+    if not args.no_serve:
+        out["serving"] = bench_serving(cf, torch, args, rate_3d)
 
     gold = os.path.join(ROOT, "tests", "golden", "c2_piston_tetm_oracle.json")
     if os.path.exists(gold) and not args.n_steps:

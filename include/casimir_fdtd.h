@@ -120,8 +120,17 @@ typedef struct cf_surface {
  * duration (cf_result.stencil_ms_avg); the stepping loop is otherwise
  * unchanged.
  * CF_FLAG_SPLIT makes the batched path use one launch per half step instead
- * of the fused multi-step kernel (same arithmetic, bitwise-equal results). */
-enum { CF_FLAG_KEEP_GAMMA = 1, CF_FLAG_TIME_STENCIL = 2, CF_FLAG_SPLIT = 4 };
+ * of the fused multi-step kernel (same arithmetic, bitwise-equal results).
+ * CF_FLAG_GRAPH captures the fused stepping loop of each channel wave (and
+ * of a batched solve) into a HIP graph and launches it as one graph instead
+ * of one kernel launch per K steps (same kernels and arguments, bitwise-equal
+ * results; ignored together with CF_FLAG_TIME_STENCIL).
+ * CF_FLAG_INJECT_NAN is a fault-injection hook for failure-handling tests:
+ * the kick of the first channel run is scaled by NaN, so its accumulator
+ * becomes non-finite and the solve (or served request) fails with
+ * CF_E_NONFINITE; nothing else changes. */
+enum { CF_FLAG_KEEP_GAMMA = 1, CF_FLAG_TIME_STENCIL = 2, CF_FLAG_SPLIT = 4, CF_FLAG_INJECT_NAN = 8,
+       CF_FLAG_GRAPH = 16 };
 
 typedef struct cf_opts {
     double sigma;       /* uniform conductivity (decay rate), >= 0            */
@@ -237,6 +246,81 @@ cf_status cf_kernel_table(int kernel, double sigma, double dt, int n, double* ou
 
 /* Message describing the last failure on this thread ("" if none). */
 const char* cf_last_error(void);
+
+/* ---- Serving: continuous batching of force solves (one GPU) ------------
+ *
+ * A server owns a device memory budget and a scheduler thread.  Requests
+ * (one problem + options each, the whole Sec. II force computation) are
+ * queued in arrival order; a request enters as soon as its memory fits the
+ * budget (a later request may pass an earlier one that does not fit yet) and
+ * leaves when all its time steps have run, returning its memory.  Every
+ * scheduler tick advances all resident requests by the same number of steps;
+ * 2D requests whose stress surface fits a fused tile share fused launches.
+ * A request's arithmetic does not depend on what else is resident: a result
+ * is bitwise the same alone and in any mix, and equals cf_solve with the
+ * same options and tile_variant (fused 2D) or CF_FLAG_SPLIT (others).
+ *
+ * Ownership: the problem handle passed to cf_server_submit must stay alive
+ * until its request is done, failed or cancelled.  cf_server_destroy cancels
+ * what is still queued or running and must not overlap other calls on the
+ * same server.  All other calls are thread-safe. */
+typedef struct cf_server cf_server;
+
+enum {
+    CF_REQ_QUEUED = 0,
+    CF_REQ_RUNNING = 1,
+    CF_REQ_DONE = 2,
+    CF_REQ_FAILED = 3,
+    CF_REQ_CANCELLED = 4
+};
+
+typedef struct cf_server_info {
+    uint64_t submitted, completed, failed, cancelled;
+    int queued, running;       /* requests waiting / resident now */
+    size_t bytes_in_use;       /* of the request arena */
+    size_t budget;             /* request arena size (budget minus server tables) */
+    int64_t clock_steps;       /* time steps the scheduler clock has advanced */
+    double busy_s;             /* wall time spent in ticks */
+    int steps_per_tick;
+} cf_server_info;
+
+/* Create a server.  hbm_budget_bytes: device memory for the server's tables
+ * and every resident request; arena: a device buffer of that size, or NULL
+ * to allocate one.  precision: CF_FP32 / CF_FP64 for every request.
+ * tile_variant: fused kernel variant (1-based, as in cf_opts) used for all
+ * fused requests, 0 for the default.  stream: hipStream_t, or NULL for a
+ * stream of the server's own.  CF_E_BUDGET when the budget cannot hold the
+ * server's tables. */
+cf_status cf_server_create(size_t hbm_budget_bytes, int precision, int tile_variant, void* arena,
+                           void* stream, cf_server** out);
+
+/* Queue a request; *ticket identifies it.  opts->precision must match the
+ * server's, path must be CF_PATH_BATCHED, channel_subset empty;
+ * opts->max_resident bounds the channel waves of non-fused requests (0:
+ * all channels, halved until the request fits the budget).  CF_E_BUDGET
+ * when the request can never fit. */
+cf_status cf_server_submit(cf_server* s, cf_problem* p, const cf_opts* opts, uint64_t* ticket);
+
+/* State of a request (CF_REQ_*); when done, *out (may be NULL) receives its
+ * result as from cf_solve (device_ms = wall time from admission to
+ * completion).  Returns the request's error for failed / cancelled ones. */
+cf_status cf_server_poll(cf_server* s, uint64_t ticket, int* state, cf_result* out);
+
+/* As cf_server_poll after waiting up to timeout_s seconds (< 0: no limit)
+ * for the request to finish. */
+cf_status cf_server_wait(cf_server* s, uint64_t ticket, double timeout_s, int* state, cf_result* out);
+
+/* Ask for a request to stop: a queued one leaves at once, a running one at
+ * the end of the current tick; its state becomes CF_REQ_CANCELLED. */
+cf_status cf_server_cancel(cf_server* s, uint64_t ticket);
+
+/* Submission, admission and completion times of a request (seconds on a
+ * monotonic clock; 0 when not reached yet). */
+cf_status cf_server_times(cf_server* s, uint64_t ticket, double* submit_s, double* admit_s,
+                          double* done_s);
+
+cf_status cf_server_stats(cf_server* s, cf_server_info* out);
+cf_status cf_server_destroy(cf_server* s);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,8 @@ PATH = {"batched": 0, "plain": 1}
 FLAG_KEEP_GAMMA = 1
 FLAG_TIME_STENCIL = 2
 FLAG_SPLIT = 4
+FLAG_INJECT_NAN = 8
+FLAG_GRAPH = 16
 STATUS = {0: "CF_OK", 1: "CF_E_ARG", 2: "CF_E_CFL", 3: "CF_E_SURFACE", 4: "CF_E_BUDGET",
           5: "CF_E_NONFINITE", 6: "CF_E_DEVICE", 7: "CF_E_CANCELLED", 8: "CF_E_UNSUPPORTED"}
 
@@ -82,7 +84,9 @@ _lib = None
 
 EXPORTS = ("cf_problem_create", "cf_problem_destroy", "cf_problem_info", "cf_channel_table",
            "cf_validate", "cf_workspace_size", "cf_solve", "cf_kernel_table", "cf_last_error",
-           "cf_batch_workspace_size", "cf_batch_solve")
+           "cf_batch_workspace_size", "cf_batch_solve", "cf_server_create", "cf_server_submit",
+           "cf_server_poll", "cf_server_wait", "cf_server_cancel", "cf_server_times", "cf_server_stats",
+           "cf_server_destroy")
 
 
 def load():
@@ -115,6 +119,14 @@ def load():
                                             C.POINTER(C.c_size_t)]
     lib.cf_batch_solve.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(_Opts), C.c_void_p, C.c_size_t,
                                    C.POINTER(_Result)]
+    lib.cf_server_create.argtypes = [C.c_size_t, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.POINTER(P)]
+    lib.cf_server_submit.argtypes = [P, P, C.POINTER(_Opts), C.POINTER(C.c_uint64)]
+    lib.cf_server_poll.argtypes = [P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(_Result)]
+    lib.cf_server_wait.argtypes = [P, C.c_uint64, C.c_double, C.POINTER(C.c_int), C.POINTER(_Result)]
+    lib.cf_server_cancel.argtypes = [P, C.c_uint64]
+    lib.cf_server_times.argtypes = [P, C.c_uint64] + [C.POINTER(C.c_double)] * 3
+    lib.cf_server_stats.argtypes = [P, C.POINTER(_ServerInfo)]
+    lib.cf_server_destroy.argtypes = [P]
     for name in EXPORTS:
         getattr(lib, name).restype = C.c_int if name != "cf_last_error" else C.c_char_p
     _lib = lib
@@ -128,6 +140,39 @@ def _check(code: int):
 
 def _dptr(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _result_buffers(n_harm: int, n_chan: int, n_steps_gamma: int = 0):
+    """A cf_result whose output arrays point at fresh NumPy buffers."""
+    ph = np.zeros(max(1, n_harm))
+    pf = np.zeros(6)
+    pc = np.zeros(n_chan)
+    r = _Result()
+    r.per_harmonic, r.per_harmonic_len = _dptr(ph), len(ph)
+    r.per_face, r.per_face_len = _dptr(pf), 6
+    r.per_channel, r.per_channel_len = _dptr(pc), n_chan
+    bufs = dict(ph=ph, n_harm=n_harm, pf=pf, pc=pc, gam=None, tr=None)
+    if n_steps_gamma:
+        bufs["gam"] = np.zeros(n_steps_gamma * n_chan)
+        bufs["tr"] = np.zeros(n_steps_gamma)
+        r.gamma, r.gamma_len = _dptr(bufs["gam"]), bufs["gam"].size
+        r.trace, r.trace_len = _dptr(bufs["tr"]), n_steps_gamma
+        bufs["T"] = n_steps_gamma
+    return r, bufs
+
+
+def _result_dict(r, bufs) -> dict:
+    out = dict(force=r.force, per_harmonic=bufs["ph"][:bufs["n_harm"]], per_face=bufs["pf"],
+               per_channel=bufs["pc"], n_channels=r.n_channels_run, cell_updates=r.cell_updates,
+               device_ms=r.device_ms, stencil_ms_avg=r.stencil_ms_avg,
+               stencil_samples=r.stencil_samples, stencil_launches=r.stencil_launches,
+               stencil_alg_bytes=r.stencil_alg_bytes,
+               stencil_cell_updates=r.stencil_cell_updates, fused=bool(r.fused),
+               tile_variant=r.tile_variant, tile_halo=r.tile_halo)
+    if bufs["gam"] is not None:
+        out["gamma"] = bufs["gam"].reshape(bufs["T"], len(bufs["pc"]))
+        out["trace"] = bufs["tr"]
+    return out
 
 
 def kernel_table(kernel: str, sigma: float, dt: float, n: int) -> np.ndarray:
@@ -200,7 +245,8 @@ class Problem:
 
     def _opts(self, sigma=1.0, courant=0.5, n_steps=1000, pol="TM", kernel="zinv2d",
               precision="fp64", path="batched", keep_gamma=False, channel_subset=None, stream=None,
-              time_stencil=False, split=False, max_resident=0, tile_variant=0):
+              time_stencil=False, split=False, max_resident=0, tile_variant=0, inject_nan=False,
+              graph=False):
         o = _Opts()
         o.sigma = float(sigma)
         o.courant = float(courant)
@@ -210,7 +256,8 @@ class Problem:
         o.precision = PRECISION[precision]
         o.path = PATH[path]
         o.flags = ((FLAG_KEEP_GAMMA if keep_gamma else 0) | (FLAG_TIME_STENCIL if time_stencil else 0)
-                   | (FLAG_SPLIT if split else 0))
+                   | (FLAG_SPLIT if split else 0) | (FLAG_INJECT_NAN if inject_nan else 0)
+                   | (FLAG_GRAPH if graph else 0))
         if channel_subset is not None:
             sub = np.ascontiguousarray(channel_subset, dtype=np.int32)
             o.channel_subset = sub.ctypes.data_as(C.POINTER(C.c_int))
@@ -264,30 +311,9 @@ class Problem:
         o = self._opts(**opts)
         C_run = o.n_subset if o.n_subset > 0 else info["n_channels"]
         T = int(opts.get("n_steps", 1000))
-        ph = np.zeros(max(1, info["per_harmonic_len"]))
-        pf = np.zeros(6)
-        pc = np.zeros(C_run)
-        r = _Result()
-        r.per_harmonic, r.per_harmonic_len = _dptr(ph), len(ph)
-        r.per_face, r.per_face_len = _dptr(pf), 6
-        r.per_channel, r.per_channel_len = _dptr(pc), C_run
-        gam = tr = None
-        if opts.get("keep_gamma"):
-            gam = np.zeros(T * C_run)
-            tr = np.zeros(T)
-            r.gamma, r.gamma_len = _dptr(gam), gam.size
-            r.trace, r.trace_len = _dptr(tr), T
+        r, bufs = _result_buffers(info["per_harmonic_len"], C_run, T if opts.get("keep_gamma") else 0)
         _check(load().cf_solve(self._h, C.byref(o), C.c_void_p(workspace.data_ptr()), nbytes, C.byref(r)))
-        out = dict(force=r.force, per_harmonic=ph[:info["per_harmonic_len"]], per_face=pf,
-                   per_channel=pc, n_channels=r.n_channels_run, cell_updates=r.cell_updates,
-                   device_ms=r.device_ms, stencil_ms_avg=r.stencil_ms_avg,
-                   stencil_samples=r.stencil_samples, stencil_launches=r.stencil_launches,
-                   stencil_alg_bytes=r.stencil_alg_bytes,
-                   stencil_cell_updates=r.stencil_cell_updates, fused=bool(r.fused),
-                   tile_variant=r.tile_variant, tile_halo=r.tile_halo)
-        if gam is not None:
-            out["gamma"] = gam.reshape(T, C_run)
-            out["trace"] = tr
+        out = _result_dict(r, bufs)
         return out
 
 
@@ -333,6 +359,105 @@ def batch_solve(problems: Sequence["Problem"], workspace=None, **opts):
                         device_ms=r.device_ms, fused=bool(r.fused), tile_variant=r.tile_variant,
                         tile_halo=r.tile_halo))
     return out
+
+
+REQ_STATE = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
+
+
+class _ServerInfo(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
+                ("cancelled", C.c_uint64), ("queued", C.c_int), ("running", C.c_int),
+                ("bytes_in_use", C.c_size_t), ("budget", C.c_size_t), ("clock_steps", C.c_int64),
+                ("busy_s", C.c_double), ("steps_per_tick", C.c_int)]
+
+
+class Server:
+    """Continuous-batching force-solve server on the current GPU (see
+    cf_server_create).  The device memory budget is one torch uint8 tensor
+    handed to the library as its arena; the scheduler runs on a stream of
+    its own.  Problems submitted are kept alive here until their results
+    have been taken."""
+
+    def __init__(self, budget_bytes: int, precision: str = "fp32", tile_variant: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("cf server needs a ROCm GPU")
+        lib = load()
+        self._arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        self.precision = precision
+        h = C.c_void_p()
+        _check(lib.cf_server_create(int(budget_bytes), PRECISION[precision], int(tile_variant),
+                                    C.c_void_p(self._arena.data_ptr()), None, C.byref(h)))
+        self._h = h
+        self._reqs = {}
+
+    def submit(self, problem: "Problem", **opts) -> int:
+        opts = dict(opts)
+        opts.setdefault("precision", self.precision)
+        o = problem._opts(**opts)
+        t = C.c_uint64()
+        _check(load().cf_server_submit(self._h, problem._h, C.byref(o), C.byref(t)))
+        info = problem.info(**opts)
+        self._reqs[t.value] = (problem, info)
+        return t.value
+
+    def _take(self, fn, ticket, *extra):
+        problem, info = self._reqs[ticket]
+        r, bufs = _result_buffers(info["per_harmonic_len"], info["n_channels"])
+        st = C.c_int()
+        _check(fn(self._h, C.c_uint64(ticket), *extra, C.byref(st), C.byref(r)))
+        state = REQ_STATE[st.value]
+        return state, (_result_dict(r, bufs) if state == "done" else None)
+
+    def poll(self, ticket: int):
+        """(state, result or None)."""
+        return self._take(load().cf_server_poll, ticket)
+
+    def wait(self, ticket: int, timeout: float = -1.0) -> dict:
+        """Block until the request is done and return its result (raises
+        CfError if it failed or was cancelled, TimeoutError on timeout)."""
+        state, res = self._take(load().cf_server_wait, ticket, C.c_double(timeout))
+        if state != "done":
+            raise TimeoutError(f"request {ticket} still {state}")
+        return res
+
+    def cancel(self, ticket: int):
+        _check(load().cf_server_cancel(self._h, C.c_uint64(ticket)))
+
+    def times(self, ticket: int):
+        """(submitted, admitted, done) on a monotonic clock, seconds."""
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        _check(load().cf_server_times(self._h, C.c_uint64(ticket), C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def stats(self) -> dict:
+        i = _ServerInfo()
+        _check(load().cf_server_stats(self._h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in _ServerInfo._fields_}
+
+    def release(self, ticket: int):
+        """Drop the problem reference kept for a finished request."""
+        self._reqs.pop(ticket, None)
+
+    def close(self):
+        if self._h is not None:
+            load().cf_server_destroy(self._h)
+            self._h = None
+            self._reqs.clear()
+            self._arena = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def solve_workload(wl, **over) -> dict:

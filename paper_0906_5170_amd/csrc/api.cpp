@@ -136,6 +136,7 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         d.basis_off = basis_face_off[ch.face] + ch.row * p.faces[ch.face].nsamp;
         d.meas_slot = cf::comp_slot(ch.pol, ch.meas);
         d.kick_scale = -res / (ch.kind == 0 ? p.eps_s : p.mu_s);
+        if (c == 0 && (o.flags & CF_FLAG_INJECT_NAN)) d.kick_scale = std::nan("");
         st.max_uniq = std::max(st.max_uniq, d.n_uniq);
         st.dev.push_back(d);
     }
@@ -333,6 +334,49 @@ struct Sampler {
     }
 };
 
+// Optional capture of a launch sequence into a HIP graph (CF_FLAG_GRAPH).
+// The launches are captured on a private stream (the caller's stream may be
+// the null stream, which cannot be captured); end() instantiates the graph
+// and launches it once on the caller's stream.  Graphs and the private
+// stream live until the object dies, after the caller has drained its stream.
+struct GraphRun {
+    bool on = false;
+    hipStream_t cap = nullptr;
+    std::vector<hipGraph_t> graphs;
+    std::vector<hipGraphExec_t> execs;
+    // stream the captured launches are issued on
+    hipStream_t launch_stream(hipStream_t s) const { return on ? cap : s; }
+    hipError_t begin() {
+        if (!on) return hipSuccess;
+        if (!cap) {
+            const hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+        }
+        return hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    }
+    hipError_t end(hipStream_t s, hipError_t body) {
+        if (!on) return body;
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(cap, &g);   // the capture ends whatever the body did
+        if (g) graphs.push_back(g);
+        if (body != hipSuccess) return body;
+        if (ec != hipSuccess) return ec;
+        hipGraphExec_t x = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) return ei;
+        execs.push_back(x);
+        return hipGraphLaunch(x, s);
+    }
+    GraphRun() = default;
+    GraphRun(const GraphRun&) = delete;
+    GraphRun& operator=(const GraphRun&) = delete;
+    ~GraphRun() {
+        for (auto x : execs) (void)hipGraphExecDestroy(x);
+        for (auto g : graphs) (void)hipGraphDestroy(g);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
 template <typename T>
 cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, const Layout& L,
                     char* ws, hipStream_t s, std::vector<double>& acc_out, std::vector<double>& gamma_out,
@@ -478,6 +522,8 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     };
     int variant = st.variant;
     hipError_t err = hipSuccess;
+    GraphRun graph;
+    graph.on = (o.flags & CF_FLAG_GRAPH) && !smp.on;
 #define STEP_OK(expr)                     \
     do {                                  \
         err = (expr);                     \
@@ -580,20 +626,28 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             STEP_OK(upload_inst(make_inst(pl, true)));
             STEP_OK(upload_work(st.slot_lists.data() + w.tm_off, w.n_tm, pl, 0, &nw_tm));
             STEP_OK(upload_work(st.slot_lists.data() + w.te_off, w.n_te, pl, L.work_items, &nw_te));
-            int parity = 0;
-            for (int m = 0; m < o.n_steps; m += kh) {
-                const int ks = std::min(kh, o.n_steps - m);
-                for (int pol : {CF_POL_TM, CF_POL_TE}) {
-                    const int n = pol == CF_POL_TM ? w.n_tm : w.n_te;
-                    if (n == 0) continue;
-                    const bool take = smp.begin(s);
-                    STEP_OK(cf::launch_tb2d<T>(variant, pol, dch, pol == CF_POL_TM ? dwork : dwork + L.work_items,
-                                               pol == CF_POL_TM ? nw_tm : nw_te, dinst, kh, m, parity, s));
-                    const double cu = (double)n * p.ncell * ks;
-                    smp.end(take, s, cu, cu * state_bytes);
+            STEP_OK(graph.begin());
+            const hipStream_t ls = graph.launch_stream(s);
+            const hipError_t body = [&]() -> hipError_t {
+                int parity = 0;
+                for (int m = 0; m < o.n_steps; m += kh) {
+                    const int ks = std::min(kh, o.n_steps - m);
+                    for (int pol : {CF_POL_TM, CF_POL_TE}) {
+                        const int n = pol == CF_POL_TM ? w.n_tm : w.n_te;
+                        if (n == 0) continue;
+                        const bool take = smp.begin(ls);
+                        const hipError_t e = cf::launch_tb2d<T>(
+                            variant, pol, dch, pol == CF_POL_TM ? dwork : dwork + L.work_items,
+                            pol == CF_POL_TM ? nw_tm : nw_te, dinst, kh, m, parity, ls);
+                        if (e != hipSuccess) return e;
+                        const double cu = (double)n * p.ncell * ks;
+                        smp.end(take, ls, cu, cu * state_bytes);
+                    }
+                    parity ^= 1;
                 }
-                parity ^= 1;
-            }
+                return hipSuccess;
+            }();
+            STEP_OK(graph.end(s, body));
         } else {
             for (int m = 0; m < o.n_steps; ++m) {
                 const bool take = smp.begin(s);
@@ -967,6 +1021,8 @@ cf_status run_batch(const BatchPlan& B, const BatchLayout& L, const cf_opts& o, 
     CF_HIP(hipEventCreate(&e1));
     int variant = B.variants_ok[0];
     const size_t fbytes = B.field_elems * sizeof(T);
+    GraphRun graph;
+    graph.on = (o.flags & CF_FLAG_GRAPH) != 0;
 #define BSTEP(expr)                        \
     do {                                   \
         err = (expr);                      \
@@ -1035,14 +1091,25 @@ cf_status run_batch(const BatchPlan& B, const BatchLayout& L, const cf_opts& o, 
             BSTEP(cf::launch_e2d<T>(CF_POL_TM, 1, A, dch, tm, B.inst_tm_n[i], g, lut, s));
             BSTEP(cf::launch_e2d<T>(CF_POL_TE, 1, A, dch, te, B.inst_te_n[i], g, lut, s));
         }
-        int launches = 0, parity = 0;
-        for (int m = 0; m < o.n_steps; m += kh) {
-            if (n_tm) BSTEP(cf::launch_tb2d<T>(variant, CF_POL_TM, dch, dwork, nw_tm, dinst, kh, m, parity, s));
-            if (n_te)
-                BSTEP(cf::launch_tb2d<T>(variant, CF_POL_TE, dch, dwork + B.work_items, nw_te, dinst, kh, m, parity,
-                                         s));
-            launches += (n_tm > 0) + (n_te > 0);
-            parity ^= 1;
+        int launches = 0;
+        BSTEP(graph.begin());
+        {
+            const hipStream_t ls = graph.launch_stream(s);
+            const hipError_t body = [&]() -> hipError_t {
+                int parity = 0;
+                for (int m = 0; m < o.n_steps; m += kh) {
+                    hipError_t e = hipSuccess;
+                    if (n_tm) e = cf::launch_tb2d<T>(variant, CF_POL_TM, dch, dwork, nw_tm, dinst, kh, m, parity, ls);
+                    if (e == hipSuccess && n_te)
+                        e = cf::launch_tb2d<T>(variant, CF_POL_TE, dch, dwork + B.work_items, nw_te, dinst, kh, m,
+                                               parity, ls);
+                    if (e != hipSuccess) return e;
+                    launches += (n_tm > 0) + (n_te > 0);
+                    parity ^= 1;
+                }
+                return hipSuccess;
+            }();
+            BSTEP(graph.end(s, body));
         }
         timing->launches = launches;
         BSTEP(hipEventRecord(e1, s));
@@ -1199,7 +1266,7 @@ cf_status cf_solve(cf_problem* h, const cf_opts* o, void* workspace, size_t ws_b
     StencilTiming tim;
     cf_status rs = o->precision == CF_FP64 ? run_solve<double>(p, *o, sg, L, ws, s, acc, gam, &ms, &tim)
                                            : run_solve<float>(p, *o, sg, L, ws, s, acc, gam, &ms, &tim);
-    if (owned) hipFree(owned);
+    if (owned) (void)hipFree(owned);
     if (rs != CF_OK) return rs;
     const bool finite = fill_result(p, chans, acc, gam, *o, ms, tim, sg, out);
     if (!finite) return fail(CF_E_NONFINITE, "a force accumulator is not finite");

@@ -89,7 +89,7 @@ struct WorkItem {
 struct TBShape {
     int tx, ty, kh;
 };
-constexpr int kMaxVariants = 8;
+constexpr int kMaxVariants = 16;
 template <typename T>
 int tb_variants(TBShape* out, int max);
 

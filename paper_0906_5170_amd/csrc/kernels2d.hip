@@ -258,13 +258,23 @@ __device__ __forceinline__ double from_prev(double v) {
                             __builtin_amdgcn_mov_dpp(lo, 0x138, 0xf, 0xf, true));
 }
 
-template <typename T, int POL, int RBW, int B, int KH, bool CREG>
-__global__ __launch_bounds__(64 * RBW) __attribute__((amdgpu_waves_per_eu(CREG ? 3 : 4)))
+// Register-blocked fused kernel.  A block holds a (64 CX) x (RBW B) region
+// of one channel: lane l of wave w owns columns CX l .. CX l + CX - 1 and rows
+// w B .. w B + B - 1, with every field value in registers.  x neighbours come
+// from the lane's own registers or, across lanes, by DPP row shifts; y
+// neighbours inside a wave's band from registers, across bands through LDS
+// exchange rows.  KH steps run per launch; the outer KH cells of the region
+// go stale one per step, so only the interior (64 CX - 2 KH) x (RBW B - 2 KH)
+// is written back.
+template <typename T, int POL, int RBW, int B, int KH, bool CREG, int CX, int WPE>
+__global__ __launch_bounds__(64 * RBW) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
             const InstDev* __restrict__ insts, int kmax, int mclock, int parity) {
     constexpr int RH = RBW * B;
+    constexpr int RW = 64 * CX;
     constexpr int NTB = 64 * RBW;
-    constexpr int TX = 64 - 2 * KH, TY = RH - 2 * KH;
+    constexpr int TX = RW - 2 * KH, TY = RH - 2 * KH;
+    constexpr int NP = (B + 3) / 4;
     constexpr int C0 = POL == CF_POL_TM ? CF_EZ : CF_EX;
     constexpr int C1 = POL == CF_POL_TM ? CF_HX : CF_EY;
     constexpr int C2 = POL == CF_POL_TM ? CF_HY : CF_HZ;
@@ -272,9 +282,9 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
     // wave-boundary rows: E rows (read by the wave below) and H rows (read by
     // the wave above) in separate buffers, so each write is separated from
     // the previous reads of the same buffer by the other half step's barrier
-    __shared__ T xe[RBW][64];
-    __shared__ T xh[RBW][64];
-    __shared__ T stage[RH * 64];     // measured component (surface tile only)
+    __shared__ T xe[RBW][CX][64];
+    __shared__ T xh[RBW][CX][64];
+    __shared__ T stage[RH * RW];     // measured component (surface tile only), [row][col j][lane]
     __shared__ double red[RBW];
 
     const WorkItem wi = work[blockIdx.x];
@@ -303,43 +313,48 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
         L[s][id].b = p[1];
     }
 
-    T f0[B], f1[B], f2[B];
-    uint32_t m0p[(B + 3) / 4], m1p[(B + 3) / 4], m2p[(B + 3) / 4];
+    T f0[CX][B], f1[CX][B], f2[CX][B];
+    uint32_t m0p[CX][NP], m1p[CX][NP], m2p[CX][NP];
 #pragma unroll
-    for (int r = 0; r < (B + 3) / 4; ++r) m0p[r] = m1p[r] = m2p[r] = 0;
+    for (int j = 0; j < CX; ++j)
+#pragma unroll
+        for (int r = 0; r < NP; ++r) m0p[j][r] = m1p[j][r] = m2p[j][r] = 0;
     {
         const T* S = src + d.field_off;
-        int gx = rx0 + lane;
-        bool inx = true;
-        if (gx < 0 || gx >= g.nx) {
-            if (g.perx) gx = ((gx % g.nx) + g.nx) % g.nx;
-            else inx = false;
-        }
 #pragma unroll
-        for (int r = 0; r < B; ++r) {
-            int gy = ry0 + w * B + r;
-            bool in = inx;
-            if (gy < 0 || gy >= g.ny) {
-                if (g.pery) gy = ((gy % g.ny) + g.ny) % g.ny;
-                else in = false;
+        for (int j = 0; j < CX; ++j) {
+            int gx = rx0 + lane * CX + j;
+            bool inx = true;
+            if (gx < 0 || gx >= g.nx) {
+                if (g.perx) gx = ((gx % g.nx) + g.nx) % g.nx;
+                else inx = false;
             }
-            uint32_t i0 = kNullId, i1 = kNullId, i2 = kNullId;
-            if (in) {
-                const int64_t gi = (int64_t)gy * g.nx + gx;
-                f0[r] = S[gi];
-                f1[r] = S[g.ncell + gi];
-                f2[r] = S[2 * g.ncell + gi];
-                i0 = g.ids[C0][gi];
-                i1 = g.ids[C1][gi];
-                i2 = g.ids[C2][gi];
-            } else {
-                f0[r] = T(0);
-                f1[r] = T(0);
-                f2[r] = T(0);
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                int gy = ry0 + w * B + r;
+                bool in = inx;
+                if (gy < 0 || gy >= g.ny) {
+                    if (g.pery) gy = ((gy % g.ny) + g.ny) % g.ny;
+                    else in = false;
+                }
+                uint32_t i0 = kNullId, i1 = kNullId, i2 = kNullId;
+                if (in) {
+                    const int64_t gi = (int64_t)gy * g.nx + gx;
+                    f0[j][r] = S[gi];
+                    f1[j][r] = S[g.ncell + gi];
+                    f2[j][r] = S[2 * g.ncell + gi];
+                    i0 = g.ids[C0][gi];
+                    i1 = g.ids[C1][gi];
+                    i2 = g.ids[C2][gi];
+                } else {
+                    f0[j][r] = T(0);
+                    f1[j][r] = T(0);
+                    f2[j][r] = T(0);
+                }
+                m0p[j][r >> 2] |= i0 << (8 * (r & 3));
+                m1p[j][r >> 2] |= i1 << (8 * (r & 3));
+                m2p[j][r >> 2] |= i2 << (8 * (r & 3));
             }
-            m0p[r >> 2] |= i0 << (8 * (r & 3));
-            m1p[r >> 2] |= i1 << (8 * (r & 3));
-            m2p[r >> 2] |= i2 << (8 * (r & 3));
         }
     }
     const bool stile = tile == g.stile;
@@ -350,80 +365,101 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
     }
     __syncthreads();
 
-#define CF_ID(p, r) ((p[(r) >> 2] >> (8 * ((r) & 3))) & 255u)
+#define CF_ID(p, j, r) ((p[j][(r) >> 2] >> (8 * ((r) & 3))) & 255u)
     // CREG: each cell's (a, b) pairs are constant over the launch and can be
     // held in registers instead of being looked up in LDS every step.
-    Pair<T> k0[CREG ? B : 1], k1[CREG ? B : 1], k2[CREG ? B : 1];
+    constexpr int KJ = CREG ? CX : 1, KB = CREG ? B : 1;
+    Pair<T> k0[KJ][KB], k1[KJ][KB], k2[KJ][KB];
     if constexpr (CREG) {
 #pragma unroll
-        for (int r = 0; r < B; ++r) {
-            k0[r] = L[0][CF_ID(m0p, r)];
-            k1[r] = L[1][CF_ID(m1p, r)];
-            k2[r] = L[2][CF_ID(m2p, r)];
-        }
+        for (int j = 0; j < CX; ++j)
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                k0[j % KJ][r % KB] = L[0][CF_ID(m0p, j, r)];
+                k1[j % KJ][r % KB] = L[1][CF_ID(m1p, j, r)];
+                k2[j % KJ][r % KB] = L[2][CF_ID(m2p, j, r)];
+            }
     }
-#define CF_K(s, r) (CREG ? k##s[(CREG ? (r) : 0)] : L[s][CF_ID(m##s##p, r)])
+#define CF_K(s, j, r) (CREG ? k##s[(j) % KJ][(r) % KB] : L[s][CF_ID(m##s##p, j, r)])
     for (int step = 0; step < ksteps; ++step) {
         // ---- H half: needs the E row above the wave's band ----
-        xe[w][lane] = f0[0];
+        T e_above[CX];
+#pragma unroll
+        for (int j = 0; j < CX; ++j) xe[w][j][lane] = f0[j][0];
         __syncthreads();
-        const T e_above = w + 1 < RBW ? xe[w + 1][lane] : f0[B - 1];
+#pragma unroll
+        for (int j = 0; j < CX; ++j) e_above[j] = w + 1 < RBW ? xe[w + 1][j][lane] : f0[j][B - 1];
         if (POL == CF_POL_TM) {
 #pragma unroll
-            for (int r = 0; r < B; ++r) {
-                const T ez = f0[r];
-                const T ezr = from_next(ez);
-                const T ezu = r + 1 < B ? f0[r + 1] : e_above;
-                const Pair<T> cx = CF_K(1, r), cy = CF_K(2, r);
-                f1[r] = yee_sub(cx.a, f1[r], cx.b, ezu - ez);
-                f2[r] = yee_sub(cy.a, f2[r], cy.b, ez - ezr);
-            }
+            for (int r = 0; r < B; ++r)
+#pragma unroll
+                for (int j = 0; j < CX; ++j) {
+                    const T ez = f0[j][r];
+                    const T ezr = j + 1 < CX ? f0[(j + 1) % CX][r] : from_next(f0[0][r]);
+                    const T ezu = r + 1 < B ? f0[j][(r + 1) % B] : e_above[j];
+                    const Pair<T> cx = CF_K(1, j, r), cy = CF_K(2, j, r);
+                    f1[j][r] = yee_sub(cx.a, f1[j][r], cx.b, ezu - ez);
+                    f2[j][r] = yee_sub(cy.a, f2[j][r], cy.b, ez - ezr);
+                }
         } else {
 #pragma unroll
-            for (int r = 0; r < B; ++r) {
-                const T ex = f0[r], ey = f1[r];
-                const T eyr = from_next(ey);
-                const T exu = r + 1 < B ? f0[r + 1] : e_above;
-                const Pair<T> cz = CF_K(2, r);
-                f2[r] = yee_sub(cz.a, f2[r], cz.b, (eyr - ey) - (exu - ex));
-            }
+            for (int r = 0; r < B; ++r)
+#pragma unroll
+                for (int j = 0; j < CX; ++j) {
+                    const T ex = f0[j][r], ey = f1[j][r];
+                    const T eyr = j + 1 < CX ? f1[(j + 1) % CX][r] : from_next(f1[0][r]);
+                    const T exu = r + 1 < B ? f0[j][(r + 1) % B] : e_above[j];
+                    const Pair<T> cz = CF_K(2, j, r);
+                    f2[j][r] = yee_sub(cz.a, f2[j][r], cz.b, (eyr - ey) - (exu - ex));
+                }
         }
         // ---- E half: needs the H row below the wave's band ----
-        xh[w][lane] = POL == CF_POL_TM ? f1[B - 1] : f2[B - 1];
+        T h_below[CX];
+#pragma unroll
+        for (int j = 0; j < CX; ++j) xh[w][j][lane] = POL == CF_POL_TM ? f1[j][B - 1] : f2[j][B - 1];
         __syncthreads();
-        const T h_below = w > 0 ? xh[w - 1][lane] : (POL == CF_POL_TM ? f1[0] : f2[0]);
+#pragma unroll
+        for (int j = 0; j < CX; ++j)
+            h_below[j] = w > 0 ? xh[w - 1][j][lane] : (POL == CF_POL_TM ? f1[j][0] : f2[j][0]);
         if (POL == CF_POL_TM) {
 #pragma unroll
-            for (int r = 0; r < B; ++r) {
-                const T hx = f1[r], hy = f2[r];
-                const T hyl = from_prev(hy);
-                const T hxd = r > 0 ? f1[r - 1] : h_below;
-                const T curl = (hy - hyl) - (hx - hxd);
-                const Pair<T> cz = CF_K(0, r);
-                f0[r] = yee_add(cz.a, f0[r], cz.b, curl);
-            }
+            for (int r = 0; r < B; ++r)
+#pragma unroll
+                for (int j = 0; j < CX; ++j) {
+                    const T hx = f1[j][r], hy = f2[j][r];
+                    const T hyl = j > 0 ? f2[(j + CX - 1) % CX][r] : from_prev(f2[CX - 1][r]);
+                    const T hxd = r > 0 ? f1[j][(r + B - 1) % B] : h_below[j];
+                    const T curl = (hy - hyl) - (hx - hxd);
+                    const Pair<T> cz = CF_K(0, j, r);
+                    f0[j][r] = yee_add(cz.a, f0[j][r], cz.b, curl);
+                }
         } else {
 #pragma unroll
-            for (int r = 0; r < B; ++r) {
-                const T hz = f2[r];
-                const T hzl = from_prev(hz);
-                const T hzd = r > 0 ? f2[r - 1] : h_below;
-                const Pair<T> cx = CF_K(0, r), cy = CF_K(1, r);
-                f0[r] = yee_add(cx.a, f0[r], cx.b, hz - hzd);
-                f1[r] = yee_sub(cy.a, f1[r], cy.b, hz - hzl);
-            }
+            for (int r = 0; r < B; ++r)
+#pragma unroll
+                for (int j = 0; j < CX; ++j) {
+                    const T hz = f2[j][r];
+                    const T hzl = j > 0 ? f2[(j + CX - 1) % CX][r] : from_prev(f2[CX - 1][r]);
+                    const T hzd = r > 0 ? f2[j][(r + B - 1) % B] : h_below[j];
+                    const Pair<T> cx = CF_K(0, j, r), cy = CF_K(1, j, r);
+                    f0[j][r] = yee_add(cx.a, f0[j][r], cx.b, hz - hzd);
+                    f1[j][r] = yee_sub(cy.a, f1[j][r], cy.b, hz - hzl);
+                }
         }
         if (stile) {
             const int ms = d.meas_slot;
 #pragma unroll
             for (int r = 0; r < B; ++r)
-                stage[(w * B + r) * 64 + lane] = ms == 0 ? f0[r] : (ms == 1 ? f1[r] : f2[r]);
+#pragma unroll
+                for (int j = 0; j < CX; ++j)
+                    stage[(w * B + r) * RW + j * 64 + lane] = ms == 0 ? f0[j][r] : (ms == 1 ? f1[j][r] : f2[j][r]);
             __syncthreads();
             const double s = block_surface_sum(
                 d, t,
                 [&](int32_t idx) {
                     const int gx = idx % g.nx, gy = idx / g.nx;
-                    return (double)stage[(gy - ry0) * 64 + (gx - rx0)];
+                    const int cx = gx - rx0;
+                    return (double)stage[(gy - ry0) * RW + (cx % CX) * 64 + cx / CX];
                 },
                 red);
             if (tid == 0) {
@@ -442,17 +478,20 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
         acc[1] = acc_c;
     }
     T* D = dst + d.field_off;
-    const int gx = rx0 + lane;
-    if (lane >= KH && lane < KH + TX && gx >= 0 && gx < g.nx) {
+#pragma unroll
+    for (int j = 0; j < CX; ++j) {
+        const int cx = lane * CX + j;
+        const int gx = rx0 + cx;
+        if (cx < KH || cx >= KH + TX || gx < 0 || gx >= g.nx) continue;
 #pragma unroll
         for (int r = 0; r < B; ++r) {
             const int ry = w * B + r;
             const int gy = ry0 + ry;
             if (ry < KH || ry >= KH + TY || gy < 0 || gy >= g.ny) continue;
             const int64_t gi = (int64_t)gy * g.nx + gx;
-            D[gi] = f0[r];
-            D[g.ncell + gi] = f1[r];
-            D[2 * g.ncell + gi] = f2[r];
+            D[gi] = f0[j][r];
+            D[g.ncell + gi] = f1[j][r];
+            D[2 * g.ncell + gi] = f2[j][r];
         }
     }
 }
@@ -464,16 +503,21 @@ inline dim3 grid2d(const Grid2D& g, int nslots) {
 
 }  // namespace
 
-// Register-blocking variants: W waves of B rows and halo KH give a tile of
-// (64 - 2 KH) x (W B - 2 KH) cells and at most KH steps per launch.  All
-// variants evaluate the same arithmetic; the autotuner picks among them.
+// Register-blocking variants: W waves of B rows, CX columns per lane and
+// halo KH give a tile of (64 CX - 2 KH) x (W B - 2 KH) cells and at most KH
+// steps per launch.  All variants evaluate the same arithmetic; the
+// autotuner picks among them.  Indices are part of the ABI (tile_variant).
 struct RbVariant {
     int W, B, KH;
     bool creg;   // coefficients held in registers over the launch
+    int CX;
 };
-constexpr RbVariant kRbF32[] = {{8, 8, 8, false}, {8, 8, 6, false}, {8, 8, 4, false}, {16, 4, 8, false},
-                                {8, 8, 8, true},  {16, 4, 8, true},  {8, 8, 6, true}};
-constexpr RbVariant kRbF64[] = {{8, 4, 4, false}, {8, 4, 2, false}, {16, 4, 4, false}, {16, 4, 4, true}};
+constexpr RbVariant kRbF32[] = {{8, 8, 8, false, 1},  {8, 8, 6, false, 1},  {8, 8, 4, false, 1},
+                                {16, 4, 8, false, 1}, {8, 8, 8, true, 1},   {16, 4, 8, true, 1},
+                                {8, 8, 6, true, 1},   {16, 4, 8, false, 2}, {8, 8, 8, false, 2},
+                                {16, 4, 8, true, 2},  {8, 8, 8, true, 2}};
+constexpr RbVariant kRbF64[] = {{8, 4, 4, false, 1}, {8, 4, 2, false, 1}, {16, 4, 4, false, 1},
+                                {16, 4, 4, true, 1}, {8, 4, 4, false, 2}};
 
 template <typename T>
 static const RbVariant* rb_table(int* n) {
@@ -489,7 +533,7 @@ template <typename T>
 int tb_variants(TBShape* out, int max) {
     int n;
     const RbVariant* v = rb_table<T>(&n);
-    for (int i = 0; i < n && i < max; ++i) out[i] = TBShape{64 - 2 * v[i].KH, v[i].W * v[i].B - 2 * v[i].KH, v[i].KH};
+    for (int i = 0; i < n && i < max; ++i) out[i] = TBShape{64 * v[i].CX - 2 * v[i].KH, v[i].W * v[i].B - 2 * v[i].KH, v[i].KH};
     return n;
 }
 template int tb_variants<float>(TBShape*, int);
@@ -544,16 +588,24 @@ hipError_t launch_surface(const T* fields, const ChanDev* ch, const int* slots, 
     return hipGetLastError();
 }
 
-template <typename T, int W, int B, int KH, bool CREG>
+// waves per SIMD the register budget is sized for: the field state per lane
+// is 3 B CX values of sizeof(T) bytes (plus as many coefficient pairs with
+// creg)
+constexpr int rb_wpe(int B, bool creg, int CX, int tsize) {
+    return B * CX * (tsize / 4) >= 16 ? 2 : (creg ? 3 : 4);
+}
+
+template <typename T, int W, int B, int KH, bool CREG, int CX>
 static void rb_launch(int pol, int nwork, hipStream_t s, const ChanDev* ch, const WorkItem* work,
                       const InstDev* inst, int kmax, int m, int parity) {
+    constexpr int WPE = rb_wpe(B, CREG, CX, (int)sizeof(T));
     dim3 grid(nwork), block(64 * W);
     if (pol == CF_POL_TM)
-        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TM, W, B, KH, CREG>), grid, block, 0, s, ch, work, inst, kmax, m,
-                           parity);
+        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TM, W, B, KH, CREG, CX, WPE>), grid, block, 0, s, ch, work, inst, kmax,
+                           m, parity);
     else
-        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TE, W, B, KH, CREG>), grid, block, 0, s, ch, work, inst, kmax, m,
-                           parity);
+        hipLaunchKernelGGL((k_rb2d<T, CF_POL_TE, W, B, KH, CREG, CX, WPE>), grid, block, 0, s, ch, work, inst, kmax,
+                           m, parity);
 }
 
 template <typename T>
@@ -564,23 +616,28 @@ hipError_t launch_tb2d(int variant, int pol, const ChanDev* ch, const WorkItem* 
     const RbVariant* v = rb_table<T>(&n);
     if (variant < 0 || variant >= n) return hipErrorInvalidValue;
     if (kmax < 1 || kmax > v[variant].KH) return hipErrorInvalidValue;
-#define CF_RB(W, B, KH, CR) rb_launch<T, W, B, KH, CR>(pol, nwork, s, ch, work, inst, kmax, m, parity)
+#define CF_RB(W, B, KH, CR, CX) rb_launch<T, W, B, KH, CR, CX>(pol, nwork, s, ch, work, inst, kmax, m, parity)
     if constexpr (sizeof(T) == 4) {
         switch (variant) {
-            case 0: CF_RB(8, 8, 8, false); break;
-            case 1: CF_RB(8, 8, 6, false); break;
-            case 2: CF_RB(8, 8, 4, false); break;
-            case 3: CF_RB(16, 4, 8, false); break;
-            case 4: CF_RB(8, 8, 8, true); break;
-            case 5: CF_RB(16, 4, 8, true); break;
-            default: CF_RB(8, 8, 6, true); break;
+            case 0: CF_RB(8, 8, 8, false, 1); break;
+            case 1: CF_RB(8, 8, 6, false, 1); break;
+            case 2: CF_RB(8, 8, 4, false, 1); break;
+            case 3: CF_RB(16, 4, 8, false, 1); break;
+            case 4: CF_RB(8, 8, 8, true, 1); break;
+            case 5: CF_RB(16, 4, 8, true, 1); break;
+            case 6: CF_RB(8, 8, 6, true, 1); break;
+            case 7: CF_RB(16, 4, 8, false, 2); break;
+            case 8: CF_RB(8, 8, 8, false, 2); break;
+            case 9: CF_RB(16, 4, 8, true, 2); break;
+            default: CF_RB(8, 8, 8, true, 2); break;
         }
     } else {
         switch (variant) {
-            case 0: CF_RB(8, 4, 4, false); break;
-            case 1: CF_RB(8, 4, 2, false); break;
-            case 2: CF_RB(16, 4, 4, false); break;
-            default: CF_RB(16, 4, 4, true); break;
+            case 0: CF_RB(8, 4, 4, false, 1); break;
+            case 1: CF_RB(8, 4, 2, false, 1); break;
+            case 2: CF_RB(16, 4, 4, false, 1); break;
+            case 3: CF_RB(16, 4, 4, true, 1); break;
+            default: CF_RB(8, 4, 4, false, 2); break;
         }
     }
 #undef CF_RB

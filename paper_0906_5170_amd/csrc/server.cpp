@@ -1,0 +1,790 @@
+// Serving: continuous batching of force-solve requests on one GPU.
+//
+// A scheduler thread owns a device arena (the HBM budget).  Requests wait in
+// arrival order; at every tick boundary each queued request whose memory fits
+// is admitted (later requests may pass an earlier one that does not fit yet):
+// its tables are uploaded, its fields zeroed and kicked, and it joins the
+// resident set with its own time origin on the scheduler clock.  A tick
+// advances every resident request by K time steps:
+//   - all 2D requests whose stress surface fits a fused tile share one fused
+//     launch per polarization (each instance reads its own buffers, tables
+//     and K(t) and starts at its own clock step);
+//   - other requests (3D, or surfaces wider than a tile) take the split
+//     half-step kernels, one request after another, in channel waves that
+//     bound their memory.
+// When a request has run all its steps its accumulators are copied back,
+// its memory returns to the arena and waiting requests can enter.  Every
+// request's arithmetic is independent of its co-residents, so a result is
+// bitwise the same alone and in the mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/casimir_fdtd.h"
+#include "arena.hpp"
+#include "device.hpp"
+#include "plan.hpp"
+#include "solver.hpp"
+
+struct cf_problem {
+    cf::Problem p;
+};
+
+namespace {
+
+using cfi::fail;
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+enum { ST_QUEUED = 0, ST_RUNNING = 1, ST_DONE = 2, ST_FAILED = 3, ST_CANCELLED = 4 };
+
+struct Req {
+    uint64_t ticket = 0;
+    const cf::Problem* prob = nullptr;
+    cf_opts opts{};
+    std::vector<cf::Channel> chans;
+    cfi::Staged st;
+    bool fused = false;
+    int variant = -1;                 // fused variant of this request
+    int C = 0;
+    size_t bytes = 0, off = 0;
+    size_t o_ids, o_lut, o_ktab, o_pml, o_ch, o_slots, o_gidx, o_gw, o_uidx, o_uoff, o_usamp, o_uw, o_basis,
+        o_acc, o_fa, o_fb, o_psi;
+    std::vector<uint8_t> ids;
+    std::vector<uint8_t> lut;     // field-precision bytes
+    std::vector<double> ktab, pml;
+    int wave = 0;
+    long long start = 0;          // clock step of the current wave's step 0
+    int state = ST_QUEUED;
+    cf_status status = CF_OK;
+    std::string err;
+    std::vector<double> acc;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    bool cancel = false;
+};
+
+}  // namespace
+
+struct cf_server {
+    std::mutex mu;
+    std::condition_variable cv;       // new work / completions
+    std::thread worker;
+    bool stop = false;
+    int device = 0;
+    int precision = CF_FP32;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char* arena_base = nullptr;
+    bool own_arena = false;
+    cfi::Arena arena;
+    std::deque<std::shared_ptr<Req>> queue;
+    std::vector<std::shared_ptr<Req>> active;
+    std::map<uint64_t, std::shared_ptr<Req>> all;
+    uint64_t next_ticket = 1;
+    long long clock = 0;
+    int parity = 0;
+    int kh = 8;                       // steps per tick
+    std::vector<int> prefer;          // fused variants in order of preference (same steps per launch)
+    // fused group tables (server-owned device memory)
+    char* group = nullptr;
+    size_t group_bytes = 0, g_ch = 0, g_inst = 0, g_work = 0;
+    size_t cap_ch = 0, cap_inst = 0, cap_work = 0;
+    bool membership_changed = true;
+    struct Launch {
+        int variant, pol;
+        size_t off;                   // first work item in the concatenated lists
+        int n;
+    };
+    std::vector<Launch> launches;     // fused launches of one tick
+    std::deque<std::vector<cf::ChanDev>> keep_ch;
+    std::deque<std::vector<cf::InstDev>> keep_inst;
+    std::deque<std::vector<cf::WorkItem>> keep_work;
+    // statistics
+    uint64_t n_submitted = 0, n_completed = 0, n_failed = 0, n_cancelled = 0;
+    double busy_s = 0;
+    std::string thread_error;
+};
+
+namespace {
+
+// Bytes of one request region and the offsets inside it.
+void layout_request(const cf_server* S, Req& r) {
+    const cf::Problem& p = *r.prob;
+    const size_t fsz = S->precision == CF_FP64 ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = cfi::align_up(off + bytes, 256);
+        return at;
+    };
+    const cfi::Staged& st = r.st;
+    r.o_ids = take((size_t)cf::kNumComp * p.ncell);
+    r.o_lut = take(2 * cf::kNumComp * 256 * 2 * fsz);
+    r.o_ktab = take((size_t)r.opts.n_steps * 8);
+    r.o_pml = take((size_t)4 * p.nz * 8);
+    r.o_ch = take(st.dev.size() * sizeof(cf::ChanDev));
+    r.o_slots = take(st.slot_lists.size() * sizeof(int) + 4);
+    r.o_gidx = take(st.gidx.size() * 4 + 4);
+    r.o_gw = take(st.gw.size() * 8 + 8);
+    r.o_uidx = take(st.uidx.size() * 4 + 4);
+    r.o_uoff = take(st.uoff.size() * 4 + 4);
+    r.o_usamp = take(st.usamp.size() * 4 + 4);
+    r.o_uw = take(st.uw.size() * 8 + 8);
+    r.o_basis = take(st.basis.size() * 8 + 8);
+    r.o_acc = take((size_t)r.C * 2 * 8);
+    const size_t block = (size_t)st.resident * st.ncomp * p.ncell * fsz;
+    r.o_fa = take(block);
+    r.o_fb = r.fused ? take(block) : off;
+    r.o_psi = st.psi_comp > 0 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
+    r.bytes = off;
+}
+
+// Stage a request: channels, tables; decide fused vs split; pick the channel
+// wave size so the request fits the budget.  Returns "" or an error.
+std::string prepare(cf_server* S, Req& r) {
+    const cf::Problem& p = *r.prob;
+    r.chans = cf::channel_table(p, r.opts.pol);
+    r.C = (int)r.chans.size();
+    cf_opts o = r.opts;
+    o.n_subset = 0;
+    o.channel_subset = nullptr;
+    o.path = CF_PATH_BATCHED;
+    o.flags &= ~(CF_FLAG_KEEP_GAMMA | CF_FLAG_TIME_STENCIL);
+    o.max_resident = 0;
+    cfi::stage(p, o, r.chans, r.st);
+    r.variant = -1;
+    if (p.grid.ndim == 2)
+        for (int v : S->prefer)
+            if (v < (int)r.st.plans.size() && r.st.plans[v].ok && r.st.shapes[v].kh == S->kh) {
+                r.variant = v;
+                break;
+            }
+    r.fused = r.variant >= 0;
+    int R = r.opts.max_resident > 0 ? std::min(r.opts.max_resident, r.C) : r.C;
+    if (r.fused) R = r.C;   // fused requests keep every channel resident
+    for (;;) {
+        if (R != r.st.resident) {
+            o.max_resident = R;
+            r.st = cfi::Staged();
+            cfi::stage(p, o, r.chans, r.st);
+        }
+        layout_request(S, r);
+        if (r.bytes <= S->arena.size() || R == 1 || r.fused) break;
+        R = std::max(1, R / 2);
+    }
+    if (r.bytes > S->arena.size()) return "request larger than the server's memory budget";
+    // host copies of the per-request tables
+    r.ids.resize((size_t)cf::kNumComp * p.ncell);
+    for (int c = 0; c < cf::kNumComp; ++c)
+        std::memcpy(r.ids.data() + (size_t)c * p.ncell, p.ids[c].data(), p.ncell);
+    std::vector<double> l64 = cf::coefficient_lut(p, r.opts.sigma, r.opts.courant);
+    if (S->precision == CF_FP64) {
+        r.lut.resize(l64.size() * 8);
+        std::memcpy(r.lut.data(), l64.data(), r.lut.size());
+    } else {
+        std::vector<float> l32(l64.begin(), l64.end());
+        r.lut.resize(l32.size() * 4);
+        std::memcpy(r.lut.data(), l32.data(), r.lut.size());
+    }
+    r.ktab.resize(r.opts.n_steps);
+    cf::kernel_table(r.opts.kernel, r.opts.sigma, r.opts.courant / p.grid.res, r.opts.n_steps, r.ktab.data());
+    std::vector<double> bh, ch, be, ce;
+    cf::pml_tables(p, r.opts.courant, bh, ch, be, ce);
+    r.pml.clear();
+    for (auto* v : {&bh, &ch, &be, &ce}) r.pml.insert(r.pml.end(), v->begin(), v->end());
+    return "";
+}
+
+template <typename T>
+struct Dev {
+    // device views of a request region
+    static cf::SurfTables tabs(char* b, const Req& r) {
+        cf::SurfTables t;
+        t.gidx = reinterpret_cast<const int32_t*>(b + r.o_gidx);
+        t.gw = reinterpret_cast<const double*>(b + r.o_gw);
+        t.uidx = reinterpret_cast<const int32_t*>(b + r.o_uidx);
+        t.uoff = reinterpret_cast<const int32_t*>(b + r.o_uoff);
+        t.usamp = reinterpret_cast<const int32_t*>(b + r.o_usamp);
+        t.uw = reinterpret_cast<const double*>(b + r.o_uw);
+        t.basis = reinterpret_cast<const double*>(b + r.o_basis);
+        return t;
+    }
+    static cf::Grid2D grid2(char* b, const Req& r) {
+        const cf::Problem& p = *r.prob;
+        cf::Grid2D g{};
+        g.nx = p.nx;
+        g.ny = p.ny;
+        g.ncell = p.ncell;
+        g.perx = p.grid.bc[0] == CF_BC_PERIODIC;
+        g.pery = p.grid.bc[1] == CF_BC_PERIODIC;
+        for (int c = 0; c < cf::kNumComp; ++c)
+            g.ids[c] = reinterpret_cast<const uint8_t*>(b + r.o_ids) + (size_t)c * p.ncell;
+        return g;
+    }
+    static cf::Grid3D grid3(char* b, const Req& r) {
+        const cf::Problem& p = *r.prob;
+        cf::Grid3D g{};
+        g.nx = p.nx;
+        g.ny = p.ny;
+        g.nz = p.nz;
+        g.ncell = p.ncell;
+        for (int a = 0; a < 3; ++a) g.per[a] = p.grid.bc[a] == CF_BC_PERIODIC;
+        for (int c = 0; c < cf::kNumComp; ++c)
+            g.ids[c] = reinterpret_cast<const uint8_t*>(b + r.o_ids) + (size_t)c * p.ncell;
+        g.pml = p.grid.ndim == 3 && p.grid.bc[2] == CF_BC_PML ? p.grid.pml_cells[2] : 0;
+        g.psi_comp = r.st.psi_comp;
+        const double* pm = reinterpret_cast<const double*>(b + r.o_pml);
+        g.pml_bh = pm;
+        g.pml_ch = pm + p.nz;
+        g.pml_be = pm + 2 * p.nz;
+        g.pml_ce = pm + 3 * p.nz;
+        return g;
+    }
+};
+
+// Zero, kick and start one wave of a request in buffer `f`.
+template <typename T>
+hipError_t start_wave(cf_server* S, Req& r, T* f) {
+    char* b = S->arena_base + r.off;
+    hipStream_t s = S->stream;
+    const cf::Problem& p = *r.prob;
+    const cfi::Wave& w = r.st.waves[r.wave];
+    const cf::ChanDev* dch = reinterpret_cast<const cf::ChanDev*>(b + r.o_ch);
+    const int* dl = reinterpret_cast<const int*>(b + r.o_slots);
+    const T* lut = reinterpret_cast<const T*>(b + r.o_lut);
+    const cf::SurfTables t = Dev<T>::tabs(b, r);
+    const size_t fbytes = (size_t)r.st.resident * r.st.ncomp * p.ncell * sizeof(T);
+    hipError_t e;
+    if ((e = hipMemsetAsync(f, 0, fbytes, s)) != hipSuccess) return e;
+    if (r.st.psi_comp > 0 &&
+        (e = hipMemsetAsync(b + r.o_psi, 0, (size_t)r.st.resident * 4 * r.st.psi_comp * sizeof(T), s)) != hipSuccess)
+        return e;
+    if ((e = cf::launch_kick<T>(f, dch, dl + w.all_off, w.n_all, r.st.max_uniq, t, s)) != hipSuccess) return e;
+    if (p.grid.ndim == 3) {
+        const cf::Grid3D g = Dev<T>::grid3(b, r);
+        T* psi = r.st.psi_comp > 0 ? reinterpret_cast<T*>(b + r.o_psi) : nullptr;
+        if ((e = cf::launch_h3d<T>(1, f, psi, dch, dl + w.d3_off, w.n_3d, g, lut, s)) != hipSuccess) return e;
+        return cf::launch_e3d<T>(1, f, psi, dch, dl + w.d3_off, w.n_3d, g, lut, s);
+    }
+    const cf::Grid2D g = Dev<T>::grid2(b, r);
+    if ((e = cf::launch_h2d<T>(CF_POL_TM, 1, f, dch, dl + w.tm_off, w.n_tm, g, lut, s)) != hipSuccess) return e;
+    if ((e = cf::launch_h2d<T>(CF_POL_TE, 1, f, dch, dl + w.te_off, w.n_te, g, lut, s)) != hipSuccess) return e;
+    if ((e = cf::launch_e2d<T>(CF_POL_TM, 1, f, dch, dl + w.tm_off, w.n_tm, g, lut, s)) != hipSuccess) return e;
+    return cf::launch_e2d<T>(CF_POL_TE, 1, f, dch, dl + w.te_off, w.n_te, g, lut, s);
+}
+
+template <typename T>
+hipError_t admit(cf_server* S, Req& r) {
+    char* b = S->arena_base + r.off;
+    hipStream_t s = S->stream;
+    const cfi::Staged& st = r.st;
+    auto up = [&](size_t o, const void* src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(b + o, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    hipError_t e;
+#define UP(o, p_, n_) \
+    if ((e = up(o, p_, n_)) != hipSuccess) return e
+    UP(r.o_ids, r.ids.data(), r.ids.size());
+    UP(r.o_lut, r.lut.data(), r.lut.size());
+    UP(r.o_ktab, r.ktab.data(), r.ktab.size() * 8);
+    UP(r.o_pml, r.pml.data(), r.pml.size() * 8);
+    UP(r.o_ch, st.dev.data(), st.dev.size() * sizeof(cf::ChanDev));
+    UP(r.o_slots, st.slot_lists.data(), st.slot_lists.size() * sizeof(int));
+    UP(r.o_gidx, st.gidx.data(), st.gidx.size() * 4);
+    UP(r.o_gw, st.gw.data(), st.gw.size() * 8);
+    UP(r.o_uidx, st.uidx.data(), st.uidx.size() * 4);
+    UP(r.o_uoff, st.uoff.data(), st.uoff.size() * 4);
+    UP(r.o_usamp, st.usamp.data(), st.usamp.size() * 4);
+    UP(r.o_uw, st.uw.data(), st.uw.size() * 8);
+    UP(r.o_basis, st.basis.data(), st.basis.size() * 8);
+#undef UP
+    if ((e = hipMemsetAsync(b + r.o_acc, 0, (size_t)r.C * 2 * 8, s)) != hipSuccess) return e;
+    r.wave = 0;
+    r.start = S->clock;
+    // a fused request is kicked into the buffer the next fused launch reads
+    T* f = reinterpret_cast<T*>(b + (r.fused && S->parity ? r.o_fb : r.o_fa));
+    return start_wave<T>(S, r, f);
+}
+
+// Rebuild the fused group: descriptors and instances of every fused request
+// and one work list per (variant, polarization) in use.
+template <typename T>
+hipError_t rebuild_group(cf_server* S) {
+    std::vector<cf::ChanDev> ch;
+    std::vector<cf::InstDev> inst;
+    std::map<std::pair<int, int>, std::pair<std::vector<int>, std::vector<int>>> lists;   // (v, pol) -> slots, tiles
+    for (auto& rp : S->active) {
+        Req& r = *rp;
+        if (!r.fused) continue;
+        char* b = S->arena_base + r.off;
+        const cf::Problem& p = *r.prob;
+        const cfi::TBPlan& pl = r.st.plans[r.variant];
+        const int ii = (int)inst.size();
+        cf::InstDev I{};
+        I.fa = b + r.o_fa;
+        I.fb = b + r.o_fb;
+        I.acc = reinterpret_cast<double*>(b + r.o_acc);
+        I.nx = p.nx;
+        I.ny = p.ny;
+        I.ncell = p.ncell;
+        const cf::Grid2D g = Dev<T>::grid2(b, r);
+        I.perx = g.perx;
+        I.pery = g.pery;
+        for (int c = 0; c < cf::kNumComp; ++c) I.ids[c] = g.ids[c];
+        I.lut = b + r.o_lut;
+        I.base_x = pl.base_x;
+        I.base_y = pl.base_y;
+        I.ntx = pl.ntx;
+        I.nty = pl.nty;
+        I.stile = pl.stile;
+        I.start = (int)r.start;
+        I.nsteps = r.opts.n_steps;
+        I.dt = r.opts.courant / p.grid.res;
+        I.dA = std::pow(1.0 / p.grid.res, p.grid.ndim - 1);
+        I.ktab = reinterpret_cast<const double*>(b + r.o_ktab);
+        I.gamma = nullptr;
+        I.gamma_stride = r.C;
+        I.t = Dev<T>::tabs(b, r);
+        inst.push_back(I);
+        for (int c = 0; c < r.C; ++c) {
+            cf::ChanDev d = r.st.dev[c];
+            d.inst = ii;
+            const int slot = (int)ch.size();
+            ch.push_back(d);
+            auto& l = lists[{r.variant, r.chans[c].pol}];
+            l.first.push_back(slot);
+            l.second.push_back(pl.ntx * pl.nty);
+        }
+    }
+    std::vector<cf::WorkItem> work;
+    std::vector<cf_server::Launch> launches;
+    for (auto& kv : lists) {
+        std::vector<cf::WorkItem> w = cfi::make_work(kv.second.first, kv.second.second);
+        launches.push_back({kv.first.first, kv.first.second, work.size(), (int)w.size()});
+        work.insert(work.end(), w.begin(), w.end());
+    }
+    if (ch.size() > S->cap_ch || inst.size() > S->cap_inst || work.size() > S->cap_work) return hipErrorOutOfMemory;
+    hipStream_t s = S->stream;
+    S->keep_ch.push_back(std::move(ch));
+    S->keep_inst.push_back(std::move(inst));
+    S->keep_work.push_back(std::move(work));
+    const auto& kc = S->keep_ch.back();
+    const auto& ki = S->keep_inst.back();
+    const auto& kw = S->keep_work.back();
+    hipError_t e;
+    if (!kc.empty() && (e = hipMemcpyAsync(S->group + S->g_ch, kc.data(), kc.size() * sizeof(cf::ChanDev),
+                                           hipMemcpyHostToDevice, s)) != hipSuccess)
+        return e;
+    if (!ki.empty() && (e = hipMemcpyAsync(S->group + S->g_inst, ki.data(), ki.size() * sizeof(cf::InstDev),
+                                           hipMemcpyHostToDevice, s)) != hipSuccess)
+        return e;
+    if (!kw.empty() && (e = hipMemcpyAsync(S->group + S->g_work, kw.data(), kw.size() * sizeof(cf::WorkItem),
+                                           hipMemcpyHostToDevice, s)) != hipSuccess)
+        return e;
+    S->launches = std::move(launches);
+    S->membership_changed = false;
+    return hipSuccess;
+}
+
+// One tick: K steps of every resident request.
+template <typename T>
+hipError_t tick(cf_server* S) {
+    hipStream_t s = S->stream;
+    hipError_t e;
+    bool any_fused = false;
+    for (auto& rp : S->active) any_fused = any_fused || rp->fused;
+    if (any_fused) {
+        if (S->membership_changed && (e = rebuild_group<T>(S)) != hipSuccess) return e;
+        const cf::ChanDev* gch = reinterpret_cast<const cf::ChanDev*>(S->group + S->g_ch);
+        const cf::InstDev* gin = reinterpret_cast<const cf::InstDev*>(S->group + S->g_inst);
+        const cf::WorkItem* gw = reinterpret_cast<const cf::WorkItem*>(S->group + S->g_work);
+        for (const auto& l : S->launches)
+            if ((e = cf::launch_tb2d<T>(l.variant, l.pol, gch, gw + l.off, l.n, gin, S->kh, (int)S->clock,
+                                        S->parity, s)) != hipSuccess)
+                return e;
+    }
+    for (auto& rp : S->active) {
+        Req& r = *rp;
+        if (r.fused) continue;
+        char* b = S->arena_base + r.off;
+        const cf::Problem& p = *r.prob;
+        const cfi::Wave& w = r.st.waves[r.wave];
+        const cf::ChanDev* dch = reinterpret_cast<const cf::ChanDev*>(b + r.o_ch);
+        const int* dl = reinterpret_cast<const int*>(b + r.o_slots);
+        const T* lut = reinterpret_cast<const T*>(b + r.o_lut);
+        const cf::SurfTables t = Dev<T>::tabs(b, r);
+        T* f = reinterpret_cast<T*>(b + r.o_fa);
+        T* psi = r.st.psi_comp > 0 ? reinterpret_cast<T*>(b + r.o_psi) : nullptr;
+        const double* kt = reinterpret_cast<const double*>(b + r.o_ktab);
+        double* acc = reinterpret_cast<double*>(b + r.o_acc);
+        const double dt = r.opts.courant / p.grid.res, dA = std::pow(1.0 / p.grid.res, p.grid.ndim - 1);
+        for (int k = 0; k < S->kh; ++k) {
+            const long long m = S->clock + k - r.start;
+            if (m < 0 || m >= r.opts.n_steps) continue;
+            if (p.grid.ndim == 3) {
+                const cf::Grid3D g = Dev<T>::grid3(b, r);
+                if ((e = cf::launch_h3d<T>(0, f, psi, dch, dl + w.d3_off, w.n_3d, g, lut, s)) != hipSuccess) return e;
+                if ((e = cf::launch_e3d<T>(0, f, psi, dch, dl + w.d3_off, w.n_3d, g, lut, s)) != hipSuccess) return e;
+            } else {
+                const cf::Grid2D g = Dev<T>::grid2(b, r);
+                if ((e = cf::launch_h2d<T>(CF_POL_TM, 0, f, dch, dl + w.tm_off, w.n_tm, g, lut, s)) != hipSuccess)
+                    return e;
+                if ((e = cf::launch_h2d<T>(CF_POL_TE, 0, f, dch, dl + w.te_off, w.n_te, g, lut, s)) != hipSuccess)
+                    return e;
+                if ((e = cf::launch_e2d<T>(CF_POL_TM, 0, f, dch, dl + w.tm_off, w.n_tm, g, lut, s)) != hipSuccess)
+                    return e;
+                if ((e = cf::launch_e2d<T>(CF_POL_TE, 0, f, dch, dl + w.te_off, w.n_te, g, lut, s)) != hipSuccess)
+                    return e;
+            }
+            if ((e = cf::launch_surface<T>(f, dch, dl + w.all_off, w.n_all, t, kt, (int)m, dt, dA, acc, nullptr, 0,
+                                           s)) != hipSuccess)
+                return e;
+        }
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+void loop(cf_server* S) {
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        // ---- admission (arrival order, later requests may pass) ----
+        for (auto it = S->queue.begin(); it != S->queue.end();) {
+            Req& r = **it;
+            if (!r.cancel) {
+                ++it;
+                continue;
+            }
+            r.state = ST_CANCELLED;
+            r.status = CF_E_CANCELLED;
+            r.err = "request cancelled";
+            r.t_done = now_s();
+            ++S->n_cancelled;
+            it = S->queue.erase(it);
+            S->cv.notify_all();
+        }
+        std::vector<size_t> want;
+        for (auto& q : S->queue) want.push_back(q->bytes);
+        const auto picked = cfi::admit_pass(S->arena, want);
+        std::vector<bool> taken(S->queue.size(), false);
+        for (const auto& kp : picked) {
+            Req& r = *S->queue[kp.first];
+            taken[kp.first] = true;
+            r.off = kp.second;
+            r.t_admit = now_s();
+            hipError_t e = admit<T>(S, r);
+            if (e != hipSuccess) {
+                S->thread_error = std::string("admission failed: ") + hipGetErrorString(e);
+                r.state = ST_FAILED;
+                r.status = CF_E_DEVICE;
+                r.err = S->thread_error;
+                r.t_done = now_s();
+                S->arena.release(r.off, r.bytes);
+                ++S->n_failed;
+                S->cv.notify_all();
+                continue;
+            }
+            r.state = ST_RUNNING;
+            S->active.push_back(S->queue[kp.first]);
+            if (r.fused) S->membership_changed = true;
+        }
+        {
+            std::deque<std::shared_ptr<Req>> rest;
+            for (size_t k = 0; k < S->queue.size(); ++k)
+                if (!taken[k]) rest.push_back(S->queue[k]);
+            S->queue.swap(rest);
+        }
+        if (S->active.empty() && !S->queue.empty()) {
+            // nothing resident and still nothing fits: the head can never run
+            Req& r = *S->queue.front();
+            r.state = ST_FAILED;
+            r.status = CF_E_BUDGET;
+            r.err = "request does not fit the server's memory budget";
+            r.t_done = now_s();
+            ++S->n_failed;
+            S->queue.pop_front();
+            S->cv.notify_all();
+            continue;
+        }
+        if (S->active.empty()) {
+            if (S->stop) break;
+            S->cv.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+            if (S->stop && S->queue.empty()) break;
+            continue;
+        }
+        // ---- one tick ----
+        const double t0 = now_s();
+        lk.unlock();
+        hipError_t e = tick<T>(S);
+        if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+        lk.lock();
+        S->busy_s += now_s() - t0;
+        if (e != hipSuccess) {
+            S->thread_error = std::string("tick failed: ") + hipGetErrorString(e);
+            for (auto& rp : S->active) {
+                rp->state = ST_FAILED;
+                rp->status = CF_E_DEVICE;
+                rp->err = S->thread_error;
+                rp->t_done = now_s();
+                S->arena.release(rp->off, rp->bytes);
+                ++S->n_failed;
+            }
+            S->active.clear();
+            S->membership_changed = true;
+            S->cv.notify_all();
+            continue;
+        }
+        S->clock += S->kh;
+        S->parity ^= 1;
+        // the stream has drained: staged group tables are no longer read
+        S->keep_ch.clear();
+        S->keep_inst.clear();
+        S->keep_work.clear();
+        // ---- retire finished requests / start next channel waves ----
+        for (auto it = S->active.begin(); it != S->active.end();) {
+            Req& r = **it;
+            const bool wave_done = S->clock - r.start >= r.opts.n_steps;
+            if (!wave_done && !r.cancel) {
+                ++it;
+                continue;
+            }
+            if (!r.cancel && !r.fused && r.wave + 1 < (int)r.st.waves.size()) {
+                ++r.wave;
+                r.start = S->clock;
+                hipError_t e2 = start_wave<T>(S, r, reinterpret_cast<T*>(S->arena_base + r.off + r.o_fa));
+                if (e2 == hipSuccess) {
+                    ++it;
+                    continue;
+                }
+                r.status = CF_E_DEVICE;
+                r.err = hipGetErrorString(e2);
+            }
+            if (r.cancel) {
+                r.state = ST_CANCELLED;
+                r.status = CF_E_CANCELLED;
+                r.err = "request cancelled";
+                ++S->n_cancelled;
+            } else if (r.status == CF_OK) {
+                r.acc.assign((size_t)r.C * 2, 0.0);
+                hipError_t e3 = hipMemcpyAsync(r.acc.data(), S->arena_base + r.off + r.o_acc, r.acc.size() * 8,
+                                               hipMemcpyDeviceToHost, S->stream);
+                if (e3 == hipSuccess) e3 = hipStreamSynchronize(S->stream);
+                bool finite = e3 == hipSuccess;
+                for (double v : r.acc) finite = finite && std::isfinite(v);
+                if (e3 != hipSuccess) {
+                    r.status = CF_E_DEVICE;
+                    r.err = hipGetErrorString(e3);
+                } else if (!finite) {
+                    r.status = CF_E_NONFINITE;
+                    r.err = "a force accumulator is not finite";
+                }
+                r.state = r.status == CF_OK ? ST_DONE : ST_FAILED;
+                (r.status == CF_OK ? S->n_completed : S->n_failed)++;
+            } else {
+                r.state = ST_FAILED;
+                ++S->n_failed;
+            }
+            r.t_done = now_s();
+            S->arena.release(r.off, r.bytes);
+            if (r.fused) S->membership_changed = true;
+            it = S->active.erase(it);
+            S->cv.notify_all();
+        }
+    }
+}
+
+std::shared_ptr<Req> find(cf_server* S, uint64_t ticket) {
+    auto it = S->all.find(ticket);
+    return it == S->all.end() ? nullptr : it->second;
+}
+
+}  // namespace
+
+extern "C" {
+
+cf_status cf_server_create(size_t hbm_budget_bytes, int precision, int tile_variant, void* arena, void* stream,
+                           cf_server** out) {
+    if (!out || hbm_budget_bytes < (size_t)1 << 20) return fail(CF_E_ARG, "bad server arguments");
+    if (precision != CF_FP32 && precision != CF_FP64) return fail(CF_E_ARG, "unknown precision");
+    *out = nullptr;
+    std::unique_ptr<cf_server> S(new cf_server);
+    S->precision = precision;
+    if (hipGetDevice(&S->device) != hipSuccess) return fail(CF_E_DEVICE, "no HIP device");
+    // fused variant and steps per tick
+    cf::TBShape sh[cf::kMaxVariants];
+    const int nv = precision == CF_FP64 ? cf::tb_variants<double>(sh, cf::kMaxVariants)
+                                        : cf::tb_variants<float>(sh, cf::kMaxVariants);
+    if (tile_variant < 0 || tile_variant > nv) return fail(CF_E_ARG, "tile_variant out of range");
+    const int first = tile_variant > 0 ? tile_variant - 1 : (precision == CF_FP64 ? 0 : std::min(4, nv - 1));
+    S->kh = sh[first].kh;
+    // the preferred variant, then every other one with the same steps per
+    // launch (wider tiles take surfaces the preferred one cannot hold)
+    S->prefer.push_back(first);
+    for (int v = 0; v < nv; ++v)
+        if (v != first && sh[v].kh == S->kh) S->prefer.push_back(v);
+    // fused group tables: descriptors, instances and two work lists
+    S->cap_ch = 1 << 16;
+    S->cap_inst = 1 << 10;
+    S->cap_work = (size_t)1 << 20;
+    S->g_ch = 0;
+    S->g_inst = cfi::align_up(S->cap_ch * sizeof(cf::ChanDev), 256);
+    S->g_work = S->g_inst + cfi::align_up(S->cap_inst * sizeof(cf::InstDev), 256);
+    S->group_bytes = S->g_work + S->cap_work * sizeof(cf::WorkItem);
+    if (hbm_budget_bytes <= S->group_bytes + ((size_t)1 << 20))
+        return fail(CF_E_BUDGET, "budget too small for the server's tables");
+    if (arena) {
+        S->arena_base = static_cast<char*>(arena);
+    } else {
+        void* a = nullptr;
+        if (hipMalloc(&a, hbm_budget_bytes) != hipSuccess) return fail(CF_E_DEVICE, "hipMalloc of the budget failed");
+        S->arena_base = static_cast<char*>(a);
+        S->own_arena = true;
+    }
+    S->group = S->arena_base;
+    S->arena.reset(hbm_budget_bytes - S->group_bytes);
+    S->arena_base += S->group_bytes;   // request regions follow the group tables
+    if (stream) {
+        S->stream = static_cast<hipStream_t>(stream);
+    } else {
+        if (hipStreamCreate(&S->stream) != hipSuccess) return fail(CF_E_DEVICE, "hipStreamCreate failed");
+        S->own_stream = true;
+    }
+    cf_server* raw = S.get();
+    if (precision == CF_FP64) S->worker = std::thread([raw] { loop<double>(raw); });
+    else S->worker = std::thread([raw] { loop<float>(raw); });
+    *out = S.release();
+    return CF_OK;
+}
+
+cf_status cf_server_submit(cf_server* S, cf_problem* prob, const cf_opts* o, uint64_t* ticket) {
+    if (!S || !prob || !o || !ticket) return fail(CF_E_ARG, "null argument");
+    if (o->precision != S->precision) return fail(CF_E_ARG, "request precision differs from the server's");
+    if (o->path != CF_PATH_BATCHED) return fail(CF_E_ARG, "served requests use the batched path");
+    if (o->n_subset > 0) return fail(CF_E_ARG, "served requests run every channel");
+    cf_status st = cf_validate(prob, o);
+    if (st != CF_OK) return st;
+    auto r = std::make_shared<Req>();
+    r->prob = &prob->p;
+    r->opts = *o;
+    r->t_submit = now_s();
+    // staging reads only settings fixed at creation: no lock needed
+    std::string err = prepare(S, *r);
+    if (!err.empty()) return fail(CF_E_BUDGET, err);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        r->ticket = S->next_ticket++;
+        S->queue.push_back(r);
+        S->all[r->ticket] = r;
+        ++S->n_submitted;
+        *ticket = r->ticket;
+    }
+    S->cv.notify_all();
+    return CF_OK;
+}
+
+static cf_status report(cf_server* S, const std::shared_ptr<Req>& r, int* state, cf_result* out) {
+    if (state) *state = r->state;
+    if (r->state == ST_DONE && out) {
+        cfi::StencilTiming tim;
+        tim.variant = r->variant;
+        cf_opts o = r->opts;
+        const bool ok = cfi::fill_result(*r->prob, r->chans, r->acc, {}, o, (r->t_done - r->t_admit) * 1e3, tim,
+                                         r->st, out);
+        if (!ok) return fail(CF_E_NONFINITE, "a force accumulator is not finite");
+    }
+    if (r->state == ST_FAILED || r->state == ST_CANCELLED) return fail(r->status, r->err.empty() ? "request failed" : r->err);
+    cfi::clear_error();
+    return CF_OK;
+}
+
+cf_status cf_server_poll(cf_server* S, uint64_t ticket, int* state, cf_result* out) {
+    if (!S) return fail(CF_E_ARG, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto r = find(S, ticket);
+    if (!r) return fail(CF_E_ARG, "unknown ticket");
+    return report(S, r, state, out);
+}
+
+cf_status cf_server_wait(cf_server* S, uint64_t ticket, double timeout_s, int* state, cf_result* out) {
+    if (!S) return fail(CF_E_ARG, "null server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto r = find(S, ticket);
+    if (!r) return fail(CF_E_ARG, "unknown ticket");
+    auto pred = [&] { return r->state >= ST_DONE; };
+    if (timeout_s < 0) S->cv.wait(lk, pred);
+    else S->cv.wait_for(lk, std::chrono::duration<double>(timeout_s), pred);
+    return report(S, r, state, out);
+}
+
+cf_status cf_server_cancel(cf_server* S, uint64_t ticket) {
+    if (!S) return fail(CF_E_ARG, "null server");
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto r = find(S, ticket);
+        if (!r) return fail(CF_E_ARG, "unknown ticket");
+        r->cancel = true;
+    }
+    S->cv.notify_all();
+    return CF_OK;
+}
+
+cf_status cf_server_times(cf_server* S, uint64_t ticket, double* submit_s, double* admit_s, double* done_s) {
+    if (!S) return fail(CF_E_ARG, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto r = find(S, ticket);
+    if (!r) return fail(CF_E_ARG, "unknown ticket");
+    if (submit_s) *submit_s = r->t_submit;
+    if (admit_s) *admit_s = r->t_admit;
+    if (done_s) *done_s = r->t_done;
+    return CF_OK;
+}
+
+cf_status cf_server_stats(cf_server* S, cf_server_info* out) {
+    if (!S || !out) return fail(CF_E_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    out->submitted = S->n_submitted;
+    out->completed = S->n_completed;
+    out->failed = S->n_failed;
+    out->cancelled = S->n_cancelled;
+    out->queued = (int)S->queue.size();
+    out->running = (int)S->active.size();
+    out->bytes_in_use = S->arena.used();
+    out->budget = S->arena.size();
+    out->clock_steps = S->clock;
+    out->busy_s = S->busy_s;
+    out->steps_per_tick = S->kh;
+    return CF_OK;
+}
+
+cf_status cf_server_destroy(cf_server* S) {
+    if (!S) return CF_OK;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto& kv : S->all) kv.second->cancel = true;
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    (void)hipStreamSynchronize(S->stream);
+    if (S->own_stream) (void)hipStreamDestroy(S->stream);
+    if (S->own_arena) (void)hipFree(S->group);
+    delete S;
+    return CF_OK;
+}
+
+}  // extern "C"

@@ -31,8 +31,10 @@ def test_batch_equals_individual_solves(cf, precision):
     probs = [cf.Problem.from_workload(w) for w in wls]
     o = opts_of(wls[0], precision=precision)
     res = cf.batch_solve(probs, **o)
-    for p, r in zip(probs, res):
+    res_graph = cf.batch_solve(probs, graph=True, **o)
+    for p, r, rg in zip(probs, res, res_graph):
         assert r["fused"]
+        np.testing.assert_array_equal(r["per_channel"], rg["per_channel"])
         single = p.solve(**o)
         np.testing.assert_array_equal(r["per_channel"], single["per_channel"])
         assert r["force"] == single["force"]
@@ -41,7 +43,7 @@ def test_batch_equals_individual_solves(cf, precision):
 def test_mixed_batch_falls_back(cf):
     announce("mixed batch: a fused piston + a piston whose S is wider than any tile")
     a = piston2d(40, 24, 4, 10, 5, 10, 7, 10.0, pol="TM+TE", n_steps=60, n_harm=8)
-    b = piston2d(150, 24, 4, 60, 5, 10, 7, 10.0, pol="TM+TE", n_steps=60, n_harm=8)
+    b = piston2d(300, 24, 4, 120, 5, 10, 7, 10.0, pol="TM+TE", n_steps=60, n_harm=8)
     probs = [cf.Problem.from_workload(w) for w in (a, b)]
     o = opts_of(a)
     res = cf.batch_solve(probs, **o)

@@ -118,7 +118,21 @@ def test_fused_bitwise_equals_split(cf, precision):
     np.testing.assert_array_equal(a["per_channel"], b["per_channel"])
 
 
-@pytest.mark.parametrize("precision,nvar", [("fp32", 7), ("fp64", 4)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_launch_bitwise_equals_stream_launches(cf, precision):
+    announce(f"fused loop captured in a HIP graph vs launched one by one, {precision}")
+    wl = SMALL["tmte_pec"]().replace(n_steps=203)
+    a = run(cf, wl, precision=precision)
+    for rep in range(2):
+        g = run(cf, wl, precision=precision, graph=True)
+        assert g["fused"]
+        np.testing.assert_array_equal(a["per_channel"], g["per_channel"])
+    # channel waves: one graph per wave
+    w = run(cf, wl, precision=precision, graph=True, max_resident=5)
+    np.testing.assert_array_equal(a["per_channel"], w["per_channel"])
+
+
+@pytest.mark.parametrize("precision,nvar", [("fp32", 11), ("fp64", 5)])
 def test_every_tile_variant_bitwise_equals_split(cf, precision, nvar):
     announce(f"fused tile variants 1..{nvar} vs split, {precision}")
     wl = SMALL["ragged_61x37"]().replace(n_steps=53)
