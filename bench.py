@@ -102,13 +102,23 @@ def bench_3d(cf, torch, n_chan=64, n_steps=200):
     dt = time.perf_counter() - t1
     ceiling = HBM_PEAK_GBS * 1e9 / 48.0       # 48 B per 3D FP32 cell-update
     rate = r["cell_updates"] / dt
+    sweep = []
+    for v in range(0, 5):                      # 0: split half-step kernels, 1..4: fused variants
+        ov = dict(o, n_steps=60)
+        ov.update(split=True) if v == 0 else ov.update(tile_variant=v)
+        rv = p.solve(channel_subset=sub, time_stencil=True, **ov)
+        if v and (not rv["fused"] or rv["tile_variant"] != v):
+            continue
+        cu_s = rv["stencil_cell_updates"] / (rv["stencil_ms_avg"] * 1e-3) if rv["stencil_ms_avg"] else None
+        sweep.append({"variant": v, "fused": rv["fused"], "stencil_cell_updates_per_s": cu_s})
     step_rate = r["stencil_cell_updates"] / (r["stencil_ms_avg"] * 1e-3) if r["stencil_ms_avg"] else None
     log(f"[bench] 3d: {rate:.3e} cell-updates/s over the solve, stencil {step_rate:.3e}")
     return {"workload": f"sphere over indented plate 192^3 res 48, z CPML 16, {n_chan} of {C} channels "
                         f"x {n_steps} steps, FP32 fields", "value": rate, "unit": "cell-updates/s",
             "stencil_cell_updates_per_s": step_rate,
             "stencil_frac_of_hbm_ceiling": step_rate / ceiling if step_rate else None,
-            "hbm_ceiling_cell_updates_per_s": ceiling,
+            "hbm_ceiling_cell_updates_per_s": ceiling, "fused": r["fused"], "variant": r["tile_variant"],
+            "variant_sweep": sweep,
             "projected_full_solve_s": 1280 * wl.n_cells * wl.n_steps / rate}
 
 

@@ -148,7 +148,7 @@ typedef struct cf_opts {
                         /* the channels run in consecutive waves of this many */
                         /* (0 = all at once).  Bounds the workspace of large  */
                         /* 3D problems; results do not depend on it.          */
-    int tile_variant;   /* fused 2D kernel tile shape: 0 = autotune (timed on */
+    int tile_variant;   /* fused kernel variant (2D tile shape, or 3D band shape): 0 = autotune (timed on */
                         /* the solve's own data, cached per shape in the      */
                         /* process and in $CF_AUTOTUNE_CACHE when set),       */
                         /* k >= 1 = variant k-1.  Results do not depend on it. */

@@ -53,7 +53,7 @@ bool g_tune_loaded = false;
 // Device workspace layout of one solve.
 struct Layout {
     size_t ids, lut, ktab, pml, chans, slots, gidx, gw, uidx, uoff, usamp, uw, basis, acc, gamma,
-        fields, fields2, psi, inst, work, total;
+        fields, fields2, psi, psi2, idp, inst, work, total;
     size_t work_items;    // capacity of one work list
 };
 
@@ -154,6 +154,23 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         add(CF_POL_3D, &w.d3_off, &w.n_3d);
         add(0, &w.all_off, &w.n_all);
         st.waves.push_back(w);
+    }
+    if (!plain && p.grid.ndim == 3 && !(o.flags & CF_FLAG_SPLIT)) {
+        cf::Grid3D g{};
+        g.nx = p.nx;
+        g.ny = p.ny;
+        g.nz = p.nz;
+        for (int a = 0; a < 3; ++a) g.per[a] = p.grid.bc[a] == CF_BC_PERIODIC;
+        const int nv = cf::f3d_variants();
+        auto usable = [&](int v) {
+            return o.precision == CF_FP64 ? cf::f3d_usable<double>(v, g) : cf::f3d_usable<float>(v, g);
+        };
+        if (o.tile_variant >= 1 && o.tile_variant <= nv && usable(o.tile_variant - 1)) {
+            st.f3d = true;
+            st.v3d = o.tile_variant - 1;
+        } else {
+            for (int v = 0; v < nv; ++v) st.f3d = st.f3d || usable(v);
+        }
     }
     if (!plain && p.grid.ndim == 2 && !(o.flags & CF_FLAG_SPLIT)) {
         cf::TBShape sh[cf::kMaxVariants];
@@ -300,8 +317,10 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.acc = take(C * 2 * 8);
     L.gamma = (o.flags & CF_FLAG_KEEP_GAMMA) ? take((size_t)o.n_steps * C * 8) : off;
     L.fields = take(block);
-    L.fields2 = st.variant >= 0 ? take(block) : off;
+    L.fields2 = st.variant >= 0 || st.f3d ? take(block) : off;
     L.psi = st.psi_comp > 0 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
+    L.psi2 = st.psi_comp > 0 && st.f3d ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
+    L.idp = st.f3d ? take((size_t)p.ncell * 8) : off;
     int max_tiles = 0;
     for (const TBPlan& pl : st.plans)
         if (pl.ok) max_tiles = std::max(max_tiles, pl.ntx * pl.nty);
@@ -413,6 +432,17 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     CF_HIP(up(L.usamp, st.usamp.data(), st.usamp.size() * 4));
     CF_HIP(up(L.uw, st.uw.data(), st.uw.size() * 8));
     CF_HIP(up(L.basis, st.basis.data(), st.basis.size() * 8));
+    std::vector<uint32_t> idp;
+    if (st.f3d) {
+        // material ids of the six components packed per cell for the fused 3D step
+        idp.resize((size_t)p.ncell * 2);
+        for (int64_t c = 0; c < p.ncell; ++c) {
+            idp[2 * c] = uint32_t(p.ids[CF_EX][c]) | (uint32_t(p.ids[CF_EY][c]) << 8) |
+                         (uint32_t(p.ids[CF_EZ][c]) << 16) | (uint32_t(p.ids[CF_HX][c]) << 24);
+            idp[2 * c + 1] = uint32_t(p.ids[CF_HY][c]) | (uint32_t(p.ids[CF_HZ][c]) << 8);
+        }
+        CF_HIP(up(L.idp, idp.data(), idp.size() * 4));
+    }
     CF_HIP(hipMemsetAsync(ws + L.acc, 0, C * 2 * 8, s));
     const bool keep_gamma = (o.flags & CF_FLAG_KEEP_GAMMA) != 0;
     if (keep_gamma) CF_HIP(hipMemsetAsync(ws + L.gamma, 0, (size_t)o.n_steps * C * 8, s));
@@ -455,6 +485,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     g3.pml_ch = dpml + p.nz;
     g3.pml_be = dpml + 2 * p.nz;
     g3.pml_ce = dpml + 3 * p.nz;
+    g3.idp = st.f3d ? reinterpret_cast<const uint2*>(ws + L.idp) : nullptr;
     const double dt = o.courant / p.grid.res;
     const double dA = std::pow(1.0 / p.grid.res, p.grid.ndim - 1);
     const size_t field_bytes = (size_t)st.resident * st.ncomp * p.ncell * sizeof(T);
@@ -521,6 +552,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
         return hipMemcpyAsync(dinst, &host_inst.back(), sizeof(cf::InstDev), hipMemcpyHostToDevice, s);
     };
     int variant = st.variant;
+    int v3 = st.v3d;                       // fused 3D variant (autotuned below when -1)
     hipError_t err = hipSuccess;
     GraphRun graph;
     graph.on = (o.flags & CF_FLAG_GRAPH) && !smp.on;
@@ -571,6 +603,44 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
         STEP_OK(hipMemsetAsync(ws + L.acc, 0, C * 2 * 8, s));
     }
     timing->variant = variant;
+    if (st.f3d && !st.waves.empty()) {
+        auto usable3 = [&](int v) { return v >= 0 && cf::f3d_usable<T>(v, g3); };
+        const Wave& w0 = st.waves[0];
+        const std::string key = tune_key(p, o, 0, w0.n_3d) + " f3d";
+        int cached;
+        if (v3 < 0 && tune_lookup(key, &cached) && usable3(cached)) v3 = cached;
+        if (v3 < 0) {
+            // time every usable variant on this solve's buffers (the fields
+            // are cleared again when the first wave starts)
+            STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
+            T* fb = reinterpret_cast<T*>(ws + L.fields2);
+            T* pb = psi ? reinterpret_cast<T*>(ws + L.psi2) : nullptr;
+            double best = 1e300;
+            hipEvent_t t0, t1;
+            STEP_OK(hipEventCreate(&t0));
+            STEP_OK(hipEventCreate(&t1));
+            for (int v = 0; v < cf::f3d_variants(); ++v) {
+                if (!usable3(v)) continue;
+                const int* sl = dslots + w0.d3_off;
+                STEP_OK(cf::launch_f3d<T>(v, dch, sl, w0.n_3d, g3, dlut, fields, fb, psi, pb, s));
+                STEP_OK(hipEventRecord(t0, s));
+                for (int r = 0; r < 2; ++r)
+                    STEP_OK(cf::launch_f3d<T>(v, dch, sl, w0.n_3d, g3, dlut, fields, fb, psi, pb, s));
+                STEP_OK(hipEventRecord(t1, s));
+                STEP_OK(hipEventSynchronize(t1));
+                float ms = 0;
+                STEP_OK(hipEventElapsedTime(&ms, t0, t1));
+                if (ms < best) {
+                    best = ms;
+                    v3 = v;
+                }
+            }
+            (void)hipEventDestroy(t0);
+            (void)hipEventDestroy(t1);
+            tune_store(key, v3);
+        }
+        timing->variant = v3;
+    }
     STEP_OK(hipEventRecord(e0, s));
     for (const Wave& w : st.waves) {
         const int* s_tm = dslots + w.tm_off;
@@ -648,6 +718,24 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
                 return hipSuccess;
             }();
             STEP_OK(graph.end(s, body));
+        } else if (three && st.f3d) {
+            // fused 3D: one launch per step, ping-pong between the two field
+            // (and psi) arrays; the surface is read from the array just written
+            T* fa = fields;
+            T* fb = reinterpret_cast<T*>(ws + L.fields2);
+            T* pa = psi;
+            T* pb = psi ? reinterpret_cast<T*>(ws + L.psi2) : nullptr;
+            if (pb) STEP_OK(hipMemsetAsync(pb, 0, psi_bytes, s));
+            for (int m = 0; m < o.n_steps; ++m) {
+                const bool take = smp.begin(s);
+                STEP_OK(cf::launch_f3d<T>(v3, dch, s_3d, w.n_3d, g3, dlut, fa, fb, pa, pb, s));
+                const double cu = (double)w.n_3d * p.ncell;
+                smp.end(take, s, cu, cu * state_bytes);
+                STEP_OK(cf::launch_surface<T>(fb, dch, s_all, w.n_all, tabs, dk, m, dt, dA, dacc, dgam, (int)C,
+                                              s));
+                std::swap(fa, fb);
+                std::swap(pa, pb);
+            }
         } else {
             for (int m = 0; m < o.n_steps; ++m) {
                 const bool take = smp.begin(s);

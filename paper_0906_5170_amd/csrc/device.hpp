@@ -108,6 +108,9 @@ struct Grid3D {
     const double* pml_ch;
     const double* pml_be;
     const double* pml_ce;
+    // fused 3D step only: material ids packed per cell, x = Ex | Ey << 8 |
+    // Ez << 16 | Hx << 24, y = Hy | Hz << 8
+    const uint2* idp;
 };
 
 
@@ -146,6 +149,15 @@ hipError_t launch_e3d(int mode, T* fields, T* psi, const ChanDev* ch, const int*
 // every item advances its channel by min(kmax, remaining steps of its
 // instance) steps starting at launch-clock step m, between its instance's
 // two field buffers in the direction given by parity.
+// Fused 3D step (one full step per launch, z-streaming; reads src, writes
+// dst, CPML psi likewise).  Usable for nx <= 256, z walls PEC or CPML.
+int f3d_variants();
+template <typename T>
+bool f3d_usable(int variant, const Grid3D& g);
+template <typename T>
+hipError_t launch_f3d(int variant, const ChanDev* ch, const int* slots, int nslots, const Grid3D& g, const T* lut,
+                      const T* src, T* dst, const T* psrc, T* pdst, hipStream_t s);
+
 template <typename T>
 hipError_t launch_tb2d(int variant, int pol, const ChanDev* ch, const WorkItem* work, int nwork,
                        const InstDev* inst, int kmax, int m, int parity, hipStream_t s);

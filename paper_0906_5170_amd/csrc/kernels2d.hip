@@ -17,6 +17,7 @@
 // bitwise-identical fields.
 #include "../../include/casimir_fdtd.h"
 #include "device.hpp"
+#include "yee_common.hpp"
 
 namespace cf {
 
@@ -26,17 +27,16 @@ constexpr int BX = 64;
 constexpr int BY = 4;
 constexpr int NT = 256;   // threads of the surface and fused kernels
 
+using yee::from_next;
+using yee::from_prev;
+using yee::lut_ab;
+using yee::Pair;
 template <typename T>
-__device__ __forceinline__ T yee_sub(T a, T x, T b, T d) { return fma(a, x, -(b * d)); }
+__device__ __forceinline__ T yee_sub(T a, T x, T b, T d) { return yee::sub(a, x, b, d); }
 template <typename T>
-__device__ __forceinline__ T yee_add(T a, T x, T b, T d) { return fma(a, x, b * d); }
+__device__ __forceinline__ T yee_add(T a, T x, T b, T d) { return yee::add(a, x, b, d); }
 template <typename T>
-__device__ __forceinline__ T yee_half(T b, T d) { return (T(0.5) * b) * d; }
-
-template <typename T>
-__device__ __forceinline__ const T* lut_ab(const T* lut, int kind, int comp, int id) {
-    return lut + (((kind * 6 + comp) << 8) + id) * 2;
-}
+__device__ __forceinline__ T yee_half(T b, T d) { return yee::half(b, d); }
 
 __device__ __forceinline__ void neumaier(double& sum, double& comp, double term) {
     const double nt = sum + term;
@@ -205,9 +205,9 @@ __global__ __launch_bounds__(NT) void k_surface(const T* __restrict__ fields, co
 // ---------------------------------------------------------------------------
 // fused temporal-blocked kernel, register-blocked
 //
-// Block b works on one tile of channel slots[k].  Its region is 64 columns
-// (one per lane) by W*B rows (wave w of W holds rows w*B .. w*B+B-1 of every
-// column in registers); the tile proper is the region minus a KH-cell halo on
+// Block b works on one tile of one channel.  Its region is 64 CX columns (CX
+// per lane) by W*B rows (wave w of W holds rows w*B .. w*B+B-1 of its
+// columns in registers); the tile proper is the region minus a KH-cell halo on
 // every side.  The block loads the region, takes `ksteps` <= KH full time
 // steps and writes the tile's cells to dst.  After step s the fields are
 // exact on the region shrunk by s cells on every side, so the tile stays
@@ -232,31 +232,6 @@ __global__ __launch_bounds__(NT) void k_surface(const T* __restrict__ fields, co
 // the list out so that b % 8, the XCD a block is dispatched to, is the same
 // for every tile of a channel (halo re-reads hit that XCD's L2).  Instances
 // (problems) of one launch have their own grids, tables and time origin.
-
-template <typename T>
-struct Pair {
-    T a, b;
-};
-
-// Value of v held by lane l+1 (DPP wave_shl:1) / lane l-1 (wave_shr:1).  The
-// lane with no neighbour (63 / 0) reads 0 (bound_ctrl); it lies in the rim
-// that is never written back.
-__device__ __forceinline__ float from_next(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
-}
-__device__ __forceinline__ float from_prev(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
-}
-__device__ __forceinline__ double from_next(double v) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x130, 0xf, 0xf, true),
-                            __builtin_amdgcn_mov_dpp(lo, 0x130, 0xf, 0xf, true));
-}
-__device__ __forceinline__ double from_prev(double v) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x138, 0xf, 0xf, true),
-                            __builtin_amdgcn_mov_dpp(lo, 0x138, 0xf, 0xf, true));
-}
 
 // Register-blocked fused kernel.  A block holds a (64 CX) x (RBW B) region
 // of one channel: lane l of wave w owns columns CX l .. CX l + CX - 1 and rows

@@ -15,8 +15,11 @@
 // Inside the z layers every z difference D becomes D + psi with
 // psi <- b_z psi + c_z D (b_z, c_z at the updated component's z position);
 // psi lives only in the two layers (2 P planes per psi component).
+#include <algorithm>
+
 #include "../../include/casimir_fdtd.h"
 #include "device.hpp"
+#include "yee_common.hpp"
 
 namespace cf {
 
@@ -26,16 +29,12 @@ constexpr int BX = 64;
 constexpr int BY = 4;
 
 template <typename T>
-__device__ __forceinline__ T yee_sub(T a, T x, T b, T d) { return fma(a, x, -(b * d)); }
+__device__ __forceinline__ T yee_sub(T a, T x, T b, T d) { return yee::sub(a, x, b, d); }
 template <typename T>
-__device__ __forceinline__ T yee_add(T a, T x, T b, T d) { return fma(a, x, b * d); }
+__device__ __forceinline__ T yee_add(T a, T x, T b, T d) { return yee::add(a, x, b, d); }
 template <typename T>
-__device__ __forceinline__ T yee_half(T b, T d) { return (T(0.5) * b) * d; }
-
-template <typename T>
-__device__ __forceinline__ const T* lut_ab(const T* lut, int kind, int comp, int id) {
-    return lut + (((kind * 6 + comp) << 8) + id) * 2;
-}
+__device__ __forceinline__ T yee_half(T b, T d) { return yee::half(b, d); }
+using yee::lut_ab;
 
 // psi plane of z index k inside the layers, or -1 outside
 __device__ __forceinline__ int pml_plane(int k, int nz, int P) {
@@ -163,6 +162,413 @@ __global__ __launch_bounds__(BX* BY) void k_e3d(T* __restrict__ fields, T* __res
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Fused 3D step: one full time step (H then E) per launch, streaming in z.
+//
+// Block (band b, channel slots[blockIdx.y]) owns the interior rows
+// y0 .. y0 + band - 1 (y0 = b band) of every z plane, for the whole x range:
+// lane l of wave w holds columns l, l + 64, .. (CX of them, so every load of
+// a row is one contiguous 64-value segment) of rows w B .. w B + B - 1
+// of a region that starts one row below y0 (region row 0 and row W B - 1 are
+// halo rows, computed but never stored).  The block marches k = 0 .. nz - 1
+// keeping E(k), E(k+1), H(k) and the new H(k-1) of its columns in registers:
+//   H_new(k) needs E(k), E(k+1) and the x+1 / y+1 neighbours of E(k);
+//   E_new(k) needs H_new(k), H_new(k-1) and the x-1 / y-1 neighbours of H_new(k).
+// x neighbours come from the next / previous lane (DPP) or, across a
+// 64-column segment, from a lane broadcast of the neighbouring register; at
+// the row ends a periodic wall takes column 0 / nx - 1 (lane broadcast), a
+// PEC wall reads 0.  y neighbours
+// inside a wave's rows are registers, across waves one LDS row per half step.
+// Reads come from src (fields and CPML psi) and writes go to dst, so the
+// halo rows a block reads are never the rows a neighbouring block writes in
+// the same launch.  z walls are PEC or CPML (periodic z is not handled here).
+// The arithmetic of every cell is that of k_h3d followed by k_e3d.
+constexpr int kF3MaxPml = 64;   // CPML layers the fused 3D step stages in LDS
+
+template <typename T, int W, int B, int CX>
+__global__ __launch_bounds__(64 * W) void k_f3d(const ChanDev* __restrict__ ch, const int* __restrict__ slots,
+                                                 Grid3D g, const T* __restrict__ lut, const T* __restrict__ src,
+                                                 T* __restrict__ dst, const T* __restrict__ psrc,
+                                                 T* __restrict__ pdst, int band) {
+    constexpr int NTB = 64 * W;
+    __shared__ yee::Pair<T> L[6][256];
+    __shared__ T xe[W][2][CX][64];     // first region row of each wave: Ez, Ex (read by the wave below)
+    __shared__ T xh[W][2][CX][64];     // last region row of each wave: Hz, Hx (read by the wave above)
+    __shared__ T Lz[4][2 * kF3MaxPml];    // CPML b, c at H and E z positions of the layer planes
+    const ChanDev d = ch[slots[blockIdx.y]];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int yb = blockIdx.x * band - 1;            // global y of region row 0
+    for (int i = threadIdx.x; i < 6 * 256; i += NTB) {
+        const int comp = i >> 8, id = i & 255;
+        const T* p = lut_ab(lut, d.kind, comp, id);
+        L[comp][id].a = p[0];
+        L[comp][id].b = p[1];
+    }
+    for (int i = threadIdx.x; i < 2 * g.pml; i += NTB) {
+        const int kz = i < g.pml ? i : g.nz - 2 * g.pml + i;   // psi plane i -> z index
+        Lz[0][i] = (T)g.pml_bh[kz];
+        Lz[1][i] = (T)g.pml_ch[kz];
+        Lz[2][i] = (T)g.pml_be[kz];
+        Lz[3][i] = (T)g.pml_ce[kz];
+    }
+    const int64_t n = g.ncell, sz = (int64_t)g.nx * g.ny;
+    const T* __restrict__ S = src + d.field_off;
+    T* __restrict__ D = dst + d.field_off;
+    int64_t rowoff[B];
+    bool rin[B], rst[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+        const int ry = w * B + r;
+        int y = yb + ry;
+        bool in = true;
+        if (y < 0 || y >= g.ny) {
+            if (g.per[1]) y = ((y % g.ny) + g.ny) % g.ny;
+            else in = false;
+        }
+        rin[r] = in;
+        rowoff[r] = (int64_t)y * g.nx;
+        rst[r] = in && ry >= 1 && ry <= band && yb + ry < g.ny;   // stored (interior) row
+    }
+    bool cin[CX];
+#pragma unroll
+    for (int j = 0; j < CX; ++j) cin[j] = j * 64 + lane < g.nx;
+    const bool perx = g.per[0] != 0;
+    const int lastj = (g.nx - 1) / 64, lastl = (g.nx - 1) % 64;   // register / lane of column nx - 1
+    const bool T_PSI = g.pml > 0 && psrc != nullptr;
+
+    // z chunk of this block: planes z0 .. z1-1 are stored; a chunk that does
+    // not start at 0 first marches plane z0 - 1 to obtain H_new(z0 - 1)
+    // (nothing of that plane is stored)
+    const int zc = (g.nz + (int)gridDim.z - 1) / (int)gridDim.z;
+    const int z0 = blockIdx.z * zc, z1 = min(g.nz, z0 + zc);
+    if (z0 >= z1) return;                          // whole block: before any barrier
+    const int kb = z0 > 0 ? z0 - 1 : 0;
+    // Loads are issued from clamped (always valid) addresses and masked only
+    // where the values are taken up, one plane later for the prefetched set,
+    // so the memory latency overlaps a whole plane of arithmetic.
+    bool vc[B][CX];                          // cell (r, j) lies in the grid
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int j = 0; j < CX; ++j) vc[r][j] = rin[r] && cin[j];
+    auto raw3 = [&](int k, int comp0, T (&a)[B][CX], T (&b)[B][CX], T (&c)[B][CX]) {
+        const int64_t pk = (int64_t)min(max(k, 0), g.nz - 1) * sz;
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                const int64_t at = comp0 * n + (vc[r][j] ? pk + rowoff[r] + j * 64 + lane : 0);
+                a[r][j] = S[at];
+                b[r][j] = S[n + at];
+                c[r][j] = S[2 * n + at];
+            }
+    };
+    auto raw_ids = [&](int k, uint2 (&id)[B][CX]) {
+        const int64_t pk = (int64_t)min(max(k, 0), g.nz - 1) * sz;
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int j = 0; j < CX; ++j)
+                id[r][j] = g.idp[vc[r][j] ? pk + rowoff[r] + j * 64 + lane : 0];
+    };
+    auto mask3 = [&](bool kin, T (&a)[B][CX], T (&b)[B][CX], T (&c)[B][CX]) {
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                const bool v = kin && vc[r][j];
+                a[r][j] = v ? a[r][j] : T(0);
+                b[r][j] = v ? b[r][j] : T(0);
+                c[r][j] = v ? c[r][j] : T(0);
+            }
+    };
+    // null material (kNullId, a = b = 0) for cells outside the grid
+    constexpr uint32_t kNull4 = 0x01010101u * kNullId, kNull2 = 0x0101u * kNullId;
+
+    T ex[B][CX], ey[B][CX], ez[B][CX];       // E(k)
+    T ex1[B][CX], ey1[B][CX], ez1[B][CX];    // E(k+1)
+    T hx[B][CX], hy[B][CX], hz[B][CX];       // H(k), then H_new(k)
+    uint32_t id0[B][CX], id1[B][CX];         // material ids of plane k (Ex Ey Ez Hx | Hy Hz)
+    T px[B][CX], py[B][CX];                  // H_new(k-1): Hx, Hy
+    {
+        uint2 i2[B][CX];
+        raw3(kb, 0, ex, ey, ez);
+        raw3(kb + 1, 0, ex1, ey1, ez1);
+        raw3(kb, 3, hx, hy, hz);
+        raw_ids(kb, i2);
+        mask3(true, ex, ey, ez);
+        mask3(kb + 1 < g.nz, ex1, ey1, ez1);
+        mask3(true, hx, hy, hz);
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                id0[r][j] = vc[r][j] ? i2[r][j].x : kNull4;
+                id1[r][j] = vc[r][j] ? i2[r][j].y : kNull2;
+                px[r][j] = T(0);
+                py[r][j] = T(0);
+            }
+    }
+    __syncthreads();   // coefficient table
+
+    for (int k = kb; k < z1; ++k) {
+        const int64_t pk = (int64_t)k * sz;
+        const bool warm = k < z0;                  // uniform over the block
+        const int plane = pml_plane(k, g.nz, g.pml);
+        const bool zp = T_PSI && plane >= 0;       // uniform
+        const T bh = zp ? Lz[0][plane] : T(1), chh = zp ? Lz[1][plane] : T(0);
+        const T be = zp ? Lz[2][plane] : T(1), ce = zp ? Lz[3][plane] : T(0);
+        const int64_t pp = (int64_t)plane * sz;
+        // this plane's psi (layer planes only), loaded before the prefetch so
+        // that waiting for it does not wait for the next plane's inputs
+        T ps[4][B][CX];
+        if (zp) {
+#pragma unroll
+            for (int r = 0; r < B; ++r)
+#pragma unroll
+                for (int j = 0; j < CX; ++j) {
+                    const int64_t pa = d.psi_off + (vc[r][j] ? pp + rowoff[r] + j * 64 + lane : 0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) ps[q][r][j] = psrc[pa + q * g.psi_comp];
+                }
+        }
+        // next plane's inputs, issued before this plane's arithmetic
+        T ex2[B][CX], ey2[B][CX], ez2[B][CX];
+        T hxn[B][CX], hyn[B][CX], hzn[B][CX];
+        uint2 idn[B][CX];
+        raw3(k + 2, 0, ex2, ey2, ez2);
+        raw3(k + 1, 3, hxn, hyn, hzn);
+        raw_ids(k + 1, idn);
+
+        // ---- H half ----
+#pragma unroll
+        for (int j = 0; j < CX; ++j) {
+            xe[w][0][j][lane] = ez[0][j];
+            xe[w][1][j][lane] = ex[0][j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            // x + 1 neighbours: the next lane, or lane 0 of the next register
+            // for lane 63; column 0 of the row for the periodic wrap
+            T nez[CX], ney[CX];
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                const T a = yee::from_next(ez[r][j]), b = yee::from_next(ey[r][j]);
+                const T a1 = j + 1 < CX ? yee::lane_value(ez[r][(j + 1) % CX], 0) : T(0);
+                const T b1 = j + 1 < CX ? yee::lane_value(ey[r][(j + 1) % CX], 0) : T(0);
+                nez[j] = lane == 63 ? a1 : a;
+                ney[j] = lane == 63 ? b1 : b;
+            }
+            const T fez = yee::lane_value(ez[r][0], 0), fey = yee::lane_value(ey[r][0], 0);
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                T ez_y, ex_y;
+                if (r + 1 < B) {
+                    ez_y = ez[(r + 1) % B][j];
+                    ex_y = ex[(r + 1) % B][j];
+                } else if (w + 1 < W) {
+                    ez_y = xe[(w + 1) % W][0][j][lane];
+                    ex_y = xe[(w + 1) % W][1][j][lane];
+                } else {
+                    ez_y = T(0);   // last region row: halo, never stored
+                    ex_y = T(0);
+                }
+                T ez_x = nez[j];
+                T ey_x = ney[j];
+                if (j * 64 + lane == g.nx - 1) {
+                    ez_x = perx ? fez : T(0);
+                    ey_x = perx ? fey : T(0);
+                }
+                T dzEy = ey1[r][j] - ey[r][j];
+                T dzEx = ex1[r][j] - ex[r][j];
+                if (zp && vc[r][j]) {
+                    const int64_t pa = d.psi_off + pp + rowoff[r] + j * 64 + lane;
+                    const T p0 = fma(bh, ps[0][r][j], chh * dzEy);
+                    const T p1 = fma(bh, ps[1][r][j], chh * dzEx);
+                    if (rst[r] && !warm) {
+                        pdst[pa] = p0;
+                        pdst[pa + g.psi_comp] = p1;
+                    }
+                    dzEy = dzEy + p0;
+                    dzEx = dzEx + p1;
+                }
+                const T curl_x = (ez_y - ez[r][j]) - dzEy;
+                const T curl_y = dzEx - (ez_x - ez[r][j]);
+                const T curl_z = (ey_x - ey[r][j]) - (ex_y - ex[r][j]);
+                const yee::Pair<T> cx = L[CF_HX][id0[r][j] >> 24];
+                const yee::Pair<T> cy = L[CF_HY][id1[r][j] & 255u];
+                const yee::Pair<T> cz = L[CF_HZ][(id1[r][j] >> 8) & 255u];
+                const bool v = rin[r] && cin[j];
+                hx[r][j] = v ? yee_sub(cx.a, hx[r][j], cx.b, curl_x) : T(0);
+                hy[r][j] = v ? yee_sub(cy.a, hy[r][j], cy.b, curl_y) : T(0);
+                hz[r][j] = v ? yee_sub(cz.a, hz[r][j], cz.b, curl_z) : T(0);
+            }
+        }
+
+        // ---- E half (not on the warm-up plane) ----
+        if (!warm) {
+#pragma unroll
+        for (int j = 0; j < CX; ++j) {
+            xh[w][0][j][lane] = hz[B - 1][j];
+            xh[w][1][j][lane] = hx[B - 1][j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            // x - 1 neighbours: the previous lane, or lane 63 of the previous
+            // register for lane 0; column nx - 1 of the row for the periodic wrap
+            T phz[CX], phy[CX];
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                const T a = yee::from_prev(hz[r][j]), b = yee::from_prev(hy[r][j]);
+                const T a1 = j > 0 ? yee::lane_value(hz[r][(j + CX - 1) % CX], 63) : T(0);
+                const T b1 = j > 0 ? yee::lane_value(hy[r][(j + CX - 1) % CX], 63) : T(0);
+                phz[j] = lane == 0 ? a1 : a;
+                phy[j] = lane == 0 ? b1 : b;
+            }
+            T lhz = hz[r][0], lhy = hy[r][0];
+#pragma unroll
+            for (int j = 1; j < CX; ++j)
+                if (lastj == j) {
+                    lhz = hz[r][j];
+                    lhy = hy[r][j];
+                }
+            lhz = yee::lane_value(lhz, lastl);
+            lhy = yee::lane_value(lhy, lastl);
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                T hz_y, hx_y;
+                if (r > 0) {
+                    hz_y = hz[(r + B - 1) % B][j];
+                    hx_y = hx[(r + B - 1) % B][j];
+                } else if (w > 0) {
+                    hz_y = xh[(w + W - 1) % W][0][j][lane];
+                    hx_y = xh[(w + W - 1) % W][1][j][lane];
+                } else {
+                    hz_y = T(0);   // region row 0: halo, never stored
+                    hx_y = T(0);
+                }
+                T hz_x = phz[j];
+                T hy_x = phy[j];
+                if (j * 64 + lane == 0) {
+                    hz_x = perx ? lhz : T(0);
+                    hy_x = perx ? lhy : T(0);
+                }
+                T dzHy = hy[r][j] - py[r][j];
+                T dzHx = hx[r][j] - px[r][j];
+                if (zp && vc[r][j]) {
+                    const int64_t pa = d.psi_off + 2 * g.psi_comp + pp + rowoff[r] + j * 64 + lane;
+                    const T p2 = fma(be, ps[2][r][j], ce * dzHy);
+                    const T p3 = fma(be, ps[3][r][j], ce * dzHx);
+                    if (rst[r]) {
+                        pdst[pa] = p2;
+                        pdst[pa + g.psi_comp] = p3;
+                    }
+                    dzHy = dzHy + p2;
+                    dzHx = dzHx + p3;
+                }
+                const T curl_x = (hz[r][j] - hz_y) - dzHy;
+                const T curl_y = dzHx - (hz[r][j] - hz_x);
+                const T curl_z = (hy[r][j] - hy_x) - (hx[r][j] - hx_y);
+                const yee::Pair<T> cx = L[CF_EX][id0[r][j] & 255u];
+                const yee::Pair<T> cy = L[CF_EY][(id0[r][j] >> 8) & 255u];
+                const yee::Pair<T> cz = L[CF_EZ][(id0[r][j] >> 16) & 255u];
+                const T nex = yee_add(cx.a, ex[r][j], cx.b, curl_x);
+                const T ney = yee_add(cy.a, ey[r][j], cy.b, curl_y);
+                const T nez = yee_add(cz.a, ez[r][j], cz.b, curl_z);
+                if (rst[r] && cin[j]) {
+                    const int64_t at = pk + rowoff[r] + j * 64 + lane;
+                    D[at] = nex;
+                    D[n + at] = ney;
+                    D[2 * n + at] = nez;
+                    D[3 * n + at] = hx[r][j];
+                    D[4 * n + at] = hy[r][j];
+                    D[5 * n + at] = hz[r][j];
+                }
+            }
+        }
+        } else {
+            __syncthreads();   // the xe rows of this plane are read before the next plane writes them
+        }
+        mask3(k + 2 < g.nz, ex2, ey2, ez2);
+        mask3(true, hxn, hyn, hzn);
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                px[r][j] = hx[r][j];
+                py[r][j] = hy[r][j];
+                ex[r][j] = ex1[r][j];
+                ey[r][j] = ey1[r][j];
+                ez[r][j] = ez1[r][j];
+                ex1[r][j] = ex2[r][j];
+                ey1[r][j] = ey2[r][j];
+                ez1[r][j] = ez2[r][j];
+                hx[r][j] = hxn[r][j];
+                hy[r][j] = hyn[r][j];
+                hz[r][j] = hzn[r][j];
+                id0[r][j] = vc[r][j] ? idn[r][j].x : kNull4;
+                id1[r][j] = vc[r][j] ? idn[r][j].y : kNull2;
+            }
+    }
+}
+
+// Fused 3D variants: W waves of B rows (band = W B - 2 stored rows).
+struct F3Variant {
+    int W, B;
+};
+constexpr F3Variant kF3[] = {{8, 2}, {16, 1}, {8, 1}, {12, 1}};
+constexpr int kNumF3 = sizeof(kF3) / sizeof(kF3[0]);
+
+template <typename T, int W, int CX>
+constexpr bool f3_fits() {
+    return (size_t)2 * W * 2 * CX * 64 * sizeof(T) + (size_t)6 * 256 * 2 * sizeof(T) +
+               (size_t)4 * 2 * kF3MaxPml * sizeof(T) <=
+           65536;
+}
+
+template <typename T, int W, int B, int CX>
+hipError_t f3_launch(const ChanDev* ch, const int* slots, int nslots, const Grid3D& g, const T* lut, const T* src,
+                     T* dst, const T* psrc, T* pdst, hipStream_t s) {
+    if constexpr (!f3_fits<T, W, CX>()) {
+        return hipErrorInvalidValue;
+    } else {
+        const int band = W * B - 2;
+        const int bands = (g.ny + band - 1) / band;
+        // z chunks: enough blocks to fill the chip several times over, each
+        // chunk at least 24 planes deep (one extra H plane per chunk)
+        const long xy = (long)bands * nslots;
+        int nzc = (int)std::min<long>((4096 + xy - 1) / xy, std::max(1, g.nz / 24));
+        nzc = std::max(1, std::min(nzc, 65535));
+        dim3 grid(bands, nslots, nzc), block(64 * W, 1, 1);
+        hipLaunchKernelGGL((k_f3d<T, W, B, CX>), grid, block, 0, s, ch, slots, g, lut, src, dst, psrc, pdst, band);
+        return hipGetLastError();
+    }
+}
+
+template <typename T, int W, int B>
+hipError_t f3_dispatch_cx(int cx, const ChanDev* ch, const int* slots, int nslots, const Grid3D& g, const T* lut,
+                          const T* src, T* dst, const T* psrc, T* pdst, hipStream_t s) {
+    switch (cx) {
+        case 1: return f3_launch<T, W, B, 1>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
+        case 2: return f3_launch<T, W, B, 2>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
+        case 3: return f3_launch<T, W, B, 3>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
+        case 4: return f3_launch<T, W, B, 4>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+constexpr bool f3_variant_fits(int v, int cx) {
+    bool ok = false;
+    const int W = kF3[v].W;
+    const size_t bytes = (size_t)2 * W * 2 * cx * 64 * sizeof(T) + (size_t)6 * 256 * 2 * sizeof(T) +
+                         (size_t)4 * 2 * kF3MaxPml * sizeof(T);
+    ok = bytes <= 65536;
+    return ok;
+}
 }  // namespace
 
 template <typename T>
@@ -187,11 +593,39 @@ hipError_t launch_e3d(int mode, T* fields, T* psi, const ChanDev* ch, const int*
     return hipGetLastError();
 }
 
+
+template <typename T>
+bool f3d_usable(int variant, const Grid3D& g) {
+    if (variant < 0 || variant >= kNumF3) return false;
+    if (g.nx < 1 || g.nx > 256 || g.per[2] || g.pml > kF3MaxPml) return false;
+    const int cx = (g.nx + 63) / 64;
+    return f3_variant_fits<T>(variant, cx) && g.ny >= 1;
+}
+
+int f3d_variants() { return kNumF3; }
+
+template <typename T>
+hipError_t launch_f3d(int variant, const ChanDev* ch, const int* slots, int nslots, const Grid3D& g, const T* lut,
+                      const T* src, T* dst, const T* psrc, T* pdst, hipStream_t s) {
+    if (nslots <= 0) return hipSuccess;
+    if (!f3d_usable<T>(variant, g)) return hipErrorInvalidValue;
+    const int cx = (g.nx + 63) / 64;
+    switch (variant) {
+        case 0: return f3_dispatch_cx<T, 8, 2>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
+        case 1: return f3_dispatch_cx<T, 16, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
+        case 2: return f3_dispatch_cx<T, 8, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
+        default: return f3_dispatch_cx<T, 12, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
+    }
+}
+
 #define CF_INSTANTIATE(T)                                                                                    \
     template hipError_t launch_h3d<T>(int, T*, T*, const ChanDev*, const int*, int, const Grid3D&, const T*, \
                                       hipStream_t);                                                          \
     template hipError_t launch_e3d<T>(int, T*, T*, const ChanDev*, const int*, int, const Grid3D&, const T*, \
-                                      hipStream_t);
+                                      hipStream_t);                                                          \
+    template bool f3d_usable<T>(int, const Grid3D&);                                                         \
+    template hipError_t launch_f3d<T>(int, const ChanDev*, const int*, int, const Grid3D&, const T*, const T*, \
+                                      T*, const T*, T*, hipStream_t);
 CF_INSTANTIATE(float)
 CF_INSTANTIATE(double)
 #undef CF_INSTANTIATE

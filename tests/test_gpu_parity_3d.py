@@ -30,13 +30,13 @@ def run(cf, wl, **over):
     return cf.Problem.from_workload(wl).solve(**opts)
 
 
-def sphere_case(nx, ny, nz, bc_z="pec", pml=0, n_steps=40, n_harm=2, eps_bg=1.0):
+def sphere_case(nx, ny, nz, bc_z="pec", pml=0, n_steps=40, n_harm=2, eps_bg=1.0, bc_xy=("periodic", "periodic")):
     zlo = pml + 2
     prims = [Box((-BIG, -BIG, -BIG), (BIG, BIG, zlo), 1),
              Sphere((nx / 2 + 0.3, ny / 2, zlo + 5.5), 1.7, 2)]
     ids = rasterize((nx, ny, nz), prims)
     return Workload(name="s3", ndim=3, shape=(nx, ny, nz), res=4.0,
-                    bc=("periodic", "periodic", bc_z), pml_cells=(0, 0, pml),
+                    bc=(bc_xy[0], bc_xy[1], bc_z), pml_cells=(0, 0, pml),
                     eps=[eps_bg, float("-inf"), 3.0], mu=[1.0, 1.0, 1.0], comp_ids=ids,
                     s_lo=(nx // 2 - 3, ny // 2 - 3, zlo + 2), s_hi=(nx // 2 + 4, ny // 2 + 3, zlo + 9),
                     n_harm=n_harm, force_axis=2, pol="3D", kernel="general", n_steps=n_steps)
@@ -46,6 +46,14 @@ CASES = {
     "pec_z": lambda: sphere_case(12, 11, 18),
     "pml_z_fluid": lambda: sphere_case(12, 12, 26, bc_z="pml", pml=4, eps_bg=1.8, n_steps=60),
     "pml_z_force_x": lambda: sphere_case(13, 12, 26, bc_z="pml", pml=4, n_steps=30).replace(force_axis=0),
+}
+
+
+FUSED_ONLY = {
+    # PEC x/y walls, and a grid wider than one 64-lane row (3 columns per lane)
+    "pec_xy_pml_z": lambda: sphere_case(13, 11, 26, bc_z="pml", pml=4, n_steps=23, bc_xy=("pec", "pec")),
+    "wide_x_130": lambda: sphere_case(130, 10, 22, bc_z="pml", pml=3, n_steps=17, bc_xy=("periodic", "pec")),
+    "wide_x_pec_97": lambda: sphere_case(97, 12, 18, n_steps=15, bc_xy=("pec", "periodic")),
 }
 
 
@@ -63,6 +71,29 @@ def test_small_3d(cf, name, precision):
     ref = oracle.solve(wl)
     g = run(cf, wl, precision=precision)
     compare(g, ref, 1e-9 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_3d_every_variant_bitwise_equals_split(cf, precision):
+    """The fused z-streaming 3D step evaluates exactly the split kernels'
+    arithmetic: every variant gives bitwise the same channel integrals."""
+    cases = [CASES["pec_z"]().replace(n_steps=19), CASES["pml_z_fluid"]().replace(n_steps=21)]
+    cases += [f() for f in FUSED_ONLY.values()]
+    for wl in cases:
+        announce(f"fused 3d vs split {wl.shape} bc {wl.bc} {precision}")
+        ref = run(cf, wl, precision=precision, split=True)
+        assert not ref["fused"]
+        n_ok = 0
+        for v in range(1, 5):
+            r = run(cf, wl, precision=precision, tile_variant=v)
+            np.testing.assert_array_equal(r["per_channel"], ref["per_channel"])
+            if r["fused"] and r["tile_variant"] == v:
+                n_ok += 1            # else the variant's LDS rows do not fit this width / precision
+        auto = run(cf, wl, precision=precision)
+        np.testing.assert_array_equal(auto["per_channel"], ref["per_channel"])
+        assert auto["fused"] == (n_ok > 0)
+        if precision == "fp32":
+            assert n_ok >= 2
 
 
 def test_3d_waves_and_plain_equal_batched(cf):
