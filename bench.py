@@ -84,7 +84,7 @@ def cpu_baseline(wl, n_channels=16, n_steps=3000):
                       f"({cu:.3e} cell-updates, {dt:.1f} s, FP64 NumPy, one process per channel)"}
 
 
-def bench_3d(cf, torch, n_chan=64, n_steps=200):
+def bench_3d(cf, torch, n_chan=64, n_steps=200, variant=0):
     """3D FP32 path on the 192^3 sphere-over-indented-plate cell (16-cell z
     CPML): a sample of n_chan of its 1280 channels, spread over faces, kinds
     and harmonics, for n_steps steps, all resident at once."""
@@ -92,7 +92,7 @@ def bench_3d(cf, torch, n_chan=64, n_steps=200):
     wl = c4_sphere_plate()
     p = cf.Problem.from_workload(wl)
     o = dict(sigma=wl.sigma, courant=wl.courant, n_steps=n_steps, pol=wl.pol, kernel=wl.kernel,
-             precision="fp32")
+             precision="fp32", tile_variant=variant)
     C = p.info(**o)["n_channels"]
     sub = np.linspace(0, C - 1, n_chan).astype(int).tolist()
     p.solve(channel_subset=sub, **dict(o, n_steps=10))
@@ -103,7 +103,7 @@ def bench_3d(cf, torch, n_chan=64, n_steps=200):
     ceiling = HBM_PEAK_GBS * 1e9 / 48.0       # 48 B per 3D FP32 cell-update
     rate = r["cell_updates"] / dt
     sweep = []
-    for v in range(0, 5):                      # 0: split half-step kernels, 1..4: fused variants
+    for v in (range(0, 5) if not variant else ()):   # 0: split half-step kernels, 1..4: fused variants
         ov = dict(o, n_steps=60)
         ov.update(split=True) if v == 0 else ov.update(tile_variant=v)
         rv = p.solve(channel_subset=sub, time_stencil=True, **ov)
@@ -257,6 +257,10 @@ def main():
                     help="only the headline solve and its stencil timing (for counter runs)")
     ap.add_argument("--tile-variant", type=int, default=0,
                     help="fused kernel variant for the headline solve (0: autotuned)")
+    ap.add_argument("--with-3d", action="store_true", help="run the 3D sample even with --main-only")
+    ap.add_argument("--c4-steps", type=int, default=200, help="time steps of the 3D sample")
+    ap.add_argument("--c4-variant", type=int, default=0,
+                    help="fused 3D variant of the 3D sample (0: autotuned, with a sweep of all variants)")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--serve-n", type=int, default=24, help="requests in the served piston stream")
     ap.add_argument("--serve-mixed", type=int, default=0,
@@ -269,6 +273,8 @@ def main():
     args = ap.parse_args()
     if args.main_only:
         args.no_cpu = args.no_plain = args.no_batch = args.no_serve = args.no_3d = args.no_sweep = True
+        if args.with_3d:
+            args.no_3d = False
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the channel-parallel "
               "multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
@@ -397,7 +403,7 @@ def main():
 
     rate_3d = None
     if not args.no_3d:
-        out["c4_3d"] = bench_3d(cf, torch)
+        out["c4_3d"] = bench_3d(cf, torch, n_steps=args.c4_steps, variant=args.c4_variant)
         rate_3d = out["c4_3d"]["value"]
     if not args.no_serve:
         out["serving"] = bench_serving(cf, torch, args, rate_3d)

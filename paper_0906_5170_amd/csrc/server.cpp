@@ -59,10 +59,13 @@ struct Req {
     cfi::Staged st;
     bool fused = false;
     int variant = -1;                 // fused variant of this request
+    int v3 = -1;                      // fused 3D step variant (-1: split 3D kernels)
+    int par = 0;                      // fused 3D: field array holding the current step
     int C = 0;
     size_t bytes = 0, off = 0;
     size_t o_ids, o_lut, o_ktab, o_pml, o_ch, o_slots, o_gidx, o_gw, o_uidx, o_uoff, o_usamp, o_uw, o_basis,
-        o_acc, o_fa, o_fb, o_psi;
+        o_acc, o_fa, o_fb, o_psi, o_psi2, o_idp;
+    std::vector<uint32_t> idp;        // fused 3D: packed material ids
     std::vector<uint8_t> ids;
     std::vector<uint8_t> lut;     // field-precision bytes
     std::vector<double> ktab, pml;
@@ -147,8 +150,11 @@ void layout_request(const cf_server* S, Req& r) {
     r.o_acc = take((size_t)r.C * 2 * 8);
     const size_t block = (size_t)st.resident * st.ncomp * p.ncell * fsz;
     r.o_fa = take(block);
-    r.o_fb = r.fused ? take(block) : off;
+    const bool f3 = r.v3 >= 0;
+    r.o_fb = r.fused || f3 ? take(block) : off;
     r.o_psi = st.psi_comp > 0 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
+    r.o_psi2 = st.psi_comp > 0 && f3 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
+    r.o_idp = f3 ? take((size_t)p.ncell * 8) : off;
     r.bytes = off;
 }
 
@@ -173,6 +179,24 @@ std::string prepare(cf_server* S, Req& r) {
                 break;
             }
     r.fused = r.variant >= 0;
+    // 3D requests take the fused z-streaming step when it applies: the
+    // preferred band shape (8 waves of 1 row), else the first usable one
+    r.v3 = -1;
+    if (p.grid.ndim == 3 && r.st.f3d) {
+        cf::Grid3D g{};
+        g.nx = p.nx;
+        g.ny = p.ny;
+        g.nz = p.nz;
+        for (int a = 0; a < 3; ++a) g.per[a] = p.grid.bc[a] == CF_BC_PERIODIC;
+        g.pml = p.grid.bc[2] == CF_BC_PML ? p.grid.pml_cells[2] : 0;
+        auto usable = [&](int v) {
+            return S->precision == CF_FP64 ? cf::f3d_usable<double>(v, g) : cf::f3d_usable<float>(v, g);
+        };
+        const int pref = 2;
+        if (usable(pref)) r.v3 = pref;
+        for (int v = 0; v < cf::f3d_variants() && r.v3 < 0; ++v)
+            if (usable(v)) r.v3 = v;
+    }
     int R = r.opts.max_resident > 0 ? std::min(r.opts.max_resident, r.C) : r.C;
     if (r.fused) R = r.C;   // fused requests keep every channel resident
     for (;;) {
@@ -190,6 +214,14 @@ std::string prepare(cf_server* S, Req& r) {
     r.ids.resize((size_t)cf::kNumComp * p.ncell);
     for (int c = 0; c < cf::kNumComp; ++c)
         std::memcpy(r.ids.data() + (size_t)c * p.ncell, p.ids[c].data(), p.ncell);
+    if (r.v3 >= 0) {
+        r.idp.resize((size_t)p.ncell * 2);
+        for (int64_t c = 0; c < p.ncell; ++c) {
+            r.idp[2 * c] = uint32_t(p.ids[CF_EX][c]) | (uint32_t(p.ids[CF_EY][c]) << 8) |
+                           (uint32_t(p.ids[CF_EZ][c]) << 16) | (uint32_t(p.ids[CF_HX][c]) << 24);
+            r.idp[2 * c + 1] = uint32_t(p.ids[CF_HY][c]) | (uint32_t(p.ids[CF_HZ][c]) << 8);
+        }
+    }
     std::vector<double> l64 = cf::coefficient_lut(p, r.opts.sigma, r.opts.courant);
     if (S->precision == CF_FP64) {
         r.lut.resize(l64.size() * 8);
@@ -251,6 +283,7 @@ struct Dev {
         g.pml_ch = pm + p.nz;
         g.pml_be = pm + 2 * p.nz;
         g.pml_ce = pm + 3 * p.nz;
+        g.idp = r.v3 >= 0 ? reinterpret_cast<const uint2*>(b + r.o_idp) : nullptr;
         return g;
     }
 };
@@ -272,6 +305,10 @@ hipError_t start_wave(cf_server* S, Req& r, T* f) {
     if (r.st.psi_comp > 0 &&
         (e = hipMemsetAsync(b + r.o_psi, 0, (size_t)r.st.resident * 4 * r.st.psi_comp * sizeof(T), s)) != hipSuccess)
         return e;
+    if (r.v3 >= 0 && r.st.psi_comp > 0 &&
+        (e = hipMemsetAsync(b + r.o_psi2, 0, (size_t)r.st.resident * 4 * r.st.psi_comp * sizeof(T), s)) != hipSuccess)
+        return e;
+    r.par = 0;
     if ((e = cf::launch_kick<T>(f, dch, dl + w.all_off, w.n_all, r.st.max_uniq, t, s)) != hipSuccess) return e;
     if (p.grid.ndim == 3) {
         const cf::Grid3D g = Dev<T>::grid3(b, r);
@@ -311,6 +348,7 @@ hipError_t admit(cf_server* S, Req& r) {
     UP(r.o_usamp, st.usamp.data(), st.usamp.size() * 4);
     UP(r.o_uw, st.uw.data(), st.uw.size() * 8);
     UP(r.o_basis, st.basis.data(), st.basis.size() * 8);
+    UP(r.o_idp, r.idp.data(), r.idp.size() * 4);
 #undef UP
     if ((e = hipMemsetAsync(b + r.o_acc, 0, (size_t)r.C * 2 * 8, s)) != hipSuccess) return e;
     r.wave = 0;
@@ -435,7 +473,21 @@ hipError_t tick(cf_server* S) {
         for (int k = 0; k < S->kh; ++k) {
             const long long m = S->clock + k - r.start;
             if (m < 0 || m >= r.opts.n_steps) continue;
-            if (p.grid.ndim == 3) {
+            T* cur = f;   // field array the surface is read from after this step
+            if (p.grid.ndim == 3 && r.v3 >= 0) {
+                const cf::Grid3D g = Dev<T>::grid3(b, r);
+                T* fa = reinterpret_cast<T*>(b + r.o_fa);
+                T* fb = reinterpret_cast<T*>(b + r.o_fb);
+                T* pa = psi;
+                T* pb = psi ? reinterpret_cast<T*>(b + r.o_psi2) : nullptr;
+                T* src = r.par ? fb : fa;
+                T* dst = r.par ? fa : fb;
+                if ((e = cf::launch_f3d<T>(r.v3, dch, dl + w.d3_off, w.n_3d, g, lut, src, dst, r.par ? pb : pa,
+                                           r.par ? pa : pb, s)) != hipSuccess)
+                    return e;
+                r.par ^= 1;
+                cur = dst;
+            } else if (p.grid.ndim == 3) {
                 const cf::Grid3D g = Dev<T>::grid3(b, r);
                 if ((e = cf::launch_h3d<T>(0, f, psi, dch, dl + w.d3_off, w.n_3d, g, lut, s)) != hipSuccess) return e;
                 if ((e = cf::launch_e3d<T>(0, f, psi, dch, dl + w.d3_off, w.n_3d, g, lut, s)) != hipSuccess) return e;
@@ -450,7 +502,7 @@ hipError_t tick(cf_server* S) {
                 if ((e = cf::launch_e2d<T>(CF_POL_TE, 0, f, dch, dl + w.te_off, w.n_te, g, lut, s)) != hipSuccess)
                     return e;
             }
-            if ((e = cf::launch_surface<T>(f, dch, dl + w.all_off, w.n_all, t, kt, (int)m, dt, dA, acc, nullptr, 0,
+            if ((e = cf::launch_surface<T>(cur, dch, dl + w.all_off, w.n_all, t, kt, (int)m, dt, dA, acc, nullptr, 0,
                                            s)) != hipSuccess)
                 return e;
         }
@@ -701,7 +753,7 @@ static cf_status report(cf_server* S, const std::shared_ptr<Req>& r, int* state,
     if (state) *state = r->state;
     if (r->state == ST_DONE && out) {
         cfi::StencilTiming tim;
-        tim.variant = r->variant;
+        tim.variant = r->variant >= 0 ? r->variant : r->v3;   // fused 2D tile or fused 3D band shape
         cf_opts o = r->opts;
         const bool ok = cfi::fill_result(*r->prob, r->chans, r->acc, {}, o, (r->t_done - r->t_admit) * 1e3, tim,
                                          r->st, out);

@@ -46,7 +46,7 @@ def sphere3d(n_steps=40):
 def mix():
     """Fused pistons of three heights and step counts, a piston whose S needs
     the two-columns-per-lane tiles, one whose S is wider than any fused tile
-    (split kernels) and a 3D sphere case."""
+    (split kernels) and a 3D sphere case (fused 3D step)."""
     wls = [piston2d(40, ny, 4, 10, 5, 10, (ny - 5) // 2, 10.0, pol="TM+TE", n_steps=T, n_harm=8)
            for ny, T in ((20, 97), (31, 61), (40, 130))]
     wls.append(piston2d(150, 24, 4, 60, 5, 10, 7, 10.0, pol="TM+TE", n_steps=75, n_harm=8))
@@ -55,7 +55,7 @@ def mix():
     return wls
 
 
-N_FUSED = 4      # leading entries of mix() that run on the fused kernel
+SPLIT_ONLY = 4   # the entry of mix() no fused kernel takes (S wider than any tile)
 
 
 def test_server_results_alone_equal_mix_and_one_shot(cf):
@@ -79,7 +79,7 @@ def test_server_results_alone_equal_mix_and_one_shot(cf):
         a, m = alone[k], mixed[k]
         np.testing.assert_array_equal(a["per_channel"], m["per_channel"])
         assert a["force"] == m["force"]
-        fused = k < N_FUSED
+        fused = k != SPLIT_ONLY
         assert a["fused"] == fused
         if fused:
             if k < 3:
