@@ -243,6 +243,54 @@ def bench_serving(cf, torch, args, rate_3d):
     return res
 
 
+def bench_precision(cf, torch):
+    """FP32 fields with FP64 accumulation against the stored FP64 oracle
+    results (tests/golden), per configuration: relative force error (C1,
+    C3 members) or relative channel-integral error (C4 sample channels over
+    the full T).  The C2 headline error is reported beside the main line."""
+    from casimir_inputs import c1_piston_tm_fp64, c3_uneven_set, c4_sphere_plate
+    gdir = os.path.join(ROOT, "tests", "golden")
+    res = {}
+
+    def opts(wl, **over):
+        o = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol=wl.pol, kernel=wl.kernel,
+                 precision="fp32")
+        o.update(over)
+        return o
+    path = os.path.join(gdir, "c1_piston_tm_oracle.json")
+    if os.path.exists(path):
+        ref = json.load(open(path))
+        wl = c1_piston_tm_fp64()
+        p = cf.Problem.from_workload(wl)
+        r32 = p.solve(**opts(wl))
+        r64 = p.solve(**opts(wl, precision="fp64"))
+        res["c1"] = {"workload": "2D TM piston 80x40 res 20, T=2000",
+                     "fp32_force_rel_err": abs(r32["force"] / ref["force"] - 1),
+                     "fp64_force_rel_err": abs(r64["force"] / ref["force"] - 1)}
+    path = os.path.join(gdir, "c3_uneven_members_oracle.json")
+    if os.path.exists(path):
+        ref = json.load(open(path))
+        wls = c3_uneven_set()
+        errs = []
+        for m in ref["members"]:
+            wl = wls[m["index"]]
+            r = cf.Problem.from_workload(wl).solve(**opts(wl))
+            errs.append({"member": m["index"], "h": m["h"], "shape": m["shape"],
+                         "fp32_force_rel_err": abs(r["force"] / m["force"] - 1)})
+        res["c3"] = {"workload": "uneven piston set members, 400 x (84 | 160), T=10000", "members": errs}
+    path = os.path.join(gdir, "c4_sphere_plate_channels_full_T_oracle.json")
+    if os.path.exists(path):
+        ref = json.load(open(path))
+        wl = c4_sphere_plate()
+        r = cf.Problem.from_workload(wl).solve(channel_subset=ref["subset"], **opts(wl))
+        acc_ref = np.array(ref["per_channel"])
+        err = np.abs(r["per_channel"] - acc_ref) / np.abs(acc_ref)
+        res["c4"] = {"workload": f"192^3 sphere-plate, channels {ref['subset']}, T={ref['n_steps']}",
+                     "fp32_channel_rel_err_max": float(err.max()),
+                     "fp32_channel_rel_err": [float(e) for e in err]}
+    log(f"[bench] precision: {json.dumps(res)}")
+    return res
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +301,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--main-only", action="store_true",
                     help="only the headline solve and its stencil timing (for counter runs)")
     ap.add_argument("--tile-variant", type=int, default=0,
@@ -273,6 +322,7 @@ def main():
     args = ap.parse_args()
     if args.main_only:
         args.no_cpu = args.no_plain = args.no_batch = args.no_serve = args.no_3d = args.no_sweep = True
+        args.no_precision = True
         if args.with_3d:
             args.no_3d = False
     if args.gpus != 1:
@@ -412,6 +462,8 @@ def main():
     if os.path.exists(gold) and not args.n_steps:
         ref = json.load(open(gold))
         out["force_rel_err_vs_fp64_oracle"] = abs(r["force"] / ref["force"] - 1)
+    if not args.no_precision:
+        out["precision"] = bench_precision(cf, torch)
 
     if not args.no_plain:
         # plain path: one channel at a time, three launches per step; one TM

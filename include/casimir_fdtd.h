@@ -152,6 +152,12 @@ typedef struct cf_opts {
                         /* the solve's own data, cached per shape in the      */
                         /* process and in $CF_AUTOTUNE_CACHE when set),       */
                         /* k >= 1 = variant k-1.  Results do not depend on it. */
+    double stop_tol;    /* time-convergence stop (Appendix A, Fig. 12): 0 = off.  Every */
+    int stop_every;     /* stop_every steps (0: 500) the partial force F(T') is formed   */
+                        /* from the FP64 accumulators; the run ends once two consecutive */
+                        /* windows change it by at most stop_tol |F(T')|.  Used when all */
+                        /* channels are resident at once (one wave); turns off           */
+                        /* CF_FLAG_GRAPH.  cf_result.n_steps_run gives the steps run.    */
 } cf_opts;
 
 typedef struct cf_info {
@@ -192,6 +198,7 @@ typedef struct cf_result {
     int fused;                   /* 1 when the fused multi-step kernel advanced the fields          */
     int tile_variant;            /* fused kernel variant used (1-based), 0 if not fused             */
     int tile_halo;               /* steps per fused launch of that variant                          */
+    int n_steps_run;             /* time steps run (< n_steps when the convergence stop ended it)   */
 } cf_result;
 
 typedef struct cf_problem cf_problem;

@@ -57,7 +57,8 @@ class _Opts(C.Structure):
     _fields_ = [("sigma", C.c_double), ("courant", C.c_double), ("n_steps", C.c_int),
                 ("pol", C.c_int), ("kernel", C.c_int), ("precision", C.c_int), ("path", C.c_int),
                 ("flags", C.c_int), ("channel_subset", C.POINTER(C.c_int)), ("n_subset", C.c_int),
-                ("stream", C.c_void_p), ("max_resident", C.c_int), ("tile_variant", C.c_int)]
+                ("stream", C.c_void_p), ("max_resident", C.c_int), ("tile_variant", C.c_int),
+                ("stop_tol", C.c_double), ("stop_every", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -77,7 +78,8 @@ class _Result(C.Structure):
                 ("device_ms", C.c_double), ("stencil_ms_avg", C.c_double),
                 ("stencil_samples", C.c_int), ("stencil_launches", C.c_int),
                 ("stencil_alg_bytes", C.c_double), ("stencil_cell_updates", C.c_double),
-                ("fused", C.c_int), ("tile_variant", C.c_int), ("tile_halo", C.c_int)]
+                ("fused", C.c_int), ("tile_variant", C.c_int), ("tile_halo", C.c_int),
+                ("n_steps_run", C.c_int)]
 
 
 _lib = None
@@ -168,7 +170,7 @@ def _result_dict(r, bufs) -> dict:
                stencil_samples=r.stencil_samples, stencil_launches=r.stencil_launches,
                stencil_alg_bytes=r.stencil_alg_bytes,
                stencil_cell_updates=r.stencil_cell_updates, fused=bool(r.fused),
-               tile_variant=r.tile_variant, tile_halo=r.tile_halo)
+               tile_variant=r.tile_variant, tile_halo=r.tile_halo, n_steps_run=r.n_steps_run)
     if bufs["gam"] is not None:
         out["gamma"] = bufs["gam"].reshape(bufs["T"], len(bufs["pc"]))
         out["trace"] = bufs["tr"]
@@ -246,7 +248,7 @@ class Problem:
     def _opts(self, sigma=1.0, courant=0.5, n_steps=1000, pol="TM", kernel="zinv2d",
               precision="fp64", path="batched", keep_gamma=False, channel_subset=None, stream=None,
               time_stencil=False, split=False, max_resident=0, tile_variant=0, inject_nan=False,
-              graph=False):
+              graph=False, stop_tol=0.0, stop_every=0):
         o = _Opts()
         o.sigma = float(sigma)
         o.courant = float(courant)
@@ -269,6 +271,8 @@ class Problem:
         o.stream = stream
         o.max_resident = int(max_resident)
         o.tile_variant = int(tile_variant)
+        o.stop_tol = float(stop_tol)
+        o.stop_every = int(stop_every)
         return o
 
     def info(self, **opts) -> dict:

@@ -555,7 +555,26 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     int v3 = st.v3d;                       // fused 3D variant (autotuned below when -1)
     hipError_t err = hipSuccess;
     GraphRun graph;
-    graph.on = (o.flags & CF_FLAG_GRAPH) && !smp.on;
+    graph.on = (o.flags & CF_FLAG_GRAPH) && !smp.on && !(o.stop_tol > 0);
+    // time-convergence stop (one wave of resident channels only)
+    cfi::ConvergenceStop conv;
+    conv.on = o.stop_tol > 0 && st.waves.size() == 1 && o.path != CF_PATH_PLAIN;
+    conv.tol = o.stop_tol;
+    conv.every = conv.next = o.stop_every > 0 ? o.stop_every : 500;
+    int steps_run = o.n_steps;
+    std::vector<double> acc_probe;
+    // after `done` steps: true when the run has converged (syncs the stream)
+    auto converged = [&](int done) -> bool {
+        if (!conv.on || done < conv.next || done >= o.n_steps) return false;
+        while (conv.next <= done) conv.next += conv.every;
+        acc_probe.assign(C * 2, 0.0);
+        if (hipMemcpyAsync(acc_probe.data(), dacc, C * 2 * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return false;
+        if (!conv.update(acc_probe, st.chans)) return false;
+        steps_run = done;
+        return true;
+    };
 #define STEP_OK(expr)                     \
     do {                                  \
         err = (expr);                     \
@@ -714,6 +733,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
                         smp.end(take, ls, cu, cu * state_bytes);
                     }
                     parity ^= 1;
+                    if (converged(m + ks)) break;
                 }
                 return hipSuccess;
             }();
@@ -735,6 +755,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
                                               s));
                 std::swap(fa, fb);
                 std::swap(pa, pb);
+                if (converged(m + 1)) break;
             }
         } else {
             for (int m = 0; m < o.n_steps; ++m) {
@@ -752,6 +773,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
                 smp.end(take, s, cu, cu * state_bytes);
                 STEP_OK(cf::launch_surface<T>(fields, dch, s_all, w.n_all, tabs, dk, m, dt, dA, dacc, dgam,
                                               (int)C, s));
+                if (converged(m + 1)) break;
             }
         }
     }
@@ -775,6 +797,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
         timing->cu_total = smp.cu;
         timing->launches = smp.seen;
     }
+    timing->steps_run = steps_run;
     acc_out.assign(C * 2, 0.0);
     STEP_OK(hipMemcpy(acc_out.data(), ws + L.acc, C * 2 * 8, hipMemcpyDeviceToHost));
     if (keep_gamma) {
@@ -833,8 +856,10 @@ bool fill_result(const cf::Problem& p, const std::vector<cf::Channel>& chans, co
             out->trace[m] = run;
         }
     }
+    const int steps = tim.steps_run >= 0 ? tim.steps_run : o.n_steps;
     out->n_channels_run = (int)C;
-    out->cell_updates = (double)C * (double)p.ncell * (double)o.n_steps;
+    out->n_steps_run = steps;
+    out->cell_updates = (double)C * (double)p.ncell * (double)steps;
     out->device_ms = ms;
     out->stencil_samples = tim.samples;
     out->stencil_launches = tim.launches;

@@ -60,6 +60,8 @@ struct Req {
     bool fused = false;
     int variant = -1;                 // fused variant of this request
     int v3 = -1;                      // fused 3D step variant (-1: split 3D kernels)
+    cfi::ConvergenceStop conv;        // time-convergence stop (single-wave requests)
+    int steps_run = -1;
     int par = 0;                      // fused 3D: field array holding the current step
     int C = 0;
     size_t bytes = 0, off = 0;
@@ -210,6 +212,9 @@ std::string prepare(cf_server* S, Req& r) {
         R = std::max(1, R / 2);
     }
     if (r.bytes > S->arena.size()) return "request larger than the server's memory budget";
+    r.conv.on = r.opts.stop_tol > 0 && r.st.waves.size() == 1;
+    r.conv.tol = r.opts.stop_tol;
+    r.conv.every = r.conv.next = r.opts.stop_every > 0 ? r.opts.stop_every : 500;
     // host copies of the per-request tables
     r.ids.resize((size_t)cf::kNumComp * p.ncell);
     for (int c = 0; c < cf::kNumComp; ++c)
@@ -610,7 +615,19 @@ void loop(cf_server* S) {
         // ---- retire finished requests / start next channel waves ----
         for (auto it = S->active.begin(); it != S->active.end();) {
             Req& r = **it;
-            const bool wave_done = S->clock - r.start >= r.opts.n_steps;
+            bool wave_done = S->clock - r.start >= r.opts.n_steps;
+            const long long done = std::min<long long>(S->clock - r.start, r.opts.n_steps);
+            if (!wave_done && r.conv.on && done >= r.conv.next) {
+                // time-convergence check on the accumulators (the stream has drained)
+                while (r.conv.next <= done) r.conv.next += r.conv.every;
+                std::vector<double> a((size_t)r.C * 2);
+                if (hipMemcpyAsync(a.data(), S->arena_base + r.off + r.o_acc, a.size() * 8, hipMemcpyDeviceToHost,
+                                   S->stream) == hipSuccess &&
+                    hipStreamSynchronize(S->stream) == hipSuccess && r.conv.update(a, r.chans)) {
+                    wave_done = true;
+                    r.steps_run = (int)done;
+                }
+            }
             if (!wave_done && !r.cancel) {
                 ++it;
                 continue;
@@ -753,6 +770,7 @@ static cf_status report(cf_server* S, const std::shared_ptr<Req>& r, int* state,
     if (state) *state = r->state;
     if (r->state == ST_DONE && out) {
         cfi::StencilTiming tim;
+        tim.steps_run = r->steps_run;
         tim.variant = r->variant >= 0 ? r->variant : r->v3;   // fused 2D tile or fused 3D band shape
         cf_opts o = r->opts;
         const bool ok = cfi::fill_result(*r->prob, r->chans, r->acc, {}, o, (r->t_done - r->t_admit) * 1e3, tim,

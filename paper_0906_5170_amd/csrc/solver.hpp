@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -53,6 +54,31 @@ struct StencilTiming {
     int samples = 0;
     int launches = 0;
     int variant = -1;
+    int steps_run = -1;     // time steps run (-1: all of opts.n_steps)
+};
+
+// Time-convergence stop: every `every` steps the partial force F(T') is
+// formed from the FP64 accumulators on the host; the run ends once two
+// consecutive windows change it by at most tol |F(T')|.
+struct ConvergenceStop {
+    bool on = false;
+    double tol = 0;
+    int every = 500;
+    int next = 500;
+    int calm = 0;
+    double f_prev = 0;
+    bool have_prev = false;
+    // F(T') from (sum, compensation) pairs and the channel signs
+    bool update(const std::vector<double>& acc, const std::vector<cf::Channel>& chans) {
+        double f = 0;
+        for (size_t c = 0; c < chans.size(); ++c) f += chans[c].sign * (acc[2 * c] + acc[2 * c + 1]);
+        f /= 3.14159265358979323846;
+        const bool quiet = have_prev && std::abs(f - f_prev) <= tol * std::abs(f);
+        calm = quiet ? calm + 1 : 0;
+        f_prev = f;
+        have_prev = true;
+        return calm >= 2;
+    }
 };
 
 // Stage the tables of one problem for the given channels and options.

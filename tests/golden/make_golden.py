@@ -6,6 +6,8 @@ casimir_inputs; no value comes from the HIP library.
     python tests/golden/make_golden.py c2      # 2D TE+TM piston, 400x200, T=10000
     python tests/golden/make_golden.py c1      # 2D TM piston, 80x40, T=2000
     python tests/golden/make_golden.py c4s     # 3D sphere-plate 192^3: 5 channels, 24 steps
+    python tests/golden/make_golden.py c4f     # the same 5 channels over the full T = 6000
+    python tests/golden/make_golden.py c3      # uneven piston set: members 0 and 23, full T
 """
 import json
 import os
@@ -17,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
-from casimir_inputs import c1_piston_tm_fp64, c2_piston_tetm_fp32, c4_sphere_plate  # noqa: E402
+from casimir_inputs import c1_piston_tm_fp64, c2_piston_tetm_fp32, c3_uneven_set, c4_sphere_plate  # noqa: E402
 
 CASES = {
     "c1": ("c1_piston_tm_oracle.json", c1_piston_tm_fp64),
@@ -41,6 +43,43 @@ def c4_sample(workers=5):
     with open(os.path.join(HERE, "c4_sphere_plate_sample_oracle.json"), "w") as f:
         json.dump(out, f, indent=1)
     print("c4s", f"{time.time() - t0:.1f}s")
+
+
+def c4_full(workers=5):
+    """The C4 sample channels integrated over the configuration's full T:
+    the FP64 reference for the 3D FP32 error (channel integrals, not a
+    force: the other 1275 channels are beyond the oracle's reach)."""
+    wl = c4_sphere_plate()
+    t0 = time.time()
+    r = oracle.solve(wl, channel_subset=C4_SUBSET, workers=workers, chunk=1)
+    out = dict(workload=wl.name, shape=list(wl.shape), n_steps=wl.n_steps, subset=C4_SUBSET,
+               per_channel=[float(v) for v in r.acc], sign=[float(v) for v in r.sign],
+               oracle_seconds=time.time() - t0,
+               source="oracle.solve (FP64 NumPy), written by tests/golden/make_golden.py")
+    with open(os.path.join(HERE, "c4_sphere_plate_channels_full_T_oracle.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("c4f", f"{time.time() - t0:.1f}s")
+
+
+C3_MEMBERS = [0, 23]
+
+
+def c3_members(workers=8):
+    """Members 0 (h = 0.1, 400 x 84) and 23 (h = 2.0, 400 x 160) of the
+    uneven piston set, full T = 10000."""
+    wls = c3_uneven_set()
+    t0 = time.time()
+    members = []
+    for k in C3_MEMBERS:
+        wl = wls[k]
+        r = oracle.solve(wl, workers=workers, chunk=16)
+        members.append(dict(index=k, h=wl.meta["h"], workload=wl.name, shape=list(wl.shape), force=r.force,
+                            per_channel=[float(v) for v in r.acc]))
+        print("c3 member", k, r.force, f"{time.time() - t0:.1f}s", flush=True)
+    out = dict(n_steps=wls[0].n_steps, members=members, oracle_seconds=time.time() - t0,
+               source="oracle.solve (FP64 NumPy), written by tests/golden/make_golden.py")
+    with open(os.path.join(HERE, "c3_uneven_members_oracle.json"), "w") as f:
+        json.dump(out, f, indent=1)
 
 
 def main(which, workers=8):
@@ -68,5 +107,9 @@ def main(which, workers=8):
 if __name__ == "__main__":
     if sys.argv[1] == "c4s":
         c4_sample()
+    elif sys.argv[1] == "c4f":
+        c4_full()
+    elif sys.argv[1] == "c3":
+        c3_members()
     else:
         main(sys.argv[1])

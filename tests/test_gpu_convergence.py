@@ -1,0 +1,101 @@
+"""Time-convergence stop (the partial force F(T') settles as T' grows, as
+the paper's force-error-versus-time figure shows): a run with a tolerance
+ends early, reports the steps it ran, and its force stays within a small
+multiple of the tolerance of the full-length run.  The FP64 oracle's trace
+of this piston settles to 6e-10 relative by T' = 500 of 3000 steps."""
+import numpy as np
+import pytest
+
+from casimir_inputs.configs import piston2d
+from casimir_inputs.geometry import Box, Sphere, Workload, rasterize
+
+pytestmark = pytest.mark.gpu
+MiB = 1 << 20
+BIG = 1e30
+
+
+def announce(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+def piston():
+    return piston2d(40, 31, 4, 10, 5, 10, 13, 10.0, pol="TM+TE", n_steps=3000, n_harm=8)
+
+
+def opts_of(wl, **over):
+    o = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol=wl.pol, kernel=wl.kernel,
+             precision="fp64")
+    o.update(over)
+    return o
+
+
+@pytest.mark.parametrize("path", ["fused", "split"])
+def test_stop_ends_early_within_tolerance(cf, path):
+    announce(f"convergence stop, 2D piston, {path}")
+    wl = piston()
+    p = cf.Problem.from_workload(wl)
+    extra = dict(split=True) if path == "split" else {}
+    full = p.solve(**opts_of(wl, **extra))
+    assert full["n_steps_run"] == wl.n_steps
+    r = p.solve(**opts_of(wl, stop_tol=1e-8, stop_every=100, **extra))
+    print(f"[stop] {path}: {r['n_steps_run']} of {wl.n_steps} steps, "
+          f"rel diff {abs(r['force'] / full['force'] - 1):.2e}", flush=True)
+    assert 300 <= r["n_steps_run"] < 1200
+    assert abs(r["force"] / full["force"] - 1) <= 1e-7
+    assert r["cell_updates"] == pytest.approx(full["cell_updates"] * r["n_steps_run"] / wl.n_steps)
+
+
+def test_stop_off_with_channel_waves(cf):
+    """With channels in several waves the partial force is not known during a
+    wave, so the stop does not apply and the run is the full one."""
+    announce("convergence stop ignored with channel waves")
+    wl = piston().replace(n_steps=400)
+    p = cf.Problem.from_workload(wl)
+    full = p.solve(**opts_of(wl))
+    r = p.solve(**opts_of(wl, stop_tol=1e-3, stop_every=50, max_resident=7))
+    assert r["n_steps_run"] == wl.n_steps
+    np.testing.assert_array_equal(r["per_channel"], full["per_channel"])
+
+
+def test_stop_3d(cf):
+    announce("convergence stop, 3D fused step")
+    nx, ny, nz, pml = 12, 12, 26, 4
+    zlo = pml + 2
+    prims = [Box((-BIG, -BIG, -BIG), (BIG, BIG, zlo), 1), Sphere((nx / 2 + 0.3, ny / 2, zlo + 5.5), 1.7, 2)]
+    wl = Workload(name="s3", ndim=3, shape=(nx, ny, nz), res=4.0, bc=("periodic", "periodic", "pml"),
+                  pml_cells=(0, 0, pml), eps=[1.8, float("-inf"), 3.0], mu=[1.0, 1.0, 1.0],
+                  comp_ids=rasterize((nx, ny, nz), prims), s_lo=(nx // 2 - 3, ny // 2 - 3, zlo + 2),
+                  s_hi=(nx // 2 + 4, ny // 2 + 3, zlo + 9), n_harm=2, force_axis=2, pol="3D",
+                  kernel="general", n_steps=1500)
+    p = cf.Problem.from_workload(wl)
+    full = p.solve(**opts_of(wl, keep_gamma=True))
+    tr = full["trace"]
+    F = tr[-1]
+    # a tolerance the partial force meets over the last 300 steps of the run
+    checks = np.arange(50, wl.n_steps + 1, 50)
+    d = np.abs(np.diff(tr[checks - 1])) / abs(F)
+    tol = float(2 * d[-6:].max())
+    r = p.solve(**opts_of(wl, stop_tol=tol, stop_every=50))
+    T = r["n_steps_run"]
+    print(f"[stop] 3d: tol {tol:.2e}, {T} of {wl.n_steps} steps, "
+          f"rel diff {abs(r['force'] / F - 1):.2e}", flush=True)
+    assert r["fused"] and T < wl.n_steps and T % 50 == 0
+    # the stopped run's force is the full run's partial force at that step
+    assert r["force"] == pytest.approx(tr[T - 1], rel=1e-9)
+
+
+def test_server_stop(cf):
+    announce("convergence stop in the server")
+    wl = piston()
+    p = cf.Problem.from_workload(wl)
+    o = opts_of(wl, precision="fp32")
+    full = p.solve(**o)
+    with cf.Server(128 * MiB) as srv:
+        t_stop = srv.submit(p, stop_tol=1e-6, stop_every=80, **o)
+        t_full = srv.submit(p, **o)
+        rs = srv.wait(t_stop, timeout=120)
+        rf = srv.wait(t_full, timeout=120)
+    assert rf["n_steps_run"] == wl.n_steps
+    np.testing.assert_array_equal(rf["per_channel"], full["per_channel"])
+    assert rs["n_steps_run"] < wl.n_steps
+    assert abs(rs["force"] / full["force"] - 1) <= 1e-5

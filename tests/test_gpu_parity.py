@@ -250,3 +250,25 @@ def test_c2_full_size_bench_configuration(cf):
     print(f"c2 fp32 force {g['force']:.12e} oracle {ref.force:.12e} rel {rel:.3e}")
     assert rel <= 1e-4
     np.testing.assert_allclose(g["per_channel"], ref.acc, rtol=0, atol=1e-5 * np.max(np.abs(ref.acc)))
+
+
+def test_c3_members_full_T_vs_oracle(cf):
+    """Members 0 (h = 0.1, 400 x 84) and 23 (h = 2.0, 400 x 160) of the uneven
+    piston set at the full T = 10000, FP32 fields, advanced together with
+    the other 22 members in one batched solve, against the stored FP64
+    oracle forces: within 1e-4 relative."""
+    path = os.path.join(HERE, "golden", "c3_uneven_members_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("golden uneven-set members not generated")
+    ref = json.load(open(path))
+    from casimir_inputs import c3_uneven_set
+    announce("c3 24 uneven pistons batched, full T=10000, fp32")
+    wls = c3_uneven_set()
+    probs = [cf.Problem.from_workload(w) for w in wls]
+    w0 = wls[0]
+    res = cf.batch_solve(probs, sigma=w0.sigma, courant=w0.courant, n_steps=w0.n_steps, pol=w0.pol,
+                         kernel=w0.kernel, precision="fp32")
+    for m in ref["members"]:
+        rel = abs(res[m["index"]]["force"] / m["force"] - 1)
+        print(f"[precision] c3 member {m['index']} fp32 force rel err {rel:.3e}", flush=True)
+        assert rel <= 1e-4

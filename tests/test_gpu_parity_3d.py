@@ -144,3 +144,20 @@ def test_c4_full_size_sample(cf):
     np.testing.assert_allclose(g["gamma"], gam_ref, rtol=0, atol=2e-5 * scale.max())
     np.testing.assert_allclose(g["per_channel"], ref["per_channel"], rtol=0,
                                atol=2e-5 * np.max(np.abs(ref["per_channel"])))
+
+
+def test_c4_channels_full_T(cf):
+    """The five sampled channels of the 192^3 cell over the full T = 6000,
+    FP32 fields with FP64 accumulation, against the stored FP64 oracle
+    integrals: within 1e-4 relative per channel."""
+    path = os.path.join(HERE, "golden", "c4_sphere_plate_channels_full_T_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("golden full-T channel integrals not generated")
+    ref = json.load(open(path))
+    announce("c4 192^3 five channels, full T=6000, fp32")
+    wl = c4_sphere_plate()
+    g = run(cf, wl, channel_subset=ref["subset"])
+    acc = np.array(ref["per_channel"])
+    rel = np.abs(g["per_channel"] - acc) / np.abs(acc)
+    print(f"[precision] c4 channel rel err max {rel.max():.3e}", flush=True)
+    assert rel.max() <= 1e-4
