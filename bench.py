@@ -129,6 +129,7 @@ def _serve(cf, srv_budget, reqs, probs, opts_list, lam_times=True):
     with cf.Server(srv_budget) as srv:
         t0 = time.perf_counter()
         tickets = []
+        o_of = {}
         for q, p, o in zip(reqs, probs, opts_list):
             if lam_times:
                 delay = q.t_arrive - (time.perf_counter() - t0)
@@ -136,6 +137,7 @@ def _serve(cf, srv_budget, reqs, probs, opts_list, lam_times=True):
                     time.sleep(delay)
             try:
                 tickets.append((q, srv.submit(p, **o)))
+                o_of[tickets[-1][1]] = o["n_steps"]
             except cf.CfError as e:
                 tickets.append((q, None))
                 log(f"[bench] serve: request {q.index} rejected: {e}")
@@ -146,7 +148,7 @@ def _serve(cf, srv_budget, reqs, probs, opts_list, lam_times=True):
             r = srv.wait(t, timeout=-1)
             ts, ta, td = srv.times(t)
             rows.append(dict(kind=q.kind, submit=ts, admit=ta, done=td, cu=r["cell_updates"],
-                             fused=r["fused"], rejected=False))
+                             fused=r["fused"], rejected=False, steps=r["n_steps_run"], t_full=o_of[t]))
             srv.release(t)
     return rows
 
@@ -160,7 +162,8 @@ def _summary(rows):
            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
            "mean_queue_wait_s": float(wait.mean()), "span_s": span,
            "cell_updates_per_s": sum(r["cu"] for r in ok) / span,
-           "fused_requests": sum(1 for r in ok if r["fused"])}
+           "fused_requests": sum(1 for r in ok if r["fused"]),
+           "steps_run_fraction": sum(r["steps"] for r in ok) / sum(r["t_full"] for r in ok)}
     for kind in sorted({r["kind"] for r in ok}):
         lk = np.array([r["done"] - r["submit"] for r in ok if r["kind"] == kind])
         out[f"{kind}_p50_s"] = float(np.percentile(lk, 50))
@@ -197,10 +200,21 @@ def bench_serving(cf, torch, args, rate_3d):
     lam = 0.7 * cap
     log(f"[bench] serve: capacity {cap:.2f} req/s; Poisson pass at {lam:.2f} req/s ...")
     matched = _summary(_serve(cf, budget, rescale_arrivals(reqs, lam), probs, opts))
+    # the same requests with the time-convergence stop (FP32 noise floor 1e-6,
+    # checked every 100 steps): all at once, then at 0.7 of that capacity
+    stop_opts = [dict(o, stop_tol=1e-6, stop_every=100) for o in opts]
+    sat_stop = _summary(_serve(cf, budget, reqs, probs, stop_opts, lam_times=False))
+    cap_stop = sat_stop["n"] / sat_stop["span_s"]
+    matched_stop = _summary(_serve(cf, budget, rescale_arrivals(reqs, 0.7 * cap_stop), probs, stop_opts))
+    log(f"[bench] serve with stop: capacity {cap_stop:.2f} req/s, steps run {sat_stop['steps_run_fraction']:.2f}, "
+        f"p50 {matched_stop['p50_s']:.3f} s p99 {matched_stop['p99_s']:.3f} s")
     res = {"stream": f"piston class of the seeded mixed stream (seed 0), {len(reqs)} requests: "
                      "clearance h ~ U[0.1,2], res ~ U{20..60}, T = 250 res, 40 harmonics/face, TE+TM, FP32",
            "budget_bytes": budget, "saturated": sat, "capacity_req_per_s": cap,
-           "load_matched": dict(matched, lam_req_per_s=lam, load=0.7)}
+           "load_matched": dict(matched, lam_req_per_s=lam, load=0.7),
+           "with_convergence_stop": {"stop_tol": 1e-6, "stop_every": 100, "saturated": sat_stop,
+                                     "capacity_req_per_s": cap_stop,
+                                     "load_matched": dict(matched_stop, lam_req_per_s=0.7 * cap_stop, load=0.7)}}
     # the literal mixed stream (4 req/s, 70 % pistons / 30 % 3D cells): offered
     # load against capacity from the measured per-class rates
     if rate_3d:
