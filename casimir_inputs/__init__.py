@@ -29,6 +29,8 @@ from .configs import (
     c2_piston_tetm_fp32,
     c3_uneven_set,
     c4_sphere_plate,
+    cyl_piston,
+    c_cyl_piston,
     small_cases,
 )
 
@@ -48,5 +50,7 @@ __all__ = [
     "c2_piston_tetm_fp32",
     "c3_uneven_set",
     "c4_sphere_plate",
+    "cyl_piston",
+    "c_cyl_piston",
     "small_cases",
 ]

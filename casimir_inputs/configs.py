@@ -202,6 +202,63 @@ def c4_sphere_plate(**over) -> Workload:
     return sphere_plate3d(192, 0.45, **kw)
 
 
+def cyl_piston(res: int = 40, h_u: float = 0.5, length_u: float = 10.0, n_harm: int = 3, m_max: int = 2,
+               sidewall: str = "pec", margin: int = 2, **opts) -> Workload:
+    """Cylindrically symmetric piston (Sec. III D, Fig. 7): the 2D piston's
+    blocks rotated about their common axis become two PEC cylinders of
+    radius 0.25 and length 1.0, a = 1.0 apart on the axis, inside a tube
+    whose wall lies h/2 outside them (the sidewalls joined into a tube).
+
+    Grid (x = z along the axis, y = r): nz = length_u res cells with PEC
+    ends; nr = round((0.25 + h/2) res) + 1 cells, the wall at r = nr - 1/2
+    cells.  ``sidewall`` "pmc" lines the tube with a two-cell PMC layer
+    (mu = -inf).  S: the right cylinder grown by ``margin`` cells, closed on
+    the axis.  n_harm cosine harmonics per face, orders m = 0..m_max.
+    """
+    nz = int(round(length_u * res))
+    rb = int(round(0.25 * res))
+    nr = int(round((0.25 + 0.5 * h_u) * res)) + 1
+    blen = int(round(1.0 * res))
+    gap = int(round(1.0 * res))
+    left_hi = (nz - gap) // 2
+    left_lo = left_hi - blen
+    right_lo = left_hi + gap
+    right_hi = right_lo + blen
+    eps = [1.0, PEC, 1.0]
+    mu = [1.0, 1.0, 1.0]
+    # grid y = r + 1/2: a cylinder of radius rb cells covers y < rb + 1/2
+    prims = [Box((left_lo, -BIG, -BIG), (left_hi, rb + 0.5, BIG), 1),
+             Box((right_lo, -BIG, -BIG), (right_hi, rb + 0.5, BIG), 1)]
+    if sidewall == "pmc":
+        mu[2] = PMC
+        prims.insert(0, Box((-BIG, nr - 2.0, -BIG), (BIG, BIG, BIG), 2))
+    elif sidewall != "pec":
+        raise ValueError(sidewall)
+    ids = rasterize((nz, nr, 1), prims)
+    if rb + margin >= nr - (2 if sidewall == "pmc" else 0) - 1:
+        raise ValueError("clearance too small for the surface margin")
+    kw = dict(sigma=1.0, courant=0.5, n_steps=250 * res, pol="3D", kernel="general", precision="fp32")
+    kw.update(opts)
+    return Workload(
+        name=kw.pop("name", f"cyl_piston_{nz}x{nr}_h{h_u:g}"), ndim=2, shape=(nz, nr, 1), res=float(res),
+        bc=("pec", "pec", "periodic"), pml_cells=(0, 0, 0), eps=eps, mu=mu, comp_ids=ids,
+        s_lo=(right_lo - margin, 0, 0), s_hi=(right_hi + margin, rb + margin, 1), n_harm=int(n_harm),
+        force_axis=0, coord="cylindrical", m_max=int(m_max),
+        meta=dict(h=float(h_u), tube_radius=(nr - 0.5) / res, cyl_radius=rb / res, sidewall=sidewall,
+                  blocks=((left_lo, left_hi), (right_lo, right_hi))),
+        **kw,
+    )
+
+
+def c_cyl_piston(**over) -> Workload:
+    """Cylindrical piston at resolution 40, h = 0.5, n, m in {0, 1, 2}
+    (3 harmonics per face, orders 0..2), 10000 steps, FP32 fields."""
+    kw = dict(res=40, h_u=0.5, n_harm=3, m_max=2, n_steps=10000, precision="fp32",
+              name="cyl_piston_res40_h0.5")
+    kw.update(over)
+    return cyl_piston(**kw)
+
+
 def small_cases():
     """Small workloads the oracle finishes in seconds (parity test sizes)."""
     return {

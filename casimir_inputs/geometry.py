@@ -103,6 +103,10 @@ class Workload:
     force_axis 0/1/2
     sigma, courant, n_steps, pol ("TM", "TE", "TM+TE", "3D"), kernel
     ("zinv2d" | "general"), precision ("fp64" | "fp32")
+    coord      "cartesian" or "cylindrical": a cylindrical workload is a 2D
+               (z, r) grid, x = z along the symmetry axis, y = r + 1/2
+               (cells), the tube wall at r = ny - 1/2
+    m_max      cylindrical workloads: azimuthal orders 0..m_max
     """
 
     name: str
@@ -125,6 +129,8 @@ class Workload:
     kernel: str = "zinv2d"
     precision: str = "fp64"
     meta: dict = dataclasses.field(default_factory=dict)
+    coord: str = "cartesian"
+    m_max: int = 0
 
     def replace(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)

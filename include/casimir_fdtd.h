@@ -73,12 +73,35 @@ enum { CF_PATH_BATCHED = 0, CF_PATH_PLAIN = 1 };
 /* Component order of every per-component array: Ex, Ey, Ez, Hx, Hy, Hz. */
 enum { CF_EX = 0, CF_EY, CF_EZ, CF_HX, CF_HY, CF_HZ };
 
+/*
+ * Coordinates (cf_grid.coord).  CF_COORD_CYLINDRICAL describes a problem
+ * with cylindrical symmetry (Sec. III D; Appendix, harmonic expansion in
+ * cylindrical coordinates): fields proportional to exp(i m phi) reduce to
+ * the (r, z) half plane, solved once per azimuthal order m = 0..m_max.
+ *   - ndim = 2; axis 0 is z (the symmetry axis, n[0] cells), axis 1 is r
+ *     (n[1] cells); n[2] = 1.  bc[0] is CF_BC_PEC or CF_BC_PERIODIC; bc[1]
+ *     must be CF_BC_PEC: a perfectly conducting tube wall at
+ *     r = (n[1] - 1/2) / res.
+ *   - The six component slots hold Ex = E_z, Ey = E_r, Ez = -i E_phi,
+ *     Hx = -i H_z, Hy = -i H_r, Hz = H_phi (the phase factors make the
+ *     reduced system real).  Components with doubled Yee offset 1 along
+ *     axis 1 (Ey, Hx, Hz) sit at r = j / res, the others (Ex, Ez, Hy) at
+ *     r = (j - 1/2) / res; row j = 0 of the latter lies outside the domain
+ *     and stays zero.  comp_id uses the Cartesian index (j * n[0] + i).
+ *   - The symmetry axis: H_z on it follows the circulation of E_phi around
+ *     the disk of radius half a cell (m = 0) and is zero otherwise; E_r and
+ *     H_phi on it are the next row's values for m = 1 and zero otherwise
+ *     (the interpolation onto S applies this; the arrays hold zero there).
+ */
+enum { CF_COORD_CARTESIAN = 0, CF_COORD_CYLINDRICAL = 1 };
+
 typedef struct cf_grid {
     int ndim;          /* 2 or 3                                                   */
     int n[3];          /* cells nx, ny, nz (nz == 1 when ndim == 2)               */
     double res;        /* cells per unit length                                    */
     int bc[3];         /* CF_BC_* per axis; 2D problems ignore bc[2]               */
     int pml_cells[3];  /* PML thickness in cells at each end of a CF_BC_PML axis   */
+    int coord;         /* CF_COORD_* (0 = Cartesian)                               */
 } cf_grid;
 
 /*
@@ -112,7 +135,29 @@ typedef struct cf_surface {
     int hi[3];
     int n_harm;
     int force_axis;    /* 0, 1 or 2 */
+    int m_max;         /* cylindrical problems: azimuthal orders 0..m_max (<= 32) */
 } cf_surface;
+
+/*
+ * Cylindrical problems.  S is the surface of revolution of the (z, r)
+ * rectangle lo..hi: lo[1] = 0 closes it on the axis (no inner face),
+ * hi[1] = n[1] extends it to the tube wall (no outer face; the stress on a
+ * conducting wall has no axial component).  Samples along r sit at
+ * r = k + 1/2 cells; a face ending at the wall ends with a half-cell sample
+ * at r = n[1] - 1 of weight 1/2.  The per-face basis is the cosine basis
+ * made orthonormal under these quadrature weights (Gram-Schmidt); the line
+ * element is the Cartesian ds of the (r, z) plane (the Jacobian r cancels).
+ * force_axis must be 0 (the axial force).  Each order m runs on its own time
+ * step: courant_m = courant for m <= 1 and min(courant, 1/(1 + m)) above
+ * (the m/r couplings raise the scheme's largest frequency), for
+ * T_m = round(n_steps courant / courant_m) steps (the same physical time),
+ * with K sampled at its own steps.  The force is
+ *   F = (1/pi) sum_m w_m sum_c s_c sum_k dt_m K(t_k) Gamma_c(t_k),
+ * w_0 = 1, w_m>0 = 2 (the -m term is the conjugate of the +m term).
+ * Options: pol = CF_POL_3D (all six components), courant <= 0.5, the split
+ * update kernels only (tile_variant is ignored); stop_tol and the server
+ * are not available (CF_E_UNSUPPORTED).
+ */
 
 /* CF_FLAG_KEEP_GAMMA keeps Gamma_c(t_m) for the gamma/trace outputs.
  * CF_FLAG_TIME_STENCIL brackets sampled launches of the field-update
@@ -167,6 +212,8 @@ typedef struct cf_info {
     int n_comp;            /* field components per channel (3 in 2D, 6 in 3D) */
     size_t workspace_bytes;
     double eps_s, mu_s;    /* medium S lies in                                 */
+    int n_steps_max;       /* time steps of the longest run (n_steps unless    */
+                           /* a cylindrical order runs on a smaller step)      */
 } cf_info;
 
 /*
@@ -178,6 +225,9 @@ typedef struct cf_info {
  * trace[m] = F after m+1 steps (Fig. 12; needs CF_FLAG_KEEP_GAMMA).
  * Optional arrays may be NULL.  With a channel subset, per_channel and gamma
  * follow the subset order and force/per_* sum over the subset only.
+ * Cylindrical problems: gamma has cf_info.n_steps_max rows, row k holding
+ * step k + 1 of each channel's own order (zero past its T_m); trace is not
+ * defined (orders advance on different time steps) and is left untouched.
  */
 typedef struct cf_result {
     double force;
@@ -218,7 +268,9 @@ cf_status cf_problem_info(const cf_problem* p, const cf_opts* opts, cf_info* out
  * for channel c, face index, harmonic label, kind (0 = E-current source,
  * 1 = H-current source), source and measured component (CF_EX..CF_HZ) and
  * sign (outward-normal side times stress coefficient).  Arrays of length
- * >= n (n = cf_info.n_channels); NULL arrays are skipped. */
+ * >= n (n = cf_info.n_channels); NULL arrays are skipped.  Cylindrical
+ * problems list the channels of order 0, then 1, ... m_max; their label is
+ * m * n_harm + n and their sign includes the order weight w_m. */
 cf_status cf_channel_table(const cf_problem* p, const cf_opts* opts, int n, int* face,
                            int* label, int* kind, int* src, int* meas, double* sign);
 

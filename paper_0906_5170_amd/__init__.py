@@ -22,6 +22,7 @@ POL = {"TM": 1, "TE": 2, "TM+TE": 3, "3D": 4}
 KERNEL = {"general": 0, "zinv2d": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 PATH = {"batched": 0, "plain": 1}
+COORD = {"cartesian": 0, "cylindrical": 1}
 FLAG_KEEP_GAMMA = 1
 FLAG_TIME_STENCIL = 2
 FLAG_SPLIT = 4
@@ -40,7 +41,7 @@ class CfError(RuntimeError):
 
 class _Grid(C.Structure):
     _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("res", C.c_double), ("bc", C.c_int * 3),
-                ("pml_cells", C.c_int * 3)]
+                ("pml_cells", C.c_int * 3), ("coord", C.c_int)]
 
 
 class _Materials(C.Structure):
@@ -50,7 +51,7 @@ class _Materials(C.Structure):
 
 class _Surface(C.Structure):
     _fields_ = [("lo", C.c_int * 3), ("hi", C.c_int * 3), ("n_harm", C.c_int),
-                ("force_axis", C.c_int)]
+                ("force_axis", C.c_int), ("m_max", C.c_int)]
 
 
 class _Opts(C.Structure):
@@ -64,7 +65,7 @@ class _Opts(C.Structure):
 class _Info(C.Structure):
     _fields_ = [("n_channels", C.c_int), ("n_faces", C.c_int), ("per_harmonic_len", C.c_int),
                 ("n_comp", C.c_int), ("workspace_bytes", C.c_size_t), ("eps_s", C.c_double),
-                ("mu_s", C.c_double)]
+                ("mu_s", C.c_double), ("n_steps_max", C.c_int)]
 
 
 class _Result(C.Structure):
@@ -190,10 +191,11 @@ class Problem:
     def __init__(self, ndim: int, shape: Sequence[int], res: float, bc: Sequence[str],
                  eps: Sequence[float], mu: Sequence[float], comp_ids: Dict[str, np.ndarray],
                  s_lo: Sequence[int], s_hi: Sequence[int], n_harm: int, force_axis: int,
-                 pml_cells: Sequence[int] = (0, 0, 0)):
+                 pml_cells: Sequence[int] = (0, 0, 0), coord: str = "cartesian", m_max: int = 0):
         lib = load()
         g = _Grid()
         g.ndim = int(ndim)
+        g.coord = COORD[coord]
         for a in range(3):
             g.n[a] = int(shape[a])
             g.bc[a] = BC[bc[a]]
@@ -222,10 +224,12 @@ class Problem:
             s.hi[a] = int(s_hi[a])
         s.n_harm = int(n_harm)
         s.force_axis = int(force_axis)
+        s.m_max = int(m_max)
         h = C.c_void_p()
         _check(lib.cf_problem_create(C.byref(g), C.byref(m), C.byref(s), C.byref(h)))
         self._h = h
         self.ndim = ndim
+        self.coord = coord
         self.shape = tuple(int(v) for v in shape)
         self.res = float(res)
         self._ids = None
@@ -233,7 +237,7 @@ class Problem:
     @classmethod
     def from_workload(cls, wl) -> "Problem":
         return cls(wl.ndim, wl.shape, wl.res, wl.bc, wl.eps, wl.mu, wl.comp_ids, wl.s_lo, wl.s_hi,
-                   wl.n_harm, wl.force_axis, wl.pml_cells)
+                   wl.n_harm, wl.force_axis, wl.pml_cells, coord=wl.coord, m_max=wl.m_max)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -281,7 +285,8 @@ class Problem:
         _check(load().cf_problem_info(self._h, C.byref(o), C.byref(inf)))
         return dict(n_channels=inf.n_channels, n_faces=inf.n_faces,
                     per_harmonic_len=inf.per_harmonic_len, n_comp=inf.n_comp,
-                    workspace_bytes=int(inf.workspace_bytes), eps_s=inf.eps_s, mu_s=inf.mu_s)
+                    workspace_bytes=int(inf.workspace_bytes), eps_s=inf.eps_s, mu_s=inf.mu_s,
+                    n_steps_max=inf.n_steps_max)
 
     def validate(self, **opts):
         o = self._opts(**opts)
@@ -314,7 +319,7 @@ class Problem:
             raise ValueError("workspace too small")
         o = self._opts(**opts)
         C_run = o.n_subset if o.n_subset > 0 else info["n_channels"]
-        T = int(opts.get("n_steps", 1000))
+        T = info["n_steps_max"]
         r, bufs = _result_buffers(info["per_harmonic_len"], C_run, T if opts.get("keep_gamma") else 0)
         _check(load().cf_solve(self._h, C.byref(o), C.c_void_p(workspace.data_ptr()), nbytes, C.byref(r)))
         out = _result_dict(r, bufs)

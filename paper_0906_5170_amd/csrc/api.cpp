@@ -81,7 +81,7 @@ std::vector<cf::Channel> selected_channels(const cf::Problem& p, const cf_opts& 
 // of `resident` consecutive channels; channel c uses field block c % resident.
 void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel>& chans, Staged& st) {
     st.chans = chans;
-    st.ncomp = cf::n_comp_for(p.grid.ndim);
+    st.ncomp = cf::n_comp(p);
     const int C = (int)chans.size();
     const bool plain = o.path == CF_PATH_PLAIN;
     st.resident = plain ? 1 : (o.max_resident > 0 ? std::min(o.max_resident, C) : C);
@@ -111,20 +111,46 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         basis_face_off[f] = (int)st.basis.size();
         st.basis.insert(st.basis.end(), p.basis[f].begin(), p.basis[f].end());
     }
+    // waves: consecutive runs of `resident` channels; the split cylindrical
+    // path groups the channels by azimuthal order first (one order per wave),
+    // the resident cylindrical kernel takes any mix of orders
+    st.cyl_res = p.cyl && !plain && !(o.flags & CF_FLAG_SPLIT);
+    std::vector<std::vector<int>> wave_lists;
+    std::vector<int> wave_order;
+    {
+        std::vector<std::vector<int>> groups;
+        if (p.cyl && !st.cyl_res) {
+            groups.assign(p.m_max + 1, {});
+            for (int c = 0; c < C; ++c) groups[chans[c].order].push_back(c);
+        } else {
+            groups.emplace_back();
+            for (int c = 0; c < C; ++c) groups[0].push_back(c);
+        }
+        for (size_t gi = 0; gi < groups.size(); ++gi)
+            for (size_t k0 = 0; k0 < groups[gi].size(); k0 += st.resident) {
+                const size_t k1 = std::min(groups[gi].size(), k0 + st.resident);
+                wave_lists.emplace_back(groups[gi].begin() + k0, groups[gi].begin() + k1);
+                wave_order.push_back(p.cyl && !st.cyl_res ? (int)gi : -1);
+            }
+    }
+    std::vector<int> block_of(C, 0);
+    for (const auto& wl : wave_lists)
+        for (size_t k = 0; k < wl.size(); ++k) block_of[wl[k]] = (int)k;
     const double res = p.grid.res;
     for (int c = 0; c < C; ++c) {
         const cf::Channel& ch = chans[c];
-        int gm = p.gather_of.at({ch.face, ch.meas});
-        int gs = p.gather_of.at({ch.face, ch.src});
+        int gm = p.gather_of.at({ch.face, cf::gather_key(p, ch.meas, ch.order)});
+        int gs = p.gather_of.at({ch.face, cf::gather_key(p, ch.src, ch.order)});
         add_gather(gm);
         add_gather(gs);
-        const int blk = c % st.resident;
+        const int blk = block_of[c];
         cf::ChanDev d{};
         d.field_off = (int64_t)blk * st.ncomp * p.ncell;
         d.psi_off = (int64_t)blk * 4 * st.psi_comp;
         d.src_off = d.field_off + (int64_t)cf::comp_slot(ch.pol, ch.src) * p.ncell;
         d.meas_off = d.field_off + (int64_t)cf::comp_slot(ch.pol, ch.meas) * p.ncell;
         d.kind = ch.kind;
+        d.order = ch.order;
         d.inst = 0;
         d.pol = ch.pol;
         d.local = c;
@@ -140,12 +166,13 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         st.max_uniq = std::max(st.max_uniq, d.n_uniq);
         st.dev.push_back(d);
     }
-    for (int w0 = 0; w0 < C; w0 += st.resident) {
-        const int w1 = std::min(C, w0 + st.resident);
+    for (size_t wi = 0; wi < wave_lists.size(); ++wi) {
+        const std::vector<int>& wl = wave_lists[wi];
         Wave w{};
+        w.order = wave_order[wi];
         auto add = [&](int pol, int* off, int* n) {
             *off = (int)st.slot_lists.size();
-            for (int c = w0; c < w1; ++c)
+            for (int c : wl)
                 if (pol == 0 || chans[c].pol == pol) st.slot_lists.push_back(c);
             *n = (int)st.slot_lists.size() - *off;
         };
@@ -155,6 +182,7 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         add(0, &w.all_off, &w.n_all);
         st.waves.push_back(w);
     }
+    if (p.cyl) return;   // split cylindrical kernels only
     if (!plain && p.grid.ndim == 3 && !(o.flags & CF_FLAG_SPLIT)) {
         cf::Grid3D g{};
         g.nx = p.nx;
@@ -246,7 +274,7 @@ static bool place_axis(int lo, int hi, int n, int w, int* base, int* ntiles, int
 
 TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, cf::TBShape sh) {
     TBPlan t;
-    if (p.grid.ndim != 2 || chans.empty()) return t;
+    if (p.grid.ndim != 2 || p.cyl || chans.empty()) return t;
     int xmin = p.nx, xmax = -1, ymin = p.ny, ymax = -1;
     for (const auto& ch : chans) {
         const cf::Gather& g = p.gathers[p.gather_of.at({ch.face, ch.meas})];
@@ -302,8 +330,10 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     const size_t C = st.chans.size();
     const size_t block = (size_t)st.resident * st.ncomp * p.ncell * fsz;
     L.ids = take((size_t)cf::kNumComp * p.ncell);
-    L.lut = take(2 * cf::kNumComp * 256 * 2 * fsz);
-    L.ktab = take((size_t)o.n_steps * 8);
+    const size_t n_orders = p.cyl ? (size_t)p.m_max + 1 : 1;   // cylindrical: one table per order
+    L.lut = take(n_orders * 2 * cf::kNumComp * 256 * 2 * fsz);
+    const int t_max = cf::max_steps(p, o);
+    L.ktab = take(n_orders * (size_t)t_max * 8);
     L.pml = take((size_t)4 * p.nz * 8);
     L.chans = take(C * sizeof(cf::ChanDev));
     L.slots = take(st.slot_lists.size() * sizeof(int) + 4);
@@ -315,7 +345,7 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.uw = take(st.uw.size() * 8 + 8);
     L.basis = take(st.basis.size() * 8 + 8);
     L.acc = take(C * 2 * 8);
-    L.gamma = (o.flags & CF_FLAG_KEEP_GAMMA) ? take((size_t)o.n_steps * C * 8) : off;
+    L.gamma = (o.flags & CF_FLAG_KEEP_GAMMA) ? take((size_t)t_max * C * 8) : off;
     L.fields = take(block);
     L.fields2 = st.variant >= 0 || st.f3d ? take(block) : off;
     L.psi = st.psi_comp > 0 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
@@ -396,10 +426,180 @@ struct GraphRun {
     }
 };
 
+// Cylindrical solve.  Every azimuthal order m has its own coefficient table
+// and K(t_k) (its own time step and step count).  Resident path: one launch
+// per wave, each block carrying one channel (any order) through all its
+// steps.  Split path (CF_FLAG_SPLIT, plain): waves of one order each; per
+// wave clear, kick, consistent start, then per step the H and E half steps
+// and the surface projection with the g-weighted accumulation.
+template <typename T>
+cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, const Layout& L, char* ws,
+                  hipStream_t s, std::vector<double>& acc_out, std::vector<double>& gamma_out, double* device_ms,
+                  StencilTiming* timing) {
+    const size_t C = st.chans.size();
+    const int t_max = cf::max_steps(p, o);
+    std::vector<uint8_t> ids((size_t)cf::kNumComp * p.ncell);
+    for (int c = 0; c < cf::kNumComp; ++c)
+        std::memcpy(ids.data() + (size_t)c * p.ncell, p.ids[c].data(), p.ncell);
+    auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    CF_HIP(up(L.ids, ids.data(), ids.size()));
+    CF_HIP(up(L.chans, st.dev.data(), st.dev.size() * sizeof(cf::ChanDev)));
+    CF_HIP(up(L.slots, st.slot_lists.data(), st.slot_lists.size() * sizeof(int)));
+    CF_HIP(up(L.gidx, st.gidx.data(), st.gidx.size() * 4));
+    CF_HIP(up(L.gw, st.gw.data(), st.gw.size() * 8));
+    CF_HIP(up(L.uidx, st.uidx.data(), st.uidx.size() * 4));
+    CF_HIP(up(L.uoff, st.uoff.data(), st.uoff.size() * 4));
+    CF_HIP(up(L.usamp, st.usamp.data(), st.usamp.size() * 4));
+    CF_HIP(up(L.uw, st.uw.data(), st.uw.size() * 8));
+    CF_HIP(up(L.basis, st.basis.data(), st.basis.size() * 8));
+    CF_HIP(hipMemsetAsync(ws + L.acc, 0, C * 2 * 8, s));
+    const bool keep_gamma = (o.flags & CF_FLAG_KEEP_GAMMA) != 0;
+    if (keep_gamma) CF_HIP(hipMemsetAsync(ws + L.gamma, 0, (size_t)t_max * C * 8, s));
+
+    T* fields = reinterpret_cast<T*>(ws + L.fields);
+    const cf::ChanDev* dch = reinterpret_cast<const cf::ChanDev*>(ws + L.chans);
+    const int* dslots = reinterpret_cast<const int*>(ws + L.slots);
+    const T* dlut = reinterpret_cast<const T*>(ws + L.lut);
+    const double* dk = reinterpret_cast<const double*>(ws + L.ktab);
+    double* dacc = reinterpret_cast<double*>(ws + L.acc);
+    double* dgam = keep_gamma ? reinterpret_cast<double*>(ws + L.gamma) : nullptr;
+    cf::SurfTables tabs;
+    tabs.gidx = reinterpret_cast<const int32_t*>(ws + L.gidx);
+    tabs.gw = reinterpret_cast<const double*>(ws + L.gw);
+    tabs.uidx = reinterpret_cast<const int32_t*>(ws + L.uidx);
+    tabs.uoff = reinterpret_cast<const int32_t*>(ws + L.uoff);
+    tabs.usamp = reinterpret_cast<const int32_t*>(ws + L.usamp);
+    tabs.uw = reinterpret_cast<const double*>(ws + L.uw);
+    tabs.basis = reinterpret_cast<const double*>(ws + L.basis);
+    const uint8_t* dids = reinterpret_cast<const uint8_t*>(ws + L.ids);
+    cf::Grid2D g{};
+    g.nx = p.nx;
+    g.ny = p.ny;
+    g.ncell = p.ncell;
+    g.perx = p.grid.bc[0] == CF_BC_PERIODIC;
+    g.pery = 0;
+    for (int c = 0; c < cf::kNumComp; ++c) g.ids[c] = dids + (size_t)c * p.ncell;
+    const double dA = 1.0 / p.grid.res;       // Cartesian line element of the (r, z) plane
+    const size_t field_bytes = (size_t)st.resident * st.ncomp * p.ncell * sizeof(T);
+    const double state_bytes = 2.0 * st.ncomp * sizeof(T);
+    // per-order tables: coefficients for courant_m, K(t_k) on dt_m
+    const size_t lut_len = 2 * cf::kNumComp * 256 * 2;
+    cf::CylOrders ord{};
+    ord.lut = dlut;
+    ord.lut_stride = (int64_t)lut_len;
+    ord.ktab = dk;
+    ord.ktab_stride = t_max;
+    std::vector<T> luts(lut_len * (p.m_max + 1));
+    std::vector<double> ktabs((size_t)t_max * (p.m_max + 1), 0.0);
+    for (int m = 0; m <= p.m_max; ++m) {
+        const double cm = cf::order_courant(p, o.courant, m);
+        ord.steps[m] = cf::order_steps(p, o, m);
+        ord.dt[m] = cm / p.grid.res;
+        std::vector<double> l64 = cf::coefficient_lut(p, o.sigma, cm);
+        std::copy(l64.begin(), l64.end(), luts.begin() + m * lut_len);
+        cf::kernel_table(o.kernel, o.sigma, ord.dt[m], ord.steps[m], ktabs.data() + (size_t)m * t_max);
+    }
+    CF_HIP(up(L.lut, luts.data(), luts.size() * sizeof(T)));
+    CF_HIP(up(L.ktab, ktabs.data(), ktabs.size() * 8));
+
+    hipEvent_t e0, e1;
+    CF_HIP(hipEventCreate(&e0));
+    CF_HIP(hipEventCreate(&e1));
+    Sampler smp;
+    smp.on = (o.flags & CF_FLAG_TIME_STENCIL) != 0;
+    if (smp.on) {
+        smp.ev.resize(2 * 256);
+        for (auto& e : smp.ev) CF_HIP(hipEventCreate(&e));
+        long total = 0;
+        for (const Wave& w : st.waves) total += st.cyl_res ? 1 : cf::order_steps(p, o, w.order);
+        smp.stride = std::max(1L, total / 200);
+    }
+    hipError_t err = hipSuccess;
+#define STEP_OK(expr)                     \
+    do {                                  \
+        err = (expr);                     \
+        if (err != hipSuccess) goto done; \
+    } while (0)
+    STEP_OK(hipEventRecord(e0, s));
+    for (const Wave& w : st.waves) {
+        const int* sl = dslots + w.all_off;
+        if (st.cyl_res) {
+            // one launch: every channel of the wave, any mix of orders
+            double cu = 0;
+            for (int k = 0; k < w.n_all; ++k) {
+                const int c = st.slot_lists[w.all_off + k];
+                cu += (double)p.ncell * ord.steps[st.chans[c].order];
+            }
+            const bool take = smp.begin(s);
+            STEP_OK(cf::launch_cyl_resident<T>(fields, dch, sl, w.n_all, g, ord, tabs, dA, dacc, dgam, (int)C, s));
+            smp.end(take, s, cu, cu * state_bytes);
+            continue;
+        }
+        const int m = w.order;
+        const int tm = ord.steps[m];
+        const double dt = ord.dt[m];
+        const T* lut_m = dlut + m * lut_len;
+        const double* k_m = dk + (size_t)m * t_max;
+        STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
+        STEP_OK(cf::launch_kick<T>(fields, dch, sl, w.n_all, st.max_uniq, tabs, s));
+        STEP_OK(cf::launch_hcyl<T>(1, m, fields, dch, sl, w.n_all, g, lut_m, s));
+        STEP_OK(cf::launch_ecyl<T>(1, m, fields, dch, sl, w.n_all, g, lut_m, s));
+        for (int k = 0; k < tm; ++k) {
+            const bool take = smp.begin(s);
+            STEP_OK(cf::launch_hcyl<T>(0, m, fields, dch, sl, w.n_all, g, lut_m, s));
+            STEP_OK(cf::launch_ecyl<T>(0, m, fields, dch, sl, w.n_all, g, lut_m, s));
+            const double cu = (double)w.n_all * p.ncell;
+            smp.end(take, s, cu, cu * state_bytes);
+            STEP_OK(cf::launch_surface<T>(fields, dch, sl, w.n_all, tabs, k_m, k, dt, dA, dacc, dgam, (int)C, s));
+        }
+    }
+    STEP_OK(hipEventRecord(e1, s));
+    STEP_OK(hipEventSynchronize(e1));
+    {
+        float ms = 0;
+        STEP_OK(hipEventElapsedTime(&ms, e0, e1));
+        *device_ms = ms;
+    }
+    if (smp.on) {
+        double tot = 0;
+        for (int k = 0; k < smp.taken; ++k) {
+            float ms = 0;
+            STEP_OK(hipEventElapsedTime(&ms, smp.ev[2 * k], smp.ev[2 * k + 1]));
+            tot += ms;
+        }
+        timing->samples = smp.taken;
+        timing->ms_total = tot;
+        timing->bytes_total = smp.bytes;
+        timing->cu_total = smp.cu;
+        timing->launches = smp.seen;
+    }
+    timing->variant = -1;
+    timing->steps_run = o.n_steps;
+    acc_out.assign(C * 2, 0.0);
+    STEP_OK(hipMemcpy(acc_out.data(), ws + L.acc, C * 2 * 8, hipMemcpyDeviceToHost));
+    if (keep_gamma) {
+        gamma_out.assign((size_t)t_max * C, 0.0);
+        STEP_OK(hipMemcpy(gamma_out.data(), ws + L.gamma, gamma_out.size() * 8, hipMemcpyDeviceToHost));
+    }
+done:
+#undef STEP_OK
+    if (err != hipSuccess) (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (auto& e : smp.ev) (void)hipEventDestroy(e);
+    if (err != hipSuccess)
+        return fail(CF_E_DEVICE, std::string("device step failed: ") + hipGetErrorString(err));
+    return CF_OK;
+}
+
 template <typename T>
 cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, const Layout& L,
                     char* ws, hipStream_t s, std::vector<double>& acc_out, std::vector<double>& gamma_out,
                     double* device_ms, StencilTiming* timing) {
+    if (p.cyl) return run_cyl<T>(p, o, st, L, ws, s, acc_out, gamma_out, device_ms, timing);
     const size_t C = st.chans.size();
     // ---- upload tables --------------------------------------------------
     std::vector<uint8_t> ids((size_t)cf::kNumComp * p.ncell);
@@ -844,7 +1044,7 @@ bool fill_result(const cf::Problem& p, const std::vector<cf::Channel>& chans, co
     if (out->per_channel)
         for (size_t c = 0; c < C; ++c) out->per_channel[c] = a[c];
     if (out->gamma && !gam.empty()) std::copy(gam.begin(), gam.end(), out->gamma);
-    if (out->trace && !gam.empty()) {
+    if (out->trace && !gam.empty() && !p.cyl) {
         std::vector<double> ktab(o.n_steps);
         const double dt = o.courant / p.grid.res;
         cf::kernel_table(o.kernel, o.sigma, dt, o.n_steps, ktab.data());
@@ -860,6 +1060,10 @@ bool fill_result(const cf::Problem& p, const std::vector<cf::Channel>& chans, co
     out->n_channels_run = (int)C;
     out->n_steps_run = steps;
     out->cell_updates = (double)C * (double)p.ncell * (double)steps;
+    if (p.cyl) {
+        out->cell_updates = 0;
+        for (size_t c = 0; c < C; ++c) out->cell_updates += (double)p.ncell * cf::order_steps(p, o, chans[c].order);
+    }
     out->device_ms = ms;
     out->stencil_samples = tim.samples;
     out->stencil_launches = tim.launches;
@@ -1298,14 +1502,12 @@ cf_status cf_problem_info(const cf_problem* h, const cf_opts* o, cf_info* out) {
     Layout L = layout_for(p, *o, sg);
     out->n_channels = (int)all.size();
     out->n_faces = (int)p.faces.size();
-    int lab = 0;
-    for (auto& v : p.labels)
-        for (int l : v) lab = std::max(lab, l + 1);
-    out->per_harmonic_len = lab;
-    out->n_comp = cf::n_comp_for(p.grid.ndim);
+    out->per_harmonic_len = cf::harmonic_len(p);
+    out->n_comp = cf::n_comp(p);
     out->workspace_bytes = L.total;
     out->eps_s = p.eps_s;
     out->mu_s = p.mu_s;
+    out->n_steps_max = cf::max_steps(p, *o);
     return CF_OK;
 }
 
@@ -1351,15 +1553,13 @@ cf_status cf_solve(cf_problem* h, const cf_opts* o, void* workspace, size_t ws_b
     auto chans = selected_channels(p, *o, &e2);
     if (!e2.empty()) return fail(CF_E_ARG, e2);
     const size_t C = chans.size();
-    int lab = 0;
-    for (auto& v : p.labels)
-        for (int l : v) lab = std::max(lab, l + 1);
+    const int lab = cf::harmonic_len(p);
     const bool keep_gamma = (o->flags & CF_FLAG_KEEP_GAMMA) != 0;
     if (out->per_harmonic && out->per_harmonic_len < lab) return fail(CF_E_ARG, "per_harmonic too short");
     if (out->per_face && out->per_face_len < 2 * p.grid.ndim) return fail(CF_E_ARG, "per_face too short");
     if (out->per_channel && out->per_channel_len < (int)C) return fail(CF_E_ARG, "per_channel too short");
-    if (out->gamma && (!keep_gamma || out->gamma_len < (long long)o->n_steps * (long long)C))
-        return fail(CF_E_ARG, "gamma needs CF_FLAG_KEEP_GAMMA and n_steps*channels entries");
+    if (out->gamma && (!keep_gamma || out->gamma_len < (long long)cf::max_steps(p, *o) * (long long)C))
+        return fail(CF_E_ARG, "gamma needs CF_FLAG_KEEP_GAMMA and n_steps_max*channels entries");
     if (out->trace && (!keep_gamma || out->trace_len < o->n_steps))
         return fail(CF_E_ARG, "trace needs CF_FLAG_KEEP_GAMMA and n_steps entries");
     Staged sg;
@@ -1395,7 +1595,7 @@ cf_status cf_batch_workspace_size(cf_problem* const* probs, int n, const cf_opts
     for (int i = 0; i < n; ++i) {
         cf_status st = cf_validate(probs[i], o);
         if (st != CF_OK) return st;
-        if (probs[i]->p.grid.ndim == 2) fused.push_back(probs[i]);
+        if (probs[i]->p.grid.ndim == 2 && !probs[i]->p.cyl) fused.push_back(probs[i]);
         size_t b = 0;
         cf_opts oo = *o;
         oo.n_subset = 0;
@@ -1428,7 +1628,7 @@ cf_status cf_batch_solve(cf_problem* const* probs, int n, const cf_opts* o, void
     std::vector<int> fused_idx;
     if (!(o->flags & CF_FLAG_SPLIT))
         for (int i = 0; i < n; ++i)
-            if (probs[i]->p.grid.ndim == 2) fused_idx.push_back(i);
+            if (probs[i]->p.grid.ndim == 2 && !probs[i]->p.cyl) fused_idx.push_back(i);
     BatchPlan B;
     if (fused_idx.size() >= 1) {
         std::vector<cf_problem*> fp;

@@ -17,7 +17,7 @@ struct ChanDev {
     int32_t inst;        // instance of a fused launch
     int32_t pol;         // CF_POL_TM / CF_POL_TE / CF_POL_3D
     int32_t local;       // channel index within its instance (accumulator, Gamma column)
-    int32_t pad2;
+    int32_t order;       // azimuthal order m (cylindrical problems)
     int64_t src_off;     // field_off + slot(src) * ncell
     int64_t meas_off;    // field_off + slot(meas) * ncell
     int32_t kind;        // 0 E-current source, 1 H-current source
@@ -125,6 +125,38 @@ hipError_t launch_h2d(int pol, int mode, T* fields, const ChanDev* ch, const int
 template <typename T>
 hipError_t launch_e2d(int pol, int mode, T* fields, const ChanDev* ch, const int* slots, int nslots,
                       const Grid2D& g, const T* lut, hipStream_t s);
+
+// Cylindrical (r, z) half steps of azimuthal order m for the listed
+// channels (6-component blocks on a Grid2D with x = z, y = r); mode as for
+// the 2D launchers.
+template <typename T>
+hipError_t launch_hcyl(int mode, int m, T* fields, const ChanDev* ch, const int* slots, int nslots,
+                       const Grid2D& g, const T* lut, hipStream_t s);
+template <typename T>
+hipError_t launch_ecyl(int mode, int m, T* fields, const ChanDev* ch, const int* slots, int nslots,
+                       const Grid2D& g, const T* lut, hipStream_t s);
+
+// Per-order tables of a cylindrical solve: coefficient table of order m at
+// lut + m * lut_stride (field precision), K(t_k) at ktab + m * ktab_stride,
+// T_m steps of dt_m.
+constexpr int kCylMaxOrders = 33;
+struct CylOrders {
+    const void* lut;
+    int64_t lut_stride;
+    const double* ktab;
+    int64_t ktab_stride;
+    int steps[kCylMaxOrders];
+    double dt[kCylMaxOrders];
+};
+
+// Resident cylindrical solve: one block per listed channel clears its
+// field block, deposits the kick, takes the consistent start and all T_m
+// steps of its order (ChanDev.order), projecting onto S and accumulating
+// after each; acc/gamma as for launch_surface.
+template <typename T>
+hipError_t launch_cyl_resident(T* fields, const ChanDev* ch, const int* slots, int nslots, const Grid2D& g,
+                               const CylOrders& ord, const SurfTables& t, double dA, double* acc, double* gamma,
+                               int gamma_stride, hipStream_t s);
 
 template <typename T>
 hipError_t launch_kick(T* fields, const ChanDev* ch, const int* slots, int nslots, int max_uniq,

@@ -38,38 +38,8 @@ __device__ __forceinline__ T yee_add(T a, T x, T b, T d) { return yee::add(a, x,
 template <typename T>
 __device__ __forceinline__ T yee_half(T b, T d) { return yee::half(b, d); }
 
-__device__ __forceinline__ void neumaier(double& sum, double& comp, double term) {
-    const double nt = sum + term;
-    if (fabs(sum) >= fabs(term))
-        comp += (sum - nt) + term;
-    else
-        comp += (term - nt) + sum;
-    sum = nt;
-}
-
-// Gamma sum of one channel by a block of NT threads: thread t takes samples
-// t, t+NT, ...; sum_p w X in FP64 per sample, weighted by f_n(s); then a
-// fixed-order reduction over the wave and over the NT/64 waves.  The total is
-// returned in thread 0.  `fetch(idx)` reads the measured component at flat
-// grid index idx.
-template <typename Fetch>
-__device__ double block_surface_sum(const ChanDev& d, const SurfTables& t, Fetch fetch, double* red) {
-    double s = 0.0;
-    const int n = threadIdx.x < NT ? d.nsamp : 0;   // larger blocks: the first NT threads sum
-    for (int i = threadIdx.x; i < n; i += NT) {
-        const int32_t* gi = t.gidx + d.g_off + (int64_t)i * d.P;
-        const double* gw = t.gw + d.g_off + (int64_t)i * d.P;
-        double v = 0.0;
-        for (int p = 0; p < d.P; ++p) v += gw[p] * fetch(gi[p]);
-        s += t.basis[d.basis_off + i] * v;
-    }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0 && threadIdx.x < NT) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double tot = 0.0;
-    if (threadIdx.x == 0) tot = ((red[0] + red[1]) + red[2]) + red[3];
-    return tot;
-}
+using yee::neumaier;
+using yee::block_surface_sum;
 
 // ---------------------------------------------------------------------------
 // split half-step kernels (one launch per half step for a batch of channels)

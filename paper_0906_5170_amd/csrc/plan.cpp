@@ -41,6 +41,36 @@ int comp_slot(int pol, int comp) {
 
 int n_comp_for(int ndim) { return ndim == 2 ? 3 : 6; }
 
+int n_comp(const Problem& p) { return p.cyl ? 6 : n_comp_for(p.grid.ndim); }
+
+double order_courant(const Problem& p, double courant, int m) {
+    return p.cyl && m >= 2 ? std::min(courant, 1.0 / (1.0 + m)) : courant;
+}
+
+// Same physical time t_end = n_steps courant / res for every order; the
+// rounding is half-to-even (nearbyint in the default rounding mode).
+int order_steps(const Problem& p, const cf_opts& o, int m) {
+    if (!p.cyl) return o.n_steps;
+    const double dx = 1.0 / p.grid.res;
+    const double t_end = o.n_steps * o.courant * dx;
+    return (int)std::nearbyint(t_end / (order_courant(p, o.courant, m) * dx));
+}
+
+int max_steps(const Problem& p, const cf_opts& o) {
+    int t = o.n_steps;
+    if (p.cyl)
+        for (int m = 0; m <= p.m_max; ++m) t = std::max(t, order_steps(p, o, m));
+    return t;
+}
+
+int harmonic_len(const Problem& p) {
+    int lab = 0;
+    for (auto& v : p.labels)
+        for (int l : v) lab = std::max(lab, l + 1);
+    if (p.cyl) lab += p.m_max * p.surf.n_harm;
+    return lab;
+}
+
 static bool spans_periodic(const Problem& p, int a) {
     return p.grid.bc[a] == CF_BC_PERIODIC && p.surf.lo[a] == 0 && p.surf.hi[a] == p.grid.n[a];
 }
@@ -151,6 +181,184 @@ static std::vector<double> cosine_rows(int N, int nh, double dx) {
     return b;
 }
 
+static std::string surface_medium(Problem& p);
+static std::string finish_cyl_surface(Problem& p, const cf_surface& s);
+
+// ---- cylindrical surfaces --------------------------------------------------
+//
+// The (z, r) rectangle lo..hi in cells; r = y - 1/2 with y the grid's axis-1
+// coordinate, so the doubled y of radius r is 2 r + 1.
+
+// Points along one axis for doubled coordinate d2 and component offset o2;
+// points at or beyond n on a non-periodic axis lie in or past the wall
+// (field zero there) and are left out; false if a point falls below 0.
+static bool cyl_axis_points(int d2, int o2, int n, bool periodic, std::vector<std::pair<int, double>>& out) {
+    out.clear();
+    const int d = d2 - o2;
+    int pi[2];
+    double pw[2];
+    int np;
+    if ((d % 2 + 2) % 2 == 0) {
+        pi[0] = d / 2;
+        pw[0] = 1.0;
+        np = 1;
+    } else {
+        pi[0] = (d - 1) / 2;
+        pi[1] = (d + 1) / 2;
+        pw[0] = pw[1] = 0.5;
+        np = 2;
+    }
+    for (int k = 0; k < np; ++k) {
+        int i = pi[k];
+        if (periodic) {
+            i = ((i % n) + n) % n;
+        } else if (i >= n) {
+            continue;
+        } else if (i < 0) {
+            return false;
+        }
+        out.push_back({i, pw[k]});
+    }
+    return true;
+}
+
+static void cyl_faces(const Problem& p, const cf_surface& s, std::vector<Face>& faces) {
+    const int nr = p.ny;
+    const int z0 = s.lo[0], z1 = s.hi[0], r0 = s.lo[1], r1 = s.hi[1];
+    const bool to_wall = r1 >= nr;
+    std::vector<int> ys, xs;
+    std::vector<double> wy, wx;
+    for (int k = r0; k < (to_wall ? nr - 1 : r1); ++k) {
+        ys.push_back(2 * k + 2);      // r = k + 1/2
+        wy.push_back(1.0);
+    }
+    if (to_wall) {
+        ys.push_back(2 * nr - 1);     // r = nr - 1: the half cell up to the wall
+        wy.push_back(0.5);
+    }
+    for (int i = z0; i < z1; ++i) {
+        xs.push_back(2 * i + 1);
+        wx.push_back(1.0);
+    }
+    auto make = [&](int axis, int side, int plane2, const std::vector<int>& s2, const std::vector<double>& w) {
+        Face f{};
+        f.index = 2 * axis + (side > 0);
+        f.axis = axis;
+        f.side = side;
+        f.plane = plane2 / 2;
+        f.plane2 = plane2;
+        f.ntang = 1;
+        f.tang[0] = 1 - axis;
+        f.start[0] = 0;
+        f.count[0] = (int)s2.size();
+        f.nsamp = (int)s2.size();
+        f.samp2 = s2;
+        f.qw = w;
+        faces.push_back(f);
+    };
+    make(0, -1, 2 * z0, ys, wy);
+    make(0, +1, 2 * z1, ys, wy);
+    if (r0 > 0) make(1, -1, 2 * r0 + 1, xs, wx);
+    if (!to_wall) make(1, +1, 2 * r1 + 1, xs, wx);
+}
+
+// Rows w_s f_n(s) of the first min(nh, N) members of the cosine basis made
+// orthonormal under dx sum_s w_s f g (classical Gram-Schmidt in FP64, in
+// order n = 0, 1, ...); cos(n pi pos / L) at the sample's position pos
+// along the face (cumulative weights), L the face length in cells.
+static std::vector<double> weighted_cosine_rows(const std::vector<double>& w, int nh, double dx) {
+    const int N = (int)w.size();
+    const int rows = std::min(nh, N);
+    std::vector<double> pos(N);
+    double L = 0;
+    for (int i = 0; i < N; ++i) {
+        pos[i] = L + 0.5 * w[i];
+        L += w[i];
+    }
+    std::vector<std::vector<double>> f;
+    for (int n = 0; n < rows; ++n) {
+        std::vector<double> v(N);
+        for (int i = 0; i < N; ++i) v[i] = std::cos(n * M_PI * pos[i] / L);
+        for (const auto& u : f) {
+            double dot = 0;
+            for (int i = 0; i < N; ++i) dot += w[i] * u[i] * v[i];
+            dot *= dx;
+            for (int i = 0; i < N; ++i) v[i] -= dot * u[i];
+        }
+        double nn = 0;
+        for (int i = 0; i < N; ++i) nn += w[i] * v[i] * v[i];
+        nn = std::sqrt(dx * nn);
+        for (int i = 0; i < N; ++i) v[i] /= nn;
+        f.push_back(std::move(v));
+    }
+    std::vector<double> b((size_t)rows * N);
+    for (int n = 0; n < rows; ++n)
+        for (int i = 0; i < N; ++i) b[(size_t)n * N + i] = w[i] * f[n][i];
+    return b;
+}
+
+// Gather of one component on a cylindrical face.  order_one: the axis rows
+// of E_r and H_phi (Ey, Hz) read the next row (m = 1) instead of zero.
+// Samples with fewer points are padded with zero-weight copies of their
+// first point so every sample has the same point count.
+static std::string make_gather_cyl(const Problem& p, int fi, int comp, bool order_one, Gather& g) {
+    const Face& f = p.faces[fi];
+    g.face = fi;
+    g.comp = comp;
+    g.nsamp = f.nsamp;
+    std::vector<std::vector<std::pair<int32_t, double>>> pts(f.nsamp);
+    std::vector<std::pair<int, double>> pz, pr;
+    const bool per_z = p.grid.bc[0] == CF_BC_PERIODIC;
+    const bool axis_copy = comp == CF_EY || comp == CF_HZ;
+    int P = 0;
+    for (int s = 0; s < f.nsamp; ++s) {
+        const int zd = f.axis == 0 ? f.plane2 : f.samp2[s];
+        const int rd = f.axis == 0 ? f.samp2[s] : f.plane2;
+        if (!cyl_axis_points(zd, kOffset2[comp][0], p.nx, per_z, pz) ||
+            !cyl_axis_points(rd, kOffset2[comp][1], p.ny, false, pr))
+            return "stress surface stencil leaves the grid";
+        for (auto& a : pz)
+            for (auto& b : pr) {
+                int j = b.first;
+                double w = a.second * b.second;
+                if (axis_copy && j == 0) {
+                    if (order_one) j = 1;
+                    else w = 0.0;
+                }
+                pts[s].push_back({(int32_t)((int64_t)j * p.nx + a.first), w});
+            }
+        if (pts[s].empty()) return "stress surface sample lies outside the grid";
+        P = std::max(P, (int)pts[s].size());
+    }
+    g.P = P;
+    g.idx.clear();
+    g.w.clear();
+    for (int s = 0; s < f.nsamp; ++s) {
+        for (int q = 0; q < P; ++q) {
+            const bool real = q < (int)pts[s].size();
+            g.idx.push_back(real ? pts[s][q].first : pts[s][0].first);
+            g.w.push_back(real ? pts[s][q].second : 0.0);
+        }
+    }
+    std::map<int32_t, std::vector<std::pair<int32_t, double>>> by_point;
+    for (int s = 0; s < g.nsamp; ++s)
+        for (int q = 0; q < g.P; ++q)
+            if (g.w[s * g.P + q] != 0.0) by_point[g.idx[s * g.P + q]].push_back({s, g.w[s * g.P + q]});
+    g.uidx.clear();
+    g.uoff.assign(1, 0);
+    g.usamp.clear();
+    g.uw.clear();
+    for (auto& kv : by_point) {
+        g.uidx.push_back(kv.first);
+        for (auto& sw : kv.second) {
+            g.usamp.push_back(sw.first);
+            g.uw.push_back(sw.second);
+        }
+        g.uoff.push_back((int32_t)g.usamp.size());
+    }
+    return "";
+}
+
 std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surface& s,
                           Problem& p) {
     if (g.ndim != 2 && g.ndim != 3) return "ndim must be 2 or 3";
@@ -165,8 +373,17 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
         if (g.bc[a] == CF_BC_PML && (g.pml_cells[a] < 1 || 2 * g.pml_cells[a] >= g.n[a]))
             return "PML thickness out of range";
     }
+    if (g.coord != CF_COORD_CARTESIAN && g.coord != CF_COORD_CYLINDRICAL) return "unknown coordinate system";
+    if (g.coord == CF_COORD_CYLINDRICAL) {
+        if (g.ndim != 2) return "cylindrical problems are 2D (r, z) grids";
+        if (g.bc[1] != CF_BC_PEC) return "cylindrical problems need a PEC tube wall (bc[1])";
+        if (g.bc[0] == CF_BC_PML) return "PML is implemented for 3D grids";
+        if (s.m_max < 0 || s.m_max > 32) return "m_max must be in 0..32";
+    }
     if (m.n_materials < 1 || m.n_materials > 254 || !m.eps || !m.mu) return "bad material table";
     p.grid = g;
+    p.cyl = g.coord == CF_COORD_CYLINDRICAL;
+    p.m_max = p.cyl ? s.m_max : 0;
     if (g.ndim == 2) {
         p.grid.bc[2] = CF_BC_PERIODIC;
         p.grid.pml_cells[2] = 0;
@@ -210,6 +427,13 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
     if (s.force_axis < 0 || s.force_axis >= g.ndim) return "force_axis out of range";
     if (s.n_harm < 1) return "n_harm must be >= 1";
     p.faces.clear();
+    if (p.cyl) {
+        if (s.force_axis != 0) return "cylindrical problems take the axial force (force_axis 0)";
+        if (s.lo[0] >= s.hi[0] || s.lo[1] >= s.hi[1]) return "surface box is empty";
+        if (s.lo[1] < 0 || s.hi[1] > p.ny) return "stress surface leaves the grid radially";
+        cyl_faces(p, s, p.faces);
+        return finish_cyl_surface(p, s);
+    }
     for (int a = 0; a < g.ndim; ++a) {
         if (s.lo[a] >= s.hi[a]) return "surface box is empty";
         if (spans_periodic(p, a)) continue;
@@ -269,23 +493,32 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
     // interpolation tables for every (face, component)
     p.gathers.clear();
     p.gather_of.clear();
-    std::set<double> e_vals, h_vals;
     for (int fi = 0; fi < (int)p.faces.size(); ++fi)
         for (int c = 0; c < kNumComp; ++c) {
             Gather gt;
             std::string err = make_gather(p, fi, c, gt);
             if (!err.empty()) return err;
-            for (int32_t ix : gt.idx) {
-                int id = p.ids[c][ix];
-                if (is_e(c)) {
-                    e_vals.insert(id == kWallId ? -INFINITY : p.eps[id]);
-                } else {
-                    h_vals.insert(p.mu[id]);
-                }
-            }
             p.gather_of[{fi, c}] = (int)p.gathers.size();
             p.gathers.push_back(std::move(gt));
         }
+    return surface_medium(p);
+}
+
+// Medium S lies in: every interpolation point of every gather must hold the
+// same eps (E components) and mu (H components), finite and positive.
+static std::string surface_medium(Problem& p) {
+    std::set<double> e_vals, h_vals;
+    for (const Gather& gt : p.gathers) {
+        const int c = gt.comp;
+        for (int32_t ix : gt.idx) {
+            int id = p.ids[c][ix];
+            if (is_e(c)) {
+                e_vals.insert(id == kWallId ? -INFINITY : p.eps[id]);
+            } else {
+                h_vals.insert(p.mu[id]);
+            }
+        }
+    }
     if (e_vals.size() != 1 || h_vals.size() != 1)
         return "stress surface does not lie in one uniform medium";
     p.eps_s = *e_vals.begin();
@@ -293,6 +526,35 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
     if (!(std::isfinite(p.eps_s) && p.eps_s > 0 && std::isfinite(p.mu_s) && p.mu_s > 0))
         return "stress surface touches a conductor";
     return "";
+}
+
+// Basis and gathers of a cylindrical surface (faces already built).
+static std::string finish_cyl_surface(Problem& p, const cf_surface& s) {
+    const double dx = 1.0 / p.grid.res;
+    p.basis.clear();
+    p.labels.clear();
+    p.nrows.clear();
+    for (const Face& f : p.faces) {
+        auto b = weighted_cosine_rows(f.qw, s.n_harm, dx);
+        const int rows = (int)(b.size() / f.nsamp);
+        std::vector<int> lab(rows);
+        for (int r = 0; r < rows; ++r) lab[r] = r;
+        p.basis.push_back(std::move(b));
+        p.labels.push_back(lab);
+        p.nrows.push_back(rows);
+    }
+    p.gathers.clear();
+    p.gather_of.clear();
+    for (int fi = 0; fi < (int)p.faces.size(); ++fi)
+        for (int c = 0; c < kNumComp; ++c)
+            for (int one = 0; one < 2; ++one) {
+                Gather gt;
+                std::string err = make_gather_cyl(p, fi, c, one == 1, gt);
+                if (!err.empty()) return err;
+                p.gather_of[{fi, c + (one ? 8 : 0)}] = (int)p.gathers.size();
+                p.gathers.push_back(std::move(gt));
+            }
+    return surface_medium(p);
 }
 
 std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
@@ -303,7 +565,13 @@ std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
     if (o.precision != CF_FP64 && o.precision != CF_FP32) return "unknown precision";
     if (o.path != CF_PATH_BATCHED && o.path != CF_PATH_PLAIN) return "unknown path";
     if (o.kernel != CF_KERNEL_GENERAL && o.kernel != CF_KERNEL_ZINV2D) return "unknown kernel";
-    if (p.grid.ndim == 2) {
+    if (p.cyl) {
+        if (o.pol != CF_POL_3D) return "cylindrical runs take CF_POL_3D (all six components)";
+        if (o.stop_tol > 0) {
+            *code = CF_E_UNSUPPORTED;
+            return "the convergence stop is not available for cylindrical problems";
+        }
+    } else if (p.grid.ndim == 2) {
         if (o.pol < 1 || o.pol > 3) return "2D runs take CF_POL_TM and/or CF_POL_TE";
     } else {
         if (o.pol != CF_POL_3D) return "3D runs take CF_POL_3D";
@@ -337,6 +605,10 @@ std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
         *code = CF_E_CFL;
         return "courant number above the Yee stability limit";
     }
+    if (p.cyl && o.courant * vmax > 0.5) {
+        *code = CF_E_CFL;
+        return "cylindrical runs need courant * max speed <= 0.5";
+    }
     *code = CF_OK;
     return "";
 }
@@ -349,7 +621,7 @@ std::vector<Channel> channel_table(const Problem& p, int pol_mask) {
     std::vector<Channel> out;
     const int d = p.surf.force_axis;
     std::vector<int> pols;
-    if (p.grid.ndim == 3) {
+    if (p.grid.ndim == 3 || p.cyl) {
         pols = {CF_POL_3D};
     } else {
         if (pol_mask & CF_POL_TM) pols.push_back(CF_POL_TM);
@@ -387,6 +659,20 @@ std::vector<Channel> channel_table(const Problem& p, int pol_mask) {
                     out.push_back(ch);
                 }
         }
+    }
+    if (p.cyl) {
+        // order-major: the channel set once per azimuthal order m, with the
+        // order weight w_m (1 for m = 0, 2 above: the -m term is the
+        // conjugate of the +m term) in the sign
+        const std::vector<Channel> base = std::move(out);
+        out.clear();
+        for (int m = 0; m <= p.m_max; ++m)
+            for (Channel ch : base) {
+                ch.order = m;
+                ch.label += m * p.surf.n_harm;
+                ch.sign *= m == 0 ? 1.0 : 2.0;
+                out.push_back(ch);
+            }
     }
     return out;
 }

@@ -34,6 +34,11 @@ struct Face {
     int start[2];
     int count[2];
     int nsamp;
+    // cylindrical faces: doubled coordinate of the plane along the normal
+    // axis, doubled tangential coordinate and quadrature weight per sample
+    int plane2 = 0;
+    std::vector<int> samp2;
+    std::vector<double> qw;
 };
 
 // Interpolation W of one component on one face: for sample s, points
@@ -55,6 +60,7 @@ struct Channel {
     int pol;         // CF_POL_TM / CF_POL_TE / CF_POL_3D
     int src, meas;   // component ids
     double sign;
+    int order = 0;   // azimuthal order m (cylindrical problems)
 };
 
 struct Problem {
@@ -69,10 +75,27 @@ struct Problem {
     std::vector<std::vector<double>> basis;   // per face: rows x nsamp
     std::vector<std::vector<int>> labels;     // per face: label per row
     std::vector<int> nrows;
-    std::map<std::pair<int, int>, int> gather_of;   // (face, comp) -> gathers index
+    std::map<std::pair<int, int>, int> gather_of;   // (face, gather_key) -> gathers index
     std::vector<Gather> gathers;
     double eps_s = 0, mu_s = 0;
+    bool cyl = false;                         // cylindrical (r, z) problem
+    int m_max = 0;
 };
+
+// Key of a (face, component) gather: cylindrical problems keep a second
+// table per component for order m = 1, whose axis values of E_r and H_phi
+// are the next row's (every other order reads zero there).
+inline int gather_key(const Problem& p, int comp, int order) {
+    return comp + (p.cyl && order == 1 ? 8 : 0);
+}
+
+// Courant number and step count of azimuthal order m (cylindrical
+// problems); Cartesian problems run every channel on (courant, n_steps).
+double order_courant(const Problem& p, double courant, int m);
+int order_steps(const Problem& p, const cf_opts& o, int m);
+int max_steps(const Problem& p, const cf_opts& o);
+int n_comp(const Problem& p);
+int harmonic_len(const Problem& p);
 
 // Components of each polarization: (E list, H list) as component ids.
 void pol_components(int pol, std::vector<int>& e, std::vector<int>& h);

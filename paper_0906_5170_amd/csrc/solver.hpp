@@ -28,6 +28,7 @@ struct TBPlan {
 // polarization and in channel order.
 struct Wave {
     int tm_off, n_tm, te_off, n_te, d3_off, n_3d, all_off, n_all;
+    int order;   // azimuthal order of every channel in the wave (cylindrical problems)
 };
 
 struct Staged {
@@ -45,6 +46,7 @@ struct Staged {
     int resident = 0;                      // field blocks on the device
     int ncomp = 3;
     int64_t psi_comp = 0;                  // values per psi component (3D CPML)
+    bool cyl_res = false;                  // cylindrical waves on the resident solve kernel
     bool f3d = false;                      // 3D steps on the fused z-streaming kernel
     int v3d = -1;                          // its variant when fixed by the options (-1: autotune)
 };

@@ -1,10 +1,13 @@
-// Device helpers shared by the 2D and 3D kernels: the update forms with
-// explicit fused multiply-adds (the library is built without automatic
-// contraction, so every path that uses these evaluates bitwise the same
-// arithmetic), coefficient-table addressing, and cross-lane moves.
+// Device helpers shared by the 2D, 3D and cylindrical kernels: the update
+// forms with explicit fused multiply-adds (the library is built without
+// automatic contraction, so every path that uses these evaluates bitwise the
+// same arithmetic), coefficient-table addressing, cross-lane moves, and the
+// surface projection with its compensated time accumulation.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "device.hpp"
 
 namespace cf {
 namespace yee {
@@ -56,6 +59,45 @@ __device__ __forceinline__ double lane_value(double v, int l) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
     return __hiloint2double(hi, lo);
+}
+
+// Threads that take part in a surface sum (the first kSurfThreads of the block).
+constexpr int kSurfThreads = 256;
+
+// Neumaier-compensated (sum, comp) += term.
+__device__ __forceinline__ void neumaier(double& sum, double& comp, double term) {
+    const double nt = sum + term;
+    if (fabs(sum) >= fabs(term))
+        comp += (sum - nt) + term;
+    else
+        comp += (term - nt) + sum;
+    sum = nt;
+}
+
+// Gamma sum of one channel by the first kSurfThreads threads of a block:
+// thread t takes samples t, t + kSurfThreads, ...; sum_p w X in FP64 per
+// sample, weighted by the basis row; then a fixed-order reduction over the
+// wave and over the kSurfThreads / 64 waves.  Every thread of the block must
+// call it (it holds a barrier); the total is returned in thread 0.
+// `fetch(idx)` reads the measured component at flat grid index idx.
+template <typename Fetch>
+__device__ __forceinline__ double block_surface_sum(const ChanDev& d, const SurfTables& t, Fetch fetch,
+                                                    double* red) {
+    double s = 0.0;
+    const int n = threadIdx.x < kSurfThreads ? d.nsamp : 0;
+    for (int i = threadIdx.x; i < n; i += kSurfThreads) {
+        const int32_t* gi = t.gidx + d.g_off + (int64_t)i * d.P;
+        const double* gw = t.gw + d.g_off + (int64_t)i * d.P;
+        double v = 0.0;
+        for (int p = 0; p < d.P; ++p) v += gw[p] * fetch(gi[p]);
+        s += t.basis[d.basis_off + i] * v;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0 && threadIdx.x < kSurfThreads) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double tot = 0.0;
+    if (threadIdx.x == 0) tot = ((red[0] + red[1]) + red[2]) + red[3];
+    return tot;
 }
 
 }  // namespace yee

@@ -1,0 +1,214 @@
+"""GPU parity of the cylindrical (r, z) path against the FP64 oracle
+(Sec. III D; Appendix, harmonic expansion in cylindrical coordinates).
+
+Cases (each printed before it runs):
+* ``closed``: the cylindrical piston of Fig. 7 at resolution 10 (150 x 7
+  cells: three 64-cell tiles along z with a ragged tail, two 4-row tiles
+  along r with a ragged one), S closed on the axis, orders 0..2;
+* ``wall``: plates filling the tube cross-section, S reaching the tube wall
+  (half-cell sample at the wall), orders 0..3 (order 2 and 3 on their own
+  smaller time steps);
+* ``ring``: a PEC ring off the axis with periodic ends, S with an inner and
+  an outer radial face, orders 0..2;
+* ``pmc``: the piston with a PMC-lined tube at resolution 20, orders 0..3.
+
+Tolerances: FP64 fields follow the oracle up to rounding order (the
+coefficients and the 1/r factors are formed differently): 1e-9 of the
+largest channel per channel and 1e-9 of the term magnitude
+sum_c |s_c acc_c| / pi for the force.  FP32 fields with FP64 accumulation:
+2e-5 of the largest channel per channel and of the term magnitude for the
+force on the small cases; at the benchmark size (resolution 40, 10000
+steps of order 0) sampled channels against the oracle run on those channels
+only, 1e-4 of each channel's term magnitude sum_k |dt K(t_k) Gamma(t_k)|
+(some channels cancel by five orders of magnitude in time: the r-face H
+channel of order 2 integrates to 7e-8 from terms summing to 2e-2 in
+magnitude).
+"""
+import numpy as np
+import pytest
+
+from casimir_inputs import Box, Workload, c_cyl_piston, cyl_piston, rasterize
+from oracle import cylforce
+from oracle.cyl import cylindrical_courant
+from oracle.kernels import kernel_table
+
+pytestmark = pytest.mark.gpu
+BIG = 1e30
+
+
+def announce(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+def plates_to_wall(res=10, na=20, nd=5, nb=45, nr=9, gap=6, n_harm=4, m_max=3, n_steps=300):
+    nz = na + nd + nb
+    ids = rasterize((nz, nr, 1), [Box((na, -BIG, -BIG), (na + nd, BIG, BIG), 1)])
+    return Workload(name="cyl_plates_wall", ndim=2, shape=(nz, nr, 1), res=float(res),
+                    bc=("pec", "pec", "periodic"), pml_cells=(0, 0, 0), eps=[1.0, float("-inf")], mu=[1.0, 1.0],
+                    comp_ids=ids, s_lo=(na - gap, 0, 0), s_hi=(na + nd + gap, nr, 1), n_harm=n_harm, force_axis=0,
+                    pol="3D", kernel="general", n_steps=n_steps, sigma=1.0, courant=0.5, precision="fp64",
+                    coord="cylindrical", m_max=m_max)
+
+
+def ring_periodic(res=10, nz=66, nr=11, n_steps=300):
+    # PEC ring r in [3, 6) cells (grid y = r + 1/2), z in [30, 36)
+    ids = rasterize((nz, nr, 1), [Box((30, 3.5, -BIG), (36, 6.5, BIG), 1)])
+    return Workload(name="cyl_ring_periodic", ndim=2, shape=(nz, nr, 1), res=float(res),
+                    bc=("periodic", "pec", "periodic"), pml_cells=(0, 0, 0), eps=[1.0, float("-inf")],
+                    mu=[1.0, 1.0], comp_ids=ids, s_lo=(27, 1, 0), s_hi=(39, 8, 1), n_harm=3, force_axis=0,
+                    pol="3D", kernel="general", n_steps=n_steps, sigma=1.0, courant=0.5, precision="fp64",
+                    coord="cylindrical", m_max=2)
+
+
+CASES = {
+    "closed": lambda: cyl_piston(res=10, h_u=0.8, length_u=15.0, n_harm=3, m_max=2, n_steps=400, precision="fp64"),
+    "wall": plates_to_wall,
+    "ring": ring_periodic,
+    "pmc": lambda: cyl_piston(res=20, h_u=0.5, length_u=6.0, n_harm=5, m_max=3, sidewall="pmc", n_steps=300,
+                              precision="fp64"),
+}
+_ORACLE = {}
+
+
+def oracle_result(name):
+    if name not in _ORACLE:
+        wl = CASES[name]()
+        _ORACLE[name] = (wl, cylforce.solve(wl, m_max=wl.m_max))
+    return _ORACLE[name]
+
+
+def run(cf, wl, **over):
+    opts = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol="3D", kernel=wl.kernel,
+                precision=wl.precision)
+    opts.update(over)
+    return cf.Problem.from_workload(wl).solve(**opts)
+
+
+def check(res, ref, tol):
+    acc_ref = ref.acc.reshape(-1)                  # order-major, the library's channel order
+    sign = np.concatenate([(1.0 if m == 0 else 2.0) * ref.sign for m in range(ref.acc.shape[0])])
+    assert res["per_channel"].shape == acc_ref.shape
+    scale = np.max(np.abs(acc_ref))
+    err = np.max(np.abs(res["per_channel"] - acc_ref))
+    assert err <= tol * scale, (err, scale)
+    mag = np.sum(np.abs(sign * acc_ref)) / np.pi
+    assert abs(res["force"] - ref.force) <= tol * mag, (res["force"], ref.force, mag)
+    return err / scale
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_matches_oracle(cf, name):
+    announce(f"cylindrical fp64 vs oracle: {name}")
+    wl, ref = oracle_result(name)
+    res = run(cf, wl, precision="fp64")
+    rel = check(res, ref, 1e-9)
+    # per-harmonic sums: label m * n_harm + n
+    n_h = wl.n_harm
+    for m in range(wl.m_max + 1):
+        mine = res["per_harmonic"][m * n_h:(m + 1) * n_h].sum()
+        mag = np.sum(np.abs((1.0 if m == 0 else 2.0) * ref.sign * ref.acc[m])) / np.pi
+        assert abs(mine - ref.per_m[m]) <= 1e-9 * mag
+    print(f"[cyl] {name}: max channel error {rel:.2e} of the largest, F = {res['force']:.6e}", flush=True)
+
+
+@pytest.mark.parametrize("name", ["closed", "wall", "ring"])
+def test_fp32_matches_oracle(cf, name):
+    announce(f"cylindrical fp32 vs oracle: {name}")
+    wl, ref = oracle_result(name)
+    res = run(cf, wl, precision="fp32")
+    rel = check(res, ref, 2e-5)
+    print(f"[cyl] {name} fp32: max channel error {rel:.2e} of the largest", flush=True)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_resident_split_plain_bitwise(cf, precision):
+    """The resident solve (default), the split half-step launches and the
+    plain one-channel-at-a-time path share the per-cell updates and the
+    surface reduction: identical accumulators."""
+    announce(f"cylindrical resident / split / plain, bitwise, {precision}")
+    for name in ("closed", "wall"):
+        wl, _ = oracle_result(name)
+        full = run(cf, wl, precision=precision, keep_gamma=True)
+        split = run(cf, wl, precision=precision, split=True, keep_gamma=True)
+        np.testing.assert_array_equal(split["per_channel"], full["per_channel"])
+        np.testing.assert_array_equal(split["gamma"], full["gamma"])
+        plain = run(cf, wl, precision=precision, path="plain")
+        np.testing.assert_array_equal(plain["per_channel"], full["per_channel"])
+
+
+def test_plain_path_and_waves_bitwise(cf):
+    announce("cylindrical plain path / resident waves / subset, bitwise")
+    wl, _ = oracle_result("closed")
+    full = run(cf, wl)
+    plain = run(cf, wl, path="plain")
+    np.testing.assert_array_equal(plain["per_channel"], full["per_channel"])
+    waves = run(cf, wl, max_resident=5)
+    np.testing.assert_array_equal(waves["per_channel"], full["per_channel"])
+    n = len(full["per_channel"])
+    sub = [n - 1, 3, n // 2, 0, 50]                # mixed orders, arbitrary order
+    part = run(cf, wl, channel_subset=sub)
+    np.testing.assert_array_equal(part["per_channel"], full["per_channel"][sub])
+
+
+def test_gamma_rows_per_order(cf):
+    """KEEP_GAMMA: row k holds step k + 1 of each channel's own order; rows
+    past that order's step count are zero."""
+    announce("cylindrical gamma rows vs oracle")
+    wl = plates_to_wall(n_steps=120)
+    res = run(cf, wl, keep_gamma=True)
+    faces, bases, eps_s, mu_s, chans = cylforce.setup(wl)
+    n0 = len(chans)
+    gam = res["gamma"]
+    t_end = wl.n_steps * wl.courant / wl.res
+    assert gam.shape[0] == max(int(round(t_end / (cylindrical_courant(wl.courant, m) / wl.res)))
+                               for m in range(wl.m_max + 1))
+    for m in range(wl.m_max + 1):
+        cm = cylindrical_courant(wl.courant, m)
+        T = int(round(t_end / (cm / wl.res)))
+        ref, dt = cylforce.run_order(wl, m, faces, bases, eps_s, mu_s, chans, T, cm)
+        mine = gam[:, m * n0:(m + 1) * n0]
+        scale = np.max(np.abs(ref))
+        assert np.max(np.abs(mine[:T] - ref)) <= 1e-9 * scale
+        assert not np.any(mine[T:])
+
+
+def test_edge_cases(cf):
+    announce("cylindrical edge cases: one step, order 0 only, clamped harmonics")
+    wl = CASES["closed"]().replace(n_steps=1)
+    ref = cylforce.solve(wl, m_max=wl.m_max)
+    check(run(cf, wl), ref, 1e-9)
+    wl0 = CASES["closed"]().replace(m_max=0, n_steps=50)
+    ref0 = cylforce.solve(wl0, m_max=0)
+    check(run(cf, wl0), ref0, 1e-9)
+    # more harmonics than the z-faces have samples: clamped per face
+    wlh = CASES["closed"]().replace(n_harm=8, n_steps=40)
+    refh = cylforce.solve(wlh, m_max=wlh.m_max)
+    check(run(cf, wlh), refh, 1e-9)
+
+
+def test_benchmark_size_sampled_channels_fp32(cf):
+    """Resolution 40 piston (n, m in {0, 1, 2}), the full 10000 steps of
+    order 0 (15000 of order 2): one channel per order, run by the oracle on
+    those channels only."""
+    announce("cylindrical benchmark size: sampled channels fp32 vs oracle")
+    wl = c_cyl_piston()
+    p = cf.Problem.from_workload(wl)
+    faces, bases, eps_s, mu_s, chans = cylforce.setup(wl)
+    n0 = len(chans)
+    picks = {0: 0, 1: n0 // 2 + 1, 2: n0 - 1}       # z-face E channel, mid channel, r-face H channel
+    subset = [m * n0 + c for m, c in picks.items()]
+    res = p.solve(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol="3D", kernel=wl.kernel,
+                  precision="fp32", channel_subset=subset)
+    t_end = wl.n_steps * wl.courant / wl.res
+    for k, (m, c) in enumerate(picks.items()):
+        cm = cylindrical_courant(wl.courant, m)
+        T = int(round(t_end / (cm / wl.res)))
+        gam, dt = cylforce.run_order(wl, m, faces, bases, eps_s, mu_s, [chans[c]], T, cm)
+        K = kernel_table(wl.kernel, wl.sigma, dt, T)
+        terms = dt * K * gam[:, 0]
+        ref = float(np.sum(terms))
+        mag = float(np.sum(np.abs(terms)))
+        err = abs(res["per_channel"][k] - ref)
+        print(f"[cyl] order {m} channel {c}: acc {ref:.4e}, error {err:.2e} = {err / mag:.2e} of sum|terms|",
+              flush=True)
+        assert err <= 1e-4 * mag

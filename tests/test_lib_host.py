@@ -6,7 +6,9 @@
 * its channel table (faces, labels, kinds, components, signs) is the
   oracle's, channel for channel;
 * validation rejects CFL violations, surfaces outside a uniform medium and
-  unsupported option combinations with the documented status codes.
+  unsupported option combinations with the documented status codes;
+* cylindrical problems: the order-major channel table and the per-order
+  step counts follow the oracle's.
 """
 import os
 import re
@@ -15,7 +17,10 @@ import numpy as np
 import pytest
 
 from casimir_inputs import c1_piston_tm_fp64, c2_piston_tetm_fp32, c4_sphere_plate, parallel_plates_1d
+from casimir_inputs import c_cyl_piston, cyl_piston
 from casimir_inputs.configs import piston2d
+from oracle.cyl import cylindrical_courant
+from oracle.cylforce import setup as cyl_setup
 from oracle.force import setup as oracle_setup
 from oracle.kernels import kernel_table as oracle_ktab
 
@@ -106,3 +111,57 @@ def test_invalid_material_ids_rejected(cf):
     with pytest.raises(cf.CfError) as e:
         cf.Problem.from_workload(wl.replace(comp_ids=ids))
     assert e.value.status == "CF_E_ARG"
+
+
+# ---- cylindrical (r, z) problems -------------------------------------------
+
+@pytest.mark.parametrize("make", [
+    lambda: cyl_piston(res=10, h_u=0.8, length_u=15.0, n_harm=3, m_max=2),
+    lambda: cyl_piston(res=20, h_u=0.5, length_u=6.0, n_harm=5, m_max=3, sidewall="pmc"),
+    lambda: c_cyl_piston(),
+])
+def test_cylindrical_channel_table_matches_oracle(cf, make):
+    """Order-major channel table: the oracle's per-order channels for every
+    m = 0..m_max, label m * n_harm + n, sign times w_m (1, then 2)."""
+    wl = make()
+    p = cf.Problem.from_workload(wl)
+    tab = p.channel_table(pol="3D", kernel="general")
+    faces, bases, eps_s, mu_s, chans = cyl_setup(wl)
+    n0 = len(chans)
+    assert len(tab["face"]) == n0 * (wl.m_max + 1)
+    for m in range(wl.m_max + 1):
+        wm = 1.0 if m == 0 else 2.0
+        for c, ch in enumerate(chans):
+            k = m * n0 + c
+            assert tab["face"][k] == faces[ch["face"]].index
+            assert tab["label"][k] == m * wl.n_harm + ch["label"]
+            assert tab["kind"][k] == (0 if ch["kind"] == "E" else 1)
+            assert tab["src"][k] == COMP_ID[ch["src"]] and tab["meas"][k] == COMP_ID[ch["meas"]]
+            assert tab["sign"][k] == pytest.approx(wm * ch["sign"], rel=1e-15)
+    info = p.info(pol="3D", kernel="general", n_steps=wl.n_steps, courant=wl.courant)
+    assert info["n_comp"] == 6
+    assert info["per_harmonic_len"] == (wl.m_max + 1) * wl.n_harm
+    assert info["eps_s"] == eps_s and info["mu_s"] == mu_s
+    # order m >= 2 runs on courant 1/(1+m) over the same physical time
+    t_end = wl.n_steps * wl.courant / wl.res
+    t_max = max(int(round(t_end / (cylindrical_courant(wl.courant, m) / wl.res))) for m in range(wl.m_max + 1))
+    assert info["n_steps_max"] == t_max
+
+
+def test_cylindrical_validation(cf):
+    wl = cyl_piston(res=10, h_u=0.8, length_u=15.0, n_harm=3, m_max=2)
+    p = cf.Problem.from_workload(wl)
+    p.validate(pol="3D", courant=0.5)
+    for opts, status in [(dict(pol="TM"), "CF_E_ARG"), (dict(pol="3D", courant=0.6), "CF_E_CFL"),
+                         (dict(pol="3D", stop_tol=1e-6), "CF_E_UNSUPPORTED")]:
+        with pytest.raises(cf.CfError) as e:
+            p.validate(**opts)
+        assert e.value.status == status, opts
+    for bad, status in [(wl.replace(bc=("pec", "periodic", "periodic")), "CF_E_ARG"),
+                        (wl.replace(m_max=40), "CF_E_ARG"),
+                        (wl.replace(force_axis=1), "CF_E_ARG"),
+                        (wl.replace(s_hi=(wl.s_hi[0], wl.shape[1] + 1, 1)), "CF_E_SURFACE"),
+                        (wl.replace(s_lo=(wl.s_lo[0] + 4, 0, 0)), "CF_E_SURFACE")]:   # S inside the cylinder
+        with pytest.raises(cf.CfError) as e:
+            cf.Problem.from_workload(bad)
+        assert e.value.status == status, bad.bc
