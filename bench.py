@@ -122,6 +122,53 @@ def bench_3d(cf, torch, n_chan=64, n_steps=200, variant=0):
             "projected_full_solve_s": 1280 * wl.n_cells * wl.n_steps / rate}
 
 
+def bench_cyl(cf, torch, cpu_sample=True):
+    """Cylindrical piston (Sec. III D, Fig. 7) at resolution 40, n, m in
+    {0, 1, 2}: one whole force point (126 channels; orders 0 and 1 take
+    10000 steps, order 2 15000 on its smaller step), FP32 fields, on the
+    resident kernel; the split half-step path and FP64 beside it.  The paper
+    quotes about 5 minutes on 8 processors per such force point (2009 CPUs,
+    time span unstated)."""
+    from casimir_inputs import c_cyl_piston
+    wl = c_cyl_piston()
+    p = cf.Problem.from_workload(wl)
+    o = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol="3D", kernel=wl.kernel,
+             precision="fp32")
+    p.solve(**dict(o, n_steps=200))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r = p.solve(time_stencil=True, **o)
+    wall = time.perf_counter() - t1
+    rate = r["cell_updates"] / (r["device_ms"] * 1e-3)
+    rs = p.solve(split=True, **o)
+    r64 = p.solve(**dict(o, precision="fp64"))
+    alg = rate * 48.0                                  # read + write of 6 FP32 values per cell-update
+    out = {"workload": f"cylindrical piston res 40, h 0.5, tube {wl.shape[0]} x {wl.shape[1]} (z x r), "
+                       f"n_harm 3, m 0..2, {r['n_channels']} channels, T 10000 (order 2: 15000), FP32",
+           "force": r["force"], "force_fp64_fields": r64["force"],
+           "force_point_wall_s": wall, "device_ms": r["device_ms"], "value": rate, "unit": "cell-updates/s",
+           "resident_variant": r["tile_variant"], "split_path_device_ms": rs["device_ms"],
+           "speedup_vs_split": rs["device_ms"] / r["device_ms"], "fp64_device_ms": r64["device_ms"],
+           "alg_bytes_per_s": alg, "alg_frac_of_hbm_peak": alg / (HBM_PEAK_GBS * 1e9),
+           "paper_quote": "about 5 minutes per force point on 8 processors (2009), res 40, n,m in {0,1,2}"}
+    if cpu_sample:
+        from oracle import cylforce
+        from oracle.cyl import cylindrical_courant
+        faces, bases, eps_s, mu_s, chans = cylforce.setup(wl)
+        n_s = 300
+        t1 = time.perf_counter()
+        cylforce.run_order(wl, 0, faces, bases, eps_s, mu_s, chans, n_s, cylindrical_courant(wl.courant, 0))
+        dt = time.perf_counter() - t1
+        per = dt / (len(chans) * n_s)                  # seconds per channel-step
+        total = sum(len(chans) * round(wl.n_steps * wl.courant / cylindrical_courant(wl.courant, m))
+                    for m in range(wl.m_max + 1))
+        out["cpu_oracle"] = {"projected_force_point_s": per * total, "cores": 1,
+                             "sample": f"order 0, all {len(chans)} channels x {n_s} steps, {dt:.1f} s, FP64 NumPy"}
+    log(f"[bench] cyl: force point {wall:.3f} s wall ({r['device_ms']:.1f} ms device), {rate:.3e} cell-updates/s, "
+        f"split {rs['device_ms']:.1f} ms, fp64 {r64['device_ms']:.1f} ms")
+    return out
+
+
 def _serve(cf, srv_budget, reqs, probs, opts_list, lam_times=True):
     """Submit requests at their arrival times (or all at once) and wait for
     all; returns per-request (kind, submit, admit, done, cell-updates)."""
@@ -325,6 +372,7 @@ def main():
     ap.add_argument("--c4-variant", type=int, default=0,
                     help="fused 3D variant of the 3D sample (0: autotuned, with a sweep of all variants)")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-cyl", action="store_true")
     ap.add_argument("--serve-n", type=int, default=24, help="requests in the served piston stream")
     ap.add_argument("--serve-mixed", type=int, default=0,
                     help="also serve this many requests of the mixed 2D/3D stream (long: 3D requests "
@@ -336,6 +384,7 @@ def main():
     args = ap.parse_args()
     if args.main_only:
         args.no_cpu = args.no_plain = args.no_batch = args.no_serve = args.no_3d = args.no_sweep = True
+        args.no_cyl = True
         args.no_precision = True
         if args.with_3d:
             args.no_3d = False
@@ -471,6 +520,8 @@ def main():
         rate_3d = out["c4_3d"]["value"]
     if not args.no_serve:
         out["serving"] = bench_serving(cf, torch, args, rate_3d)
+    if not args.no_cyl:
+        out["cylindrical"] = bench_cyl(cf, torch, cpu_sample=not args.no_cpu)
 
     gold = os.path.join(ROOT, "tests", "golden", "c2_piston_tetm_oracle.json")
     if os.path.exists(gold) and not args.n_steps:

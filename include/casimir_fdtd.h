@@ -154,9 +154,16 @@ typedef struct cf_surface {
  * with K sampled at its own steps.  The force is
  *   F = (1/pi) sum_m w_m sum_c s_c sum_k dt_m K(t_k) Gamma_c(t_k),
  * w_0 = 1, w_m>0 = 2 (the -m term is the conjugate of the +m term).
- * Options: pol = CF_POL_3D (all six components), courant <= 0.5, the split
- * update kernels only (tile_variant is ignored); stop_tol and the server
- * are not available (CF_E_UNSUPPORTED).
+ * Options: pol = CF_POL_3D (all six components), courant <= 0.5; stop_tol
+ * and the server are not available (CF_E_UNSUPPORTED).  Execution: by
+ * default one launch per wave of resident channels (any mix of orders),
+ * each block carrying one channel through all its steps; tile_variant 1
+ * keeps the fields in registers with an LDS exchange (grids of up to 4096
+ * cells in FP32, 2048 in FP64, when the device's LDS holds 3 values per
+ * cell; otherwise variant 2 runs), 2 keeps them in global memory, 0 picks 1
+ * when it fits.  CF_FLAG_SPLIT (and CF_PATH_PLAIN) use one launch per half
+ * step.  All give bitwise-identical results; cf_result.fused/tile_variant
+ * report the variant that ran.
  */
 
 /* CF_FLAG_KEEP_GAMMA keeps Gamma_c(t_m) for the gamma/trace outputs.

@@ -53,7 +53,7 @@ bool g_tune_loaded = false;
 // Device workspace layout of one solve.
 struct Layout {
     size_t ids, lut, ktab, pml, chans, slots, gidx, gw, uidx, uoff, usamp, uw, basis, acc, gamma,
-        fields, fields2, psi, psi2, idp, inst, work, total;
+        fields, fields2, psi, psi2, idp, rinv, inst, work, total;
     size_t work_items;    // capacity of one work list
 };
 
@@ -350,7 +350,8 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.fields2 = st.variant >= 0 || st.f3d ? take(block) : off;
     L.psi = st.psi_comp > 0 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
     L.psi2 = st.psi_comp > 0 && st.f3d ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
-    L.idp = st.f3d ? take((size_t)p.ncell * 8) : off;
+    L.idp = st.f3d ? take((size_t)p.ncell * 8) : st.cyl_res ? take((size_t)p.ncell * 4) : off;
+    L.rinv = p.cyl ? take((size_t)2 * p.ny * fsz) : off;
     int max_tiles = 0;
     for (const TBPlan& pl : st.plans)
         if (pl.ok) max_tiles = std::max(max_tiles, pl.ntx * pl.nty);
@@ -504,6 +505,35 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
     }
     CF_HIP(up(L.lut, luts.data(), luts.size() * sizeof(T)));
     CF_HIP(up(L.ktab, ktabs.data(), ktabs.size() * 8));
+    // reciprocal radii per row in the field precision (row 0 unused: zeros)
+    std::vector<T> rinv(2 * (size_t)p.ny, T(0));
+    for (int j = 1; j < p.ny; ++j) {
+        rinv[2 * j] = T(1) / T(j);
+        rinv[2 * j + 1] = T(1) / (T(j) - T(0.5));
+    }
+    CF_HIP(up(L.rinv, rinv.data(), rinv.size() * sizeof(T)));
+    ord.rinv = ws + L.rinv;
+    const T* drinv = reinterpret_cast<const T*>(ws + L.rinv);
+    // material ids packed in 4 bits per component for the register kernel
+    // (15 = wall id), when every id fits
+    std::vector<uint32_t> idw;
+    if (st.cyl_res) {
+        idw.assign(p.ncell, 0u);
+        bool fits = true;
+        for (int c = 0; c < cf::kNumComp && fits; ++c)
+            for (int64_t k = 0; k < p.ncell; ++k) {
+                const int id = p.ids[c][k];
+                if (id >= 15 && id != cf::kWallId) {
+                    fits = false;
+                    break;
+                }
+                idw[k] |= uint32_t(id == cf::kWallId ? 15 : id) << (4 * c);
+            }
+        if (fits) {
+            CF_HIP(up(L.idp, idw.data(), idw.size() * 4));
+            ord.idw = reinterpret_cast<const uint32_t*>(ws + L.idp);
+        }
+    }
 
     hipEvent_t e0, e1;
     CF_HIP(hipEventCreate(&e0));
@@ -518,6 +548,7 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
         smp.stride = std::max(1L, total / 200);
     }
     hipError_t err = hipSuccess;
+    timing->variant = -1;     // resident variant - 1 (-1: split path)
 #define STEP_OK(expr)                     \
     do {                                  \
         err = (expr);                     \
@@ -534,8 +565,11 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
                 cu += (double)p.ncell * ord.steps[st.chans[c].order];
             }
             const bool take = smp.begin(s);
-            STEP_OK(cf::launch_cyl_resident<T>(fields, dch, sl, w.n_all, g, ord, tabs, dA, dacc, dgam, (int)C, s));
+            int used = 0;
+            STEP_OK(cf::launch_cyl_resident<T>(o.tile_variant, fields, dch, sl, w.n_all, g, ord, tabs, dA, dacc, dgam,
+                                               (int)C, s, &used));
             smp.end(take, s, cu, cu * state_bytes);
+            timing->variant = std::max(timing->variant, used - 1);
             continue;
         }
         const int m = w.order;
@@ -545,12 +579,12 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
         const double* k_m = dk + (size_t)m * t_max;
         STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
         STEP_OK(cf::launch_kick<T>(fields, dch, sl, w.n_all, st.max_uniq, tabs, s));
-        STEP_OK(cf::launch_hcyl<T>(1, m, fields, dch, sl, w.n_all, g, lut_m, s));
-        STEP_OK(cf::launch_ecyl<T>(1, m, fields, dch, sl, w.n_all, g, lut_m, s));
+        STEP_OK(cf::launch_hcyl<T>(1, m, fields, dch, sl, w.n_all, g, lut_m, drinv, s));
+        STEP_OK(cf::launch_ecyl<T>(1, m, fields, dch, sl, w.n_all, g, lut_m, drinv, s));
         for (int k = 0; k < tm; ++k) {
             const bool take = smp.begin(s);
-            STEP_OK(cf::launch_hcyl<T>(0, m, fields, dch, sl, w.n_all, g, lut_m, s));
-            STEP_OK(cf::launch_ecyl<T>(0, m, fields, dch, sl, w.n_all, g, lut_m, s));
+            STEP_OK(cf::launch_hcyl<T>(0, m, fields, dch, sl, w.n_all, g, lut_m, drinv, s));
+            STEP_OK(cf::launch_ecyl<T>(0, m, fields, dch, sl, w.n_all, g, lut_m, drinv, s));
             const double cu = (double)w.n_all * p.ncell;
             smp.end(take, s, cu, cu * state_bytes);
             STEP_OK(cf::launch_surface<T>(fields, dch, sl, w.n_all, tabs, k_m, k, dt, dA, dacc, dgam, (int)C, s));
@@ -576,7 +610,6 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
         timing->cu_total = smp.cu;
         timing->launches = smp.seen;
     }
-    timing->variant = -1;
     timing->steps_run = o.n_steps;
     acc_out.assign(C * 2, 0.0);
     STEP_OK(hipMemcpy(acc_out.data(), ws + L.acc, C * 2 * 8, hipMemcpyDeviceToHost));

@@ -129,12 +129,13 @@ hipError_t launch_e2d(int pol, int mode, T* fields, const ChanDev* ch, const int
 // Cylindrical (r, z) half steps of azimuthal order m for the listed
 // channels (6-component blocks on a Grid2D with x = z, y = r); mode as for
 // the 2D launchers.
+// rinv: per row j the pair (1/j, 1/(j - 1/2)) in the field precision (row 0: zeros).
 template <typename T>
 hipError_t launch_hcyl(int mode, int m, T* fields, const ChanDev* ch, const int* slots, int nslots,
-                       const Grid2D& g, const T* lut, hipStream_t s);
+                       const Grid2D& g, const T* lut, const T* rinv, hipStream_t s);
 template <typename T>
 hipError_t launch_ecyl(int mode, int m, T* fields, const ChanDev* ch, const int* slots, int nslots,
-                       const Grid2D& g, const T* lut, hipStream_t s);
+                       const Grid2D& g, const T* lut, const T* rinv, hipStream_t s);
 
 // Per-order tables of a cylindrical solve: coefficient table of order m at
 // lut + m * lut_stride (field precision), K(t_k) at ktab + m * ktab_stride,
@@ -147,16 +148,23 @@ struct CylOrders {
     int64_t ktab_stride;
     int steps[kCylMaxOrders];
     double dt[kCylMaxOrders];
+    // the six material ids of each cell in 4 bits each (component c at bit
+    // 4 c; 15 stands for the wall id), or null when an id does not fit
+    const uint32_t* idw;
+    const void* rinv;   // per row: (1/j, 1/(j - 1/2)), field precision
 };
 
 // Resident cylindrical solve: one block per listed channel clears its
 // field block, deposits the kick, takes the consistent start and all T_m
 // steps of its order (ChanDev.order), projecting onto S and accumulating
-// after each; acc/gamma as for launch_surface.
+// after each; acc/gamma as for launch_surface.  variant 1: fields in
+// registers with an LDS exchange (used when the grid fits, else variant 2),
+// 2: fields in global memory (L2-resident); 0 picks 1 when it fits.  *used
+// receives the variant launched.
 template <typename T>
-hipError_t launch_cyl_resident(T* fields, const ChanDev* ch, const int* slots, int nslots, const Grid2D& g,
-                               const CylOrders& ord, const SurfTables& t, double dA, double* acc, double* gamma,
-                               int gamma_stride, hipStream_t s);
+hipError_t launch_cyl_resident(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
+                               const Grid2D& g, const CylOrders& ord, const SurfTables& t, double dA, double* acc,
+                               double* gamma, int gamma_stride, hipStream_t s, int* used);
 
 template <typename T>
 hipError_t launch_kick(T* fields, const ChanDev* ch, const int* slots, int nslots, int max_uniq,

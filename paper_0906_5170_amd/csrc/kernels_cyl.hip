@@ -33,6 +33,8 @@
 // one channel through clear, kick, start and all its steps with the surface
 // projection, in a single launch for channels of any mix of orders (a
 // channel's block of 6 x nr x nz values stays in the L2 of its XCD).
+#include <type_traits>
+
 #include "../../include/casimir_fdtd.h"
 #include "device.hpp"
 #include "yee_common.hpp"
@@ -52,11 +54,80 @@ inline dim3 grid_cyl(const Grid2D& g, int nslots) {
     return dim3(tiles, nslots, 1);
 }
 
-// H update of cell (i, j) of the channel block F: MODE 0 h <- a h - b curl e,
-// MODE 1 the consistent start h^{-1/2} = (b / 2) curl e^0.
+// Updated h_z, h_r, h_phi (hx, hy, hz) of a cell at row j from its own
+// fields, the neighbours e(j+1) (ezu, exu) and e(i+1) (ezr, eyr) and the
+// (a, b) pairs lx, ly, lz: MODE 0 h <- a h - b curl e, MODE 1 the consistent
+// start h^{-1/2} = (b / 2) curl e^0.  inv_r1 = 1/j and inv_r0 = 1/(j - 1/2)
+// come from the row table (correctly rounded in the field precision).
+// Every driver evaluates these forms, so their fields agree bitwise.
+template <typename T, int MODE>
+__device__ __forceinline__ void h_values(T& hx, T& hy, T& hz, T ex, T ey, T ez, T ezu, T exu, T ezr, T eyr,
+                                         const T* lx, const T* ly, const T* lz, int m, int j, T inv_r1, T inv_r0) {
+    if (j == 0) {
+        // axis: h_z from the disk circulation (m = 0), h_r outside, h_phi 0
+        const T cz = T(4) * ezu;
+        if (MODE == 0) hx = m == 0 ? yee::sub(lx[0], hx, lx[1], cz) : T(0);
+        else hx = m == 0 ? yee::half(lx[1], cz) : T(0);
+        hy = T(0);
+        hz = T(0);
+        return;
+    }
+    const T M = T(m);
+    const T r1 = T(j);                 // radius of h_z (cells)
+    const T r0 = T(j) - T(0.5);        // radius of h_r
+    // h_z: (1/r) d_r (r e_phi) - (m/r) e_r
+    const T cz = (((r1 + T(0.5)) * ezu - r0 * ez) - M * ey) * inv_r1;
+    // h_r: (m/r) e_z - d_z e_phi
+    const T cr = (M * ex) * inv_r0 - (ezr - ez);
+    // h_phi: d_z e_r - d_r e_z
+    const T cp = (eyr - ey) - (exu - ex);
+    if (MODE == 0) {
+        hx = yee::sub(lx[0], hx, lx[1], cz);
+        hy = yee::sub(ly[0], hy, ly[1], cr);
+        hz = yee::sub(lz[0], hz, lz[1], cp);
+    } else {
+        hx = yee::half(lx[1], cz);
+        hy = yee::half(ly[1], cr);
+        hz = yee::half(lz[1], cp);
+    }
+}
+
+// Updated e_z, e_r, e_phi (ex, ey, ez) of a cell at row j from its own
+// fields and the neighbours h(j-1) (hxd, hzd) and h(i-1) (hyl, hzl): MODE 0
+// e <- a e + b curl h, MODE 1 the consistent start e^{+1/2} = (b / 2) curl h^0.
+template <typename T, int MODE>
+__device__ __forceinline__ void e_values(T& ex, T& ey, T& ez, T hx, T hy, T hz, T hxd, T hzd, T hyl, T hzl,
+                                         const T* lx, const T* ly, const T* lz, int m, int j, T inv_r1, T inv_r0) {
+    if (j == 0) {
+        // e_z, e_phi outside / on the wall id, e_r on the axis: all 0
+        ex = T(0);
+        ey = T(0);
+        ez = T(0);
+        return;
+    }
+    const T M = T(m);
+    const T r1 = T(j);                 // radius of e_r
+    // e_z: (1/r) d_r (r h_phi) + (m/r) h_r
+    const T cz = ((r1 * hz - (r1 - T(1)) * hzd) + M * hy) * inv_r0;
+    // e_r: -(m/r) h_z - d_z h_phi
+    const T cr = -((M * hx) * inv_r1) - (hz - hzl);
+    // e_phi: d_z h_r - d_r h_z
+    const T cp = (hy - hyl) - (hx - hxd);
+    if (MODE == 0) {
+        ex = yee::add(lx[0], ex, lx[1], cz);
+        ey = yee::add(ly[0], ey, ly[1], cr);
+        ez = yee::add(lz[0], ez, lz[1], cp);
+    } else {
+        ex = yee::half(lx[1], cz);
+        ey = yee::half(ly[1], cr);
+        ez = yee::half(lz[1], cp);
+    }
+}
+
+// H update of cell (i, j) of the channel block F in global memory.
 template <typename T, int MODE>
 __device__ __forceinline__ void hcyl_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
-                                          int m, int i, int j) {
+                                          int m, int i, int j, const T* __restrict__ rinv) {
     const T* Ex = F;
     const T* Ey = F + g.ncell;
     const T* Ez = F + 2 * g.ncell;
@@ -66,47 +137,22 @@ __device__ __forceinline__ void hcyl_cell(T* __restrict__ F, const Grid2D& g, co
     const int64_t c = (int64_t)j * g.nx + i;
     const bool in_r = i + 1 < g.nx, in_u = j + 1 < g.ny;
     const T ezu = in_u ? Ez[c + g.nx] : T(0);
-    const T* lx = lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]);
-    if (j == 0) {
-        // axis: h_z from the disk circulation (m = 0), h_r outside, h_phi 0
-        const T cz = T(4) * ezu;
-        if (MODE == 0) Hx[c] = m == 0 ? yee::sub(lx[0], Hx[c], lx[1], cz) : T(0);
-        else Hx[c] = m == 0 ? yee::half(lx[1], cz) : T(0);
-        Hy[c] = T(0);
-        Hz[c] = T(0);
-        return;
-    }
-    const T ex = Ex[c], ey = Ey[c], ez = Ez[c];
     const T exu = in_u ? Ex[c + g.nx] : T(0);
     const T ezr = in_r ? Ez[c + 1] : (g.perx ? Ez[c + 1 - g.nx] : T(0));
     const T eyr = in_r ? Ey[c + 1] : (g.perx ? Ey[c + 1 - g.nx] : T(0));
-    const T M = T(m);
-    const T r1 = T(j);                 // radius of h_z (cells)
-    const T r0 = T(j) - T(0.5);        // radius of h_r
-    // h_z: (1/r) d_r (r e_phi) - (m/r) e_r
-    const T cz = (((r1 + T(0.5)) * ezu - r0 * ez) - M * ey) / r1;
-    // h_r: (m/r) e_z - d_z e_phi
-    const T cr = (M * ex) / r0 - (ezr - ez);
-    // h_phi: d_z e_r - d_r e_z
-    const T cp = (eyr - ey) - (exu - ex);
-    const T* ly = lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]);
-    const T* lz = lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]);
-    if (MODE == 0) {
-        Hx[c] = yee::sub(lx[0], Hx[c], lx[1], cz);
-        Hy[c] = yee::sub(ly[0], Hy[c], ly[1], cr);
-        Hz[c] = yee::sub(lz[0], Hz[c], lz[1], cp);
-    } else {
-        Hx[c] = yee::half(lx[1], cz);
-        Hy[c] = yee::half(ly[1], cr);
-        Hz[c] = yee::half(lz[1], cp);
-    }
+    T hx = Hx[c], hy = Hy[c], hz = Hz[c];
+    h_values<T, MODE>(hx, hy, hz, Ex[c], Ey[c], Ez[c], ezu, exu, ezr, eyr,
+                      lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]), lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]),
+                      lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]), m, j, rinv[2 * j], rinv[2 * j + 1]);
+    Hx[c] = hx;
+    Hy[c] = hy;
+    Hz[c] = hz;
 }
 
-// E update of cell (i, j): MODE 0 e <- a e + b curl h, MODE 1 the
-// consistent start e^{+1/2} = (b / 2) curl h^0.
+// E update of cell (i, j) of the channel block F in global memory.
 template <typename T, int MODE>
 __device__ __forceinline__ void ecyl_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
-                                          int m, int i, int j) {
+                                          int m, int i, int j, const T* __restrict__ rinv) {
     T* Ex = F;
     T* Ey = F + g.ncell;
     T* Ez = F + 2 * g.ncell;
@@ -114,71 +160,51 @@ __device__ __forceinline__ void ecyl_cell(T* __restrict__ F, const Grid2D& g, co
     const T* Hy = F + 4 * g.ncell;
     const T* Hz = F + 5 * g.ncell;
     const int64_t c = (int64_t)j * g.nx + i;
-    if (j == 0) {
-        // e_z, e_phi outside / on the wall id, e_r on the axis: all 0
-        Ex[c] = T(0);
-        Ey[c] = T(0);
-        Ez[c] = T(0);
-        return;
-    }
-    const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
-    const T hxd = Hx[c - g.nx], hzd = Hz[c - g.nx];
+    const bool in_d = j > 0;
+    const T hxd = in_d ? Hx[c - g.nx] : T(0);
+    const T hzd = in_d ? Hz[c - g.nx] : T(0);
     const T hyl = i > 0 ? Hy[c - 1] : (g.perx ? Hy[c - 1 + g.nx] : T(0));
     const T hzl = i > 0 ? Hz[c - 1] : (g.perx ? Hz[c - 1 + g.nx] : T(0));
-    const T M = T(m);
-    const T r1 = T(j);                 // radius of e_r
-    const T r0 = T(j) - T(0.5);        // radius of e_z
-    // e_z: (1/r) d_r (r h_phi) + (m/r) h_r
-    const T cz = ((r1 * hz - (r1 - T(1)) * hzd) + M * hy) / r0;
-    // e_r: -(m/r) h_z - d_z h_phi
-    const T cr = -((M * hx) / r1) - (hz - hzl);
-    // e_phi: d_z h_r - d_r h_z
-    const T cp = (hy - hyl) - (hx - hxd);
-    const T* lx = lut_ab(lut, kind, CF_EX, g.ids[CF_EX][c]);
-    const T* ly = lut_ab(lut, kind, CF_EY, g.ids[CF_EY][c]);
-    const T* lz = lut_ab(lut, kind, CF_EZ, g.ids[CF_EZ][c]);
-    if (MODE == 0) {
-        Ex[c] = yee::add(lx[0], Ex[c], lx[1], cz);
-        Ey[c] = yee::add(ly[0], Ey[c], ly[1], cr);
-        Ez[c] = yee::add(lz[0], Ez[c], lz[1], cp);
-    } else {
-        Ex[c] = yee::half(lx[1], cz);
-        Ey[c] = yee::half(ly[1], cr);
-        Ez[c] = yee::half(lz[1], cp);
-    }
+    T ex = Ex[c], ey = Ey[c], ez = Ez[c];
+    e_values<T, MODE>(ex, ey, ez, Hx[c], Hy[c], Hz[c], hxd, hzd, hyl, hzl,
+                      lut_ab(lut, kind, CF_EX, g.ids[CF_EX][c]), lut_ab(lut, kind, CF_EY, g.ids[CF_EY][c]),
+                      lut_ab(lut, kind, CF_EZ, g.ids[CF_EZ][c]), m, j, rinv[2 * j], rinv[2 * j + 1]);
+    Ex[c] = ex;
+    Ey[c] = ey;
+    Ez[c] = ez;
 }
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(BX* BY) void k_hcyl(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                const int* __restrict__ slots, Grid2D g,
-                                               const T* __restrict__ lut, int m) {
+                                               const T* __restrict__ lut, int m, const T* __restrict__ rinv) {
     const ChanDev d = ch[slots[blockIdx.y]];
     if (MODE == 1 && d.kind != 0) return;   // start: E-kind runs set H^{-1/2}
     const int tiles_x = (g.nx + BX - 1) / BX;
     const int i = (blockIdx.x % tiles_x) * BX + threadIdx.x;
     const int j = (blockIdx.x / tiles_x) * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
-    hcyl_cell<T, MODE>(fields + d.field_off, g, lut, d.kind, m, i, j);
+    hcyl_cell<T, MODE>(fields + d.field_off, g, lut, d.kind, m, i, j, rinv);
 }
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(BX* BY) void k_ecyl(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                const int* __restrict__ slots, Grid2D g,
-                                               const T* __restrict__ lut, int m) {
+                                               const T* __restrict__ lut, int m, const T* __restrict__ rinv) {
     const ChanDev d = ch[slots[blockIdx.y]];
     if (MODE == 1 && d.kind != 1) return;   // start: H-kind runs set E^{+1/2}
     const int tiles_x = (g.nx + BX - 1) / BX;
     const int i = (blockIdx.x % tiles_x) * BX + threadIdx.x;
     const int j = (blockIdx.x / tiles_x) * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
-    ecyl_cell<T, MODE>(fields + d.field_off, g, lut, d.kind, m, i, j);
+    ecyl_cell<T, MODE>(fields + d.field_off, g, lut, d.kind, m, i, j, rinv);
 }
 
 // Every cell of the grid once, block-strided: thread t takes flat cells
-// t, t + kResThreads, ... (consecutive threads on consecutive z).
-template <typename Body>
+// t, t + NTH, ... (consecutive threads on consecutive z).
+template <int NTH = kResThreads, typename Body>
 __device__ __forceinline__ void for_cells(const Grid2D& g, Body body) {
-    const int di = kResThreads % g.nx, dj = kResThreads / g.nx;
+    const int di = NTH % g.nx, dj = NTH / g.nx;
     int i = threadIdx.x % g.nx, j = threadIdx.x / g.nx;
     while (j < g.ny) {
         body(i, j);
@@ -191,12 +217,147 @@ __device__ __forceinline__ void for_cells(const Grid2D& g, Body body) {
     }
 }
 
+// One H (or E) half step of a channel block in global memory by a whole
+// block, kBatch cells per thread at a time (4 in FP32, 2 in FP64: the
+// register budget of a 1024-thread block): all loads of those cells are
+// issued before the first update, then the updates and stores.  Coefficient
+// pairs come from Lc, the pairs of the block's kind (6 x 256).
+template <typename T>
+constexpr int batch_of() {
+    return sizeof(T) == 8 ? 2 : 4;
+}
+
+template <typename T, int MODE, int NTH = kResThreads>
+__device__ __forceinline__ void h_phase(T* __restrict__ F, const Grid2D& g, const T* __restrict__ Lc, int m,
+                                        const T* __restrict__ R) {
+    constexpr int kBatch = batch_of<T>();
+    const T* Ex = F;
+    const T* Ey = F + g.ncell;
+    const T* Ez = F + 2 * g.ncell;
+    T* Hx = F + 3 * g.ncell;
+    T* Hy = F + 4 * g.ncell;
+    T* Hz = F + 5 * g.ncell;
+    const int nx = g.nx, ny = g.ny;
+    const int di = NTH % nx, dj = NTH / nx;
+    int i = threadIdx.x % nx, j = threadIdx.x / nx;
+    while (j < ny) {
+        T ex[kBatch], ey[kBatch], ez[kBatch], ezu[kBatch], exu[kBatch], ezr[kBatch], eyr[kBatch];
+        T hx[kBatch], hy[kBatch], hz[kBatch];
+        int cc[kBatch], jj[kBatch];
+        uint32_t id[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            jj[q] = j;
+            cc[q] = j * nx + i;
+            if (j < ny) {
+                const int c = cc[q];
+                const bool in_r = i + 1 < nx, in_u = j + 1 < ny;
+                ezu[q] = in_u ? Ez[c + nx] : T(0);
+                exu[q] = in_u ? Ex[c + nx] : T(0);
+                ezr[q] = in_r ? Ez[c + 1] : (g.perx ? Ez[c + 1 - nx] : T(0));
+                eyr[q] = in_r ? Ey[c + 1] : (g.perx ? Ey[c + 1 - nx] : T(0));
+                ex[q] = Ex[c];
+                ey[q] = Ey[c];
+                ez[q] = Ez[c];
+                hx[q] = Hx[c];
+                hy[q] = Hy[c];
+                hz[q] = Hz[c];
+                id[q] = uint32_t(g.ids[CF_HX][c]) | (uint32_t(g.ids[CF_HY][c]) << 8) |
+                        (uint32_t(g.ids[CF_HZ][c]) << 16);
+            }
+            i += di;
+            j += dj;
+            if (i >= nx) {
+                i -= nx;
+                ++j;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            if (jj[q] < ny) {
+                const int c = cc[q];
+                h_values<T, MODE>(hx[q], hy[q], hz[q], ex[q], ey[q], ez[q], ezu[q], exu[q], ezr[q], eyr[q],
+                                  Lc + ((CF_HX << 8) + (int)(id[q] & 255)) * 2,
+                                  Lc + ((CF_HY << 8) + (int)((id[q] >> 8) & 255)) * 2,
+                                  Lc + ((CF_HZ << 8) + (int)(id[q] >> 16)) * 2, m, jj[q], R[2 * jj[q]],
+                                  R[2 * jj[q] + 1]);
+                Hx[c] = hx[q];
+                Hy[c] = hy[q];
+                Hz[c] = hz[q];
+            }
+        }
+    }
+}
+
+template <typename T, int MODE, int NTH = kResThreads>
+__device__ __forceinline__ void e_phase(T* __restrict__ F, const Grid2D& g, const T* __restrict__ Lc, int m,
+                                        const T* __restrict__ R) {
+    constexpr int kBatch = batch_of<T>();
+    T* Ex = F;
+    T* Ey = F + g.ncell;
+    T* Ez = F + 2 * g.ncell;
+    const T* Hx = F + 3 * g.ncell;
+    const T* Hy = F + 4 * g.ncell;
+    const T* Hz = F + 5 * g.ncell;
+    const int nx = g.nx, ny = g.ny;
+    const int di = NTH % nx, dj = NTH / nx;
+    int i = threadIdx.x % nx, j = threadIdx.x / nx;
+    while (j < ny) {
+        T hx[kBatch], hy[kBatch], hz[kBatch], hxd[kBatch], hzd[kBatch], hyl[kBatch], hzl[kBatch];
+        T ex[kBatch], ey[kBatch], ez[kBatch];
+        int cc[kBatch], jj[kBatch];
+        uint32_t id[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            jj[q] = j;
+            cc[q] = j * nx + i;
+            if (j < ny) {
+                const int c = cc[q];
+                const bool in_d = j > 0;
+                hxd[q] = in_d ? Hx[c - nx] : T(0);
+                hzd[q] = in_d ? Hz[c - nx] : T(0);
+                hyl[q] = i > 0 ? Hy[c - 1] : (g.perx ? Hy[c - 1 + nx] : T(0));
+                hzl[q] = i > 0 ? Hz[c - 1] : (g.perx ? Hz[c - 1 + nx] : T(0));
+                hx[q] = Hx[c];
+                hy[q] = Hy[c];
+                hz[q] = Hz[c];
+                ex[q] = Ex[c];
+                ey[q] = Ey[c];
+                ez[q] = Ez[c];
+                id[q] = uint32_t(g.ids[CF_EX][c]) | (uint32_t(g.ids[CF_EY][c]) << 8) |
+                        (uint32_t(g.ids[CF_EZ][c]) << 16);
+            }
+            i += di;
+            j += dj;
+            if (i >= nx) {
+                i -= nx;
+                ++j;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            if (jj[q] < ny) {
+                const int c = cc[q];
+                e_values<T, MODE>(ex[q], ey[q], ez[q], hx[q], hy[q], hz[q], hxd[q], hzd[q], hyl[q], hzl[q],
+                                  Lc + ((CF_EX << 8) + (int)(id[q] & 255)) * 2,
+                                  Lc + ((CF_EY << 8) + (int)((id[q] >> 8) & 255)) * 2,
+                                  Lc + ((CF_EZ << 8) + (int)(id[q] >> 16)) * 2, m, jj[q], R[2 * jj[q]],
+                                  R[2 * jj[q] + 1]);
+                Ex[c] = ex[q];
+                Ey[c] = ey[q];
+                Ez[c] = ez[q];
+            }
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                               const int* __restrict__ slots, Grid2D g, CylOrders ord,
                                                               SurfTables t, double dA, double* __restrict__ acc,
                                                               double* __restrict__ gamma, int gamma_stride) {
     __shared__ double red[yee::kSurfThreads / 64];
+    __shared__ T Lc[6 * 256 * 2];
     const int slot = slots[blockIdx.x];
     const ChanDev d = ch[slot];
     const int m = d.order;
@@ -205,6 +366,8 @@ __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fi
     const int nsteps = ord.steps[m];
     const double dt = ord.dt[m];
     T* F = fields + d.field_off;
+    const T* lk = lut + d.kind * 6 * 256 * 2;
+    for (int k = threadIdx.x; k < 6 * 256 * 2; k += kResThreads) Lc[k] = lk[k];
     const int64_t nval = 6 * g.ncell;
     for (int64_t k = threadIdx.x; k < nval; k += kResThreads) F[k] = T(0);
     __syncthreads();
@@ -216,8 +379,9 @@ __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fi
         fields[d.src_off + t.uidx[d.u_off + u]] = T(d.kick_scale * s);
     }
     __syncthreads();
-    if (d.kind == 0) for_cells(g, [&](int i, int j) { hcyl_cell<T, 1>(F, g, lut, d.kind, m, i, j); });
-    else for_cells(g, [&](int i, int j) { ecyl_cell<T, 1>(F, g, lut, d.kind, m, i, j); });
+    const T* R = static_cast<const T*>(ord.rinv);
+    if (d.kind == 0) h_phase<T, 1>(F, g, Lc, m, R);
+    else e_phase<T, 1>(F, g, Lc, m, R);
     __syncthreads();
     const T* X = fields + d.meas_off;
     double sum = 0.0, comp = 0.0;
@@ -226,9 +390,9 @@ __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fi
         comp = acc[2 * slot + 1];
     }
     for (int step = 0; step < nsteps; ++step) {
-        for_cells(g, [&](int i, int j) { hcyl_cell<T, 0>(F, g, lut, d.kind, m, i, j); });
+        h_phase<T, 0>(F, g, Lc, m, R);
         __syncthreads();
-        for_cells(g, [&](int i, int j) { ecyl_cell<T, 0>(F, g, lut, d.kind, m, i, j); });
+        e_phase<T, 0>(F, g, Lc, m, R);
         __syncthreads();
         // every read of X ends at the barrier inside; the next writes of the
         // fields come after it
@@ -245,33 +409,288 @@ __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fi
     }
 }
 
+// Length of the exchange array of the register kernel: 3 n values, and at
+// least the 6 x 256 coefficient pairs it holds during the start.
+__host__ __device__ constexpr int regs_x_len(int n) { return 3 * n > 6 * 256 * 2 ? 3 * n : 6 * 256 * 2; }
+
+// Register-resident solve: the clear, kick and start as in k_cyl_resident,
+// then every thread keeps the six fields of its K cells (flat cells t,
+// t + NTH, ...) in registers for all steps.  LDS holds one array of 3 x ncell
+// values that carries the E triple during the H half step and the H triple
+// during the E half step (the neighbour exchange), the six material ids of
+// every cell packed in 4 bits each (ord.idw; 15 stands for the wall id), and
+// the 6 x 16 coefficient pairs of the block's kind.  The surface projection
+// reads the measured component from the exchange array (H components before
+// the E half step overwrites it: the values the other drivers read after the
+// step).  A cell's coordinates are recomputed in every half step from the
+// thread's first cell, passed through an empty asm statement so that the
+// compiler keeps no per-cell addresses in registers across steps.
+template <typename T, int K, int NTH>
+__global__ __launch_bounds__(NTH) void k_cyl_regs(T* __restrict__ fields, const ChanDev* __restrict__ ch,
+                                                  const int* __restrict__ slots, Grid2D g, CylOrders ord,
+                                                  SurfTables t, double dA, double* __restrict__ acc,
+                                                  double* __restrict__ gamma, int gamma_stride) {
+    extern __shared__ double lds_dyn[];
+    __shared__ double red[yee::kSurfThreads / 64];
+    const int n = (int)g.ncell;
+    T* X = reinterpret_cast<T*>(lds_dyn);          // 3 n exchange values
+    T* Lg = X;                                      // the kind's full table, for the start (before X is used)
+    T* Lc = X + regs_x_len(n);                      // 6 x 16 (a, b) pairs
+    T* R = Lc + 6 * 16 * 2;                         // 1/r per row: (1/j, 1/(j - 1/2))
+    uint32_t* W = reinterpret_cast<uint32_t*>(R + 2 * g.ny);   // packed ids per cell
+    const int slot = slots[blockIdx.x];
+    const ChanDev d = ch[slot];
+    const int m = d.order;
+    const T* lut = static_cast<const T*>(ord.lut) + m * ord.lut_stride;
+    const double* ktab = ord.ktab + m * ord.ktab_stride;
+    const int nsteps = ord.steps[m];
+    const double dt = ord.dt[m];
+    T* F = fields + d.field_off;
+    const T* lk = lut + d.kind * 6 * 256 * 2;
+    for (int k = threadIdx.x; k < 6 * 256 * 2; k += NTH) Lg[k] = lk[k];
+    for (int k = threadIdx.x; k < 6 * 16 * 2; k += NTH) {
+        const int cmp = k / 32, q = (k / 2) % 16;
+        Lc[k] = lk[((cmp << 8) + (q == 15 ? 255 : q)) * 2 + (k & 1)];
+    }
+    for (int k = threadIdx.x; k < n; k += NTH) W[k] = ord.idw[k];
+    for (int k = threadIdx.x; k < 2 * g.ny; k += NTH) R[k] = static_cast<const T*>(ord.rinv)[k];
+    for (int64_t k = threadIdx.x; k < 6 * g.ncell; k += NTH) F[k] = T(0);
+    __syncthreads();
+    // (the exchange array takes over Lg's space after the start)
+    for (int u = threadIdx.x; u < d.n_uniq; u += NTH) {
+        const int k0 = t.uoff[d.u_off + u], k1 = t.uoff[d.u_off + u + 1];
+        double s = 0.0;
+        for (int k = k0; k < k1; ++k) s += t.uw[k] * t.basis[d.basis_off + t.usamp[k]];
+        fields[d.src_off + t.uidx[d.u_off + u]] = T(d.kick_scale * s);
+    }
+    __syncthreads();
+    if (d.kind == 0) h_phase<T, 1, NTH>(F, g, Lg, m, R);
+    else e_phase<T, 1, NTH>(F, g, Lg, m, R);
+    __syncthreads();
+    T e0[K], e1[K], e2[K], h0[K], h1[K], h2[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int c = threadIdx.x + k * NTH;
+        if (c < n) {
+            e0[k] = F[c];
+            e1[k] = F[n + c];
+            e2[k] = F[2 * n + c];
+            h0[k] = F[3 * n + c];
+            h1[k] = F[4 * n + c];
+            h2[k] = F[5 * n + c];
+            X[c] = e0[k];
+            X[n + c] = e1[k];
+            X[2 * n + c] = e2[k];
+        } else {
+            e0[k] = e1[k] = e2[k] = h0[k] = h1[k] = h2[k] = T(0);
+        }
+    }
+    __syncthreads();
+    const bool meas_h = d.meas_slot >= 3;
+    const T* Xq = X + (d.meas_slot % 3) * n;
+    const int nx = g.nx, ny = g.ny;
+    const int di = NTH % nx, dj = NTH / nx;
+    int i0 = threadIdx.x % nx, j0 = threadIdx.x / nx;
+    double sum = 0.0, comp = 0.0;
+    if (threadIdx.x == 0) {
+        sum = acc[2 * slot];
+        comp = acc[2 * slot + 1];
+    }
+    auto pair = [&](int cmp, uint32_t w) { return Lc + ((cmp << 4) + (int)((w >> (4 * cmp)) & 15)) * 2; };
+    auto measure = [&](int step) {
+        const double s = yee::block_surface_sum(d, t, [&](int32_t idx) { return (double)Xq[idx]; }, red);
+        if (threadIdx.x == 0) {
+            const double G = dA * s;
+            yee::neumaier(sum, comp, (dt * ktab[step]) * G);
+            if (gamma) gamma[(int64_t)step * gamma_stride + slot] = G;
+        }
+    };
+    for (int step = 0; step < nsteps; ++step) {
+        asm volatile("" : "+v"(i0), "+v"(j0));
+        {
+            int i = i0, j = j0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (j < ny) {
+                    const int c = j * nx + i;
+                    const bool in_r = i + 1 < nx, in_u = j + 1 < ny;
+                    const uint32_t w = W[c];
+                    const T ezu = in_u ? X[2 * n + c + nx] : T(0);
+                    const T exu = in_u ? X[c + nx] : T(0);
+                    const T ezr = in_r ? X[2 * n + c + 1] : (g.perx ? X[2 * n + c + 1 - nx] : T(0));
+                    const T eyr = in_r ? X[n + c + 1] : (g.perx ? X[n + c + 1 - nx] : T(0));
+                    h_values<T, 0>(h0[k], h1[k], h2[k], e0[k], e1[k], e2[k], ezu, exu, ezr, eyr, pair(CF_HX, w),
+                                   pair(CF_HY, w), pair(CF_HZ, w), m, j, R[2 * j], R[2 * j + 1]);
+                }
+                i += di;
+                j += dj;
+                if (i >= nx) {
+                    i -= nx;
+                    ++j;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int c = threadIdx.x + k * NTH;
+            if (c < n) {
+                X[c] = h0[k];
+                X[n + c] = h1[k];
+                X[2 * n + c] = h2[k];
+            }
+        }
+        __syncthreads();
+        if (meas_h) measure(step);
+        asm volatile("" : "+v"(i0), "+v"(j0));
+        {
+            int i = i0, j = j0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (j < ny) {
+                    const int c = j * nx + i;
+                    const bool in_d = j > 0;
+                    const uint32_t w = W[c];
+                    const T hxd = in_d ? X[c - nx] : T(0);
+                    const T hzd = in_d ? X[2 * n + c - nx] : T(0);
+                    const T hyl = i > 0 ? X[n + c - 1] : (g.perx ? X[n + c - 1 + nx] : T(0));
+                    const T hzl = i > 0 ? X[2 * n + c - 1] : (g.perx ? X[2 * n + c - 1 + nx] : T(0));
+                    e_values<T, 0>(e0[k], e1[k], e2[k], h0[k], h1[k], h2[k], hxd, hzd, hyl, hzl, pair(CF_EX, w),
+                                   pair(CF_EY, w), pair(CF_EZ, w), m, j, R[2 * j], R[2 * j + 1]);
+                }
+                i += di;
+                j += dj;
+                if (i >= nx) {
+                    i -= nx;
+                    ++j;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int c = threadIdx.x + k * NTH;
+            if (c < n) {
+                X[c] = e0[k];
+                X[n + c] = e1[k];
+                X[2 * n + c] = e2[k];
+            }
+        }
+        __syncthreads();
+        if (!meas_h) measure(step);
+    }
+    if (threadIdx.x == 0) {
+        acc[2 * slot] = sum;
+        acc[2 * slot + 1] = comp;
+    }
+}
+
+template <typename T>
+size_t regs_lds_bytes(const Grid2D& g) {
+    return ((size_t)regs_x_len((int)g.ncell) + 6 * 16 * 2 + 2 * (size_t)g.ny) * sizeof(T) + 4 * (size_t)g.ncell;
+}
+
+
+// Register variants (cells per thread K, threads per block NTH), each
+// without register spills, smallest first: FP32 up to 10240 cells, FP64 up
+// to 6144 (the LDS of a CU, 16 or 28 bytes per cell, bounds both first).
+struct RegVariant {
+    int K, NTH;
+};
+constexpr int kNumRegVariants = 6;
+template <typename T>
+constexpr RegVariant kRegVariants[kNumRegVariants] = {{1, 1024}, {2, 1024}, {4, 1024}, {6, 1024}, {8, 1024}, {10, 1024}};
+template <>
+constexpr RegVariant kRegVariants<double>[kNumRegVariants] = {{1, 1024}, {2, 1024}, {3, 1024}, {4, 1024}, {6, 1024},
+                                                               {6, 1024}};
+
+// LDS bytes a block may take on the current device
+inline size_t device_lds_limit() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 65536;
+    return (size_t)v;
+}
+
+// Dynamic LDS above 64 KB needs the kernel's attribute raised first; false
+// when the runtime refuses (the caller then takes the global-memory variant).
+template <typename T, int K, int NTH>
+bool regs_lds_ok(size_t lds) {
+    if (lds <= 65536) return true;
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cyl_regs<T, K, NTH>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return true;
+}
+
+// Launch register variant v if the grid fits it: *launched tells whether it did.
+template <typename T, int V>
+hipError_t regs_try(int64_t ncell, size_t lds, bool* launched, T* fields, const ChanDev* ch, const int* slots,
+                    int nslots, const Grid2D& g, const CylOrders& ord, const SurfTables& t, double dA, double* acc,
+                    double* gamma, int gamma_stride, hipStream_t s) {
+    constexpr int K = kRegVariants<T>[V].K, NTH = kRegVariants<T>[V].NTH;
+    *launched = false;
+    if (ncell > (int64_t)K * NTH || !regs_lds_ok<T, K, NTH>(lds)) return hipSuccess;
+    *launched = true;
+    hipLaunchKernelGGL((k_cyl_regs<T, K, NTH>), dim3(nslots), dim3(NTH), lds, s, fields, ch, slots, g, ord, t, dA,
+                       acc, gamma, gamma_stride);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 template <typename T>
 hipError_t launch_hcyl(int mode, int m, T* fields, const ChanDev* ch, const int* slots, int nslots,
-                       const Grid2D& g, const T* lut, hipStream_t s) {
+                       const Grid2D& g, const T* lut, const T* rinv, hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
     const dim3 grid = grid_cyl(g, nslots), block(BX, BY, 1);
-    if (mode == 0) hipLaunchKernelGGL((k_hcyl<T, 0>), grid, block, 0, s, fields, ch, slots, g, lut, m);
-    else hipLaunchKernelGGL((k_hcyl<T, 1>), grid, block, 0, s, fields, ch, slots, g, lut, m);
+    if (mode == 0) hipLaunchKernelGGL((k_hcyl<T, 0>), grid, block, 0, s, fields, ch, slots, g, lut, m, rinv);
+    else hipLaunchKernelGGL((k_hcyl<T, 1>), grid, block, 0, s, fields, ch, slots, g, lut, m, rinv);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_ecyl(int mode, int m, T* fields, const ChanDev* ch, const int* slots, int nslots,
-                       const Grid2D& g, const T* lut, hipStream_t s) {
+                       const Grid2D& g, const T* lut, const T* rinv, hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
     const dim3 grid = grid_cyl(g, nslots), block(BX, BY, 1);
-    if (mode == 0) hipLaunchKernelGGL((k_ecyl<T, 0>), grid, block, 0, s, fields, ch, slots, g, lut, m);
-    else hipLaunchKernelGGL((k_ecyl<T, 1>), grid, block, 0, s, fields, ch, slots, g, lut, m);
+    if (mode == 0) hipLaunchKernelGGL((k_ecyl<T, 0>), grid, block, 0, s, fields, ch, slots, g, lut, m, rinv);
+    else hipLaunchKernelGGL((k_ecyl<T, 1>), grid, block, 0, s, fields, ch, slots, g, lut, m, rinv);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cyl_resident(T* fields, const ChanDev* ch, const int* slots, int nslots, const Grid2D& g,
-                               const CylOrders& ord, const SurfTables& t, double dA, double* acc, double* gamma,
-                               int gamma_stride, hipStream_t s) {
+hipError_t launch_cyl_resident(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
+                               const Grid2D& g, const CylOrders& ord, const SurfTables& t, double dA, double* acc,
+                               double* gamma, int gamma_stride, hipStream_t s, int* used) {
+    *used = 0;
     if (nslots <= 0) return hipSuccess;
+    const size_t dyn = regs_lds_bytes<T>(g);
+    if (variant != 2 && ord.idw && dyn + 64 <= device_lds_limit()) {
+        bool launched = false;
+        hipError_t e = hipSuccess;
+        auto attempt = [&](auto v) {
+            if (!launched && e == hipSuccess)
+                e = regs_try<T, decltype(v)::value>(g.ncell, dyn, &launched, fields, ch, slots, nslots, g, ord, t,
+                                                    dA, acc, gamma, gamma_stride, s);
+        };
+        attempt(std::integral_constant<int, 0>{});
+        attempt(std::integral_constant<int, 1>{});
+        attempt(std::integral_constant<int, 2>{});
+        attempt(std::integral_constant<int, 3>{});
+        attempt(std::integral_constant<int, 4>{});
+        attempt(std::integral_constant<int, 5>{});
+        static_assert(kNumRegVariants == 6, "one attempt per register variant");
+        if (e != hipSuccess) return e;
+        if (launched) {
+            *used = 1;
+            return hipSuccess;
+        }
+    }
+    *used = 2;
     hipLaunchKernelGGL((k_cyl_resident<T>), dim3(nslots), dim3(kResThreads), 0, s, fields, ch, slots, g, ord, t, dA,
                        acc, gamma, gamma_stride);
     return hipGetLastError();
@@ -279,12 +698,12 @@ hipError_t launch_cyl_resident(T* fields, const ChanDev* ch, const int* slots, i
 
 #define CF_CYL_INSTANTIATE(T)                                                                                   \
     template hipError_t launch_hcyl<T>(int, int, T*, const ChanDev*, const int*, int, const Grid2D&, const T*, \
-                                       hipStream_t);                                                           \
+                                       const T*, hipStream_t);                                                 \
     template hipError_t launch_ecyl<T>(int, int, T*, const ChanDev*, const int*, int, const Grid2D&, const T*, \
-                                       hipStream_t);                                                           \
-    template hipError_t launch_cyl_resident<T>(T*, const ChanDev*, const int*, int, const Grid2D&,            \
+                                       const T*, hipStream_t);                                                 \
+    template hipError_t launch_cyl_resident<T>(int, T*, const ChanDev*, const int*, int, const Grid2D&,       \
                                                const CylOrders&, const SurfTables&, double, double*, double*, \
-                                               int, hipStream_t);
+                                               int, hipStream_t, int*);
 CF_CYL_INSTANTIATE(float)
 CF_CYL_INSTANTIATE(double)
 #undef CF_CYL_INSTANTIATE

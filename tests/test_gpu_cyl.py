@@ -122,18 +122,40 @@ def test_fp32_matches_oracle(cf, name):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_resident_split_plain_bitwise(cf, precision):
-    """The resident solve (default), the split half-step launches and the
-    plain one-channel-at-a-time path share the per-cell updates and the
-    surface reduction: identical accumulators."""
+    """The resident solve (default; register and global-memory variants),
+    the split half-step launches and the plain one-channel-at-a-time path
+    share the per-cell updates and the surface reduction: identical
+    accumulators and Gamma rows."""
     announce(f"cylindrical resident / split / plain, bitwise, {precision}")
     for name in ("closed", "wall"):
         wl, _ = oracle_result(name)
-        full = run(cf, wl, precision=precision, keep_gamma=True)
         split = run(cf, wl, precision=precision, split=True, keep_gamma=True)
-        np.testing.assert_array_equal(split["per_channel"], full["per_channel"])
-        np.testing.assert_array_equal(split["gamma"], full["gamma"])
+        assert not split["fused"]
+        for variant, expect in ((0, 1), (1, 1), (2, 2)):     # auto, registers + LDS, global memory
+            res = run(cf, wl, precision=precision, keep_gamma=True, tile_variant=variant)
+            assert res["fused"] and res["tile_variant"] == expect, (variant, res["tile_variant"])
+            np.testing.assert_array_equal(split["per_channel"], res["per_channel"])
+            np.testing.assert_array_equal(split["gamma"], res["gamma"])
         plain = run(cf, wl, precision=precision, path="plain")
-        np.testing.assert_array_equal(plain["per_channel"], full["per_channel"])
+        np.testing.assert_array_equal(plain["per_channel"], split["per_channel"])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_resident_variants_at_benchmark_size(cf, precision):
+    """Resolution 40 piston (400 x 21 cells): the register variant with 10
+    cells per thread (FP32; FP64 exceeds the LDS there and takes the
+    global-memory variant), the global-memory variant and the split path
+    agree bitwise on a sample of channels of every order."""
+    announce(f"cylindrical resident variants at benchmark size, {precision}")
+    wl = c_cyl_piston(n_steps=300)
+    n = cf.Problem.from_workload(wl).info(pol="3D", kernel=wl.kernel, n_steps=300)["n_channels"]
+    sub = [0, 7, 41, 42, 60, 83, 84, 100, n - 1]
+    ref = run(cf, wl, precision=precision, split=True, channel_subset=sub)
+    for variant in (0, 2):
+        res = run(cf, wl, precision=precision, tile_variant=variant, channel_subset=sub)
+        expect = 1 if (variant == 0 and precision == "fp32") else 2
+        assert res["tile_variant"] == expect, (variant, res["tile_variant"])
+        np.testing.assert_array_equal(ref["per_channel"], res["per_channel"])
 
 
 def test_plain_path_and_waves_bitwise(cf):
