@@ -122,7 +122,7 @@ def bench_3d(cf, torch, n_chan=64, n_steps=200, variant=0):
             "projected_full_solve_s": 1280 * wl.n_cells * wl.n_steps / rate}
 
 
-def bench_cyl(cf, torch, cpu_sample=True):
+def bench_cyl(cf, torch, cpu_sample=True, quick=False):
     """Cylindrical piston (Sec. III D, Fig. 7) at resolution 40, n, m in
     {0, 1, 2}: one whole force point (126 channels; orders 0 and 1 take
     10000 steps, order 2 15000 on its smaller step), FP32 fields, on the
@@ -140,6 +140,9 @@ def bench_cyl(cf, torch, cpu_sample=True):
     r = p.solve(time_stencil=True, **o)
     wall = time.perf_counter() - t1
     rate = r["cell_updates"] / (r["device_ms"] * 1e-3)
+    if quick:
+        return {"force": r["force"], "device_ms": r["device_ms"], "value": rate, "unit": "cell-updates/s",
+                "resident_variant": r["tile_variant"], "launch_ms": r["stencil_ms_avg"]}
     rs = p.solve(split=True, **o)
     r64 = p.solve(**dict(o, precision="fp64"))
     alg = rate * 48.0                                  # read + write of 6 FP32 values per cell-update
@@ -373,6 +376,10 @@ def main():
                     help="fused 3D variant of the 3D sample (0: autotuned, with a sweep of all variants)")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-cyl", action="store_true")
+    ap.add_argument("--cyl-only", action="store_true",
+                    help="only the cylindrical piston section (for profiling); prints its record")
+    ap.add_argument("--cyl-quick", action="store_true",
+                    help="with --cyl-only: the register-resident FP32 solve only (no split / FP64 / oracle)")
     ap.add_argument("--serve-n", type=int, default=24, help="requests in the served piston stream")
     ap.add_argument("--serve-mixed", type=int, default=0,
                     help="also serve this many requests of the mixed 2D/3D stream (long: 3D requests "
@@ -388,6 +395,8 @@ def main():
         args.no_precision = True
         if args.with_3d:
             args.no_3d = False
+    if args.cyl_only:
+        args.no_cpu = True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the channel-parallel "
               "multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
@@ -418,6 +427,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
         del a, b
+    if args.cyl_only:
+        print(json.dumps(bench_cyl(cf, torch, cpu_sample=False, quick=args.cyl_quick)), flush=True)
+        return
     prob = cf.Problem.from_workload(wl)
     opts = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol=wl.pol,
                 kernel=wl.kernel, precision="fp32", tile_variant=args.tile_variant)
