@@ -31,6 +31,8 @@ from .configs import (
     c4_sphere_plate,
     cyl_piston,
     c_cyl_piston,
+    dielectric_piston2d,
+    kz_workload,
     small_cases,
 )
 
@@ -52,5 +54,7 @@ __all__ = [
     "c4_sphere_plate",
     "cyl_piston",
     "c_cyl_piston",
+    "dielectric_piston2d",
+    "kz_workload",
     "small_cases",
 ]

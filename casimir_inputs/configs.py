@@ -259,6 +259,33 @@ def c_cyl_piston(**over) -> Workload:
     return cyl_piston(**kw)
 
 
+def kz_workload(wl: Workload, kz, kz_weight) -> Workload:
+    """The z-invariant 2D workload wl solved at Bloch wavevectors kz along
+    z (six components, general kernel); the force is sum_q kz_weight[q] F(kz[q])."""
+    return wl.replace(coord="kz", kz=tuple(float(k) for k in kz), kz_weight=tuple(float(w) for w in kz_weight),
+                      pol="3D", kernel="general", name=wl.name + f"_kz{len(kz)}")
+
+
+def dielectric_piston2d(nx: int, ny: int, slab_px: int, block_w: int, block_h: int, gap: int, block_y0: int,
+                        res: float, eps_block: float = 4.0, n_harm: int = 16, **opts) -> Workload:
+    """The 2D piston with dielectric blocks (eps_block) instead of PEC ones,
+    between PEC sidewall slabs: a z-invariant geometry whose two
+    polarizations hybridize at k_z != 0 (Sec. III C)."""
+    wl = piston2d(nx, ny, slab_px, block_w, block_h, gap, block_y0, res, n_harm=n_harm, **opts)
+    eps = [1.0, PEC, float(eps_block)]
+    left, right = wl.meta["blocks"]
+    y0, y1 = wl.meta["block_y"]
+    prims = [
+        Box((-BIG, -BIG, -BIG), (BIG, slab_px, BIG), 1),
+        Box((-BIG, ny - slab_px, -BIG), (BIG, BIG, BIG), 1),
+        Box((left[0], y0, -BIG), (left[1], y1, BIG), 2),
+        Box((right[0], y0, -BIG), (right[1], y1, BIG), 2),
+    ]
+    ids = rasterize((nx, ny, 1), prims)
+    return wl.replace(eps=eps, mu=[1.0, 1.0, 1.0], comp_ids=ids, name=f"dielectric_piston2d_{nx}x{ny}",
+                      meta=dict(wl.meta, eps_block=float(eps_block)))
+
+
 def small_cases():
     """Small workloads the oracle finishes in seconds (parity test sizes)."""
     return {

@@ -103,10 +103,12 @@ class Workload:
     force_axis 0/1/2
     sigma, courant, n_steps, pol ("TM", "TE", "TM+TE", "3D"), kernel
     ("zinv2d" | "general"), precision ("fp64" | "fp32")
-    coord      "cartesian" or "cylindrical": a cylindrical workload is a 2D
+    coord      "cartesian", "cylindrical" or "kz": a cylindrical workload is a 2D
                (z, r) grid, x = z along the symmetry axis, y = r + 1/2
                (cells), the tube wall at r = ny - 1/2
     m_max      cylindrical workloads: azimuthal orders 0..m_max
+    kz, kz_weight  "kz" workloads (z-invariant 2D, six components): the
+               Bloch wavevectors along z and the weights of F(k_q) in the force
     """
 
     name: str
@@ -131,6 +133,8 @@ class Workload:
     meta: dict = dataclasses.field(default_factory=dict)
     coord: str = "cartesian"
     m_max: int = 0
+    kz: Tuple[float, ...] = ()
+    kz_weight: Tuple[float, ...] = ()
 
     def replace(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)

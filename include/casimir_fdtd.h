@@ -93,7 +93,29 @@ enum { CF_EX = 0, CF_EY, CF_EZ, CF_HX, CF_HY, CF_HZ };
  *     H_phi on it are the next row's values for m = 1 and zero otherwise
  *     (the interpolation onto S applies this; the arrays hold zero there).
  */
-enum { CF_COORD_CARTESIAN = 0, CF_COORD_CYLINDRICAL = 1 };
+enum { CF_COORD_CARTESIAN = 0, CF_COORD_CYLINDRICAL = 1, CF_COORD_KZ = 2 };
+
+/*
+ * CF_COORD_KZ describes a z-invariant two-dimensional problem solved at
+ * Bloch wavevectors k_z along the invariant axis (Sec. III C: dielectrics
+ * hybridize the polarizations, so every k_z is its own two-dimensional
+ * simulation; Sec. III E: the force as an integral over the wavevectors).
+ *   - ndim = 2, bc[0], bc[1] CF_BC_PEC or CF_BC_PERIODIC; the grid, the
+ *     materials and S as for a Cartesian 2D problem.
+ *   - Fields proportional to exp(i k z) with E_z, H_x, H_y carried as
+ *     -i times their value: a real system in all six components, the k
+ *     terms coupling E_x with H_y and E_y with H_x (at k = 0 it splits into
+ *     TM and TE).
+ *   - cf_surface.kz[q], kz_weight[q] (q < n_kz <= 33): the force is
+ *     F = sum_q kz_weight[q] F(k_q), F(k) = (1/pi) sum_c s_c acc_c the
+ *     two-dimensional force of the run at k (use the general kernel).  For
+ *     the force per unit length, (1/pi) int_0^inf F(k) dk, the weights of a
+ *     quadrature on [0, inf) times 1/pi.
+ *   - Every k runs with the same time step and step count; courant must
+ *     satisfy courant * v_max * sqrt(8 + (k_max / res)^2) / 2 < 1.
+ *   - Channels, labels (q * n_harm + n) and signs (times kz_weight[q]) are
+ *     ordered as for cylindrical orders.
+ */
 
 typedef struct cf_grid {
     int ndim;          /* 2 or 3                                                   */
@@ -136,6 +158,9 @@ typedef struct cf_surface {
     int n_harm;
     int force_axis;    /* 0, 1 or 2 */
     int m_max;         /* cylindrical problems: azimuthal orders 0..m_max (<= 32) */
+    const double* kz;        /* CF_COORD_KZ problems: the wavevectors k_q (host, copied) */
+    const double* kz_weight; /* and their weights                                        */
+    int n_kz;                /* number of wavevectors (1..33)                            */
 } cf_surface;
 
 /*
@@ -154,8 +179,9 @@ typedef struct cf_surface {
  * with K sampled at its own steps.  The force is
  *   F = (1/pi) sum_m w_m sum_c s_c sum_k dt_m K(t_k) Gamma_c(t_k),
  * w_0 = 1, w_m>0 = 2 (the -m term is the conjugate of the +m term).
- * Options: pol = CF_POL_3D (all six components), courant <= 0.5; stop_tol
- * and the server are not available (CF_E_UNSUPPORTED).  Execution: by
+ * Options (cylindrical and k_z problems alike): pol = CF_POL_3D (all six
+ * components); cylindrical runs need courant <= 0.5; stop_tol and the
+ * server are not available (CF_E_UNSUPPORTED).  Execution: by
  * default one launch per wave of resident channels (any mix of orders),
  * each block carrying one channel through all its steps; tile_variant 1
  * keeps the fields in registers with an LDS exchange (grids of up to 4096

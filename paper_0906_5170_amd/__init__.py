@@ -22,7 +22,7 @@ POL = {"TM": 1, "TE": 2, "TM+TE": 3, "3D": 4}
 KERNEL = {"general": 0, "zinv2d": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 PATH = {"batched": 0, "plain": 1}
-COORD = {"cartesian": 0, "cylindrical": 1}
+COORD = {"cartesian": 0, "cylindrical": 1, "kz": 2}
 FLAG_KEEP_GAMMA = 1
 FLAG_TIME_STENCIL = 2
 FLAG_SPLIT = 4
@@ -51,7 +51,8 @@ class _Materials(C.Structure):
 
 class _Surface(C.Structure):
     _fields_ = [("lo", C.c_int * 3), ("hi", C.c_int * 3), ("n_harm", C.c_int),
-                ("force_axis", C.c_int), ("m_max", C.c_int)]
+                ("force_axis", C.c_int), ("m_max", C.c_int), ("kz", C.POINTER(C.c_double)),
+                ("kz_weight", C.POINTER(C.c_double)), ("n_kz", C.c_int)]
 
 
 class _Opts(C.Structure):
@@ -191,7 +192,8 @@ class Problem:
     def __init__(self, ndim: int, shape: Sequence[int], res: float, bc: Sequence[str],
                  eps: Sequence[float], mu: Sequence[float], comp_ids: Dict[str, np.ndarray],
                  s_lo: Sequence[int], s_hi: Sequence[int], n_harm: int, force_axis: int,
-                 pml_cells: Sequence[int] = (0, 0, 0), coord: str = "cartesian", m_max: int = 0):
+                 pml_cells: Sequence[int] = (0, 0, 0), coord: str = "cartesian", m_max: int = 0,
+                 kz: Sequence[float] = (), kz_weight: Sequence[float] = ()):
         lib = load()
         g = _Grid()
         g.ndim = int(ndim)
@@ -225,6 +227,12 @@ class Problem:
         s.n_harm = int(n_harm)
         s.force_axis = int(force_axis)
         s.m_max = int(m_max)
+        kz_arr = np.ascontiguousarray(kz, dtype=np.float64)
+        kzw_arr = np.ascontiguousarray(kz_weight, dtype=np.float64)
+        if len(kz_arr) != len(kzw_arr):
+            raise ValueError("kz and kz_weight differ in length")
+        if len(kz_arr):
+            s.kz, s.kz_weight, s.n_kz = _dptr(kz_arr), _dptr(kzw_arr), len(kz_arr)
         h = C.c_void_p()
         _check(lib.cf_problem_create(C.byref(g), C.byref(m), C.byref(s), C.byref(h)))
         self._h = h
@@ -237,7 +245,8 @@ class Problem:
     @classmethod
     def from_workload(cls, wl) -> "Problem":
         return cls(wl.ndim, wl.shape, wl.res, wl.bc, wl.eps, wl.mu, wl.comp_ids, wl.s_lo, wl.s_hi,
-                   wl.n_harm, wl.force_axis, wl.pml_cells, coord=wl.coord, m_max=wl.m_max)
+                   wl.n_harm, wl.force_axis, wl.pml_cells, coord=wl.coord, m_max=wl.m_max,
+                   kz=wl.kz, kz_weight=wl.kz_weight)
 
     def __del__(self):
         h = getattr(self, "_h", None)

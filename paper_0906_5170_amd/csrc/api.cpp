@@ -114,13 +114,13 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
     // waves: consecutive runs of `resident` channels; the split cylindrical
     // path groups the channels by azimuthal order first (one order per wave),
     // the resident cylindrical kernel takes any mix of orders
-    st.cyl_res = p.cyl && !plain && !(o.flags & CF_FLAG_SPLIT);
+    st.cyl_res = p.reduced() && !plain && !(o.flags & CF_FLAG_SPLIT);
     std::vector<std::vector<int>> wave_lists;
     std::vector<int> wave_order;
     {
         std::vector<std::vector<int>> groups;
-        if (p.cyl && !st.cyl_res) {
-            groups.assign(p.m_max + 1, {});
+        if (p.reduced() && !st.cyl_res) {
+            groups.assign(p.n_orders(), {});
             for (int c = 0; c < C; ++c) groups[chans[c].order].push_back(c);
         } else {
             groups.emplace_back();
@@ -130,7 +130,7 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
             for (size_t k0 = 0; k0 < groups[gi].size(); k0 += st.resident) {
                 const size_t k1 = std::min(groups[gi].size(), k0 + st.resident);
                 wave_lists.emplace_back(groups[gi].begin() + k0, groups[gi].begin() + k1);
-                wave_order.push_back(p.cyl && !st.cyl_res ? (int)gi : -1);
+                wave_order.push_back(p.reduced() && !st.cyl_res ? (int)gi : -1);
             }
     }
     std::vector<int> block_of(C, 0);
@@ -182,7 +182,7 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         add(0, &w.all_off, &w.n_all);
         st.waves.push_back(w);
     }
-    if (p.cyl) return;   // split cylindrical kernels only
+    if (p.reduced()) return;   // no fused 2D / 3D kernels for reduced problems
     if (!plain && p.grid.ndim == 3 && !(o.flags & CF_FLAG_SPLIT)) {
         cf::Grid3D g{};
         g.nx = p.nx;
@@ -274,7 +274,7 @@ static bool place_axis(int lo, int hi, int n, int w, int* base, int* ntiles, int
 
 TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, cf::TBShape sh) {
     TBPlan t;
-    if (p.grid.ndim != 2 || p.cyl || chans.empty()) return t;
+    if (p.grid.ndim != 2 || p.reduced() || chans.empty()) return t;
     int xmin = p.nx, xmax = -1, ymin = p.ny, ymax = -1;
     for (const auto& ch : chans) {
         const cf::Gather& g = p.gathers[p.gather_of.at({ch.face, ch.meas})];
@@ -330,7 +330,7 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     const size_t C = st.chans.size();
     const size_t block = (size_t)st.resident * st.ncomp * p.ncell * fsz;
     L.ids = take((size_t)cf::kNumComp * p.ncell);
-    const size_t n_orders = p.cyl ? (size_t)p.m_max + 1 : 1;   // cylindrical: one table per order
+    const size_t n_orders = (size_t)p.n_orders();   // reduced problems: one table per order
     L.lut = take(n_orders * 2 * cf::kNumComp * 256 * 2 * fsz);
     const int t_max = cf::max_steps(p, o);
     L.ktab = take(n_orders * (size_t)t_max * 8);
@@ -351,7 +351,7 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.psi = st.psi_comp > 0 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
     L.psi2 = st.psi_comp > 0 && st.f3d ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
     L.idp = st.f3d ? take((size_t)p.ncell * 8) : st.cyl_res ? take((size_t)p.ncell * 4) : off;
-    L.rinv = p.cyl ? take((size_t)2 * p.ny * fsz) : off;
+    L.rinv = p.reduced() ? take((size_t)6 * p.ny * fsz) : off;
     int max_tiles = 0;
     for (const TBPlan& pl : st.plans)
         if (pl.ok) max_tiles = std::max(max_tiles, pl.ntx * pl.nty);
@@ -427,8 +427,9 @@ struct GraphRun {
     }
 };
 
-// Cylindrical solve.  Every azimuthal order m has its own coefficient table
-// and K(t_k) (its own time step and step count).  Resident path: one launch
+// Reduced solve (cylindrical orders m, or k_z points q).  Every order has
+// its own coefficient table, K(t_k) and coupling (a cylindrical order its
+// own time step and step count).  Resident path: one launch
 // per wave, each block carrying one channel (any order) through all its
 // steps.  Split path (CF_FLAG_SPLIT, plain): waves of one order each; per
 // wave clear, kick, consistent start, then per step the H and E half steps
@@ -481,9 +482,9 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
     g.ny = p.ny;
     g.ncell = p.ncell;
     g.perx = p.grid.bc[0] == CF_BC_PERIODIC;
-    g.pery = 0;
+    g.pery = p.grid.bc[1] == CF_BC_PERIODIC;   // k_z problems only (the tube wall is PEC)
     for (int c = 0; c < cf::kNumComp; ++c) g.ids[c] = dids + (size_t)c * p.ncell;
-    const double dA = 1.0 / p.grid.res;       // Cartesian line element of the (r, z) plane
+    const double dA = 1.0 / p.grid.res;       // line element of the two-dimensional plane
     const size_t field_bytes = (size_t)st.resident * st.ncomp * p.ncell * sizeof(T);
     const double state_bytes = 2.0 * st.ncomp * sizeof(T);
     // per-order tables: coefficients for courant_m, K(t_k) on dt_m
@@ -493,27 +494,38 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
     ord.lut_stride = (int64_t)lut_len;
     ord.ktab = dk;
     ord.ktab_stride = t_max;
-    std::vector<T> luts(lut_len * (p.m_max + 1));
-    std::vector<double> ktabs((size_t)t_max * (p.m_max + 1), 0.0);
-    for (int m = 0; m <= p.m_max; ++m) {
+    const int n_ord = p.n_orders();
+    std::vector<T> luts(lut_len * n_ord);
+    std::vector<double> ktabs((size_t)t_max * n_ord, 0.0);
+    for (int m = 0; m < n_ord; ++m) {
         const double cm = cf::order_courant(p, o.courant, m);
         ord.steps[m] = cf::order_steps(p, o, m);
         ord.dt[m] = cm / p.grid.res;
+        ord.coup[m] = p.coupling(m);
         std::vector<double> l64 = cf::coefficient_lut(p, o.sigma, cm);
         std::copy(l64.begin(), l64.end(), luts.begin() + m * lut_len);
         cf::kernel_table(o.kernel, o.sigma, ord.dt[m], ord.steps[m], ktabs.data() + (size_t)m * t_max);
     }
+    ord.axis = p.cyl ? 1 : 0;
     CF_HIP(up(L.lut, luts.data(), luts.size() * sizeof(T)));
     CF_HIP(up(L.ktab, ktabs.data(), ktabs.size() * 8));
-    // reciprocal radii per row in the field precision (row 0 unused: zeros)
-    std::vector<T> rinv(2 * (size_t)p.ny, T(0));
-    for (int j = 1; j < p.ny; ++j) {
-        rinv[2 * j] = T(1) / T(j);
-        rinv[2 * j + 1] = T(1) / (T(j) - T(0.5));
-    }
-    CF_HIP(up(L.rinv, rinv.data(), rinv.size() * sizeof(T)));
-    ord.rinv = ws + L.rinv;
-    const T* drinv = reinterpret_cast<const T*>(ws + L.rinv);
+    // row factors in the field precision (A, B, C, D, P, Q per row):
+    // cylindrical (j + 1/2, j - 1/2, 1/j, 1/(j - 1/2), j, j - 1) with row 0
+    // on the axis (unused); k_z all 1
+    std::vector<T> rows(6 * (size_t)p.ny, p.cyl ? T(0) : T(1));
+    if (p.cyl)
+        for (int j = 1; j < p.ny; ++j) {
+            const T r = T(j);
+            rows[6 * j + 0] = r + T(0.5);
+            rows[6 * j + 1] = r - T(0.5);
+            rows[6 * j + 2] = T(1) / r;
+            rows[6 * j + 3] = T(1) / (r - T(0.5));
+            rows[6 * j + 4] = r;
+            rows[6 * j + 5] = r - T(1);
+        }
+    CF_HIP(up(L.rinv, rows.data(), rows.size() * sizeof(T)));
+    ord.rows = ws + L.rinv;
+    const T* drows = reinterpret_cast<const T*>(ws + L.rinv);
     // material ids packed in 4 bits per component for the register kernel
     // (15 = wall id), when every id fits
     std::vector<uint32_t> idw;
@@ -579,12 +591,12 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
         const double* k_m = dk + (size_t)m * t_max;
         STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
         STEP_OK(cf::launch_kick<T>(fields, dch, sl, w.n_all, st.max_uniq, tabs, s));
-        STEP_OK(cf::launch_hcyl<T>(1, m, fields, dch, sl, w.n_all, g, lut_m, drinv, s));
-        STEP_OK(cf::launch_ecyl<T>(1, m, fields, dch, sl, w.n_all, g, lut_m, drinv, s));
+        STEP_OK(cf::launch_hcyl<T>(1, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, s));
+        STEP_OK(cf::launch_ecyl<T>(1, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, s));
         for (int k = 0; k < tm; ++k) {
             const bool take = smp.begin(s);
-            STEP_OK(cf::launch_hcyl<T>(0, m, fields, dch, sl, w.n_all, g, lut_m, drinv, s));
-            STEP_OK(cf::launch_ecyl<T>(0, m, fields, dch, sl, w.n_all, g, lut_m, drinv, s));
+            STEP_OK(cf::launch_hcyl<T>(0, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, s));
+            STEP_OK(cf::launch_ecyl<T>(0, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, s));
             const double cu = (double)w.n_all * p.ncell;
             smp.end(take, s, cu, cu * state_bytes);
             STEP_OK(cf::launch_surface<T>(fields, dch, sl, w.n_all, tabs, k_m, k, dt, dA, dacc, dgam, (int)C, s));
@@ -632,7 +644,7 @@ template <typename T>
 cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, const Layout& L,
                     char* ws, hipStream_t s, std::vector<double>& acc_out, std::vector<double>& gamma_out,
                     double* device_ms, StencilTiming* timing) {
-    if (p.cyl) return run_cyl<T>(p, o, st, L, ws, s, acc_out, gamma_out, device_ms, timing);
+    if (p.reduced()) return run_cyl<T>(p, o, st, L, ws, s, acc_out, gamma_out, device_ms, timing);
     const size_t C = st.chans.size();
     // ---- upload tables --------------------------------------------------
     std::vector<uint8_t> ids((size_t)cf::kNumComp * p.ncell);
@@ -1077,7 +1089,7 @@ bool fill_result(const cf::Problem& p, const std::vector<cf::Channel>& chans, co
     if (out->per_channel)
         for (size_t c = 0; c < C; ++c) out->per_channel[c] = a[c];
     if (out->gamma && !gam.empty()) std::copy(gam.begin(), gam.end(), out->gamma);
-    if (out->trace && !gam.empty() && !p.cyl) {
+    if (out->trace && !gam.empty() && !p.reduced()) {
         std::vector<double> ktab(o.n_steps);
         const double dt = o.courant / p.grid.res;
         cf::kernel_table(o.kernel, o.sigma, dt, o.n_steps, ktab.data());
@@ -1093,7 +1105,7 @@ bool fill_result(const cf::Problem& p, const std::vector<cf::Channel>& chans, co
     out->n_channels_run = (int)C;
     out->n_steps_run = steps;
     out->cell_updates = (double)C * (double)p.ncell * (double)steps;
-    if (p.cyl) {
+    if (p.reduced()) {
         out->cell_updates = 0;
         for (size_t c = 0; c < C; ++c) out->cell_updates += (double)p.ncell * cf::order_steps(p, o, chans[c].order);
     }
@@ -1628,7 +1640,7 @@ cf_status cf_batch_workspace_size(cf_problem* const* probs, int n, const cf_opts
     for (int i = 0; i < n; ++i) {
         cf_status st = cf_validate(probs[i], o);
         if (st != CF_OK) return st;
-        if (probs[i]->p.grid.ndim == 2 && !probs[i]->p.cyl) fused.push_back(probs[i]);
+        if (probs[i]->p.grid.ndim == 2 && !probs[i]->p.reduced()) fused.push_back(probs[i]);
         size_t b = 0;
         cf_opts oo = *o;
         oo.n_subset = 0;
@@ -1661,7 +1673,7 @@ cf_status cf_batch_solve(cf_problem* const* probs, int n, const cf_opts* o, void
     std::vector<int> fused_idx;
     if (!(o->flags & CF_FLAG_SPLIT))
         for (int i = 0; i < n; ++i)
-            if (probs[i]->p.grid.ndim == 2 && !probs[i]->p.cyl) fused_idx.push_back(i);
+            if (probs[i]->p.grid.ndim == 2 && !probs[i]->p.reduced()) fused_idx.push_back(i);
     BatchPlan B;
     if (fused_idx.size() >= 1) {
         std::vector<cf_problem*> fp;

@@ -129,17 +129,19 @@ hipError_t launch_e2d(int pol, int mode, T* fields, const ChanDev* ch, const int
 // Cylindrical (r, z) half steps of azimuthal order m for the listed
 // channels (6-component blocks on a Grid2D with x = z, y = r); mode as for
 // the 2D launchers.
-// rinv: per row j the pair (1/j, 1/(j - 1/2)) in the field precision (row 0: zeros).
+// Reduced two-dimensional problems (cylindrical orders, k_z runs): coupling
+// = m or k dx of the run, axis = 1 when row 0 is the symmetry axis, rows =
+// 6 factors per row j in the field precision (see kernels_cyl.hip).
 template <typename T>
-hipError_t launch_hcyl(int mode, int m, T* fields, const ChanDev* ch, const int* slots, int nslots,
-                       const Grid2D& g, const T* lut, const T* rinv, hipStream_t s);
+hipError_t launch_hcyl(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
+                       int nslots, const Grid2D& g, const T* lut, const T* rows, hipStream_t s);
 template <typename T>
-hipError_t launch_ecyl(int mode, int m, T* fields, const ChanDev* ch, const int* slots, int nslots,
-                       const Grid2D& g, const T* lut, const T* rinv, hipStream_t s);
+hipError_t launch_ecyl(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
+                       int nslots, const Grid2D& g, const T* lut, const T* rows, hipStream_t s);
 
-// Per-order tables of a cylindrical solve: coefficient table of order m at
-// lut + m * lut_stride (field precision), K(t_k) at ktab + m * ktab_stride,
-// T_m steps of dt_m.
+// Per-order tables of a reduced solve (cylindrical orders m, or k_z points):
+// coefficient table of order q at lut + q * lut_stride (field precision),
+// K(t_k) at ktab + q * ktab_stride, T_q steps of dt_q.
 constexpr int kCylMaxOrders = 33;
 struct CylOrders {
     const void* lut;
@@ -151,7 +153,9 @@ struct CylOrders {
     // the six material ids of each cell in 4 bits each (component c at bit
     // 4 c; 15 stands for the wall id), or null when an id does not fit
     const uint32_t* idw;
-    const void* rinv;   // per row: (1/j, 1/(j - 1/2)), field precision
+    const void* rows;                 // 6 row factors per row (field precision)
+    double coup[kCylMaxOrders];       // coupling of each order: m, or k dx
+    int axis;                         // row 0 is the symmetry axis (cylindrical)
 };
 
 // Resident cylindrical solve: one block per listed channel clears its

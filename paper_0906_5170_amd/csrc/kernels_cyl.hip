@@ -54,32 +54,36 @@ inline dim3 grid_cyl(const Grid2D& g, int nslots) {
     return dim3(tiles, nslots, 1);
 }
 
-// Updated h_z, h_r, h_phi (hx, hy, hz) of a cell at row j from its own
-// fields, the neighbours e(j+1) (ezu, exu) and e(i+1) (ezr, eyr) and the
-// (a, b) pairs lx, ly, lz: MODE 0 h <- a h - b curl e, MODE 1 the consistent
-// start h^{-1/2} = (b / 2) curl e^0.  inv_r1 = 1/j and inv_r0 = 1/(j - 1/2)
-// come from the row table (correctly rounded in the field precision).
-// Every driver evaluates these forms, so their fields agree bitwise.
+// Row factors of the reduced update (6 per row j, field precision):
+//   cylindrical: (j + 1/2, j - 1/2, 1/j, 1/(j - 1/2), j, j - 1), row 0 unused
+//   (the axis rules apply there);  k_z: all 1.
+// With M the coupling of the run (m, or k dx), the curls in undivided form:
+//   h_x/h_z: ((A e_z(j+1) - B e_z) - M e_y) C       h_y/h_r: M e_x D - d_x e_z
+//   e_x/e_z: ((P h_z - Q h_z(j-1)) + M h_y) D       e_y/e_r: -M h_x C - d_x h_z
+//   h_z/h_phi and e_z/e_phi: the Cartesian two-dimensional forms.
+enum { RA = 0, RB, RC, RD, RP, RQ, kRowFactors };
+
+// Updated h components (hx, hy, hz) of a cell at row j from its own fields,
+// the neighbours e(j+1) (ezu, exu) and e(i+1) (ezr, eyr) and the (a, b)
+// pairs lx, ly, lz: MODE 0 h <- a h - b curl e, MODE 1 the consistent start
+// h^{-1/2} = (b / 2) curl e^0.  axis: row 0 is the symmetry axis
+// (cylindrical).  Every driver evaluates these forms, so their fields agree
+// bitwise.
 template <typename T, int MODE>
 __device__ __forceinline__ void h_values(T& hx, T& hy, T& hz, T ex, T ey, T ez, T ezu, T exu, T ezr, T eyr,
-                                         const T* lx, const T* ly, const T* lz, int m, int j, T inv_r1, T inv_r0) {
-    if (j == 0) {
+                                         const T* lx, const T* ly, const T* lz, T M, bool axis, int j,
+                                         const T* rw) {
+    if (axis && j == 0) {
         // axis: h_z from the disk circulation (m = 0), h_r outside, h_phi 0
         const T cz = T(4) * ezu;
-        if (MODE == 0) hx = m == 0 ? yee::sub(lx[0], hx, lx[1], cz) : T(0);
-        else hx = m == 0 ? yee::half(lx[1], cz) : T(0);
+        if (MODE == 0) hx = M == T(0) ? yee::sub(lx[0], hx, lx[1], cz) : T(0);
+        else hx = M == T(0) ? yee::half(lx[1], cz) : T(0);
         hy = T(0);
         hz = T(0);
         return;
     }
-    const T M = T(m);
-    const T r1 = T(j);                 // radius of h_z (cells)
-    const T r0 = T(j) - T(0.5);        // radius of h_r
-    // h_z: (1/r) d_r (r e_phi) - (m/r) e_r
-    const T cz = (((r1 + T(0.5)) * ezu - r0 * ez) - M * ey) * inv_r1;
-    // h_r: (m/r) e_z - d_z e_phi
-    const T cr = (M * ex) * inv_r0 - (ezr - ez);
-    // h_phi: d_z e_r - d_r e_z
+    const T cz = ((rw[RA] * ezu - rw[RB] * ez) - M * ey) * rw[RC];
+    const T cr = (M * ex) * rw[RD] - (ezr - ez);
     const T cp = (eyr - ey) - (exu - ex);
     if (MODE == 0) {
         hx = yee::sub(lx[0], hx, lx[1], cz);
@@ -92,26 +96,22 @@ __device__ __forceinline__ void h_values(T& hx, T& hy, T& hz, T ex, T ey, T ez, 
     }
 }
 
-// Updated e_z, e_r, e_phi (ex, ey, ez) of a cell at row j from its own
-// fields and the neighbours h(j-1) (hxd, hzd) and h(i-1) (hyl, hzl): MODE 0
+// Updated e components (ex, ey, ez) of a cell at row j from its own fields
+// and the neighbours h(j-1) (hxd, hzd) and h(i-1) (hyl, hzl): MODE 0
 // e <- a e + b curl h, MODE 1 the consistent start e^{+1/2} = (b / 2) curl h^0.
 template <typename T, int MODE>
 __device__ __forceinline__ void e_values(T& ex, T& ey, T& ez, T hx, T hy, T hz, T hxd, T hzd, T hyl, T hzl,
-                                         const T* lx, const T* ly, const T* lz, int m, int j, T inv_r1, T inv_r0) {
-    if (j == 0) {
+                                         const T* lx, const T* ly, const T* lz, T M, bool axis, int j,
+                                         const T* rw) {
+    if (axis && j == 0) {
         // e_z, e_phi outside / on the wall id, e_r on the axis: all 0
         ex = T(0);
         ey = T(0);
         ez = T(0);
         return;
     }
-    const T M = T(m);
-    const T r1 = T(j);                 // radius of e_r
-    // e_z: (1/r) d_r (r h_phi) + (m/r) h_r
-    const T cz = ((r1 * hz - (r1 - T(1)) * hzd) + M * hy) * inv_r0;
-    // e_r: -(m/r) h_z - d_z h_phi
-    const T cr = -((M * hx) * inv_r1) - (hz - hzl);
-    // e_phi: d_z h_r - d_r h_z
+    const T cz = ((rw[RP] * hz - rw[RQ] * hzd) + M * hy) * rw[RD];
+    const T cr = -((M * hx) * rw[RC]) - (hz - hzl);
     const T cp = (hy - hyl) - (hx - hxd);
     if (MODE == 0) {
         ex = yee::add(lx[0], ex, lx[1], cz);
@@ -124,10 +124,18 @@ __device__ __forceinline__ void e_values(T& ex, T& ey, T& ez, T hx, T hy, T hz, 
     }
 }
 
+// Reduced-update parameters of one run: coupling M, axis flag, row factors.
+template <typename T>
+struct RedRun {
+    T M;
+    bool axis;
+    const T* rows;
+};
+
 // H update of cell (i, j) of the channel block F in global memory.
 template <typename T, int MODE>
 __device__ __forceinline__ void hcyl_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
-                                          int m, int i, int j, const T* __restrict__ rinv) {
+                                          const RedRun<T>& rr, int i, int j) {
     const T* Ex = F;
     const T* Ey = F + g.ncell;
     const T* Ez = F + 2 * g.ncell;
@@ -136,14 +144,16 @@ __device__ __forceinline__ void hcyl_cell(T* __restrict__ F, const Grid2D& g, co
     T* Hz = F + 5 * g.ncell;
     const int64_t c = (int64_t)j * g.nx + i;
     const bool in_r = i + 1 < g.nx, in_u = j + 1 < g.ny;
-    const T ezu = in_u ? Ez[c + g.nx] : T(0);
-    const T exu = in_u ? Ex[c + g.nx] : T(0);
+    const int64_t cu = in_u ? c + g.nx : i;                     // row above (wrapped when periodic)
+    const bool has_u = in_u || g.pery;
+    const T ezu = has_u ? Ez[cu] : T(0);
+    const T exu = has_u ? Ex[cu] : T(0);
     const T ezr = in_r ? Ez[c + 1] : (g.perx ? Ez[c + 1 - g.nx] : T(0));
     const T eyr = in_r ? Ey[c + 1] : (g.perx ? Ey[c + 1 - g.nx] : T(0));
     T hx = Hx[c], hy = Hy[c], hz = Hz[c];
     h_values<T, MODE>(hx, hy, hz, Ex[c], Ey[c], Ez[c], ezu, exu, ezr, eyr,
                       lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]), lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]),
-                      lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]), m, j, rinv[2 * j], rinv[2 * j + 1]);
+                      lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]), rr.M, rr.axis, j, rr.rows + kRowFactors * j);
     Hx[c] = hx;
     Hy[c] = hy;
     Hz[c] = hz;
@@ -152,7 +162,7 @@ __device__ __forceinline__ void hcyl_cell(T* __restrict__ F, const Grid2D& g, co
 // E update of cell (i, j) of the channel block F in global memory.
 template <typename T, int MODE>
 __device__ __forceinline__ void ecyl_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
-                                          int m, int i, int j, const T* __restrict__ rinv) {
+                                          const RedRun<T>& rr, int i, int j) {
     T* Ex = F;
     T* Ey = F + g.ncell;
     T* Ez = F + 2 * g.ncell;
@@ -161,14 +171,16 @@ __device__ __forceinline__ void ecyl_cell(T* __restrict__ F, const Grid2D& g, co
     const T* Hz = F + 5 * g.ncell;
     const int64_t c = (int64_t)j * g.nx + i;
     const bool in_d = j > 0;
-    const T hxd = in_d ? Hx[c - g.nx] : T(0);
-    const T hzd = in_d ? Hz[c - g.nx] : T(0);
+    const int64_t cd = in_d ? c - g.nx : c + g.ncell - g.nx;    // row below (wrapped when periodic)
+    const bool has_d = in_d || g.pery;
+    const T hxd = has_d ? Hx[cd] : T(0);
+    const T hzd = has_d ? Hz[cd] : T(0);
     const T hyl = i > 0 ? Hy[c - 1] : (g.perx ? Hy[c - 1 + g.nx] : T(0));
     const T hzl = i > 0 ? Hz[c - 1] : (g.perx ? Hz[c - 1 + g.nx] : T(0));
     T ex = Ex[c], ey = Ey[c], ez = Ez[c];
     e_values<T, MODE>(ex, ey, ez, Hx[c], Hy[c], Hz[c], hxd, hzd, hyl, hzl,
                       lut_ab(lut, kind, CF_EX, g.ids[CF_EX][c]), lut_ab(lut, kind, CF_EY, g.ids[CF_EY][c]),
-                      lut_ab(lut, kind, CF_EZ, g.ids[CF_EZ][c]), m, j, rinv[2 * j], rinv[2 * j + 1]);
+                      lut_ab(lut, kind, CF_EZ, g.ids[CF_EZ][c]), rr.M, rr.axis, j, rr.rows + kRowFactors * j);
     Ex[c] = ex;
     Ey[c] = ey;
     Ez[c] = ez;
@@ -177,27 +189,27 @@ __device__ __forceinline__ void ecyl_cell(T* __restrict__ F, const Grid2D& g, co
 template <typename T, int MODE>
 __global__ __launch_bounds__(BX* BY) void k_hcyl(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                const int* __restrict__ slots, Grid2D g,
-                                               const T* __restrict__ lut, int m, const T* __restrict__ rinv) {
+                                               const T* __restrict__ lut, RedRun<T> rr) {
     const ChanDev d = ch[slots[blockIdx.y]];
     if (MODE == 1 && d.kind != 0) return;   // start: E-kind runs set H^{-1/2}
     const int tiles_x = (g.nx + BX - 1) / BX;
     const int i = (blockIdx.x % tiles_x) * BX + threadIdx.x;
     const int j = (blockIdx.x / tiles_x) * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
-    hcyl_cell<T, MODE>(fields + d.field_off, g, lut, d.kind, m, i, j, rinv);
+    hcyl_cell<T, MODE>(fields + d.field_off, g, lut, d.kind, rr, i, j);
 }
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(BX* BY) void k_ecyl(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                const int* __restrict__ slots, Grid2D g,
-                                               const T* __restrict__ lut, int m, const T* __restrict__ rinv) {
+                                               const T* __restrict__ lut, RedRun<T> rr) {
     const ChanDev d = ch[slots[blockIdx.y]];
     if (MODE == 1 && d.kind != 1) return;   // start: H-kind runs set E^{+1/2}
     const int tiles_x = (g.nx + BX - 1) / BX;
     const int i = (blockIdx.x % tiles_x) * BX + threadIdx.x;
     const int j = (blockIdx.x / tiles_x) * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
-    ecyl_cell<T, MODE>(fields + d.field_off, g, lut, d.kind, m, i, j, rinv);
+    ecyl_cell<T, MODE>(fields + d.field_off, g, lut, d.kind, rr, i, j);
 }
 
 // Every cell of the grid once, block-strided: thread t takes flat cells
@@ -228,8 +240,8 @@ constexpr int batch_of() {
 }
 
 template <typename T, int MODE, int NTH = kResThreads>
-__device__ __forceinline__ void h_phase(T* __restrict__ F, const Grid2D& g, const T* __restrict__ Lc, int m,
-                                        const T* __restrict__ R) {
+__device__ __forceinline__ void h_phase(T* __restrict__ F, const Grid2D& g, const T* __restrict__ Lc,
+                                        const RedRun<T>& rr) {
     constexpr int kBatch = batch_of<T>();
     const T* Ex = F;
     const T* Ey = F + g.ncell;
@@ -252,8 +264,10 @@ __device__ __forceinline__ void h_phase(T* __restrict__ F, const Grid2D& g, cons
             if (j < ny) {
                 const int c = cc[q];
                 const bool in_r = i + 1 < nx, in_u = j + 1 < ny;
-                ezu[q] = in_u ? Ez[c + nx] : T(0);
-                exu[q] = in_u ? Ex[c + nx] : T(0);
+                const int cu = in_u ? c + nx : i;
+                const bool has_u = in_u || g.pery;
+                ezu[q] = has_u ? Ez[cu] : T(0);
+                exu[q] = has_u ? Ex[cu] : T(0);
                 ezr[q] = in_r ? Ez[c + 1] : (g.perx ? Ez[c + 1 - nx] : T(0));
                 eyr[q] = in_r ? Ey[c + 1] : (g.perx ? Ey[c + 1 - nx] : T(0));
                 ex[q] = Ex[c];
@@ -279,8 +293,8 @@ __device__ __forceinline__ void h_phase(T* __restrict__ F, const Grid2D& g, cons
                 h_values<T, MODE>(hx[q], hy[q], hz[q], ex[q], ey[q], ez[q], ezu[q], exu[q], ezr[q], eyr[q],
                                   Lc + ((CF_HX << 8) + (int)(id[q] & 255)) * 2,
                                   Lc + ((CF_HY << 8) + (int)((id[q] >> 8) & 255)) * 2,
-                                  Lc + ((CF_HZ << 8) + (int)(id[q] >> 16)) * 2, m, jj[q], R[2 * jj[q]],
-                                  R[2 * jj[q] + 1]);
+                                  Lc + ((CF_HZ << 8) + (int)(id[q] >> 16)) * 2, rr.M, rr.axis, jj[q],
+                                  rr.rows + kRowFactors * jj[q]);
                 Hx[c] = hx[q];
                 Hy[c] = hy[q];
                 Hz[c] = hz[q];
@@ -290,8 +304,8 @@ __device__ __forceinline__ void h_phase(T* __restrict__ F, const Grid2D& g, cons
 }
 
 template <typename T, int MODE, int NTH = kResThreads>
-__device__ __forceinline__ void e_phase(T* __restrict__ F, const Grid2D& g, const T* __restrict__ Lc, int m,
-                                        const T* __restrict__ R) {
+__device__ __forceinline__ void e_phase(T* __restrict__ F, const Grid2D& g, const T* __restrict__ Lc,
+                                        const RedRun<T>& rr) {
     constexpr int kBatch = batch_of<T>();
     T* Ex = F;
     T* Ey = F + g.ncell;
@@ -314,8 +328,10 @@ __device__ __forceinline__ void e_phase(T* __restrict__ F, const Grid2D& g, cons
             if (j < ny) {
                 const int c = cc[q];
                 const bool in_d = j > 0;
-                hxd[q] = in_d ? Hx[c - nx] : T(0);
-                hzd[q] = in_d ? Hz[c - nx] : T(0);
+                const int cd = in_d ? c - nx : c + (int)g.ncell - nx;
+                const bool has_d = in_d || g.pery;
+                hxd[q] = has_d ? Hx[cd] : T(0);
+                hzd[q] = has_d ? Hz[cd] : T(0);
                 hyl[q] = i > 0 ? Hy[c - 1] : (g.perx ? Hy[c - 1 + nx] : T(0));
                 hzl[q] = i > 0 ? Hz[c - 1] : (g.perx ? Hz[c - 1 + nx] : T(0));
                 hx[q] = Hx[c];
@@ -341,8 +357,8 @@ __device__ __forceinline__ void e_phase(T* __restrict__ F, const Grid2D& g, cons
                 e_values<T, MODE>(ex[q], ey[q], ez[q], hx[q], hy[q], hz[q], hxd[q], hzd[q], hyl[q], hzl[q],
                                   Lc + ((CF_EX << 8) + (int)(id[q] & 255)) * 2,
                                   Lc + ((CF_EY << 8) + (int)((id[q] >> 8) & 255)) * 2,
-                                  Lc + ((CF_EZ << 8) + (int)(id[q] >> 16)) * 2, m, jj[q], R[2 * jj[q]],
-                                  R[2 * jj[q] + 1]);
+                                  Lc + ((CF_EZ << 8) + (int)(id[q] >> 16)) * 2, rr.M, rr.axis, jj[q],
+                                  rr.rows + kRowFactors * jj[q]);
                 Ex[c] = ex[q];
                 Ey[c] = ey[q];
                 Ez[c] = ez[q];
@@ -379,9 +395,9 @@ __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fi
         fields[d.src_off + t.uidx[d.u_off + u]] = T(d.kick_scale * s);
     }
     __syncthreads();
-    const T* R = static_cast<const T*>(ord.rinv);
-    if (d.kind == 0) h_phase<T, 1>(F, g, Lc, m, R);
-    else e_phase<T, 1>(F, g, Lc, m, R);
+    const RedRun<T> rr{T(ord.coup[m]), ord.axis != 0, static_cast<const T*>(ord.rows)};
+    if (d.kind == 0) h_phase<T, 1>(F, g, Lc, rr);
+    else e_phase<T, 1>(F, g, Lc, rr);
     __syncthreads();
     const T* X = fields + d.meas_off;
     double sum = 0.0, comp = 0.0;
@@ -390,9 +406,9 @@ __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fi
         comp = acc[2 * slot + 1];
     }
     for (int step = 0; step < nsteps; ++step) {
-        h_phase<T, 0>(F, g, Lc, m, R);
+        h_phase<T, 0>(F, g, Lc, rr);
         __syncthreads();
-        e_phase<T, 0>(F, g, Lc, m, R);
+        e_phase<T, 0>(F, g, Lc, rr);
         __syncthreads();
         // every read of X ends at the barrier inside; the next writes of the
         // fields come after it
@@ -436,8 +452,8 @@ __global__ __launch_bounds__(NTH) void k_cyl_regs(T* __restrict__ fields, const 
     T* X = reinterpret_cast<T*>(lds_dyn);          // 3 n exchange values
     T* Lg = X;                                      // the kind's full table, for the start (before X is used)
     T* Lc = X + regs_x_len(n);                      // 6 x 16 (a, b) pairs
-    T* R = Lc + 6 * 16 * 2;                         // 1/r per row: (1/j, 1/(j - 1/2))
-    uint32_t* W = reinterpret_cast<uint32_t*>(R + 2 * g.ny);   // packed ids per cell
+    T* R = Lc + 6 * 16 * 2;                         // row factors (kRowFactors per row)
+    uint32_t* W = reinterpret_cast<uint32_t*>(R + kRowFactors * g.ny);   // packed ids per cell
     const int slot = slots[blockIdx.x];
     const ChanDev d = ch[slot];
     const int m = d.order;
@@ -453,7 +469,7 @@ __global__ __launch_bounds__(NTH) void k_cyl_regs(T* __restrict__ fields, const 
         Lc[k] = lk[((cmp << 8) + (q == 15 ? 255 : q)) * 2 + (k & 1)];
     }
     for (int k = threadIdx.x; k < n; k += NTH) W[k] = ord.idw[k];
-    for (int k = threadIdx.x; k < 2 * g.ny; k += NTH) R[k] = static_cast<const T*>(ord.rinv)[k];
+    for (int k = threadIdx.x; k < kRowFactors * g.ny; k += NTH) R[k] = static_cast<const T*>(ord.rows)[k];
     for (int64_t k = threadIdx.x; k < 6 * g.ncell; k += NTH) F[k] = T(0);
     __syncthreads();
     // (the exchange array takes over Lg's space after the start)
@@ -464,8 +480,9 @@ __global__ __launch_bounds__(NTH) void k_cyl_regs(T* __restrict__ fields, const 
         fields[d.src_off + t.uidx[d.u_off + u]] = T(d.kick_scale * s);
     }
     __syncthreads();
-    if (d.kind == 0) h_phase<T, 1, NTH>(F, g, Lg, m, R);
-    else e_phase<T, 1, NTH>(F, g, Lg, m, R);
+    const RedRun<T> rr{T(ord.coup[m]), ord.axis != 0, R};
+    if (d.kind == 0) h_phase<T, 1, NTH>(F, g, Lg, rr);
+    else e_phase<T, 1, NTH>(F, g, Lg, rr);
     __syncthreads();
     T e0[K], e1[K], e2[K], h0[K], h1[K], h2[K];
 #pragma unroll
@@ -515,12 +532,14 @@ __global__ __launch_bounds__(NTH) void k_cyl_regs(T* __restrict__ fields, const 
                     const int c = j * nx + i;
                     const bool in_r = i + 1 < nx, in_u = j + 1 < ny;
                     const uint32_t w = W[c];
-                    const T ezu = in_u ? X[2 * n + c + nx] : T(0);
-                    const T exu = in_u ? X[c + nx] : T(0);
+                    const int cu = in_u ? c + nx : i;
+                    const bool has_u = in_u || g.pery;
+                    const T ezu = has_u ? X[2 * n + cu] : T(0);
+                    const T exu = has_u ? X[cu] : T(0);
                     const T ezr = in_r ? X[2 * n + c + 1] : (g.perx ? X[2 * n + c + 1 - nx] : T(0));
                     const T eyr = in_r ? X[n + c + 1] : (g.perx ? X[n + c + 1 - nx] : T(0));
                     h_values<T, 0>(h0[k], h1[k], h2[k], e0[k], e1[k], e2[k], ezu, exu, ezr, eyr, pair(CF_HX, w),
-                                   pair(CF_HY, w), pair(CF_HZ, w), m, j, R[2 * j], R[2 * j + 1]);
+                                   pair(CF_HY, w), pair(CF_HZ, w), rr.M, rr.axis, j, R + kRowFactors * j);
                 }
                 i += di;
                 j += dj;
@@ -551,12 +570,14 @@ __global__ __launch_bounds__(NTH) void k_cyl_regs(T* __restrict__ fields, const 
                     const int c = j * nx + i;
                     const bool in_d = j > 0;
                     const uint32_t w = W[c];
-                    const T hxd = in_d ? X[c - nx] : T(0);
-                    const T hzd = in_d ? X[2 * n + c - nx] : T(0);
+                    const int cd = in_d ? c - nx : c + n - nx;
+                    const bool has_d = in_d || g.pery;
+                    const T hxd = has_d ? X[cd] : T(0);
+                    const T hzd = has_d ? X[2 * n + cd] : T(0);
                     const T hyl = i > 0 ? X[n + c - 1] : (g.perx ? X[n + c - 1 + nx] : T(0));
                     const T hzl = i > 0 ? X[2 * n + c - 1] : (g.perx ? X[2 * n + c - 1 + nx] : T(0));
                     e_values<T, 0>(e0[k], e1[k], e2[k], h0[k], h1[k], h2[k], hxd, hzd, hyl, hzl, pair(CF_EX, w),
-                                   pair(CF_EY, w), pair(CF_EZ, w), m, j, R[2 * j], R[2 * j + 1]);
+                                   pair(CF_EY, w), pair(CF_EZ, w), rr.M, rr.axis, j, R + kRowFactors * j);
                 }
                 i += di;
                 j += dj;
@@ -587,7 +608,8 @@ __global__ __launch_bounds__(NTH) void k_cyl_regs(T* __restrict__ fields, const 
 
 template <typename T>
 size_t regs_lds_bytes(const Grid2D& g) {
-    return ((size_t)regs_x_len((int)g.ncell) + 6 * 16 * 2 + 2 * (size_t)g.ny) * sizeof(T) + 4 * (size_t)g.ncell;
+    return ((size_t)regs_x_len((int)g.ncell) + 6 * 16 * 2 + kRowFactors * (size_t)g.ny) * sizeof(T) +
+           4 * (size_t)g.ncell;
 }
 
 
@@ -643,22 +665,24 @@ hipError_t regs_try(int64_t ncell, size_t lds, bool* launched, T* fields, const 
 }  // namespace
 
 template <typename T>
-hipError_t launch_hcyl(int mode, int m, T* fields, const ChanDev* ch, const int* slots, int nslots,
-                       const Grid2D& g, const T* lut, const T* rinv, hipStream_t s) {
+hipError_t launch_hcyl(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
+                       int nslots, const Grid2D& g, const T* lut, const T* rows, hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
     const dim3 grid = grid_cyl(g, nslots), block(BX, BY, 1);
-    if (mode == 0) hipLaunchKernelGGL((k_hcyl<T, 0>), grid, block, 0, s, fields, ch, slots, g, lut, m, rinv);
-    else hipLaunchKernelGGL((k_hcyl<T, 1>), grid, block, 0, s, fields, ch, slots, g, lut, m, rinv);
+    const RedRun<T> rr{T(coupling), axis != 0, rows};
+    if (mode == 0) hipLaunchKernelGGL((k_hcyl<T, 0>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+    else hipLaunchKernelGGL((k_hcyl<T, 1>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_ecyl(int mode, int m, T* fields, const ChanDev* ch, const int* slots, int nslots,
-                       const Grid2D& g, const T* lut, const T* rinv, hipStream_t s) {
+hipError_t launch_ecyl(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
+                       int nslots, const Grid2D& g, const T* lut, const T* rows, hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
     const dim3 grid = grid_cyl(g, nslots), block(BX, BY, 1);
-    if (mode == 0) hipLaunchKernelGGL((k_ecyl<T, 0>), grid, block, 0, s, fields, ch, slots, g, lut, m, rinv);
-    else hipLaunchKernelGGL((k_ecyl<T, 1>), grid, block, 0, s, fields, ch, slots, g, lut, m, rinv);
+    const RedRun<T> rr{T(coupling), axis != 0, rows};
+    if (mode == 0) hipLaunchKernelGGL((k_ecyl<T, 0>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+    else hipLaunchKernelGGL((k_ecyl<T, 1>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
     return hipGetLastError();
 }
 
@@ -697,10 +721,10 @@ hipError_t launch_cyl_resident(int variant, T* fields, const ChanDev* ch, const 
 }
 
 #define CF_CYL_INSTANTIATE(T)                                                                                   \
-    template hipError_t launch_hcyl<T>(int, int, T*, const ChanDev*, const int*, int, const Grid2D&, const T*, \
-                                       const T*, hipStream_t);                                                 \
-    template hipError_t launch_ecyl<T>(int, int, T*, const ChanDev*, const int*, int, const Grid2D&, const T*, \
-                                       const T*, hipStream_t);                                                 \
+    template hipError_t launch_hcyl<T>(int, double, int, T*, const ChanDev*, const int*, int, const Grid2D&,  \
+                                       const T*, const T*, hipStream_t);                                       \
+    template hipError_t launch_ecyl<T>(int, double, int, T*, const ChanDev*, const int*, int, const Grid2D&,  \
+                                       const T*, const T*, hipStream_t);                                       \
     template hipError_t launch_cyl_resident<T>(int, T*, const ChanDev*, const int*, int, const Grid2D&,       \
                                                const CylOrders&, const SurfTables&, double, double*, double*, \
                                                int, hipStream_t, int*);

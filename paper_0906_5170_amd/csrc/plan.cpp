@@ -41,7 +41,7 @@ int comp_slot(int pol, int comp) {
 
 int n_comp_for(int ndim) { return ndim == 2 ? 3 : 6; }
 
-int n_comp(const Problem& p) { return p.cyl ? 6 : n_comp_for(p.grid.ndim); }
+int n_comp(const Problem& p) { return p.reduced() ? 6 : n_comp_for(p.grid.ndim); }
 
 double order_courant(const Problem& p, double courant, int m) {
     return p.cyl && m >= 2 ? std::min(courant, 1.0 / (1.0 + m)) : courant;
@@ -67,7 +67,7 @@ int harmonic_len(const Problem& p) {
     int lab = 0;
     for (auto& v : p.labels)
         for (int l : v) lab = std::max(lab, l + 1);
-    if (p.cyl) lab += p.m_max * p.surf.n_harm;
+    if (p.reduced()) lab += (p.n_orders() - 1) * p.surf.n_harm;
     return lab;
 }
 
@@ -373,7 +373,15 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
         if (g.bc[a] == CF_BC_PML && (g.pml_cells[a] < 1 || 2 * g.pml_cells[a] >= g.n[a]))
             return "PML thickness out of range";
     }
-    if (g.coord != CF_COORD_CARTESIAN && g.coord != CF_COORD_CYLINDRICAL) return "unknown coordinate system";
+    if (g.coord != CF_COORD_CARTESIAN && g.coord != CF_COORD_CYLINDRICAL && g.coord != CF_COORD_KZ)
+        return "unknown coordinate system";
+    if (g.coord == CF_COORD_KZ) {
+        if (g.ndim != 2) return "k_z problems are 2D grids";
+        if (g.bc[0] == CF_BC_PML || g.bc[1] == CF_BC_PML) return "PML is implemented for 3D grids";
+        if (s.n_kz < 1 || s.n_kz > 33 || !s.kz || !s.kz_weight) return "k_z problems need 1..33 wavevectors";
+        for (int q = 0; q < s.n_kz; ++q)
+            if (!std::isfinite(s.kz[q]) || !std::isfinite(s.kz_weight[q])) return "k_z points must be finite";
+    }
     if (g.coord == CF_COORD_CYLINDRICAL) {
         if (g.ndim != 2) return "cylindrical problems are 2D (r, z) grids";
         if (g.bc[1] != CF_BC_PEC) return "cylindrical problems need a PEC tube wall (bc[1])";
@@ -383,7 +391,14 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
     if (m.n_materials < 1 || m.n_materials > 254 || !m.eps || !m.mu) return "bad material table";
     p.grid = g;
     p.cyl = g.coord == CF_COORD_CYLINDRICAL;
+    p.kz = g.coord == CF_COORD_KZ;
     p.m_max = p.cyl ? s.m_max : 0;
+    p.kzs.clear();
+    p.kz_w.clear();
+    if (p.kz) {
+        p.kzs.assign(s.kz, s.kz + s.n_kz);
+        p.kz_w.assign(s.kz_weight, s.kz_weight + s.n_kz);
+    }
     if (g.ndim == 2) {
         p.grid.bc[2] = CF_BC_PERIODIC;
         p.grid.pml_cells[2] = 0;
@@ -424,6 +439,8 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
         }
     // stress surface
     p.surf = s;
+    p.surf.kz = nullptr;          // copied into kzs / kz_w above
+    p.surf.kz_weight = nullptr;
     if (s.force_axis < 0 || s.force_axis >= g.ndim) return "force_axis out of range";
     if (s.n_harm < 1) return "n_harm must be >= 1";
     p.faces.clear();
@@ -565,11 +582,11 @@ std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
     if (o.precision != CF_FP64 && o.precision != CF_FP32) return "unknown precision";
     if (o.path != CF_PATH_BATCHED && o.path != CF_PATH_PLAIN) return "unknown path";
     if (o.kernel != CF_KERNEL_GENERAL && o.kernel != CF_KERNEL_ZINV2D) return "unknown kernel";
-    if (p.cyl) {
-        if (o.pol != CF_POL_3D) return "cylindrical runs take CF_POL_3D (all six components)";
+    if (p.reduced()) {
+        if (o.pol != CF_POL_3D) return "cylindrical and k_z runs take CF_POL_3D (all six components)";
         if (o.stop_tol > 0) {
             *code = CF_E_UNSUPPORTED;
-            return "the convergence stop is not available for cylindrical problems";
+            return "the convergence stop is not available for cylindrical and k_z problems";
         }
     } else if (p.grid.ndim == 2) {
         if (o.pol < 1 || o.pol > 3) return "2D runs take CF_POL_TM and/or CF_POL_TE";
@@ -609,6 +626,14 @@ std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
         *code = CF_E_CFL;
         return "cylindrical runs need courant * max speed <= 0.5";
     }
+    if (p.kz) {
+        double kmax = 0;
+        for (double k : p.kzs) kmax = std::max(kmax, std::abs(k) / p.grid.res);
+        if (o.courant * vmax * std::sqrt(8.0 + kmax * kmax) / 2.0 >= 1.0) {
+            *code = CF_E_CFL;
+            return "courant number above the stability limit of the largest k_z";
+        }
+    }
     *code = CF_OK;
     return "";
 }
@@ -621,7 +646,7 @@ std::vector<Channel> channel_table(const Problem& p, int pol_mask) {
     std::vector<Channel> out;
     const int d = p.surf.force_axis;
     std::vector<int> pols;
-    if (p.grid.ndim == 3 || p.cyl) {
+    if (p.grid.ndim == 3 || p.reduced()) {
         pols = {CF_POL_3D};
     } else {
         if (pol_mask & CF_POL_TM) pols.push_back(CF_POL_TM);
@@ -660,17 +685,18 @@ std::vector<Channel> channel_table(const Problem& p, int pol_mask) {
                 }
         }
     }
-    if (p.cyl) {
-        // order-major: the channel set once per azimuthal order m, with the
-        // order weight w_m (1 for m = 0, 2 above: the -m term is the
-        // conjugate of the +m term) in the sign
+    if (p.reduced()) {
+        // order-major: the channel set once per order (azimuthal order m,
+        // weight 1 for m = 0 and 2 above: the -m term is the conjugate of
+        // the +m term; or k_z point q with its quadrature weight) with the
+        // weight in the sign
         const std::vector<Channel> base = std::move(out);
         out.clear();
-        for (int m = 0; m <= p.m_max; ++m)
+        for (int q = 0; q < p.n_orders(); ++q)
             for (Channel ch : base) {
-                ch.order = m;
-                ch.label += m * p.surf.n_harm;
-                ch.sign *= m == 0 ? 1.0 : 2.0;
+                ch.order = q;
+                ch.label += q * p.surf.n_harm;
+                ch.sign *= p.order_weight(q);
                 out.push_back(ch);
             }
     }

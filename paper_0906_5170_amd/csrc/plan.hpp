@@ -79,7 +79,16 @@ struct Problem {
     std::vector<Gather> gathers;
     double eps_s = 0, mu_s = 0;
     bool cyl = false;                         // cylindrical (r, z) problem
+    bool kz = false;                          // z-invariant problem at Bloch wavevectors k_z
     int m_max = 0;
+    std::vector<double> kzs, kz_w;            // k_z points and weights
+    // reduced two-dimensional problems: six components, one run per order
+    // (azimuthal order m, or k_z point q)
+    bool reduced() const { return cyl || kz; }
+    int n_orders() const { return cyl ? m_max + 1 : kz ? (int)kzs.size() : 1; }
+    double order_weight(int q) const { return cyl ? (q == 0 ? 1.0 : 2.0) : kz ? kz_w[q] : 1.0; }
+    // coupling of order q in the undivided curls: m, or k dx
+    double coupling(int q) const { return cyl ? (double)q : kz ? kzs[q] / grid.res : 0.0; }
 };
 
 // Key of a (face, component) gather: cylindrical problems keep a second

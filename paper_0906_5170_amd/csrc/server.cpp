@@ -745,7 +745,8 @@ cf_status cf_server_submit(cf_server* S, cf_problem* prob, const cf_opts* o, uin
     if (o->precision != S->precision) return fail(CF_E_ARG, "request precision differs from the server's");
     if (o->path != CF_PATH_BATCHED) return fail(CF_E_ARG, "served requests use the batched path");
     if (o->n_subset > 0) return fail(CF_E_ARG, "served requests run every channel");
-    if (prob->p.cyl) return fail(CF_E_UNSUPPORTED, "cylindrical problems are solved with cf_solve, not served");
+    if (prob->p.reduced())
+        return fail(CF_E_UNSUPPORTED, "cylindrical and k_z problems are solved with cf_solve, not served");
     cf_status st = cf_validate(prob, o);
     if (st != CF_OK) return st;
     auto r = std::make_shared<Req>();

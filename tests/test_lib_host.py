@@ -8,7 +8,8 @@
 * validation rejects CFL violations, surfaces outside a uniform medium and
   unsupported option combinations with the documented status codes;
 * cylindrical problems: the order-major channel table and the per-order
-  step counts follow the oracle's.
+  step counts follow the oracle's; k_z problems likewise, with the
+  quadrature weights in the signs.
 """
 import os
 import re
@@ -17,7 +18,7 @@ import numpy as np
 import pytest
 
 from casimir_inputs import c1_piston_tm_fp64, c2_piston_tetm_fp32, c4_sphere_plate, parallel_plates_1d
-from casimir_inputs import c_cyl_piston, cyl_piston
+from casimir_inputs import c_cyl_piston, cyl_piston, dielectric_piston2d, kz_workload
 from casimir_inputs.configs import piston2d
 from oracle.cyl import cylindrical_courant
 from oracle.cylforce import setup as cyl_setup
@@ -165,3 +166,49 @@ def test_cylindrical_validation(cf):
         with pytest.raises(cf.CfError) as e:
             cf.Problem.from_workload(bad)
         assert e.value.status == status, bad.bc
+
+
+# ---- z-invariant problems at Bloch wavevectors k_z ---------------------------
+
+def test_kz_channel_table_matches_oracle(cf):
+    """Channel order q-major, label q * n_harm + n, sign times the weight."""
+    base = dielectric_piston2d(40, 31, 4, 10, 5, 10, 13, 10.0, n_steps=400, n_harm=6)
+    ks, ws = [0.0, 0.8, 2.5], [0.3, 0.5, 0.25]
+    wl = kz_workload(base, ks, ws)
+    p = cf.Problem.from_workload(wl)
+    tab = p.channel_table(pol="3D", kernel="general")
+    faces, bases, eps_s, mu_s, chans = oracle_setup(wl)
+    n0 = len(chans)
+    assert len(tab["face"]) == n0 * len(ks)
+    for q in range(len(ks)):
+        for c, ch in enumerate(chans):
+            k = q * n0 + c
+            assert tab["face"][k] == faces[ch.face].index
+            assert tab["label"][k] == q * wl.n_harm + ch.label
+            assert tab["kind"][k] == (0 if ch.kind == "E" else 1)
+            assert tab["src"][k] == COMP_ID[ch.src] and tab["meas"][k] == COMP_ID[ch.meas]
+            assert tab["sign"][k] == pytest.approx(ws[q] * ch.sign, rel=1e-15)
+    info = p.info(pol="3D", kernel="general", n_steps=400)
+    assert info["n_comp"] == 6 and info["per_harmonic_len"] == len(ks) * wl.n_harm
+    assert info["n_steps_max"] == 400
+
+
+def test_kz_validation(cf):
+    base = dielectric_piston2d(40, 31, 4, 10, 5, 10, 13, 10.0, n_steps=400, n_harm=6)
+    wl = kz_workload(base, [0.0, 5.0], [1.0, 1.0])
+    p = cf.Problem.from_workload(wl)
+    p.validate(pol="3D", courant=0.5)
+    for opts, status in [(dict(pol="TM"), "CF_E_ARG"), (dict(pol="3D", stop_tol=1e-6), "CF_E_UNSUPPORTED")]:
+        with pytest.raises(cf.CfError) as e:
+            p.validate(**opts)
+        assert e.value.status == status, opts
+    # k dx = 3: stability limit 2 / sqrt(8 + 9) = 0.485 < 0.5
+    hot = cf.Problem.from_workload(kz_workload(base, [30.0], [1.0]))
+    with pytest.raises(cf.CfError) as e:
+        hot.validate(pol="3D", courant=0.5)
+    assert e.value.status == "CF_E_CFL"
+    hot.validate(pol="3D", courant=0.48)
+    for bad in (wl.replace(kz=(), kz_weight=()), wl.replace(kz=tuple(range(40)), kz_weight=(1.0,) * 40)):
+        with pytest.raises(cf.CfError) as e:
+            cf.Problem.from_workload(bad)
+        assert e.value.status == "CF_E_ARG"
