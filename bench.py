@@ -172,6 +172,45 @@ def bench_cyl(cf, torch, cpu_sample=True, quick=False):
     return out
 
 
+def bench_kz(cf, torch, cpu_sample=True):
+    """z-invariant dielectric piston (eps = 4 blocks between PEC slabs; the
+    C1 geometry: res 20, 80 x 40, 16 harmonics, T = 2000) integrated over
+    k_z with 8-point Gauss-Legendre on [0, 12] (Sec. III C: dielectrics
+    hybridize the polarizations): 8 six-component runs in one launch, FP32."""
+    from casimir_inputs import dielectric_piston2d, kz_gauss, kz_workload
+    base = dielectric_piston2d(80, 40, 10, 20, 10, 20, 15, 20.0, n_steps=2000, n_harm=16, precision="fp32")
+    ks, ws = kz_gauss(8, 12.0)
+    wl = kz_workload(base, ks, ws)
+    p = cf.Problem.from_workload(wl)
+    o = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol="3D", kernel="general", precision="fp32")
+    p.solve(**dict(o, n_steps=100))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r = p.solve(time_stencil=True, **o)
+    wall = time.perf_counter() - t1
+    rate = r["cell_updates"] / (r["device_ms"] * 1e-3)
+    rs = p.solve(split=True, **o)
+    out = {"workload": f"dielectric piston (eps 4) res 20, 80 x 40, 16 harmonics, k_z 8-point Gauss on [0, 12], "
+                       f"{r['n_channels']} channels, T 2000, FP32",
+           "force_per_length": r["force"], "wall_s": wall, "device_ms": r["device_ms"], "value": rate,
+           "unit": "cell-updates/s", "resident_variant": r["tile_variant"],
+           "split_path_device_ms": rs["device_ms"], "speedup_vs_split": rs["device_ms"] / r["device_ms"]}
+    if cpu_sample:
+        from oracle import kz
+        from oracle.force import setup
+        _, _, _, _, chans = setup(wl)
+        n_s = 200
+        t1 = time.perf_counter()
+        kz.solve(wl.replace(n_steps=n_s), [ks[3]], [1.0])
+        dt = time.perf_counter() - t1
+        per = dt / (len(chans) * n_s)
+        out["cpu_oracle"] = {"projected_s": per * len(chans) * len(ks) * wl.n_steps, "cores": 1,
+                             "sample": f"one k_z, all {len(chans)} channels x {n_s} steps, {dt:.1f} s, FP64 NumPy"}
+    log(f"[bench] kz: {wall:.3f} s wall ({r['device_ms']:.1f} ms device), {rate:.3e} cell-updates/s, "
+        f"split {rs['device_ms']:.1f} ms")
+    return out
+
+
 def _serve(cf, srv_budget, reqs, probs, opts_list, lam_times=True):
     """Submit requests at their arrival times (or all at once) and wait for
     all; returns per-request (kind, submit, admit, done, cell-updates)."""
@@ -428,7 +467,10 @@ def main():
         log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
         del a, b
     if args.cyl_only:
-        print(json.dumps(bench_cyl(cf, torch, cpu_sample=False, quick=args.cyl_quick)), flush=True)
+        rec = bench_cyl(cf, torch, cpu_sample=False, quick=args.cyl_quick)
+        if not args.cyl_quick:
+            rec["kz"] = bench_kz(cf, torch, cpu_sample=False)
+        print(json.dumps(rec), flush=True)
         return
     prob = cf.Problem.from_workload(wl)
     opts = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol=wl.pol,
@@ -534,6 +576,7 @@ def main():
         out["serving"] = bench_serving(cf, torch, args, rate_3d)
     if not args.no_cyl:
         out["cylindrical"] = bench_cyl(cf, torch, cpu_sample=not args.no_cpu)
+        out["kz"] = bench_kz(cf, torch, cpu_sample=not args.no_cpu)
 
     gold = os.path.join(ROOT, "tests", "golden", "c2_piston_tetm_oracle.json")
     if os.path.exists(gold) and not args.n_steps:

@@ -33,6 +33,7 @@ from .configs import (
     c_cyl_piston,
     dielectric_piston2d,
     kz_workload,
+    kz_gauss,
     small_cases,
 )
 
@@ -56,5 +57,6 @@ __all__ = [
     "c_cyl_piston",
     "dielectric_piston2d",
     "kz_workload",
+    "kz_gauss",
     "small_cases",
 ]

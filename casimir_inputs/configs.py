@@ -259,6 +259,13 @@ def c_cyl_piston(**over) -> Workload:
     return cyl_piston(**kw)
 
 
+def kz_gauss(n: int, k_max: float):
+    """Nodes and weights of (1/pi) int_0^k_max dk with n-point Gauss-Legendre
+    (the weights include the 1/pi of the force per unit length)."""
+    t, w = np.polynomial.legendre.leggauss(int(n))
+    return 0.5 * k_max * (t + 1.0), 0.5 * k_max * w / np.pi
+
+
 def kz_workload(wl: Workload, kz, kz_weight) -> Workload:
     """The z-invariant 2D workload wl solved at Bloch wavevectors kz along
     z (six components, general kernel); the force is sum_q kz_weight[q] F(kz[q])."""

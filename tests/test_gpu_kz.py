@@ -17,7 +17,7 @@ FP32 fields with FP64 accumulation 2e-5.
 import numpy as np
 import pytest
 
-from casimir_inputs import dielectric_piston2d, kz_workload, parallel_plates_1d
+from casimir_inputs import dielectric_piston2d, kz_gauss, kz_workload, parallel_plates_1d
 from oracle import kz
 
 pytestmark = pytest.mark.gpu
@@ -105,3 +105,17 @@ def test_drivers_bitwise(cf, precision):
             np.testing.assert_array_equal(split["gamma"], res["gamma"])
         plain = run(cf, wl, precision=precision, path="plain")
         np.testing.assert_array_equal(plain["per_channel"], split["per_channel"])
+
+
+def test_k_integral_equals_z_invariant_kernel_on_gpu(cf):
+    """Appendix A.2 on the GPU path: the 8-point Gauss k_z integral of the
+    plates (FP64 fields) equals the TM + TE force with the z-invariant kernel
+    (the fused 2D kernel) to 5e-4, as the oracle pin states."""
+    announce("k_z integral vs z-invariant kernel, plates, GPU")
+    base = parallel_plates_1d(20, 0.5, 0.25, 1.0, n_steps=1600, precision="fp64")
+    ks, ws = kz_gauss(8, 12.0)
+    f_kz = run(cf, kz_workload(base, ks, ws))["force"]
+    f_2d = cf.Problem.from_workload(base).solve(sigma=base.sigma, courant=base.courant, n_steps=base.n_steps,
+                                                 pol="TM+TE", kernel="zinv2d", precision="fp64")["force"]
+    print(f"[kz] k integral {f_kz:.8f}, z-invariant kernel {f_2d:.8f}", flush=True)
+    assert abs(f_kz / f_2d - 1) < 5e-4

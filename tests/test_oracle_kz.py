@@ -17,13 +17,19 @@ along the invariant axis: Sec. III C, Sec. III E).
   is pinned to.
 * The stability limit 2 / sqrt(8 + (k dx)^2): growth just above it, none
   just below.
+* The k integral (1/pi) int_0^inf F(k) dk of the plates (8-point
+  Gauss-Legendre on [0, 12]; F(k) falls like exp(-2 a k)) equals the
+  z-invariant-kernel TM + TE force on the same grid to 5e-4 (Appendix A.2:
+  that kernel is the k_z integral done in closed form), and both approach
+  the exact plate force.
 """
 import numpy as np
 import pytest
 from scipy.integrate import quad
+from scipy.special import zeta
 
 import oracle
-from casimir_inputs.configs import parallel_plates_1d, piston2d
+from casimir_inputs.configs import kz_gauss, kz_workload, parallel_plates_1d, piston2d
 from oracle import kz
 
 A, D, B = 0.5, 0.25, 1.0
@@ -108,3 +114,14 @@ def test_courant_limit():
     assert lim == pytest.approx(2 / np.sqrt(12))
     assert grows(lim * 1.02)
     assert not grows(lim * 0.98)
+
+
+def test_k_integral_equals_z_invariant_kernel():
+    res = 20
+    base = parallel_plates_1d(res, A, D, B, n_steps=int(40 / (0.5 / res)))
+    ks, ws = kz_gauss(8, 12.0)
+    f_kz = kz.solve(kz_workload(base, ks, ws), ks, ws).force
+    f_2d = oracle.solve(base.replace(pol="TM+TE", kernel="zinv2d")).force
+    exact = -2 * zeta(3) / (8 * np.pi) * (A ** -3 - B ** -3)
+    assert f_kz / f_2d - 1 == pytest.approx(0.0, abs=5e-4)
+    assert abs(f_kz / exact - 1) < 0.015
