@@ -54,13 +54,15 @@ inline dim3 grid_cyl(const Grid2D& g, int nslots) {
     return dim3(tiles, nslots, 1);
 }
 
-// Row factors of the reduced update (6 per row j, field precision):
-//   cylindrical: (j + 1/2, j - 1/2, 1/j, 1/(j - 1/2), j, j - 1), row 0 unused
-//   (the axis rules apply there);  k_z: all 1.
-// With M the coupling of the run (m, or k dx), the curls in undivided form:
+// Reduced update, with M the coupling of the run (m, or k dx) and the curls
+// in undivided form:
 //   h_x/h_z: ((A e_z(j+1) - B e_z) - M e_y) C       h_y/h_r: M e_x D - d_x e_z
 //   e_x/e_z: ((P h_z - Q h_z(j-1)) + M h_y) D       e_y/e_r: -M h_x C - d_x h_z
-//   h_z/h_phi and e_z/e_phi: the Cartesian two-dimensional forms.
+//   h_z/h_phi and e_z/e_phi: the Cartesian two-dimensional forms;
+// cylindrical (CYL): (A, B, C, D, P, Q) = (j + 1/2, j - 1/2, 1/j, 1/(j - 1/2),
+// j, j - 1), row 0 the axis with its own rules; k_z: all 1.  The row table
+// holds 6 values per row (field precision); the kernels read C and D from it
+// and form the others from j.
 enum { RA = 0, RB, RC, RD, RP, RQ, kRowFactors };
 
 // Updated h components (hx, hy, hz) of a cell at row j from its own fields,
@@ -69,21 +71,27 @@ enum { RA = 0, RB, RC, RD, RP, RQ, kRowFactors };
 // h^{-1/2} = (b / 2) curl e^0.  axis: row 0 is the symmetry axis
 // (cylindrical).  Every driver evaluates these forms, so their fields agree
 // bitwise.
-template <typename T, int MODE>
+template <typename T, int MODE, bool CYL>
 __device__ __forceinline__ void h_values(T& hx, T& hy, T& hz, T ex, T ey, T ez, T ezu, T exu, T ezr, T eyr,
-                                         const T* lx, const T* ly, const T* lz, T M, bool axis, int j,
-                                         const T* rw) {
-    if (axis && j == 0) {
-        // axis: h_z from the disk circulation (m = 0), h_r outside, h_phi 0
-        const T cz = T(4) * ezu;
-        if (MODE == 0) hx = M == T(0) ? yee::sub(lx[0], hx, lx[1], cz) : T(0);
-        else hx = M == T(0) ? yee::half(lx[1], cz) : T(0);
-        hy = T(0);
-        hz = T(0);
-        return;
+                                         const T* lx, const T* ly, const T* lz, T M, int j, const T* rw) {
+    T cz, cr;
+    if (CYL) {
+        if (j == 0) {
+            // axis: h_z from the disk circulation (m = 0), h_r outside, h_phi 0
+            const T c4 = T(4) * ezu;
+            if (MODE == 0) hx = M == T(0) ? yee::sub(lx[0], hx, lx[1], c4) : T(0);
+            else hx = M == T(0) ? yee::half(lx[1], c4) : T(0);
+            hy = T(0);
+            hz = T(0);
+            return;
+        }
+        const T r = T(j);
+        cz = (((r + T(0.5)) * ezu - (r - T(0.5)) * ez) - M * ey) * rw[RC];
+        cr = (M * ex) * rw[RD] - (ezr - ez);
+    } else {
+        cz = (ezu - ez) - M * ey;
+        cr = M * ex - (ezr - ez);
     }
-    const T cz = ((rw[RA] * ezu - rw[RB] * ez) - M * ey) * rw[RC];
-    const T cr = (M * ex) * rw[RD] - (ezr - ez);
     const T cp = (eyr - ey) - (exu - ex);
     if (MODE == 0) {
         hx = yee::sub(lx[0], hx, lx[1], cz);
@@ -99,19 +107,25 @@ __device__ __forceinline__ void h_values(T& hx, T& hy, T& hz, T ex, T ey, T ez, 
 // Updated e components (ex, ey, ez) of a cell at row j from its own fields
 // and the neighbours h(j-1) (hxd, hzd) and h(i-1) (hyl, hzl): MODE 0
 // e <- a e + b curl h, MODE 1 the consistent start e^{+1/2} = (b / 2) curl h^0.
-template <typename T, int MODE>
+template <typename T, int MODE, bool CYL>
 __device__ __forceinline__ void e_values(T& ex, T& ey, T& ez, T hx, T hy, T hz, T hxd, T hzd, T hyl, T hzl,
-                                         const T* lx, const T* ly, const T* lz, T M, bool axis, int j,
-                                         const T* rw) {
-    if (axis && j == 0) {
-        // e_z, e_phi outside / on the wall id, e_r on the axis: all 0
-        ex = T(0);
-        ey = T(0);
-        ez = T(0);
-        return;
+                                         const T* lx, const T* ly, const T* lz, T M, int j, const T* rw) {
+    T cz, cr;
+    if (CYL) {
+        if (j == 0) {
+            // e_z, e_phi outside / on the wall id, e_r on the axis: all 0
+            ex = T(0);
+            ey = T(0);
+            ez = T(0);
+            return;
+        }
+        const T r = T(j);
+        cz = ((r * hz - (r - T(1)) * hzd) + M * hy) * rw[RD];
+        cr = -((M * hx) * rw[RC]) - (hz - hzl);
+    } else {
+        cz = (hz - hzd) + M * hy;
+        cr = -(M * hx) - (hz - hzl);
     }
-    const T cz = ((rw[RP] * hz - rw[RQ] * hzd) + M * hy) * rw[RD];
-    const T cr = -((M * hx) * rw[RC]) - (hz - hzl);
     const T cp = (hy - hyl) - (hx - hxd);
     if (MODE == 0) {
         ex = yee::add(lx[0], ex, lx[1], cz);
@@ -124,16 +138,15 @@ __device__ __forceinline__ void e_values(T& ex, T& ey, T& ez, T hx, T hy, T hz, 
     }
 }
 
-// Reduced-update parameters of one run: coupling M, axis flag, row factors.
+// Reduced-update parameters of one run: coupling M and the row factors.
 template <typename T>
 struct RedRun {
     T M;
-    bool axis;
     const T* rows;
 };
 
 // H update of cell (i, j) of the channel block F in global memory.
-template <typename T, int MODE>
+template <typename T, int MODE, bool CYL>
 __device__ __forceinline__ void hcyl_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
                                           const RedRun<T>& rr, int i, int j) {
     const T* Ex = F;
@@ -145,22 +158,22 @@ __device__ __forceinline__ void hcyl_cell(T* __restrict__ F, const Grid2D& g, co
     const int64_t c = (int64_t)j * g.nx + i;
     const bool in_r = i + 1 < g.nx, in_u = j + 1 < g.ny;
     const int64_t cu = in_u ? c + g.nx : i;                     // row above (wrapped when periodic)
-    const bool has_u = in_u || g.pery;
+    const bool has_u = in_u || (!CYL && g.pery);   // the tube wall is never periodic
     const T ezu = has_u ? Ez[cu] : T(0);
     const T exu = has_u ? Ex[cu] : T(0);
     const T ezr = in_r ? Ez[c + 1] : (g.perx ? Ez[c + 1 - g.nx] : T(0));
     const T eyr = in_r ? Ey[c + 1] : (g.perx ? Ey[c + 1 - g.nx] : T(0));
     T hx = Hx[c], hy = Hy[c], hz = Hz[c];
-    h_values<T, MODE>(hx, hy, hz, Ex[c], Ey[c], Ez[c], ezu, exu, ezr, eyr,
+    h_values<T, MODE, CYL>(hx, hy, hz, Ex[c], Ey[c], Ez[c], ezu, exu, ezr, eyr,
                       lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]), lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]),
-                      lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]), rr.M, rr.axis, j, rr.rows + kRowFactors * j);
+                      lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]), rr.M, j, rr.rows + kRowFactors * j);
     Hx[c] = hx;
     Hy[c] = hy;
     Hz[c] = hz;
 }
 
 // E update of cell (i, j) of the channel block F in global memory.
-template <typename T, int MODE>
+template <typename T, int MODE, bool CYL>
 __device__ __forceinline__ void ecyl_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
                                           const RedRun<T>& rr, int i, int j) {
     T* Ex = F;
@@ -172,21 +185,21 @@ __device__ __forceinline__ void ecyl_cell(T* __restrict__ F, const Grid2D& g, co
     const int64_t c = (int64_t)j * g.nx + i;
     const bool in_d = j > 0;
     const int64_t cd = in_d ? c - g.nx : c + g.ncell - g.nx;    // row below (wrapped when periodic)
-    const bool has_d = in_d || g.pery;
+    const bool has_d = in_d || (!CYL && g.pery);
     const T hxd = has_d ? Hx[cd] : T(0);
     const T hzd = has_d ? Hz[cd] : T(0);
     const T hyl = i > 0 ? Hy[c - 1] : (g.perx ? Hy[c - 1 + g.nx] : T(0));
     const T hzl = i > 0 ? Hz[c - 1] : (g.perx ? Hz[c - 1 + g.nx] : T(0));
     T ex = Ex[c], ey = Ey[c], ez = Ez[c];
-    e_values<T, MODE>(ex, ey, ez, Hx[c], Hy[c], Hz[c], hxd, hzd, hyl, hzl,
+    e_values<T, MODE, CYL>(ex, ey, ez, Hx[c], Hy[c], Hz[c], hxd, hzd, hyl, hzl,
                       lut_ab(lut, kind, CF_EX, g.ids[CF_EX][c]), lut_ab(lut, kind, CF_EY, g.ids[CF_EY][c]),
-                      lut_ab(lut, kind, CF_EZ, g.ids[CF_EZ][c]), rr.M, rr.axis, j, rr.rows + kRowFactors * j);
+                      lut_ab(lut, kind, CF_EZ, g.ids[CF_EZ][c]), rr.M, j, rr.rows + kRowFactors * j);
     Ex[c] = ex;
     Ey[c] = ey;
     Ez[c] = ez;
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool CYL>
 __global__ __launch_bounds__(BX* BY) void k_hcyl(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                const int* __restrict__ slots, Grid2D g,
                                                const T* __restrict__ lut, RedRun<T> rr) {
@@ -196,10 +209,10 @@ __global__ __launch_bounds__(BX* BY) void k_hcyl(T* __restrict__ fields, const C
     const int i = (blockIdx.x % tiles_x) * BX + threadIdx.x;
     const int j = (blockIdx.x / tiles_x) * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
-    hcyl_cell<T, MODE>(fields + d.field_off, g, lut, d.kind, rr, i, j);
+    hcyl_cell<T, MODE, CYL>(fields + d.field_off, g, lut, d.kind, rr, i, j);
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool CYL>
 __global__ __launch_bounds__(BX* BY) void k_ecyl(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                const int* __restrict__ slots, Grid2D g,
                                                const T* __restrict__ lut, RedRun<T> rr) {
@@ -209,7 +222,7 @@ __global__ __launch_bounds__(BX* BY) void k_ecyl(T* __restrict__ fields, const C
     const int i = (blockIdx.x % tiles_x) * BX + threadIdx.x;
     const int j = (blockIdx.x / tiles_x) * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
-    ecyl_cell<T, MODE>(fields + d.field_off, g, lut, d.kind, rr, i, j);
+    ecyl_cell<T, MODE, CYL>(fields + d.field_off, g, lut, d.kind, rr, i, j);
 }
 
 // Every cell of the grid once, block-strided: thread t takes flat cells
@@ -239,7 +252,7 @@ constexpr int batch_of() {
     return sizeof(T) == 8 ? 2 : 4;
 }
 
-template <typename T, int MODE, int NTH = kResThreads>
+template <typename T, int MODE, bool CYL, int NTH = kResThreads>
 __device__ __forceinline__ void h_phase(T* __restrict__ F, const Grid2D& g, const T* __restrict__ Lc,
                                         const RedRun<T>& rr) {
     constexpr int kBatch = batch_of<T>();
@@ -265,7 +278,7 @@ __device__ __forceinline__ void h_phase(T* __restrict__ F, const Grid2D& g, cons
                 const int c = cc[q];
                 const bool in_r = i + 1 < nx, in_u = j + 1 < ny;
                 const int cu = in_u ? c + nx : i;
-                const bool has_u = in_u || g.pery;
+                const bool has_u = in_u || (!CYL && g.pery);   // the tube wall is never periodic
                 ezu[q] = has_u ? Ez[cu] : T(0);
                 exu[q] = has_u ? Ex[cu] : T(0);
                 ezr[q] = in_r ? Ez[c + 1] : (g.perx ? Ez[c + 1 - nx] : T(0));
@@ -290,10 +303,10 @@ __device__ __forceinline__ void h_phase(T* __restrict__ F, const Grid2D& g, cons
         for (int q = 0; q < kBatch; ++q) {
             if (jj[q] < ny) {
                 const int c = cc[q];
-                h_values<T, MODE>(hx[q], hy[q], hz[q], ex[q], ey[q], ez[q], ezu[q], exu[q], ezr[q], eyr[q],
+                h_values<T, MODE, CYL>(hx[q], hy[q], hz[q], ex[q], ey[q], ez[q], ezu[q], exu[q], ezr[q], eyr[q],
                                   Lc + ((CF_HX << 8) + (int)(id[q] & 255)) * 2,
                                   Lc + ((CF_HY << 8) + (int)((id[q] >> 8) & 255)) * 2,
-                                  Lc + ((CF_HZ << 8) + (int)(id[q] >> 16)) * 2, rr.M, rr.axis, jj[q],
+                                  Lc + ((CF_HZ << 8) + (int)(id[q] >> 16)) * 2, rr.M, jj[q],
                                   rr.rows + kRowFactors * jj[q]);
                 Hx[c] = hx[q];
                 Hy[c] = hy[q];
@@ -303,7 +316,7 @@ __device__ __forceinline__ void h_phase(T* __restrict__ F, const Grid2D& g, cons
     }
 }
 
-template <typename T, int MODE, int NTH = kResThreads>
+template <typename T, int MODE, bool CYL, int NTH = kResThreads>
 __device__ __forceinline__ void e_phase(T* __restrict__ F, const Grid2D& g, const T* __restrict__ Lc,
                                         const RedRun<T>& rr) {
     constexpr int kBatch = batch_of<T>();
@@ -329,7 +342,7 @@ __device__ __forceinline__ void e_phase(T* __restrict__ F, const Grid2D& g, cons
                 const int c = cc[q];
                 const bool in_d = j > 0;
                 const int cd = in_d ? c - nx : c + (int)g.ncell - nx;
-                const bool has_d = in_d || g.pery;
+                const bool has_d = in_d || (!CYL && g.pery);
                 hxd[q] = has_d ? Hx[cd] : T(0);
                 hzd[q] = has_d ? Hz[cd] : T(0);
                 hyl[q] = i > 0 ? Hy[c - 1] : (g.perx ? Hy[c - 1 + nx] : T(0));
@@ -354,10 +367,10 @@ __device__ __forceinline__ void e_phase(T* __restrict__ F, const Grid2D& g, cons
         for (int q = 0; q < kBatch; ++q) {
             if (jj[q] < ny) {
                 const int c = cc[q];
-                e_values<T, MODE>(ex[q], ey[q], ez[q], hx[q], hy[q], hz[q], hxd[q], hzd[q], hyl[q], hzl[q],
+                e_values<T, MODE, CYL>(ex[q], ey[q], ez[q], hx[q], hy[q], hz[q], hxd[q], hzd[q], hyl[q], hzl[q],
                                   Lc + ((CF_EX << 8) + (int)(id[q] & 255)) * 2,
                                   Lc + ((CF_EY << 8) + (int)((id[q] >> 8) & 255)) * 2,
-                                  Lc + ((CF_EZ << 8) + (int)(id[q] >> 16)) * 2, rr.M, rr.axis, jj[q],
+                                  Lc + ((CF_EZ << 8) + (int)(id[q] >> 16)) * 2, rr.M, jj[q],
                                   rr.rows + kRowFactors * jj[q]);
                 Ex[c] = ex[q];
                 Ey[c] = ey[q];
@@ -367,7 +380,7 @@ __device__ __forceinline__ void e_phase(T* __restrict__ F, const Grid2D& g, cons
     }
 }
 
-template <typename T>
+template <typename T, bool CYL>
 __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                               const int* __restrict__ slots, Grid2D g, CylOrders ord,
                                                               SurfTables t, double dA, double* __restrict__ acc,
@@ -395,9 +408,9 @@ __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fi
         fields[d.src_off + t.uidx[d.u_off + u]] = T(d.kick_scale * s);
     }
     __syncthreads();
-    const RedRun<T> rr{T(ord.coup[m]), ord.axis != 0, static_cast<const T*>(ord.rows)};
-    if (d.kind == 0) h_phase<T, 1>(F, g, Lc, rr);
-    else e_phase<T, 1>(F, g, Lc, rr);
+    const RedRun<T> rr{T(ord.coup[m]), static_cast<const T*>(ord.rows)};
+    if (d.kind == 0) h_phase<T, 1, CYL>(F, g, Lc, rr);
+    else e_phase<T, 1, CYL>(F, g, Lc, rr);
     __syncthreads();
     const T* X = fields + d.meas_off;
     double sum = 0.0, comp = 0.0;
@@ -406,9 +419,9 @@ __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fi
         comp = acc[2 * slot + 1];
     }
     for (int step = 0; step < nsteps; ++step) {
-        h_phase<T, 0>(F, g, Lc, rr);
+        h_phase<T, 0, CYL>(F, g, Lc, rr);
         __syncthreads();
-        e_phase<T, 0>(F, g, Lc, rr);
+        e_phase<T, 0, CYL>(F, g, Lc, rr);
         __syncthreads();
         // every read of X ends at the barrier inside; the next writes of the
         // fields come after it
@@ -441,7 +454,7 @@ __host__ __device__ constexpr int regs_x_len(int n) { return 3 * n > 6 * 256 * 2
 // step).  A cell's coordinates are recomputed in every half step from the
 // thread's first cell, passed through an empty asm statement so that the
 // compiler keeps no per-cell addresses in registers across steps.
-template <typename T, int K, int NTH>
+template <typename T, int K, int NTH, bool CYL>
 __global__ __launch_bounds__(NTH) void k_cyl_regs(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                   const int* __restrict__ slots, Grid2D g, CylOrders ord,
                                                   SurfTables t, double dA, double* __restrict__ acc,
@@ -480,9 +493,9 @@ __global__ __launch_bounds__(NTH) void k_cyl_regs(T* __restrict__ fields, const 
         fields[d.src_off + t.uidx[d.u_off + u]] = T(d.kick_scale * s);
     }
     __syncthreads();
-    const RedRun<T> rr{T(ord.coup[m]), ord.axis != 0, R};
-    if (d.kind == 0) h_phase<T, 1, NTH>(F, g, Lg, rr);
-    else e_phase<T, 1, NTH>(F, g, Lg, rr);
+    const RedRun<T> rr{T(ord.coup[m]), R};
+    if (d.kind == 0) h_phase<T, 1, CYL, NTH>(F, g, Lg, rr);
+    else e_phase<T, 1, CYL, NTH>(F, g, Lg, rr);
     __syncthreads();
     T e0[K], e1[K], e2[K], h0[K], h1[K], h2[K];
 #pragma unroll
@@ -533,13 +546,13 @@ __global__ __launch_bounds__(NTH) void k_cyl_regs(T* __restrict__ fields, const 
                     const bool in_r = i + 1 < nx, in_u = j + 1 < ny;
                     const uint32_t w = W[c];
                     const int cu = in_u ? c + nx : i;
-                    const bool has_u = in_u || g.pery;
+                    const bool has_u = in_u || (!CYL && g.pery);   // the tube wall is never periodic
                     const T ezu = has_u ? X[2 * n + cu] : T(0);
                     const T exu = has_u ? X[cu] : T(0);
                     const T ezr = in_r ? X[2 * n + c + 1] : (g.perx ? X[2 * n + c + 1 - nx] : T(0));
                     const T eyr = in_r ? X[n + c + 1] : (g.perx ? X[n + c + 1 - nx] : T(0));
-                    h_values<T, 0>(h0[k], h1[k], h2[k], e0[k], e1[k], e2[k], ezu, exu, ezr, eyr, pair(CF_HX, w),
-                                   pair(CF_HY, w), pair(CF_HZ, w), rr.M, rr.axis, j, R + kRowFactors * j);
+                    h_values<T, 0, CYL>(h0[k], h1[k], h2[k], e0[k], e1[k], e2[k], ezu, exu, ezr, eyr,
+                                        pair(CF_HX, w), pair(CF_HY, w), pair(CF_HZ, w), rr.M, j, R + kRowFactors * j);
                 }
                 i += di;
                 j += dj;
@@ -571,13 +584,13 @@ __global__ __launch_bounds__(NTH) void k_cyl_regs(T* __restrict__ fields, const 
                     const bool in_d = j > 0;
                     const uint32_t w = W[c];
                     const int cd = in_d ? c - nx : c + n - nx;
-                    const bool has_d = in_d || g.pery;
+                    const bool has_d = in_d || (!CYL && g.pery);
                     const T hxd = has_d ? X[cd] : T(0);
                     const T hzd = has_d ? X[2 * n + cd] : T(0);
                     const T hyl = i > 0 ? X[n + c - 1] : (g.perx ? X[n + c - 1 + nx] : T(0));
                     const T hzl = i > 0 ? X[2 * n + c - 1] : (g.perx ? X[2 * n + c - 1 + nx] : T(0));
-                    e_values<T, 0>(e0[k], e1[k], e2[k], h0[k], h1[k], h2[k], hxd, hzd, hyl, hzl, pair(CF_EX, w),
-                                   pair(CF_EY, w), pair(CF_EZ, w), rr.M, rr.axis, j, R + kRowFactors * j);
+                    e_values<T, 0, CYL>(e0[k], e1[k], e2[k], h0[k], h1[k], h2[k], hxd, hzd, hyl, hzl,
+                                        pair(CF_EX, w), pair(CF_EY, w), pair(CF_EZ, w), rr.M, j, R + kRowFactors * j);
                 }
                 i += di;
                 j += dj;
@@ -636,10 +649,10 @@ inline size_t device_lds_limit() {
 
 // Dynamic LDS above 64 KB needs the kernel's attribute raised first; false
 // when the runtime refuses (the caller then takes the global-memory variant).
-template <typename T, int K, int NTH>
+template <typename T, int K, int NTH, bool CYL>
 bool regs_lds_ok(size_t lds) {
     if (lds <= 65536) return true;
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cyl_regs<T, K, NTH>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cyl_regs<T, K, NTH, CYL>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -649,16 +662,16 @@ bool regs_lds_ok(size_t lds) {
 }
 
 // Launch register variant v if the grid fits it: *launched tells whether it did.
-template <typename T, int V>
+template <typename T, int V, bool CYL>
 hipError_t regs_try(int64_t ncell, size_t lds, bool* launched, T* fields, const ChanDev* ch, const int* slots,
                     int nslots, const Grid2D& g, const CylOrders& ord, const SurfTables& t, double dA, double* acc,
                     double* gamma, int gamma_stride, hipStream_t s) {
     constexpr int K = kRegVariants<T>[V].K, NTH = kRegVariants<T>[V].NTH;
     *launched = false;
-    if (ncell > (int64_t)K * NTH || !regs_lds_ok<T, K, NTH>(lds)) return hipSuccess;
+    if (ncell > (int64_t)K * NTH || !regs_lds_ok<T, K, NTH, CYL>(lds)) return hipSuccess;
     *launched = true;
-    hipLaunchKernelGGL((k_cyl_regs<T, K, NTH>), dim3(nslots), dim3(NTH), lds, s, fields, ch, slots, g, ord, t, dA,
-                       acc, gamma, gamma_stride);
+    hipLaunchKernelGGL((k_cyl_regs<T, K, NTH, CYL>), dim3(nslots), dim3(NTH), lds, s, fields, ch, slots, g, ord, t,
+                       dA, acc, gamma, gamma_stride);
     return hipGetLastError();
 }
 
@@ -669,9 +682,14 @@ hipError_t launch_hcyl(int mode, double coupling, int axis, T* fields, const Cha
                        int nslots, const Grid2D& g, const T* lut, const T* rows, hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
     const dim3 grid = grid_cyl(g, nslots), block(BX, BY, 1);
-    const RedRun<T> rr{T(coupling), axis != 0, rows};
-    if (mode == 0) hipLaunchKernelGGL((k_hcyl<T, 0>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
-    else hipLaunchKernelGGL((k_hcyl<T, 1>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+    const RedRun<T> rr{T(coupling), rows};
+    if (axis) {
+        if (mode == 0) hipLaunchKernelGGL((k_hcyl<T, 0, true>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+        else hipLaunchKernelGGL((k_hcyl<T, 1, true>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+    } else {
+        if (mode == 0) hipLaunchKernelGGL((k_hcyl<T, 0, false>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+        else hipLaunchKernelGGL((k_hcyl<T, 1, false>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+    }
     return hipGetLastError();
 }
 
@@ -680,16 +698,21 @@ hipError_t launch_ecyl(int mode, double coupling, int axis, T* fields, const Cha
                        int nslots, const Grid2D& g, const T* lut, const T* rows, hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
     const dim3 grid = grid_cyl(g, nslots), block(BX, BY, 1);
-    const RedRun<T> rr{T(coupling), axis != 0, rows};
-    if (mode == 0) hipLaunchKernelGGL((k_ecyl<T, 0>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
-    else hipLaunchKernelGGL((k_ecyl<T, 1>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+    const RedRun<T> rr{T(coupling), rows};
+    if (axis) {
+        if (mode == 0) hipLaunchKernelGGL((k_ecyl<T, 0, true>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+        else hipLaunchKernelGGL((k_ecyl<T, 1, true>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+    } else {
+        if (mode == 0) hipLaunchKernelGGL((k_ecyl<T, 0, false>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+        else hipLaunchKernelGGL((k_ecyl<T, 1, false>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+    }
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_cyl_resident(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
-                               const Grid2D& g, const CylOrders& ord, const SurfTables& t, double dA, double* acc,
-                               double* gamma, int gamma_stride, hipStream_t s, int* used) {
+template <typename T, bool CYL>
+hipError_t resident_launch(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
+                           const Grid2D& g, const CylOrders& ord, const SurfTables& t, double dA, double* acc,
+                           double* gamma, int gamma_stride, hipStream_t s, int* used) {
     *used = 0;
     if (nslots <= 0) return hipSuccess;
     const size_t dyn = regs_lds_bytes<T>(g);
@@ -698,7 +721,7 @@ hipError_t launch_cyl_resident(int variant, T* fields, const ChanDev* ch, const 
         hipError_t e = hipSuccess;
         auto attempt = [&](auto v) {
             if (!launched && e == hipSuccess)
-                e = regs_try<T, decltype(v)::value>(g.ncell, dyn, &launched, fields, ch, slots, nslots, g, ord, t,
+                e = regs_try<T, decltype(v)::value, CYL>(g.ncell, dyn, &launched, fields, ch, slots, nslots, g, ord, t,
                                                     dA, acc, gamma, gamma_stride, s);
         };
         attempt(std::integral_constant<int, 0>{});
@@ -715,9 +738,20 @@ hipError_t launch_cyl_resident(int variant, T* fields, const ChanDev* ch, const 
         }
     }
     *used = 2;
-    hipLaunchKernelGGL((k_cyl_resident<T>), dim3(nslots), dim3(kResThreads), 0, s, fields, ch, slots, g, ord, t, dA,
+    hipLaunchKernelGGL((k_cyl_resident<T, CYL>), dim3(nslots), dim3(kResThreads), 0, s, fields, ch, slots, g, ord, t, dA,
                        acc, gamma, gamma_stride);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cyl_resident(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
+                               const Grid2D& g, const CylOrders& ord, const SurfTables& t, double dA, double* acc,
+                               double* gamma, int gamma_stride, hipStream_t s, int* used) {
+    if (ord.axis)
+        return resident_launch<T, true>(variant, fields, ch, slots, nslots, g, ord, t, dA, acc, gamma, gamma_stride, s,
+                                        used);
+    return resident_launch<T, false>(variant, fields, ch, slots, nslots, g, ord, t, dA, acc, gamma, gamma_stride, s,
+                                     used);
 }
 
 #define CF_CYL_INSTANTIATE(T)                                                                                   \
