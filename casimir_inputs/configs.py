@@ -266,10 +266,12 @@ def kz_gauss(n: int, k_max: float):
     return 0.5 * k_max * (t + 1.0), 0.5 * k_max * w / np.pi
 
 
-def kz_workload(wl: Workload, kz, kz_weight) -> Workload:
+def kz_workload(wl: Workload, kz, kz_weight, kx=None) -> Workload:
     """The z-invariant 2D workload wl solved at Bloch wavevectors kz along
-    z (six components, general kernel); the force is sum_q kz_weight[q] F(kz[q])."""
+    z (six components, general kernel) and, when kx is given, Bloch
+    wavevectors along a periodic x; the force is sum_q kz_weight[q] F_q."""
     return wl.replace(coord="kz", kz=tuple(float(k) for k in kz), kz_weight=tuple(float(w) for w in kz_weight),
+                      kx=tuple(float(k) for k in kx) if kx is not None else (),
                       pol="3D", kernel="general", name=wl.name + f"_kz{len(kz)}")
 
 

@@ -109,6 +109,8 @@ class Workload:
     m_max      cylindrical workloads: azimuthal orders 0..m_max
     kz, kz_weight  "kz" workloads (z-invariant 2D, six components): the
                Bloch wavevectors along z and the weights of F(k_q) in the force
+    kx         "kz" workloads: Bloch wavevector along a periodic x per point
+               (empty: all zero; any nonzero value makes the fields complex)
     """
 
     name: str
@@ -135,6 +137,7 @@ class Workload:
     m_max: int = 0
     kz: Tuple[float, ...] = ()
     kz_weight: Tuple[float, ...] = ()
+    kx: Tuple[float, ...] = ()
 
     def replace(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)

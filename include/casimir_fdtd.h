@@ -115,6 +115,15 @@ enum { CF_COORD_CARTESIAN = 0, CF_COORD_CYLINDRICAL = 1, CF_COORD_KZ = 2 };
  *     satisfy courant * v_max * sqrt(8 + (k_max / res)^2) / 2 < 1.
  *   - Channels, labels (q * n_harm + n) and signs (times kz_weight[q]) are
  *     ordered as for cylindrical orders.
+ *   - Bloch-periodic x (Sec. III E, a cell periodic in x with period
+ *     L = n[0] / res): kx[q] != 0 at any point makes the fields complex
+ *     (quasi-periodic: F(x + L) = exp(i kx L) F(x)); bc[0] must be
+ *     CF_BC_PERIODIC and S must not reach across the periodic x edge (no
+ *     interpolation point beyond it), else CF_E_SURFACE.  Sources are real
+ *     and the force takes the real part of the response (the -kx point is
+ *     the complex conjugate: weight the pair accordingly).  Complex runs use
+ *     12 values per cell and the global-memory resident kernel (or the
+ *     split kernels).
  */
 
 typedef struct cf_grid {
@@ -161,6 +170,7 @@ typedef struct cf_surface {
     const double* kz;        /* CF_COORD_KZ problems: the wavevectors k_q (host, copied) */
     const double* kz_weight; /* and their weights                                        */
     int n_kz;                /* number of wavevectors (1..33)                            */
+    const double* kx;        /* CF_COORD_KZ: Bloch wavevector along x per point, or NULL  */
 } cf_surface;
 
 /*

@@ -52,7 +52,7 @@ class _Materials(C.Structure):
 class _Surface(C.Structure):
     _fields_ = [("lo", C.c_int * 3), ("hi", C.c_int * 3), ("n_harm", C.c_int),
                 ("force_axis", C.c_int), ("m_max", C.c_int), ("kz", C.POINTER(C.c_double)),
-                ("kz_weight", C.POINTER(C.c_double)), ("n_kz", C.c_int)]
+                ("kz_weight", C.POINTER(C.c_double)), ("n_kz", C.c_int), ("kx", C.POINTER(C.c_double))]
 
 
 class _Opts(C.Structure):
@@ -193,7 +193,7 @@ class Problem:
                  eps: Sequence[float], mu: Sequence[float], comp_ids: Dict[str, np.ndarray],
                  s_lo: Sequence[int], s_hi: Sequence[int], n_harm: int, force_axis: int,
                  pml_cells: Sequence[int] = (0, 0, 0), coord: str = "cartesian", m_max: int = 0,
-                 kz: Sequence[float] = (), kz_weight: Sequence[float] = ()):
+                 kz: Sequence[float] = (), kz_weight: Sequence[float] = (), kx: Sequence[float] = ()):
         lib = load()
         g = _Grid()
         g.ndim = int(ndim)
@@ -233,6 +233,11 @@ class Problem:
             raise ValueError("kz and kz_weight differ in length")
         if len(kz_arr):
             s.kz, s.kz_weight, s.n_kz = _dptr(kz_arr), _dptr(kzw_arr), len(kz_arr)
+        kx_arr = np.ascontiguousarray(kx, dtype=np.float64)
+        if len(kx_arr):
+            if len(kx_arr) != len(kz_arr):
+                raise ValueError("kx and kz differ in length")
+            s.kx = _dptr(kx_arr)
         h = C.c_void_p()
         _check(lib.cf_problem_create(C.byref(g), C.byref(m), C.byref(s), C.byref(h)))
         self._h = h
@@ -246,7 +251,7 @@ class Problem:
     def from_workload(cls, wl) -> "Problem":
         return cls(wl.ndim, wl.shape, wl.res, wl.bc, wl.eps, wl.mu, wl.comp_ids, wl.s_lo, wl.s_hi,
                    wl.n_harm, wl.force_axis, wl.pml_cells, coord=wl.coord, m_max=wl.m_max,
-                   kz=wl.kz, kz_weight=wl.kz_weight)
+                   kz=wl.kz, kz_weight=wl.kz_weight, kx=wl.kx)
 
     def __del__(self):
         h = getattr(self, "_h", None)

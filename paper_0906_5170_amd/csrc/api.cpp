@@ -502,11 +502,15 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
         ord.steps[m] = cf::order_steps(p, o, m);
         ord.dt[m] = cm / p.grid.res;
         ord.coup[m] = p.coupling(m);
+        const double phi = p.bloch ? p.kxs[m] * p.nx / p.grid.res : 0.0;   // k_x L
+        ord.ph_c[m] = std::cos(phi);
+        ord.ph_s[m] = std::sin(phi);
         std::vector<double> l64 = cf::coefficient_lut(p, o.sigma, cm);
         std::copy(l64.begin(), l64.end(), luts.begin() + m * lut_len);
         cf::kernel_table(o.kernel, o.sigma, ord.dt[m], ord.steps[m], ktabs.data() + (size_t)m * t_max);
     }
     ord.axis = p.cyl ? 1 : 0;
+    ord.cplx = p.bloch ? 1 : 0;
     CF_HIP(up(L.lut, luts.data(), luts.size() * sizeof(T)));
     CF_HIP(up(L.ktab, ktabs.data(), ktabs.size() * 8));
     // row factors in the field precision (A, B, C, D, P, Q per row):
@@ -591,12 +595,16 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
         const double* k_m = dk + (size_t)m * t_max;
         STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
         STEP_OK(cf::launch_kick<T>(fields, dch, sl, w.n_all, st.max_uniq, tabs, s));
-        STEP_OK(cf::launch_hcyl<T>(1, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, s));
-        STEP_OK(cf::launch_ecyl<T>(1, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, s));
+        STEP_OK(cf::launch_hcyl<T>(1, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, ord.ph_c[m],
+                                   ord.ph_s[m], ord.cplx, s));
+        STEP_OK(cf::launch_ecyl<T>(1, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, ord.ph_c[m],
+                                   ord.ph_s[m], ord.cplx, s));
         for (int k = 0; k < tm; ++k) {
             const bool take = smp.begin(s);
-            STEP_OK(cf::launch_hcyl<T>(0, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, s));
-            STEP_OK(cf::launch_ecyl<T>(0, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, s));
+            STEP_OK(cf::launch_hcyl<T>(0, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows,
+                                       ord.ph_c[m], ord.ph_s[m], ord.cplx, s));
+            STEP_OK(cf::launch_ecyl<T>(0, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows,
+                                       ord.ph_c[m], ord.ph_s[m], ord.cplx, s));
             const double cu = (double)w.n_all * p.ncell;
             smp.end(take, s, cu, cu * state_bytes);
             STEP_OK(cf::launch_surface<T>(fields, dch, sl, w.n_all, tabs, k_m, k, dt, dA, dacc, dgam, (int)C, s));

@@ -132,12 +132,16 @@ hipError_t launch_e2d(int pol, int mode, T* fields, const ChanDev* ch, const int
 // Reduced two-dimensional problems (cylindrical orders, k_z runs): coupling
 // = m or k dx of the run, axis = 1 when row 0 is the symmetry axis, rows =
 // 6 factors per row j in the field precision (see kernels_cyl.hip).
+// cplx: complex (Bloch-periodic x) run, 12 values per cell (real part, then
+// imaginary part), with the phase ph_c + i ph_s across the periodic x edge.
 template <typename T>
 hipError_t launch_hcyl(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
-                       int nslots, const Grid2D& g, const T* lut, const T* rows, hipStream_t s);
+                       int nslots, const Grid2D& g, const T* lut, const T* rows, double ph_c, double ph_s, int cplx,
+                       hipStream_t s);
 template <typename T>
 hipError_t launch_ecyl(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
-                       int nslots, const Grid2D& g, const T* lut, const T* rows, hipStream_t s);
+                       int nslots, const Grid2D& g, const T* lut, const T* rows, double ph_c, double ph_s, int cplx,
+                       hipStream_t s);
 
 // Per-order tables of a reduced solve (cylindrical orders m, or k_z points):
 // coefficient table of order q at lut + q * lut_stride (field precision),
@@ -155,7 +159,10 @@ struct CylOrders {
     const uint32_t* idw;
     const void* rows;                 // 6 row factors per row (field precision)
     double coup[kCylMaxOrders];       // coupling of each order: m, or k dx
+    double ph_c[kCylMaxOrders];       // Bloch phase across the periodic x edge (complex runs)
+    double ph_s[kCylMaxOrders];
     int axis;                         // row 0 is the symmetry axis (cylindrical)
+    int cplx;                         // complex fields (Bloch-periodic x)
 };
 
 // Resident cylindrical solve: one block per listed channel clears its

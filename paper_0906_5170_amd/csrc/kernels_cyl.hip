@@ -138,17 +138,36 @@ __device__ __forceinline__ void e_values(T& ex, T& ey, T& ez, T hx, T hy, T hz, 
     }
 }
 
-// Reduced-update parameters of one run: coupling M and the row factors.
+// Reduced-update parameters of one run: coupling M, the row factors and,
+// for complex (Bloch-periodic x) runs, the phase p = pc + i ps that a field
+// gains across the periodic x edge.
 template <typename T>
 struct RedRun {
     T M;
     const T* rows;
+    T pc, ps;
 };
 
-// H update of cell (i, j) of the channel block F in global memory.
-template <typename T, int MODE, bool CYL>
+// Complex runs keep the real part of the six components in the first
+// 6 x ncell values of a channel block and the imaginary part in the next.
+// The x neighbour across the periodic edge of part `part` (0 real, 1
+// imaginary): forward (F[nx] = p F[0]) or backward (F[-1] = conj(p) F[nx-1]),
+// from the wrapped cell's own-part value a and other-part value b.
+template <typename T>
+__device__ __forceinline__ T bloch_fwd(T a, T b, int part, T pc, T ps) {
+    return part == 0 ? a * pc - b * ps : a * pc + b * ps;
+}
+template <typename T>
+__device__ __forceinline__ T bloch_bwd(T a, T b, int part, T pc, T ps) {
+    return part == 0 ? a * pc + b * ps : a * pc - b * ps;
+}
+
+// H update of cell (i, j), part `part`, of the channel block F in global memory.
+template <typename T, int MODE, bool CYL, bool CPLX = false>
 __device__ __forceinline__ void hcyl_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
-                                          const RedRun<T>& rr, int i, int j) {
+                                          const RedRun<T>& rr, int i, int j, int part = 0) {
+    T* const Fo = F + (CPLX ? (1 - part) * 6 * g.ncell : 0);    // the other part (complex runs)
+    F += CPLX ? part * 6 * g.ncell : 0;
     const T* Ex = F;
     const T* Ey = F + g.ncell;
     const T* Ez = F + 2 * g.ncell;
@@ -161,8 +180,20 @@ __device__ __forceinline__ void hcyl_cell(T* __restrict__ F, const Grid2D& g, co
     const bool has_u = in_u || (!CYL && g.pery);   // the tube wall is never periodic
     const T ezu = has_u ? Ez[cu] : T(0);
     const T exu = has_u ? Ex[cu] : T(0);
-    const T ezr = in_r ? Ez[c + 1] : (g.perx ? Ez[c + 1 - g.nx] : T(0));
-    const T eyr = in_r ? Ey[c + 1] : (g.perx ? Ey[c + 1 - g.nx] : T(0));
+    T ezr, eyr;
+    if (in_r) {
+        ezr = Ez[c + 1];
+        eyr = Ey[c + 1];
+    } else if (!g.perx) {
+        ezr = eyr = T(0);
+    } else if (CPLX) {
+        const int64_t w = c + 1 - g.nx;
+        ezr = bloch_fwd(Ez[w], Fo[2 * g.ncell + w], part, rr.pc, rr.ps);
+        eyr = bloch_fwd(Ey[w], Fo[g.ncell + w], part, rr.pc, rr.ps);
+    } else {
+        ezr = Ez[c + 1 - g.nx];
+        eyr = Ey[c + 1 - g.nx];
+    }
     T hx = Hx[c], hy = Hy[c], hz = Hz[c];
     h_values<T, MODE, CYL>(hx, hy, hz, Ex[c], Ey[c], Ez[c], ezu, exu, ezr, eyr,
                       lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]), lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]),
@@ -172,10 +203,12 @@ __device__ __forceinline__ void hcyl_cell(T* __restrict__ F, const Grid2D& g, co
     Hz[c] = hz;
 }
 
-// E update of cell (i, j) of the channel block F in global memory.
-template <typename T, int MODE, bool CYL>
+// E update of cell (i, j), part `part`, of the channel block F in global memory.
+template <typename T, int MODE, bool CYL, bool CPLX = false>
 __device__ __forceinline__ void ecyl_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
-                                          const RedRun<T>& rr, int i, int j) {
+                                          const RedRun<T>& rr, int i, int j, int part = 0) {
+    T* const Fo = F + (CPLX ? (1 - part) * 6 * g.ncell : 0);
+    F += CPLX ? part * 6 * g.ncell : 0;
     T* Ex = F;
     T* Ey = F + g.ncell;
     T* Ez = F + 2 * g.ncell;
@@ -188,8 +221,20 @@ __device__ __forceinline__ void ecyl_cell(T* __restrict__ F, const Grid2D& g, co
     const bool has_d = in_d || (!CYL && g.pery);
     const T hxd = has_d ? Hx[cd] : T(0);
     const T hzd = has_d ? Hz[cd] : T(0);
-    const T hyl = i > 0 ? Hy[c - 1] : (g.perx ? Hy[c - 1 + g.nx] : T(0));
-    const T hzl = i > 0 ? Hz[c - 1] : (g.perx ? Hz[c - 1 + g.nx] : T(0));
+    T hyl, hzl;
+    if (i > 0) {
+        hyl = Hy[c - 1];
+        hzl = Hz[c - 1];
+    } else if (!g.perx) {
+        hyl = hzl = T(0);
+    } else if (CPLX) {
+        const int64_t w = c - 1 + g.nx;
+        hyl = bloch_bwd(Hy[w], Fo[4 * g.ncell + w], part, rr.pc, rr.ps);
+        hzl = bloch_bwd(Hz[w], Fo[5 * g.ncell + w], part, rr.pc, rr.ps);
+    } else {
+        hyl = Hy[c - 1 + g.nx];
+        hzl = Hz[c - 1 + g.nx];
+    }
     T ex = Ex[c], ey = Ey[c], ez = Ez[c];
     e_values<T, MODE, CYL>(ex, ey, ez, Hx[c], Hy[c], Hz[c], hxd, hzd, hyl, hzl,
                       lut_ab(lut, kind, CF_EX, g.ids[CF_EX][c]), lut_ab(lut, kind, CF_EY, g.ids[CF_EY][c]),
@@ -199,7 +244,7 @@ __device__ __forceinline__ void ecyl_cell(T* __restrict__ F, const Grid2D& g, co
     Ez[c] = ez;
 }
 
-template <typename T, int MODE, bool CYL>
+template <typename T, int MODE, bool CYL, bool CPLX>
 __global__ __launch_bounds__(BX* BY) void k_hcyl(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                const int* __restrict__ slots, Grid2D g,
                                                const T* __restrict__ lut, RedRun<T> rr) {
@@ -209,10 +254,11 @@ __global__ __launch_bounds__(BX* BY) void k_hcyl(T* __restrict__ fields, const C
     const int i = (blockIdx.x % tiles_x) * BX + threadIdx.x;
     const int j = (blockIdx.x / tiles_x) * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
-    hcyl_cell<T, MODE, CYL>(fields + d.field_off, g, lut, d.kind, rr, i, j);
+    for (int part = 0; part < (CPLX ? 2 : 1); ++part)
+        hcyl_cell<T, MODE, CYL, CPLX>(fields + d.field_off, g, lut, d.kind, rr, i, j, part);
 }
 
-template <typename T, int MODE, bool CYL>
+template <typename T, int MODE, bool CYL, bool CPLX>
 __global__ __launch_bounds__(BX* BY) void k_ecyl(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                const int* __restrict__ slots, Grid2D g,
                                                const T* __restrict__ lut, RedRun<T> rr) {
@@ -222,7 +268,8 @@ __global__ __launch_bounds__(BX* BY) void k_ecyl(T* __restrict__ fields, const C
     const int i = (blockIdx.x % tiles_x) * BX + threadIdx.x;
     const int j = (blockIdx.x / tiles_x) * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
-    ecyl_cell<T, MODE, CYL>(fields + d.field_off, g, lut, d.kind, rr, i, j);
+    for (int part = 0; part < (CPLX ? 2 : 1); ++part)
+        ecyl_cell<T, MODE, CYL, CPLX>(fields + d.field_off, g, lut, d.kind, rr, i, j, part);
 }
 
 // Every cell of the grid once, block-strided: thread t takes flat cells
@@ -252,9 +299,12 @@ constexpr int batch_of() {
     return sizeof(T) == 8 ? 2 : 4;
 }
 
-template <typename T, int MODE, bool CYL, int NTH = kResThreads>
-__device__ __forceinline__ void h_phase(T* __restrict__ F, const Grid2D& g, const T* __restrict__ Lc,
+template <typename T, int MODE, bool CYL, int NTH = kResThreads, bool CPLX = false>
+__device__ __forceinline__ void h_phase(T* __restrict__ F0, const Grid2D& g, const T* __restrict__ Lc,
                                         const RedRun<T>& rr) {
+  for (int part = 0; part < (CPLX ? 2 : 1); ++part) {
+    T* const F = F0 + (CPLX ? part * 6 * g.ncell : 0);
+    const T* const Fo = F0 + (CPLX ? (1 - part) * 6 * g.ncell : 0);   // the other part (complex runs)
     constexpr int kBatch = batch_of<T>();
     const T* Ex = F;
     const T* Ey = F + g.ncell;
@@ -281,8 +331,19 @@ __device__ __forceinline__ void h_phase(T* __restrict__ F, const Grid2D& g, cons
                 const bool has_u = in_u || (!CYL && g.pery);   // the tube wall is never periodic
                 ezu[q] = has_u ? Ez[cu] : T(0);
                 exu[q] = has_u ? Ex[cu] : T(0);
-                ezr[q] = in_r ? Ez[c + 1] : (g.perx ? Ez[c + 1 - nx] : T(0));
-                eyr[q] = in_r ? Ey[c + 1] : (g.perx ? Ey[c + 1 - nx] : T(0));
+                if (in_r) {
+                    ezr[q] = Ez[c + 1];
+                    eyr[q] = Ey[c + 1];
+                } else if (!g.perx) {
+                    ezr[q] = eyr[q] = T(0);
+                } else if (CPLX) {
+                    const int w = c + 1 - nx;
+                    ezr[q] = bloch_fwd(Ez[w], Fo[2 * (int)g.ncell + w], part, rr.pc, rr.ps);
+                    eyr[q] = bloch_fwd(Ey[w], Fo[(int)g.ncell + w], part, rr.pc, rr.ps);
+                } else {
+                    ezr[q] = Ez[c + 1 - nx];
+                    eyr[q] = Ey[c + 1 - nx];
+                }
                 ex[q] = Ex[c];
                 ey[q] = Ey[c];
                 ez[q] = Ez[c];
@@ -314,11 +375,15 @@ __device__ __forceinline__ void h_phase(T* __restrict__ F, const Grid2D& g, cons
             }
         }
     }
+  }
 }
 
-template <typename T, int MODE, bool CYL, int NTH = kResThreads>
-__device__ __forceinline__ void e_phase(T* __restrict__ F, const Grid2D& g, const T* __restrict__ Lc,
+template <typename T, int MODE, bool CYL, int NTH = kResThreads, bool CPLX = false>
+__device__ __forceinline__ void e_phase(T* __restrict__ F0, const Grid2D& g, const T* __restrict__ Lc,
                                         const RedRun<T>& rr) {
+  for (int part = 0; part < (CPLX ? 2 : 1); ++part) {
+    T* const F = F0 + (CPLX ? part * 6 * g.ncell : 0);
+    const T* const Fo = F0 + (CPLX ? (1 - part) * 6 * g.ncell : 0);
     constexpr int kBatch = batch_of<T>();
     T* Ex = F;
     T* Ey = F + g.ncell;
@@ -345,8 +410,19 @@ __device__ __forceinline__ void e_phase(T* __restrict__ F, const Grid2D& g, cons
                 const bool has_d = in_d || (!CYL && g.pery);
                 hxd[q] = has_d ? Hx[cd] : T(0);
                 hzd[q] = has_d ? Hz[cd] : T(0);
-                hyl[q] = i > 0 ? Hy[c - 1] : (g.perx ? Hy[c - 1 + nx] : T(0));
-                hzl[q] = i > 0 ? Hz[c - 1] : (g.perx ? Hz[c - 1 + nx] : T(0));
+                if (i > 0) {
+                    hyl[q] = Hy[c - 1];
+                    hzl[q] = Hz[c - 1];
+                } else if (!g.perx) {
+                    hyl[q] = hzl[q] = T(0);
+                } else if (CPLX) {
+                    const int w = c - 1 + nx;
+                    hyl[q] = bloch_bwd(Hy[w], Fo[4 * (int)g.ncell + w], part, rr.pc, rr.ps);
+                    hzl[q] = bloch_bwd(Hz[w], Fo[5 * (int)g.ncell + w], part, rr.pc, rr.ps);
+                } else {
+                    hyl[q] = Hy[c - 1 + nx];
+                    hzl[q] = Hz[c - 1 + nx];
+                }
                 hx[q] = Hx[c];
                 hy[q] = Hy[c];
                 hz[q] = Hz[c];
@@ -378,9 +454,10 @@ __device__ __forceinline__ void e_phase(T* __restrict__ F, const Grid2D& g, cons
             }
         }
     }
+  }
 }
 
-template <typename T, bool CYL>
+template <typename T, bool CYL, bool CPLX>
 __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                               const int* __restrict__ slots, Grid2D g, CylOrders ord,
                                                               SurfTables t, double dA, double* __restrict__ acc,
@@ -397,7 +474,7 @@ __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fi
     T* F = fields + d.field_off;
     const T* lk = lut + d.kind * 6 * 256 * 2;
     for (int k = threadIdx.x; k < 6 * 256 * 2; k += kResThreads) Lc[k] = lk[k];
-    const int64_t nval = 6 * g.ncell;
+    const int64_t nval = (CPLX ? 12 : 6) * g.ncell;
     for (int64_t k = threadIdx.x; k < nval; k += kResThreads) F[k] = T(0);
     __syncthreads();
     // kick: the source component's surface deposit (one writer per point)
@@ -408,9 +485,9 @@ __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fi
         fields[d.src_off + t.uidx[d.u_off + u]] = T(d.kick_scale * s);
     }
     __syncthreads();
-    const RedRun<T> rr{T(ord.coup[m]), static_cast<const T*>(ord.rows)};
-    if (d.kind == 0) h_phase<T, 1, CYL>(F, g, Lc, rr);
-    else e_phase<T, 1, CYL>(F, g, Lc, rr);
+    const RedRun<T> rr{T(ord.coup[m]), static_cast<const T*>(ord.rows), T(ord.ph_c[m]), T(ord.ph_s[m])};
+    if (d.kind == 0) h_phase<T, 1, CYL, kResThreads, CPLX>(F, g, Lc, rr);
+    else e_phase<T, 1, CYL, kResThreads, CPLX>(F, g, Lc, rr);
     __syncthreads();
     const T* X = fields + d.meas_off;
     double sum = 0.0, comp = 0.0;
@@ -419,9 +496,9 @@ __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fi
         comp = acc[2 * slot + 1];
     }
     for (int step = 0; step < nsteps; ++step) {
-        h_phase<T, 0, CYL>(F, g, Lc, rr);
+        h_phase<T, 0, CYL, kResThreads, CPLX>(F, g, Lc, rr);
         __syncthreads();
-        e_phase<T, 0, CYL>(F, g, Lc, rr);
+        e_phase<T, 0, CYL, kResThreads, CPLX>(F, g, Lc, rr);
         __syncthreads();
         // every read of X ends at the barrier inside; the next writes of the
         // fields come after it
@@ -493,7 +570,7 @@ __global__ __launch_bounds__(NTH) void k_cyl_regs(T* __restrict__ fields, const 
         fields[d.src_off + t.uidx[d.u_off + u]] = T(d.kick_scale * s);
     }
     __syncthreads();
-    const RedRun<T> rr{T(ord.coup[m]), R};
+    const RedRun<T> rr{T(ord.coup[m]), R, T(1), T(0)};
     if (d.kind == 0) h_phase<T, 1, CYL, NTH>(F, g, Lg, rr);
     else e_phase<T, 1, CYL, NTH>(F, g, Lg, rr);
     __syncthreads();
@@ -679,44 +756,56 @@ hipError_t regs_try(int64_t ncell, size_t lds, bool* launched, T* fields, const 
 
 template <typename T>
 hipError_t launch_hcyl(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
-                       int nslots, const Grid2D& g, const T* lut, const T* rows, hipStream_t s) {
+                       int nslots, const Grid2D& g, const T* lut, const T* rows, double ph_c, double ph_s, int cplx,
+                       hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
     const dim3 grid = grid_cyl(g, nslots), block(BX, BY, 1);
-    const RedRun<T> rr{T(coupling), rows};
+    const RedRun<T> rr{T(coupling), rows, T(ph_c), T(ph_s)};
+#define CF_HCYL(M, C, X) hipLaunchKernelGGL((k_hcyl<T, M, C, X>), grid, block, 0, s, fields, ch, slots, g, lut, rr)
     if (axis) {
-        if (mode == 0) hipLaunchKernelGGL((k_hcyl<T, 0, true>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
-        else hipLaunchKernelGGL((k_hcyl<T, 1, true>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+        if (mode == 0) CF_HCYL(0, true, false);
+        else CF_HCYL(1, true, false);
+    } else if (cplx) {
+        if (mode == 0) CF_HCYL(0, false, true);
+        else CF_HCYL(1, false, true);
     } else {
-        if (mode == 0) hipLaunchKernelGGL((k_hcyl<T, 0, false>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
-        else hipLaunchKernelGGL((k_hcyl<T, 1, false>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+        if (mode == 0) CF_HCYL(0, false, false);
+        else CF_HCYL(1, false, false);
     }
+#undef CF_HCYL
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_ecyl(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
-                       int nslots, const Grid2D& g, const T* lut, const T* rows, hipStream_t s) {
+                       int nslots, const Grid2D& g, const T* lut, const T* rows, double ph_c, double ph_s, int cplx,
+                       hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
     const dim3 grid = grid_cyl(g, nslots), block(BX, BY, 1);
-    const RedRun<T> rr{T(coupling), rows};
+    const RedRun<T> rr{T(coupling), rows, T(ph_c), T(ph_s)};
+#define CF_ECYL(M, C, X) hipLaunchKernelGGL((k_ecyl<T, M, C, X>), grid, block, 0, s, fields, ch, slots, g, lut, rr)
     if (axis) {
-        if (mode == 0) hipLaunchKernelGGL((k_ecyl<T, 0, true>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
-        else hipLaunchKernelGGL((k_ecyl<T, 1, true>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+        if (mode == 0) CF_ECYL(0, true, false);
+        else CF_ECYL(1, true, false);
+    } else if (cplx) {
+        if (mode == 0) CF_ECYL(0, false, true);
+        else CF_ECYL(1, false, true);
     } else {
-        if (mode == 0) hipLaunchKernelGGL((k_ecyl<T, 0, false>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
-        else hipLaunchKernelGGL((k_ecyl<T, 1, false>), grid, block, 0, s, fields, ch, slots, g, lut, rr);
+        if (mode == 0) CF_ECYL(0, false, false);
+        else CF_ECYL(1, false, false);
     }
+#undef CF_ECYL
     return hipGetLastError();
 }
 
-template <typename T, bool CYL>
+template <typename T, bool CYL, bool CPLX>
 hipError_t resident_launch(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
                            const Grid2D& g, const CylOrders& ord, const SurfTables& t, double dA, double* acc,
                            double* gamma, int gamma_stride, hipStream_t s, int* used) {
     *used = 0;
     if (nslots <= 0) return hipSuccess;
     const size_t dyn = regs_lds_bytes<T>(g);
-    if (variant != 2 && ord.idw && dyn + 64 <= device_lds_limit()) {
+    if (!CPLX && variant != 2 && ord.idw && dyn + 64 <= device_lds_limit()) {
         bool launched = false;
         hipError_t e = hipSuccess;
         auto attempt = [&](auto v) {
@@ -738,7 +827,7 @@ hipError_t resident_launch(int variant, T* fields, const ChanDev* ch, const int*
         }
     }
     *used = 2;
-    hipLaunchKernelGGL((k_cyl_resident<T, CYL>), dim3(nslots), dim3(kResThreads), 0, s, fields, ch, slots, g, ord, t, dA,
+    hipLaunchKernelGGL((k_cyl_resident<T, CYL, CPLX>), dim3(nslots), dim3(kResThreads), 0, s, fields, ch, slots, g, ord, t, dA,
                        acc, gamma, gamma_stride);
     return hipGetLastError();
 }
@@ -748,17 +837,20 @@ hipError_t launch_cyl_resident(int variant, T* fields, const ChanDev* ch, const 
                                const Grid2D& g, const CylOrders& ord, const SurfTables& t, double dA, double* acc,
                                double* gamma, int gamma_stride, hipStream_t s, int* used) {
     if (ord.axis)
-        return resident_launch<T, true>(variant, fields, ch, slots, nslots, g, ord, t, dA, acc, gamma, gamma_stride, s,
-                                        used);
-    return resident_launch<T, false>(variant, fields, ch, slots, nslots, g, ord, t, dA, acc, gamma, gamma_stride, s,
-                                     used);
+        return resident_launch<T, true, false>(variant, fields, ch, slots, nslots, g, ord, t, dA, acc, gamma,
+                                               gamma_stride, s, used);
+    if (ord.cplx)
+        return resident_launch<T, false, true>(variant, fields, ch, slots, nslots, g, ord, t, dA, acc, gamma,
+                                               gamma_stride, s, used);
+    return resident_launch<T, false, false>(variant, fields, ch, slots, nslots, g, ord, t, dA, acc, gamma,
+                                            gamma_stride, s, used);
 }
 
 #define CF_CYL_INSTANTIATE(T)                                                                                   \
     template hipError_t launch_hcyl<T>(int, double, int, T*, const ChanDev*, const int*, int, const Grid2D&,  \
-                                       const T*, const T*, hipStream_t);                                       \
+                                       const T*, const T*, double, double, int, hipStream_t);                  \
     template hipError_t launch_ecyl<T>(int, double, int, T*, const ChanDev*, const int*, int, const Grid2D&,  \
-                                       const T*, const T*, hipStream_t);                                       \
+                                       const T*, const T*, double, double, int, hipStream_t);                  \
     template hipError_t launch_cyl_resident<T>(int, T*, const ChanDev*, const int*, int, const Grid2D&,       \
                                                const CylOrders&, const SurfTables&, double, double*, double*, \
                                                int, hipStream_t, int*);

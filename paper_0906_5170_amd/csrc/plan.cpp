@@ -41,7 +41,7 @@ int comp_slot(int pol, int comp) {
 
 int n_comp_for(int ndim) { return ndim == 2 ? 3 : 6; }
 
-int n_comp(const Problem& p) { return p.reduced() ? 6 : n_comp_for(p.grid.ndim); }
+int n_comp(const Problem& p) { return p.bloch ? 12 : p.reduced() ? 6 : n_comp_for(p.grid.ndim); }
 
 double order_courant(const Problem& p, double courant, int m) {
     return p.cyl && m >= 2 ? std::min(courant, 1.0 / (1.0 + m)) : courant;
@@ -395,9 +395,19 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
     p.m_max = p.cyl ? s.m_max : 0;
     p.kzs.clear();
     p.kz_w.clear();
+    p.kxs.clear();
+    p.bloch = false;
     if (p.kz) {
         p.kzs.assign(s.kz, s.kz + s.n_kz);
         p.kz_w.assign(s.kz_weight, s.kz_weight + s.n_kz);
+        p.kxs.assign(s.n_kz, 0.0);
+        if (s.kx)
+            for (int q = 0; q < s.n_kz; ++q) {
+                if (!std::isfinite(s.kx[q])) return "k_x points must be finite";
+                p.kxs[q] = s.kx[q];
+                p.bloch = p.bloch || s.kx[q] != 0.0;
+            }
+        if (p.bloch && g.bc[0] != CF_BC_PERIODIC) return "Bloch-periodic x needs a periodic x axis";
     }
     if (g.ndim == 2) {
         p.grid.bc[2] = CF_BC_PERIODIC;
@@ -439,8 +449,9 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
         }
     // stress surface
     p.surf = s;
-    p.surf.kz = nullptr;          // copied into kzs / kz_w above
+    p.surf.kz = nullptr;          // copied into kzs / kz_w / kxs above
     p.surf.kz_weight = nullptr;
+    p.surf.kx = nullptr;
     if (s.force_axis < 0 || s.force_axis >= g.ndim) return "force_axis out of range";
     if (s.n_harm < 1) return "n_harm must be >= 1";
     p.faces.clear();
@@ -518,6 +529,27 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
             p.gather_of[{fi, c}] = (int)p.gathers.size();
             p.gathers.push_back(std::move(gt));
         }
+    if (p.bloch) {
+        // no interpolation point may lie across the Bloch-periodic x edge
+        // (its weight would need the phase): the unwrapped x index of every
+        // point must fall inside the grid
+        for (const Face& f : p.faces)
+            for (int c = 0; c < kNumComp; ++c)
+                for (int smp = 0; smp < f.nsamp; ++smp) {
+                    int s2;
+                    if (f.axis == 0) {
+                        s2 = 2 * f.plane;
+                    } else {
+                        const int t = f.ntang == 1 ? smp : (f.tang[0] == 0 ? smp / f.count[1] : smp % f.count[1]);
+                        const int k = f.tang[0] == 0 ? 0 : 1;
+                        s2 = 2 * (f.start[k] + t) + 1;
+                    }
+                    const int d = s2 - kOffset2[c][0];
+                    const int lo = (d % 2 + 2) % 2 == 0 ? d / 2 : (d - 1) / 2;
+                    const int hi = (d % 2 + 2) % 2 == 0 ? d / 2 : (d + 1) / 2;
+                    if (lo < 0 || hi >= p.nx) return "stress surface reaches across the Bloch-periodic x edge";
+                }
+    }
     return surface_medium(p);
 }
 

@@ -82,6 +82,8 @@ struct Problem {
     bool kz = false;                          // z-invariant problem at Bloch wavevectors k_z
     int m_max = 0;
     std::vector<double> kzs, kz_w;            // k_z points and weights
+    std::vector<double> kxs;                  // Bloch wavevector along x per point (k_z problems)
+    bool bloch = false;                       // complex fields: some kx != 0
     // reduced two-dimensional problems: six components, one run per order
     // (azimuthal order m, or k_z point q)
     bool reduced() const { return cyl || kz; }

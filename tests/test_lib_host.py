@@ -212,3 +212,37 @@ def test_kz_validation(cf):
         with pytest.raises(cf.CfError) as e:
             cf.Problem.from_workload(bad)
         assert e.value.status == "CF_E_ARG"
+
+
+def _grating(ncell=1, L=24, ny=30, s_lo=(6, 10, 0), s_hi=(18, 20, 1), bc=("periodic", "pec", "periodic")):
+    from casimir_inputs.geometry import Box, Workload, rasterize
+    big = 1e30
+    nx = L * ncell
+    prims = [Box((-big, -big, -big), (big, 4, big), 1)]
+    for c in range(ncell):
+        prims.append(Box((c * L + 8, 12, -big), (c * L + 16, 18, big), 2))
+    ids = rasterize((nx, ny, 1), prims)
+    return Workload(name="grating", ndim=2, shape=(nx, ny, 1), res=10.0, bc=bc, pml_cells=(0, 0, 0),
+                    eps=[1.0, float("-inf"), 4.0], mu=[1.0, 1.0, 1.0], comp_ids=ids, s_lo=s_lo, s_hi=s_hi,
+                    n_harm=4, force_axis=1, pol="3D", kernel="general", n_steps=200, sigma=1.0, courant=0.5)
+
+
+def test_bloch_problem_info_and_validation(cf):
+    wl = kz_workload(_grating(), [0.0, 0.9], [1.0, 1.0], kx=[0.4, 0.4])
+    p = cf.Problem.from_workload(wl)
+    info = p.info(pol="3D", kernel="general", n_steps=200)
+    assert info["n_comp"] == 12
+    real = cf.Problem.from_workload(kz_workload(_grating(), [0.0, 0.9], [1.0, 1.0]))
+    assert real.info(pol="3D", kernel="general", n_steps=200)["n_comp"] == 6
+    # the channel table does not depend on k_x
+    a = p.channel_table(pol="3D", kernel="general")
+    b = real.channel_table(pol="3D", kernel="general")
+    for key in a:
+        np.testing.assert_array_equal(a[key], b[key])
+    with pytest.raises(cf.CfError) as e:                     # Bloch x needs a periodic x axis
+        cf.Problem.from_workload(kz_workload(_grating(bc=("pec", "pec", "periodic")), [0.0], [1.0], kx=[0.3]))
+    assert e.value.status == "CF_E_ARG"
+    for lo, hi in (((0, 10, 0), (18, 20, 1)), ((6, 10, 0), (24, 20, 1))):   # S reaching across the x edge
+        with pytest.raises(cf.CfError) as e:
+            cf.Problem.from_workload(kz_workload(_grating(s_lo=lo, s_hi=hi), [0.0], [1.0], kx=[0.3]))
+        assert e.value.status == "CF_E_SURFACE"
