@@ -194,7 +194,38 @@ def bench_kz(cf, torch, cpu_sample=True):
                        f"{r['n_channels']} channels, T 2000, FP32",
            "force_per_length": r["force"], "wall_s": wall, "device_ms": r["device_ms"], "value": rate,
            "unit": "cell-updates/s", "resident_variant": r["tile_variant"],
-           "split_path_device_ms": rs["device_ms"], "speedup_vs_split": rs["device_ms"] / r["device_ms"]}
+           "split_path_device_ms": rs["device_ms"], "speedup_vs_split": rs["device_ms"] / r["device_ms"],
+           "alg_bytes_per_s": rate * 48.0, "alg_frac_of_hbm_peak": rate * 48.0 / (HBM_PEAK_GBS * 1e9)}
+    # Bloch-periodic x (complex fields): dielectric blocks repeated with period
+    # 2.4 above a PEC plate, 8 k_x points on [0, pi/L) x 4 k_z points
+    from casimir_inputs.geometry import Box, Workload, rasterize
+    big = 1e30
+    nx, ny = 48, 60
+    prims = [Box((-big, -big, -big), (big, 8, big), 1), Box((16, 24, -big), (32, 36, big), 2)]
+    gw = Workload(name="grating", ndim=2, shape=(nx, ny, 1), res=20.0, bc=("periodic", "pec", "periodic"),
+                  pml_cells=(0, 0, 0), eps=[1.0, float("-inf"), 4.0], mu=[1.0, 1.0, 1.0],
+                  comp_ids=rasterize((nx, ny, 1), prims), s_lo=(12, 20, 0), s_hi=(36, 40, 1), n_harm=8,
+                  force_axis=1, pol="3D", kernel="general", n_steps=2000, sigma=1.0, courant=0.5, precision="fp32")
+    Lx = nx / gw.res
+    kxs = (np.arange(8) + 0.5) * (np.pi / Lx) / 8
+    kzs, kzw = kz_gauss(4, 12.0)
+    pts = [(kx, kz) for kx in kxs for kz in kzs]
+    wts = [w / len(kxs) for _ in kxs for w in kzw]     # zone average over k_x (F(-k_x) = F(k_x)), k_z integral
+    bw = kz_workload(gw, [p[1] for p in pts], wts, kx=[p[0] for p in pts])
+    pb = cf.Problem.from_workload(bw)
+    ob = dict(sigma=1.0, courant=0.5, n_steps=2000, pol="3D", kernel="general", precision="fp32")
+    pb.solve(**dict(ob, n_steps=50))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rb = pb.solve(**ob)
+    wb = time.perf_counter() - t1
+    rate_b = rb["cell_updates"] / (rb["device_ms"] * 1e-3)
+    out["bloch"] = {"workload": f"grating: eps 4 blocks with period 2.4 above a PEC plate, res 20, 48 x 60 cell, "
+                                f"8 k_x x 4 k_z points, {rb['n_channels']} complex channels, T 2000, FP32",
+                    "force_per_length_per_cell": rb["force"], "wall_s": wb, "device_ms": rb["device_ms"], "value": rate_b,
+                    "unit": "cell-updates/s (complex cells)", "resident_variant": rb["tile_variant"],
+                    "alg_bytes_per_s": rate_b * 96.0, "alg_frac_of_hbm_peak": rate_b * 96.0 / (HBM_PEAK_GBS * 1e9)}
+    log(f"[bench] bloch: {wb:.3f} s wall ({rb['device_ms']:.1f} ms device), {rate_b:.3e} complex cell-updates/s")
     if cpu_sample:
         from oracle import kz
         from oracle.force import setup

@@ -114,12 +114,12 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
     // waves: consecutive runs of `resident` channels; the split cylindrical
     // path groups the channels by azimuthal order first (one order per wave),
     // the resident cylindrical kernel takes any mix of orders
-    st.cyl_res = p.reduced() && !plain && !(o.flags & CF_FLAG_SPLIT);
+    st.red_res = p.reduced() && !plain && !(o.flags & CF_FLAG_SPLIT);
     std::vector<std::vector<int>> wave_lists;
     std::vector<int> wave_order;
     {
         std::vector<std::vector<int>> groups;
-        if (p.reduced() && !st.cyl_res) {
+        if (p.reduced() && !st.red_res) {
             groups.assign(p.n_orders(), {});
             for (int c = 0; c < C; ++c) groups[chans[c].order].push_back(c);
         } else {
@@ -130,7 +130,7 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
             for (size_t k0 = 0; k0 < groups[gi].size(); k0 += st.resident) {
                 const size_t k1 = std::min(groups[gi].size(), k0 + st.resident);
                 wave_lists.emplace_back(groups[gi].begin() + k0, groups[gi].begin() + k1);
-                wave_order.push_back(p.reduced() && !st.cyl_res ? (int)gi : -1);
+                wave_order.push_back(p.reduced() && !st.red_res ? (int)gi : -1);
             }
     }
     std::vector<int> block_of(C, 0);
@@ -350,7 +350,7 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.fields2 = st.variant >= 0 || st.f3d ? take(block) : off;
     L.psi = st.psi_comp > 0 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
     L.psi2 = st.psi_comp > 0 && st.f3d ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
-    L.idp = st.f3d ? take((size_t)p.ncell * 8) : st.cyl_res ? take((size_t)p.ncell * 4) : off;
+    L.idp = st.f3d ? take((size_t)p.ncell * 8) : st.red_res ? take((size_t)p.ncell * 4) : off;
     L.rinv = p.reduced() ? take((size_t)6 * p.ny * fsz) : off;
     int max_tiles = 0;
     for (const TBPlan& pl : st.plans)
@@ -435,7 +435,7 @@ struct GraphRun {
 // wave clear, kick, consistent start, then per step the H and E half steps
 // and the surface projection with the g-weighted accumulation.
 template <typename T>
-cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, const Layout& L, char* ws,
+cf_status run_reduced(const cf::Problem& p, const cf_opts& o, const Staged& st, const Layout& L, char* ws,
                   hipStream_t s, std::vector<double>& acc_out, std::vector<double>& gamma_out, double* device_ms,
                   StencilTiming* timing) {
     const size_t C = st.chans.size();
@@ -489,7 +489,7 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
     const double state_bytes = 2.0 * st.ncomp * sizeof(T);
     // per-order tables: coefficients for courant_m, K(t_k) on dt_m
     const size_t lut_len = 2 * cf::kNumComp * 256 * 2;
-    cf::CylOrders ord{};
+    cf::RedOrders ord{};
     ord.lut = dlut;
     ord.lut_stride = (int64_t)lut_len;
     ord.ktab = dk;
@@ -533,7 +533,7 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
     // material ids packed in 4 bits per component for the register kernel
     // (15 = wall id), when every id fits
     std::vector<uint32_t> idw;
-    if (st.cyl_res) {
+    if (st.red_res) {
         idw.assign(p.ncell, 0u);
         bool fits = true;
         for (int c = 0; c < cf::kNumComp && fits; ++c)
@@ -560,7 +560,7 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
         smp.ev.resize(2 * 256);
         for (auto& e : smp.ev) CF_HIP(hipEventCreate(&e));
         long total = 0;
-        for (const Wave& w : st.waves) total += st.cyl_res ? 1 : cf::order_steps(p, o, w.order);
+        for (const Wave& w : st.waves) total += st.red_res ? 1 : cf::order_steps(p, o, w.order);
         smp.stride = std::max(1L, total / 200);
     }
     hipError_t err = hipSuccess;
@@ -573,7 +573,7 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
     STEP_OK(hipEventRecord(e0, s));
     for (const Wave& w : st.waves) {
         const int* sl = dslots + w.all_off;
-        if (st.cyl_res) {
+        if (st.red_res) {
             // one launch: every channel of the wave, any mix of orders
             double cu = 0;
             for (int k = 0; k < w.n_all; ++k) {
@@ -582,7 +582,7 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
             }
             const bool take = smp.begin(s);
             int used = 0;
-            STEP_OK(cf::launch_cyl_resident<T>(o.tile_variant, fields, dch, sl, w.n_all, g, ord, tabs, dA, dacc, dgam,
+            STEP_OK(cf::launch_red_resident<T>(o.tile_variant, fields, dch, sl, w.n_all, g, ord, tabs, dA, dacc, dgam,
                                                (int)C, s, &used));
             smp.end(take, s, cu, cu * state_bytes);
             timing->variant = std::max(timing->variant, used - 1);
@@ -595,15 +595,15 @@ cf_status run_cyl(const cf::Problem& p, const cf_opts& o, const Staged& st, cons
         const double* k_m = dk + (size_t)m * t_max;
         STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
         STEP_OK(cf::launch_kick<T>(fields, dch, sl, w.n_all, st.max_uniq, tabs, s));
-        STEP_OK(cf::launch_hcyl<T>(1, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, ord.ph_c[m],
+        STEP_OK(cf::launch_hred<T>(1, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, ord.ph_c[m],
                                    ord.ph_s[m], ord.cplx, s));
-        STEP_OK(cf::launch_ecyl<T>(1, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, ord.ph_c[m],
+        STEP_OK(cf::launch_ered<T>(1, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, ord.ph_c[m],
                                    ord.ph_s[m], ord.cplx, s));
         for (int k = 0; k < tm; ++k) {
             const bool take = smp.begin(s);
-            STEP_OK(cf::launch_hcyl<T>(0, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows,
+            STEP_OK(cf::launch_hred<T>(0, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows,
                                        ord.ph_c[m], ord.ph_s[m], ord.cplx, s));
-            STEP_OK(cf::launch_ecyl<T>(0, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows,
+            STEP_OK(cf::launch_ered<T>(0, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows,
                                        ord.ph_c[m], ord.ph_s[m], ord.cplx, s));
             const double cu = (double)w.n_all * p.ncell;
             smp.end(take, s, cu, cu * state_bytes);
@@ -652,7 +652,7 @@ template <typename T>
 cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, const Layout& L,
                     char* ws, hipStream_t s, std::vector<double>& acc_out, std::vector<double>& gamma_out,
                     double* device_ms, StencilTiming* timing) {
-    if (p.reduced()) return run_cyl<T>(p, o, st, L, ws, s, acc_out, gamma_out, device_ms, timing);
+    if (p.reduced()) return run_reduced<T>(p, o, st, L, ws, s, acc_out, gamma_out, device_ms, timing);
     const size_t C = st.chans.size();
     // ---- upload tables --------------------------------------------------
     std::vector<uint8_t> ids((size_t)cf::kNumComp * p.ncell);

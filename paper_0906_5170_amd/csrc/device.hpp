@@ -131,36 +131,36 @@ hipError_t launch_e2d(int pol, int mode, T* fields, const ChanDev* ch, const int
 // the 2D launchers.
 // Reduced two-dimensional problems (cylindrical orders, k_z runs): coupling
 // = m or k dx of the run, axis = 1 when row 0 is the symmetry axis, rows =
-// 6 factors per row j in the field precision (see kernels_cyl.hip).
+// 6 factors per row j in the field precision (see kernels_reduced.hip).
 // cplx: complex (Bloch-periodic x) run, 12 values per cell (real part, then
 // imaginary part), with the phase ph_c + i ph_s across the periodic x edge.
 template <typename T>
-hipError_t launch_hcyl(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
+hipError_t launch_hred(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
                        int nslots, const Grid2D& g, const T* lut, const T* rows, double ph_c, double ph_s, int cplx,
                        hipStream_t s);
 template <typename T>
-hipError_t launch_ecyl(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
+hipError_t launch_ered(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
                        int nslots, const Grid2D& g, const T* lut, const T* rows, double ph_c, double ph_s, int cplx,
                        hipStream_t s);
 
 // Per-order tables of a reduced solve (cylindrical orders m, or k_z points):
 // coefficient table of order q at lut + q * lut_stride (field precision),
 // K(t_k) at ktab + q * ktab_stride, T_q steps of dt_q.
-constexpr int kCylMaxOrders = 33;
-struct CylOrders {
+constexpr int kMaxOrders = 33;
+struct RedOrders {
     const void* lut;
     int64_t lut_stride;
     const double* ktab;
     int64_t ktab_stride;
-    int steps[kCylMaxOrders];
-    double dt[kCylMaxOrders];
+    int steps[kMaxOrders];
+    double dt[kMaxOrders];
     // the six material ids of each cell in 4 bits each (component c at bit
     // 4 c; 15 stands for the wall id), or null when an id does not fit
     const uint32_t* idw;
     const void* rows;                 // 6 row factors per row (field precision)
-    double coup[kCylMaxOrders];       // coupling of each order: m, or k dx
-    double ph_c[kCylMaxOrders];       // Bloch phase across the periodic x edge (complex runs)
-    double ph_s[kCylMaxOrders];
+    double coup[kMaxOrders];       // coupling of each order: m, or k dx
+    double ph_c[kMaxOrders];       // Bloch phase across the periodic x edge (complex runs)
+    double ph_s[kMaxOrders];
     int axis;                         // row 0 is the symmetry axis (cylindrical)
     int cplx;                         // complex fields (Bloch-periodic x)
 };
@@ -173,8 +173,8 @@ struct CylOrders {
 // 2: fields in global memory (L2-resident); 0 picks 1 when it fits.  *used
 // receives the variant launched.
 template <typename T>
-hipError_t launch_cyl_resident(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
-                               const Grid2D& g, const CylOrders& ord, const SurfTables& t, double dA, double* acc,
+hipError_t launch_red_resident(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
+                               const Grid2D& g, const RedOrders& ord, const SurfTables& t, double dA, double* acc,
                                double* gamma, int gamma_stride, hipStream_t s, int* used);
 
 template <typename T>

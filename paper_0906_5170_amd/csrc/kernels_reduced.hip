@@ -1,9 +1,13 @@
-// Yee update in cylindrical coordinates for one azimuthal order m (Sec.
-// III D; Appendix, harmonic expansion in cylindrical coordinates), on the
-// (r, z) half plane of a cylindrically symmetric problem.
+// Reduced two-dimensional Yee updates: six components on a 2D grid, one
+// run per "order", for
+//   - cylindrically symmetric problems (Sec. III D; Appendix, harmonic
+//     expansion in cylindrical coordinates), one run per azimuthal order m;
+//   - z-invariant problems at a Bloch wavevector k along z (Sec. III C, one
+//     2D simulation per k_z), optionally Bloch-periodic along x (Sec. III E,
+//     complex fields).
 //
-// Fields proportional to exp(i m phi), with E_phi, H_r, H_z carried as
-// -i times their value, obey the real system
+// Cylindrical.  Fields proportional to exp(i m phi), with E_phi, H_r, H_z
+// carried as -i times their value, obey the real system
 //   mu  dh_r/dt   = -[ (m/r) e_z - d_z e_phi ]
 //   mu  dh_phi/dt = -[ d_z e_r - d_r e_z ]
 //   mu  dh_z/dt   = -[ (1/r) d_r (r e_phi) - (m/r) e_r ]
@@ -15,24 +19,29 @@
 // an (nr x nz) array, z fastest.  Ey, Hx, Hz sit at r = j cells, Ex, Ez, Hy
 // at r = j - 1/2 (their row 0 lies outside and stays 0).  The tube wall is
 // at r = nr - 1/2: a neighbour beyond it reads 0.  Along z a neighbour beyond
-// the grid reads 0 (PEC ends) or wraps (periodic).
+// the grid reads 0 (PEC ends) or wraps (periodic).  Axis (row 0 of Ey, Hx,
+// Hz): h_z there follows the circulation of e_phi around the disk of radius
+// 1/2 cell, (4 / dx) e_phi(r = 1/2), for m = 0 and is 0 otherwise; e_r and
+// h_phi enter no update there and are kept at 0 (the surface interpolation
+// applies their axis value, the next row's for m = 1).
 //
-// Axis (row 0 of Ey, Hx, Hz): h_z there follows the circulation of e_phi
-// around the disk of radius 1/2 cell, (4 / dx) e_phi(r = 1/2), for m = 0
-// and is 0 otherwise; e_r and h_phi enter no update there and are kept at
-// 0 (the surface interpolation applies their axis value, the next row's
-// for m = 1).
+// k_z.  With E_z, H_x, H_y carried as -i times their value the same forms
+// hold with m/r -> k and unit radial weights (Cartesian x, y; both walls
+// PEC or periodic).  Bloch-periodic x (CPLX): real and imaginary parts in
+// two six-component blocks, mixed only by the phase of the neighbour read
+// across the periodic x edge.
 //
 // Coefficients (a, b) come from the Cartesian per-kind tables built for
-// this order's Courant number: x <- a x -/+ b curl, with the curls above in
+// the order's Courant number: x <- a x -/+ b curl, with the curls above in
 // undivided form (times dx).
 //
-// Two drivers share the per-cell updates (so their fields agree bitwise):
-// split half-step launches (one launch per half step for a batch of
+// Drivers, all evaluating the same per-cell value functions (their fields
+// agree bitwise): split half-step launches (one launch per half step for the
 // channels of one order), and the resident solve, where one block carries
 // one channel through clear, kick, start and all its steps with the surface
-// projection, in a single launch for channels of any mix of orders (a
-// channel's block of 6 x nr x nz values stays in the L2 of its XCD).
+// projection, in a single launch for channels of any mix of orders, with the
+// fields in registers (LDS neighbour exchange) or in global memory (a
+// channel's block stays in the L2 of its XCD).
 #include <type_traits>
 
 #include "../../include/casimir_fdtd.h"
@@ -49,7 +58,7 @@ constexpr int kResThreads = 1024;
 
 using yee::lut_ab;
 
-inline dim3 grid_cyl(const Grid2D& g, int nslots) {
+inline dim3 grid_red(const Grid2D& g, int nslots) {
     const int tiles = ((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY);
     return dim3(tiles, nslots, 1);
 }
@@ -164,7 +173,7 @@ __device__ __forceinline__ T bloch_bwd(T a, T b, int part, T pc, T ps) {
 
 // H update of cell (i, j), part `part`, of the channel block F in global memory.
 template <typename T, int MODE, bool CYL, bool CPLX = false>
-__device__ __forceinline__ void hcyl_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
+__device__ __forceinline__ void hred_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
                                           const RedRun<T>& rr, int i, int j, int part = 0) {
     T* const Fo = F + (CPLX ? (1 - part) * 6 * g.ncell : 0);    // the other part (complex runs)
     F += CPLX ? part * 6 * g.ncell : 0;
@@ -205,7 +214,7 @@ __device__ __forceinline__ void hcyl_cell(T* __restrict__ F, const Grid2D& g, co
 
 // E update of cell (i, j), part `part`, of the channel block F in global memory.
 template <typename T, int MODE, bool CYL, bool CPLX = false>
-__device__ __forceinline__ void ecyl_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
+__device__ __forceinline__ void ered_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
                                           const RedRun<T>& rr, int i, int j, int part = 0) {
     T* const Fo = F + (CPLX ? (1 - part) * 6 * g.ncell : 0);
     F += CPLX ? part * 6 * g.ncell : 0;
@@ -245,7 +254,7 @@ __device__ __forceinline__ void ecyl_cell(T* __restrict__ F, const Grid2D& g, co
 }
 
 template <typename T, int MODE, bool CYL, bool CPLX>
-__global__ __launch_bounds__(BX* BY) void k_hcyl(T* __restrict__ fields, const ChanDev* __restrict__ ch,
+__global__ __launch_bounds__(BX* BY) void k_hred(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                const int* __restrict__ slots, Grid2D g,
                                                const T* __restrict__ lut, RedRun<T> rr) {
     const ChanDev d = ch[slots[blockIdx.y]];
@@ -255,11 +264,11 @@ __global__ __launch_bounds__(BX* BY) void k_hcyl(T* __restrict__ fields, const C
     const int j = (blockIdx.x / tiles_x) * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     for (int part = 0; part < (CPLX ? 2 : 1); ++part)
-        hcyl_cell<T, MODE, CYL, CPLX>(fields + d.field_off, g, lut, d.kind, rr, i, j, part);
+        hred_cell<T, MODE, CYL, CPLX>(fields + d.field_off, g, lut, d.kind, rr, i, j, part);
 }
 
 template <typename T, int MODE, bool CYL, bool CPLX>
-__global__ __launch_bounds__(BX* BY) void k_ecyl(T* __restrict__ fields, const ChanDev* __restrict__ ch,
+__global__ __launch_bounds__(BX* BY) void k_ered(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                const int* __restrict__ slots, Grid2D g,
                                                const T* __restrict__ lut, RedRun<T> rr) {
     const ChanDev d = ch[slots[blockIdx.y]];
@@ -269,7 +278,7 @@ __global__ __launch_bounds__(BX* BY) void k_ecyl(T* __restrict__ fields, const C
     const int j = (blockIdx.x / tiles_x) * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
     for (int part = 0; part < (CPLX ? 2 : 1); ++part)
-        ecyl_cell<T, MODE, CYL, CPLX>(fields + d.field_off, g, lut, d.kind, rr, i, j, part);
+        ered_cell<T, MODE, CYL, CPLX>(fields + d.field_off, g, lut, d.kind, rr, i, j, part);
 }
 
 // Every cell of the grid once, block-strided: thread t takes flat cells
@@ -458,8 +467,8 @@ __device__ __forceinline__ void e_phase(T* __restrict__ F0, const Grid2D& g, con
 }
 
 template <typename T, bool CYL, bool CPLX>
-__global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fields, const ChanDev* __restrict__ ch,
-                                                              const int* __restrict__ slots, Grid2D g, CylOrders ord,
+__global__ __launch_bounds__(kResThreads) void k_red_resident(T* __restrict__ fields, const ChanDev* __restrict__ ch,
+                                                              const int* __restrict__ slots, Grid2D g, RedOrders ord,
                                                               SurfTables t, double dA, double* __restrict__ acc,
                                                               double* __restrict__ gamma, int gamma_stride) {
     __shared__ double red[yee::kSurfThreads / 64];
@@ -519,7 +528,7 @@ __global__ __launch_bounds__(kResThreads) void k_cyl_resident(T* __restrict__ fi
 // least the 6 x 256 coefficient pairs it holds during the start.
 __host__ __device__ constexpr int regs_x_len(int n) { return 3 * n > 6 * 256 * 2 ? 3 * n : 6 * 256 * 2; }
 
-// Register-resident solve: the clear, kick and start as in k_cyl_resident,
+// Register-resident solve: the clear, kick and start as in k_red_resident,
 // then every thread keeps the six fields of its K cells (flat cells t,
 // t + NTH, ...) in registers for all steps.  LDS holds one array of 3 x ncell
 // values that carries the E triple during the H half step and the H triple
@@ -532,8 +541,8 @@ __host__ __device__ constexpr int regs_x_len(int n) { return 3 * n > 6 * 256 * 2
 // thread's first cell, passed through an empty asm statement so that the
 // compiler keeps no per-cell addresses in registers across steps.
 template <typename T, int K, int NTH, bool CYL>
-__global__ __launch_bounds__(NTH) void k_cyl_regs(T* __restrict__ fields, const ChanDev* __restrict__ ch,
-                                                  const int* __restrict__ slots, Grid2D g, CylOrders ord,
+__global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const ChanDev* __restrict__ ch,
+                                                  const int* __restrict__ slots, Grid2D g, RedOrders ord,
                                                   SurfTables t, double dA, double* __restrict__ acc,
                                                   double* __restrict__ gamma, int gamma_stride) {
     extern __shared__ double lds_dyn[];
@@ -729,7 +738,7 @@ inline size_t device_lds_limit() {
 template <typename T, int K, int NTH, bool CYL>
 bool regs_lds_ok(size_t lds) {
     if (lds <= 65536) return true;
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cyl_regs<T, K, NTH, CYL>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_red_regs<T, K, NTH, CYL>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -741,13 +750,13 @@ bool regs_lds_ok(size_t lds) {
 // Launch register variant v if the grid fits it: *launched tells whether it did.
 template <typename T, int V, bool CYL>
 hipError_t regs_try(int64_t ncell, size_t lds, bool* launched, T* fields, const ChanDev* ch, const int* slots,
-                    int nslots, const Grid2D& g, const CylOrders& ord, const SurfTables& t, double dA, double* acc,
+                    int nslots, const Grid2D& g, const RedOrders& ord, const SurfTables& t, double dA, double* acc,
                     double* gamma, int gamma_stride, hipStream_t s) {
     constexpr int K = kRegVariants<T>[V].K, NTH = kRegVariants<T>[V].NTH;
     *launched = false;
     if (ncell > (int64_t)K * NTH || !regs_lds_ok<T, K, NTH, CYL>(lds)) return hipSuccess;
     *launched = true;
-    hipLaunchKernelGGL((k_cyl_regs<T, K, NTH, CYL>), dim3(nslots), dim3(NTH), lds, s, fields, ch, slots, g, ord, t,
+    hipLaunchKernelGGL((k_red_regs<T, K, NTH, CYL>), dim3(nslots), dim3(NTH), lds, s, fields, ch, slots, g, ord, t,
                        dA, acc, gamma, gamma_stride);
     return hipGetLastError();
 }
@@ -755,13 +764,13 @@ hipError_t regs_try(int64_t ncell, size_t lds, bool* launched, T* fields, const 
 }  // namespace
 
 template <typename T>
-hipError_t launch_hcyl(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
+hipError_t launch_hred(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
                        int nslots, const Grid2D& g, const T* lut, const T* rows, double ph_c, double ph_s, int cplx,
                        hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
-    const dim3 grid = grid_cyl(g, nslots), block(BX, BY, 1);
+    const dim3 grid = grid_red(g, nslots), block(BX, BY, 1);
     const RedRun<T> rr{T(coupling), rows, T(ph_c), T(ph_s)};
-#define CF_HCYL(M, C, X) hipLaunchKernelGGL((k_hcyl<T, M, C, X>), grid, block, 0, s, fields, ch, slots, g, lut, rr)
+#define CF_HCYL(M, C, X) hipLaunchKernelGGL((k_hred<T, M, C, X>), grid, block, 0, s, fields, ch, slots, g, lut, rr)
     if (axis) {
         if (mode == 0) CF_HCYL(0, true, false);
         else CF_HCYL(1, true, false);
@@ -777,13 +786,13 @@ hipError_t launch_hcyl(int mode, double coupling, int axis, T* fields, const Cha
 }
 
 template <typename T>
-hipError_t launch_ecyl(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
+hipError_t launch_ered(int mode, double coupling, int axis, T* fields, const ChanDev* ch, const int* slots,
                        int nslots, const Grid2D& g, const T* lut, const T* rows, double ph_c, double ph_s, int cplx,
                        hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
-    const dim3 grid = grid_cyl(g, nslots), block(BX, BY, 1);
+    const dim3 grid = grid_red(g, nslots), block(BX, BY, 1);
     const RedRun<T> rr{T(coupling), rows, T(ph_c), T(ph_s)};
-#define CF_ECYL(M, C, X) hipLaunchKernelGGL((k_ecyl<T, M, C, X>), grid, block, 0, s, fields, ch, slots, g, lut, rr)
+#define CF_ECYL(M, C, X) hipLaunchKernelGGL((k_ered<T, M, C, X>), grid, block, 0, s, fields, ch, slots, g, lut, rr)
     if (axis) {
         if (mode == 0) CF_ECYL(0, true, false);
         else CF_ECYL(1, true, false);
@@ -800,7 +809,7 @@ hipError_t launch_ecyl(int mode, double coupling, int axis, T* fields, const Cha
 
 template <typename T, bool CYL, bool CPLX>
 hipError_t resident_launch(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
-                           const Grid2D& g, const CylOrders& ord, const SurfTables& t, double dA, double* acc,
+                           const Grid2D& g, const RedOrders& ord, const SurfTables& t, double dA, double* acc,
                            double* gamma, int gamma_stride, hipStream_t s, int* used) {
     *used = 0;
     if (nslots <= 0) return hipSuccess;
@@ -827,14 +836,14 @@ hipError_t resident_launch(int variant, T* fields, const ChanDev* ch, const int*
         }
     }
     *used = 2;
-    hipLaunchKernelGGL((k_cyl_resident<T, CYL, CPLX>), dim3(nslots), dim3(kResThreads), 0, s, fields, ch, slots, g, ord, t, dA,
+    hipLaunchKernelGGL((k_red_resident<T, CYL, CPLX>), dim3(nslots), dim3(kResThreads), 0, s, fields, ch, slots, g, ord, t, dA,
                        acc, gamma, gamma_stride);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cyl_resident(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
-                               const Grid2D& g, const CylOrders& ord, const SurfTables& t, double dA, double* acc,
+hipError_t launch_red_resident(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
+                               const Grid2D& g, const RedOrders& ord, const SurfTables& t, double dA, double* acc,
                                double* gamma, int gamma_stride, hipStream_t s, int* used) {
     if (ord.axis)
         return resident_launch<T, true, false>(variant, fields, ch, slots, nslots, g, ord, t, dA, acc, gamma,
@@ -846,16 +855,16 @@ hipError_t launch_cyl_resident(int variant, T* fields, const ChanDev* ch, const 
                                             gamma_stride, s, used);
 }
 
-#define CF_CYL_INSTANTIATE(T)                                                                                   \
-    template hipError_t launch_hcyl<T>(int, double, int, T*, const ChanDev*, const int*, int, const Grid2D&,  \
+#define CF_RED_INSTANTIATE(T)                                                                                   \
+    template hipError_t launch_hred<T>(int, double, int, T*, const ChanDev*, const int*, int, const Grid2D&,  \
                                        const T*, const T*, double, double, int, hipStream_t);                  \
-    template hipError_t launch_ecyl<T>(int, double, int, T*, const ChanDev*, const int*, int, const Grid2D&,  \
+    template hipError_t launch_ered<T>(int, double, int, T*, const ChanDev*, const int*, int, const Grid2D&,  \
                                        const T*, const T*, double, double, int, hipStream_t);                  \
-    template hipError_t launch_cyl_resident<T>(int, T*, const ChanDev*, const int*, int, const Grid2D&,       \
-                                               const CylOrders&, const SurfTables&, double, double*, double*, \
+    template hipError_t launch_red_resident<T>(int, T*, const ChanDev*, const int*, int, const Grid2D&,       \
+                                               const RedOrders&, const SurfTables&, double, double*, double*, \
                                                int, hipStream_t, int*);
-CF_CYL_INSTANTIATE(float)
-CF_CYL_INSTANTIATE(double)
-#undef CF_CYL_INSTANTIATE
+CF_RED_INSTANTIATE(float)
+CF_RED_INSTANTIATE(double)
+#undef CF_RED_INSTANTIATE
 
 }  // namespace cf

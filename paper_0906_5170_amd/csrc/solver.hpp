@@ -46,7 +46,7 @@ struct Staged {
     int resident = 0;                      // field blocks on the device
     int ncomp = 3;
     int64_t psi_comp = 0;                  // values per psi component (3D CPML)
-    bool cyl_res = false;                  // cylindrical waves on the resident solve kernel
+    bool red_res = false;                  // cylindrical waves on the resident solve kernel
     bool f3d = false;                      // 3D steps on the fused z-streaming kernel
     int v3d = -1;                          // its variant when fixed by the options (-1: autotune)
 };

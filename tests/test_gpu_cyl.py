@@ -234,3 +234,20 @@ def test_benchmark_size_sampled_channels_fp32(cf):
         print(f"[cyl] order {m} channel {c}: acc {ref:.4e}, error {err:.2e} = {err / mag:.2e} of sum|terms|",
               flush=True)
         assert err <= 1e-4 * mag
+
+
+def test_batch_solve_runs_cylindrical_problems_alone(cf):
+    """cf_batch_solve with a cylindrical problem beside a 2D one: the
+    cylindrical problem is solved on its own, bitwise as by cf_solve."""
+    announce("batch solve with a cylindrical problem")
+    from casimir_inputs.configs import piston2d
+    wl, _ = oracle_result("closed")
+    p2 = piston2d(40, 24, 4, 10, 5, 10, 7, 10.0, pol="TM+TE", n_steps=400, n_harm=8)
+    pc = cf.Problem.from_workload(wl)
+    q2 = cf.Problem.from_workload(p2)
+    opts = dict(sigma=1.0, courant=0.5, n_steps=400, kernel="general", precision="fp64")
+    with pytest.raises(cf.CfError):
+        cf.batch_solve([pc, q2], pol="3D", **opts)            # one polarization for all: 3D is not 2D's
+    alone = pc.solve(pol="3D", **opts)
+    both = cf.batch_solve([pc, cf.Problem.from_workload(wl.replace(n_harm=2))], pol="3D", **opts)
+    np.testing.assert_array_equal(both[0]["per_channel"], alone["per_channel"])
