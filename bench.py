@@ -422,6 +422,34 @@ def bench_precision(cf, torch):
         res["c4"] = {"workload": f"192^3 sphere-plate, channels {ref['subset']}, T={ref['n_steps']}",
                      "fp32_channel_rel_err_max": float(err.max()),
                      "fp32_channel_rel_err": [float(e) for e in err]}
+    path = os.path.join(gdir, "cyl_piston_res40_oracle.json")
+    if os.path.exists(path):
+        from casimir_inputs import c_cyl_piston
+        ref = json.load(open(path))
+        wl = c_cyl_piston()
+        p = cf.Problem.from_workload(wl)
+        o = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol="3D", kernel=wl.kernel)
+        r32 = p.solve(precision="fp32", **o)
+        r64 = p.solve(precision="fp64", **o)
+        acc_ref = np.array(ref["per_channel"])
+        res["cylindrical"] = {"workload": "cylindrical piston res 40, n, m in {0, 1, 2}, T=10000",
+                              "fp32_force_rel_err": abs(r32["force"] / ref["force"] - 1),
+                              "fp64_force_rel_err": abs(r64["force"] / ref["force"] - 1),
+                              "fp32_channel_err_of_largest": float(np.max(np.abs(r32["per_channel"] - acc_ref))
+                                                                   / np.max(np.abs(acc_ref)))}
+    path = os.path.join(gdir, "kz_dielectric_piston_oracle.json")
+    if os.path.exists(path):
+        from casimir_inputs import dielectric_piston2d, kz_workload
+        ref = json.load(open(path))
+        base = dielectric_piston2d(80, 40, 10, 20, 10, 20, 15, 20.0, n_steps=2000, n_harm=16)
+        wl = kz_workload(base, ref["kz"], ref["kz_weight"])
+        p = cf.Problem.from_workload(wl)
+        o = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol="3D", kernel="general")
+        r32 = p.solve(precision="fp32", **o)
+        r64 = p.solve(precision="fp64", **o)
+        res["kz"] = {"workload": "k_z dielectric piston 80x40 res 20, 8 k points, T=2000",
+                     "fp32_force_rel_err": abs(r32["force"] / ref["force"] - 1),
+                     "fp64_force_rel_err": abs(r64["force"] / ref["force"] - 1)}
     log(f"[bench] precision: {json.dumps(res)}")
     return res
 

@@ -8,6 +8,8 @@ casimir_inputs; no value comes from the HIP library.
     python tests/golden/make_golden.py c4s     # 3D sphere-plate 192^3: 5 channels, 24 steps
     python tests/golden/make_golden.py c4f     # the same 5 channels over the full T = 6000
     python tests/golden/make_golden.py c3      # uneven piston set: members 0 and 23, full T
+    python tests/golden/make_golden.py cyl     # cylindrical piston res 40, n, m in {0, 1, 2}, full T
+    python tests/golden/make_golden.py kz      # k_z dielectric piston, 8 k points, full T
 """
 import json
 import os
@@ -82,6 +84,41 @@ def c3_members(workers=8):
         json.dump(out, f, indent=1)
 
 
+def cyl_piston_golden():
+    """The cylindrical piston force point of the benchmark (FP64 oracle,
+    every order and channel over its full step count)."""
+    from casimir_inputs import c_cyl_piston
+    from oracle import cylforce
+    wl = c_cyl_piston()
+    t0 = time.time()
+    r = cylforce.solve(wl, m_max=wl.m_max)
+    out = dict(workload=wl.name, shape=list(wl.shape), n_steps=wl.n_steps, m_max=wl.m_max, n_harm=wl.n_harm,
+               force=r.force, per_m={str(k): v for k, v in r.per_m.items()}, n_steps_m=r.n_steps_m,
+               per_channel=[float(v) for v in r.acc.reshape(-1)], oracle_seconds=time.time() - t0,
+               source="oracle.cylforce.solve (FP64 NumPy), written by tests/golden/make_golden.py")
+    with open(os.path.join(HERE, "cyl_piston_res40_oracle.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("cyl", r.force, f"{time.time() - t0:.1f}s")
+
+
+def kz_golden():
+    """The k_z dielectric piston of the benchmark (FP64 oracle, 8 k points)."""
+    from casimir_inputs import dielectric_piston2d, kz_gauss, kz_workload
+    from oracle import kz
+    base = dielectric_piston2d(80, 40, 10, 20, 10, 20, 15, 20.0, n_steps=2000, n_harm=16)
+    ks, ws = kz_gauss(8, 12.0)
+    wl = kz_workload(base, ks, ws)
+    t0 = time.time()
+    r = kz.solve(wl, ks, ws)
+    out = dict(workload=wl.name, shape=list(wl.shape), n_steps=wl.n_steps, kz=list(ks), kz_weight=list(ws),
+               force=r.force, per_k=r.per_k, per_channel=[float(v) for v in r.acc.reshape(-1)],
+               oracle_seconds=time.time() - t0,
+               source="oracle.kz.solve (FP64 NumPy), written by tests/golden/make_golden.py")
+    with open(os.path.join(HERE, "kz_dielectric_piston_oracle.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("kz", r.force, f"{time.time() - t0:.1f}s")
+
+
 def main(which, workers=8):
     fname, make = CASES[which]
     wl = make()
@@ -111,5 +148,9 @@ if __name__ == "__main__":
         c4_full()
     elif sys.argv[1] == "c3":
         c3_members()
+    elif sys.argv[1] == "cyl":
+        cyl_piston_golden()
+    elif sys.argv[1] == "kz":
+        kz_golden()
     else:
         main(sys.argv[1])

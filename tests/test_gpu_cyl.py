@@ -251,3 +251,33 @@ def test_batch_solve_runs_cylindrical_problems_alone(cf):
     alone = pc.solve(pol="3D", **opts)
     both = cf.batch_solve([pc, cf.Problem.from_workload(wl.replace(n_harm=2))], pol="3D", **opts)
     np.testing.assert_array_equal(both[0]["per_channel"], alone["per_channel"])
+
+
+def test_benchmark_force_point_vs_oracle_golden(cf):
+    """The whole res-40 force point against the FP64 oracle (stored by
+    tests/golden/make_golden.py): FP64 fields to 1e-9 of the term
+    magnitude; FP32 fields with FP64 accumulation to 1e-6 of the largest
+    channel per channel and 5e-3 relative on the force, whose channel terms
+    cancel by about four orders of magnitude in this geometry."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cyl_piston_res40_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("golden cyl_piston_res40_oracle.json not generated")
+    announce("cylindrical benchmark force point vs stored oracle")
+    ref = json.load(open(path))
+    wl = c_cyl_piston()
+    p = cf.Problem.from_workload(wl)
+    o = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol="3D", kernel=wl.kernel)
+    tab = p.channel_table(**o)
+    acc = np.array(ref["per_channel"])
+    mag = np.sum(np.abs(tab["sign"] * acc)) / np.pi
+    r64 = p.solve(precision="fp64", **o)
+    assert abs(r64["force"] - ref["force"]) <= 1e-9 * mag
+    r32 = p.solve(precision="fp32", **o)
+    ch = np.max(np.abs(r32["per_channel"] - acc)) / np.max(np.abs(acc))
+    rel = abs(r32["force"] / ref["force"] - 1)
+    print(f"[cyl] force point: fp32 force rel err {rel:.2e}, channel err {ch:.2e} of the largest, "
+          f"terms / |F| = {mag / abs(ref['force']):.1e}", flush=True)
+    assert ch <= 1e-6
+    assert rel <= 5e-3

@@ -119,3 +119,30 @@ def test_k_integral_equals_z_invariant_kernel_on_gpu(cf):
                                                  pol="TM+TE", kernel="zinv2d", precision="fp64")["force"]
     print(f"[kz] k integral {f_kz:.8f}, z-invariant kernel {f_2d:.8f}", flush=True)
     assert abs(f_kz / f_2d - 1) < 5e-4
+
+
+def test_benchmark_case_vs_oracle_golden(cf):
+    """The k_z dielectric piston of the benchmark (8 k points) against the
+    stored FP64 oracle: FP64 fields to 1e-9 of the term magnitude; FP32
+    fields to 1e-4 relative on the force."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "kz_dielectric_piston_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("golden kz_dielectric_piston_oracle.json not generated")
+    announce("k_z benchmark case vs stored oracle")
+    ref = json.load(open(path))
+    base = dielectric_piston2d(80, 40, 10, 20, 10, 20, 15, 20.0, n_steps=2000, n_harm=16)
+    wl = kz_workload(base, ref["kz"], ref["kz_weight"])
+    p = cf.Problem.from_workload(wl)
+    o = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol="3D", kernel="general")
+    tab = p.channel_table(**o)
+    acc = np.array(ref["per_channel"])
+    mag = np.sum(np.abs(tab["sign"] * acc)) / np.pi
+    r64 = p.solve(precision="fp64", **o)
+    assert abs(r64["force"] - ref["force"]) <= 1e-9 * mag
+    r32 = p.solve(precision="fp32", **o)
+    rel = abs(r32["force"] / ref["force"] - 1)
+    print(f"[kz] benchmark case: fp32 force rel err {rel:.2e}, terms / |F| = {mag / abs(ref['force']):.1e}",
+          flush=True)
+    assert rel <= 1e-4
