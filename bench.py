@@ -41,7 +41,7 @@ def kernel_source_hash():
     record only hold for the code they were taken on)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels2d.hip", "device.hpp"):
+    for name in ("kernels2d.hip", "device.hpp", "yee_common.hpp"):
         with open(os.path.join(ROOT, "paper_0906_5170_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -103,7 +103,7 @@ def bench_3d(cf, torch, n_chan=64, n_steps=200, variant=0):
     ceiling = HBM_PEAK_GBS * 1e9 / 48.0       # 48 B per 3D FP32 cell-update
     rate = r["cell_updates"] / dt
     sweep = []
-    for v in (range(0, 5) if not variant else ()):   # 0: split half-step kernels, 1..4: fused variants
+    for v in (range(0, 7) if not variant else ()):   # 0: split half-step kernels, 1..6: fused variants
         ov = dict(o, n_steps=60)
         ov.update(split=True) if v == 0 else ov.update(tile_variant=v)
         rv = p.solve(channel_subset=sub, time_stencil=True, **ov)

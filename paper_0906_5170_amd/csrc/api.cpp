@@ -53,7 +53,7 @@ bool g_tune_loaded = false;
 // Device workspace layout of one solve.
 struct Layout {
     size_t ids, lut, ktab, pml, chans, slots, gidx, gw, uidx, uoff, usamp, uw, basis, acc, gamma,
-        fields, fields2, psi, psi2, idp, rinv, inst, work, total;
+        fields, fields2, psi, psi2, idp, shadow, rinv, inst, work, total;
     size_t work_items;    // capacity of one work list
 };
 
@@ -199,6 +199,26 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         } else {
             for (int v = 0; v < nv; ++v) st.f3d = st.f3d || usable(v);
         }
+        if (st.f3d && !st.gidx.empty()) {
+            // bounding box of every surface stencil point (all gathers)
+            int lo[3] = {p.nx, p.ny, p.nz}, hi[3] = {-1, -1, -1};
+            for (int32_t ix : st.gidx) {
+                const int c[3] = {(int)(ix % p.nx), (int)((ix / p.nx) % p.ny), (int)(ix / ((int64_t)p.nx * p.ny))};
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = std::min(lo[a], c[a]);
+                    hi[a] = std::max(hi[a], c[a]);
+                }
+            }
+            cf::ShadowBox& b = st.sbox;
+            b.x0 = lo[0];
+            b.y0 = lo[1];
+            b.z0 = lo[2];
+            b.bnx = hi[0] - lo[0] + 1;
+            b.bny = hi[1] - lo[1] + 1;
+            b.bnz = hi[2] - lo[2] + 1;
+            b.vol = (int64_t)b.bnx * b.bny * b.bnz;
+        }
+        if (st.v3d >= 0 && cf::f3d_steps(st.v3d) == 2 && st.sbox.vol <= 0) st.v3d = cf::f3d_single(st.v3d);
     }
     if (!plain && p.grid.ndim == 2 && !(o.flags & CF_FLAG_SPLIT)) {
         cf::TBShape sh[cf::kMaxVariants];
@@ -351,6 +371,7 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.psi = st.psi_comp > 0 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
     L.psi2 = st.psi_comp > 0 && st.f3d ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
     L.idp = st.f3d ? take((size_t)p.ncell * 8) : st.red_res ? take((size_t)p.ncell * 4) : off;
+    L.shadow = st.f3d && st.sbox.vol > 0 ? take((size_t)st.resident * st.sbox.vol * fsz) : off;
     L.rinv = p.reduced() ? take((size_t)6 * p.ny * fsz) : off;
     int max_tiles = 0;
     for (const TBPlan& pl : st.plans)
@@ -876,7 +897,9 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     }
     timing->variant = variant;
     if (st.f3d && !st.waves.empty()) {
-        auto usable3 = [&](int v) { return v >= 0 && cf::f3d_usable<T>(v, g3); };
+        auto usable3 = [&](int v) {
+            return v >= 0 && cf::f3d_usable<T>(v, g3) && (cf::f3d_steps(v) == 1 || st.sbox.vol > 0);
+        };
         const Wave& w0 = st.waves[0];
         const std::string key = tune_key(p, o, 0, w0.n_3d) + " f3d";
         int cached;
@@ -891,17 +914,19 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             hipEvent_t t0, t1;
             STEP_OK(hipEventCreate(&t0));
             STEP_OK(hipEventCreate(&t1));
+            T* sh = reinterpret_cast<T*>(ws + L.shadow);
             for (int v = 0; v < cf::f3d_variants(); ++v) {
                 if (!usable3(v)) continue;
                 const int* sl = dslots + w0.d3_off;
-                STEP_OK(cf::launch_f3d<T>(v, dch, sl, w0.n_3d, g3, dlut, fields, fb, psi, pb, s));
+                STEP_OK(cf::launch_f3d<T>(v, dch, sl, w0.n_3d, g3, dlut, fields, fb, psi, pb, sh, st.sbox, s));
                 STEP_OK(hipEventRecord(t0, s));
                 for (int r = 0; r < 2; ++r)
-                    STEP_OK(cf::launch_f3d<T>(v, dch, sl, w0.n_3d, g3, dlut, fields, fb, psi, pb, s));
+                    STEP_OK(cf::launch_f3d<T>(v, dch, sl, w0.n_3d, g3, dlut, fields, fb, psi, pb, sh, st.sbox, s));
                 STEP_OK(hipEventRecord(t1, s));
                 STEP_OK(hipEventSynchronize(t1));
                 float ms = 0;
                 STEP_OK(hipEventElapsedTime(&ms, t0, t1));
+                ms /= (float)cf::f3d_steps(v);      // per time step
                 if (ms < best) {
                     best = ms;
                     v3 = v;
@@ -999,16 +1024,26 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             T* pa = psi;
             T* pb = psi ? reinterpret_cast<T*>(ws + L.psi2) : nullptr;
             if (pb) STEP_OK(hipMemsetAsync(pb, 0, psi_bytes, s));
-            for (int m = 0; m < o.n_steps; ++m) {
+            T* sh = reinterpret_cast<T*>(ws + L.shadow);
+            // a two-step variant takes steps in pairs (the surface of the first
+            // step of a pair is read from the shadow box); an odd last step
+            // runs on the single-step variant of the same band shape
+            for (int m = 0; m < o.n_steps;) {
+                const bool two = cf::f3d_steps(v3) == 2 && o.n_steps - m >= 2;
+                const int v = two || cf::f3d_steps(v3) == 1 ? v3 : cf::f3d_single(v3);
                 const bool take = smp.begin(s);
-                STEP_OK(cf::launch_f3d<T>(v3, dch, s_3d, w.n_3d, g3, dlut, fa, fb, pa, pb, s));
-                const double cu = (double)w.n_3d * p.ncell;
+                STEP_OK(cf::launch_f3d<T>(v, dch, s_3d, w.n_3d, g3, dlut, fa, fb, pa, pb, sh, st.sbox, s));
+                const double cu = (double)w.n_3d * p.ncell * (two ? 2 : 1);
                 smp.end(take, s, cu, cu * state_bytes);
-                STEP_OK(cf::launch_surface<T>(fb, dch, s_all, w.n_all, tabs, dk, m, dt, dA, dacc, dgam, (int)C,
+                if (two)
+                    STEP_OK(cf::launch_surface_box<T>(sh, st.sbox, g3, dch, s_all, w.n_all, tabs, dk, m, dt, dA, dacc,
+                                                      dgam, (int)C, s));
+                m += two ? 2 : 1;
+                STEP_OK(cf::launch_surface<T>(fb, dch, s_all, w.n_all, tabs, dk, m - 1, dt, dA, dacc, dgam, (int)C,
                                               s));
                 std::swap(fa, fb);
                 std::swap(pa, pb);
-                if (converged(m + 1)) break;
+                if (converged(m)) break;
             }
         } else {
             for (int m = 0; m < o.n_steps; ++m) {

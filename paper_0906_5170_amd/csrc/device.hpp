@@ -200,14 +200,37 @@ hipError_t launch_e3d(int mode, T* fields, T* psi, const ChanDev* ch, const int*
 // every item advances its channel by min(kmax, remaining steps of its
 // instance) steps starting at launch-clock step m, between its instance's
 // two field buffers in the direction given by parity.
-// Fused 3D step (one full step per launch, z-streaming; reads src, writes
-// dst, CPML psi likewise).  Usable for nx <= 256, z walls PEC or CPML.
+// Box of grid cells that holds every surface stencil point of a 3D solve:
+// x0 .. x0 + bnx - 1 (likewise y, z), vol = bnx bny bnz.  A two-step fused
+// 3D launch stores there the measured component of every channel after the
+// first of its two steps: the channel whose field block is b (field_off =
+// 6 ncell b) at shadow + b vol, cell (x, y, z) at
+// ((z - z0) bny + (y - y0)) bnx + (x - x0).
+struct ShadowBox {
+    int x0, y0, z0, bnx, bny, bnz;
+    int64_t vol;
+};
+
+// Fused 3D step (z-streaming; reads src, writes dst, CPML psi likewise).
+// Usable for nx <= 256, z walls PEC or CPML.  f3d_steps(variant) time steps
+// per launch: 1, or 2 for the two-step variants, which also fill `shadow`
+// (see ShadowBox); a single-step launch ignores shadow.  f3d_single(v) is
+// the single-step variant of the same band shape.
 int f3d_variants();
+int f3d_steps(int variant);
+int f3d_single(int variant);
 template <typename T>
 bool f3d_usable(int variant, const Grid3D& g);
 template <typename T>
 hipError_t launch_f3d(int variant, const ChanDev* ch, const int* slots, int nslots, const Grid3D& g, const T* lut,
-                      const T* src, T* dst, const T* psrc, T* pdst, hipStream_t s);
+                      const T* src, T* dst, const T* psrc, T* pdst, T* shadow, const ShadowBox& sb,
+                      hipStream_t s);
+// Surface projection and accumulation of step m (as launch_surface) reading
+// the measured component from the shadow box of a two-step launch.
+template <typename T>
+hipError_t launch_surface_box(const T* shadow, const ShadowBox& sb, const Grid3D& g, const ChanDev* ch,
+                              const int* slots, int nslots, const SurfTables& t, const double* ktab, int m,
+                              double dt, double dA, double* acc, double* gamma, int gamma_stride, hipStream_t s);
 
 template <typename T>
 hipError_t launch_tb2d(int variant, int pol, const ChanDev* ch, const WorkItem* work, int nwork,

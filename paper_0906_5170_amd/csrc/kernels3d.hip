@@ -515,11 +515,465 @@ __global__ __launch_bounds__(64 * W) void k_f3d(const ChanDev* __restrict__ ch, 
     }
 }
 
-// Fused 3D variants: W waves of B rows (band = W B - 2 stored rows).
+// ---------------------------------------------------------------------------
+// Two-step fused 3D kernel: one launch takes a wave of channels from step n
+// to step n + 2 in a single z march.  Iteration k advances plane k to step
+// n + 1 (level 1: the single-step kernel's plane update) and then plane
+// k - 1 to step n + 2 (level 2), which needs level-1 values of planes k - 1
+// and k only; level-1 values stay in registers.  The region has two halo
+// rows below and two above the band (each level uses up one row on either
+// side), so band = W B - 4.  Level 2 keeps E(k-1), H(k-1) and the new
+// Hx, Hy of plane k - 2; the CPML psi of a layer plane goes from level 1 to
+// level 2 in registers and only level 2 writes psi.
+//
+// The surface projection of step n + 1 needs level-1 values: each block
+// stores the measured component of its channel for the cells of its band
+// that lie in the surface box `sb` (see ShadowBox).
+//
+// A z chunk z0 .. z1-1 starts level 1 at z0 - 2 and level 2 at z0 - 1 (the
+// level-2 plane z0 - 1 gives only the H values E(z0) needs), so that a
+// chunk stores exactly its own planes.  Below plane 0 and above nz - 1 the
+// fields are 0 (PEC or CPML walls), as in the single-step kernel.
+//
+// Every level half writes its LDS row and passes its barrier even when its
+// arithmetic is skipped (chunk edges), so the four exchanges of an iteration
+// alternate between the two row buffers and every write is separated from
+// the previous reads of that buffer by a barrier.  The arithmetic of every
+// cell is that of k_h3d followed by k_e3d, twice.
+template <typename T, int W, int B, int CX>
+__global__ __launch_bounds__(64 * W) void k_f3d2(const ChanDev* __restrict__ ch, const int* __restrict__ slots,
+                                                  Grid3D g, const T* __restrict__ lut, const T* __restrict__ src,
+                                                  T* __restrict__ dst, const T* __restrict__ psrc,
+                                                  T* __restrict__ pdst, T* __restrict__ shadow, ShadowBox sb,
+                                                  int band) {
+    constexpr int NTB = 64 * W;
+    __shared__ yee::Pair<T> L[6][256];
+    __shared__ T xe[W][2][CX][64];     // first region row of each wave: Ez, Ex (read by the wave below)
+    __shared__ T xh[W][2][CX][64];     // last region row of each wave: Hz, Hx (read by the wave above)
+    __shared__ T Lz[4][2 * kF3MaxPml];
+    const ChanDev d = ch[slots[blockIdx.y]];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int yb = blockIdx.x * band - 2;            // global y of region row 0
+    for (int i = threadIdx.x; i < 6 * 256; i += NTB) {
+        const int comp = i >> 8, id = i & 255;
+        const T* p = lut_ab(lut, d.kind, comp, id);
+        L[comp][id].a = p[0];
+        L[comp][id].b = p[1];
+    }
+    for (int i = threadIdx.x; i < 2 * g.pml; i += NTB) {
+        const int kz = i < g.pml ? i : g.nz - 2 * g.pml + i;
+        Lz[0][i] = (T)g.pml_bh[kz];
+        Lz[1][i] = (T)g.pml_ch[kz];
+        Lz[2][i] = (T)g.pml_be[kz];
+        Lz[3][i] = (T)g.pml_ce[kz];
+    }
+    const int64_t n = g.ncell, sz = (int64_t)g.nx * g.ny;
+    const T* __restrict__ S = src + d.field_off;
+    T* __restrict__ D = dst + d.field_off;
+    T* __restrict__ SH = shadow + (d.field_off / (6 * n)) * sb.vol;
+    int64_t rowoff[B], sbrow[B];
+    bool rin[B], rst[B], sbr[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+        const int ry = w * B + r;
+        int y = yb + ry;
+        bool in = true;
+        if (y < 0 || y >= g.ny) {
+            if (g.per[1]) y = ((y % g.ny) + g.ny) % g.ny;
+            else in = false;
+        }
+        rin[r] = in;
+        rowoff[r] = (int64_t)y * g.nx;
+        rst[r] = in && ry >= 2 && ry < 2 + band && yb + ry < g.ny;   // stored (interior) row
+        sbr[r] = rst[r] && y >= sb.y0 && y < sb.y0 + sb.bny;
+        sbrow[r] = (int64_t)(y - sb.y0) * sb.bnx;
+    }
+    bool cin[CX], sbc[CX];
+#pragma unroll
+    for (int j = 0; j < CX; ++j) {
+        const int x = j * 64 + lane;
+        cin[j] = x < g.nx;
+        sbc[j] = cin[j] && x >= sb.x0 && x < sb.x0 + sb.bnx;
+    }
+    const bool perx = g.per[0] != 0;
+    const int lastj = (g.nx - 1) / 64, lastl = (g.nx - 1) % 64;
+    const bool T_PSI = g.pml > 0 && psrc != nullptr;
+    const int ms = d.meas_slot;
+
+    const int zc = (g.nz + (int)gridDim.z - 1) / (int)gridDim.z;
+    const int z0 = blockIdx.z * zc, z1 = min(g.nz, z0 + zc);
+    if (z0 >= z1) return;                          // whole block: before any barrier
+    const int kb = max(z0 - 2, 0);                 // first level-1 plane
+    const int p0 = z0 > 0 ? z0 - 1 : 0;            // first level-2 plane
+    bool vc[B][CX];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int j = 0; j < CX; ++j) vc[r][j] = rin[r] && cin[j];
+    auto raw3 = [&](int k, int comp0, T (&a)[B][CX], T (&b)[B][CX], T (&c)[B][CX]) {
+        const int64_t pk = (int64_t)min(max(k, 0), g.nz - 1) * sz;
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                const int64_t at = comp0 * n + (vc[r][j] ? pk + rowoff[r] + j * 64 + lane : 0);
+                a[r][j] = S[at];
+                b[r][j] = S[n + at];
+                c[r][j] = S[2 * n + at];
+            }
+    };
+    auto raw_ids = [&](int k, uint2 (&id)[B][CX]) {
+        const int64_t pk = (int64_t)min(max(k, 0), g.nz - 1) * sz;
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int j = 0; j < CX; ++j)
+                id[r][j] = g.idp[vc[r][j] ? pk + rowoff[r] + j * 64 + lane : 0];
+    };
+    auto mask3 = [&](bool kin, T (&a)[B][CX], T (&b)[B][CX], T (&c)[B][CX]) {
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                const bool v = kin && vc[r][j];
+                a[r][j] = v ? a[r][j] : T(0);
+                b[r][j] = v ? b[r][j] : T(0);
+                c[r][j] = v ? c[r][j] : T(0);
+            }
+    };
+    constexpr uint32_t kNull4 = 0x01010101u * kNullId, kNull2 = 0x0101u * kNullId;
+
+    // H half on one plane: H <- a H - b curl E from E of the plane, Ex, Ey of
+    // the next plane (En*) and the x+1 / y+1 neighbours; in a layer plane the
+    // z differences carry psi (P0 for Hx, P1 for Hy), advanced in place.
+    auto h_half = [&](bool active, const T (&Ex)[B][CX], const T (&Ey)[B][CX], const T (&Ez)[B][CX],
+                      const T (&Enx)[B][CX], const T (&Eny)[B][CX], T (&Hx)[B][CX], T (&Hy)[B][CX],
+                      T (&Hz)[B][CX], const uint32_t (&I0)[B][CX], const uint32_t (&I1)[B][CX], T (&P0)[B][CX],
+                      T (&P1)[B][CX], bool zp, T bh, T chh) {
+#pragma unroll
+        for (int j = 0; j < CX; ++j) {
+            xe[w][0][j][lane] = Ez[0][j];
+            xe[w][1][j][lane] = Ex[0][j];
+        }
+        __syncthreads();
+        if (!active) return;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            T nez[CX], ney[CX];
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                const T a = yee::from_next(Ez[r][j]), b = yee::from_next(Ey[r][j]);
+                const T a1 = j + 1 < CX ? yee::lane_value(Ez[r][(j + 1) % CX], 0) : T(0);
+                const T b1 = j + 1 < CX ? yee::lane_value(Ey[r][(j + 1) % CX], 0) : T(0);
+                nez[j] = lane == 63 ? a1 : a;
+                ney[j] = lane == 63 ? b1 : b;
+            }
+            const T fez = yee::lane_value(Ez[r][0], 0), fey = yee::lane_value(Ey[r][0], 0);
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                T ez_y, ex_y;
+                if (r + 1 < B) {
+                    ez_y = Ez[(r + 1) % B][j];
+                    ex_y = Ex[(r + 1) % B][j];
+                } else if (w + 1 < W) {
+                    ez_y = xe[(w + 1) % W][0][j][lane];
+                    ex_y = xe[(w + 1) % W][1][j][lane];
+                } else {
+                    ez_y = T(0);   // last region row: halo, never stored
+                    ex_y = T(0);
+                }
+                T ez_x = nez[j];
+                T ey_x = ney[j];
+                if (j * 64 + lane == g.nx - 1) {
+                    ez_x = perx ? fez : T(0);
+                    ey_x = perx ? fey : T(0);
+                }
+                T dzEy = Eny[r][j] - Ey[r][j];
+                T dzEx = Enx[r][j] - Ex[r][j];
+                if (zp && vc[r][j]) {
+                    const T q0 = fma(bh, P0[r][j], chh * dzEy);
+                    const T q1 = fma(bh, P1[r][j], chh * dzEx);
+                    P0[r][j] = q0;
+                    P1[r][j] = q1;
+                    dzEy = dzEy + q0;
+                    dzEx = dzEx + q1;
+                }
+                const T curl_x = (ez_y - Ez[r][j]) - dzEy;
+                const T curl_y = dzEx - (ez_x - Ez[r][j]);
+                const T curl_z = (ey_x - Ey[r][j]) - (ex_y - Ex[r][j]);
+                const yee::Pair<T> cx = L[CF_HX][I0[r][j] >> 24];
+                const yee::Pair<T> cy = L[CF_HY][I1[r][j] & 255u];
+                const yee::Pair<T> cz = L[CF_HZ][(I1[r][j] >> 8) & 255u];
+                const bool v = vc[r][j];
+                Hx[r][j] = v ? yee_sub(cx.a, Hx[r][j], cx.b, curl_x) : T(0);
+                Hy[r][j] = v ? yee_sub(cy.a, Hy[r][j], cy.b, curl_y) : T(0);
+                Hz[r][j] = v ? yee_sub(cz.a, Hz[r][j], cz.b, curl_z) : T(0);
+            }
+        }
+    };
+    // E half on one plane: E <- a E + b curl H from H of the plane, Hx, Hy of
+    // the previous plane (Hp*) and the x-1 / y-1 neighbours; psi P2 (Ex), P3
+    // (Ey) in a layer plane.
+    auto e_half = [&](bool active, T (&Ex)[B][CX], T (&Ey)[B][CX], T (&Ez)[B][CX], const T (&Hx)[B][CX],
+                      const T (&Hy)[B][CX], const T (&Hz)[B][CX], const T (&Hpx)[B][CX], const T (&Hpy)[B][CX],
+                      const uint32_t (&I0)[B][CX], T (&P2)[B][CX], T (&P3)[B][CX], bool zp, T be, T ce) {
+#pragma unroll
+        for (int j = 0; j < CX; ++j) {
+            xh[w][0][j][lane] = Hz[B - 1][j];
+            xh[w][1][j][lane] = Hx[B - 1][j];
+        }
+        __syncthreads();
+        if (!active) return;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            T phz[CX], phy[CX];
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                const T a = yee::from_prev(Hz[r][j]), b = yee::from_prev(Hy[r][j]);
+                const T a1 = j > 0 ? yee::lane_value(Hz[r][(j + CX - 1) % CX], 63) : T(0);
+                const T b1 = j > 0 ? yee::lane_value(Hy[r][(j + CX - 1) % CX], 63) : T(0);
+                phz[j] = lane == 0 ? a1 : a;
+                phy[j] = lane == 0 ? b1 : b;
+            }
+            T lhz = Hz[r][0], lhy = Hy[r][0];
+#pragma unroll
+            for (int j = 1; j < CX; ++j)
+                if (lastj == j) {
+                    lhz = Hz[r][j];
+                    lhy = Hy[r][j];
+                }
+            lhz = yee::lane_value(lhz, lastl);
+            lhy = yee::lane_value(lhy, lastl);
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                T hz_y, hx_y;
+                if (r > 0) {
+                    hz_y = Hz[(r + B - 1) % B][j];
+                    hx_y = Hx[(r + B - 1) % B][j];
+                } else if (w > 0) {
+                    hz_y = xh[(w + W - 1) % W][0][j][lane];
+                    hx_y = xh[(w + W - 1) % W][1][j][lane];
+                } else {
+                    hz_y = T(0);   // region row 0: halo, never stored
+                    hx_y = T(0);
+                }
+                T hz_x = phz[j];
+                T hy_x = phy[j];
+                if (j * 64 + lane == 0) {
+                    hz_x = perx ? lhz : T(0);
+                    hy_x = perx ? lhy : T(0);
+                }
+                T dzHy = Hy[r][j] - Hpy[r][j];
+                T dzHx = Hx[r][j] - Hpx[r][j];
+                if (zp && vc[r][j]) {
+                    const T q2 = fma(be, P2[r][j], ce * dzHy);
+                    const T q3 = fma(be, P3[r][j], ce * dzHx);
+                    P2[r][j] = q2;
+                    P3[r][j] = q3;
+                    dzHy = dzHy + q2;
+                    dzHx = dzHx + q3;
+                }
+                const T curl_x = (Hz[r][j] - hz_y) - dzHy;
+                const T curl_y = dzHx - (Hz[r][j] - hz_x);
+                const T curl_z = (Hy[r][j] - hy_x) - (Hx[r][j] - hx_y);
+                const yee::Pair<T> cx = L[CF_EX][I0[r][j] & 255u];
+                const yee::Pair<T> cy = L[CF_EY][(I0[r][j] >> 8) & 255u];
+                const yee::Pair<T> cz = L[CF_EZ][(I0[r][j] >> 16) & 255u];
+                Ex[r][j] = yee_add(cx.a, Ex[r][j], cx.b, curl_x);
+                Ey[r][j] = yee_add(cy.a, Ey[r][j], cy.b, curl_y);
+                Ez[r][j] = yee_add(cz.a, Ez[r][j], cz.b, curl_z);
+            }
+        }
+    };
+
+    T ex[B][CX], ey[B][CX], ez[B][CX];       // level 1: E(k), step n, then n + 1
+    T ex1[B][CX], ey1[B][CX], ez1[B][CX];    // E(k+1), step n
+    T hx[B][CX], hy[B][CX], hz[B][CX];       // H(k), step n, then n + 1
+    uint32_t id0[B][CX], id1[B][CX];         // material ids of plane k (Ex Ey Ez Hx | Hy Hz)
+    T fx[B][CX], fy[B][CX], fz[B][CX];       // level 2: E(k-1), step n + 1, then n + 2
+    T gx[B][CX], gy[B][CX], gz[B][CX];       // H(k-1), step n + 1, then n + 2
+    T qx[B][CX], qy[B][CX];                  // Hx, Hy of plane k-2 at step n + 2
+    uint32_t jd0[B][CX], jd1[B][CX];         // material ids of plane k-1
+    T pc[4][B][CX];                          // psi of plane k-1 after step n + 1 (layer planes)
+    {
+        uint2 i2[B][CX];
+        raw3(kb, 0, ex, ey, ez);
+        raw3(kb + 1, 0, ex1, ey1, ez1);
+        raw3(kb, 3, hx, hy, hz);
+        raw_ids(kb, i2);
+        mask3(true, ex, ey, ez);
+        mask3(kb + 1 < g.nz, ex1, ey1, ez1);
+        mask3(true, hx, hy, hz);
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                id0[r][j] = vc[r][j] ? i2[r][j].x : kNull4;
+                id1[r][j] = vc[r][j] ? i2[r][j].y : kNull2;
+                fx[r][j] = fy[r][j] = fz[r][j] = T(0);
+                gx[r][j] = gy[r][j] = gz[r][j] = T(0);
+                qx[r][j] = qy[r][j] = T(0);
+                jd0[r][j] = kNull4;
+                jd1[r][j] = kNull2;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pc[q][r][j] = T(0);
+            }
+    }
+    __syncthreads();   // coefficient tables
+
+    for (int k = kb; k <= z1; ++k) {
+        const int p = k - 1;
+        const bool l1 = k < g.nz;                  // uniform over the block
+        const bool l2 = p >= p0;
+        const bool l2e = p >= z0;                  // level-2 E half and the stores
+        const int plane1 = l1 ? pml_plane(k, g.nz, g.pml) : -1;
+        const int plane2 = l2 ? pml_plane(p, g.nz, g.pml) : -1;
+        const bool zp1 = T_PSI && plane1 >= 0, zp2 = T_PSI && plane2 >= 0;
+        const T bh1 = zp1 ? Lz[0][plane1] : T(1), ch1 = zp1 ? Lz[1][plane1] : T(0);
+        const T be1 = zp1 ? Lz[2][plane1] : T(1), ce1 = zp1 ? Lz[3][plane1] : T(0);
+        const T bh2 = zp2 ? Lz[0][plane2] : T(1), ch2 = zp2 ? Lz[1][plane2] : T(0);
+        const T be2 = zp2 ? Lz[2][plane2] : T(1), ce2 = zp2 ? Lz[3][plane2] : T(0);
+        // psi of plane k at step n (layer planes), loaded before the prefetch
+        T ps[4][B][CX];
+        if (zp1) {
+            const int64_t pp = (int64_t)plane1 * sz;
+#pragma unroll
+            for (int r = 0; r < B; ++r)
+#pragma unroll
+                for (int j = 0; j < CX; ++j) {
+                    const int64_t pa = d.psi_off + (vc[r][j] ? pp + rowoff[r] + j * 64 + lane : 0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) ps[q][r][j] = psrc[pa + q * g.psi_comp];
+                }
+        }
+        // next plane's inputs, issued before this plane's arithmetic
+        T ex2[B][CX], ey2[B][CX], ez2[B][CX];
+        T hxn[B][CX], hyn[B][CX], hzn[B][CX];
+        uint2 idn[B][CX];
+        raw3(k + 2, 0, ex2, ey2, ez2);
+        raw3(k + 1, 3, hxn, hyn, hzn);
+        raw_ids(k + 1, idn);
+
+        // ---- level 1 on plane k (step n -> n + 1) ----
+        h_half(l1, ex, ey, ez, ex1, ey1, hx, hy, hz, id0, id1, ps[0], ps[1], zp1, bh1, ch1);
+        e_half(l1, ex, ey, ez, hx, hy, hz, gx, gy, id0, ps[2], ps[3], zp1, be1, ce1);
+        if (!l1) {
+#pragma unroll
+            for (int r = 0; r < B; ++r)
+#pragma unroll
+                for (int j = 0; j < CX; ++j) ex[r][j] = ey[r][j] = ez[r][j] = T(0);   // beyond the top wall
+        }
+        if (l1 && k >= z0 && k < z1 && k >= sb.z0 && k < sb.z0 + sb.bnz) {
+            const int64_t zo = (int64_t)(k - sb.z0) * sb.bny * sb.bnx - sb.x0;
+#pragma unroll
+            for (int r = 0; r < B; ++r)
+#pragma unroll
+                for (int j = 0; j < CX; ++j)
+                    if (sbr[r] && sbc[j]) {
+                        const T v = ms == 0 ? ex[r][j]
+                                  : ms == 1 ? ey[r][j]
+                                  : ms == 2 ? ez[r][j]
+                                  : ms == 3 ? hx[r][j]
+                                  : ms == 4 ? hy[r][j] : hz[r][j];
+                        SH[zo + sbrow[r] + j * 64 + lane] = v;
+                    }
+        }
+
+        // ---- level 2 on plane k - 1 (step n + 1 -> n + 2) ----
+        h_half(l2, fx, fy, fz, ex, ey, gx, gy, gz, jd0, jd1, pc[0], pc[1], zp2, bh2, ch2);
+        e_half(l2e, fx, fy, fz, gx, gy, gz, qx, qy, jd0, pc[2], pc[3], zp2, be2, ce2);
+        if (l2e) {
+            const int64_t pk = (int64_t)p * sz;
+            const int64_t pp = (int64_t)plane2 * sz;
+#pragma unroll
+            for (int r = 0; r < B; ++r)
+#pragma unroll
+                for (int j = 0; j < CX; ++j) {
+                    if (!rst[r] || !cin[j]) continue;
+                    const int64_t at = pk + rowoff[r] + j * 64 + lane;
+                    D[at] = fx[r][j];
+                    D[n + at] = fy[r][j];
+                    D[2 * n + at] = fz[r][j];
+                    D[3 * n + at] = gx[r][j];
+                    D[4 * n + at] = gy[r][j];
+                    D[5 * n + at] = gz[r][j];
+                    if (zp2) {
+                        const int64_t pa = d.psi_off + pp + rowoff[r] + j * 64 + lane;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) pdst[pa + q * g.psi_comp] = pc[q][r][j];
+                    }
+                }
+        }
+
+        // ---- rotate ----
+        mask3(k + 2 < g.nz, ex2, ey2, ez2);
+        mask3(k + 1 < g.nz, hxn, hyn, hzn);
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int j = 0; j < CX; ++j) {
+                qx[r][j] = gx[r][j];
+                qy[r][j] = gy[r][j];
+                fx[r][j] = ex[r][j];
+                fy[r][j] = ey[r][j];
+                fz[r][j] = ez[r][j];
+                gx[r][j] = hx[r][j];
+                gy[r][j] = hy[r][j];
+                gz[r][j] = hz[r][j];
+                jd0[r][j] = id0[r][j];
+                jd1[r][j] = id1[r][j];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pc[q][r][j] = ps[q][r][j];
+                ex[r][j] = ex1[r][j];
+                ey[r][j] = ey1[r][j];
+                ez[r][j] = ez1[r][j];
+                ex1[r][j] = ex2[r][j];
+                ey1[r][j] = ey2[r][j];
+                ez1[r][j] = ez2[r][j];
+                hx[r][j] = hxn[r][j];
+                hy[r][j] = hyn[r][j];
+                hz[r][j] = hzn[r][j];
+                const bool v = vc[r][j] && k + 1 < g.nz;
+                id0[r][j] = v ? idn[r][j].x : kNull4;
+                id1[r][j] = v ? idn[r][j].y : kNull2;
+            }
+    }
+}
+
+// Surface projection of step m from the shadow box of a two-step launch.
+template <typename T>
+__global__ __launch_bounds__(yee::kSurfThreads) void k_surface_box(
+    const T* __restrict__ shadow, ShadowBox sb, int nx, int ny, int64_t block_elems,
+    const ChanDev* __restrict__ ch, const int* __restrict__ slots, SurfTables t, const double* __restrict__ ktab,
+    int m, double dt, double dA, double* __restrict__ acc, double* __restrict__ gamma, int gamma_stride) {
+    __shared__ double red[yee::kSurfThreads / 64];
+    const int slot = slots[blockIdx.x];
+    const ChanDev d = ch[slot];
+    const T* X = shadow + (d.field_off / block_elems) * sb.vol;
+    const double s = yee::block_surface_sum(
+        d, t,
+        [&](int32_t idx) {
+            const int x = idx % nx, y = (idx / nx) % ny, z = idx / (nx * ny);
+            return (double)X[((int64_t)(z - sb.z0) * sb.bny + (y - sb.y0)) * sb.bnx + (x - sb.x0)];
+        },
+        red);
+    if (threadIdx.x == 0) {
+        const double G = dA * s;
+        double sum = acc[2 * slot], comp = acc[2 * slot + 1];
+        yee::neumaier(sum, comp, (dt * ktab[m]) * G);
+        acc[2 * slot] = sum;
+        acc[2 * slot + 1] = comp;
+        if (gamma) gamma[(int64_t)m * gamma_stride + slot] = G;
+    }
+}
+
+// Fused 3D variants: W waves of B rows, `steps` time steps per launch
+// (band = W B - 2 steps stored rows).  Indices are part of the ABI
+// (tile_variant); the single-step variants come first.
 struct F3Variant {
-    int W, B;
+    int W, B, steps;
 };
-constexpr F3Variant kF3[] = {{8, 2}, {16, 1}, {8, 1}, {12, 1}};
+constexpr F3Variant kF3[] = {{8, 2, 1}, {16, 1, 1}, {8, 1, 1}, {12, 1, 1}, {8, 1, 2}, {12, 1, 2}};
 constexpr int kNumF3 = sizeof(kF3) / sizeof(kF3[0]);
 
 template <typename T, int W, int CX>
@@ -529,13 +983,13 @@ constexpr bool f3_fits() {
            65536;
 }
 
-template <typename T, int W, int B, int CX>
+template <typename T, int W, int B, int CX, int STEPS>
 hipError_t f3_launch(const ChanDev* ch, const int* slots, int nslots, const Grid3D& g, const T* lut, const T* src,
-                     T* dst, const T* psrc, T* pdst, hipStream_t s) {
+                     T* dst, const T* psrc, T* pdst, T* shadow, const ShadowBox& sb, hipStream_t s) {
     if constexpr (!f3_fits<T, W, CX>()) {
         return hipErrorInvalidValue;
     } else {
-        const int band = W * B - 2;
+        const int band = W * B - 2 * STEPS;
         const int bands = (g.ny + band - 1) / band;
         // z chunks: enough blocks to fill the chip several times over, each
         // chunk at least 24 planes deep (one extra H plane per chunk)
@@ -543,19 +997,27 @@ hipError_t f3_launch(const ChanDev* ch, const int* slots, int nslots, const Grid
         int nzc = (int)std::min<long>((4096 + xy - 1) / xy, std::max(1, g.nz / 24));
         nzc = std::max(1, std::min(nzc, 65535));
         dim3 grid(bands, nslots, nzc), block(64 * W, 1, 1);
-        hipLaunchKernelGGL((k_f3d<T, W, B, CX>), grid, block, 0, s, ch, slots, g, lut, src, dst, psrc, pdst, band);
+        if constexpr (STEPS == 1) {
+            hipLaunchKernelGGL((k_f3d<T, W, B, CX>), grid, block, 0, s, ch, slots, g, lut, src, dst, psrc, pdst,
+                               band);
+        } else {
+            if (shadow == nullptr || sb.vol <= 0) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_f3d2<T, W, B, CX>), grid, block, 0, s, ch, slots, g, lut, src, dst, psrc, pdst,
+                               shadow, sb, band);
+        }
         return hipGetLastError();
     }
 }
 
-template <typename T, int W, int B>
+template <typename T, int W, int B, int STEPS>
 hipError_t f3_dispatch_cx(int cx, const ChanDev* ch, const int* slots, int nslots, const Grid3D& g, const T* lut,
-                          const T* src, T* dst, const T* psrc, T* pdst, hipStream_t s) {
+                          const T* src, T* dst, const T* psrc, T* pdst, T* sh, const ShadowBox& sb,
+                          hipStream_t s) {
     switch (cx) {
-        case 1: return f3_launch<T, W, B, 1>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
-        case 2: return f3_launch<T, W, B, 2>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
-        case 3: return f3_launch<T, W, B, 3>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
-        case 4: return f3_launch<T, W, B, 4>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
+        case 1: return f3_launch<T, W, B, 1, STEPS>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
+        case 2: return f3_launch<T, W, B, 2, STEPS>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
+        case 3: return f3_launch<T, W, B, 3, STEPS>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
+        case 4: return f3_launch<T, W, B, 4, STEPS>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -604,18 +1066,39 @@ bool f3d_usable(int variant, const Grid3D& g) {
 
 int f3d_variants() { return kNumF3; }
 
+int f3d_steps(int variant) { return variant >= 0 && variant < kNumF3 ? kF3[variant].steps : 0; }
+
+int f3d_single(int variant) {
+    if (variant < 0 || variant >= kNumF3) return -1;
+    for (int v = 0; v < kNumF3; ++v)
+        if (kF3[v].steps == 1 && kF3[v].W == kF3[variant].W && kF3[v].B == kF3[variant].B) return v;
+    return -1;
+}
+
 template <typename T>
 hipError_t launch_f3d(int variant, const ChanDev* ch, const int* slots, int nslots, const Grid3D& g, const T* lut,
-                      const T* src, T* dst, const T* psrc, T* pdst, hipStream_t s) {
+                      const T* src, T* dst, const T* psrc, T* pdst, T* sh, const ShadowBox& sb, hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
     if (!f3d_usable<T>(variant, g)) return hipErrorInvalidValue;
     const int cx = (g.nx + 63) / 64;
     switch (variant) {
-        case 0: return f3_dispatch_cx<T, 8, 2>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
-        case 1: return f3_dispatch_cx<T, 16, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
-        case 2: return f3_dispatch_cx<T, 8, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
-        default: return f3_dispatch_cx<T, 12, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, s);
+        case 0: return f3_dispatch_cx<T, 8, 2, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
+        case 1: return f3_dispatch_cx<T, 16, 1, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
+        case 2: return f3_dispatch_cx<T, 8, 1, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
+        case 3: return f3_dispatch_cx<T, 12, 1, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
+        case 4: return f3_dispatch_cx<T, 8, 1, 2>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
+        default: return f3_dispatch_cx<T, 12, 1, 2>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
     }
+}
+
+template <typename T>
+hipError_t launch_surface_box(const T* shadow, const ShadowBox& sb, const Grid3D& g, const ChanDev* ch,
+                              const int* slots, int nslots, const SurfTables& t, const double* ktab, int m,
+                              double dt, double dA, double* acc, double* gamma, int gamma_stride, hipStream_t s) {
+    if (nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_surface_box<T>), dim3(nslots), dim3(yee::kSurfThreads), 0, s, shadow, sb, g.nx, g.ny,
+                       (int64_t)6 * g.ncell, ch, slots, t, ktab, m, dt, dA, acc, gamma, gamma_stride);
+    return hipGetLastError();
 }
 
 #define CF_INSTANTIATE(T)                                                                                    \
@@ -625,7 +1108,10 @@ hipError_t launch_f3d(int variant, const ChanDev* ch, const int* slots, int nslo
                                       hipStream_t);                                                          \
     template bool f3d_usable<T>(int, const Grid3D&);                                                         \
     template hipError_t launch_f3d<T>(int, const ChanDev*, const int*, int, const Grid3D&, const T*, const T*, \
-                                      T*, const T*, T*, hipStream_t);
+                                      T*, const T*, T*, T*, const ShadowBox&, hipStream_t);               \
+    template hipError_t launch_surface_box<T>(const T*, const ShadowBox&, const Grid3D&, const ChanDev*,     \
+                                              const int*, int, const SurfTables&, const double*, int, double, \
+                                              double, double*, double*, int, hipStream_t);
 CF_INSTANTIATE(float)
 CF_INSTANTIATE(double)
 #undef CF_INSTANTIATE

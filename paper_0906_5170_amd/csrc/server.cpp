@@ -197,7 +197,7 @@ std::string prepare(cf_server* S, Req& r) {
         const int pref = 2;
         if (usable(pref)) r.v3 = pref;
         for (int v = 0; v < cf::f3d_variants() && r.v3 < 0; ++v)
-            if (usable(v)) r.v3 = v;
+            if (usable(v) && cf::f3d_steps(v) == 1) r.v3 = v;   // one step per clock tick
     }
     int R = r.opts.max_resident > 0 ? std::min(r.opts.max_resident, r.C) : r.C;
     if (r.fused) R = r.C;   // fused requests keep every channel resident
@@ -488,7 +488,7 @@ hipError_t tick(cf_server* S) {
                 T* src = r.par ? fb : fa;
                 T* dst = r.par ? fa : fb;
                 if ((e = cf::launch_f3d<T>(r.v3, dch, dl + w.d3_off, w.n_3d, g, lut, src, dst, r.par ? pb : pa,
-                                           r.par ? pa : pb, s)) != hipSuccess)
+                                           r.par ? pa : pb, nullptr, cf::ShadowBox{}, s)) != hipSuccess)
                     return e;
                 r.par ^= 1;
                 cur = dst;

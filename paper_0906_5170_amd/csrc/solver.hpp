@@ -49,6 +49,7 @@ struct Staged {
     bool red_res = false;                  // cylindrical waves on the resident solve kernel
     bool f3d = false;                      // 3D steps on the fused z-streaming kernel
     int v3d = -1;                          // its variant when fixed by the options (-1: autotune)
+    cf::ShadowBox sbox{};                  // surface box of a 3D solve (two-step fused launches)
 };
 
 struct StencilTiming {

@@ -84,7 +84,7 @@ def test_fused_3d_every_variant_bitwise_equals_split(cf, precision):
         ref = run(cf, wl, precision=precision, split=True)
         assert not ref["fused"]
         n_ok = 0
-        for v in range(1, 5):
+        for v in range(1, 7):        # 1..4 single-step band shapes, 5..6 two-step
             r = run(cf, wl, precision=precision, tile_variant=v)
             np.testing.assert_array_equal(r["per_channel"], ref["per_channel"])
             if r["fused"] and r["tile_variant"] == v:
@@ -93,7 +93,7 @@ def test_fused_3d_every_variant_bitwise_equals_split(cf, precision):
         np.testing.assert_array_equal(auto["per_channel"], ref["per_channel"])
         assert auto["fused"] == (n_ok > 0)
         if precision == "fp32":
-            assert n_ok >= 2
+            assert n_ok >= 4
 
 
 def test_3d_waves_and_plain_equal_batched(cf):
