@@ -460,7 +460,8 @@ struct RbVariant {
 constexpr RbVariant kRbF32[] = {{8, 8, 8, false, 1},  {8, 8, 6, false, 1},  {8, 8, 4, false, 1},
                                 {16, 4, 8, false, 1}, {8, 8, 8, true, 1},   {16, 4, 8, true, 1},
                                 {8, 8, 6, true, 1},   {16, 4, 8, false, 2}, {8, 8, 8, false, 2},
-                                {16, 4, 8, true, 2},  {8, 8, 8, true, 2}};
+                                {16, 4, 8, true, 2},  {8, 8, 8, true, 2},   {7, 8, 8, true, 1},
+                                {8, 7, 8, true, 1}};
 constexpr RbVariant kRbF64[] = {{8, 4, 4, false, 1}, {8, 4, 2, false, 1}, {16, 4, 4, false, 1},
                                 {16, 4, 4, true, 1}, {8, 4, 4, false, 2}};
 
@@ -574,7 +575,9 @@ hipError_t launch_tb2d(int variant, int pol, const ChanDev* ch, const WorkItem* 
             case 7: CF_RB(16, 4, 8, false, 2); break;
             case 8: CF_RB(8, 8, 8, false, 2); break;
             case 9: CF_RB(16, 4, 8, true, 2); break;
-            default: CF_RB(8, 8, 8, true, 2); break;
+            case 10: CF_RB(8, 8, 8, true, 2); break;
+            case 11: CF_RB(7, 8, 8, true, 1); break;
+            default: CF_RB(8, 7, 8, true, 1); break;
         }
     } else {
         switch (variant) {

@@ -699,7 +699,9 @@ cf_status cf_server_create(size_t hbm_budget_bytes, int precision, int tile_vari
     const int nv = precision == CF_FP64 ? cf::tb_variants<double>(sh, cf::kMaxVariants)
                                         : cf::tb_variants<float>(sh, cf::kMaxVariants);
     if (tile_variant < 0 || tile_variant > nv) return fail(CF_E_ARG, "tile_variant out of range");
-    const int first = tile_variant > 0 ? tile_variant - 1 : (precision == CF_FP64 ? 0 : std::min(4, nv - 1));
+    // default: the FP32 shape that is fastest on the piston workloads (8 waves
+    // of 7 rows, 8 steps per launch), the first FP64 shape
+    const int first = tile_variant > 0 ? tile_variant - 1 : (precision == CF_FP64 ? 0 : std::min(12, nv - 1));
     S->kh = sh[first].kh;
     // the preferred variant, then every other one with the same steps per
     // launch (wider tiles take surfaces the preferred one cannot hold)

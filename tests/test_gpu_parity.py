@@ -132,7 +132,7 @@ def test_graph_launch_bitwise_equals_stream_launches(cf, precision):
     np.testing.assert_array_equal(a["per_channel"], w["per_channel"])
 
 
-@pytest.mark.parametrize("precision,nvar", [("fp32", 11), ("fp64", 5)])
+@pytest.mark.parametrize("precision,nvar", [("fp32", 13), ("fp64", 5)])
 def test_every_tile_variant_bitwise_equals_split(cf, precision, nvar):
     announce(f"fused tile variants 1..{nvar} vs split, {precision}")
     wl = SMALL["ragged_61x37"]().replace(n_steps=53)

@@ -15,7 +15,7 @@ from casimir_inputs.geometry import Box, Sphere, Workload, rasterize
 pytestmark = pytest.mark.gpu
 BIG = 1e30
 MiB = 1 << 20
-FP32_DEFAULT_VARIANT = 5     # the server's default fused variant in FP32 (1-based)
+FP32_DEFAULT_VARIANT = 13    # the server's default fused variant in FP32 (1-based)
 FP64_DEFAULT_VARIANT = 1
 
 
