@@ -281,15 +281,29 @@ void tune_store(const std::string& key, int v) {
 
 // Place the tile grid along one axis so that [lo, hi] sits in one tile of
 // width w: returns false when it cannot.
+// Tiling origin base in (-w, 0] along one axis such that the cells lo..hi
+// (the surface stencil) lie in one tile: the fewest tiles over 0..n-1, and
+// among those the origin that centres lo..hi best in its tile.
 static bool place_axis(int lo, int hi, int n, int w, int* base, int* ntiles, int* stile) {
     const int span = hi - lo + 1;
     if (span > w) return false;
-    const int X0 = lo - (w - span) / 2;
-    const int r = ((X0 % w) + w) % w;
-    *base = r == 0 ? 0 : r - w;
-    *ntiles = (n - *base + w - 1) / w;
-    *stile = (X0 - *base) / w;
-    return true;
+    auto fdiv = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+    int best_n = 0, best_slack = -1;
+    for (int b = 0; b > -w; --b) {
+        const int t = fdiv(lo - b, w);
+        if (fdiv(hi - b, w) != t) continue;              // S straddles two tiles
+        const int nt = (n - b + w - 1) / w;
+        const int t0 = b + t * w;                         // first cell of S's tile
+        const int slack = std::min(lo - t0, t0 + w - 1 - hi);
+        if (best_slack < 0 || nt < best_n || (nt == best_n && slack > best_slack)) {
+            best_n = nt;
+            best_slack = slack;
+            *base = b;
+            *ntiles = nt;
+            *stile = t;
+        }
+    }
+    return best_slack >= 0;
 }
 
 TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, cf::TBShape sh) {
