@@ -524,9 +524,12 @@ __global__ __launch_bounds__(kResThreads) void k_red_resident(T* __restrict__ fi
     }
 }
 
-// Length of the exchange array of the register kernel: 3 n values, and at
-// least the 6 x 256 coefficient pairs it holds during the start.
-__host__ __device__ constexpr int regs_x_len(int n) { return 3 * n > 6 * 256 * 2 ? 3 * n : 6 * 256 * 2; }
+// Length of the exchange array of the register kernel: 3 n values per part
+// (np = 2 for complex runs), and at least the 6 x 256 coefficient pairs it
+// holds during the start.
+__host__ __device__ constexpr int regs_x_len(int n, int np) {
+    return 3 * np * n > 6 * 256 * 2 ? 3 * np * n : 6 * 256 * 2;
+}
 
 // Register-resident solve: the clear, kick and start as in k_red_resident,
 // then every thread keeps the six fields of its K cells (flat cells t,
@@ -540,17 +543,22 @@ __host__ __device__ constexpr int regs_x_len(int n) { return 3 * n > 6 * 256 * 2
 // step).  A cell's coordinates are recomputed in every half step from the
 // thread's first cell, passed through an empty asm statement so that the
 // compiler keeps no per-cell addresses in registers across steps.
-template <typename T, int K, int NTH, bool CYL>
+// CPLX (Bloch-periodic x): both parts of every field in registers, the
+// exchange array holds the real part's triple and then the imaginary part's,
+// and the neighbours across the periodic x edge take the Bloch phase as in
+// the other drivers; the surface reads the real part.
+template <typename T, int K, int NTH, bool CYL, bool CPLX>
 __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                   const int* __restrict__ slots, Grid2D g, RedOrders ord,
                                                   SurfTables t, double dA, double* __restrict__ acc,
                                                   double* __restrict__ gamma, int gamma_stride) {
+    constexpr int NP = CPLX ? 2 : 1;               // parts: real (and imaginary)
     extern __shared__ double lds_dyn[];
     __shared__ double red[yee::kSurfThreads / 64];
     const int n = (int)g.ncell;
-    T* X = reinterpret_cast<T*>(lds_dyn);          // 3 n exchange values
+    T* X = reinterpret_cast<T*>(lds_dyn);          // 3 n exchange values per part
     T* Lg = X;                                      // the kind's full table, for the start (before X is used)
-    T* Lc = X + regs_x_len(n);                      // 6 x 16 (a, b) pairs
+    T* Lc = X + regs_x_len(n, NP);                  // 6 x 16 (a, b) pairs
     T* R = Lc + 6 * 16 * 2;                         // row factors (kRowFactors per row)
     uint32_t* W = reinterpret_cast<uint32_t*>(R + kRowFactors * g.ny);   // packed ids per cell
     const int slot = slots[blockIdx.x];
@@ -569,7 +577,7 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
     }
     for (int k = threadIdx.x; k < n; k += NTH) W[k] = ord.idw[k];
     for (int k = threadIdx.x; k < kRowFactors * g.ny; k += NTH) R[k] = static_cast<const T*>(ord.rows)[k];
-    for (int64_t k = threadIdx.x; k < 6 * g.ncell; k += NTH) F[k] = T(0);
+    for (int64_t k = threadIdx.x; k < NP * 6 * g.ncell; k += NTH) F[k] = T(0);
     __syncthreads();
     // (the exchange array takes over Lg's space after the start)
     for (int u = threadIdx.x; u < d.n_uniq; u += NTH) {
@@ -579,28 +587,32 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
         fields[d.src_off + t.uidx[d.u_off + u]] = T(d.kick_scale * s);
     }
     __syncthreads();
-    const RedRun<T> rr{T(ord.coup[m]), R, T(1), T(0)};
-    if (d.kind == 0) h_phase<T, 1, CYL, NTH>(F, g, Lg, rr);
-    else e_phase<T, 1, CYL, NTH>(F, g, Lg, rr);
+    const RedRun<T> rr{T(ord.coup[m]), R, CPLX ? T(ord.ph_c[m]) : T(1), CPLX ? T(ord.ph_s[m]) : T(0)};
+    if (d.kind == 0) h_phase<T, 1, CYL, NTH, CPLX>(F, g, Lg, rr);
+    else e_phase<T, 1, CYL, NTH, CPLX>(F, g, Lg, rr);
     __syncthreads();
-    T e0[K], e1[K], e2[K], h0[K], h1[K], h2[K];
+    T e0[NP][K], e1[NP][K], e2[NP][K], h0[NP][K], h1[NP][K], h2[NP][K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int c = threadIdx.x + k * NTH;
-        if (c < n) {
-            e0[k] = F[c];
-            e1[k] = F[n + c];
-            e2[k] = F[2 * n + c];
-            h0[k] = F[3 * n + c];
-            h1[k] = F[4 * n + c];
-            h2[k] = F[5 * n + c];
-            X[c] = e0[k];
-            X[n + c] = e1[k];
-            X[2 * n + c] = e2[k];
-        } else {
-            e0[k] = e1[k] = e2[k] = h0[k] = h1[k] = h2[k] = T(0);
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int c = threadIdx.x + k * NTH;
+            const T* Fp = F + p * 6 * n;
+            T* Xp = X + p * 3 * n;
+            if (c < n) {
+                e0[p][k] = Fp[c];
+                e1[p][k] = Fp[n + c];
+                e2[p][k] = Fp[2 * n + c];
+                h0[p][k] = Fp[3 * n + c];
+                h1[p][k] = Fp[4 * n + c];
+                h2[p][k] = Fp[5 * n + c];
+                Xp[c] = e0[p][k];
+                Xp[n + c] = e1[p][k];
+                Xp[2 * n + c] = e2[p][k];
+            } else {
+                e0[p][k] = e1[p][k] = e2[p][k] = h0[p][k] = h1[p][k] = h2[p][k] = T(0);
+            }
         }
-    }
     __syncthreads();
     const bool meas_h = d.meas_slot >= 3;
     const T* Xq = X + (d.meas_slot % 3) * n;
@@ -633,12 +645,25 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
                     const uint32_t w = W[c];
                     const int cu = in_u ? c + nx : i;
                     const bool has_u = in_u || (!CYL && g.pery);   // the tube wall is never periodic
-                    const T ezu = has_u ? X[2 * n + cu] : T(0);
-                    const T exu = has_u ? X[cu] : T(0);
-                    const T ezr = in_r ? X[2 * n + c + 1] : (g.perx ? X[2 * n + c + 1 - nx] : T(0));
-                    const T eyr = in_r ? X[n + c + 1] : (g.perx ? X[n + c + 1 - nx] : T(0));
-                    h_values<T, 0, CYL>(h0[k], h1[k], h2[k], e0[k], e1[k], e2[k], ezu, exu, ezr, eyr,
-                                        pair(CF_HX, w), pair(CF_HY, w), pair(CF_HZ, w), rr.M, j, R + kRowFactors * j);
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        const T* Xp = X + p * 3 * n;
+                        const T ezu = has_u ? Xp[2 * n + cu] : T(0);
+                        const T exu = has_u ? Xp[cu] : T(0);
+                        T ezr, eyr;
+                        if (in_r || !g.perx || !CPLX) {
+                            ezr = in_r ? Xp[2 * n + c + 1] : (g.perx ? Xp[2 * n + c + 1 - nx] : T(0));
+                            eyr = in_r ? Xp[n + c + 1] : (g.perx ? Xp[n + c + 1 - nx] : T(0));
+                        } else {   // across the Bloch-periodic edge
+                            const T* Xo = X + (1 - p) * 3 * n;
+                            const int wr = c + 1 - nx;
+                            ezr = bloch_fwd(Xp[2 * n + wr], Xo[2 * n + wr], p, rr.pc, rr.ps);
+                            eyr = bloch_fwd(Xp[n + wr], Xo[n + wr], p, rr.pc, rr.ps);
+                        }
+                        h_values<T, 0, CYL>(h0[p][k], h1[p][k], h2[p][k], e0[p][k], e1[p][k], e2[p][k], ezu, exu,
+                                            ezr, eyr, pair(CF_HX, w), pair(CF_HY, w), pair(CF_HZ, w), rr.M, j,
+                                            R + kRowFactors * j);
+                    }
                 }
                 i += di;
                 j += dj;
@@ -650,14 +675,16 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int c = threadIdx.x + k * NTH;
-            if (c < n) {
-                X[c] = h0[k];
-                X[n + c] = h1[k];
-                X[2 * n + c] = h2[k];
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int c = threadIdx.x + k * NTH;
+                if (c < n) {
+                    X[p * 3 * n + c] = h0[p][k];
+                    X[p * 3 * n + n + c] = h1[p][k];
+                    X[p * 3 * n + 2 * n + c] = h2[p][k];
+                }
             }
-        }
         __syncthreads();
         if (meas_h) measure(step);
         asm volatile("" : "+v"(i0), "+v"(j0));
@@ -671,12 +698,25 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
                     const uint32_t w = W[c];
                     const int cd = in_d ? c - nx : c + n - nx;
                     const bool has_d = in_d || (!CYL && g.pery);
-                    const T hxd = has_d ? X[cd] : T(0);
-                    const T hzd = has_d ? X[2 * n + cd] : T(0);
-                    const T hyl = i > 0 ? X[n + c - 1] : (g.perx ? X[n + c - 1 + nx] : T(0));
-                    const T hzl = i > 0 ? X[2 * n + c - 1] : (g.perx ? X[2 * n + c - 1 + nx] : T(0));
-                    e_values<T, 0, CYL>(e0[k], e1[k], e2[k], h0[k], h1[k], h2[k], hxd, hzd, hyl, hzl,
-                                        pair(CF_EX, w), pair(CF_EY, w), pair(CF_EZ, w), rr.M, j, R + kRowFactors * j);
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        const T* Xp = X + p * 3 * n;
+                        const T hxd = has_d ? Xp[cd] : T(0);
+                        const T hzd = has_d ? Xp[2 * n + cd] : T(0);
+                        T hyl, hzl;
+                        if (i > 0 || !g.perx || !CPLX) {
+                            hyl = i > 0 ? Xp[n + c - 1] : (g.perx ? Xp[n + c - 1 + nx] : T(0));
+                            hzl = i > 0 ? Xp[2 * n + c - 1] : (g.perx ? Xp[2 * n + c - 1 + nx] : T(0));
+                        } else {   // across the Bloch-periodic edge
+                            const T* Xo = X + (1 - p) * 3 * n;
+                            const int wl = c - 1 + nx;
+                            hyl = bloch_bwd(Xp[n + wl], Xo[n + wl], p, rr.pc, rr.ps);
+                            hzl = bloch_bwd(Xp[2 * n + wl], Xo[2 * n + wl], p, rr.pc, rr.ps);
+                        }
+                        e_values<T, 0, CYL>(e0[p][k], e1[p][k], e2[p][k], h0[p][k], h1[p][k], h2[p][k], hxd, hzd,
+                                            hyl, hzl, pair(CF_EX, w), pair(CF_EY, w), pair(CF_EZ, w), rr.M, j,
+                                            R + kRowFactors * j);
+                    }
                 }
                 i += di;
                 j += dj;
@@ -688,14 +728,16 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int c = threadIdx.x + k * NTH;
-            if (c < n) {
-                X[c] = e0[k];
-                X[n + c] = e1[k];
-                X[2 * n + c] = e2[k];
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int c = threadIdx.x + k * NTH;
+                if (c < n) {
+                    X[p * 3 * n + c] = e0[p][k];
+                    X[p * 3 * n + n + c] = e1[p][k];
+                    X[p * 3 * n + 2 * n + c] = e2[p][k];
+                }
             }
-        }
         __syncthreads();
         if (!meas_h) measure(step);
     }
@@ -706,8 +748,8 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
 }
 
 template <typename T>
-size_t regs_lds_bytes(const Grid2D& g) {
-    return ((size_t)regs_x_len((int)g.ncell) + 6 * 16 * 2 + kRowFactors * (size_t)g.ny) * sizeof(T) +
+size_t regs_lds_bytes(const Grid2D& g, int np) {
+    return ((size_t)regs_x_len((int)g.ncell, np) + 6 * 16 * 2 + kRowFactors * (size_t)g.ny) * sizeof(T) +
            4 * (size_t)g.ncell;
 }
 
@@ -735,10 +777,10 @@ inline size_t device_lds_limit() {
 
 // Dynamic LDS above 64 KB needs the kernel's attribute raised first; false
 // when the runtime refuses (the caller then takes the global-memory variant).
-template <typename T, int K, int NTH, bool CYL>
+template <typename T, int K, int NTH, bool CYL, bool CPLX>
 bool regs_lds_ok(size_t lds) {
     if (lds <= 65536) return true;
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_red_regs<T, K, NTH, CYL>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_red_regs<T, K, NTH, CYL, CPLX>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -747,18 +789,30 @@ bool regs_lds_ok(size_t lds) {
     return true;
 }
 
+// Register variants a complex run may take (both parts of every field in
+// registers): the first kCplxRegVariants, which do not spill (FP32 up to 6
+// cells per thread, FP64 up to 3).
+template <typename T>
+constexpr int kCplxRegVariants = 4;
+template <>
+constexpr int kCplxRegVariants<double> = 3;
+
 // Launch register variant v if the grid fits it: *launched tells whether it did.
-template <typename T, int V, bool CYL>
+template <typename T, int V, bool CYL, bool CPLX>
 hipError_t regs_try(int64_t ncell, size_t lds, bool* launched, T* fields, const ChanDev* ch, const int* slots,
                     int nslots, const Grid2D& g, const RedOrders& ord, const SurfTables& t, double dA, double* acc,
                     double* gamma, int gamma_stride, hipStream_t s) {
-    constexpr int K = kRegVariants<T>[V].K, NTH = kRegVariants<T>[V].NTH;
     *launched = false;
-    if (ncell > (int64_t)K * NTH || !regs_lds_ok<T, K, NTH, CYL>(lds)) return hipSuccess;
-    *launched = true;
-    hipLaunchKernelGGL((k_red_regs<T, K, NTH, CYL>), dim3(nslots), dim3(NTH), lds, s, fields, ch, slots, g, ord, t,
-                       dA, acc, gamma, gamma_stride);
-    return hipGetLastError();
+    if constexpr (CPLX && V >= kCplxRegVariants<T>) {
+        return hipSuccess;
+    } else {
+        constexpr int K = kRegVariants<T>[V].K, NTH = kRegVariants<T>[V].NTH;
+        if (ncell > (int64_t)K * NTH || !regs_lds_ok<T, K, NTH, CYL, CPLX>(lds)) return hipSuccess;
+        *launched = true;
+        hipLaunchKernelGGL((k_red_regs<T, K, NTH, CYL, CPLX>), dim3(nslots), dim3(NTH), lds, s, fields, ch, slots, g,
+                           ord, t, dA, acc, gamma, gamma_stride);
+        return hipGetLastError();
+    }
 }
 
 }  // namespace
@@ -813,14 +867,14 @@ hipError_t resident_launch(int variant, T* fields, const ChanDev* ch, const int*
                            double* gamma, int gamma_stride, hipStream_t s, int* used) {
     *used = 0;
     if (nslots <= 0) return hipSuccess;
-    const size_t dyn = regs_lds_bytes<T>(g);
-    if (!CPLX && variant != 2 && ord.idw && dyn + 64 <= device_lds_limit()) {
+    const size_t dyn = regs_lds_bytes<T>(g, CPLX ? 2 : 1);
+    if (variant != 2 && ord.idw && dyn + 64 <= device_lds_limit()) {
         bool launched = false;
         hipError_t e = hipSuccess;
         auto attempt = [&](auto v) {
             if (!launched && e == hipSuccess)
-                e = regs_try<T, decltype(v)::value, CYL>(g.ncell, dyn, &launched, fields, ch, slots, nslots, g, ord, t,
-                                                    dA, acc, gamma, gamma_stride, s);
+                e = regs_try<T, decltype(v)::value, CYL, CPLX>(g.ncell, dyn, &launched, fields, ch, slots, nslots, g,
+                                                               ord, t, dA, acc, gamma, gamma_stride, s);
         };
         attempt(std::integral_constant<int, 0>{});
         attempt(std::integral_constant<int, 1>{});

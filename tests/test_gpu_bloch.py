@@ -76,7 +76,7 @@ def test_fp64_matches_oracle(cf, name):
     announce(f"Bloch fp64 vs oracle: {name}")
     wl, ref = oracle_result(name)
     res = run(cf, wl)
-    assert res["fused"] and res["tile_variant"] == 2          # complex runs: global-memory resident kernel
+    assert res["fused"] and res["tile_variant"] == 1          # both parts in registers
     rel = check(res, ref, 1e-9)
     print(f"[bloch] {name}: max channel error {rel:.2e} of the largest", flush=True)
 
@@ -107,9 +107,12 @@ def test_supercell_folding_on_gpu(cf):
 def test_drivers_bitwise(cf, precision):
     announce(f"Bloch drivers bitwise, {precision}")
     wl, _ = oracle_result("cell")
-    res = run(cf, wl, precision=precision, keep_gamma=True)
     split = run(cf, wl, precision=precision, split=True, keep_gamma=True)
     plain = run(cf, wl, precision=precision, path="plain")
-    np.testing.assert_array_equal(split["per_channel"], res["per_channel"])
-    np.testing.assert_array_equal(split["gamma"], res["gamma"])
-    np.testing.assert_array_equal(plain["per_channel"], res["per_channel"])
+    np.testing.assert_array_equal(plain["per_channel"], split["per_channel"])
+    # register-resident (both parts in registers) and global-memory resident kernels
+    for variant, expect in ((0, 1), (2, 2)):
+        res = run(cf, wl, precision=precision, tile_variant=variant, keep_gamma=True)
+        assert res["fused"] and res["tile_variant"] == expect
+        np.testing.assert_array_equal(split["per_channel"], res["per_channel"])
+        np.testing.assert_array_equal(split["gamma"], res["gamma"])
