@@ -69,3 +69,24 @@ def test_c3_uneven_set_sampled_against_oracle(cf):
         terms = float(np.sum(np.abs(ref.sign * ref.acc)) / np.pi)
         assert abs(res[k]["force"] - ref.force) <= 1e-5 * terms
         np.testing.assert_allclose(res[k]["per_channel"], ref.acc, rtol=0, atol=1e-5 * np.max(np.abs(ref.acc)))
+
+
+def test_c3_with_mu5_sidewalls_one_graph_sequence(cf):
+    """The uneven set with metallic sidewalls and the same set with mu = 5
+    magnetic sidewalls (48 problems), FP32, in one graph-captured batched
+    sequence (T cut to 120): every problem fused; members equal their own
+    solves bit for bit; a mu = 5 member matches the FP64 oracle."""
+    announce("c3 metallic + mu=5 sidewalls, 48 problems, one graph sequence, T=120")
+    wls = [w.replace(n_steps=120) for side in ("pec", "mu5") for w in c3_uneven_set(side)]
+    probs = [cf.Problem.from_workload(w) for w in wls]
+    o = opts_of(wls[0])
+    res = cf.batch_solve(probs, graph=True, **o)
+    assert len(res) == 48 and all(r["fused"] for r in res)
+    for k in (3, 24 + 17):
+        single = probs[k].solve(**o)
+        np.testing.assert_array_equal(res[k]["per_channel"], single["per_channel"])
+    k = 24 + 9
+    assert wls[k].mu[2] == 5.0
+    ref = oracle.solve(wls[k])
+    terms = float(np.sum(np.abs(ref.sign * ref.acc)) / np.pi)
+    assert abs(res[k]["force"] - ref.force) <= 1e-5 * terms
