@@ -60,13 +60,14 @@ struct Req {
     bool fused = false;
     int variant = -1;                 // fused variant of this request
     int v3 = -1;                      // fused 3D step variant (-1: split 3D kernels)
+    int v3s = -1;                     // its single-step band shape (a step without a partner in the tick)
     cfi::ConvergenceStop conv;        // time-convergence stop (single-wave requests)
     int steps_run = -1;
     int par = 0;                      // fused 3D: field array holding the current step
     int C = 0;
     size_t bytes = 0, off = 0;
     size_t o_ids, o_lut, o_ktab, o_pml, o_ch, o_slots, o_gidx, o_gw, o_uidx, o_uoff, o_usamp, o_uw, o_basis,
-        o_acc, o_fa, o_fb, o_psi, o_psi2, o_idp;
+        o_acc, o_fa, o_fb, o_psi, o_psi2, o_idp, o_shadow;
     std::vector<uint32_t> idp;        // fused 3D: packed material ids
     std::vector<uint8_t> ids;
     std::vector<uint8_t> lut;     // field-precision bytes
@@ -157,6 +158,7 @@ void layout_request(const cf_server* S, Req& r) {
     r.o_psi = st.psi_comp > 0 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
     r.o_psi2 = st.psi_comp > 0 && f3 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
     r.o_idp = f3 ? take((size_t)p.ncell * 8) : off;
+    r.o_shadow = f3 && cf::f3d_steps(r.v3) == 2 ? take((size_t)st.resident * st.sbox.vol * fsz) : off;
     r.bytes = off;
 }
 
@@ -181,8 +183,10 @@ std::string prepare(cf_server* S, Req& r) {
                 break;
             }
     r.fused = r.variant >= 0;
-    // 3D requests take the fused z-streaming step when it applies: the
-    // preferred band shape (8 waves of 1 row), else the first usable one
+    // 3D requests take the fused z-streaming step when it applies: in FP32
+    // the two-step kernel (12 waves of 1 row; steps go in pairs within a clock
+    // tick), else the single-step band shape of 8 waves of 1 row, else the
+    // first usable one
     r.v3 = -1;
     if (p.grid.ndim == 3 && r.st.f3d) {
         cf::Grid3D g{};
@@ -194,10 +198,12 @@ std::string prepare(cf_server* S, Req& r) {
         auto usable = [&](int v) {
             return S->precision == CF_FP64 ? cf::f3d_usable<double>(v, g) : cf::f3d_usable<float>(v, g);
         };
-        const int pref = 2;
-        if (usable(pref)) r.v3 = pref;
+        const int pref2 = 5, pref = 2;
+        if (S->precision != CF_FP64 && usable(pref2) && r.st.sbox.vol > 0) r.v3 = pref2;
+        if (r.v3 < 0 && usable(pref)) r.v3 = pref;
         for (int v = 0; v < cf::f3d_variants() && r.v3 < 0; ++v)
-            if (usable(v) && cf::f3d_steps(v) == 1) r.v3 = v;   // one step per clock tick
+            if (usable(v) && cf::f3d_steps(v) == 1) r.v3 = v;
+        r.v3s = r.v3 >= 0 && cf::f3d_steps(r.v3) == 2 ? cf::f3d_single(r.v3) : r.v3;
     }
     int R = r.opts.max_resident > 0 ? std::min(r.opts.max_resident, r.C) : r.C;
     if (r.fused) R = r.C;   // fused requests keep every channel resident
@@ -487,11 +493,26 @@ hipError_t tick(cf_server* S) {
                 T* pb = psi ? reinterpret_cast<T*>(b + r.o_psi2) : nullptr;
                 T* src = r.par ? fb : fa;
                 T* dst = r.par ? fa : fb;
-                if ((e = cf::launch_f3d<T>(r.v3, dch, dl + w.d3_off, w.n_3d, g, lut, src, dst, r.par ? pb : pa,
-                                           r.par ? pa : pb, nullptr, cf::ShadowBox{}, s)) != hipSuccess)
+                // steps m and m + 1 in one two-step launch when both fall in this tick
+                const bool two = cf::f3d_steps(r.v3) == 2 && k + 1 < S->kh && m + 1 < r.opts.n_steps;
+                T* sh = reinterpret_cast<T*>(b + r.o_shadow);
+                if ((e = cf::launch_f3d<T>(two ? r.v3 : r.v3s, dch, dl + w.d3_off, w.n_3d, g, lut, src, dst,
+                                           r.par ? pb : pa, r.par ? pa : pb, sh, r.st.sbox, s)) != hipSuccess)
                     return e;
+                if (two) {
+                    if ((e = cf::launch_surface_box<T>(sh, r.st.sbox, g, dch, dl + w.all_off, w.n_all, t, kt, (int)m,
+                                                       dt, dA, acc, nullptr, 0, s)) != hipSuccess)
+                        return e;
+                    ++k;   // the pair's second step: measured below
+                }
                 r.par ^= 1;
                 cur = dst;
+                if (two) {
+                    if ((e = cf::launch_surface<T>(cur, dch, dl + w.all_off, w.n_all, t, kt, (int)m + 1, dt, dA, acc,
+                                                   nullptr, 0, s)) != hipSuccess)
+                        return e;
+                    continue;
+                }
             } else if (p.grid.ndim == 3) {
                 const cf::Grid3D g = Dev<T>::grid3(b, r);
                 if ((e = cf::launch_h3d<T>(0, f, psi, dch, dl + w.d3_off, w.n_3d, g, lut, s)) != hipSuccess) return e;

@@ -84,6 +84,8 @@ def test_server_results_alone_equal_mix_and_one_shot(cf):
         if fused:
             if k < 3:
                 assert a["tile_variant"] == FP32_DEFAULT_VARIANT
+            if wls[k].ndim == 3:
+                assert a["tile_variant"] == 6      # the two-step fused 3D kernel, steps paired in each tick
             one = p.solve(**opts_of(w, tile_variant=a["tile_variant"]))
             assert one["tile_variant"] == a["tile_variant"]
         else:
