@@ -86,6 +86,41 @@ def cpu_baseline(wl, n_channels=32, n_steps=None):
                       f"({cu:.3e} cell-updates, {dt:.1f} s, FP64 NumPy, one process per channel)"}
 
 
+def cpu_baseline_reduced():
+    """The oracle on bounded samples of the two reduced workloads of the
+    benchmark (one process each), projected to a whole force point: the
+    cylindrical piston (order 0, all channels, 300 steps) and the k_z
+    dielectric piston (one k point, all channels, 200 steps)."""
+    from casimir_inputs import c_cyl_piston, dielectric_piston2d, kz_gauss, kz_workload
+    from oracle import cylforce, kz
+    from oracle.cyl import cylindrical_courant
+    from oracle.force import setup
+    out = {}
+    wl = c_cyl_piston()
+    faces, bases, eps_s, mu_s, chans = cylforce.setup(wl)
+    n_s = 300
+    t1 = time.perf_counter()
+    cylforce.run_order(wl, 0, faces, bases, eps_s, mu_s, chans, n_s, cylindrical_courant(wl.courant, 0))
+    dt = time.perf_counter() - t1
+    per = dt / (len(chans) * n_s)                  # seconds per channel-step
+    total = sum(len(chans) * round(wl.n_steps * wl.courant / cylindrical_courant(wl.courant, m))
+                for m in range(wl.m_max + 1))
+    out["cylindrical"] = {"projected_force_point_s": per * total, "cores": 1,
+                          "sample": f"order 0, all {len(chans)} channels x {n_s} steps, {dt:.1f} s, FP64 NumPy"}
+    base = dielectric_piston2d(80, 40, 10, 20, 10, 20, 15, 20.0, n_steps=2000, n_harm=16, precision="fp32")
+    ks, ws = kz_gauss(8, 12.0)
+    wl = kz_workload(base, ks, ws)
+    _, _, _, _, chans = setup(wl)
+    n_s = 200
+    t1 = time.perf_counter()
+    kz.solve(wl.replace(n_steps=n_s), [ks[3]], [1.0])
+    dt = time.perf_counter() - t1
+    per = dt / (len(chans) * n_s)
+    out["kz"] = {"projected_s": per * len(chans) * len(ks) * wl.n_steps, "cores": 1,
+                 "sample": f"one k_z, all {len(chans)} channels x {n_s} steps, {dt:.1f} s, FP64 NumPy"}
+    return out
+
+
 def bench_3d(cf, torch, n_chan=64, n_steps=200, variant=0):
     """3D FP32 path on the 192^3 sphere-over-indented-plate cell (16-cell z
     CPML): a sample of n_chan of its 1280 channels, spread over faces, kinds
@@ -124,7 +159,7 @@ def bench_3d(cf, torch, n_chan=64, n_steps=200, variant=0):
             "projected_full_solve_s": 1280 * wl.n_cells * wl.n_steps / rate}
 
 
-def bench_cyl(cf, torch, cpu_sample=True, quick=False):
+def bench_cyl(cf, torch, quick=False):
     """Cylindrical piston (Sec. III D, Fig. 7) at resolution 40, n, m in
     {0, 1, 2}: one whole force point (126 channels; orders 0 and 1 take
     10000 steps, order 2 15000 on its smaller step), FP32 fields, on the
@@ -156,25 +191,12 @@ def bench_cyl(cf, torch, cpu_sample=True, quick=False):
            "speedup_vs_split": rs["device_ms"] / r["device_ms"], "fp64_device_ms": r64["device_ms"],
            "alg_bytes_per_s": alg, "alg_frac_of_hbm_peak": alg / (HBM_PEAK_GBS * 1e9),
            "paper_quote": "about 5 minutes per force point on 8 processors (2009), res 40, n,m in {0,1,2}"}
-    if cpu_sample:
-        from oracle import cylforce
-        from oracle.cyl import cylindrical_courant
-        faces, bases, eps_s, mu_s, chans = cylforce.setup(wl)
-        n_s = 300
-        t1 = time.perf_counter()
-        cylforce.run_order(wl, 0, faces, bases, eps_s, mu_s, chans, n_s, cylindrical_courant(wl.courant, 0))
-        dt = time.perf_counter() - t1
-        per = dt / (len(chans) * n_s)                  # seconds per channel-step
-        total = sum(len(chans) * round(wl.n_steps * wl.courant / cylindrical_courant(wl.courant, m))
-                    for m in range(wl.m_max + 1))
-        out["cpu_oracle"] = {"projected_force_point_s": per * total, "cores": 1,
-                             "sample": f"order 0, all {len(chans)} channels x {n_s} steps, {dt:.1f} s, FP64 NumPy"}
     log(f"[bench] cyl: force point {wall:.3f} s wall ({r['device_ms']:.1f} ms device), {rate:.3e} cell-updates/s, "
         f"split {rs['device_ms']:.1f} ms, fp64 {r64['device_ms']:.1f} ms")
     return out
 
 
-def bench_kz(cf, torch, cpu_sample=True):
+def bench_kz(cf, torch):
     """z-invariant dielectric piston (eps = 4 blocks between PEC slabs; the
     C1 geometry: res 20, 80 x 40, 16 harmonics, T = 2000) integrated over
     k_z with 8-point Gauss-Legendre on [0, 12] (Sec. III C: dielectrics
@@ -228,17 +250,6 @@ def bench_kz(cf, torch, cpu_sample=True):
                     "unit": "cell-updates/s (complex cells)", "resident_variant": rb["tile_variant"],
                     "alg_bytes_per_s": rate_b * 96.0, "alg_frac_of_hbm_peak": rate_b * 96.0 / (HBM_PEAK_GBS * 1e9)}
     log(f"[bench] bloch: {wb:.3f} s wall ({rb['device_ms']:.1f} ms device), {rate_b:.3e} complex cell-updates/s")
-    if cpu_sample:
-        from oracle import kz
-        from oracle.force import setup
-        _, _, _, _, chans = setup(wl)
-        n_s = 200
-        t1 = time.perf_counter()
-        kz.solve(wl.replace(n_steps=n_s), [ks[3]], [1.0])
-        dt = time.perf_counter() - t1
-        per = dt / (len(chans) * n_s)
-        out["cpu_oracle"] = {"projected_s": per * len(chans) * len(ks) * wl.n_steps, "cores": 1,
-                             "sample": f"one k_z, all {len(chans)} channels x {n_s} steps, {dt:.1f} s, FP64 NumPy"}
     log(f"[bench] kz: {wall:.3f} s wall ({r['device_ms']:.1f} ms device), {rate:.3e} cell-updates/s, "
         f"split {rs['device_ms']:.1f} ms")
     return out
@@ -512,6 +523,8 @@ def main():
         log("[bench] cpu baseline (oracle) ...")
         cpu = cpu_baseline(c2_piston_tetm_fp32())
         log(f"[bench] cpu baseline {cpu['value']:.3e} cell-updates/s on {cpu['cores']} cores")
+        if not args.no_cyl and not args.cyl_only:
+            cpu["reduced"] = cpu_baseline_reduced()
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
     cf.load()
@@ -528,9 +541,9 @@ def main():
         log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
         del a, b
     if args.cyl_only:
-        rec = bench_cyl(cf, torch, cpu_sample=False, quick=args.cyl_quick)
+        rec = bench_cyl(cf, torch, quick=args.cyl_quick)
         if not args.cyl_quick:
-            rec["kz"] = bench_kz(cf, torch, cpu_sample=False)
+            rec["kz"] = bench_kz(cf, torch)
         print(json.dumps(rec), flush=True)
         return
     prob = cf.Problem.from_workload(wl)
@@ -654,8 +667,8 @@ def main():
     if not args.no_serve:
         out["serving"] = bench_serving(cf, torch, args, rate_3d)
     if not args.no_cyl:
-        out["cylindrical"] = bench_cyl(cf, torch, cpu_sample=not args.no_cpu)
-        out["kz"] = bench_kz(cf, torch, cpu_sample=not args.no_cpu)
+        out["cylindrical"] = bench_cyl(cf, torch)
+        out["kz"] = bench_kz(cf, torch)
 
     gold = os.path.join(ROOT, "tests", "golden", "c2_piston_tetm_oracle.json")
     if os.path.exists(gold) and not args.n_steps:
