@@ -194,10 +194,11 @@ typedef struct cf_surface {
  * server are not available (CF_E_UNSUPPORTED).  Execution: by
  * default one launch per wave of resident channels (any mix of orders),
  * each block carrying one channel through all its steps; tile_variant 1
- * keeps the fields in registers with an LDS exchange (grids of up to 4096
- * cells in FP32, 2048 in FP64, when the device's LDS holds 3 values per
- * cell; otherwise variant 2 runs), 2 keeps them in global memory, 0 picks 1
- * when it fits.  CF_FLAG_SPLIT (and CF_PATH_PLAIN) use one launch per half
+ * keeps the fields in registers with an LDS exchange (real runs: grids of up
+ * to 10240 cells in FP32, 6144 in FP64; complex runs, both parts in
+ * registers: 6144 and 3072; and only when the device's LDS holds the
+ * exchange array of 3 values per cell and part; otherwise variant 2 runs),
+ * 2 keeps them in global memory, 0 picks 1 when it fits.  CF_FLAG_SPLIT (and CF_PATH_PLAIN) use one launch per half
  * step.  All give bitwise-identical results; cf_result.fused/tile_variant
  * report the variant that ran.
  */
@@ -239,7 +240,9 @@ typedef struct cf_opts {
     int tile_variant;   /* fused kernel variant (2D tile shape, or 3D band shape): 0 = autotune (timed on */
                         /* the solve's own data, cached per shape in the      */
                         /* process and in $CF_AUTOTUNE_CACHE when set),       */
-                        /* k >= 1 = variant k-1.  Results do not depend on it. */
+                        /* k >= 1 = variant k-1.  3D: 1..4 one time step per  */
+                        /* launch, 5..6 two (paired steps; an odd last step   */
+                        /* on the one-step shape).  Results do not depend on it. */
     double stop_tol;    /* time-convergence stop (Appendix A, Fig. 12): 0 = off.  Every */
     int stop_every;     /* stop_every steps (0: 500) the partial force F(T') is formed   */
                         /* from the FP64 accumulators; the run ends once two consecutive */
