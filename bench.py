@@ -62,6 +62,32 @@ def measured_traffic(variant):
     return rec["hbm_bytes_per_launch"], rec.get("command", "")
 
 
+TRAFFIC_RECORD_3D = os.path.join(ROOT, "profiles", "traffic_k_f3d2_sphere_plate_192_fp32.json")
+
+
+def kernel3d_source_hash():
+    """sha256 over the sources of the fused 3D kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels3d.hip", "device.hpp", "yee_common.hpp"):
+        with open(os.path.join(ROOT, "paper_0906_5170_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic_3d(variant):
+    """HBM bytes per launch of the fused 3D kernel from its committed counter
+    record, or None when the record does not match the source or variant."""
+    if not os.path.exists(TRAFFIC_RECORD_3D):
+        return None, "no counter record"
+    rec = json.load(open(TRAFFIC_RECORD_3D))
+    if rec.get("source_sha256") != kernel3d_source_hash():
+        return None, "kernel source changed since the counters were taken"
+    if rec.get("tile_variant") != variant:
+        return None, f"counters taken on variant {rec.get('tile_variant')}, not {variant}"
+    return rec["hbm_bytes_per_launch"], rec.get("command", "")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -149,12 +175,16 @@ def bench_3d(cf, torch, n_chan=64, n_steps=200, variant=0):
         cu_s = rv["stencil_cell_updates"] / (rv["stencil_ms_avg"] * 1e-3) if rv["stencil_ms_avg"] else None
         sweep.append({"variant": v, "fused": rv["fused"], "stencil_cell_updates_per_s": cu_s})
     step_rate = r["stencil_cell_updates"] / (r["stencil_ms_avg"] * 1e-3) if r["stencil_ms_avg"] else None
+    traffic, traffic_note = measured_traffic_3d(r["tile_variant"])
     log(f"[bench] 3d: {rate:.3e} cell-updates/s over the solve, stencil {step_rate:.3e}")
     return {"workload": f"sphere over indented plate 192^3 res 48, z CPML 16, {n_chan} of {C} channels "
                         f"x {n_steps} steps, FP32 fields", "value": rate, "unit": "cell-updates/s",
             "stencil_cell_updates_per_s": step_rate,
             "stencil_frac_of_hbm_ceiling": step_rate / ceiling if step_rate else None,
             "hbm_ceiling_cell_updates_per_s": ceiling, "fused": r["fused"], "variant": r["tile_variant"],
+            "avg_launch_ms": r["stencil_ms_avg"], "cell_updates_per_launch": r["stencil_cell_updates"],
+            "traffic_bytes_per_launch": traffic, "traffic_note": traffic_note,
+            "real_hbm_GBps": traffic / (r["stencil_ms_avg"] * 1e-3) / 1e9 if traffic and r["stencil_ms_avg"] else None,
             "variant_sweep": sweep,
             "projected_full_solve_s": 1280 * wl.n_cells * wl.n_steps / rate}
 
