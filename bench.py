@@ -189,6 +189,41 @@ def bench_3d(cf, torch, n_chan=64, n_steps=200, variant=0):
             "projected_full_solve_s": 1280 * wl.n_cells * wl.n_steps / rate}
 
 
+def bench_3d_full(cf, torch, waves=3, precision="fp32", run=None):
+    """The whole 3D sphere-over-indented-plate force solve (192^3, 1280
+    channels, T = 6000, FP32 fields): the channels in `waves` equal channel
+    waves, each all resident on the GPU (about 160 GB each), one solve per
+    wave; the force is the sum of the waves' forces (it is linear in the
+    channels)."""
+    from casimir_inputs import c4_sphere_plate
+    wl = c4_sphere_plate()
+    p = cf.Problem.from_workload(wl)
+    o = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol=wl.pol, kernel=wl.kernel,
+             precision=precision)
+    C = p.info(**o)["n_channels"]
+    parts = np.array_split(np.arange(C), waves)
+    ws = torch.empty(p.info(**dict(o, max_resident=len(parts[0])))["workspace_bytes"], dtype=torch.uint8,
+                     device="cuda")
+    force, cu, dev_ms = 0.0, 0.0, 0.0
+    t0 = time.perf_counter()
+    run = list(range(waves)) if run is None else list(run)
+    for k, sub in enumerate(parts):
+        if k not in run:
+            continue
+        r = p.solve(workspace=ws, channel_subset=sub.tolist(), max_resident=len(sub), **o)
+        force += r["force"]
+        cu += r["cell_updates"]
+        dev_ms += r["device_ms"]
+        log(f"[bench] c4 full: wave {k + 1}/{waves} ({len(sub)} channels) {r['device_ms'] / 1e3:.1f} s, "
+            f"variant {r['tile_variant']}, partial force {r['force']:+.6e}")
+    wall = time.perf_counter() - t0
+    return {"workload": f"sphere over indented plate 192^3 res 48, z CPML 16, all {C} channels x {wl.n_steps} "
+                        f"steps, {precision.upper()} fields, {waves} channel waves", "waves_run": run,
+            "force": force, "wall_s": wall,
+            "device_s": dev_ms / 1e3, "cell_updates": cu, "value": cu / (dev_ms * 1e-3),
+            "unit": "cell-updates/s", "workspace_bytes": ws.numel()}
+
+
 def bench_cyl(cf, torch, quick=False):
     """Cylindrical piston (Sec. III D, Fig. 7) at resolution 40, n, m in
     {0, 1, 2}: one whole force point (126 channels; orders 0 and 1 take
@@ -513,6 +548,17 @@ def main():
                     help="fused kernel variant for the headline solve (0: autotuned)")
     ap.add_argument("--with-3d", action="store_true", help="run the 3D sample even with --main-only")
     ap.add_argument("--c4-steps", type=int, default=200, help="time steps of the 3D sample")
+    ap.add_argument("--c4-full", action="store_true",
+                    help="only the whole 3D sphere-plate force solve (1280 channels x 6000 steps, several "
+                         "minutes), in channel waves that fit the GPU's memory")
+    ap.add_argument("--c4-full-precision", default="fp32", choices=("fp32", "fp64"),
+                    help="field precision of --c4-full")
+    ap.add_argument("--c4-full-waves", type=int, default=0,
+                    help="channel waves of --c4-full (0: 3 in FP32, 16 in FP64)")
+    ap.add_argument("--c4-full-from", type=int, default=0, help="first wave of --c4-full to run")
+    ap.add_argument("--c4-full-count", type=int, default=0,
+                    help="waves of --c4-full to run (0: all from --c4-full-from on); the partial force of "
+                         "the waves run is reported")
     ap.add_argument("--c4-variant", type=int, default=0,
                     help="fused 3D variant of the 3D sample (0: autotuned, with a sweep of all variants)")
     ap.add_argument("--no-3d", action="store_true")
@@ -570,6 +616,13 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
         del a, b
+    if args.c4_full:
+        nw = args.c4_full_waves or (3 if args.c4_full_precision == "fp32" else 16)
+        run = range(args.c4_full_from, nw if not args.c4_full_count else
+                    min(nw, args.c4_full_from + args.c4_full_count))
+        print(json.dumps(bench_3d_full(cf, torch, waves=nw, precision=args.c4_full_precision, run=run)),
+              flush=True)
+        return
     if args.cyl_only:
         rec = bench_cyl(cf, torch, quick=args.cyl_quick)
         if not args.cyl_quick:
