@@ -186,16 +186,30 @@ __global__ __launch_bounds__(BX* BY) void k_e3d(T* __restrict__ fields, T* __res
 // The arithmetic of every cell is that of k_h3d followed by k_e3d.
 constexpr int kF3MaxPml = 64;   // CPML layers the fused 3D step stages in LDS
 
+// LDS of a fused 3D block (dynamic, carved in this order): the kind's
+// coefficient pairs [6][256], the E exchange rows [W][2][CX][64], the H
+// exchange rows [W][2][CX][64] and the CPML coefficients [4][2 kF3MaxPml].
+template <typename T>
+constexpr size_t f3_lds_bytes(int W, int CX) {
+    return (size_t)6 * 256 * 2 * sizeof(T) + (size_t)2 * W * 2 * CX * 64 * sizeof(T) +
+           (size_t)4 * 2 * kF3MaxPml * sizeof(T);
+}
+constexpr size_t kF3LdsMax = 160 * 1024;   // LDS of a gfx950 CU
+
 template <typename T, int W, int B, int CX>
 __global__ __launch_bounds__(64 * W) void k_f3d(const ChanDev* __restrict__ ch, const int* __restrict__ slots,
                                                  Grid3D g, const T* __restrict__ lut, const T* __restrict__ src,
                                                  T* __restrict__ dst, const T* __restrict__ psrc,
                                                  T* __restrict__ pdst, int band) {
     constexpr int NTB = 64 * W;
-    __shared__ yee::Pair<T> L[6][256];
-    __shared__ T xe[W][2][CX][64];     // first region row of each wave: Ez, Ex (read by the wave below)
-    __shared__ T xh[W][2][CX][64];     // last region row of each wave: Hz, Hx (read by the wave above)
-    __shared__ T Lz[4][2 * kF3MaxPml];    // CPML b, c at H and E z positions of the layer planes
+    extern __shared__ double f3_lds[];
+    yee::Pair<T> (*L)[256] = reinterpret_cast<yee::Pair<T> (*)[256]>(f3_lds);   // [6][256] coefficient pairs
+    char* const lds_xe = reinterpret_cast<char*>(f3_lds) + (size_t)6 * 256 * 2 * sizeof(T);
+    char* const lds_xh = lds_xe + (size_t)W * 2 * CX * 64 * sizeof(T);
+    T (*xe)[2][CX][64] = reinterpret_cast<T (*)[2][CX][64]>(lds_xe);   // first region row of each wave: Ez, Ex
+    T (*xh)[2][CX][64] = reinterpret_cast<T (*)[2][CX][64]>(lds_xh);   // last region row of each wave: Hz, Hx
+    T (*Lz)[2 * kF3MaxPml] =                                           // CPML b, c of the layer planes
+        reinterpret_cast<T (*)[2 * kF3MaxPml]>(lds_xh + (size_t)W * 2 * CX * 64 * sizeof(T));
     const ChanDev d = ch[slots[blockIdx.y]];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int yb = blockIdx.x * band - 1;            // global y of region row 0
@@ -547,10 +561,14 @@ __global__ __launch_bounds__(64 * W) void k_f3d2(const ChanDev* __restrict__ ch,
                                                   T* __restrict__ pdst, T* __restrict__ shadow, ShadowBox sb,
                                                   int band) {
     constexpr int NTB = 64 * W;
-    __shared__ yee::Pair<T> L[6][256];
-    __shared__ T xe[W][2][CX][64];     // first region row of each wave: Ez, Ex (read by the wave below)
-    __shared__ T xh[W][2][CX][64];     // last region row of each wave: Hz, Hx (read by the wave above)
-    __shared__ T Lz[4][2 * kF3MaxPml];
+    extern __shared__ double f3_lds[];
+    yee::Pair<T> (*L)[256] = reinterpret_cast<yee::Pair<T> (*)[256]>(f3_lds);   // [6][256] coefficient pairs
+    char* const lds_xe = reinterpret_cast<char*>(f3_lds) + (size_t)6 * 256 * 2 * sizeof(T);
+    char* const lds_xh = lds_xe + (size_t)W * 2 * CX * 64 * sizeof(T);
+    T (*xe)[2][CX][64] = reinterpret_cast<T (*)[2][CX][64]>(lds_xe);   // first region row of each wave: Ez, Ex
+    T (*xh)[2][CX][64] = reinterpret_cast<T (*)[2][CX][64]>(lds_xh);   // last region row of each wave: Hz, Hx
+    T (*Lz)[2 * kF3MaxPml] =                                           // CPML b, c of the layer planes
+        reinterpret_cast<T (*)[2 * kF3MaxPml]>(lds_xh + (size_t)W * 2 * CX * 64 * sizeof(T));
     const ChanDev d = ch[slots[blockIdx.y]];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int yb = blockIdx.x * band - 2;            // global y of region row 0
@@ -978,9 +996,24 @@ constexpr int kNumF3 = sizeof(kF3) / sizeof(kF3[0]);
 
 template <typename T, int W, int CX>
 constexpr bool f3_fits() {
-    return (size_t)2 * W * 2 * CX * 64 * sizeof(T) + (size_t)6 * 256 * 2 * sizeof(T) +
-               (size_t)4 * 2 * kF3MaxPml * sizeof(T) <=
-           65536;
+    return f3_lds_bytes<T>(W, CX) <= kF3LdsMax;
+}
+
+// LDS a block may take on the current device
+inline size_t f3_device_lds() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 65536;
+    return (size_t)v;
+}
+
+// A dynamic LDS size above 64 KB needs the kernel's attribute raised first
+// (once per kernel instantiation).
+template <typename K>
+bool f3_lds_attr(K kernel, size_t bytes) {
+    if (bytes <= 65536) return true;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes) == hipSuccess;
 }
 
 template <typename T, int W, int B, int CX, int STEPS>
@@ -997,12 +1030,17 @@ hipError_t f3_launch(const ChanDev* ch, const int* slots, int nslots, const Grid
         int nzc = (int)std::min<long>((4096 + xy - 1) / xy, std::max(1, g.nz / 24));
         nzc = std::max(1, std::min(nzc, 65535));
         dim3 grid(bands, nslots, nzc), block(64 * W, 1, 1);
+        constexpr size_t lds = f3_lds_bytes<T>(W, CX);
         if constexpr (STEPS == 1) {
-            hipLaunchKernelGGL((k_f3d<T, W, B, CX>), grid, block, 0, s, ch, slots, g, lut, src, dst, psrc, pdst,
+            static const bool attr = f3_lds_attr(&k_f3d<T, W, B, CX>, lds);
+            if (!attr) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_f3d<T, W, B, CX>), grid, block, lds, s, ch, slots, g, lut, src, dst, psrc, pdst,
                                band);
         } else {
             if (shadow == nullptr || sb.vol <= 0) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_f3d2<T, W, B, CX>), grid, block, 0, s, ch, slots, g, lut, src, dst, psrc, pdst,
+            static const bool attr = f3_lds_attr(&k_f3d2<T, W, B, CX>, lds);
+            if (!attr) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_f3d2<T, W, B, CX>), grid, block, lds, s, ch, slots, g, lut, src, dst, psrc, pdst,
                                shadow, sb, band);
         }
         return hipGetLastError();
@@ -1023,13 +1061,9 @@ hipError_t f3_dispatch_cx(int cx, const ChanDev* ch, const int* slots, int nslot
 }
 
 template <typename T>
-constexpr bool f3_variant_fits(int v, int cx) {
-    bool ok = false;
-    const int W = kF3[v].W;
-    const size_t bytes = (size_t)2 * W * 2 * cx * 64 * sizeof(T) + (size_t)6 * 256 * 2 * sizeof(T) +
-                         (size_t)4 * 2 * kF3MaxPml * sizeof(T);
-    ok = bytes <= 65536;
-    return ok;
+bool f3_variant_fits(int v, int cx) {
+    const size_t bytes = f3_lds_bytes<T>(kF3[v].W, cx);
+    return bytes <= kF3LdsMax && bytes <= f3_device_lds();
 }
 }  // namespace
 
