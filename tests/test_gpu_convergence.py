@@ -57,8 +57,12 @@ def test_stop_off_with_channel_waves(cf):
     np.testing.assert_array_equal(r["per_channel"], full["per_channel"])
 
 
-def test_stop_3d(cf):
-    announce("convergence stop, 3D fused step")
+@pytest.mark.parametrize("variant,every", [(0, 50), (6, 25)])
+def test_stop_3d(cf, variant, every):
+    """variant 6 is the two-step fused kernel: steps advance in pairs, so an
+    odd check interval is met one step late; the stopped force is still the
+    full run's partial force at the step the run ended."""
+    announce(f"convergence stop, 3D fused step, tile_variant {variant}, every {every}")
     nx, ny, nz, pml = 12, 12, 26, 4
     zlo = pml + 2
     prims = [Box((-BIG, -BIG, -BIG), (BIG, BIG, zlo), 1), Sphere((nx / 2 + 0.3, ny / 2, zlo + 5.5), 1.7, 2)]
@@ -75,11 +79,15 @@ def test_stop_3d(cf):
     checks = np.arange(50, wl.n_steps + 1, 50)
     d = np.abs(np.diff(tr[checks - 1])) / abs(F)
     tol = float(2 * d[-6:].max())
-    r = p.solve(**opts_of(wl, stop_tol=tol, stop_every=50))
+    r = p.solve(**opts_of(wl, stop_tol=tol, stop_every=every, tile_variant=variant))
     T = r["n_steps_run"]
-    print(f"[stop] 3d: tol {tol:.2e}, {T} of {wl.n_steps} steps, "
+    print(f"[stop] 3d: tol {tol:.2e}, {T} of {wl.n_steps} steps, variant {r['tile_variant']}, "
           f"rel diff {abs(r['force'] / F - 1):.2e}", flush=True)
-    assert r["fused"] and T < wl.n_steps and T % 50 == 0
+    assert r["fused"] and T < wl.n_steps
+    if variant == 6:
+        assert r["tile_variant"] == 6 and T % 2 == 0 and T % every in (0, 1)
+    else:
+        assert T % every == 0
     # the stopped run's force is the full run's partial force at that step
     assert r["force"] == pytest.approx(tr[T - 1], rel=1e-9)
 
