@@ -585,8 +585,8 @@ def main():
     if args.cyl_only:
         args.no_cpu = True
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the channel-parallel "
-              "multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding the channels over "
+              "several GPUs is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
