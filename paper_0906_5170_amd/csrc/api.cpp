@@ -332,12 +332,16 @@ TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, c
 // tiles.  Each channel is assigned whole to the XCD queue with the fewest
 // tiles so far; block b = 8 i + x takes item i of queue x, so every tile of
 // a channel runs on XCD x (blocks are dispatched to XCDs round-robin).
-std::vector<cf::WorkItem> make_work(const std::vector<int>& slots, const std::vector<int>& ntiles) {
+std::vector<cf::WorkItem> make_work(const std::vector<int>& slots, const std::vector<int>& ntiles,
+                                    const std::vector<int>& stile) {
     std::vector<std::vector<cf::WorkItem>> q(8);
     std::vector<long> load(8, 0);
     for (size_t k = 0; k < slots.size(); ++k) {
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        for (int t = 0; t < ntiles[k]; ++t) q[x].push_back({slots[k], t});
+        const int first = stile[k] >= 0 && stile[k] < ntiles[k] ? stile[k] : 0;
+        q[x].push_back({slots[k], first});
+        for (int t = 0; t < ntiles[k]; ++t)
+            if (t != first) q[x].push_back({slots[k], t});
         load[x] += ntiles[k];
     }
     size_t len = 0;
@@ -828,8 +832,8 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     std::deque<cf::InstDev> host_inst;
     // work list of one wave's channels of one polarization for plan pl
     auto upload_work = [&](const int* list, int n, const TBPlan& pl, size_t slot_off, int* nwork) -> hipError_t {
-        std::vector<int> sl(list, list + n), nt(n, pl.ntx * pl.nty);
-        host_work.push_back(make_work(sl, nt));
+        std::vector<int> sl(list, list + n), nt(n, pl.ntx * pl.nty), st(n, pl.stile);
+        host_work.push_back(make_work(sl, nt, st));
         *nwork = (int)host_work.back().size();
         if ((size_t)*nwork > L.work_items) return hipErrorInvalidValue;
         return hipMemcpyAsync(dwork + slot_off, host_work.back().data(), *nwork * sizeof(cf::WorkItem),
@@ -1426,12 +1430,13 @@ cf_status run_batch(const BatchPlan& B, const BatchLayout& L, const cf_opts& o, 
         return I;
     };
     auto work_for = [&](int v, const std::vector<int>& slots) {
-        std::vector<int> nt;
+        std::vector<int> nt, st;
         for (int sl : slots) {
             const int i = B.dev[sl].inst;
             nt.push_back(B.st[i].plans[v].ntx * B.st[i].plans[v].nty);
+            st.push_back(B.st[i].plans[v].stile);
         }
-        return make_work(slots, nt);
+        return make_work(slots, nt, st);
     };
     const int n_tm = (int)B.tm.size(), n_te = (int)B.te.size();
     hipError_t err = hipSuccess;

@@ -375,7 +375,10 @@ template <typename T>
 hipError_t rebuild_group(cf_server* S) {
     std::vector<cf::ChanDev> ch;
     std::vector<cf::InstDev> inst;
-    std::map<std::pair<int, int>, std::pair<std::vector<int>, std::vector<int>>> lists;   // (v, pol) -> slots, tiles
+    struct SlotTiles {
+        std::vector<int> first, second, third;   // slots, tiles per slot, surface tile per slot
+    };
+    std::map<std::pair<int, int>, SlotTiles> lists;   // (v, pol) -> slots, tiles, surface tiles
     for (auto& rp : S->active) {
         Req& r = *rp;
         if (!r.fused) continue;
@@ -417,12 +420,13 @@ hipError_t rebuild_group(cf_server* S) {
             auto& l = lists[{r.variant, r.chans[c].pol}];
             l.first.push_back(slot);
             l.second.push_back(pl.ntx * pl.nty);
+            l.third.push_back(pl.stile);
         }
     }
     std::vector<cf::WorkItem> work;
     std::vector<cf_server::Launch> launches;
     for (auto& kv : lists) {
-        std::vector<cf::WorkItem> w = cfi::make_work(kv.second.first, kv.second.second);
+        std::vector<cf::WorkItem> w = cfi::make_work(kv.second.first, kv.second.second, kv.second.third);
         launches.push_back({kv.first.first, kv.first.second, work.size(), (int)w.size()});
         work.insert(work.end(), w.begin(), w.end());
     }

@@ -87,7 +87,12 @@ struct ConvergenceStop {
 // Stage the tables of one problem for the given channels and options.
 void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel>& chans, Staged& st);
 // XCD-balanced work list (see api.cpp).
-std::vector<cf::WorkItem> make_work(const std::vector<int>& slots, const std::vector<int>& ntiles);
+// Work list of the fused 2D launch: the tiles of each slot on one XCD
+// (channels balanced over the 8 XCDs, block b on XCD b mod 8), each slot's
+// surface tile stile[k] first (its block does the per-step surface work, so
+// it should not be left for the tail of the launch).
+std::vector<cf::WorkItem> make_work(const std::vector<int>& slots, const std::vector<int>& ntiles,
+                                    const std::vector<int>& stile);
 // Host reduction of accumulators into a cf_result; false if not finite.
 bool fill_result(const cf::Problem& p, const std::vector<cf::Channel>& chans, const std::vector<double>& acc,
                  const std::vector<double>& gam, const cf_opts& o, double ms, const StencilTiming& tim,
