@@ -554,7 +554,7 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
                                                   double* __restrict__ gamma, int gamma_stride) {
     constexpr int NP = CPLX ? 2 : 1;               // parts: real (and imaginary)
     extern __shared__ double lds_dyn[];
-    __shared__ double red[yee::kSurfThreads / 64];
+    __shared__ double red[yee::kSurfThreads / 64];   // wave partials of the pending measurement
     const int n = (int)g.ncell;
     T* X = reinterpret_cast<T*>(lds_dyn);          // 3 n exchange values per part
     T* Lg = X;                                      // the kind's full table, for the start (before X is used)
@@ -625,13 +625,23 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
         comp = acc[2 * slot + 1];
     }
     auto pair = [&](int cmp, uint32_t w) { return Lc + ((cmp << 4) + (int)((w >> (4 * cmp)) & 15)) * 2; };
+    // The surface sum of a step is split: its wave partials are formed right
+    // after the exchange array holds the measured fields, with no barrier of
+    // their own, and thread 0 adds them up behind the next barrier of the
+    // half steps.  One partial buffer suffices: thread 0 reads it before the
+    // barrier after that, and the next partials are written later still.
+    int pending = -1;                    // step whose partials wait in red
     auto measure = [&](int step) {
-        const double s = yee::block_surface_sum(d, t, [&](int32_t idx) { return (double)Xq[idx]; }, red);
-        if (threadIdx.x == 0) {
-            const double G = dA * s;
-            yee::neumaier(sum, comp, (dt * ktab[step]) * G);
-            if (gamma) gamma[(int64_t)step * gamma_stride + slot] = G;
+        yee::wave_surface_partials(d, t, [&](int32_t idx) { return (double)Xq[idx]; }, red);
+        pending = step;
+    };
+    auto finish = [&]() {               // call right after a barrier
+        if (pending >= 0 && threadIdx.x == 0) {
+            const double G = dA * yee::wave_partials_total(red);
+            yee::neumaier(sum, comp, (dt * ktab[pending]) * G);
+            if (gamma) gamma[(int64_t)pending * gamma_stride + slot] = G;
         }
+        pending = -1;
     };
     for (int step = 0; step < nsteps; ++step) {
         asm volatile("" : "+v"(i0), "+v"(j0));
@@ -674,6 +684,7 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
             }
         }
         __syncthreads();
+        finish();
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -727,6 +738,7 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
             }
         }
         __syncthreads();
+        finish();
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -741,6 +753,8 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
         __syncthreads();
         if (!meas_h) measure(step);
     }
+    __syncthreads();
+    finish();
     if (threadIdx.x == 0) {
         acc[2 * slot] = sum;
         acc[2 * slot + 1] = comp;

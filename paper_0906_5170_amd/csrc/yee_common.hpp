@@ -80,9 +80,11 @@ __device__ __forceinline__ void neumaier(double& sum, double& comp, double term)
 // wave and over the kSurfThreads / 64 waves.  Every thread of the block must
 // call it (it holds a barrier); the total is returned in thread 0.
 // `fetch(idx)` reads the measured component at flat grid index idx.
+// First part of the sum, without a barrier: the per-wave partial sums of the
+// first kSurfThreads threads land in red[0 .. kSurfThreads / 64 - 1].
 template <typename Fetch>
-__device__ __forceinline__ double block_surface_sum(const ChanDev& d, const SurfTables& t, Fetch fetch,
-                                                    double* red) {
+__device__ __forceinline__ void wave_surface_partials(const ChanDev& d, const SurfTables& t, Fetch fetch,
+                                                      double* red) {
     double s = 0.0;
     const int n = threadIdx.x < kSurfThreads ? d.nsamp : 0;
     for (int i = threadIdx.x; i < n; i += kSurfThreads) {
@@ -94,9 +96,21 @@ __device__ __forceinline__ double block_surface_sum(const ChanDev& d, const Surf
     }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if ((threadIdx.x & 63) == 0 && threadIdx.x < kSurfThreads) red[threadIdx.x >> 6] = s;
+}
+
+// The fixed-order total of the wave partials (after a barrier that follows
+// wave_surface_partials).
+__device__ __forceinline__ double wave_partials_total(const double* red) {
+    return ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+template <typename Fetch>
+__device__ __forceinline__ double block_surface_sum(const ChanDev& d, const SurfTables& t, Fetch fetch,
+                                                    double* red) {
+    wave_surface_partials(d, t, fetch, red);
     __syncthreads();
     double tot = 0.0;
-    if (threadIdx.x == 0) tot = ((red[0] + red[1]) + red[2]) + red[3];
+    if (threadIdx.x == 0) tot = wave_partials_total(red);
     return tot;
 }
 
