@@ -62,6 +62,26 @@ def measured_traffic(variant):
     return rec["hbm_bytes_per_launch"], rec.get("command", "")
 
 
+VALU_RECORD = os.path.join(ROOT, "profiles", "valu_k_rb2d_piston2d_400x200_tetm_fp32.json")
+# VALU issue ceiling: 256 CUs x 4 SIMDs, each issuing one wave64 vector
+# instruction every 4 cycles (16 lanes per SIMD), at 2.4 GHz
+VALU_PEAK_WAVE_INSTR = 256 * 4 * 2.4e9 / 4
+
+
+def measured_valu(variant):
+    """Wave-level VALU instructions per launch of the fused 2D kernel
+    (SQ_INSTS_VALU, mean over the TM and TE kernels) from the committed
+    counter record, or None when it does not match the source or variant."""
+    if not os.path.exists(VALU_RECORD):
+        return None, "no counter record"
+    rec = json.load(open(VALU_RECORD))
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None, "kernel source changed since the counters were taken"
+    if rec.get("tile_variant") != variant:
+        return None, f"counters taken on variant {rec.get('tile_variant')}, not {variant}"
+    return rec["valu_wave_instr_per_launch"], rec.get("command", "")
+
+
 TRAFFIC_RECORD_3D = os.path.join(ROOT, "profiles", "traffic_k_f3d2_sphere_plate_192_fp32.json")
 
 
@@ -668,6 +688,13 @@ def main():
                 "alg_bytes_per_launch": rt["stencil_alg_bytes"],
                 "alg_bytes_per_cell_update": rt["stencil_alg_bytes"] / rt["stencil_cell_updates"],
                 "tile_variant": rt["tile_variant"], "steps_per_launch": rt["tile_halo"]}
+    # the kernel beats the algorithmic HBM ceiling (several steps per launch
+    # in registers); its own limit is vector-instruction issue
+    valu, valu_note = measured_valu(rt["tile_variant"])
+    roofline["valu"] = {"achieved": valu / avg_s if (valu and avg_s > 0) else None,
+                        "peak": VALU_PEAK_WAVE_INSTR, "unit": "VALU wave-instructions/s",
+                        "frac": valu / avg_s / VALU_PEAK_WAVE_INSTR if (valu and avg_s > 0) else None,
+                        "instr_per_launch": valu, "note": valu_note}
 
     out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
