@@ -326,7 +326,11 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
             }
     }
 #define CF_K(s, j, r) (CREG ? k##s[(j) % KJ][(r) % KB] : L[s][CF_ID(m##s##p, j, r)])
-    for (int step = 0; step < ksteps; ++step) {
+    // Unrolled over the KH steps of a launch: a rolled loop ends every step
+    // with a copy of each field into the register the next step reads.
+#pragma unroll
+    for (int step = 0; step < KH; ++step) {
+        if (step >= ksteps) break;
         // ---- H half: needs the E row above the wave's band ----
         T e_above[CX];
 #pragma unroll
