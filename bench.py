@@ -278,6 +278,26 @@ def bench_cyl(cf, torch, quick=False):
            "paper_quote": "about 5 minutes per force point on 8 processors (2009), res 40, n,m in {0,1,2}"}
     log(f"[bench] cyl: force point {wall:.3f} s wall ({r['device_ms']:.1f} ms device), {rate:.3e} cell-updates/s, "
         f"split {rs['device_ms']:.1f} ms, fp64 {r64['device_ms']:.1f} ms")
+    # a sweep of four clearances: one at a time, then as one batch (the
+    # reduced solves run concurrently and share the CUs a single force point
+    # leaves idle)
+    hs = [0.4, 0.5, 0.6, 0.7]
+    sweep = [cf.Problem.from_workload(c_cyl_piston(h_u=h)) for h in hs]
+    cf.batch_solve(sweep, **dict(o, n_steps=200))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    seq = [q.solve(**o)["force"] for q in sweep]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    bat = [x["force"] for x in cf.batch_solve(sweep, **o)]
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t1
+    assert bat == seq, (bat, seq)
+    out["sweep4"] = {"clearances": hs, "one_at_a_time_wall_s": t_seq, "batched_wall_s": t_bat,
+                     "force_points_per_s": len(hs) / t_bat, "speedup": t_seq / t_bat}
+    log(f"[bench] cyl sweep of {len(hs)} clearances: {t_seq:.3f} s one at a time, {t_bat:.3f} s batched "
+        f"({len(hs) / t_bat:.1f} force points/s)")
     return out
 
 

@@ -335,8 +335,12 @@ cf_status cf_solve(cf_problem* p, const cf_opts* opts, void* workspace, size_t w
  * with the same options, advanced together.  2D problems whose stress
  * surfaces fit the fused kernel's tiles share one fused launch sequence:
  * every launch advances the channels of all of them (each problem keeps its
- * own grid, materials, surface and coefficient table).  Any other problem is
- * solved on its own as by cf_solve.  outs[i] receives problem i's result;
+ * own grid, materials, surface and coefficient table).  Reduced problems
+ * (cylindrical, k_z, Bloch), when there are two or more, are solved
+ * concurrently: up to four host threads, each with a stream of its own
+ * (default priority) that first waits for the work queued on opts->stream,
+ * take them in turn, each result bitwise as by cf_solve.  Any other problem
+ * is solved on its own as by cf_solve.  outs[i] receives problem i's result;
  * channel_subset, max_resident and CF_FLAG_KEEP_GAMMA are not used.
  * workspace is NULL (allocated internally) or a device buffer of at least
  * cf_batch_workspace_size() bytes. */

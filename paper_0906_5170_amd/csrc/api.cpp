@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -15,6 +16,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/casimir_fdtd.h"
@@ -1695,9 +1697,18 @@ cf_status cf_solve(cf_problem* h, const cf_opts* o, void* workspace, size_t ws_b
 }
 
 
+// Reduced problems of a batch (cylindrical, k_z, Bloch) are solved
+// concurrently by this many host threads, each with its own stream and
+// workspace slot: one such solve runs one block per channel, often on fewer
+// CUs than the chip has, so several of them share the GPU.
+constexpr int kRedWorkers = 4;
+
+static size_t ws_align(size_t b) { return (b + 255) & ~size_t(255); }
+
 cf_status cf_batch_workspace_size(cf_problem* const* probs, int n, const cf_opts* o, size_t* bytes) {
     if (!probs || n < 1 || !o || !bytes) return fail(CF_E_ARG, "bad batch arguments");
-    size_t solo = 0;
+    size_t solo = 0, red_max = 0;
+    int n_red = 0;
     std::vector<cf_problem*> fused;
     for (int i = 0; i < n; ++i) {
         cf_status st = cf_validate(probs[i], o);
@@ -1710,13 +1721,64 @@ cf_status cf_batch_workspace_size(cf_problem* const* probs, int n, const cf_opts
         st = cf_workspace_size(probs[i], &oo, &b);
         if (st != CF_OK) return st;
         solo = std::max(solo, b);
+        if (probs[i]->p.reduced()) {
+            ++n_red;
+            red_max = std::max(red_max, ws_align(b));
+        }
     }
     size_t fb = 0;
     if (!fused.empty()) {
         BatchPlan B;
         if (plan_batch(fused.data(), (int)fused.size(), *o, B).empty()) fb = batch_layout(B, *o).total;
     }
-    *bytes = std::max(solo, fb);
+    const size_t rb = n_red >= 2 ? (size_t)std::min(n_red, kRedWorkers) * red_max : 0;
+    *bytes = std::max({solo, fb, rb});
+    return CF_OK;
+}
+
+// Solve probs[idx[..]] concurrently (see kRedWorkers); slot k of the
+// workspace is [k * slot, (k + 1) * slot).  Work already queued on the
+// caller's stream finishes before any of them starts.
+static cf_status solve_concurrently(cf_problem* const* probs, const std::vector<int>& idx, const cf_opts& oo,
+                                    char* ws, size_t slot, cf_result* outs) {
+    const int nw = std::min((int)idx.size(), kRedWorkers);
+    int dev = 0;
+    CF_HIP(hipGetDevice(&dev));
+    hipEvent_t ready;
+    CF_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ready, static_cast<hipStream_t>(oo.stream));
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(ready);
+        return fail(CF_E_DEVICE, std::string("device step failed: ") + hipGetErrorString(e));
+    }
+    std::atomic<int> next{0};
+    std::vector<cf_status> status(nw, CF_OK);
+    std::vector<std::string> msg(nw);
+    auto worker = [&](int k) {
+        hipStream_t s = nullptr;
+        hipError_t he = hipSetDevice(dev);
+        if (he == hipSuccess) he = hipStreamCreate(&s);                 // default priority
+        if (he == hipSuccess) he = hipStreamWaitEvent(s, ready, 0);
+        if (he != hipSuccess) {
+            status[k] = CF_E_DEVICE;
+            msg[k] = std::string("device step failed: ") + hipGetErrorString(he);
+        }
+        for (int j; status[k] == CF_OK && (j = next.fetch_add(1)) < (int)idx.size();) {
+            cf_opts oi = oo;
+            oi.stream = s;
+            const int i = idx[j];
+            status[k] = cf_solve(probs[i], &oi, ws + (size_t)k * slot, slot, &outs[i]);
+            if (status[k] != CF_OK) msg[k] = cf_last_error();
+        }
+        if (s) (void)hipStreamDestroy(s);
+    };
+    std::vector<std::thread> pool;
+    for (int k = 1; k < nw; ++k) pool.emplace_back(worker, k);
+    worker(0);
+    for (auto& t : pool) t.join();
+    (void)hipEventDestroy(ready);
+    for (int k = 0; k < nw; ++k)
+        if (status[k] != CF_OK) return fail(status[k], msg[k]);
     return CF_OK;
 }
 
@@ -1769,6 +1831,31 @@ cf_status cf_batch_solve(cf_problem* const* probs, int n, const cf_opts* o, void
             if (!finite) return fail(CF_E_NONFINITE, "a force accumulator is not finite");
             done[i] = true;
         }
+    }
+    std::vector<int> red_idx;
+    size_t red_max = 0;
+    for (int i = 0; i < n; ++i)
+        if (!done[i] && probs[i]->p.reduced()) {
+            size_t b = 0;
+            cf_status st = cf_workspace_size(probs[i], &oo, &b);
+            if (st != CF_OK) return st;
+            red_max = std::max(red_max, ws_align(b));
+            red_idx.push_back(i);
+        }
+    if (red_idx.size() >= 2) {
+        const size_t need = (size_t)std::min((int)red_idx.size(), kRedWorkers) * red_max;
+        char* ws = static_cast<char*>(workspace);
+        void* owned = nullptr;
+        if (!ws) {
+            CF_HIP(hipMalloc(&owned, need));
+            ws = static_cast<char*>(owned);
+        } else if (ws_bytes < need) {
+            return fail(CF_E_BUDGET, "workspace smaller than cf_batch_workspace_size()");
+        }
+        cf_status st = solve_concurrently(probs, red_idx, oo, ws, red_max, outs);
+        if (owned) (void)hipFree(owned);
+        if (st != CF_OK) return st;
+        for (int i : red_idx) done[i] = true;
     }
     for (int i = 0; i < n; ++i) {
         if (done[i]) continue;

@@ -42,6 +42,7 @@
 // projection, in a single launch for channels of any mix of orders, with the
 // fields in registers (LDS neighbour exchange) or in global memory (a
 // channel's block stays in the L2 of its XCD).
+#include <mutex>
 #include <type_traits>
 
 #include "../../include/casimir_fdtd.h"
@@ -789,17 +790,25 @@ inline size_t device_lds_limit() {
     return (size_t)v;
 }
 
-// Dynamic LDS above 64 KB needs the kernel's attribute raised first; false
-// when the runtime refuses (the caller then takes the global-memory variant).
+// Dynamic LDS above 64 KB needs the kernel's attribute raised first.  The
+// attribute is a cap and is only ever raised (under a lock), so solves on
+// concurrent host threads never lower it below what another one launches
+// with; false when the runtime refuses (the caller then takes the
+// global-memory variant).
 template <typename T, int K, int NTH, bool CYL, bool CPLX>
 bool regs_lds_ok(size_t lds) {
     if (lds <= 65536) return true;
+    static std::mutex mu;
+    static size_t cap = 65536;
+    std::lock_guard<std::mutex> lk(mu);
+    if (lds <= cap) return true;
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_red_regs<T, K, NTH, CYL, CPLX>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return false;
     }
+    cap = lds;
     return true;
 }
 

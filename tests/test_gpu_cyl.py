@@ -253,6 +253,30 @@ def test_batch_solve_runs_cylindrical_problems_alone(cf):
     np.testing.assert_array_equal(both[0]["per_channel"], alone["per_channel"])
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_solves_reduced_problems_concurrently_bitwise(cf, precision):
+    """Five cylindrical pistons in one cf_batch_solve (clearances with tubes
+    of 6, 7, 8, 9 and 11 rows at resolution 10, so every force differs): the
+    reduced problems are solved concurrently, four host threads with a
+    stream each taking them in turn; every result equals the problem's own
+    cf_solve bit for bit."""
+    announce(f"batch of five cylindrical pistons, concurrent, {precision}")
+    hs = [0.5, 0.6, 0.9, 1.0, 1.5]
+    wls = [cyl_piston(res=10, h_u=h, length_u=15.0, n_harm=3, m_max=2, n_steps=400, precision=precision)
+           for h in hs]
+    probs = [cf.Problem.from_workload(w) for w in wls]
+    opts = dict(sigma=1.0, courant=0.5, n_steps=400, pol="3D", kernel="general", precision=precision)
+    both = cf.batch_solve(probs, **opts)
+    forces = []
+    for p, r in zip(probs, both):
+        alone = p.solve(**opts)
+        np.testing.assert_array_equal(r["per_channel"], alone["per_channel"])
+        assert r["force"] == alone["force"]
+        forces.append(r["force"])
+    assert len(set(forces)) == len(hs)              # each result belongs to its own problem
+    print(f"[cyl] batch of {len(hs)}: forces {forces}", flush=True)
+
+
 def test_benchmark_force_point_vs_oracle_golden(cf):
     """The whole res-40 force point against the FP64 oracle (stored by
     tests/golden/make_golden.py): FP64 fields to 1e-9 of the term
