@@ -16,6 +16,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -1767,13 +1768,27 @@ static cf_status solve_concurrently(cf_problem* const* probs, const std::vector<
             cf_opts oi = oo;
             oi.stream = s;
             const int i = idx[j];
-            status[k] = cf_solve(probs[i], &oi, ws + (size_t)k * slot, slot, &outs[i]);
-            if (status[k] != CF_OK) msg[k] = cf_last_error();
+            try {
+                status[k] = cf_solve(probs[i], &oi, ws + (size_t)k * slot, slot, &outs[i]);
+                if (status[k] != CF_OK) msg[k] = cf_last_error();
+            } catch (const std::bad_alloc&) {   // nothing may escape a worker thread
+                status[k] = CF_E_BUDGET;
+                msg[k] = "host allocation failed";
+            } catch (const std::exception& ex) {
+                status[k] = CF_E_DEVICE;
+                msg[k] = ex.what();
+            }
         }
         if (s) (void)hipStreamDestroy(s);
     };
     std::vector<std::thread> pool;
-    for (int k = 1; k < nw; ++k) pool.emplace_back(worker, k);
+    for (int k = 1; k < nw; ++k) {
+        try {
+            pool.emplace_back(worker, k);
+        } catch (const std::system_error&) {   // the started workers take the rest
+            break;
+        }
+    }
     worker(0);
     for (auto& t : pool) t.join();
     (void)hipEventDestroy(ready);
