@@ -245,17 +245,18 @@ def bench_3d_full(cf, torch, waves=3, precision="fp32", run=None):
 
 
 def bench_cyl(cf, torch, quick=False):
-    """Cylindrical piston (Sec. III D, Fig. 7) at resolution 40, n, m in
+    """Cylindrical piston (Sec. III C, Fig. 7) at resolution 40, n, m in
     {0, 1, 2}: one whole force point (126 channels; orders 0 and 1 take
-    10000 steps, order 2 15000 on its smaller step), FP32 fields, on the
-    resident kernel; the split half-step path and FP64 beside it.  The paper
-    quotes about 5 minutes on 8 processors per such force point (2009 CPUs,
-    time span unstated)."""
+    10000 steps, order 2 15000 on its smaller step) at the default FP64
+    fields on the resident kernel; the split half-step path and FP32 fields
+    (a stated-error option: its channel terms cancel by 3e8, see the
+    precision record) beside it.  The paper quotes about 5 minutes on 8
+    processors per such force point (2009 CPUs, time span unstated)."""
     from casimir_inputs import c_cyl_piston
     wl = c_cyl_piston()
     p = cf.Problem.from_workload(wl)
     o = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol="3D", kernel=wl.kernel,
-             precision="fp32")
+             precision=wl.precision)
     p.solve(**dict(o, n_steps=200))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -266,18 +267,21 @@ def bench_cyl(cf, torch, quick=False):
         return {"force": r["force"], "device_ms": r["device_ms"], "value": rate, "unit": "cell-updates/s",
                 "resident_variant": r["tile_variant"], "launch_ms": r["stencil_ms_avg"]}
     rs = p.solve(split=True, **o)
-    r64 = p.solve(**dict(o, precision="fp64"))
-    alg = rate * 48.0                                  # read + write of 6 FP32 values per cell-update
+    r32 = p.solve(**dict(o, precision="fp32"))
+    fsz = 8.0 if wl.precision == "fp64" else 4.0
+    alg = rate * 12.0 * fsz                            # read + write of 6 field values per cell-update
     out = {"workload": f"cylindrical piston res 40, h 0.5, tube {wl.shape[0]} x {wl.shape[1]} (z x r), "
-                       f"n_harm 3, m 0..2, {r['n_channels']} channels, T 10000 (order 2: 15000), FP32",
-           "force": r["force"], "force_fp64_fields": r64["force"],
+                       f"n_harm 3, m 0..2, {r['n_channels']} channels, T 10000 (order 2: 15000), "
+                       f"{wl.precision.upper()} fields",
+           "precision": wl.precision, "force": r["force"], "force_fp32_fields": r32["force"],
            "force_point_wall_s": wall, "device_ms": r["device_ms"], "value": rate, "unit": "cell-updates/s",
            "resident_variant": r["tile_variant"], "split_path_device_ms": rs["device_ms"],
-           "speedup_vs_split": rs["device_ms"] / r["device_ms"], "fp64_device_ms": r64["device_ms"],
+           "speedup_vs_split": rs["device_ms"] / r["device_ms"], "fp32_device_ms": r32["device_ms"],
+           "fp32_resident_variant": r32["tile_variant"],
            "alg_bytes_per_s": alg, "alg_frac_of_hbm_peak": alg / (HBM_PEAK_GBS * 1e9),
            "paper_quote": "about 5 minutes per force point on 8 processors (2009), res 40, n,m in {0,1,2}"}
-    log(f"[bench] cyl: force point {wall:.3f} s wall ({r['device_ms']:.1f} ms device), {rate:.3e} cell-updates/s, "
-        f"split {rs['device_ms']:.1f} ms, fp64 {r64['device_ms']:.1f} ms")
+    log(f"[bench] cyl: force point {wall:.3f} s wall ({r['device_ms']:.1f} ms device, {wl.precision}), "
+        f"{rate:.3e} cell-updates/s, split {rs['device_ms']:.1f} ms, fp32 {r32['device_ms']:.1f} ms")
     # a sweep of four clearances: one at a time, then as one batch (the
     # reduced solves run concurrently and share the CUs a single force point
     # leaves idle)
@@ -304,7 +308,7 @@ def bench_cyl(cf, torch, quick=False):
 def bench_kz(cf, torch):
     """z-invariant dielectric piston (eps = 4 blocks between PEC slabs; the
     C1 geometry: res 20, 80 x 40, 16 harmonics, T = 2000) integrated over
-    k_z with 8-point Gauss-Legendre on [0, 12] (Sec. III C: dielectrics
+    k_z with 8-point Gauss-Legendre on [0, 12] (Sec. III B: dielectrics
     hybridize the polarizations): 8 six-component runs in one launch, FP32."""
     from casimir_inputs import dielectric_piston2d, kz_gauss, kz_workload
     base = dielectric_piston2d(80, 40, 10, 20, 10, 20, 15, 20.0, n_steps=2000, n_harm=16, precision="fp32")
@@ -551,6 +555,9 @@ def bench_precision(cf, torch):
         r64 = p.solve(precision="fp64", **o)
         acc_ref = np.array(ref["per_channel"])
         res["cylindrical"] = {"workload": "cylindrical piston res 40, n, m in {0, 1, 2}, T=10000",
+                              "default_precision": wl.precision,
+                              "default_force_rel_err": abs((r64 if wl.precision == "fp64" else r32)["force"]
+                                                           / ref["force"] - 1),
                               "fp32_force_rel_err": abs(r32["force"] / ref["force"] - 1),
                               "fp64_force_rel_err": abs(r64["force"] / ref["force"] - 1),
                               "fp32_channel_err_of_largest": float(np.max(np.abs(r32["per_channel"] - acc_ref))
@@ -757,7 +764,7 @@ def main():
             set_wl = c3_uneven_set(side)
             T_b = set_wl[0].n_steps
             probs = [cf.Problem.from_workload(w) for w in set_wl]
-            bo = dict(opts, n_steps=T_b)
+            bo = dict(opts, n_steps=T_b, kernel=set_wl[0].kernel)
             cf.batch_solve(probs, graph=True, **dict(bo, n_steps=16))
             torch.cuda.synchronize()
             t1 = time.perf_counter()

@@ -39,6 +39,9 @@ def piston2d(nx: int, ny: int, slab_px: int, block_w: int, block_h: int, gap: in
     are PEC, the left one ending at x = (nx - gap)//2 and the right one
     starting gap pixels later; both span y in [block_y0, block_y0 + block_h].
     ``sidewall`` is "pec", "pmc" or "mu5" (a magnetic slab with mu = 5).
+    The time kernel defaults to the z-invariant one (Appendix A.2), which
+    holds for perfect conductors in vacuum; with mu = 5 slabs it defaults to
+    the general kernel (the force of the two-dimensional system).
     """
     eps = [1.0, PEC, 1.0]
     mu = [1.0, 1.0, 1.0]
@@ -67,8 +70,8 @@ def piston2d(nx: int, ny: int, slab_px: int, block_w: int, block_h: int, gap: in
     gap_above = (ny - slab_px) - y1
     gap_right = nx - right_hi
     m = _margin(min(gap, gap_below, gap_above, gap_right))
-    kw = dict(sigma=1.0, courant=0.5, n_steps=1000, pol="TM", kernel="zinv2d",
-              precision="fp64")
+    kw = dict(sigma=1.0, courant=0.5, n_steps=1000, pol="TM",
+              kernel="general" if sidewall == "mu5" else "zinv2d", precision="fp64")
     kw.update(opts)
     return Workload(
         name=kw.pop("name", f"piston2d_{nx}x{ny}"), ndim=2, shape=(nx, ny, 1), res=float(res),
@@ -116,7 +119,9 @@ def c2_piston_tetm_fp32(**over) -> Workload:
 
 def c3_uneven_set(sidewall: str = "pec", n_inst: int = 24, res: int = 40, **over) -> List[Workload]:
     """24 pistons with total clearance h in linspace(0.1, 2.0), grid height
-    round(res*(2+h)) (84..160 px at res 40), 0.75-unit sidewall slabs."""
+    round(res*(2+h)) (84..160 px at res 40), 0.75-unit sidewall slabs.
+    PEC and PMC sidewalls use the z-invariant kernel; mu = 5 sidewalls the
+    general kernel (Appendix A.2 assumes perfect conductors in vacuum)."""
     out = []
     for h in np.linspace(0.1, 2.0, n_inst):
         ny = int(round(res * (2.0 + h)))
@@ -124,7 +129,8 @@ def c3_uneven_set(sidewall: str = "pec", n_inst: int = 24, res: int = 40, **over
         block_h = int(round(0.5 * res))
         clear = ny - 2 * slab - block_h
         y0 = slab + clear // 2
-        kw = dict(pol="TM+TE", precision="fp32", n_steps=10000, kernel="zinv2d", n_harm=40,
+        kw = dict(pol="TM+TE", precision="fp32", n_steps=10000,
+                  kernel="general" if sidewall == "mu5" else "zinv2d", n_harm=40,
                   name=f"c3_{sidewall}_h{h:.3f}_400x{ny}")
         kw.update(over)
         w = piston2d(int(round(10 * res)), ny, slab, int(round(res)), block_h, int(round(res)), y0,
@@ -204,7 +210,7 @@ def c4_sphere_plate(**over) -> Workload:
 
 def cyl_piston(res: int = 40, h_u: float = 0.5, length_u: float = 10.0, n_harm: int = 3, m_max: int = 2,
                sidewall: str = "pec", margin: int = 2, **opts) -> Workload:
-    """Cylindrically symmetric piston (Sec. III D, Fig. 7): the 2D piston's
+    """Cylindrically symmetric piston (Sec. III C, Fig. 7): the 2D piston's
     blocks rotated about their common axis become two PEC cylinders of
     radius 0.25 and length 1.0, a = 1.0 apart on the axis, inside a tube
     whose wall lies h/2 outside them (the sidewalls joined into a tube).
@@ -252,8 +258,12 @@ def cyl_piston(res: int = 40, h_u: float = 0.5, length_u: float = 10.0, n_harm: 
 
 def c_cyl_piston(**over) -> Workload:
     """Cylindrical piston at resolution 40, h = 0.5, n, m in {0, 1, 2}
-    (3 harmonics per face, orders 0..2), 10000 steps, FP32 fields."""
-    kw = dict(res=40, h_u=0.5, n_harm=3, m_max=2, n_steps=10000, precision="fp32",
+    (3 harmonics per face, orders 0..2), 10000 steps, FP64 fields.  The two
+    end faces of S carry channel terms of about 5e3 that cancel to the force
+    of 2.6e-4; FP32 fields round the part after the mirror symmetry of the
+    two ends breaks at about 1e-3 of the force, so FP64 is the default here
+    (FP32 stays available with that stated error)."""
+    kw = dict(res=40, h_u=0.5, n_harm=3, m_max=2, n_steps=10000, precision="fp64",
               name="cyl_piston_res40_h0.5")
     kw.update(over)
     return cyl_piston(**kw)
@@ -279,7 +289,7 @@ def dielectric_piston2d(nx: int, ny: int, slab_px: int, block_w: int, block_h: i
                         res: float, eps_block: float = 4.0, n_harm: int = 16, **opts) -> Workload:
     """The 2D piston with dielectric blocks (eps_block) instead of PEC ones,
     between PEC sidewall slabs: a z-invariant geometry whose two
-    polarizations hybridize at k_z != 0 (Sec. III C)."""
+    polarizations hybridize at k_z != 0 (Sec. III B)."""
     wl = piston2d(nx, ny, slab_px, block_w, block_h, gap, block_y0, res, n_harm=n_harm, **opts)
     eps = [1.0, PEC, float(eps_block)]
     left, right = wl.meta["blocks"]

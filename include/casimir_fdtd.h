@@ -17,8 +17,9 @@
  *
  * Conventions shared by every entry point:
  *   - Every function returns cf_status (CF_OK == 0) and never throws or
- *     aborts on bad input; cf_last_error() returns a thread-local message
- *     describing the most recent failure on the calling thread.
+ *     aborts: bad input gives its status, a failed host allocation inside
+ *     the library CF_E_BUDGET; cf_last_error() returns a thread-local
+ *     message describing the most recent failure on the calling thread.
  *   - Units: hbar = c = eps_0 = mu_0 = 1.  Lengths are in units of the
  *     geometry (1/res per cell); time step dt = courant / res.
  *   - Arrays passed in are host memory, read during the call and copied;
@@ -75,7 +76,7 @@ enum { CF_EX = 0, CF_EY, CF_EZ, CF_HX, CF_HY, CF_HZ };
 
 /*
  * Coordinates (cf_grid.coord).  CF_COORD_CYLINDRICAL describes a problem
- * with cylindrical symmetry (Sec. III D; Appendix, harmonic expansion in
+ * with cylindrical symmetry (Sec. III C; Appendix, harmonic expansion in
  * cylindrical coordinates): fields proportional to exp(i m phi) reduce to
  * the (r, z) half plane, solved once per azimuthal order m = 0..m_max.
  *   - ndim = 2; axis 0 is z (the symmetry axis, n[0] cells), axis 1 is r
@@ -97,9 +98,9 @@ enum { CF_COORD_CARTESIAN = 0, CF_COORD_CYLINDRICAL = 1, CF_COORD_KZ = 2 };
 
 /*
  * CF_COORD_KZ describes a z-invariant two-dimensional problem solved at
- * Bloch wavevectors k_z along the invariant axis (Sec. III C: dielectrics
+ * Bloch wavevectors k_z along the invariant axis (Sec. III B: dielectrics
  * hybridize the polarizations, so every k_z is its own two-dimensional
- * simulation; Sec. III E: the force as an integral over the wavevectors).
+ * simulation; Sec. III D: the force as an integral over the wavevectors).
  *   - ndim = 2, bc[0], bc[1] CF_BC_PEC or CF_BC_PERIODIC; the grid, the
  *     materials and S as for a Cartesian 2D problem.
  *   - Fields proportional to exp(i k z) with E_z, H_x, H_y carried as
@@ -115,7 +116,7 @@ enum { CF_COORD_CARTESIAN = 0, CF_COORD_CYLINDRICAL = 1, CF_COORD_KZ = 2 };
  *     satisfy courant * v_max * sqrt(8 + (k_max / res)^2) / 2 < 1.
  *   - Channels, labels (q * n_harm + n) and signs (times kz_weight[q]) are
  *     ordered as for cylindrical orders.
- *   - Bloch-periodic x (Sec. III E, a cell periodic in x with period
+ *   - Bloch-periodic x (Sec. III D, a cell periodic in x with period
  *     L = n[0] / res): kx[q] != 0 at any point makes the fields complex
  *     (quasi-periodic: F(x + L) = exp(i kx L) F(x)); bc[0] must be
  *     CF_BC_PERIODIC and S must not reach across the periodic x edge (no
@@ -369,8 +370,9 @@ const char* cf_last_error(void);
  * is bitwise the same alone and in any mix, and equals cf_solve with the
  * same options and tile_variant (fused 2D) or CF_FLAG_SPLIT (others).
  *
- * Ownership: the problem handle passed to cf_server_submit must stay alive
- * until its request is done, failed or cancelled.  cf_server_destroy cancels
+ * Ownership: cf_server_submit copies the problem into the request, so the
+ * caller may destroy its handle as soon as the call returns.  A request that
+ * has finished keeps only what its result needs.  cf_server_destroy cancels
  * what is still queued or running and must not overlap other calls on the
  * same server.  All other calls are thread-safe. */
 typedef struct cf_server cf_server;

@@ -1,4 +1,4 @@
-"""Bloch-periodic boundaries along x for z-invariant problems (Sec. III E:
+"""Bloch-periodic boundaries along x for z-invariant problems (Sec. III D:
 for a system periodic in x with period L the force is an integral over the
 Bloch wavevectors k_x of one unit cell, each a simulation with
 Bloch-periodic boundaries; with the k_z runs of oracle.kz this covers a cell

@@ -1,5 +1,5 @@
 """Yee leapfrog in cylindrical coordinates for one azimuthal order m (Sec.
-III D, three dimensions with cylindrical symmetry; Appendix, harmonic
+III C, three dimensions with cylindrical symmetry; Appendix, harmonic
 expansion in cylindrical coordinates).  Test infrastructure: only tests/,
 the package smoke check and the benchmark's CPU baseline use this module.
 

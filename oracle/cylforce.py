@@ -1,4 +1,4 @@
-"""Force on an object in a cylindrically symmetric geometry (Sec. III D;
+"""Force on an object in a cylindrically symmetric geometry (Sec. III C;
 Appendix, harmonic expansion in cylindrical coordinates).  Test
 infrastructure: only tests/, the package smoke check and the benchmark's CPU
 baseline use this module.

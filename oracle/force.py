@@ -161,9 +161,27 @@ def run_gammas(wl, chans, faces, bases, eps_s, mu_s, n_steps: int, workers: int 
     return gam
 
 
+def zinv_premise_holds(wl) -> bool:
+    """Appendix A.2 derives the z-invariant kernel for perfect conductors
+    in vacuum (TE and TM decouple at every k_z with the vacuum dispersion):
+    every material the grid uses must be vacuum or a perfect conductor."""
+    used = set()
+    for name in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):
+        arr = wl.comp_ids.get(name) if wl.comp_ids else None
+        used |= {0} if arr is None else set(np.unique(np.asarray(arr)).tolist())
+    for i in used:
+        e, m = float(wl.eps[i]), float(wl.mu[i])
+        conductor = (np.isinf(e) and e < 0) or (np.isinf(m) and m < 0)
+        if not conductor and not (e == 1.0 and m == 1.0):
+            return False
+    return True
+
+
 def solve(wl, basis: str = "dct", workers: int = 1, keep_gamma: bool = False,
           n_steps: Optional[int] = None, chunk: int = 64, start: str = "consistent",
           channel_subset=None) -> OracleResult:
+    if wl.kernel == "zinv2d" and not zinv_premise_holds(wl):
+        raise ValueError("the z-invariant kernel (Appendix A.2) holds for perfect conductors in vacuum only")
     T = int(wl.n_steps if n_steps is None else n_steps)
     faces, bases, eps_s, mu_s, chans = setup(wl, basis)
     dt = wl.courant / wl.res

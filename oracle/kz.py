@@ -1,6 +1,6 @@
 """z-invariant two-dimensional problems at a Bloch wavevector k along the
-invariant axis (Sec. III C: dielectrics hybridize the two polarizations, so
-every k_z is its own two-dimensional simulation; Sec. III E: the force as an
+invariant axis (Sec. III B: dielectrics hybridize the two polarizations, so
+every k_z is its own two-dimensional simulation; Sec. III D: the force as an
 integral over the Bloch wavevectors).  Test infrastructure: only tests/, the
 package smoke check and the benchmark's CPU baseline use this module.
 

@@ -398,8 +398,9 @@ class Server:
     """Continuous-batching force-solve server on the current GPU (see
     cf_server_create).  The device memory budget is one torch uint8 tensor
     handed to the library as its arena; the scheduler runs on a stream of
-    its own.  Problems submitted are kept alive here until their results
-    have been taken."""
+    its own.  The library copies each submitted problem into its request, so
+    the Problem objects need not outlive their requests; the binding keeps
+    them only to size the result buffers."""
 
     def __init__(self, budget_bytes: int, precision: str = "fp32", tile_variant: int = 0):
         import torch
@@ -460,7 +461,9 @@ class Server:
         return {k: getattr(i, k) for k, _ in _ServerInfo._fields_}
 
     def release(self, ticket: int):
-        """Drop the problem reference kept for a finished request."""
+        """Forget a request on the Python side (the library keeps its own
+        copy of the problem, so this is safe at any time; the ticket can no
+        longer be polled through this object afterwards)."""
         self._reqs.pop(ticket, None)
 
     def close(self):

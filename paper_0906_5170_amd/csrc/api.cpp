@@ -38,6 +38,15 @@ cf_status fail(cf_status code, const std::string& msg) {
     return code;
 }
 
+cf_status fail_nothrow(cf_status code, const char* msg) noexcept {
+    try {
+        g_err = msg;
+    } catch (...) {
+        g_err.clear();
+    }
+    return code;
+}
+
 void clear_error() { g_err.clear(); }
 
 #define CF_HIP(expr)                                                                  \
@@ -1561,11 +1570,9 @@ bdone:
 
 using namespace cfi;
 
-extern "C" {
+// ---- entry points: bodies (no C linkage) -----------------------------------
 
-const char* cf_last_error(void) { return g_err.c_str(); }
-
-cf_status cf_problem_create(const cf_grid* grid, const cf_materials* mats, const cf_surface* surf,
+static cf_status cf_problem_create_impl(const cf_grid* grid, const cf_materials* mats, const cf_surface* surf,
                             cf_problem** out) {
     if (!grid || !mats || !surf || !out) return fail(CF_E_ARG, "null argument");
     *out = nullptr;
@@ -1581,12 +1588,12 @@ cf_status cf_problem_create(const cf_grid* grid, const cf_materials* mats, const
     return CF_OK;
 }
 
-cf_status cf_problem_destroy(cf_problem* p) {
+static cf_status cf_problem_destroy_impl(cf_problem* p) {
     delete p;
     return CF_OK;
 }
 
-cf_status cf_validate(const cf_problem* h, const cf_opts* o) {
+static cf_status cf_validate_impl(const cf_problem* h, const cf_opts* o) {
     if (!h || !o) return fail(CF_E_ARG, "null argument");
     cf_status code;
     std::string err = cf::validate_opts(h->p, *o, &code);
@@ -1599,7 +1606,7 @@ cf_status cf_validate(const cf_problem* h, const cf_opts* o) {
     return CF_OK;
 }
 
-cf_status cf_problem_info(const cf_problem* h, const cf_opts* o, cf_info* out) {
+static cf_status cf_problem_info_impl(const cf_problem* h, const cf_opts* o, cf_info* out) {
     cf_status st = cf_validate(h, o);
     if (st != CF_OK) return st;
     if (!out) return fail(CF_E_ARG, "null argument");
@@ -1621,7 +1628,7 @@ cf_status cf_problem_info(const cf_problem* h, const cf_opts* o, cf_info* out) {
     return CF_OK;
 }
 
-cf_status cf_channel_table(const cf_problem* h, const cf_opts* o, int n, int* face, int* label,
+static cf_status cf_channel_table_impl(const cf_problem* h, const cf_opts* o, int n, int* face, int* label,
                            int* kind, int* src, int* meas, double* sign) {
     cf_status st = cf_validate(h, o);
     if (st != CF_OK) return st;
@@ -1638,7 +1645,7 @@ cf_status cf_channel_table(const cf_problem* h, const cf_opts* o, int n, int* fa
     return CF_OK;
 }
 
-cf_status cf_workspace_size(const cf_problem* h, const cf_opts* o, size_t* bytes) {
+static cf_status cf_workspace_size_impl(const cf_problem* h, const cf_opts* o, size_t* bytes) {
     cf_info info;
     cf_status st = cf_problem_info(h, o, &info);
     if (st != CF_OK) return st;
@@ -1647,14 +1654,14 @@ cf_status cf_workspace_size(const cf_problem* h, const cf_opts* o, size_t* bytes
     return CF_OK;
 }
 
-cf_status cf_kernel_table(int kernel, double sigma, double dt, int n, double* out) {
+static cf_status cf_kernel_table_impl(int kernel, double sigma, double dt, int n, double* out) {
     if (!out || n < 0 || !(dt > 0) || !(sigma >= 0)) return fail(CF_E_ARG, "bad kernel table arguments");
     if (kernel != CF_KERNEL_GENERAL && kernel != CF_KERNEL_ZINV2D) return fail(CF_E_ARG, "unknown kernel");
     cf::kernel_table(kernel, sigma, dt, n, out);
     return CF_OK;
 }
 
-cf_status cf_solve(cf_problem* h, const cf_opts* o, void* workspace, size_t ws_bytes, cf_result* out) {
+static cf_status cf_solve_impl(cf_problem* h, const cf_opts* o, void* workspace, size_t ws_bytes, cf_result* out) {
     cf_status st = cf_validate(h, o);
     if (st != CF_OK) return st;
     if (!out) return fail(CF_E_ARG, "null result");
@@ -1706,7 +1713,7 @@ constexpr int kRedWorkers = 4;
 
 static size_t ws_align(size_t b) { return (b + 255) & ~size_t(255); }
 
-cf_status cf_batch_workspace_size(cf_problem* const* probs, int n, const cf_opts* o, size_t* bytes) {
+static cf_status cf_batch_workspace_size_impl(cf_problem* const* probs, int n, const cf_opts* o, size_t* bytes) {
     if (!probs || n < 1 || !o || !bytes) return fail(CF_E_ARG, "bad batch arguments");
     size_t solo = 0, red_max = 0;
     int n_red = 0;
@@ -1797,7 +1804,7 @@ static cf_status solve_concurrently(cf_problem* const* probs, const std::vector<
     return CF_OK;
 }
 
-cf_status cf_batch_solve(cf_problem* const* probs, int n, const cf_opts* o, void* workspace, size_t ws_bytes,
+static cf_status cf_batch_solve_impl(cf_problem* const* probs, int n, const cf_opts* o, void* workspace, size_t ws_bytes,
                          cf_result* outs) {
     if (!probs || n < 1 || !o || !outs) return fail(CF_E_ARG, "bad batch arguments");
     cf_opts oo = *o;
@@ -1879,6 +1886,56 @@ cf_status cf_batch_solve(cf_problem* const* probs, int n, const cf_opts* o, void
     }
     g_err.clear();
     return CF_OK;
+}
+
+
+// ---- the C ABI: every entry point runs its body under cfi::guarded ---------
+
+extern "C" {
+
+const char* cf_last_error(void) { return g_err.c_str(); }
+
+cf_status cf_problem_create(const cf_grid* grid, const cf_materials* mats, const cf_surface* surf,
+                            cf_problem** out) {
+    return guarded([&] { return cf_problem_create_impl(grid, mats, surf, out); });
+}
+
+cf_status cf_problem_destroy(cf_problem* p) {
+    return guarded([&] { return cf_problem_destroy_impl(p); });
+}
+
+cf_status cf_validate(const cf_problem* h, const cf_opts* o) {
+    return guarded([&] { return cf_validate_impl(h, o); });
+}
+
+cf_status cf_problem_info(const cf_problem* h, const cf_opts* o, cf_info* out) {
+    return guarded([&] { return cf_problem_info_impl(h, o, out); });
+}
+
+cf_status cf_channel_table(const cf_problem* h, const cf_opts* o, int n, int* face, int* label, int* kind,
+                           int* src, int* meas, double* sign) {
+    return guarded([&] { return cf_channel_table_impl(h, o, n, face, label, kind, src, meas, sign); });
+}
+
+cf_status cf_workspace_size(const cf_problem* h, const cf_opts* o, size_t* bytes) {
+    return guarded([&] { return cf_workspace_size_impl(h, o, bytes); });
+}
+
+cf_status cf_kernel_table(int kernel, double sigma, double dt, int n, double* out) {
+    return guarded([&] { return cf_kernel_table_impl(kernel, sigma, dt, n, out); });
+}
+
+cf_status cf_solve(cf_problem* h, const cf_opts* o, void* workspace, size_t ws_bytes, cf_result* out) {
+    return guarded([&] { return cf_solve_impl(h, o, workspace, ws_bytes, out); });
+}
+
+cf_status cf_batch_workspace_size(cf_problem* const* probs, int n, const cf_opts* o, size_t* bytes) {
+    return guarded([&] { return cf_batch_workspace_size_impl(probs, n, o, bytes); });
+}
+
+cf_status cf_batch_solve(cf_problem* const* probs, int n, const cf_opts* o, void* workspace, size_t ws_bytes,
+                         cf_result* outs) {
+    return guarded([&] { return cf_batch_solve_impl(probs, n, o, workspace, ws_bytes, outs); });
 }
 
 }  // extern "C"

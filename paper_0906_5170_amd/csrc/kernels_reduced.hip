@@ -1,9 +1,9 @@
 // Reduced two-dimensional Yee updates: six components on a 2D grid, one
 // run per "order", for
-//   - cylindrically symmetric problems (Sec. III D; Appendix, harmonic
+//   - cylindrically symmetric problems (Sec. III C; Appendix, harmonic
 //     expansion in cylindrical coordinates), one run per azimuthal order m;
-//   - z-invariant problems at a Bloch wavevector k along z (Sec. III C, one
-//     2D simulation per k_z), optionally Bloch-periodic along x (Sec. III E,
+//   - z-invariant problems at a Bloch wavevector k along z (Sec. III B, one
+//     2D simulation per k_z), optionally Bloch-periodic along x (Sec. III D,
 //     complex fields).
 //
 // Cylindrical.  Fields proportional to exp(i m phi), with E_phi, H_r, H_z

@@ -426,14 +426,26 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
         if (!pec && !(p.eps[i] > 0 && std::isfinite(p.eps[i]))) return "eps must be > 0 or -inf";
         if (!pmc && !(p.mu[i] > 0 && std::isfinite(p.mu[i]))) return "mu must be > 0 or -inf";
     }
+    std::vector<char> used(p.nmat, 0);
     for (int c = 0; c < kNumComp; ++c) {
         if (m.comp_id[c]) {
             p.ids[c].assign(m.comp_id[c], m.comp_id[c] + ncell);
-            for (uint8_t v : p.ids[c])
+            for (uint8_t v : p.ids[c]) {
                 if (v >= p.nmat) return "material id out of range";
+                used[v] = 1;
+            }
         } else {
             p.ids[c].assign(ncell, 0);
+            used[0] = 1;
         }
+    }
+    // Appendix A.2's kernel assumes perfect conductors in vacuum: note
+    // whether every material the grid uses is vacuum or a perfect conductor
+    p.vacuum_conductors = true;
+    for (int i = 0; i < p.nmat; ++i) {
+        if (!used[i]) continue;
+        const bool conductor = (std::isinf(p.eps[i]) && p.eps[i] < 0) || (std::isinf(p.mu[i]) && p.mu[i] < 0);
+        if (!conductor && !(p.eps[i] == 1.0 && p.mu[i] == 1.0)) p.vacuum_conductors = false;
     }
     // E components lying on a PEC(-backed) wall: integer coordinate 0 along
     // a non-periodic axis.
@@ -622,6 +634,12 @@ std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
         }
     } else if (p.grid.ndim == 2) {
         if (o.pol < 1 || o.pol > 3) return "2D runs take CF_POL_TM and/or CF_POL_TE";
+        if (o.kernel == CF_KERNEL_ZINV2D && !p.vacuum_conductors) {
+            *code = CF_E_UNSUPPORTED;
+            return "the z-invariant kernel holds for perfect conductors in vacuum only: a material with "
+                   "finite eps or mu other than 1 mixes the polarizations at k_z != 0 (use the general "
+                   "kernel for the two-dimensional force, or a k_z problem for the force per unit length)";
+        }
     } else {
         if (o.pol != CF_POL_3D) return "3D runs take CF_POL_3D";
         if (o.kernel == CF_KERNEL_ZINV2D) {

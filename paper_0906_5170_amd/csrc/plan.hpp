@@ -84,6 +84,9 @@ struct Problem {
     std::vector<double> kzs, kz_w;            // k_z points and weights
     std::vector<double> kxs;                  // Bloch wavevector along x per point (k_z problems)
     bool bloch = false;                       // complex fields: some kx != 0
+    // every material the grid uses is vacuum (eps = mu = 1) or a perfect
+    // electric / magnetic conductor (the premise of the z-invariant kernel)
+    bool vacuum_conductors = true;
     // reduced two-dimensional problems: six components, one run per order
     // (azimuthal order m, or k_z point q)
     bool reduced() const { return cyl || kz; }

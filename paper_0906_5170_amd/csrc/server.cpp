@@ -53,7 +53,8 @@ enum { ST_QUEUED = 0, ST_RUNNING = 1, ST_DONE = 2, ST_FAILED = 3, ST_CANCELLED =
 
 struct Req {
     uint64_t ticket = 0;
-    const cf::Problem* prob = nullptr;
+    cf::Problem own;                  // the request's copy of the submitted problem
+    const cf::Problem* prob = nullptr;   // == &own
     cf_opts opts{};
     std::vector<cf::Channel> chans;
     cfi::Staged st;
@@ -81,6 +82,28 @@ struct Req {
     double t_submit = 0, t_admit = 0, t_done = 0;
     bool cancel = false;
 };
+
+// A request that has reached a terminal state keeps only what its result
+// needs (faces, grid, channel table, tile shapes): the copied material ids,
+// interpolation tables and upload staging go.
+void drop_tables(Req& r) {
+    for (auto& v : r.own.ids) std::vector<uint8_t>().swap(v);
+    std::vector<cf::Gather>().swap(r.own.gathers);
+    r.own.gather_of.clear();
+    std::vector<uint32_t>().swap(r.idp);
+    std::vector<uint8_t>().swap(r.ids);
+    std::vector<uint8_t>().swap(r.lut);
+    std::vector<double>().swap(r.ktab);
+    std::vector<double>().swap(r.pml);
+    std::vector<int32_t>().swap(r.st.gidx);
+    std::vector<int32_t>().swap(r.st.uidx);
+    std::vector<int32_t>().swap(r.st.uoff);
+    std::vector<int32_t>().swap(r.st.usamp);
+    std::vector<double>().swap(r.st.gw);
+    std::vector<double>().swap(r.st.uw);
+    std::vector<double>().swap(r.st.basis);
+    std::vector<cf::ChanDev>().swap(r.st.dev);
+}
 
 }  // namespace
 
@@ -695,6 +718,7 @@ void loop(cf_server* S) {
             }
             r.t_done = now_s();
             S->arena.release(r.off, r.bytes);
+            drop_tables(r);
             if (r.fused) S->membership_changed = true;
             it = S->active.erase(it);
             S->cv.notify_all();
@@ -709,9 +733,9 @@ std::shared_ptr<Req> find(cf_server* S, uint64_t ticket) {
 
 }  // namespace
 
-extern "C" {
+// ---- entry points: bodies (no C linkage) -----------------------------------
 
-cf_status cf_server_create(size_t hbm_budget_bytes, int precision, int tile_variant, void* arena, void* stream,
+static cf_status cf_server_create_impl(size_t hbm_budget_bytes, int precision, int tile_variant, void* arena, void* stream,
                            cf_server** out) {
     if (!out || hbm_budget_bytes < (size_t)1 << 20) return fail(CF_E_ARG, "bad server arguments");
     if (precision != CF_FP32 && precision != CF_FP64) return fail(CF_E_ARG, "unknown precision");
@@ -767,7 +791,7 @@ cf_status cf_server_create(size_t hbm_budget_bytes, int precision, int tile_vari
     return CF_OK;
 }
 
-cf_status cf_server_submit(cf_server* S, cf_problem* prob, const cf_opts* o, uint64_t* ticket) {
+static cf_status cf_server_submit_impl(cf_server* S, cf_problem* prob, const cf_opts* o, uint64_t* ticket) {
     if (!S || !prob || !o || !ticket) return fail(CF_E_ARG, "null argument");
     if (o->precision != S->precision) return fail(CF_E_ARG, "request precision differs from the server's");
     if (o->path != CF_PATH_BATCHED) return fail(CF_E_ARG, "served requests use the batched path");
@@ -777,7 +801,8 @@ cf_status cf_server_submit(cf_server* S, cf_problem* prob, const cf_opts* o, uin
     cf_status st = cf_validate(prob, o);
     if (st != CF_OK) return st;
     auto r = std::make_shared<Req>();
-    r->prob = &prob->p;
+    r->own = prob->p;                 // the caller may destroy its problem after submitting
+    r->prob = &r->own;
     r->opts = *o;
     r->t_submit = now_s();
     // staging reads only settings fixed at creation: no lock needed
@@ -811,7 +836,7 @@ static cf_status report(cf_server* S, const std::shared_ptr<Req>& r, int* state,
     return CF_OK;
 }
 
-cf_status cf_server_poll(cf_server* S, uint64_t ticket, int* state, cf_result* out) {
+static cf_status cf_server_poll_impl(cf_server* S, uint64_t ticket, int* state, cf_result* out) {
     if (!S) return fail(CF_E_ARG, "null server");
     std::lock_guard<std::mutex> lk(S->mu);
     auto r = find(S, ticket);
@@ -819,7 +844,7 @@ cf_status cf_server_poll(cf_server* S, uint64_t ticket, int* state, cf_result* o
     return report(S, r, state, out);
 }
 
-cf_status cf_server_wait(cf_server* S, uint64_t ticket, double timeout_s, int* state, cf_result* out) {
+static cf_status cf_server_wait_impl(cf_server* S, uint64_t ticket, double timeout_s, int* state, cf_result* out) {
     if (!S) return fail(CF_E_ARG, "null server");
     std::unique_lock<std::mutex> lk(S->mu);
     auto r = find(S, ticket);
@@ -830,7 +855,7 @@ cf_status cf_server_wait(cf_server* S, uint64_t ticket, double timeout_s, int* s
     return report(S, r, state, out);
 }
 
-cf_status cf_server_cancel(cf_server* S, uint64_t ticket) {
+static cf_status cf_server_cancel_impl(cf_server* S, uint64_t ticket) {
     if (!S) return fail(CF_E_ARG, "null server");
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -842,7 +867,7 @@ cf_status cf_server_cancel(cf_server* S, uint64_t ticket) {
     return CF_OK;
 }
 
-cf_status cf_server_times(cf_server* S, uint64_t ticket, double* submit_s, double* admit_s, double* done_s) {
+static cf_status cf_server_times_impl(cf_server* S, uint64_t ticket, double* submit_s, double* admit_s, double* done_s) {
     if (!S) return fail(CF_E_ARG, "null server");
     std::lock_guard<std::mutex> lk(S->mu);
     auto r = find(S, ticket);
@@ -853,7 +878,7 @@ cf_status cf_server_times(cf_server* S, uint64_t ticket, double* submit_s, doubl
     return CF_OK;
 }
 
-cf_status cf_server_stats(cf_server* S, cf_server_info* out) {
+static cf_status cf_server_stats_impl(cf_server* S, cf_server_info* out) {
     if (!S || !out) return fail(CF_E_ARG, "null argument");
     std::lock_guard<std::mutex> lk(S->mu);
     out->submitted = S->n_submitted;
@@ -870,7 +895,7 @@ cf_status cf_server_stats(cf_server* S, cf_server_info* out) {
     return CF_OK;
 }
 
-cf_status cf_server_destroy(cf_server* S) {
+static cf_status cf_server_destroy_impl(cf_server* S) {
     if (!S) return CF_OK;
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -884,6 +909,44 @@ cf_status cf_server_destroy(cf_server* S) {
     if (S->own_arena) (void)hipFree(S->group);
     delete S;
     return CF_OK;
+}
+
+
+// ---- the C ABI: every entry point runs its body under cfi::guarded ---------
+
+extern "C" {
+
+cf_status cf_server_create(size_t hbm_budget_bytes, int precision, int tile_variant, void* arena, void* stream,
+                           cf_server** out) {
+    return cfi::guarded([&] { return cf_server_create_impl(hbm_budget_bytes, precision, tile_variant, arena, stream, out); });
+}
+
+cf_status cf_server_submit(cf_server* S, cf_problem* prob, const cf_opts* o, uint64_t* ticket) {
+    return cfi::guarded([&] { return cf_server_submit_impl(S, prob, o, ticket); });
+}
+
+cf_status cf_server_poll(cf_server* S, uint64_t ticket, int* state, cf_result* out) {
+    return cfi::guarded([&] { return cf_server_poll_impl(S, ticket, state, out); });
+}
+
+cf_status cf_server_wait(cf_server* S, uint64_t ticket, double timeout_s, int* state, cf_result* out) {
+    return cfi::guarded([&] { return cf_server_wait_impl(S, ticket, timeout_s, state, out); });
+}
+
+cf_status cf_server_cancel(cf_server* S, uint64_t ticket) {
+    return cfi::guarded([&] { return cf_server_cancel_impl(S, ticket); });
+}
+
+cf_status cf_server_times(cf_server* S, uint64_t ticket, double* submit_s, double* admit_s, double* done_s) {
+    return cfi::guarded([&] { return cf_server_times_impl(S, ticket, submit_s, admit_s, done_s); });
+}
+
+cf_status cf_server_stats(cf_server* S, cf_server_info* out) {
+    return cfi::guarded([&] { return cf_server_stats_impl(S, out); });
+}
+
+cf_status cf_server_destroy(cf_server* S) {
+    return cfi::guarded([&] { return cf_server_destroy_impl(S); });
 }
 
 }  // extern "C"

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -16,6 +18,25 @@ namespace cfi {
 cf_status fail(cf_status code, const std::string& msg);
 void clear_error();
 size_t align_up(size_t v, size_t a);
+
+// Runs the body of an entry point of the C ABI so that no C++ exception
+// crosses it: a failed host allocation becomes CF_E_BUDGET, any other
+// exception CF_E_ARG, each with its message in cf_last_error().
+cf_status fail_nothrow(cf_status code, const char* msg) noexcept;
+template <class F>
+cf_status guarded(F&& body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc&) {
+        return fail_nothrow(CF_E_BUDGET, "host memory allocation failed");
+    } catch (const std::length_error&) {
+        return fail_nothrow(CF_E_BUDGET, "host array size exceeds the allocator's limit");
+    } catch (const std::exception& e) {
+        return fail_nothrow(CF_E_ARG, e.what());
+    } catch (...) {
+        return fail_nothrow(CF_E_ARG, "unknown internal error");
+    }
+}
 
 // Tiling of the fused kernel: shifted so that every measured surface stencil
 // point of every channel lies in one tile (the surface tile).

@@ -75,9 +75,11 @@ def test_c3_with_mu5_sidewalls_one_graph_sequence(cf):
     """The uneven set with metallic sidewalls and the same set with mu = 5
     magnetic sidewalls (48 problems), FP32, in one graph-captured batched
     sequence (T cut to 120): every problem fused; members equal their own
-    solves bit for bit; a mu = 5 member matches the FP64 oracle."""
+    solves bit for bit; a mu = 5 member matches the FP64 oracle.  One batch
+    takes one set of options, so both sets run with the general kernel (the
+    z-invariant one assumes perfect conductors in vacuum)."""
     announce("c3 metallic + mu=5 sidewalls, 48 problems, one graph sequence, T=120")
-    wls = [w.replace(n_steps=120) for side in ("pec", "mu5") for w in c3_uneven_set(side)]
+    wls = [w.replace(n_steps=120, kernel="general") for side in ("pec", "mu5") for w in c3_uneven_set(side)]
     probs = [cf.Problem.from_workload(w) for w in wls]
     o = opts_of(wls[0])
     res = cf.batch_solve(probs, graph=True, **o)

@@ -1,4 +1,4 @@
-"""GPU parity of Bloch-periodic x runs (complex fields; Sec. III E) against
+"""GPU parity of Bloch-periodic x runs (complex fields; Sec. III D) against
 the FP64 Bloch oracle.
 
 Cases (each printed before it runs): dielectric blocks (eps 4) repeated with

@@ -1,5 +1,5 @@
 """GPU parity of the cylindrical (r, z) path against the FP64 oracle
-(Sec. III D; Appendix, harmonic expansion in cylindrical coordinates).
+(Sec. III C; Appendix, harmonic expansion in cylindrical coordinates).
 
 Cases (each printed before it runs):
 * ``closed``: the cylindrical piston of Fig. 7 at resolution 10 (150 x 7
@@ -279,10 +279,13 @@ def test_batch_solves_reduced_problems_concurrently_bitwise(cf, precision):
 
 def test_benchmark_force_point_vs_oracle_golden(cf):
     """The whole res-40 force point against the FP64 oracle (stored by
-    tests/golden/make_golden.py): FP64 fields to 1e-9 of the term
-    magnitude; FP32 fields with FP64 accumulation to 1e-6 of the largest
-    channel per channel and 5e-3 relative on the force, whose channel terms
-    cancel by about four orders of magnitude in this geometry."""
+    tests/golden/make_golden.py).  The default path (FP64 fields, the
+    workload's precision) meets the 1e-4 target on the force, and 1e-9 of
+    the term magnitude.  FP32 fields are a stated-error option: the two end
+    faces' channel terms (about 5e3 each) cancel to the force (2.6e-4), and
+    FP32 rounding after their mirror symmetry breaks leaves about 1.2e-3 of
+    the force (each channel within 1e-6 of the largest); the test bounds it
+    by 5e-3."""
     import json
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cyl_piston_res40_oracle.json")
@@ -296,8 +299,10 @@ def test_benchmark_force_point_vs_oracle_golden(cf):
     tab = p.channel_table(**o)
     acc = np.array(ref["per_channel"])
     mag = np.sum(np.abs(tab["sign"] * acc)) / np.pi
-    r64 = p.solve(precision="fp64", **o)
+    assert wl.precision == "fp64"
+    r64 = p.solve(precision=wl.precision, **o)
     assert abs(r64["force"] - ref["force"]) <= 1e-9 * mag
+    assert abs(r64["force"] / ref["force"] - 1) <= 1e-4
     r32 = p.solve(precision="fp32", **o)
     ch = np.max(np.abs(r32["per_channel"] - acc)) / np.max(np.abs(acc))
     rel = abs(r32["force"] / ref["force"] - 1)

@@ -1,5 +1,5 @@
-"""GPU parity of z-invariant problems at Bloch wavevectors k_z (Sec. III C,
-Sec. III E) against the FP64 k_z oracle.
+"""GPU parity of z-invariant problems at Bloch wavevectors k_z (Sec. III B,
+Sec. III D) against the FP64 k_z oracle.
 
 Cases (each printed before it runs):
 * ``dielectric``: the 2D piston with eps = 4 blocks between PEC slabs

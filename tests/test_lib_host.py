@@ -246,3 +246,58 @@ def test_bloch_problem_info_and_validation(cf):
         with pytest.raises(cf.CfError) as e:
             cf.Problem.from_workload(kz_workload(_grating(s_lo=lo, s_hi=hi), [0.0], [1.0], kx=[0.3]))
         assert e.value.status == "CF_E_SURFACE"
+
+
+def test_host_allocation_failure_returns_a_status():
+    """No C++ exception crosses the C ABI: with the address space capped, a
+    problem whose material-id copy cannot be allocated gives CF_E_BUDGET and
+    a message, and the process goes on (run in a child process, so the cap
+    stays there)."""
+    import subprocess
+    import sys
+    child = r'''
+import ctypes as C, resource, sys
+sys.path.insert(0, sys.argv[1])
+import paper_0906_5170_amd as cf
+lib = cf.load()
+kb = int([l for l in open("/proc/self/status") if l.startswith("VmSize")][0].split()[1])
+resource.setrlimit(resource.RLIMIT_AS, ((kb + 512 * 1024) * 1024, resource.RLIM_INFINITY))
+g = cf._Grid(); g.ndim = 3; g.coord = 0; g.res = 10.0
+for a in range(3):
+    g.n[a] = 1024; g.bc[a] = 0; g.pml_cells[a] = 0
+eps = (C.c_double * 1)(1.0); mu = (C.c_double * 1)(1.0)
+m = cf._Materials(); m.n_materials = 1; m.eps = eps; m.mu = mu
+s = cf._Surface()
+for a in range(3):
+    s.lo[a] = 500; s.hi[a] = 510
+s.n_harm = 2; s.force_axis = 2
+h = C.c_void_p()
+code = lib.cf_problem_create(C.byref(g), C.byref(m), C.byref(s), C.byref(h))
+print(code, lib.cf_last_error().decode(), flush=True)
+'''
+    r = subprocess.run([sys.executable, "-c", child, ROOT], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    code, msg = r.stdout.strip().split(" ", 1)
+    assert int(code) == 4 and "allocation" in msg, r.stdout
+
+
+def test_zinv_kernel_needs_perfect_conductors_in_vacuum(cf):
+    """Appendix A.2's kernel assumes perfect conductors in vacuum: the library
+    refuses it (CF_E_UNSUPPORTED) when the grid uses any other material,
+    including a medium around S, and accepts PEC and PMC walls."""
+    opts = dict(sigma=1.0, courant=0.5, n_steps=50, pol="TM+TE", precision="fp32")
+    for side in ("pec", "pmc"):
+        wl = piston2d(24, 18, 3, 6, 4, 6, 7, 6.0, sidewall=side)
+        cf.Problem.from_workload(wl).validate(kernel="zinv2d", **opts)
+    mu5 = cf.Problem.from_workload(piston2d(24, 18, 3, 6, 4, 6, 7, 6.0, sidewall="mu5"))
+    fluid = piston2d(24, 18, 3, 6, 4, 6, 7, 6.0)
+    fluid = cf.Problem.from_workload(fluid.replace(eps=[1.8] + list(fluid.eps[1:])))
+    for p in (mu5, fluid):
+        p.validate(kernel="general", **opts)
+        with pytest.raises(cf.CfError) as e:
+            p.validate(kernel="zinv2d", **opts)
+        assert e.value.status == "CF_E_UNSUPPORTED" and "vacuum" in str(e.value)
+    # a material listed in the table but used by no cell does not count
+    spare = piston2d(24, 18, 3, 6, 4, 6, 7, 6.0)
+    assert spare.eps[2] == 1.0
+    cf.Problem.from_workload(spare.replace(eps=list(spare.eps[:2]) + [4.0])).validate(kernel="zinv2d", **opts)

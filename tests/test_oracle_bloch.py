@@ -1,4 +1,4 @@
-"""Pins of the Bloch-periodic oracle (Sec. III E: a cell periodic in x with
+"""Pins of the Bloch-periodic oracle (Sec. III D: a cell periodic in x with
 period L, invariant in z; one simulation per Bloch wavevector (k_x, k_z)).
 
 * Bloch folding, exact on the grid: a supercell of two periods at k_x

@@ -1,5 +1,5 @@
 """Pins of the k_z oracle (z-invariant 2D problems at a Bloch wavevector k
-along the invariant axis: Sec. III C, Sec. III E).
+along the invariant axis: Sec. III B, Sec. III D).
 
 * Exact discrete energy conservation at sigma = 0 for k != 0 with PEC and
   periodic y walls (the k couplings enter the two half steps as transposes).
