@@ -332,6 +332,22 @@ cf_status cf_workspace_size(const cf_problem* p, const cf_opts* opts, size_t* by
 cf_status cf_solve(cf_problem* p, const cf_opts* opts, void* workspace, size_t ws_bytes,
                    cf_result* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cf_solve
+ * with the workspace taken from a fixed array of CF_STATIC_WORKSPACE_BYTES
+ * (64 MiB) in device memory that the library holds on each device it runs
+ * on until the process ends.  It calls no hipMalloc or hipFree.  A solve
+ * whose cf_workspace_size() exceeds the array gives CF_E_BUDGET (use
+ * cf_solve); CF_FLAG_GRAPH gives CF_E_UNSUPPORTED (instantiating a graph
+ * allocates).  Results are bitwise those of cf_solve with the same options.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (each call clears what it reads before writing it): calls
+ * on one device are serialized by a lock inside the library, and work that
+ * another process or module queues on the same memory is not possible, but a
+ * caller must not read the array's previous contents as a result. */
+#define CF_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+cf_status cf_solve_static(cf_problem* p, const cf_opts* opts, cf_result* out);
+
 /* Batched solve: n problems (for instance a sweep of sidewall separations)
  * with the same options, advanced together.  2D problems whose stress
  * surfaces fit the fused kernel's tiles share one fused launch sequence:

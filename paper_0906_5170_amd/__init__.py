@@ -90,7 +90,10 @@ EXPORTS = ("cf_problem_create", "cf_problem_destroy", "cf_problem_info", "cf_cha
            "cf_validate", "cf_workspace_size", "cf_solve", "cf_kernel_table", "cf_last_error",
            "cf_batch_workspace_size", "cf_batch_solve", "cf_server_create", "cf_server_submit",
            "cf_server_poll", "cf_server_wait", "cf_server_cancel", "cf_server_times", "cf_server_stats",
-           "cf_server_destroy")
+           "cf_server_destroy", "cf_solve_static")
+
+# bytes of the device array cf_solve_static takes its workspace from
+STATIC_WORKSPACE_BYTES = 64 << 20
 
 
 def load():
@@ -118,6 +121,7 @@ def load():
     lib.cf_validate.argtypes = [P, C.POINTER(_Opts)]
     lib.cf_workspace_size.argtypes = [P, C.POINTER(_Opts), C.POINTER(C.c_size_t)]
     lib.cf_solve.argtypes = [P, C.POINTER(_Opts), C.c_void_p, C.c_size_t, C.POINTER(_Result)]
+    lib.cf_solve_static.argtypes = [P, C.POINTER(_Opts), C.POINTER(_Result)]
     lib.cf_kernel_table.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_double)]
     lib.cf_batch_workspace_size.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(_Opts),
                                             C.POINTER(C.c_size_t)]
@@ -338,6 +342,24 @@ class Problem:
         _check(load().cf_solve(self._h, C.byref(o), C.c_void_p(workspace.data_ptr()), nbytes, C.byref(r)))
         out = _result_dict(r, bufs)
         return out
+
+    def solve_static(self, **opts) -> dict:
+        """Run the force solve through cf_solve_static: the library's fixed
+        device array is the workspace, and nothing is allocated on the
+        device (CF_E_BUDGET when the solve needs more than
+        STATIC_WORKSPACE_BYTES)."""
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("cf solve needs a ROCm GPU")
+        opts = dict(opts)
+        opts["stream"] = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        info = self.info(**{k: v for k, v in opts.items() if k != "stream"})
+        o = self._opts(**opts)
+        C_run = o.n_subset if o.n_subset > 0 else info["n_channels"]
+        T = info["n_steps_max"]
+        r, bufs = _result_buffers(info["per_harmonic_len"], C_run, T if opts.get("keep_gamma") else 0)
+        _check(load().cf_solve_static(self._h, C.byref(o), C.byref(r)))
+        return _result_dict(r, bufs)
 
 
 def batch_solve(problems: Sequence["Problem"], workspace=None, **opts):

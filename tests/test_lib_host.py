@@ -281,6 +281,22 @@ print(code, lib.cf_last_error().decode(), flush=True)
     assert int(code) == 4 and "allocation" in msg, r.stdout
 
 
+def test_static_entry_rejects_oversized_solve_on_the_host(cf):
+    """cf_solve_static refuses a solve whose workspace exceeds its fixed
+    device array before any device call (C2 needs about 0.9 GB)."""
+    wl = c2_piston_tetm_fp32(n_steps=100)
+    p = cf.Problem.from_workload(wl)
+    opts = dict(sigma=wl.sigma, courant=wl.courant, n_steps=wl.n_steps, pol=wl.pol, kernel=wl.kernel,
+                precision=wl.precision)
+    assert p.info(**opts)["workspace_bytes"] > cf.STATIC_WORKSPACE_BYTES
+    o = p._opts(**opts)
+    r, _ = cf._result_buffers(p.info(**opts)["per_harmonic_len"], p.info(**opts)["n_channels"])
+    import ctypes as C
+    code = cf.load().cf_solve_static(p._h, C.byref(o), C.byref(r))
+    assert code == 4
+    assert "cf_solve" in cf.load().cf_last_error().decode()
+
+
 def test_zinv_kernel_needs_perfect_conductors_in_vacuum(cf):
     """Appendix A.2's kernel assumes perfect conductors in vacuum: the library
     refuses it (CF_E_UNSUPPORTED) when the grid uses any other material,
