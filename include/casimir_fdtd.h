@@ -296,6 +296,9 @@ typedef struct cf_result {
     int tile_variant;            /* fused kernel variant used (1-based), 0 if not fused             */
     int tile_halo;               /* steps per fused launch of that variant                          */
     int n_steps_run;             /* time steps run (< n_steps when the convergence stop ended it)   */
+    double advanced_cell_updates; /* cell-updates the field kernels actually performed: below        */
+                                  /* cell_updates when the fused 2D kernel skips rows that hold only  */
+                                  /* perfect conductor (fields identically 0 there)                   */
 } cf_result;
 
 typedef struct cf_problem cf_problem;

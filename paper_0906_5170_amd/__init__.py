@@ -81,7 +81,7 @@ class _Result(C.Structure):
                 ("stencil_samples", C.c_int), ("stencil_launches", C.c_int),
                 ("stencil_alg_bytes", C.c_double), ("stencil_cell_updates", C.c_double),
                 ("fused", C.c_int), ("tile_variant", C.c_int), ("tile_halo", C.c_int),
-                ("n_steps_run", C.c_int)]
+                ("n_steps_run", C.c_int), ("advanced_cell_updates", C.c_double)]
 
 
 _lib = None
@@ -176,7 +176,8 @@ def _result_dict(r, bufs) -> dict:
                stencil_samples=r.stencil_samples, stencil_launches=r.stencil_launches,
                stencil_alg_bytes=r.stencil_alg_bytes,
                stencil_cell_updates=r.stencil_cell_updates, fused=bool(r.fused),
-               tile_variant=r.tile_variant, tile_halo=r.tile_halo, n_steps_run=r.n_steps_run)
+               tile_variant=r.tile_variant, tile_halo=r.tile_halo, n_steps_run=r.n_steps_run,
+               advanced_cell_updates=r.advanced_cell_updates)
     if bufs["gam"] is not None:
         out["gamma"] = bufs["gam"].reshape(bufs["T"], len(bufs["pc"]))
         out["trace"] = bufs["tr"]
@@ -402,7 +403,7 @@ def batch_solve(problems: Sequence["Problem"], workspace=None, **opts):
         out.append(dict(force=r.force, per_harmonic=ph[:inf["per_harmonic_len"]], per_face=pf,
                         per_channel=pc, n_channels=r.n_channels_run, cell_updates=r.cell_updates,
                         device_ms=r.device_ms, fused=bool(r.fused), tile_variant=r.tile_variant,
-                        tile_halo=r.tile_halo))
+                        tile_halo=r.tile_halo, advanced_cell_updates=r.advanced_cell_updates))
     return out
 
 

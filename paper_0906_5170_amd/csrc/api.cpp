@@ -72,7 +72,75 @@ struct Layout {
 
 
 
-TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, cf::TBShape sh);
+// Where some E component of a polarization can be nonzero: a summed-area
+// table over the grid of cells whose E coefficients are not a = b = 0 (the
+// fused kernel's test for waves that advance nothing).
+struct ELive {
+    int nx = 0, ny = 0;
+    bool perx = false, pery = false;
+    std::vector<int32_t> sat;   // (ny + 1) x (nx + 1) prefix sums
+    int64_t box(int x0, int x1, int y0, int y1) const {   // [x0, x1) x [y0, y1) inside the grid
+        const size_t W = (size_t)nx + 1;
+        return (int64_t)sat[y1 * W + x1] - sat[y0 * W + x1] - sat[y1 * W + x0] + sat[y0 * W + x0];
+    }
+    // cells of [x0, x1) x [y0, y1) in region coordinates: periodic axes wrap,
+    // others end at the grid (cells beyond it hold nothing)
+    int64_t count(int x0, int x1, int y0, int y1) const {
+        int64_t n = 0;
+        for (auto& xs : segments(x0, x1, nx, perx))
+            for (auto& ys : segments(y0, y1, ny, pery)) n += box(xs.first, xs.second, ys.first, ys.second);
+        return n;
+    }
+    static std::vector<std::pair<int, int>> segments(int lo, int hi, int n, bool periodic) {
+        std::vector<std::pair<int, int>> out;
+        if (hi <= lo) return out;
+        if (!periodic) {
+            const int a = std::max(lo, 0), b = std::min(hi, n);
+            if (a < b) out.push_back({a, b});
+            return out;
+        }
+        if (hi - lo >= n) {
+            out.push_back({0, n});
+            return out;
+        }
+        const int a = ((lo % n) + n) % n, len = hi - lo;
+        if (a + len <= n) {
+            out.push_back({a, a + len});
+        } else {
+            out.push_back({a, n});
+            out.push_back({0, a + len - n});
+        }
+        return out;
+    }
+};
+
+ELive make_elive(const cf::Problem& p, int pol) {
+    ELive e;
+    e.nx = p.nx;
+    e.ny = p.ny;
+    e.perx = p.grid.bc[0] == CF_BC_PERIODIC;
+    e.pery = p.grid.bc[1] == CF_BC_PERIODIC;
+    std::vector<int> comps = pol == CF_POL_TM ? std::vector<int>{CF_EZ} : std::vector<int>{CF_EX, CF_EY};
+    const size_t W = (size_t)p.nx + 1;
+    e.sat.assign((size_t)(p.ny + 1) * W, 0);
+    for (int y = 0; y < p.ny; ++y) {
+        int32_t row = 0;
+        for (int x = 0; x < p.nx; ++x) {
+            const int64_t c = (int64_t)y * p.nx + x;
+            bool live = false;
+            for (int comp : comps) {
+                const int id = p.ids[comp][c];
+                live = live || (id != cf::kWallId && id < p.nmat && std::isfinite(p.eps[id]));
+            }
+            row += live ? 1 : 0;
+            e.sat[(y + 1) * W + x + 1] = e.sat[y * W + x + 1] + row;
+        }
+    }
+    return e;
+}
+
+TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, cf::TBShape sh,
+                  const ELive* el);
 
 std::vector<cf::Channel> selected_channels(const cf::Problem& p, const cf_opts& o, std::string* err) {
     std::vector<cf::Channel> all = cf::channel_table(p, o.pol);
@@ -236,9 +304,10 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         cf::TBShape sh[cf::kMaxVariants];
         const int nv = o.precision == CF_FP64 ? cf::tb_variants<double>(sh, cf::kMaxVariants)
                                               : cf::tb_variants<float>(sh, cf::kMaxVariants);
+        const ELive el[2] = {make_elive(p, CF_POL_TM), make_elive(p, CF_POL_TE)};
         for (int v = 0; v < nv; ++v) {
             st.shapes.push_back(sh[v]);
-            st.plans.push_back(plan_tiles(p, chans, sh[v]));
+            st.plans.push_back(plan_tiles(p, chans, sh[v], el));
         }
         if (o.tile_variant >= 1 && o.tile_variant <= nv && st.plans[o.tile_variant - 1].ok) {
             st.variant = o.tile_variant - 1;
@@ -318,7 +387,8 @@ static bool place_axis(int lo, int hi, int n, int w, int* base, int* ntiles, int
     return best_slack >= 0;
 }
 
-TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, cf::TBShape sh) {
+TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, cf::TBShape sh,
+                  const ELive* el) {
     TBPlan t;
     if (p.grid.ndim != 2 || p.reduced() || chans.empty()) return t;
     int xmin = p.nx, xmax = -1, ymin = p.ny, ymax = -1;
@@ -337,6 +407,29 @@ TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, c
     if (!place_axis(ymin, ymax, p.ny, sh.ty, &t.base_y, &t.nty, &sy)) return t;
     t.stile = sy * t.ntx + sx;
     t.ok = true;
+    // live waves per tile: the kernel skips a wave whose rows and the first
+    // row above them hold no E component that can be nonzero (the rows above
+    // the region's top wave are stale there and not needed)
+    const int RW = sh.tx + 2 * sh.kh, RH = sh.ty + 2 * sh.kh, W = RH / sh.b;
+    for (int k = 0; k < 2; ++k) {
+        for (int tile = 0; tile < t.ntx * t.nty; ++tile) {
+            const int rx0 = t.base_x + (tile % t.ntx) * sh.tx - sh.kh;
+            const int ry0 = t.base_y + (tile / t.ntx) * sh.ty - sh.kh;
+            std::vector<char> zero(W);
+            for (int w = 0; w < W; ++w) zero[w] = el[k].count(rx0, rx0 + RW, ry0 + w * sh.b, ry0 + (w + 1) * sh.b) == 0;
+            bool any = false;
+            for (int w = 0; w < W; ++w) {
+                if (zero[w] && (w + 1 == W || zero[w + 1])) continue;   // advances nothing
+                any = true;
+                // tile-interior cells of the wave inside the grid
+                const int y0 = std::max({ry0 + w * sh.b, ry0 + sh.kh, 0});
+                const int y1 = std::min({ry0 + (w + 1) * sh.b, ry0 + sh.kh + sh.ty, p.ny});
+                const int x0 = std::max(rx0 + sh.kh, 0), x1 = std::min(rx0 + sh.kh + sh.tx, p.nx);
+                if (y1 > y0 && x1 > x0) t.live_cells[k] += (double)(y1 - y0) * (x1 - x0);
+            }
+            if (any || tile == t.stile) t.live[k].push_back(tile);
+        }
+    }
     return t;
 }
 
@@ -344,17 +437,18 @@ TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, c
 // tiles.  Each channel is assigned whole to the XCD queue with the fewest
 // tiles so far; block b = 8 i + x takes item i of queue x, so every tile of
 // a channel runs on XCD x (blocks are dispatched to XCDs round-robin).
-std::vector<cf::WorkItem> make_work(const std::vector<int>& slots, const std::vector<int>& ntiles,
+std::vector<cf::WorkItem> make_work(const std::vector<int>& slots, const std::vector<const std::vector<int>*>& tiles,
                                     const std::vector<int>& stile) {
     std::vector<std::vector<cf::WorkItem>> q(8);
     std::vector<long> load(8, 0);
     for (size_t k = 0; k < slots.size(); ++k) {
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        const int first = stile[k] >= 0 && stile[k] < ntiles[k] ? stile[k] : 0;
-        q[x].push_back({slots[k], first});
-        for (int t = 0; t < ntiles[k]; ++t)
-            if (t != first) q[x].push_back({slots[k], t});
-        load[x] += ntiles[k];
+        const std::vector<int>& tl = *tiles[k];
+        const bool has_s = std::find(tl.begin(), tl.end(), stile[k]) != tl.end();
+        if (has_s) q[x].push_back({slots[k], stile[k]});
+        for (int t : tl)
+            if (!has_s || t != stile[k]) q[x].push_back({slots[k], t});
+        load[x] += (long)tl.size();
     }
     size_t len = 0;
     for (auto& v : q) len = std::max(len, v.size());
@@ -843,9 +937,11 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     std::deque<std::vector<cf::WorkItem>> host_work;
     std::deque<cf::InstDev> host_inst;
     // work list of one wave's channels of one polarization for plan pl
-    auto upload_work = [&](const int* list, int n, const TBPlan& pl, size_t slot_off, int* nwork) -> hipError_t {
-        std::vector<int> sl(list, list + n), nt(n, pl.ntx * pl.nty), st(n, pl.stile);
-        host_work.push_back(make_work(sl, nt, st));
+    auto upload_work = [&](const int* list, int n, const TBPlan& pl, int pol, size_t slot_off,
+                           int* nwork) -> hipError_t {
+        std::vector<int> sl(list, list + n), st(n, pl.stile);
+        std::vector<const std::vector<int>*> tl(n, &live_tiles(pl, pol));
+        host_work.push_back(make_work(sl, tl, st));
         *nwork = (int)host_work.back().size();
         if ((size_t)*nwork > L.work_items) return hipErrorInvalidValue;
         return hipMemcpyAsync(dwork + slot_off, host_work.back().data(), *nwork * sizeof(cf::WorkItem),
@@ -904,8 +1000,8 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
                 const int kh = st.shapes[v].kh;
                 int nw = 0;
                 STEP_OK(upload_inst(make_inst(st.plans[v], false)));
-                STEP_OK(upload_work(st.slot_lists.data() + (tm ? w.tm_off : w.te_off), n, st.plans[v], 0, &nw));
                 const int pol = tm ? CF_POL_TM : CF_POL_TE;
+                STEP_OK(upload_work(st.slot_lists.data() + (tm ? w.tm_off : w.te_off), n, st.plans[v], pol, 0, &nw));
                 STEP_OK(cf::launch_tb2d<T>(v, pol, dch, dwork, nw, dinst, kh, 0, 0, s));
                 STEP_OK(hipEventRecord(t0, s));
                 for (int r = 0; r < 3; ++r) STEP_OK(cf::launch_tb2d<T>(v, pol, dch, dwork, nw, dinst, kh, 0, r & 1, s));
@@ -1021,8 +1117,11 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             const int kh = st.shapes[variant].kh;
             int nw_tm = 0, nw_te = 0;
             STEP_OK(upload_inst(make_inst(pl, true)));
-            STEP_OK(upload_work(st.slot_lists.data() + w.tm_off, w.n_tm, pl, 0, &nw_tm));
-            STEP_OK(upload_work(st.slot_lists.data() + w.te_off, w.n_te, pl, L.work_items, &nw_te));
+            STEP_OK(upload_work(st.slot_lists.data() + w.tm_off, w.n_tm, pl, CF_POL_TM, 0, &nw_tm));
+            STEP_OK(upload_work(st.slot_lists.data() + w.te_off, w.n_te, pl, CF_POL_TE, L.work_items, &nw_te));
+            // cells the fused kernel skips are never written: both ping-pong
+            // arrays start at zero there
+            STEP_OK(hipMemsetAsync(ws + L.fields2, 0, field_bytes, s));
             STEP_OK(graph.begin());
             const hipStream_t ls = graph.launch_stream(s);
             const hipError_t body = [&]() -> hipError_t {
@@ -1191,6 +1290,14 @@ bool fill_result(const cf::Problem& p, const std::vector<cf::Channel>& chans, co
     out->fused = tim.variant >= 0 ? 1 : 0;
     out->tile_variant = tim.variant + 1;
     out->tile_halo = tim.variant >= 0 && tim.variant < (int)sg.shapes.size() ? sg.shapes[tim.variant].kh : 0;
+    out->advanced_cell_updates = out->cell_updates;
+    if (tim.variant >= 0 && tim.variant < (int)sg.plans.size() && p.grid.ndim == 2 && !p.reduced()) {
+        // the fused 2D kernel advances the live waves' tile interiors only
+        const TBPlan& pl = sg.plans[tim.variant];
+        double a = 0;
+        for (size_t c = 0; c < C; ++c) a += pl.live_cells[chans[c].pol == CF_POL_TE ? 1 : 0];
+        out->advanced_cell_updates = a * (double)steps;
+    }
     return finite;
 }
 
@@ -1442,13 +1549,14 @@ cf_status run_batch(const BatchPlan& B, const BatchLayout& L, const cf_opts& o, 
         return I;
     };
     auto work_for = [&](int v, const std::vector<int>& slots) {
-        std::vector<int> nt, st;
+        std::vector<const std::vector<int>*> tl;
+        std::vector<int> st;
         for (int sl : slots) {
             const int i = B.dev[sl].inst;
-            nt.push_back(B.st[i].plans[v].ntx * B.st[i].plans[v].nty);
+            tl.push_back(&live_tiles(B.st[i].plans[v], B.dev[sl].pol));
             st.push_back(B.st[i].plans[v].stile);
         }
-        return make_work(slots, nt, st);
+        return make_work(slots, tl, st);
     };
     const int n_tm = (int)B.tm.size(), n_te = (int)B.te.size();
     hipError_t err = hipSuccess;
@@ -1515,6 +1623,7 @@ cf_status run_batch(const BatchPlan& B, const BatchLayout& L, const cf_opts& o, 
         BSTEP(up(L.work + B.work_items * sizeof(cf::WorkItem), keepW.back().data(), nw_te * sizeof(cf::WorkItem)));
         BSTEP(hipMemsetAsync(dacc, 0, (size_t)B.C * 2 * 8, s));
         BSTEP(hipMemsetAsync(A, 0, fbytes, s));
+        BSTEP(hipMemsetAsync(Bf, 0, fbytes, s));   // cells the fused kernel skips stay zero in both arrays
         BSTEP(hipEventRecord(e0, s));
         BSTEP(cf::launch_kick<T>(A, dch, dl, B.C, B.max_uniq, tabs, s));
         for (int i = 0; i < n; ++i) {

@@ -84,10 +84,11 @@ struct WorkItem {
     int slot, tile;
 };
 
-// Tile interior (tx x ty cells) and halo / maximum steps per launch of the
-// fused kernel's variants (index = variant).
+// Tile interior (tx x ty cells), halo / maximum steps per launch and rows
+// per wave (b) of the fused kernel's variants (index = variant); the region
+// a block holds is (tx + 2 kh) x (ty + 2 kh) cells in (ty + 2 kh) / b waves.
 struct TBShape {
-    int tx, ty, kh;
+    int tx, ty, kh, b;
 };
 constexpr int kMaxVariants = 16;
 template <typename T>

@@ -258,50 +258,36 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
         L[s][id].b = p[1];
     }
 
-    T f0[CX][B], f1[CX][B], f2[CX][B];
+    // cell (j, r) of this lane: grid index, or -1 beyond a non-periodic edge
+    auto cell_of = [&](int j, int r) -> int64_t {
+        int gx = rx0 + lane * CX + j, gy = ry0 + w * B + r;
+        if (gx < 0 || gx >= g.nx) {
+            if (!g.perx) return -1;
+            gx = ((gx % g.nx) + g.nx) % g.nx;
+        }
+        if (gy < 0 || gy >= g.ny) {
+            if (!g.pery) return -1;
+            gy = ((gy % g.ny) + g.ny) % g.ny;
+        }
+        return (int64_t)gy * g.nx + gx;
+    };
     uint32_t m0p[CX][NP], m1p[CX][NP], m2p[CX][NP];
 #pragma unroll
     for (int j = 0; j < CX; ++j)
 #pragma unroll
         for (int r = 0; r < NP; ++r) m0p[j][r] = m1p[j][r] = m2p[j][r] = 0;
-    {
-        const T* S = src + d.field_off;
 #pragma unroll
-        for (int j = 0; j < CX; ++j) {
-            int gx = rx0 + lane * CX + j;
-            bool inx = true;
-            if (gx < 0 || gx >= g.nx) {
-                if (g.perx) gx = ((gx % g.nx) + g.nx) % g.nx;
-                else inx = false;
-            }
+    for (int j = 0; j < CX; ++j)
 #pragma unroll
-            for (int r = 0; r < B; ++r) {
-                int gy = ry0 + w * B + r;
-                bool in = inx;
-                if (gy < 0 || gy >= g.ny) {
-                    if (g.pery) gy = ((gy % g.ny) + g.ny) % g.ny;
-                    else in = false;
-                }
-                uint32_t i0 = kNullId, i1 = kNullId, i2 = kNullId;
-                if (in) {
-                    const int64_t gi = (int64_t)gy * g.nx + gx;
-                    f0[j][r] = S[gi];
-                    f1[j][r] = S[g.ncell + gi];
-                    f2[j][r] = S[2 * g.ncell + gi];
-                    i0 = g.ids[C0][gi];
-                    i1 = g.ids[C1][gi];
-                    i2 = g.ids[C2][gi];
-                } else {
-                    f0[j][r] = T(0);
-                    f1[j][r] = T(0);
-                    f2[j][r] = T(0);
-                }
-                m0p[j][r >> 2] |= i0 << (8 * (r & 3));
-                m1p[j][r >> 2] |= i1 << (8 * (r & 3));
-                m2p[j][r >> 2] |= i2 << (8 * (r & 3));
-            }
+        for (int r = 0; r < B; ++r) {
+            const int64_t gi = cell_of(j, r);
+            const uint32_t i0 = gi >= 0 ? g.ids[C0][gi] : kNullId;
+            const uint32_t i1 = gi >= 0 ? g.ids[C1][gi] : kNullId;
+            const uint32_t i2 = gi >= 0 ? g.ids[C2][gi] : kNullId;
+            m0p[j][r >> 2] |= i0 << (8 * (r & 3));
+            m1p[j][r >> 2] |= i1 << (8 * (r & 3));
+            m2p[j][r >> 2] |= i2 << (8 * (r & 3));
         }
-    }
     const bool stile = tile == g.stile;
     double acc_s = 0.0, acc_c = 0.0;
     if (stile && tid == 0) {
@@ -311,11 +297,52 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
     __syncthreads();
 
 #define CF_ID(p, j, r) ((p[j][(r) >> 2] >> (8 * ((r) & 3))) & 255u)
+    // A wave whose band, and the band of the wave above, hold no E component
+    // with a nonzero coefficient advances nothing: E is held at 0 there and H,
+    // whose curl reads only those rows, keeps its value, which is 0 from the
+    // start (every field there starts at 0 and the cells are never written).
+    // Such a wave skips its loads, arithmetic and write-back; it still takes
+    // part in the barriers and writes its (zero) exchange rows.  Above the top
+    // wave lie only stale rim rows, so its own band decides.
+    __shared__ int band_e[RBW];
+    {
+        bool e_any = false;
+#pragma unroll
+        for (int j = 0; j < CX; ++j)
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                const Pair<T> c0 = L[0][CF_ID(m0p, j, r)];
+                e_any = e_any || c0.a != T(0) || c0.b != T(0);
+                if (POL == CF_POL_TE) {
+                    const Pair<T> c1 = L[1][CF_ID(m1p, j, r)];
+                    e_any = e_any || c1.a != T(0) || c1.b != T(0);
+                }
+            }
+        const int wave_any = __any(e_any) ? 1 : 0;
+        if (lane == 0) band_e[w] = wave_any;
+    }
+    __syncthreads();
+    const bool live = __builtin_amdgcn_readfirstlane((band_e[w] || (w + 1 < RBW && band_e[w + 1])) ? 1 : 0) != 0;
+
+    T f0[CX][B], f1[CX][B], f2[CX][B];
+    {
+        const T* S = src + d.field_off;
+#pragma unroll
+        for (int j = 0; j < CX; ++j)
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                const int64_t gi = live ? cell_of(j, r) : -1;
+                f0[j][r] = gi >= 0 ? S[gi] : T(0);
+                f1[j][r] = gi >= 0 ? S[g.ncell + gi] : T(0);
+                f2[j][r] = gi >= 0 ? S[2 * g.ncell + gi] : T(0);
+            }
+    }
     // CREG: each cell's (a, b) pairs are constant over the launch and can be
     // held in registers instead of being looked up in LDS every step.
     constexpr int KJ = CREG ? CX : 1, KB = CREG ? B : 1;
     Pair<T> k0[KJ][KB], k1[KJ][KB], k2[KJ][KB];
     if constexpr (CREG) {
+        if (live)
 #pragma unroll
         for (int j = 0; j < CX; ++j)
 #pragma unroll
@@ -338,7 +365,8 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < CX; ++j) e_above[j] = w + 1 < RBW ? xe[w + 1][j][lane] : f0[j][B - 1];
-        if (POL == CF_POL_TM) {
+        if (!live) {
+        } else if (POL == CF_POL_TM) {
 #pragma unroll
             for (int r = 0; r < B; ++r)
 #pragma unroll
@@ -370,7 +398,8 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
 #pragma unroll
         for (int j = 0; j < CX; ++j)
             h_below[j] = w > 0 ? xh[w - 1][j][lane] : (POL == CF_POL_TM ? f1[j][0] : f2[j][0]);
-        if (POL == CF_POL_TM) {
+        if (!live) {
+        } else if (POL == CF_POL_TM) {
 #pragma unroll
             for (int r = 0; r < B; ++r)
 #pragma unroll
@@ -426,6 +455,7 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
         acc[0] = acc_s;
         acc[1] = acc_c;
     }
+    if (!live) return;   // its cells are 0 in both arrays already
     T* D = dst + d.field_off;
 #pragma unroll
     for (int j = 0; j < CX; ++j) {
@@ -483,7 +513,8 @@ template <typename T>
 int tb_variants(TBShape* out, int max) {
     int n;
     const RbVariant* v = rb_table<T>(&n);
-    for (int i = 0; i < n && i < max; ++i) out[i] = TBShape{64 * v[i].CX - 2 * v[i].KH, v[i].W * v[i].B - 2 * v[i].KH, v[i].KH};
+    for (int i = 0; i < n && i < max; ++i)
+        out[i] = TBShape{64 * v[i].CX - 2 * v[i].KH, v[i].W * v[i].B - 2 * v[i].KH, v[i].KH, v[i].B};
     return n;
 }
 template int tb_variants<float>(TBShape*, int);

@@ -336,6 +336,11 @@ hipError_t start_wave(cf_server* S, Req& r, T* f) {
     const size_t fbytes = (size_t)r.st.resident * r.st.ncomp * p.ncell * sizeof(T);
     hipError_t e;
     if ((e = hipMemsetAsync(f, 0, fbytes, s)) != hipSuccess) return e;
+    if (r.fused) {
+        // the fused kernel never writes the cells it skips: zero in both arrays
+        char* other = b + (reinterpret_cast<char*>(f) == b + r.o_fa ? r.o_fb : r.o_fa);
+        if ((e = hipMemsetAsync(other, 0, fbytes, s)) != hipSuccess) return e;
+    }
     if (r.st.psi_comp > 0 &&
         (e = hipMemsetAsync(b + r.o_psi, 0, (size_t)r.st.resident * 4 * r.st.psi_comp * sizeof(T), s)) != hipSuccess)
         return e;
@@ -399,7 +404,9 @@ hipError_t rebuild_group(cf_server* S) {
     std::vector<cf::ChanDev> ch;
     std::vector<cf::InstDev> inst;
     struct SlotTiles {
-        std::vector<int> first, second, third;   // slots, tiles per slot, surface tile per slot
+        std::vector<int> first;                          // slots
+        std::vector<const std::vector<int>*> second;     // live tiles per slot
+        std::vector<int> third;                          // surface tile per slot
     };
     std::map<std::pair<int, int>, SlotTiles> lists;   // (v, pol) -> slots, tiles, surface tiles
     for (auto& rp : S->active) {
@@ -442,7 +449,7 @@ hipError_t rebuild_group(cf_server* S) {
             ch.push_back(d);
             auto& l = lists[{r.variant, r.chans[c].pol}];
             l.first.push_back(slot);
-            l.second.push_back(pl.ntx * pl.nty);
+            l.second.push_back(&cfi::live_tiles(pl, r.chans[c].pol));
             l.third.push_back(pl.stile);
         }
     }

@@ -272,3 +272,41 @@ def test_c3_members_full_T_vs_oracle(cf):
         rel = abs(res[m["index"]]["force"] / m["force"] - 1)
         print(f"[precision] c3 member {m['index']} fp32 force rel err {rel:.3e}", flush=True)
         assert rel <= 1e-4
+
+
+THICK = {
+    # 40-row PEC slabs: whole tiles and single waves hold only perfect conductor
+    "thick_slabs": lambda: piston2d(96, 120, 40, 20, 10, 20, 50, 20.0, pol="TM+TE", n_steps=131, n_harm=6),
+    # periodic y: the two slabs form one 80-row conductor across the periodic edge
+    "thick_slabs_periodic_y": lambda: piston2d(96, 120, 40, 20, 10, 20, 50, 20.0, pol="TM+TE", n_steps=131,
+                                               n_harm=6).replace(bc=("pec", "periodic", "periodic")),
+    # PMC slabs: E is free there, nothing may be skipped
+    "thick_slabs_pmc": lambda: piston2d(96, 120, 40, 20, 10, 20, 50, 20.0, pol="TM+TE", n_steps=131, n_harm=6,
+                                        sidewall="pmc"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(THICK))
+@pytest.mark.parametrize("precision,nvar", [("fp32", 13), ("fp64", 5)])
+def test_fused_skips_conductor_rows_bitwise(cf, name, precision, nvar):
+    """The fused kernel skips waves (and whole tiles) whose rows hold only
+    perfect conductor: every variant equals the split half-step kernels,
+    which advance every cell, bit for bit; the work it reports as advanced is
+    below the whole grid where E is held in the slabs, and equal with PMC
+    slabs (E is free there)."""
+    announce(f"fused skipping of conductor rows, {name}, {precision}")
+    wl = THICK[name]()
+    ref = run(cf, wl, precision=precision, split=True)
+    assert ref["advanced_cell_updates"] == ref["cell_updates"]
+    for v in range(1, nvar + 1):
+        r = run(cf, wl, precision=precision, tile_variant=v)
+        assert r["fused"] and r["tile_variant"] == v
+        np.testing.assert_array_equal(r["per_channel"], ref["per_channel"])
+        if name == "thick_slabs_pmc":
+            assert r["advanced_cell_updates"] == r["cell_updates"]
+        elif v in (5, 13) if precision == "fp32" else v == 1:
+            assert r["advanced_cell_updates"] < 0.8 * r["cell_updates"], (v, r["advanced_cell_updates"])
+    if precision == "fp64" and name == "thick_slabs":
+        ro = oracle.solve(wl)
+        terms = float(np.sum(np.abs(ro.sign * ro.acc)) / np.pi)
+        assert abs(r["force"] - ro.force) <= 1e-9 * terms
