@@ -86,31 +86,36 @@ struct ELive {
     // cells of [x0, x1) x [y0, y1) in region coordinates: periodic axes wrap,
     // others end at the grid (cells beyond it hold nothing)
     int64_t count(int x0, int x1, int y0, int y1) const {
+        int xs[4], ys[4];
+        const int nxs = segments(x0, x1, nx, perx, xs), nys = segments(y0, y1, ny, pery, ys);
         int64_t n = 0;
-        for (auto& xs : segments(x0, x1, nx, perx))
-            for (auto& ys : segments(y0, y1, ny, pery)) n += box(xs.first, xs.second, ys.first, ys.second);
+        for (int a = 0; a < nxs; ++a)
+            for (int b = 0; b < nys; ++b) n += box(xs[2 * a], xs[2 * a + 1], ys[2 * b], ys[2 * b + 1]);
         return n;
     }
-    static std::vector<std::pair<int, int>> segments(int lo, int hi, int n, bool periodic) {
-        std::vector<std::pair<int, int>> out;
-        if (hi <= lo) return out;
+    // the interval [lo, hi) as at most two [begin, end) pairs inside [0, n)
+    static int segments(int lo, int hi, int n, bool periodic, int* out) {
+        if (hi <= lo) return 0;
         if (!periodic) {
-            const int a = std::max(lo, 0), b = std::min(hi, n);
-            if (a < b) out.push_back({a, b});
-            return out;
+            out[0] = std::max(lo, 0);
+            out[1] = std::min(hi, n);
+            return out[0] < out[1] ? 1 : 0;
         }
         if (hi - lo >= n) {
-            out.push_back({0, n});
-            return out;
+            out[0] = 0;
+            out[1] = n;
+            return 1;
         }
         const int a = ((lo % n) + n) % n, len = hi - lo;
+        out[0] = a;
         if (a + len <= n) {
-            out.push_back({a, a + len});
-        } else {
-            out.push_back({a, n});
-            out.push_back({0, a + len - n});
+            out[1] = a + len;
+            return 1;
         }
-        return out;
+        out[1] = n;
+        out[2] = 0;
+        out[3] = a + len - n;
+        return 2;
     }
 };
 
@@ -155,6 +160,47 @@ std::vector<cf::Channel> selected_channels(const cf::Problem& p, const cf_opts& 
         out.push_back(all[c]);
     }
     return out;
+}
+
+// Tilings of a problem for a channel set and precision, kept per problem
+// (the search over tiling origins costs tens of milliseconds on the larger
+// grids, and a solve stages its problem several times).  The key is the
+// problem's unique id, the precision, the polarizations run and the box of
+// every surface stencil point, which decide the plans.
+std::mutex g_plan_mu;
+std::map<std::vector<int64_t>, std::vector<TBPlan>> g_plans;
+
+std::vector<TBPlan> cached_plans(const cf::Problem& p, const std::vector<cf::Channel>& chans, int precision,
+                                 const std::vector<cf::TBShape>& shapes) {
+    int xmin = p.nx, xmax = -1, ymin = p.ny, ymax = -1, pols = 0;
+    for (const auto& ch : chans) {
+        pols |= ch.pol;
+        const cf::Gather& g = p.gathers[p.gather_of.at({ch.face, ch.meas})];
+        for (int32_t idx : g.idx) {
+            xmin = std::min(xmin, idx % p.nx);
+            xmax = std::max(xmax, idx % p.nx);
+            ymin = std::min(ymin, idx / p.nx);
+            ymax = std::max(ymax, idx / p.nx);
+        }
+    }
+    const std::vector<int64_t> key = {(int64_t)p.uid, precision, pols, xmin, xmax, ymin, ymax};
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        auto it = g_plans.find(key);
+        if (it != g_plans.end()) return it->second;
+    }
+    const ELive el[2] = {make_elive(p, CF_POL_TM), make_elive(p, CF_POL_TE)};
+    std::vector<TBPlan> plans;
+    for (const cf::TBShape& sh : shapes) plans.push_back(plan_tiles(p, chans, sh, el));
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (g_plans.size() >= 1024) g_plans.clear();
+    g_plans[key] = plans;
+    return plans;
+}
+
+void forget_plans(uint64_t uid) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (auto it = g_plans.begin(); it != g_plans.end();) it = (uint64_t)it->first[0] == uid ? g_plans.erase(it) : std::next(it);
 }
 
 // Build host copies of every table a solve uploads.  Channels run in waves
@@ -304,11 +350,8 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         cf::TBShape sh[cf::kMaxVariants];
         const int nv = o.precision == CF_FP64 ? cf::tb_variants<double>(sh, cf::kMaxVariants)
                                               : cf::tb_variants<float>(sh, cf::kMaxVariants);
-        const ELive el[2] = {make_elive(p, CF_POL_TM), make_elive(p, CF_POL_TE)};
-        for (int v = 0; v < nv; ++v) {
-            st.shapes.push_back(sh[v]);
-            st.plans.push_back(plan_tiles(p, chans, sh[v], el));
-        }
+        for (int v = 0; v < nv; ++v) st.shapes.push_back(sh[v]);
+        st.plans = cached_plans(p, chans, o.precision, st.shapes);
         if (o.tile_variant >= 1 && o.tile_variant <= nv && st.plans[o.tile_variant - 1].ok) {
             st.variant = o.tile_variant - 1;
         } else {
@@ -360,39 +403,76 @@ void tune_store(const std::string& key, int v) {
     }
 }
 
-// Place the tile grid along one axis so that [lo, hi] sits in one tile of
-// width w: returns false when it cannot.
-// Tiling origin base in (-w, 0] along one axis such that the cells lo..hi
-// (the surface stencil) lie in one tile: the fewest tiles over 0..n-1, and
-// among those the origin that centres lo..hi best in its tile.
-static bool place_axis(int lo, int hi, int n, int w, int* base, int* ntiles, int* stile) {
-    const int span = hi - lo + 1;
-    if (span > w) return false;
+// Tiling origins along one axis: every base in (-w, 0] for which the cells
+// lo..hi (the surface stencil) lie in one tile of width w, with its tile
+// count over 0..n-1, the tile holding lo..hi and the stencil's distance to
+// the nearer edge of that tile.
+struct AxisPlacement {
+    int base, ntiles, stile, slack;
+};
+
+static std::vector<AxisPlacement> place_axis(int lo, int hi, int n, int w) {
+    std::vector<AxisPlacement> out;
+    if (hi - lo + 1 > w) return out;
     auto fdiv = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
-    int best_n = 0, best_slack = -1;
     for (int b = 0; b > -w; --b) {
         const int t = fdiv(lo - b, w);
         if (fdiv(hi - b, w) != t) continue;              // S straddles two tiles
-        const int nt = (n - b + w - 1) / w;
         const int t0 = b + t * w;                         // first cell of S's tile
-        const int slack = std::min(lo - t0, t0 + w - 1 - hi);
-        if (best_slack < 0 || nt < best_n || (nt == best_n && slack > best_slack)) {
-            best_n = nt;
-            best_slack = slack;
-            *base = b;
-            *ntiles = nt;
-            *stile = t;
-        }
+        out.push_back({b, (n - b + w - 1) / w, t, std::min(lo - t0, t0 + w - 1 - hi)});
     }
-    return best_slack >= 0;
+    return out;
 }
 
+// Live waves of the tiling t (base, tile counts and surface tile set) for
+// polarization slot k; with fill, also its live tile list and live cells.  A
+// wave is dead when its rows, and the first row above them, hold no E
+// component that can be nonzero (the kernel's own test; above the region's
+// top wave lie only stale rim rows).  The surface tile always runs.
+static long live_waves(const cf::Problem& p, TBPlan& t, const cf::TBShape& sh, const ELive& el, int k,
+                       bool fill) {
+    const int RW = sh.tx + 2 * sh.kh, RH = sh.ty + 2 * sh.kh, W = RH / sh.b;
+    long n = 0;
+    if (fill) {
+        t.live[k].clear();
+        t.live_cells[k] = 0;
+    }
+    std::vector<char> zero(W);
+    for (int tile = 0; tile < t.ntx * t.nty; ++tile) {
+        const int rx0 = t.base_x + (tile % t.ntx) * sh.tx - sh.kh;
+        const int ry0 = t.base_y + (tile / t.ntx) * sh.ty - sh.kh;
+        for (int w = 0; w < W; ++w) zero[w] = el.count(rx0, rx0 + RW, ry0 + w * sh.b, ry0 + (w + 1) * sh.b) == 0;
+        bool any = false;
+        for (int w = 0; w < W; ++w) {
+            if (zero[w] && (w + 1 == W || zero[w + 1])) continue;   // advances nothing
+            any = true;
+            ++n;
+            if (!fill) continue;
+            // tile-interior cells of the wave inside the grid
+            const int y0 = std::max({ry0 + w * sh.b, ry0 + sh.kh, 0});
+            const int y1 = std::min({ry0 + (w + 1) * sh.b, ry0 + sh.kh + sh.ty, p.ny});
+            const int x0 = std::max(rx0 + sh.kh, 0), x1 = std::min(rx0 + sh.kh + sh.tx, p.nx);
+            if (y1 > y0 && x1 > x0) t.live_cells[k] += (double)(y1 - y0) * (x1 - x0);
+        }
+        if (!any && tile == t.stile) ++n;
+        if (fill && (any || tile == t.stile)) t.live[k].push_back(tile);
+    }
+    return n;
+}
+
+// Tiling of the fused kernel for the channels' surface stencils.  Among the
+// origins that keep every stencil point in one tile, the one with the fewest
+// live waves (summed over the polarizations run) is taken, then the fewest
+// tiles, then the stencil most centred in its tile: first along y with x at
+// its fewest-tiles origin, then along x at the chosen y.
 TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, cf::TBShape sh,
                   const ELive* el) {
     TBPlan t;
     if (p.grid.ndim != 2 || p.reduced() || chans.empty()) return t;
     int xmin = p.nx, xmax = -1, ymin = p.ny, ymax = -1;
+    bool pol_used[2] = {false, false};
     for (const auto& ch : chans) {
+        pol_used[ch.pol == CF_POL_TE ? 1 : 0] = true;
         const cf::Gather& g = p.gathers[p.gather_of.at({ch.face, ch.meas})];
         for (int32_t idx : g.idx) {
             const int x = idx % p.nx, y = idx / p.nx;
@@ -402,34 +482,56 @@ TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, c
             ymax = std::max(ymax, y);
         }
     }
-    int sx, sy;
-    if (!place_axis(xmin, xmax, p.nx, sh.tx, &t.base_x, &t.ntx, &sx)) return t;
-    if (!place_axis(ymin, ymax, p.ny, sh.ty, &t.base_y, &t.nty, &sy)) return t;
-    t.stile = sy * t.ntx + sx;
-    t.ok = true;
-    // live waves per tile: the kernel skips a wave whose rows and the first
-    // row above them hold no E component that can be nonzero (the rows above
-    // the region's top wave are stale there and not needed)
-    const int RW = sh.tx + 2 * sh.kh, RH = sh.ty + 2 * sh.kh, W = RH / sh.b;
-    for (int k = 0; k < 2; ++k) {
-        for (int tile = 0; tile < t.ntx * t.nty; ++tile) {
-            const int rx0 = t.base_x + (tile % t.ntx) * sh.tx - sh.kh;
-            const int ry0 = t.base_y + (tile / t.ntx) * sh.ty - sh.kh;
-            std::vector<char> zero(W);
-            for (int w = 0; w < W; ++w) zero[w] = el[k].count(rx0, rx0 + RW, ry0 + w * sh.b, ry0 + (w + 1) * sh.b) == 0;
-            bool any = false;
-            for (int w = 0; w < W; ++w) {
-                if (zero[w] && (w + 1 == W || zero[w + 1])) continue;   // advances nothing
-                any = true;
-                // tile-interior cells of the wave inside the grid
-                const int y0 = std::max({ry0 + w * sh.b, ry0 + sh.kh, 0});
-                const int y1 = std::min({ry0 + (w + 1) * sh.b, ry0 + sh.kh + sh.ty, p.ny});
-                const int x0 = std::max(rx0 + sh.kh, 0), x1 = std::min(rx0 + sh.kh + sh.tx, p.nx);
-                if (y1 > y0 && x1 > x0) t.live_cells[k] += (double)(y1 - y0) * (x1 - x0);
-            }
-            if (any || tile == t.stile) t.live[k].push_back(tile);
+    const std::vector<AxisPlacement> px = place_axis(xmin, xmax, p.nx, sh.tx);
+    const std::vector<AxisPlacement> py = place_axis(ymin, ymax, p.ny, sh.ty);
+    if (px.empty() || py.empty()) return t;
+    auto fewest = [](const std::vector<AxisPlacement>& v) {
+        AxisPlacement best = v[0];
+        for (const auto& a : v)
+            if (a.ntiles < best.ntiles || (a.ntiles == best.ntiles && a.slack > best.slack)) best = a;
+        return best;
+    };
+    auto set = [&](const AxisPlacement& ax, const AxisPlacement& ay) {
+        t.base_x = ax.base;
+        t.ntx = ax.ntiles;
+        t.base_y = ay.base;
+        t.nty = ay.ntiles;
+        t.stile = ay.stile * t.ntx + ax.stile;
+    };
+    auto cost = [&]() {
+        long n = 0;
+        for (int k = 0; k < 2; ++k)
+            if (pol_used[k]) n += live_waves(p, t, sh, el[k], k, false);
+        return n;
+    };
+    auto better = [](long c, const AxisPlacement& a, long bc, const AxisPlacement& b) {
+        if (c != bc) return c < bc;
+        if (a.ntiles != b.ntiles) return a.ntiles < b.ntiles;
+        return a.slack > b.slack;
+    };
+    AxisPlacement bx = fewest(px), by = py[0];
+    long bcost = -1;
+    for (const auto& ay : py) {
+        set(bx, ay);
+        const long c = cost();
+        if (bcost < 0 || better(c, ay, bcost, by)) {
+            bcost = c;
+            by = ay;
         }
     }
+    bcost = -1;
+    AxisPlacement bx2 = bx;
+    for (const auto& ax : px) {
+        set(ax, by);
+        const long c = cost();
+        if (bcost < 0 || better(c, ax, bcost, bx2)) {
+            bcost = c;
+            bx2 = ax;
+        }
+    }
+    set(bx2, by);
+    t.ok = true;
+    for (int k = 0; k < 2; ++k) live_waves(p, t, sh, el[k], k, true);
     return t;
 }
 
@@ -1698,6 +1800,7 @@ static cf_status cf_problem_create_impl(const cf_grid* grid, const cf_materials*
 }
 
 static cf_status cf_problem_destroy_impl(cf_problem* p) {
+    if (p) forget_plans(p->p.uid);
     delete p;
     return CF_OK;
 }

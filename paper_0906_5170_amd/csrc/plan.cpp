@@ -3,6 +3,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <set>
@@ -361,6 +362,8 @@ static std::string make_gather_cyl(const Problem& p, int fi, int comp, bool orde
 
 std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surface& s,
                           Problem& p) {
+    static std::atomic<uint64_t> next_uid{1};
+    p.uid = next_uid.fetch_add(1);
     if (g.ndim != 2 && g.ndim != 3) return "ndim must be 2 or 3";
     for (int a = 0; a < 3; ++a)
         if (g.n[a] < 1) return "grid sizes must be positive";

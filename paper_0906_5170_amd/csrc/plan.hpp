@@ -64,6 +64,7 @@ struct Channel {
 };
 
 struct Problem {
+    uint64_t uid = 0;                         // unique per created problem (copies share it)
     cf_grid grid{};
     int nx = 0, ny = 0, nz = 0;
     int64_t ncell = 0;
