@@ -313,3 +313,26 @@ def small_cases():
         "piston_te_small": piston2d_units(10, 4.0, 2.0, 0.6, pol="TE", n_steps=300, n_harm=6,
                                           name="piston_te_small"),
     }
+
+
+def stop_piston2d(**over) -> Workload:
+    """Small TE+TM piston whose partial force settles well inside its 3000
+    steps: the workload of the time-convergence stop checks."""
+    kw = dict(pol="TM+TE", n_steps=3000, n_harm=8, name="stop_piston_40x31")
+    kw.update(over)
+    return piston2d(40, 31, 4, 10, 5, 10, 13, 10.0, **kw)
+
+
+def stop_sphere3d(**over) -> Workload:
+    """3D sphere of eps 3 in fluid eps 1.8 above a PEC plate, z CPML (12 x 12
+    x 26 cells, 1500 steps): the 3D workload of the convergence stop checks."""
+    nx, ny, nz, pml = 12, 12, 26, 4
+    zlo = pml + 2
+    prims = [Box((-BIG, -BIG, -BIG), (BIG, BIG, zlo), 1), Sphere((nx / 2 + 0.3, ny / 2, zlo + 5.5), 1.7, 2)]
+    kw = dict(sigma=1.0, courant=0.5, n_steps=1500, pol="3D", kernel="general", precision="fp64")
+    kw.update(over)
+    return Workload(name=kw.pop("name", "stop_sphere_12x12x26"), ndim=3, shape=(nx, ny, nz), res=4.0,
+                    bc=("periodic", "periodic", "pml"), pml_cells=(0, 0, pml), eps=[1.8, PEC, 3.0],
+                    mu=[1.0, 1.0, 1.0], comp_ids=rasterize((nx, ny, nz), prims),
+                    s_lo=(nx // 2 - 3, ny // 2 - 3, zlo + 2), s_hi=(nx // 2 + 4, ny // 2 + 3, zlo + 9),
+                    n_harm=2, force_axis=2, **kw)

@@ -10,6 +10,7 @@ casimir_inputs; no value comes from the HIP library.
     python tests/golden/make_golden.py c3      # uneven piston set: members 0 and 23, full T
     python tests/golden/make_golden.py cyl     # cylindrical piston res 40, n, m in {0, 1, 2}, full T
     python tests/golden/make_golden.py kz      # k_z dielectric piston, 8 k points, full T
+    python tests/golden/make_golden.py stop    # partial-force traces of the convergence-stop workloads
 """
 import json
 import os
@@ -119,6 +120,23 @@ def kz_golden():
     print("kz", r.force, f"{time.time() - t0:.1f}s")
 
 
+def stop_traces(workers=8):
+    """The partial force F(T') after every step (the trace of Fig. 12) of the
+    two convergence-stop workloads: the reference the GPU's stop rule is
+    checked against."""
+    from casimir_inputs.configs import stop_piston2d, stop_sphere3d
+    out = {"source": "oracle.solve (FP64 NumPy), written by tests/golden/make_golden.py"}
+    for key, wl in (("piston2d", stop_piston2d()), ("sphere3d", stop_sphere3d())):
+        t0 = time.time()
+        r = oracle.solve(wl, workers=workers, chunk=8)
+        out[key] = dict(workload=wl.name, shape=list(wl.shape), n_steps=wl.n_steps, force=r.force,
+                        terms=float(sum(abs(s * a) for s, a in zip(r.sign, r.acc)) / 3.141592653589793),
+                        trace=[float(v) for v in r.trace], oracle_seconds=time.time() - t0)
+        print(key, r.force, f"{time.time() - t0:.1f}s")
+    with open(os.path.join(HERE, "stop_traces_oracle.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 def main(which, workers=8):
     fname, make = CASES[which]
     wl = make()
@@ -152,5 +170,7 @@ if __name__ == "__main__":
         cyl_piston_golden()
     elif sys.argv[1] == "kz":
         kz_golden()
+    elif sys.argv[1] == "stop":
+        stop_traces()
     else:
         main(sys.argv[1])

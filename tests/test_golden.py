@@ -28,3 +28,19 @@ def test_golden_is_current(fname, make, subset, n_steps):
     r = oracle.solve(wl, channel_subset=subset, workers=len(subset), chunk=1)
     np.testing.assert_allclose(r.acc, np.array(ref["per_channel"])[subset], rtol=1e-13, atol=0)
     np.testing.assert_allclose(r.sign, np.array(ref["sign"])[subset], rtol=0, atol=0)
+
+
+def test_stop_traces_are_current():
+    """The convergence-stop traces: the piston's whole trace is recomputed
+    (1.3 s) and must match to rounding; the 3D trace ends at its force."""
+    from casimir_inputs.configs import stop_piston2d, stop_sphere3d
+    path = os.path.join(HERE, "golden", "stop_traces_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("stop_traces_oracle.json not generated")
+    ref = json.load(open(path))
+    wl = stop_piston2d()
+    r = oracle.solve(wl, workers=4, chunk=16)
+    np.testing.assert_allclose(r.trace, ref["piston2d"]["trace"], rtol=1e-12, atol=1e-14)
+    s3 = ref["sphere3d"]
+    assert s3["workload"] == stop_sphere3d().name and len(s3["trace"]) == s3["n_steps"]
+    assert s3["trace"][-1] == pytest.approx(s3["force"], rel=1e-12)
