@@ -336,3 +336,22 @@ def stop_sphere3d(**over) -> Workload:
                     mu=[1.0, 1.0, 1.0], comp_ids=rasterize((nx, ny, nz), prims),
                     s_lo=(nx // 2 - 3, ny // 2 - 3, zlo + 2), s_hi=(nx // 2 + 4, ny // 2 + 3, zlo + 9),
                     n_harm=2, force_axis=2, **kw)
+
+
+def layered_plates_1d(res: int, a_u: float, d_u: float, b_u: float, layer_u: float, eps_inf: float,
+                      poles=(), margin: int = 2, ny: int = 1, **opts) -> Workload:
+    """parallel_plates_1d with a dielectric layer of thickness layer_u on the
+    left wall (permittivity eps_inf plus the Lorentz terms ``poles`` =
+    ((d_eps, omega_0), ...)); the vacuum gap between the layer and the PEC
+    slab is a_u - layer_u, S lies in the vacuum gaps."""
+    wl = parallel_plates_1d(res, a_u, d_u, b_u, margin=margin, ny=ny, **opts)
+    L = int(round(layer_u * res))
+    if L + margin >= int(round(a_u * res)):
+        raise ValueError("the layer reaches the stress surface")
+    nx = wl.shape[0]
+    prims = [Box((-BIG, -BIG, -BIG), (L, BIG, BIG), 2),
+             Box((wl.meta["a_px"], -BIG, -BIG), (wl.meta["a_px"] + wl.meta["d_px"], BIG, BIG), 1)]
+    ids = rasterize((nx, ny, 1), prims)
+    lor = {2: tuple((float(de), float(w0)) for de, w0 in poles)} if poles else {}
+    return wl.replace(eps=[1.0, PEC, float(eps_inf)], mu=[1.0, 1.0, 1.0], comp_ids=ids, lorentz=lor,
+                      name=f"layered_plates_{nx}x{ny}", meta=dict(wl.meta, layer_px=L))

@@ -111,6 +111,10 @@ class Workload:
                Bloch wavevectors along z and the weights of F(k_q) in the force
     kx         "kz" workloads: Bloch wavevector along a periodic x per point
                (empty: all zero; any nonzero value makes the fields complex)
+    lorentz    dispersive materials: {material id: ((d_eps, omega_0), ...)},
+               Lorentz terms d_eps omega_0^2 / (omega_0^2 - omega^2) added to
+               eps[id], which is then the high-frequency permittivity
+               (Sec. III B; empty: every material is non-dispersive)
     """
 
     name: str
@@ -138,6 +142,7 @@ class Workload:
     kz: Tuple[float, ...] = ()
     kz_weight: Tuple[float, ...] = ()
     kx: Tuple[float, ...] = ()
+    lorentz: Dict[int, Tuple[Tuple[float, float], ...]] = dataclasses.field(default_factory=dict)
 
     def replace(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)

@@ -66,12 +66,16 @@ def surface_medium(wl, faces):
     eps = np.asarray(wl.eps, dtype=np.float64)
     mu = np.asarray(wl.mu, dtype=np.float64)
     e_vals, h_vals = set(), set()
+    dispersive = {k for k, poles in (getattr(wl, "lorentz", None) or {}).items() if poles}
     for f in faces:
         for comp, ids in wl.comp_ids.items():
             idx, _ = gather(wl, f, comp)
             vals = ids.ravel()[idx.ravel()]
             if comp[0] == "E":
                 e_vals.update(eps[vals].tolist())
+                if dispersive & set(vals.tolist()):
+                    # the stress tensor's eps_S would depend on frequency
+                    raise ValueError("S lies in a dispersive material")
             else:
                 h_vals.update(mu[vals].tolist())
     if len(e_vals) != 1 or len(h_vals) != 1:

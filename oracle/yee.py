@@ -41,6 +41,28 @@ converges only at first order in dt; the tests show both orders.
 
 PEC material (epsilon = -inf) zeroes E; PMC (mu = -inf) zeroes H.
 
+Dispersive materials (Sec. III B: a fitted Lorentz model, continued onto the
+complex conductivity contour).  A term d_eps w0^2 / (w0^2 - omega^2) of
+eps(omega), on the contour omega^2 = xi^2 + i sigma xi, becomes
+d_eps w0^2 / (w0^2 - xi^2 - i sigma xi): in the simulation's time (the
+variable conjugate to xi) a polarization P with
+
+    P'' + sigma P' + w0^2 P = d_eps w0^2 E,        D = eps_inf E + sum P,
+
+and the conductivity of an E-kind run acts on D (the factor 1 + i sigma/xi
+multiplies the whole continued permittivity); in an H-kind run D is
+lossless.  Discretized with centred differences at the E time levels,
+
+    P^{m+1} = [(2 - w0^2 dt^2) P^m - (1 - sigma dt/2) P^{m-1}
+               + d_eps w0^2 dt^2 E^m] / (1 + sigma dt/2),
+    eps_inf (E^{m+1} - E^m)/dt + (P^{m+1} - P^m)/dt
+        = curl H^{m+1/2} - sigma (D^{m+1} + D^m)/2     (E-kind; no sigma for H-kind),
+
+i.e. E^{m+1} = a E^m + b curl H - (sum P^{m+1} - a sum P^m) / eps_inf with
+the non-dispersive a, b of eps_inf.  P starts at zero: the kicks sit on S,
+which must lie in a non-dispersive medium.  Stable for w0 dt < 2 (with the
+Yee limit taken at eps_inf).
+
 CPML (Roden-Gedney, kappa = 1, alpha = 0) along any axis whose boundary is
 "pml": every difference along that axis inside the layer becomes D + psi with
 psi <- b psi + (b - 1) D, b = exp(-sigma_p(x) dt), sigma_p(x) = sigma_max
@@ -126,6 +148,7 @@ class YeeSim:
         self.E = {a: np.zeros(shp) for a in self.e_comps}
         self.H = {a: np.zeros(shp) for a in self.h_comps}
         self._coefficients()
+        self._lorentz_setup()
         self._pml_setup()
 
     # -- coefficients ---------------------------------------------------
@@ -171,6 +194,36 @@ class YeeSim:
                 db = self.courant / m_safe
             self.da[a] = np.where(pmc, 0.0, da)
             self.db[a] = np.where(pmc, 0.0, db)
+
+    def _lorentz_setup(self):
+        """Per E component: the Lorentz terms of every cell (d_eps, w0 as
+        arrays, zero where a cell has fewer terms or is a conductor), eps_inf,
+        and the polarizations P^m, P^{m-1} of each term."""
+        wl = self.wl
+        lor = {k: tuple(v) for k, v in (getattr(wl, "lorentz", None) or {}).items() if v}
+        self.poles, self.P = {}, {}
+        if not lor:
+            return
+        n_terms = max(len(v) for v in lor.values())
+        eps = np.asarray(wl.eps, dtype=np.float64)
+        for a in self.e_comps:
+            ids = wl.comp_ids["E" + a]
+            live = self.cb[a] != 0.0                        # not a conductor or a PEC wall
+            terms = []
+            for j in range(n_terms):
+                de = np.zeros(ids.shape)
+                w0 = np.zeros(ids.shape)
+                for k, v in lor.items():
+                    if j < len(v):
+                        sel = (ids == k) & live
+                        de[sel] = v[j][0]
+                        w0[sel] = v[j][1]
+                if np.any(w0 * self.dt >= 2.0):
+                    raise ValueError("Lorentz term unstable: w0 dt must stay below 2")
+                terms.append((de, w0))
+            e_inf = np.where(live, eps[ids], 1.0)
+            self.poles[a] = (terms, e_inf)
+            self.P[a] = [[np.zeros(self.E[a].shape), np.zeros(self.E[a].shape)] for _ in terms]
 
     def _pml_setup(self):
         wl = self.wl
@@ -246,7 +299,21 @@ class YeeSim:
     def step_e(self):
         curls = {a: self.curl_h(a) for a in self.e_comps}
         for a in self.e_comps:
-            self.E[a] = self.ca[a] * self.E[a] + self.cb[a] * curls[a]
+            new = self.ca[a] * self.E[a] + self.cb[a] * curls[a]
+            if a in self.poles:
+                terms, e_inf = self.poles[a]
+                dt, r = self.dt, 0.5 * self.sigma * self.dt
+                p_now = np.zeros(new.shape)
+                p_next = np.zeros(new.shape)
+                for (de, w0), st in zip(terms, self.P[a]):
+                    cur, prev = st
+                    nxt = ((2.0 - (w0 * dt) ** 2) * cur - (1.0 - r) * prev
+                           + de * (w0 * dt) ** 2 * self.E[a]) / (1.0 + r)
+                    p_now += cur
+                    p_next += nxt
+                    st[0], st[1] = nxt, cur
+                new = new - (p_next - self.ca[a] * p_now) / e_inf
+            self.E[a] = new
 
     def step(self):
         self.step_h()

@@ -61,7 +61,15 @@ def curl_operators(wl, pol):
     return De, Dh, AE, AH, e_axes, h_axes, n
 
 
-def frequency_force(wl, pol, nodes=100):
+def frequency_force(*args, **kw):
+    """frequency force on one BLAS thread (the test runner's
+    workers would otherwise oversubscribe the host's cores)."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        return _frequency_force(*args, **kw)
+
+
+def _frequency_force(wl, pol, nodes=100):
     """(1/pi) int_0^inf w(kappa) sum_c s_c Gamma^_c(kappa) dkappa for the
     channels of one polarization (kappa = u^2, u = v / (1 - v), v in (0, 1)
     on Gauss-Legendre nodes)."""
