@@ -151,6 +151,23 @@ typedef struct cf_materials {
     const double* eps;
     const double* mu;
     const uint8_t* comp_id[6];
+    /* Dispersive materials (Sec. III B: a fitted Lorentz model, continued onto
+     * the complex conductivity contour).  Material id has the permittivity
+     *   eps(omega) = eps[id] + sum_j d_eps_j w0_j^2 / (w0_j^2 - omega^2),
+     * d_eps_j = lorentz_deps[id * n_lorentz + j], w0_j = lorentz_w0[...]
+     * (w0 in radians per unit time, c = 1; a term with d_eps = 0 is absent).
+     * On the contour omega^2 = xi^2 + i sigma xi every term becomes a
+     * polarization P with P'' + sigma P' + w0^2 P = d_eps w0^2 E, and
+     * D = eps[id] E + sum P carries the conductivity of E-current runs.
+     * n_lorentz = 0 (or NULL arrays): no dispersion.  Limits: Cartesian 2D
+     * problems only (else CF_E_UNSUPPORTED at validation); S must lie in a
+     * non-dispersive medium (CF_E_SURFACE); w0 dt < 2 for every term
+     * (CF_E_CFL); at most 4 terms per material.  Dispersive problems run on
+     * the split half-step kernels (the fused kernel does not take them) and
+     * are not served (CF_E_UNSUPPORTED). */
+    int n_lorentz;
+    const double* lorentz_deps;
+    const double* lorentz_w0;
 } cf_materials;
 
 /*

@@ -46,7 +46,9 @@ class _Grid(C.Structure):
 
 class _Materials(C.Structure):
     _fields_ = [("n_materials", C.c_int), ("eps", C.POINTER(C.c_double)),
-                ("mu", C.POINTER(C.c_double)), ("comp_id", C.c_void_p * 6)]
+                ("mu", C.POINTER(C.c_double)), ("comp_id", C.c_void_p * 6),
+                ("n_lorentz", C.c_int), ("lorentz_deps", C.POINTER(C.c_double)),
+                ("lorentz_w0", C.POINTER(C.c_double))]
 
 
 class _Surface(C.Structure):
@@ -198,7 +200,8 @@ class Problem:
                  eps: Sequence[float], mu: Sequence[float], comp_ids: Dict[str, np.ndarray],
                  s_lo: Sequence[int], s_hi: Sequence[int], n_harm: int, force_axis: int,
                  pml_cells: Sequence[int] = (0, 0, 0), coord: str = "cartesian", m_max: int = 0,
-                 kz: Sequence[float] = (), kz_weight: Sequence[float] = (), kx: Sequence[float] = ()):
+                 kz: Sequence[float] = (), kz_weight: Sequence[float] = (), kx: Sequence[float] = (),
+                 lorentz: Optional[Dict[int, Sequence[Sequence[float]]]] = None):
         lib = load()
         g = _Grid()
         g.ndim = int(ndim)
@@ -214,6 +217,18 @@ class Problem:
         m.n_materials = len(self._eps)
         m.eps = _dptr(self._eps)
         m.mu = _dptr(self._mu)
+        # Lorentz terms {id: ((d_eps, w0), ...)} as n_materials x n_terms arrays
+        terms = {int(k): list(v) for k, v in (lorentz or {}).items() if v}
+        n_lor = max((len(v) for v in terms.values()), default=0)
+        if n_lor:
+            self._lde = np.zeros((len(self._eps), n_lor))
+            self._lw0 = np.zeros((len(self._eps), n_lor))
+            for k, v in terms.items():
+                for j, (de, w0) in enumerate(v):
+                    self._lde[k, j], self._lw0[k, j] = float(de), float(w0)
+            m.n_lorentz = n_lor
+            m.lorentz_deps = _dptr(self._lde)
+            m.lorentz_w0 = _dptr(self._lw0)
         self._ids = []
         for k, name in enumerate(COMPONENTS):
             arr = comp_ids.get(name)
@@ -256,7 +271,7 @@ class Problem:
     def from_workload(cls, wl) -> "Problem":
         return cls(wl.ndim, wl.shape, wl.res, wl.bc, wl.eps, wl.mu, wl.comp_ids, wl.s_lo, wl.s_hi,
                    wl.n_harm, wl.force_axis, wl.pml_cells, coord=wl.coord, m_max=wl.m_max,
-                   kz=wl.kz, kz_weight=wl.kz_weight, kx=wl.kx)
+                   kz=wl.kz, kz_weight=wl.kz_weight, kx=wl.kx, lorentz=getattr(wl, "lorentz", None))
 
     def __del__(self):
         h = getattr(self, "_h", None)

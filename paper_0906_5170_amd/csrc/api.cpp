@@ -65,7 +65,7 @@ bool g_tune_loaded = false;
 // Device workspace layout of one solve.
 struct Layout {
     size_t ids, lut, ktab, pml, chans, slots, gidx, gw, uidx, uoff, usamp, uw, basis, acc, gamma,
-        fields, fields2, psi, psi2, idp, shadow, rinv, inst, work, total;
+        fields, fields2, psi, psi2, idp, shadow, rinv, inst, work, aux, lor, total;
     size_t work_items;    // capacity of one work list
 };
 
@@ -262,6 +262,8 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
     std::vector<int> block_of(C, 0);
     for (const auto& wl : wave_lists)
         for (size_t k = 0; k < wl.size(); ++k) block_of[wl[k]] = (int)k;
+    // dispersive media: (P^m, P^{m-1}) per E slot (two, the TE count) and term
+    st.aux_block = p.dispersive ? (int64_t)2 * p.n_lor * 2 * p.ncell : 0;
     const double res = p.grid.res;
     for (int c = 0; c < C; ++c) {
         const cf::Channel& ch = chans[c];
@@ -273,6 +275,7 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         cf::ChanDev d{};
         d.field_off = (int64_t)blk * st.ncomp * p.ncell;
         d.psi_off = (int64_t)blk * 4 * st.psi_comp;
+        d.aux_off = (int64_t)blk * st.aux_block;
         d.src_off = d.field_off + (int64_t)cf::comp_slot(ch.pol, ch.src) * p.ncell;
         d.meas_off = d.field_off + (int64_t)cf::comp_slot(ch.pol, ch.meas) * p.ncell;
         d.kind = ch.kind;
@@ -346,7 +349,9 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         }
         if (st.v3d >= 0 && cf::f3d_steps(st.v3d) == 2 && st.sbox.vol <= 0) st.v3d = cf::f3d_single(st.v3d);
     }
-    if (!plain && p.grid.ndim == 2 && !(o.flags & CF_FLAG_SPLIT)) {
+    // the fused kernel carries no polarizations: dispersive problems take the
+    // split half-step kernels
+    if (!plain && p.grid.ndim == 2 && !(o.flags & CF_FLAG_SPLIT) && !p.dispersive) {
         cf::TBShape sh[cf::kMaxVariants];
         const int nv = o.precision == CF_FP64 ? cf::tb_variants<double>(sh, cf::kMaxVariants)
                                               : cf::tb_variants<float>(sh, cf::kMaxVariants);
@@ -605,8 +610,34 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.work_items = max_tiles ? work_capacity(st.resident, max_tiles) : 0;
     L.inst = take(sizeof(cf::InstDev));
     L.work = take(2 * L.work_items * sizeof(cf::WorkItem) + 8);
+    L.aux = st.aux_block ? take((size_t)st.resident * st.aux_block * fsz) : off;
+    L.lor = p.dispersive ? take((size_t)256 * cf::kLorStride(p.n_lor) * 8) : off;
     L.total = off;
     return L;
+}
+
+// Per material id: [flag, 1/eps_inf, (c1, c2, c3) per term] of the centred
+// Lorentz update P^{m+1} = c1 P^m - c2 P^{m-1} + c3 E^m on the conductivity
+// contour (damping sigma): c1 = (2 - (w0 dt)^2)/(1 + r), c2 = (1 - r)/(1 + r),
+// c3 = d_eps (w0 dt)^2/(1 + r), r = sigma dt / 2.  Conductors and ids
+// without terms have flag 0.
+std::vector<double> lorentz_table(const cf::Problem& p, double sigma, double courant) {
+    const int stride = cf::kLorStride(p.n_lor);
+    std::vector<double> t((size_t)256 * stride, 0.0);
+    const double dt = courant / p.grid.res, r = 0.5 * sigma * dt;
+    for (int id = 0; id < p.nmat; ++id) {
+        if (!p.has_terms(id) || !std::isfinite(p.eps[id])) continue;
+        double* row = t.data() + (size_t)id * stride;
+        row[0] = 1.0;
+        row[1] = 1.0 / p.eps[id];
+        for (int j = 0; j < p.n_lor; ++j) {
+            const double de = p.lor_de[(size_t)id * p.n_lor + j], w = p.lor_w0[(size_t)id * p.n_lor + j] * dt;
+            row[2 + 3 * j] = de != 0.0 ? (2.0 - w * w) / (1.0 + r) : 0.0;
+            row[3 + 3 * j] = de != 0.0 ? (1.0 - r) / (1.0 + r) : 0.0;
+            row[4 + 3 * j] = de * w * w / (1.0 + r);
+        }
+    }
+    return t;
 }
 
 
@@ -946,6 +977,11 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     CF_HIP(hipMemsetAsync(ws + L.acc, 0, C * 2 * 8, s));
     const bool keep_gamma = (o.flags & CF_FLAG_KEEP_GAMMA) != 0;
     if (keep_gamma) CF_HIP(hipMemsetAsync(ws + L.gamma, 0, (size_t)o.n_steps * C * 8, s));
+    std::vector<double> lor;
+    if (p.dispersive) {
+        lor = lorentz_table(p, o.sigma, o.courant);
+        CF_HIP(up(L.lor, lor.data(), lor.size() * 8));
+    }
 
     T* fields = reinterpret_cast<T*>(ws + L.fields);
     T* psi = st.psi_comp > 0 ? reinterpret_cast<T*>(ws + L.psi) : nullptr;
@@ -972,6 +1008,12 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     g.perx = p.grid.bc[0] == CF_BC_PERIODIC;
     g.pery = p.grid.bc[1] == CF_BC_PERIODIC;
     for (int c = 0; c < cf::kNumComp; ++c) g.ids[c] = dids + (size_t)c * p.ncell;
+    if (p.dispersive) {
+        g.n_lor = p.n_lor;
+        g.lor = reinterpret_cast<const double*>(ws + L.lor);
+        g.aux = ws + L.aux;
+    }
+    const size_t aux_bytes = (size_t)st.resident * st.aux_block * sizeof(T);
     cf::Grid3D g3{};
     g3.nx = p.nx;
     g3.ny = p.ny;
@@ -1179,6 +1221,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
                 const int pol = st.chans[st.slot_lists[w.all_off + k]].pol;
                 STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
                 if (psi) STEP_OK(hipMemsetAsync(psi, 0, psi_bytes, s));
+                if (aux_bytes) STEP_OK(hipMemsetAsync(ws + L.aux, 0, aux_bytes, s));
                 STEP_OK(cf::launch_kick<T>(fields, dch, one, 1, st.max_uniq, tabs, s));
                 if (three) {
                     STEP_OK(cf::launch_h3d<T>(1, fields, psi, dch, one, 1, g3, dlut, s));
@@ -1204,6 +1247,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
         // batched: kick and consistent start for the whole wave
         STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
         if (psi) STEP_OK(hipMemsetAsync(psi, 0, psi_bytes, s));
+        if (aux_bytes) STEP_OK(hipMemsetAsync(ws + L.aux, 0, aux_bytes, s));
         STEP_OK(cf::launch_kick<T>(fields, dch, s_all, w.n_all, st.max_uniq, tabs, s));
         if (three) {
             STEP_OK(cf::launch_h3d<T>(1, fields, psi, dch, s_3d, w.n_3d, g3, dlut, s));
@@ -1933,7 +1977,7 @@ static cf_status cf_batch_workspace_size_impl(cf_problem* const* probs, int n, c
     for (int i = 0; i < n; ++i) {
         cf_status st = cf_validate(probs[i], o);
         if (st != CF_OK) return st;
-        if (probs[i]->p.grid.ndim == 2 && !probs[i]->p.reduced()) fused.push_back(probs[i]);
+        if (probs[i]->p.grid.ndim == 2 && !probs[i]->p.reduced() && !probs[i]->p.dispersive) fused.push_back(probs[i]);
         size_t b = 0;
         cf_opts oo = *o;
         oo.n_subset = 0;
@@ -2031,7 +2075,8 @@ static cf_status cf_batch_solve_impl(cf_problem* const* probs, int n, const cf_o
     std::vector<int> fused_idx;
     if (!(o->flags & CF_FLAG_SPLIT))
         for (int i = 0; i < n; ++i)
-            if (probs[i]->p.grid.ndim == 2 && !probs[i]->p.reduced()) fused_idx.push_back(i);
+            if (probs[i]->p.grid.ndim == 2 && !probs[i]->p.reduced() && !probs[i]->p.dispersive)
+                fused_idx.push_back(i);
     BatchPlan B;
     if (fused_idx.size() >= 1) {
         std::vector<cf_problem*> fp;

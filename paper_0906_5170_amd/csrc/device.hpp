@@ -29,6 +29,7 @@ struct ChanDev {
     int32_t basis_off;   // first basis value of the channel's row
     int32_t meas_slot;   // slot of the measured component in the field block
     double kick_scale;   // -res / (eps_S or mu_S)
+    int64_t aux_off;     // first element of the channel's polarization block (dispersive media)
 };
 
 // Material id of cells outside a non-periodic grid inside a fused tile's
@@ -41,7 +42,16 @@ struct Grid2D {
     int64_t ncell;
     int perx, pery;
     const uint8_t* ids[6];   // per-component material ids
+    // Dispersive media (split E half step): per material id a row of
+    // kLorStride(n_lor) doubles [flag, 1/eps_inf, (c1, c2, c3) per term] with
+    // P^{m+1} = c1 P^m - c2 P^{m-1} + c3 E^m; flag != 0 marks an id with terms.
+    // aux holds per channel (at ChanDev.aux_off) per E slot e and term j the
+    // pair (P^m, P^{m-1}) as two grids: aux[((e * n_lor + j) * 2 + k) * ncell + cell].
+    int n_lor;
+    const double* lor;
+    void* aux;
 };
+constexpr int kLorStride(int n_lor) { return 2 + 3 * n_lor; }
 
 struct SurfTables {
     const int32_t* gidx;

@@ -90,6 +90,28 @@ __global__ __launch_bounds__(BX* BY) void k_h2d(T* __restrict__ fields, const Ch
     }
 }
 
+// Dispersive media: advances the Lorentz polarizations of one E component at
+// cell c (every term's pair P^m, P^{m-1} -> P^{m+1}, P^m, from E^m = e_old)
+// and returns (sum P^{m+1} - a sum P^m) / eps_inf, the amount the E update
+// of D = eps_inf E + sum P subtracts.  Zero for an id without terms.
+template <typename T>
+__device__ __forceinline__ T lorentz_step(const Grid2D& g, T* aux, int e_slot, int64_t c, int id, T a, T e_old) {
+    const double* row = g.lor + (size_t)id * kLorStride(g.n_lor);
+    if (row[0] == 0.0) return T(0);
+    T sum_now = T(0), sum_next = T(0);
+    for (int j = 0; j < g.n_lor; ++j) {
+        T* pc = aux + (int64_t)((e_slot * g.n_lor + j) * 2) * g.ncell + c;
+        T* pp = pc + g.ncell;
+        const T cur = *pc, prev = *pp;
+        const T nxt = fma(T(row[2 + 3 * j]), cur, fma(-T(row[3 + 3 * j]), prev, T(row[4 + 3 * j]) * e_old));
+        sum_now += cur;
+        sum_next += nxt;
+        *pp = cur;
+        *pc = nxt;
+    }
+    return (sum_next - a * sum_now) * T(row[1]);
+}
+
 template <typename T, int POL, int MODE>
 __global__ __launch_bounds__(BX* BY) void k_e2d(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                               const int* __restrict__ slots, Grid2D g,
@@ -112,7 +134,11 @@ __global__ __launch_bounds__(BX* BY) void k_e2d(T* __restrict__ fields, const Ch
         const T curl = (hy - hyl) - (hx - hxd);
         const T* lz = lut_ab(lut, d.kind, CF_EZ, g.ids[CF_EZ][c]);
         if (MODE == 0) {
-            Ez[c] = yee_add(lz[0], Ez[c], lz[1], curl);
+            const T ez = Ez[c];
+            T e_new = yee_add(lz[0], ez, lz[1], curl);
+            if (g.n_lor > 0)
+                e_new -= lorentz_step(g, static_cast<T*>(g.aux) + d.aux_off, 0, c, g.ids[CF_EZ][c], lz[0], ez);
+            Ez[c] = e_new;
         } else {
             Ez[c] = yee_half(lz[1], curl);
         }
@@ -126,8 +152,16 @@ __global__ __launch_bounds__(BX* BY) void k_e2d(T* __restrict__ fields, const Ch
         const T* lx = lut_ab(lut, d.kind, CF_EX, g.ids[CF_EX][c]);
         const T* ly = lut_ab(lut, d.kind, CF_EY, g.ids[CF_EY][c]);
         if (MODE == 0) {
-            Ex[c] = yee_add(lx[0], Ex[c], lx[1], hz - hzd);
-            Ey[c] = yee_sub(ly[0], Ey[c], ly[1], hz - hzl);
+            const T ex = Ex[c], ey = Ey[c];
+            T ex_new = yee_add(lx[0], ex, lx[1], hz - hzd);
+            T ey_new = yee_sub(ly[0], ey, ly[1], hz - hzl);
+            if (g.n_lor > 0) {
+                T* aux = static_cast<T*>(g.aux) + d.aux_off;
+                ex_new -= lorentz_step(g, aux, 0, c, g.ids[CF_EX][c], lx[0], ex);
+                ey_new -= lorentz_step(g, aux, 1, c, g.ids[CF_EY][c], ly[0], ey);
+            }
+            Ex[c] = ex_new;
+            Ey[c] = ey_new;
         } else {
             Ex[c] = yee_half(lx[1], hz - hzd);
             Ey[c] = -yee_half(ly[1], hz - hzl);

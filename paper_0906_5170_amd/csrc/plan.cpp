@@ -442,13 +442,30 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
             used[0] = 1;
         }
     }
+    // Lorentz terms of dispersive materials
+    p.n_lor = 0;
+    p.lor_de.clear();
+    p.lor_w0.clear();
+    p.dispersive = false;
+    if (m.n_lorentz < 0 || m.n_lorentz > 4) return "n_lorentz must be in 0..4";
+    if (m.n_lorentz > 0 && m.lorentz_deps && m.lorentz_w0) {
+        p.n_lor = m.n_lorentz;
+        const size_t n = (size_t)p.nmat * p.n_lor;
+        p.lor_de.assign(m.lorentz_deps, m.lorentz_deps + n);
+        p.lor_w0.assign(m.lorentz_w0, m.lorentz_w0 + n);
+        for (size_t k = 0; k < n; ++k)
+            if (!std::isfinite(p.lor_de[k]) || !std::isfinite(p.lor_w0[k]) || !(p.lor_w0[k] > 0 || p.lor_de[k] == 0))
+                return "Lorentz terms need finite d_eps and w0 > 0";
+    }
     // Appendix A.2's kernel assumes perfect conductors in vacuum: note
     // whether every material the grid uses is vacuum or a perfect conductor
     p.vacuum_conductors = true;
     for (int i = 0; i < p.nmat; ++i) {
         if (!used[i]) continue;
         const bool conductor = (std::isinf(p.eps[i]) && p.eps[i] < 0) || (std::isinf(p.mu[i]) && p.mu[i] < 0);
-        if (!conductor && !(p.eps[i] == 1.0 && p.mu[i] == 1.0)) p.vacuum_conductors = false;
+        const bool terms = !(std::isinf(p.eps[i]) && p.eps[i] < 0) && p.has_terms(i);
+        p.dispersive = p.dispersive || terms;
+        if (!conductor && (terms || !(p.eps[i] == 1.0 && p.mu[i] == 1.0))) p.vacuum_conductors = false;
     }
     // E components lying on a PEC(-backed) wall: integer coordinate 0 along
     // a non-periodic axis.
@@ -578,6 +595,8 @@ static std::string surface_medium(Problem& p) {
             int id = p.ids[c][ix];
             if (is_e(c)) {
                 e_vals.insert(id == kWallId ? -INFINITY : p.eps[id]);
+                // a dispersive medium would make the stress tensor's eps_S depend on frequency
+                if (id != kWallId && p.has_terms(id)) return "stress surface lies in a dispersive material";
             } else {
                 h_vals.insert(p.mu[id]);
             }
@@ -650,6 +669,10 @@ std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
             return "the z-invariant kernel applies to 2D runs only";
         }
     }
+    if (p.dispersive && (p.grid.ndim == 3 || p.reduced())) {
+        *code = CF_E_UNSUPPORTED;
+        return "dispersive materials are implemented for Cartesian 2D problems";
+    }
     if (p.grid.ndim == 2) {
         for (int a = 0; a < 2; ++a)
             if (p.grid.bc[a] == CF_BC_PML) {
@@ -674,6 +697,15 @@ std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
     if (o.courant * vmax * std::sqrt((double)p.grid.ndim) >= 1.0) {
         *code = CF_E_CFL;
         return "courant number above the Yee stability limit";
+    }
+    if (p.dispersive) {
+        // centred Lorentz update: stable for w0 dt < 2
+        const double dt = o.courant / p.grid.res;
+        for (size_t k = 0; k < p.lor_w0.size(); ++k)
+            if (p.lor_de[k] != 0.0 && p.lor_w0[k] * dt >= 2.0) {
+                *code = CF_E_CFL;
+                return "a Lorentz term has w0 dt >= 2 (unstable)";
+            }
     }
     if (p.cyl && o.courant * vmax > 0.5) {
         *code = CF_E_CFL;

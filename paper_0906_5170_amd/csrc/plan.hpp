@@ -88,6 +88,18 @@ struct Problem {
     // every material the grid uses is vacuum (eps = mu = 1) or a perfect
     // electric / magnetic conductor (the premise of the z-invariant kernel)
     bool vacuum_conductors = true;
+    // Lorentz terms (d_eps, w0) of each material, n_lor per material
+    // (nmat x n_lor, row-major); dispersive: some material the grid uses has
+    // a term with d_eps != 0 (not a conductor)
+    int n_lor = 0;
+    std::vector<double> lor_de, lor_w0;
+    bool dispersive = false;
+    bool has_terms(int id) const {
+        if (id >= nmat) return false;
+        for (int j = 0; j < n_lor; ++j)
+            if (lor_de[(size_t)id * n_lor + j] != 0.0) return true;
+        return false;
+    }
     // reduced two-dimensional problems: six components, one run per order
     // (azimuthal order m, or k_z point q)
     bool reduced() const { return cyl || kz; }

@@ -81,6 +81,7 @@ struct Staged {
     bool f3d = false;                      // 3D steps on the fused z-streaming kernel
     int v3d = -1;                          // its variant when fixed by the options (-1: autotune)
     cf::ShadowBox sbox{};                  // surface box of a 3D solve (two-step fused launches)
+    int64_t aux_block = 0;                 // polarization values per resident channel (dispersive media)
 };
 
 struct StencilTiming {

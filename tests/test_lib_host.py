@@ -317,3 +317,28 @@ def test_zinv_kernel_needs_perfect_conductors_in_vacuum(cf):
     spare = piston2d(24, 18, 3, 6, 4, 6, 7, 6.0)
     assert spare.eps[2] == 1.0
     cf.Problem.from_workload(spare.replace(eps=list(spare.eps[:2]) + [4.0])).validate(kernel="zinv2d", **opts)
+
+
+def test_dispersive_validation(cf):
+    """Lorentz media (Sec. III B): accepted for Cartesian 2D problems with the
+    general kernel; S inside a dispersive material gives CF_E_SURFACE, a term
+    with w0 dt >= 2 CF_E_CFL, the z-invariant kernel CF_E_UNSUPPORTED."""
+    base = piston2d(40, 24, 4, 10, 5, 10, 7, 10.0, pol="TM+TE", n_harm=6, n_steps=50, kernel="general")
+    ids = {k: v.copy() for k, v in base.comp_ids.items()}
+    for v in ids.values():
+        left = v[:, :, :20]
+        left[left == 1] = 3
+    wl = base.replace(eps=[1.0, float("-inf"), 1.0, 2.0], mu=[1.0] * 4, comp_ids=ids, lorentz={3: ((3.0, 2.0),)})
+    opts = dict(sigma=1.0, courant=0.5, n_steps=50, pol="TM+TE", precision="fp32")
+    p = cf.Problem.from_workload(wl)
+    p.validate(kernel="general", **opts)
+    with pytest.raises(cf.CfError) as e:
+        p.validate(kernel="zinv2d", **opts)
+    assert e.value.status == "CF_E_UNSUPPORTED"
+    with pytest.raises(cf.CfError) as e:
+        cf.Problem.from_workload(wl.replace(lorentz={0: ((1.0, 2.0),)}))
+    assert e.value.status == "CF_E_SURFACE"
+    fast = cf.Problem.from_workload(wl.replace(lorentz={3: ((1.0, 2.0 / (0.5 / 10.0)),)}))
+    with pytest.raises(cf.CfError) as e:
+        fast.validate(kernel="general", **opts)
+    assert e.value.status == "CF_E_CFL"
