@@ -65,7 +65,7 @@ bool g_tune_loaded = false;
 // Device workspace layout of one solve.
 struct Layout {
     size_t ids, lut, ktab, pml, chans, slots, gidx, gw, uidx, uoff, usamp, uw, basis, acc, gamma,
-        fields, fields2, psi, psi2, idp, shadow, rinv, inst, work, aux, lor, total;
+        fields, fields2, psi, psi2, idp, shadow, rinv, inst, work, aux, lor, zr, total;
     size_t work_items;    // capacity of one work list
 };
 
@@ -198,9 +198,72 @@ std::vector<TBPlan> cached_plans(const cf::Problem& p, const std::vector<cf::Cha
     return plans;
 }
 
+// 3D: for every (plane z, row y), whether some E component of the row can be
+// nonzero (coefficients not a = b = 0), row-major [z][y]; kept per problem
+// (a scan of every cell).
+std::map<uint64_t, std::vector<uint8_t>> g_erows;
+
+std::vector<uint8_t> e_live_rows(const cf::Problem& p) {
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        auto it = g_erows.find(p.uid);
+        if (it != g_erows.end()) return it->second;
+    }
+    std::vector<uint8_t> rows((size_t)p.nz * p.ny, 0);
+    for (int c = CF_EX; c <= CF_EZ; ++c)
+        for (int64_t k = 0; k < p.ncell; ++k) {
+            const int id = p.ids[c][k];
+            if (id != cf::kWallId && id < p.nmat && std::isfinite(p.eps[id])) rows[k / p.nx] = 1;
+        }
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (g_erows.size() >= 64) g_erows.clear();
+    g_erows[p.uid] = rows;
+    return rows;
+}
+
 void forget_plans(uint64_t uid) {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     for (auto it = g_plans.begin(); it != g_plans.end();) it = (uint64_t)it->first[0] == uid ? g_plans.erase(it) : std::next(it);
+    g_erows.erase(uid);
+}
+
+// Per band of each fused 3D variant, the planes [lo, hi) the band's region
+// (its rows plus one halo row per step on either side) can change: E can be
+// nonzero only on planes kmin..kmax where some E component of those rows has
+// nonzero coefficients, H only on kmin - 1..kmax (its z difference reads the
+// next plane); outside, every field stays 0 and the kernel skips the planes.
+void stage_zranges(const cf::Problem& p, Staged& st) {
+    const std::vector<uint8_t> rows = e_live_rows(p);
+    const bool pery = p.grid.bc[1] == CF_BC_PERIODIC;
+    st.zr.clear();
+    std::vector<uint8_t> live(p.nz);
+    for (int v = 0; v < cf::f3d_variants() && v < 8; ++v) {
+        int W, B, steps;
+        cf::f3d_shape(v, &W, &B, &steps);
+        st.zr_off[v] = (int)(st.zr.size() / 2);
+        const int band = W * B - 2 * steps;
+        if (band <= 0) continue;
+        const int nb = (p.ny + band - 1) / band;
+        for (int b = 0; b < nb; ++b) {
+            std::fill(live.begin(), live.end(), 0);
+            for (int ry = 0; ry < W * B; ++ry) {
+                int y = b * band - steps + ry;
+                if (y < 0 || y >= p.ny) {
+                    if (!pery) continue;
+                    y = ((y % p.ny) + p.ny) % p.ny;
+                }
+                for (int z = 0; z < p.nz; ++z) live[z] |= rows[(size_t)z * p.ny + y];
+            }
+            int kmin = -1, kmax = -1;
+            for (int z = 0; z < p.nz; ++z)
+                if (live[z]) {
+                    if (kmin < 0) kmin = z;
+                    kmax = z;
+                }
+            st.zr.push_back(kmin < 0 ? 0 : std::max(kmin - 1, 0));
+            st.zr.push_back(kmin < 0 ? 0 : kmax + 1);
+        }
+    }
 }
 
 // Build host copies of every table a solve uploads.  Channels run in waves
@@ -348,6 +411,7 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
             b.vol = (int64_t)b.bnx * b.bny * b.bnz;
         }
         if (st.v3d >= 0 && cf::f3d_steps(st.v3d) == 2 && st.sbox.vol <= 0) st.v3d = cf::f3d_single(st.v3d);
+        if (st.f3d) stage_zranges(p, st);
     }
     // the fused kernel carries no polarizations: dispersive problems take the
     // split half-step kernels
@@ -611,6 +675,7 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.inst = take(sizeof(cf::InstDev));
     L.work = take(2 * L.work_items * sizeof(cf::WorkItem) + 8);
     L.aux = st.aux_block ? take((size_t)st.resident * st.aux_block * fsz) : off;
+    L.zr = st.zr.empty() ? off : take(st.zr.size() * 4 + 8);
     L.lor = p.dispersive ? take((size_t)256 * cf::kLorStride(p.n_lor) * 8) : off;
     L.total = off;
     return L;
@@ -973,6 +1038,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             idp[2 * c + 1] = uint32_t(p.ids[CF_HY][c]) | (uint32_t(p.ids[CF_HZ][c]) << 8);
         }
         CF_HIP(up(L.idp, idp.data(), idp.size() * 4));
+        if (!st.zr.empty()) CF_HIP(up(L.zr, st.zr.data(), st.zr.size() * 4));
     }
     CF_HIP(hipMemsetAsync(ws + L.acc, 0, C * 2 * 8, s));
     const bool keep_gamma = (o.flags & CF_FLAG_KEEP_GAMMA) != 0;
@@ -1028,6 +1094,8 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     g3.pml_be = dpml + 2 * p.nz;
     g3.pml_ce = dpml + 3 * p.nz;
     g3.idp = st.f3d ? reinterpret_cast<const uint2*>(ws + L.idp) : nullptr;
+    g3.zr_tab = st.f3d && !st.zr.empty() ? reinterpret_cast<const int2*>(ws + L.zr) : nullptr;
+    for (int v = 0; v < 8; ++v) g3.zr_off[v] = st.zr_off[v];
     const double dt = o.courant / p.grid.res;
     const double dA = std::pow(1.0 / p.grid.res, p.grid.ndim - 1);
     const size_t field_bytes = (size_t)st.resident * st.ncomp * p.ncell * sizeof(T);
@@ -1299,6 +1367,8 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             T* pa = psi;
             T* pb = psi ? reinterpret_cast<T*>(ws + L.psi2) : nullptr;
             if (pb) STEP_OK(hipMemsetAsync(pb, 0, psi_bytes, s));
+            // planes the kernel skips are never written: zero in both arrays
+            STEP_OK(hipMemsetAsync(fb, 0, field_bytes, s));
             T* sh = reinterpret_cast<T*>(ws + L.shadow);
             // a two-step variant takes steps in pairs (the surface of the first
             // step of a pair is read from the shadow box); an odd last step

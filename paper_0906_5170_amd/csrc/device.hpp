@@ -122,7 +122,16 @@ struct Grid3D {
     // fused 3D step only: material ids packed per cell, x = Ex | Ey << 8 |
     // Ez << 16 | Hx << 24, y = Hy | Hz << 8
     const uint2* idp;
+    // fused 3D steps: per band of a variant, the planes [x, y) outside which
+    // the band's region holds no field that can become nonzero (every E
+    // component there and on the next plane is held at 0 by a perfect
+    // conductor, so H keeps its initial 0 too); variant v's table starts at
+    // zr_tab + zr_off[v].  zr_tab == nullptr: every plane is marched.
+    const int2* zr_tab;
+    int zr_off[8];
 };
+// Shape of fused 3D variant v: waves W, rows per wave B, steps per launch.
+void f3d_shape(int variant, int* w, int* b, int* steps);
 
 
 

@@ -196,11 +196,42 @@ constexpr size_t f3_lds_bytes(int W, int CX) {
 }
 constexpr size_t kF3LdsMax = 160 * 1024;   // LDS of a gfx950 CU
 
+// Logical (band, slot, chunk) of a fused 3D block.  Blocks are dispatched
+// to the 8 XCDs round-robin in flat-id order; numbering the logical blocks so
+// that XCD x takes a contiguous range keeps neighbouring bands of a channel
+// (which read each other's halo rows) on one XCD and its L2.  The logical
+// order is band, then z chunk, then channel, so each XCD takes whole channels
+// and the same mix of chunks (chunks below a conductor may be short or
+// empty, see f3_chunk).
+struct F3Block {
+    int band, slot, chunk;
+};
+__device__ __forceinline__ F3Block f3_block() {
+    const unsigned nb = gridDim.x, nc = gridDim.z;
+    const unsigned total = nb * gridDim.y * nc;
+    const unsigned h = blockIdx.x + nb * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned q = total / 8, r = total % 8, x = h % 8;
+    const unsigned l = x * q + min(x, r) + h / 8;
+    return F3Block{(int)(l % nb), (int)(l / (nb * nc)), (int)((l / nb) % nc)};
+}
+
+// The z chunk of a block, clipped to the planes its band can change.
+__device__ __forceinline__ void f3_chunk(const Grid3D& g, const int2* zr, const F3Block& b, int* z0, int* z1) {
+    const int zc = (g.nz + (int)gridDim.z - 1) / (int)gridDim.z;
+    *z0 = b.chunk * zc;
+    *z1 = min(g.nz, *z0 + zc);
+    if (zr) {
+        const int2 r = zr[b.band];
+        *z0 = max(*z0, r.x);
+        *z1 = min(*z1, r.y);
+    }
+}
+
 template <typename T, int W, int B, int CX>
 __global__ __launch_bounds__(64 * W) void k_f3d(const ChanDev* __restrict__ ch, const int* __restrict__ slots,
                                                  Grid3D g, const T* __restrict__ lut, const T* __restrict__ src,
                                                  T* __restrict__ dst, const T* __restrict__ psrc,
-                                                 T* __restrict__ pdst, int band) {
+                                                 T* __restrict__ pdst, int band, const int2* __restrict__ zr) {
     constexpr int NTB = 64 * W;
     extern __shared__ double f3_lds[];
     yee::Pair<T> (*L)[256] = reinterpret_cast<yee::Pair<T> (*)[256]>(f3_lds);   // [6][256] coefficient pairs
@@ -210,9 +241,10 @@ __global__ __launch_bounds__(64 * W) void k_f3d(const ChanDev* __restrict__ ch, 
     T (*xh)[2][CX][64] = reinterpret_cast<T (*)[2][CX][64]>(lds_xh);   // last region row of each wave: Hz, Hx
     T (*Lz)[2 * kF3MaxPml] =                                           // CPML b, c of the layer planes
         reinterpret_cast<T (*)[2 * kF3MaxPml]>(lds_xh + (size_t)W * 2 * CX * 64 * sizeof(T));
-    const ChanDev d = ch[slots[blockIdx.y]];
+    const F3Block fb = f3_block();
+    const ChanDev d = ch[slots[fb.slot]];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int yb = blockIdx.x * band - 1;            // global y of region row 0
+    const int yb = fb.band * band - 1;               // global y of region row 0
     for (int i = threadIdx.x; i < 6 * 256; i += NTB) {
         const int comp = i >> 8, id = i & 255;
         const T* p = lut_ab(lut, d.kind, comp, id);
@@ -254,8 +286,8 @@ __global__ __launch_bounds__(64 * W) void k_f3d(const ChanDev* __restrict__ ch, 
     // z chunk of this block: planes z0 .. z1-1 are stored; a chunk that does
     // not start at 0 first marches plane z0 - 1 to obtain H_new(z0 - 1)
     // (nothing of that plane is stored)
-    const int zc = (g.nz + (int)gridDim.z - 1) / (int)gridDim.z;
-    const int z0 = blockIdx.z * zc, z1 = min(g.nz, z0 + zc);
+    int z0, z1;
+    f3_chunk(g, zr, fb, &z0, &z1);
     if (z0 >= z1) return;                          // whole block: before any barrier
     const int kb = z0 > 0 ? z0 - 1 : 0;
     // Loads are issued from clamped (always valid) addresses and masked only
@@ -559,7 +591,7 @@ __global__ __launch_bounds__(64 * W) void k_f3d2(const ChanDev* __restrict__ ch,
                                                   Grid3D g, const T* __restrict__ lut, const T* __restrict__ src,
                                                   T* __restrict__ dst, const T* __restrict__ psrc,
                                                   T* __restrict__ pdst, T* __restrict__ shadow, ShadowBox sb,
-                                                  int band) {
+                                                  int band, const int2* __restrict__ zr) {
     constexpr int NTB = 64 * W;
     extern __shared__ double f3_lds[];
     yee::Pair<T> (*L)[256] = reinterpret_cast<yee::Pair<T> (*)[256]>(f3_lds);   // [6][256] coefficient pairs
@@ -569,9 +601,10 @@ __global__ __launch_bounds__(64 * W) void k_f3d2(const ChanDev* __restrict__ ch,
     T (*xh)[2][CX][64] = reinterpret_cast<T (*)[2][CX][64]>(lds_xh);   // last region row of each wave: Hz, Hx
     T (*Lz)[2 * kF3MaxPml] =                                           // CPML b, c of the layer planes
         reinterpret_cast<T (*)[2 * kF3MaxPml]>(lds_xh + (size_t)W * 2 * CX * 64 * sizeof(T));
-    const ChanDev d = ch[slots[blockIdx.y]];
+    const F3Block fb = f3_block();
+    const ChanDev d = ch[slots[fb.slot]];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int yb = blockIdx.x * band - 2;            // global y of region row 0
+    const int yb = fb.band * band - 2;               // global y of region row 0
     for (int i = threadIdx.x; i < 6 * 256; i += NTB) {
         const int comp = i >> 8, id = i & 255;
         const T* p = lut_ab(lut, d.kind, comp, id);
@@ -618,8 +651,8 @@ __global__ __launch_bounds__(64 * W) void k_f3d2(const ChanDev* __restrict__ ch,
     const bool T_PSI = g.pml > 0 && psrc != nullptr;
     const int ms = d.meas_slot;
 
-    const int zc = (g.nz + (int)gridDim.z - 1) / (int)gridDim.z;
-    const int z0 = blockIdx.z * zc, z1 = min(g.nz, z0 + zc);
+    int z0, z1;
+    f3_chunk(g, zr, fb, &z0, &z1);
     if (z0 >= z1) return;                          // whole block: before any barrier
     const int kb = max(z0 - 2, 0);                 // first level-1 plane
     const int p0 = z0 > 0 ? z0 - 1 : 0;            // first level-2 plane
@@ -1018,7 +1051,8 @@ bool f3_lds_attr(K kernel, size_t bytes) {
 
 template <typename T, int W, int B, int CX, int STEPS>
 hipError_t f3_launch(const ChanDev* ch, const int* slots, int nslots, const Grid3D& g, const T* lut, const T* src,
-                     T* dst, const T* psrc, T* pdst, T* shadow, const ShadowBox& sb, hipStream_t s) {
+                     T* dst, const T* psrc, T* pdst, T* shadow, const ShadowBox& sb, const int2* zr,
+                     hipStream_t s) {
     if constexpr (!f3_fits<T, W, CX>()) {
         return hipErrorInvalidValue;
     } else {
@@ -1035,13 +1069,13 @@ hipError_t f3_launch(const ChanDev* ch, const int* slots, int nslots, const Grid
             static const bool attr = f3_lds_attr(&k_f3d<T, W, B, CX>, lds);
             if (!attr) return hipErrorInvalidValue;
             hipLaunchKernelGGL((k_f3d<T, W, B, CX>), grid, block, lds, s, ch, slots, g, lut, src, dst, psrc, pdst,
-                               band);
+                               band, zr);
         } else {
             if (shadow == nullptr || sb.vol <= 0) return hipErrorInvalidValue;
             static const bool attr = f3_lds_attr(&k_f3d2<T, W, B, CX>, lds);
             if (!attr) return hipErrorInvalidValue;
             hipLaunchKernelGGL((k_f3d2<T, W, B, CX>), grid, block, lds, s, ch, slots, g, lut, src, dst, psrc, pdst,
-                               shadow, sb, band);
+                               shadow, sb, band, zr);
         }
         return hipGetLastError();
     }
@@ -1049,13 +1083,13 @@ hipError_t f3_launch(const ChanDev* ch, const int* slots, int nslots, const Grid
 
 template <typename T, int W, int B, int STEPS>
 hipError_t f3_dispatch_cx(int cx, const ChanDev* ch, const int* slots, int nslots, const Grid3D& g, const T* lut,
-                          const T* src, T* dst, const T* psrc, T* pdst, T* sh, const ShadowBox& sb,
+                          const T* src, T* dst, const T* psrc, T* pdst, T* sh, const ShadowBox& sb, const int2* zr,
                           hipStream_t s) {
     switch (cx) {
-        case 1: return f3_launch<T, W, B, 1, STEPS>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
-        case 2: return f3_launch<T, W, B, 2, STEPS>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
-        case 3: return f3_launch<T, W, B, 3, STEPS>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
-        case 4: return f3_launch<T, W, B, 4, STEPS>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
+        case 1: return f3_launch<T, W, B, 1, STEPS>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, zr, s);
+        case 2: return f3_launch<T, W, B, 2, STEPS>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, zr, s);
+        case 3: return f3_launch<T, W, B, 3, STEPS>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, zr, s);
+        case 4: return f3_launch<T, W, B, 4, STEPS>(ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, zr, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1115,14 +1149,24 @@ hipError_t launch_f3d(int variant, const ChanDev* ch, const int* slots, int nslo
     if (nslots <= 0) return hipSuccess;
     if (!f3d_usable<T>(variant, g)) return hipErrorInvalidValue;
     const int cx = (g.nx + 63) / 64;
+    const int2* zr = g.zr_tab ? g.zr_tab + g.zr_off[variant] : nullptr;
+#define CF_F3(W, B, S) f3_dispatch_cx<T, W, B, S>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, zr, s)
     switch (variant) {
-        case 0: return f3_dispatch_cx<T, 8, 2, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
-        case 1: return f3_dispatch_cx<T, 16, 1, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
-        case 2: return f3_dispatch_cx<T, 8, 1, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
-        case 3: return f3_dispatch_cx<T, 12, 1, 1>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
-        case 4: return f3_dispatch_cx<T, 8, 1, 2>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
-        default: return f3_dispatch_cx<T, 12, 1, 2>(cx, ch, slots, nslots, g, lut, src, dst, psrc, pdst, sh, sb, s);
+        case 0: return CF_F3(8, 2, 1);
+        case 1: return CF_F3(16, 1, 1);
+        case 2: return CF_F3(8, 1, 1);
+        case 3: return CF_F3(12, 1, 1);
+        case 4: return CF_F3(8, 1, 2);
+        default: return CF_F3(12, 1, 2);
     }
+#undef CF_F3
+}
+
+void f3d_shape(int variant, int* w, int* b, int* steps) {
+    const bool ok = variant >= 0 && variant < kNumF3;
+    *w = ok ? kF3[variant].W : 0;
+    *b = ok ? kF3[variant].B : 0;
+    *steps = ok ? kF3[variant].steps : 0;
 }
 
 template <typename T>

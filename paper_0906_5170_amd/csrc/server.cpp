@@ -68,7 +68,7 @@ struct Req {
     int C = 0;
     size_t bytes = 0, off = 0;
     size_t o_ids, o_lut, o_ktab, o_pml, o_ch, o_slots, o_gidx, o_gw, o_uidx, o_uoff, o_usamp, o_uw, o_basis,
-        o_acc, o_fa, o_fb, o_psi, o_psi2, o_idp, o_shadow;
+        o_acc, o_fa, o_fb, o_psi, o_psi2, o_idp, o_shadow, o_zr;
     std::vector<uint32_t> idp;        // fused 3D: packed material ids
     std::vector<uint8_t> ids;
     std::vector<uint8_t> lut;     // field-precision bytes
@@ -182,6 +182,7 @@ void layout_request(const cf_server* S, Req& r) {
     r.o_psi2 = st.psi_comp > 0 && f3 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
     r.o_idp = f3 ? take((size_t)p.ncell * 8) : off;
     r.o_shadow = f3 && cf::f3d_steps(r.v3) == 2 ? take((size_t)st.resident * st.sbox.vol * fsz) : off;
+    r.o_zr = f3 && !st.zr.empty() ? take(st.zr.size() * 4 + 8) : off;
     r.bytes = off;
 }
 
@@ -318,6 +319,8 @@ struct Dev {
         g.pml_be = pm + 2 * p.nz;
         g.pml_ce = pm + 3 * p.nz;
         g.idp = r.v3 >= 0 ? reinterpret_cast<const uint2*>(b + r.o_idp) : nullptr;
+        g.zr_tab = r.v3 >= 0 && !r.st.zr.empty() ? reinterpret_cast<const int2*>(b + r.o_zr) : nullptr;
+        for (int v = 0; v < 8; ++v) g.zr_off[v] = r.st.zr_off[v];
         return g;
     }
 };
@@ -336,8 +339,8 @@ hipError_t start_wave(cf_server* S, Req& r, T* f) {
     const size_t fbytes = (size_t)r.st.resident * r.st.ncomp * p.ncell * sizeof(T);
     hipError_t e;
     if ((e = hipMemsetAsync(f, 0, fbytes, s)) != hipSuccess) return e;
-    if (r.fused) {
-        // the fused kernel never writes the cells it skips: zero in both arrays
+    if (r.fused || r.v3 >= 0) {
+        // the fused kernels never write the cells they skip: zero in both arrays
         char* other = b + (reinterpret_cast<char*>(f) == b + r.o_fa ? r.o_fb : r.o_fa);
         if ((e = hipMemsetAsync(other, 0, fbytes, s)) != hipSuccess) return e;
     }
@@ -388,6 +391,7 @@ hipError_t admit(cf_server* S, Req& r) {
     UP(r.o_uw, st.uw.data(), st.uw.size() * 8);
     UP(r.o_basis, st.basis.data(), st.basis.size() * 8);
     UP(r.o_idp, r.idp.data(), r.idp.size() * 4);
+    if (r.v3 >= 0) UP(r.o_zr, st.zr.data(), st.zr.size() * 4);
 #undef UP
     if ((e = hipMemsetAsync(b + r.o_acc, 0, (size_t)r.C * 2 * 8, s)) != hipSuccess) return e;
     r.wave = 0;

@@ -82,6 +82,8 @@ struct Staged {
     int v3d = -1;                          // its variant when fixed by the options (-1: autotune)
     cf::ShadowBox sbox{};                  // surface box of a 3D solve (two-step fused launches)
     int64_t aux_block = 0;                 // polarization values per resident channel (dispersive media)
+    std::vector<int32_t> zr;               // fused 3D: per variant and band, the planes [lo, hi) it can change
+    int zr_off[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // first band of variant v in zr (pairs)
 };
 
 struct StencilTiming {
