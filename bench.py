@@ -112,6 +112,32 @@ def measured_traffic_3d(variant):
     return rec["hbm_bytes_per_launch"], rec.get("command", "")
 
 
+SERVING_MIXED_RECORD = os.path.join(ROOT, "profiles", "serving_mixed_stream_first20.json")
+
+
+def serving_source_hash():
+    """sha256 over the scheduler and the kernels it launches."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("server.cpp", "kernels2d.hip", "kernels3d.hip", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_0906_5170_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_serving_mixed():
+    """The committed record of the mixed 2D/3D stream served at its drawn
+    sizes (bench.py --serve-mixed 20: about 13 minutes of GPU time, too long
+    for the default run), with whether the scheduler and kernels are still
+    the ones it was measured on."""
+    if not os.path.exists(SERVING_MIXED_RECORD):
+        return None
+    rec = json.load(open(SERVING_MIXED_RECORD))
+    rec["source_current"] = rec.get("source_sha256") == serving_source_hash()
+    rec["measured_in_this_run"] = False
+    return rec
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -200,14 +226,20 @@ def bench_3d(cf, torch, n_chan=64, n_steps=200, variant=0):
         sweep.append({"variant": v, "fused": rv["fused"], "stencil_cell_updates_per_s": cu_s})
     step_rate = r["stencil_cell_updates"] / (r["stencil_ms_avg"] * 1e-3) if r["stencil_ms_avg"] else None
     traffic, traffic_note = measured_traffic_3d(r["tile_variant"])
-    log(f"[bench] 3d: {rate:.3e} cell-updates/s over the solve, stencil {step_rate:.3e}")
+    # cells the fused steps advance per launch (planes below the conductor skipped)
+    adv = r["stencil_cell_updates"] * r["advanced_cell_updates"] / r["cell_updates"]
+    log(f"[bench] 3d: {rate:.3e} cell-updates/s over the solve, stencil {step_rate:.3e}, "
+        f"advanced {adv / r['stencil_cell_updates']:.3f} of the cells")
     return {"workload": f"sphere over indented plate 192^3 res 48, z CPML 16, {n_chan} of {C} channels "
                         f"x {n_steps} steps, FP32 fields", "value": rate, "unit": "cell-updates/s",
             "stencil_cell_updates_per_s": step_rate,
             "stencil_frac_of_hbm_ceiling": step_rate / ceiling if step_rate else None,
             "hbm_ceiling_cell_updates_per_s": ceiling, "fused": r["fused"], "variant": r["tile_variant"],
             "avg_launch_ms": r["stencil_ms_avg"], "cell_updates_per_launch": r["stencil_cell_updates"],
+            "advanced_cell_updates_per_launch": adv,
+            "advanced_cell_updates_per_s": r["advanced_cell_updates"] / dt,
             "traffic_bytes_per_launch": traffic, "traffic_note": traffic_note,
+            "traffic_bytes_per_advanced_cell_update": traffic / adv if traffic else None,
             "real_hbm_GBps": traffic / (r["stencil_ms_avg"] * 1e-3) / 1e9 if traffic and r["stencil_ms_avg"] else None,
             "variant_sweep": sweep,
             "projected_full_solve_s": 1280 * wl.n_cells * wl.n_steps / rate}
@@ -228,7 +260,7 @@ def bench_3d_full(cf, torch, waves=3, precision="fp32", run=None):
     parts = np.array_split(np.arange(C), waves)
     ws = torch.empty(p.info(**dict(o, max_resident=len(parts[0])))["workspace_bytes"], dtype=torch.uint8,
                      device="cuda")
-    force, cu, dev_ms = 0.0, 0.0, 0.0
+    force, cu, adv, dev_ms = 0.0, 0.0, 0.0, 0.0
     t0 = time.perf_counter()
     run = list(range(waves)) if run is None else list(run)
     for k, sub in enumerate(parts):
@@ -237,6 +269,7 @@ def bench_3d_full(cf, torch, waves=3, precision="fp32", run=None):
         r = p.solve(workspace=ws, channel_subset=sub.tolist(), max_resident=len(sub), **o)
         force += r["force"]
         cu += r["cell_updates"]
+        adv += r["advanced_cell_updates"]
         dev_ms += r["device_ms"]
         log(f"[bench] c4 full: wave {k + 1}/{waves} ({len(sub)} channels) {r['device_ms'] / 1e3:.1f} s, "
             f"variant {r['tile_variant']}, partial force {r['force']:+.6e}")
@@ -245,6 +278,7 @@ def bench_3d_full(cf, torch, waves=3, precision="fp32", run=None):
                         f"steps, {precision.upper()} fields, {waves} channel waves", "waves_run": run,
             "force": force, "wall_s": wall,
             "device_s": dev_ms / 1e3, "cell_updates": cu, "value": cu / (dev_ms * 1e-3),
+            "advanced_cell_updates": adv, "advanced_cell_updates_per_s": adv / (dev_ms * 1e-3),
             "unit": "cell-updates/s", "workspace_bytes": ws.numel()}
 
 
@@ -368,35 +402,57 @@ def bench_kz(cf, torch):
     return out
 
 
-def _serve(cf, srv_budget, reqs, probs, opts_list, lam_times=True):
-    """Submit requests at their arrival times (or all at once) and wait for
-    all; returns per-request (kind, submit, admit, done, cell-updates)."""
-    rows = []
+def _serve(cf, srv_budget, reqs, probs, opts_list, lam_times=True, keep=None):
+    """Submit requests at their arrival times (or all at once) and collect
+    them as they finish; returns per-request rows (kind, submit, admit,
+    done, cell-updates) in stream order, and the results of the requests
+    whose stream indices are in keep.  Latencies come from the server's own
+    clock (cf_server_times), so the polling interval does not enter them."""
+    rows = [None] * len(reqs)
+    kept = {}
     with cf.Server(srv_budget) as srv:
         t0 = time.perf_counter()
-        tickets = []
-        o_of = {}
-        for q, p, o in zip(reqs, probs, opts_list):
-            if lam_times:
-                delay = q.t_arrive - (time.perf_counter() - t0)
-                if delay > 0:
-                    time.sleep(delay)
-            try:
-                tickets.append((q, srv.submit(p, **o)))
-                o_of[tickets[-1][1]] = o["n_steps"]
-            except cf.CfError as e:
-                tickets.append((q, None))
-                log(f"[bench] serve: request {q.index} rejected: {e}")
-        for q, t in tickets:
-            if t is None:
-                rows.append(dict(kind=q.kind, rejected=True))
-                continue
-            r = srv.wait(t, timeout=-1)
-            ts, ta, td = srv.times(t)
-            rows.append(dict(kind=q.kind, submit=ts, admit=ta, done=td, cu=r["cell_updates"],
-                             fused=r["fused"], rejected=False, steps=r["n_steps_run"], t_full=o_of[t]))
-            srv.release(t)
-    return rows
+        pending = {}
+        nxt = 0
+        last = t0
+        while nxt < len(reqs) or pending:
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and (not lam_times or reqs[nxt].t_arrive <= now):
+                q, p, o = reqs[nxt], probs[nxt], opts_list[nxt]
+                try:
+                    pending[srv.submit(p, **o)] = nxt
+                except cf.CfError as e:
+                    rows[nxt] = dict(kind=q.kind, rejected=True, index=q.index)
+                    log(f"[bench] serve: request {q.index} rejected: {e}")
+                nxt += 1
+            for t in list(pending):
+                state, r = srv.poll(t)
+                if state in ("failed", "cancelled"):
+                    raise RuntimeError(f"served request {reqs[pending[t]].index} {state}")
+                if state != "done":
+                    continue
+                k = pending.pop(t)
+                q = reqs[k]
+                ts, ta, td = srv.times(t)
+                rows[k] = dict(kind=q.kind, index=q.index, submit=ts, admit=ta, done=td, cu=r["cell_updates"],
+                               fused=r["fused"], rejected=False, steps=r["n_steps_run"],
+                               t_full=opts_list[k]["n_steps"])
+                if keep is not None and q.index in keep:
+                    kept[q.index] = r
+                srv.release(t)
+                last = time.perf_counter()
+                if len(reqs) <= 40 or q.kind != "2d":
+                    log(f"[bench] serve: request {q.index} ({q.kind}) done, latency {td - ts:.2f} s")
+            if time.perf_counter() - last > 60:
+                st = srv.stats()
+                log(f"[bench] serve: {st['completed']} done, {st['running']} resident, {st['queued']} queued, "
+                    f"scheduler clock {st['clock_steps']} steps")
+                last = time.perf_counter()
+            wait = 0.2
+            if lam_times and nxt < len(reqs):
+                wait = min(wait, max(reqs[nxt].t_arrive - (time.perf_counter() - t0), 0.0))
+            time.sleep(wait)
+    return (rows, kept) if keep is not None else rows
 
 
 def _summary(rows):
@@ -410,10 +466,15 @@ def _summary(rows):
            "cell_updates_per_s": sum(r["cu"] for r in ok) / span,
            "fused_requests": sum(1 for r in ok if r["fused"]),
            "steps_run_fraction": sum(r["steps"] for r in ok) / sum(r["t_full"] for r in ok)}
-    for kind in sorted({r["kind"] for r in ok}):
+    for kind in sorted({r["kind"] for r in rows}):
         lk = np.array([r["done"] - r["submit"] for r in ok if r["kind"] == kind])
-        out[f"{kind}_p50_s"] = float(np.percentile(lk, 50))
-        out[f"{kind}_p99_s"] = float(np.percentile(lk, 99))
+        if len(lk):
+            out[f"{kind}_p50_s"] = float(np.percentile(lk, 50))
+            out[f"{kind}_p99_s"] = float(np.percentile(lk, 99))
+        if len({r["kind"] for r in rows}) > 1:
+            out[f"{kind}_n"] = len(lk)
+            out[f"{kind}_rejected"] = sum(1 for r in rows if r["rejected"] and r["kind"] == kind)
+            out[f"{kind}_cell_updates"] = float(sum(r["cu"] for r in ok if r["kind"] == kind))
     return out
 
 
@@ -485,21 +546,86 @@ def bench_serving(cf, torch, args, rate_3d):
                                  "note": "service times from the measured saturated piston rate and the "
                                          "3D sample rate; the stream is far beyond one GPU's capacity, "
                                          "so its backlog grows without bound"}
-    if args.serve_mixed:
-        mreq, mp, mo = [], [], []
-        for q in mixed_stream(args.serve_mixed, lam=4.0, seed=0):
-            w = q.workload()
-            try:
-                p_ = cf.Problem.from_workload(w)
-            except cf.CfError:      # S does not fit (3D: gap below the indentation limit)
-                continue
-            mreq.append(q)
-            mp.append(p_)
-            mo.append(dict(sigma=w.sigma, courant=w.courant, n_steps=w.n_steps, pol=w.pol,
-                           kernel=w.kernel, precision="fp32"))
-        log(f"[bench] serve: mixed stream of {len(mreq)} requests at 4 req/s ...")
-        res["mixed_literal"] = _summary(_serve(cf, budget, mreq, mp, mo))
     log(f"[bench] serve: p50 {matched['p50_s']:.3f} s p99 {matched['p99_s']:.3f} s")
+    mixed = measured_serving_mixed()
+    if mixed is not None:
+        res["mixed"] = mixed
+    return res
+
+
+def bench_serving_mixed(cf, torch, args):
+    """The first args.serve_mixed requests of the seeded mixed stream (seed
+    0), both classes at their drawn sizes: 2D TE+TM pistons (FP32, T = 250
+    res) and 3D sphere-above-indented-plate cells (n^3, n in {96, 128, 160,
+    192}, T = 125 n / 4, 1280 channels).  3D requests whose gap leaves no room
+    for the stress surface inside the indentation are rejected by the
+    server (CF_E_SURFACE) and counted.  Passes: 'sat' submits everything at
+    once (capacity = requests / span), 'check' solves the smallest served 3D
+    request once more as a one-shot cf_solve with the served kernel variant
+    and compares the per-channel integrals bit for bit, 'matched' replays the
+    requests as a Poisson stream at 0.7 of the capacity (or at
+    --serve-mixed-lam requests per second)."""
+    from casimir_inputs.streams import mixed_stream, rescale_arrivals
+    passes = args.serve_mixed_passes.split(",")
+    budget = int(min(torch.cuda.get_device_properties(0).total_memory * 0.8, 224 * 2**30))
+    reqs, probs, opts, built_rejects = [], [], [], []
+    for q in mixed_stream(args.serve_mixed, lam=4.0, seed=0):
+        w = q.workload()
+        try:
+            p_ = cf.Problem.from_workload(w)
+        except cf.CfError as e:
+            built_rejects.append({"index": q.index, "kind": q.kind, "error": str(e)})
+            continue
+        reqs.append(q)
+        probs.append(p_)
+        opts.append(dict(sigma=w.sigma, courant=w.courant, n_steps=w.n_steps, pol=w.pol,
+                         kernel=w.kernel, precision="fp32"))
+    n3 = sum(1 for q in reqs if q.kind == "3d")
+    log(f"[bench] serve mixed: {len(reqs)} requests ({n3} 3D), budget {budget / 2**30:.0f} GiB")
+    res = {"stream": f"first {args.serve_mixed} requests of the seeded mixed stream (seed 0): 2D TE+TM pistons "
+                     "(h ~ U[0.1,2], res ~ U{20..60}, T = 250 res, 40 harmonics/face) and 3D sphere-above-"
+                     "indented-plate cells (n^3, n ~ U{96,128,160,192}, gap ~ U[0.2,1.5], T = 125 n/4, "
+                     "8x8 harmonics/face, 1280 channels), FP32 fields",
+           "requests": [{"index": q.index, "kind": q.kind, **q.params} for q in reqs],
+           "rejected_at_build": built_rejects, "budget_bytes": budget,
+           "source_sha256": serving_source_hash()}
+    cap = None
+    if "sat" in passes or "check" in passes:
+        log("[bench] serve mixed: saturated pass ...")
+        rows, kept = _serve(cf, budget, reqs, probs, opts, lam_times=False,
+                            keep={q.index for q in reqs if q.kind == "3d"})
+        rej = [dict(kind=r["kind"], rejected=True) for r in built_rejects]
+        sat = _summary(rows + rej)
+        cap = sat["n"] / sat["span_s"]
+        res["saturated"] = sat
+        res["capacity_req_per_s"] = cap
+        log(f"[bench] serve mixed: capacity {cap:.4f} req/s, {sat['cell_updates_per_s']:.3e} cell-updates/s, "
+            f"3D p50 {sat.get('3d_p50_s', float('nan')):.1f} s, 2D p50 {sat.get('2d_p50_s', float('nan')):.2f} s")
+        served3 = [q for q in reqs if q.index in kept]
+        if "check" in passes and served3:
+            small = min(served3, key=lambda q: q.params["n"])
+            k = next(i for i, q in enumerate(reqs) if q.index == small.index)
+            served = kept[small.index]
+            one = probs[k].solve(**dict(opts[k], tile_variant=served["tile_variant"]))
+            same = bool(np.array_equal(served["per_channel"], one["per_channel"])
+                        and served["force"] == one["force"])
+            res["bitwise_check"] = {"request": small.index, "n": small.params["n"],
+                                    "tile_variant": served["tile_variant"], "fused": served["fused"],
+                                    "force": served["force"], "one_shot_force": one["force"],
+                                    "bitwise_equal": same}
+            log(f"[bench] serve mixed: request {small.index} served == one-shot bit for bit: {same}")
+            if not same:
+                raise RuntimeError("served 3D request differs from its one-shot solve")
+    if "matched" in passes:
+        lam = args.serve_mixed_lam or (0.7 * cap if cap else None)
+        if not lam:
+            raise SystemExit("the matched pass needs the saturated pass or --serve-mixed-lam")
+        log(f"[bench] serve mixed: Poisson pass at {lam:.4f} req/s ...")
+        rej = [dict(kind=r["kind"], rejected=True) for r in built_rejects]
+        m = _summary(_serve(cf, budget, rescale_arrivals(reqs, lam), probs, opts) + rej)
+        res["load_matched"] = dict(m, lam_req_per_s=lam,
+                                   load=(lam / cap) if cap else None)
+        log(f"[bench] serve mixed: matched p50 {m['p50_s']:.1f} s p99 {m['p99_s']:.1f} s")
     return res
 
 
@@ -620,8 +746,12 @@ def main():
                     help="with --cyl-only: the register-resident FP32 solve only (no split / FP64 / oracle)")
     ap.add_argument("--serve-n", type=int, default=24, help="requests in the served piston stream")
     ap.add_argument("--serve-mixed", type=int, default=0,
-                    help="also serve this many requests of the mixed 2D/3D stream (long: 3D requests "
-                         "take tens of seconds each)")
+                    help="only serve this many requests of the mixed 2D/3D stream at their drawn sizes "
+                         "(long: 3D requests take up to minutes each) and print the record")
+    ap.add_argument("--serve-mixed-passes", default="sat,check,matched",
+                    help="passes of --serve-mixed: sat, check, matched")
+    ap.add_argument("--serve-mixed-lam", type=float, default=0.0,
+                    help="arrival rate of the matched pass (0: 0.7 of the saturated capacity)")
     ap.add_argument("--n-steps", type=int, default=None, help="override T (testing only)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB (a plain copy kernel of known size, "
@@ -633,7 +763,7 @@ def main():
         args.no_precision = True
         if args.with_3d:
             args.no_3d = False
-    if args.cyl_only:
+    if args.cyl_only or args.serve_mixed:
         args.no_cpu = True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding the channels over "
@@ -673,6 +803,9 @@ def main():
                     min(nw, args.c4_full_from + args.c4_full_count))
         print(json.dumps(bench_3d_full(cf, torch, waves=nw, precision=args.c4_full_precision, run=run)),
               flush=True)
+        return
+    if args.serve_mixed:
+        print(json.dumps(bench_serving_mixed(cf, torch, args)), flush=True)
         return
     if args.cyl_only:
         rec = bench_cyl(cf, torch, quick=args.cyl_quick)

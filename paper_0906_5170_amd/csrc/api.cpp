@@ -975,11 +975,14 @@ cf_status run_reduced(const cf::Problem& p, const cf_opts& o, const Staged& st, 
     }
     timing->steps_run = o.n_steps;
     acc_out.assign(C * 2, 0.0);
-    STEP_OK(hipMemcpy(acc_out.data(), ws + L.acc, C * 2 * 8, hipMemcpyDeviceToHost));
+    // copies on the solve's own stream: a non-blocking caller stream is not
+    // ordered with the null stream
+    STEP_OK(hipMemcpyAsync(acc_out.data(), ws + L.acc, C * 2 * 8, hipMemcpyDeviceToHost, s));
     if (keep_gamma) {
         gamma_out.assign((size_t)t_max * C, 0.0);
-        STEP_OK(hipMemcpy(gamma_out.data(), ws + L.gamma, gamma_out.size() * 8, hipMemcpyDeviceToHost));
+        STEP_OK(hipMemcpyAsync(gamma_out.data(), ws + L.gamma, gamma_out.size() * 8, hipMemcpyDeviceToHost, s));
     }
+    STEP_OK(hipStreamSynchronize(s));
 done:
 #undef STEP_OK
     if (err != hipSuccess) (void)hipStreamSynchronize(s);
@@ -1432,11 +1435,12 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     }
     timing->steps_run = steps_run;
     acc_out.assign(C * 2, 0.0);
-    STEP_OK(hipMemcpy(acc_out.data(), ws + L.acc, C * 2 * 8, hipMemcpyDeviceToHost));
+    STEP_OK(hipMemcpyAsync(acc_out.data(), ws + L.acc, C * 2 * 8, hipMemcpyDeviceToHost, s));
     if (keep_gamma) {
         gamma_out.assign((size_t)o.n_steps * C, 0.0);
-        STEP_OK(hipMemcpy(gamma_out.data(), ws + L.gamma, gamma_out.size() * 8, hipMemcpyDeviceToHost));
+        STEP_OK(hipMemcpyAsync(gamma_out.data(), ws + L.gamma, gamma_out.size() * 8, hipMemcpyDeviceToHost, s));
     }
+    STEP_OK(hipStreamSynchronize(s));
 done:
 #undef STEP_OK
     // host staging vectors die with this frame: drain the stream first
@@ -1513,6 +1517,21 @@ bool fill_result(const cf::Problem& p, const std::vector<cf::Channel>& chans, co
         double a = 0;
         for (size_t c = 0; c < C; ++c) a += pl.live_cells[chans[c].pol == CF_POL_TE ? 1 : 0];
         out->advanced_cell_updates = a * (double)steps;
+    }
+    if (tim.variant >= 0 && tim.variant < 8 && p.grid.ndim == 3 && sg.f3d && !sg.zr.empty()) {
+        // the fused 3D steps advance each band's planes [z0, z1) only
+        int W, B, ks;
+        cf::f3d_shape(tim.variant, &W, &B, &ks);
+        const int band = W * B - 2 * ks;
+        if (band > 0) {
+            const int nb = (p.ny + band - 1) / band;
+            double cells = 0;
+            for (int b = 0; b < nb; ++b) {
+                const size_t k = 2 * ((size_t)sg.zr_off[tim.variant] + b);
+                cells += (double)std::min(band, p.ny - b * band) * (sg.zr[k + 1] - sg.zr[k]) * p.nx;
+            }
+            out->advanced_cell_updates = cells * (double)C * (double)steps;
+        }
     }
     return finite;
 }
@@ -1880,7 +1899,8 @@ cf_status run_batch(const BatchPlan& B, const BatchLayout& L, const cf_opts& o, 
         *device_ms = ms;
     }
     acc_out.assign((size_t)B.C * 2, 0.0);
-    BSTEP(hipMemcpy(acc_out.data(), dacc, (size_t)B.C * 2 * 8, hipMemcpyDeviceToHost));
+    BSTEP(hipMemcpyAsync(acc_out.data(), dacc, (size_t)B.C * 2 * 8, hipMemcpyDeviceToHost, s));
+    BSTEP(hipStreamSynchronize(s));
 bdone:
 #undef BSTEP
     if (err != hipSuccess) (void)hipStreamSynchronize(s);
@@ -2086,16 +2106,23 @@ static cf_status solve_concurrently(cf_problem* const* probs, const std::vector<
         return fail(CF_E_DEVICE, std::string("device step failed: ") + hipGetErrorString(e));
     }
     std::atomic<int> next{0};
+    std::atomic<int> solved{0};
     std::vector<cf_status> status(nw, CF_OK);
     std::vector<std::string> msg(nw);
+    std::vector<std::string> setup_msg(nw);
     auto worker = [&](int k) {
+        // a worker whose stream cannot be set up takes no problems; the
+        // others take them all
         hipStream_t s = nullptr;
         hipError_t he = hipSetDevice(dev);
-        if (he == hipSuccess) he = hipStreamCreate(&s);                 // default priority
+        // non-blocking (default priority): workers are not serialised
+        // through the null stream
+        if (he == hipSuccess) he = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
         if (he == hipSuccess) he = hipStreamWaitEvent(s, ready, 0);
         if (he != hipSuccess) {
-            status[k] = CF_E_DEVICE;
-            msg[k] = std::string("device step failed: ") + hipGetErrorString(he);
+            setup_msg[k] = std::string("device step failed: ") + hipGetErrorString(he);
+            if (s) (void)hipStreamDestroy(s);
+            return;
         }
         for (int j; status[k] == CF_OK && (j = next.fetch_add(1)) < (int)idx.size();) {
             cf_opts oi = oo;
@@ -2104,6 +2131,7 @@ static cf_status solve_concurrently(cf_problem* const* probs, const std::vector<
             try {
                 status[k] = cf_solve(probs[i], &oi, ws + (size_t)k * slot, slot, &outs[i]);
                 if (status[k] != CF_OK) msg[k] = cf_last_error();
+                else solved.fetch_add(1);
             } catch (const std::bad_alloc&) {   // nothing may escape a worker thread
                 status[k] = CF_E_BUDGET;
                 msg[k] = "host allocation failed";
@@ -2112,7 +2140,7 @@ static cf_status solve_concurrently(cf_problem* const* probs, const std::vector<
                 msg[k] = ex.what();
             }
         }
-        if (s) (void)hipStreamDestroy(s);
+        (void)hipStreamDestroy(s);
     };
     std::vector<std::thread> pool;
     for (int k = 1; k < nw; ++k) {
@@ -2127,6 +2155,11 @@ static cf_status solve_concurrently(cf_problem* const* probs, const std::vector<
     (void)hipEventDestroy(ready);
     for (int k = 0; k < nw; ++k)
         if (status[k] != CF_OK) return fail(status[k], msg[k]);
+    if (solved.load() < (int)idx.size()) {
+        for (int k = 0; k < nw; ++k)
+            if (!setup_msg[k].empty()) return fail(CF_E_DEVICE, setup_msg[k]);
+        return fail(CF_E_DEVICE, "concurrent solve left problems unsolved");
+    }
     return CF_OK;
 }
 

@@ -4,14 +4,18 @@
 // arrival order; at every tick boundary each queued request whose memory fits
 // is admitted (later requests may pass an earlier one that does not fit yet):
 // its tables are uploaded, its fields zeroed and kicked, and it joins the
-// resident set with its own time origin on the scheduler clock.  A tick
-// advances every resident request by K time steps:
+// resident set.  A tick advances the resident requests:
 //   - all 2D requests whose stress surface fits a fused tile share one fused
-//     launch per polarization (each instance reads its own buffers, tables
-//     and K(t) and starts at its own clock step);
-//   - other requests (3D, or surfaces wider than a tile) take the split
-//     half-step kernels, one request after another, in channel waves that
-//     bound their memory.
+//     launch per polarization and advance K steps per tick (each instance
+//     reads its own buffers, tables and K(t) and starts at its own step of
+//     the scheduler clock);
+//   - other requests (3D on the fused z-streaming step, or split kernels
+//     for surfaces wider than a tile) run one after another, in channel
+//     waves that bound their memory, each with its own step count.  Each
+//     gets an equal share of the tick's device time, the share of one
+//     fused request, as steps from its measured time per step.  A cheap 2D
+//     request is thus not held to the pace of a 3D cell many times its
+//     size (processor sharing in time rather than in steps).
 // When a request has run all its steps its accumulators are copied back,
 // its memory returns to the arena and waiting requests can enter.  Every
 // request's arithmetic is independent of its co-residents, so a result is
@@ -74,7 +78,13 @@ struct Req {
     std::vector<uint8_t> lut;     // field-precision bytes
     std::vector<double> ktab, pml;
     int wave = 0;
-    long long start = 0;          // clock step of the current wave's step 0
+    long long start = 0;          // fused: clock step of the current wave's step 0
+    // non-fused requests keep their own step count and advance by a share of
+    // device time per tick (see plan_steps)
+    long long done = 0;           // steps of the current wave run
+    int tick_steps = 0;           // steps in the coming tick
+    double credit = 0;            // step credit carried between ticks
+    double sps = 0;               // measured device seconds per step
     int state = ST_QUEUED;
     cf_status status = CF_OK;
     std::string err;
@@ -138,6 +148,11 @@ struct cf_server {
         int n;
     };
     std::vector<Launch> launches;     // fused launches of one tick
+    // tick timing: events around the fused launches and each non-fused
+    // request's steps, and the fused launches' device time last tick
+    std::vector<hipEvent_t> ev;
+    size_t n_marks = 0;
+    double group_s = 0;
     std::deque<std::vector<cf::ChanDev>> keep_ch;
     std::deque<std::vector<cf::InstDev>> keep_inst;
     std::deque<std::vector<cf::WorkItem>> keep_work;
@@ -396,6 +411,9 @@ hipError_t admit(cf_server* S, Req& r) {
     if ((e = hipMemsetAsync(b + r.o_acc, 0, (size_t)r.C * 2 * 8, s)) != hipSuccess) return e;
     r.wave = 0;
     r.start = S->clock;
+    r.done = 0;
+    r.credit = 0;
+    r.sps = 0;
     // a fused request is kicked into the buffer the next fused launch reads
     T* f = reinterpret_cast<T*>(b + (r.fused && S->parity ? r.o_fb : r.o_fa));
     return start_wave<T>(S, r, f);
@@ -492,8 +510,19 @@ template <typename T>
 hipError_t tick(cf_server* S) {
     hipStream_t s = S->stream;
     hipError_t e;
+    S->n_marks = 0;
+    auto mark = [&]() -> hipError_t {
+        if (S->n_marks == S->ev.size()) {
+            hipEvent_t x;
+            const hipError_t c = hipEventCreate(&x);
+            if (c != hipSuccess) return c;
+            S->ev.push_back(x);
+        }
+        return hipEventRecord(S->ev[S->n_marks++], s);
+    };
     bool any_fused = false;
     for (auto& rp : S->active) any_fused = any_fused || rp->fused;
+    if ((e = mark()) != hipSuccess) return e;
     if (any_fused) {
         if (S->membership_changed && (e = rebuild_group<T>(S)) != hipSuccess) return e;
         const cf::ChanDev* gch = reinterpret_cast<const cf::ChanDev*>(S->group + S->g_ch);
@@ -504,6 +533,7 @@ hipError_t tick(cf_server* S) {
                                         S->parity, s)) != hipSuccess)
                 return e;
     }
+    if ((e = mark()) != hipSuccess) return e;
     for (auto& rp : S->active) {
         Req& r = *rp;
         if (r.fused) continue;
@@ -519,9 +549,9 @@ hipError_t tick(cf_server* S) {
         const double* kt = reinterpret_cast<const double*>(b + r.o_ktab);
         double* acc = reinterpret_cast<double*>(b + r.o_acc);
         const double dt = r.opts.courant / p.grid.res, dA = std::pow(1.0 / p.grid.res, p.grid.ndim - 1);
-        for (int k = 0; k < S->kh; ++k) {
-            const long long m = S->clock + k - r.start;
-            if (m < 0 || m >= r.opts.n_steps) continue;
+        for (int k = 0; k < r.tick_steps; ++k) {
+            const long long m = r.done + k;
+            if (m >= r.opts.n_steps) break;
             T* cur = f;   // field array the surface is read from after this step
             if (p.grid.ndim == 3 && r.v3 >= 0) {
                 const cf::Grid3D g = Dev<T>::grid3(b, r);
@@ -532,7 +562,7 @@ hipError_t tick(cf_server* S) {
                 T* src = r.par ? fb : fa;
                 T* dst = r.par ? fa : fb;
                 // steps m and m + 1 in one two-step launch when both fall in this tick
-                const bool two = cf::f3d_steps(r.v3) == 2 && k + 1 < S->kh && m + 1 < r.opts.n_steps;
+                const bool two = cf::f3d_steps(r.v3) == 2 && k + 1 < r.tick_steps && m + 1 < r.opts.n_steps;
                 T* sh = reinterpret_cast<T*>(b + r.o_shadow);
                 if ((e = cf::launch_f3d<T>(two ? r.v3 : r.v3s, dch, dl + w.d3_off, w.n_3d, g, lut, src, dst,
                                            r.par ? pb : pa, r.par ? pa : pb, sh, r.st.sbox, s)) != hipSuccess)
@@ -570,8 +600,71 @@ hipError_t tick(cf_server* S) {
                                            s)) != hipSuccess)
                 return e;
         }
+        if ((e = mark()) != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// Steps of each non-fused request in the coming tick.  Every resident
+// request is entitled to the same device time per tick: the fused launches
+// advance all fused requests by K steps in group_s seconds, so the share is
+// group_s / (fused requests); with no fused request resident it is K steps
+// of the cheapest non-fused request.  A request earns share / (its seconds
+// per step) of step credit per tick.  Until its time per step is measured a
+// request runs K steps.  Convergence checks fall on tick boundaries, and
+// two-step 3D requests run their steps in pairs (a single step only at the
+// end or before a check).
+void plan_steps(cf_server* S) {
+    int nf = 0;
+    double min_sps = 0;
+    for (auto& rp : S->active) {
+        if (rp->fused) ++nf;
+        else if (rp->sps > 0 && (min_sps == 0 || rp->sps < min_sps)) min_sps = rp->sps;
+    }
+    const double share = nf > 0 ? (S->group_s > 0 ? S->group_s / nf : 0.0) : S->kh * min_sps;
+    for (auto& rp : S->active) {
+        Req& r = *rp;
+        if (r.fused) continue;
+        const long long left = r.opts.n_steps - r.done;
+        long long n = S->kh;
+        if (r.sps > 0 && share > 0) {
+            r.credit += share / r.sps;
+            n = (long long)r.credit;
+        }
+        n = std::min(n, left);
+        if (r.conv.on) n = std::min<long long>(n, r.conv.next - r.done);
+        const bool pairs = r.v3 >= 0 && cf::f3d_steps(r.v3) == 2;
+        const bool last = n == left || (r.conv.on && n == r.conv.next - r.done);
+        if (pairs && n % 2 == 1 && !last) --n;
+        n = std::max<long long>(n, 0);
+        r.tick_steps = (int)n;
+        if (r.sps > 0 && share > 0) r.credit = std::min(std::max(r.credit - n, 0.0), 2.0);
+    }
+}
+
+// Device times of the tick just drained: the fused launches and each
+// non-fused request's steps (events recorded by tick in this order).
+void read_times(cf_server* S) {
+    if (S->n_marks < 2) return;
+    auto span = [&](size_t a) {
+        float ms = 0;
+        return hipEventElapsedTime(&ms, S->ev[a], S->ev[a + 1]) == hipSuccess ? ms * 1e-3 : -1.0;
+    };
+    bool any_fused = false;
+    for (auto& rp : S->active) any_fused = any_fused || rp->fused;
+    const double g = span(0);
+    if (any_fused && g > 0) S->group_s = S->group_s > 0 ? 0.5 * (S->group_s + g) : g;
+    size_t k = 1;
+    for (auto& rp : S->active) {
+        Req& r = *rp;
+        if (r.fused) continue;
+        if (k + 1 >= S->n_marks) break;
+        const double t = span(k++);
+        if (r.tick_steps > 0 && t > 0) {
+            const double per = t / r.tick_steps;
+            r.sps = r.sps > 0 ? 0.5 * (r.sps + per) : per;
+        }
+    }
 }
 
 template <typename T>
@@ -644,6 +737,7 @@ void loop(cf_server* S) {
             continue;
         }
         // ---- one tick ----
+        plan_steps(S);
         const double t0 = now_s();
         lk.unlock();
         hipError_t e = tick<T>(S);
@@ -665,8 +759,11 @@ void loop(cf_server* S) {
             S->cv.notify_all();
             continue;
         }
+        read_times(S);
         S->clock += S->kh;
         S->parity ^= 1;
+        for (auto& rp : S->active)
+            if (!rp->fused) rp->done += rp->tick_steps;
         // the stream has drained: staged group tables are no longer read
         S->keep_ch.clear();
         S->keep_inst.clear();
@@ -674,8 +771,9 @@ void loop(cf_server* S) {
         // ---- retire finished requests / start next channel waves ----
         for (auto it = S->active.begin(); it != S->active.end();) {
             Req& r = **it;
-            bool wave_done = S->clock - r.start >= r.opts.n_steps;
-            const long long done = std::min<long long>(S->clock - r.start, r.opts.n_steps);
+            const long long ran = r.fused ? S->clock - r.start : r.done;
+            bool wave_done = ran >= r.opts.n_steps;
+            const long long done = std::min<long long>(ran, r.opts.n_steps);
             if (!wave_done && r.conv.on && done >= r.conv.next) {
                 // time-convergence check on the accumulators (the stream has drained)
                 while (r.conv.next <= done) r.conv.next += r.conv.every;
@@ -694,6 +792,8 @@ void loop(cf_server* S) {
             if (!r.cancel && !r.fused && r.wave + 1 < (int)r.st.waves.size()) {
                 ++r.wave;
                 r.start = S->clock;
+                r.done = 0;
+                r.credit = 0;
                 hipError_t e2 = start_wave<T>(S, r, reinterpret_cast<T*>(S->arena_base + r.off + r.o_fa));
                 if (e2 == hipSuccess) {
                     ++it;
@@ -918,6 +1018,7 @@ static cf_status cf_server_destroy_impl(cf_server* S) {
     S->cv.notify_all();
     if (S->worker.joinable()) S->worker.join();
     (void)hipStreamSynchronize(S->stream);
+    for (hipEvent_t x : S->ev) (void)hipEventDestroy(x);
     if (S->own_stream) (void)hipStreamDestroy(S->stream);
     if (S->own_arena) (void)hipFree(S->group);
     delete S;

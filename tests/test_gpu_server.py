@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from casimir_inputs.configs import piston2d
+from casimir_inputs.configs import piston2d, sphere_plate3d
 from casimir_inputs.geometry import Box, Sphere, Workload, rasterize
 
 pytestmark = pytest.mark.gpu
@@ -219,3 +219,30 @@ def test_solve_reports_nonfinite(cf):
     with pytest.raises(cf.CfError) as e:
         p.solve(**opts_of(w, inject_nan=True))
     assert e.value.code == 5
+
+
+def test_server_time_share_lets_small_requests_pass(cf):
+    """A 3D cell (1280 channels x 48^3) and a small 2D piston, submitted
+    together with the same step count: the 3D request's steps are paced by
+    device time, not by the scheduler's step clock, so the piston (a
+    thousandth of the cells per step) finishes long before the 3D cell.
+    Both results equal their one-shot solves bit for bit."""
+    announce("server: time-shared steps, a small 2D piston beside a 48^3 cell")
+    w3 = sphere_plate3d(48, 1.0, n_steps=400)
+    w2 = piston2d(40, 31, 4, 10, 5, 10, 13, 10.0, pol="TM+TE", n_steps=400, n_harm=8)
+    p3, p2 = cf.Problem.from_workload(w3), cf.Problem.from_workload(w2)
+    with cf.Server(16 * 1024 * MiB) as srv:
+        t3 = srv.submit(p3, **opts_of(w3))
+        t2 = srv.submit(p2, **opts_of(w2))
+        r2 = srv.wait(t2, timeout=120)
+        r3 = srv.wait(t3, timeout=120)
+        s3, _, d3 = srv.times(t3)
+        s2, _, d2 = srv.times(t2)
+    print(f"[serve] piston done after {d2 - s2:.3f} s, 3D cell after {d3 - s3:.3f} s", flush=True)
+    assert r2["n_steps_run"] == r3["n_steps_run"] == 400
+    assert d2 - s2 < 0.5 * (d3 - s3)
+    one3 = p3.solve(**opts_of(w3, tile_variant=r3["tile_variant"]))
+    one2 = p2.solve(**opts_of(w2, tile_variant=r2["tile_variant"]))
+    np.testing.assert_array_equal(r3["per_channel"], one3["per_channel"])
+    np.testing.assert_array_equal(r2["per_channel"], one2["per_channel"])
+    assert r3["force"] == one3["force"] and r2["force"] == one2["force"]
