@@ -355,3 +355,22 @@ def layered_plates_1d(res: int, a_u: float, d_u: float, b_u: float, layer_u: flo
     lor = {2: tuple((float(de), float(w0)) for de, w0 in poles)} if poles else {}
     return wl.replace(eps=[1.0, PEC, float(eps_inf)], mu=[1.0, 1.0, 1.0], comp_ids=ids, lorentz=lor,
                       name=f"layered_plates_{nx}x{ny}", meta=dict(wl.meta, layer_px=L))
+
+
+def stop_cyl(**over) -> Workload:
+    """Cylindrical piston at resolution 10 (tube 15 units, orders m = 0..2,
+    3 harmonics per face, 2000 base steps, FP64): the cylindrical workload of
+    the convergence stop checks."""
+    kw = dict(res=10, h_u=0.8, length_u=15.0, n_harm=3, m_max=2, n_steps=2000, precision="fp64",
+              name="stop_cyl_piston_res10")
+    kw.update(over)
+    return cyl_piston(**kw)
+
+
+def stop_kz(**over) -> Workload:
+    """The dielectric piston (eps 4 blocks, 40 x 31) at three k_z points,
+    2000 steps, FP64: the k_z workload of the convergence stop checks."""
+    kw = dict(n_steps=2000, n_harm=6, precision="fp64")
+    kw.update(over)
+    base = dielectric_piston2d(40, 31, 4, 10, 5, 10, 13, 10.0, **kw)
+    return kz_workload(base, [0.0, 0.8, 2.5], [0.3, 0.5, 0.25]).replace(name="stop_kz_dielectric_piston")

@@ -208,8 +208,12 @@ typedef struct cf_surface {
  *   F = (1/pi) sum_m w_m sum_c s_c sum_k dt_m K(t_k) Gamma_c(t_k),
  * w_0 = 1, w_m>0 = 2 (the -m term is the conjugate of the +m term).
  * Options (cylindrical and k_z problems alike): pol = CF_POL_3D (all six
- * components); cylindrical runs need courant <= 0.5; stop_tol and the
- * server are not available (CF_E_UNSUPPORTED).  Execution: by
+ * components); cylindrical runs need courant <= 0.5.  The convergence stop
+ * counts steps on the axis of n_steps: after d of them every order has run
+ * floor(d T_m / n_steps) of its own steps (the same physical time, to one
+ * step of each order), and F(T') sums the channels there; it applies to the
+ * resident kernels with one wave of channels.  The server runs these
+ * problems as one whole solve per request.  Execution: by
  * default one launch per wave of resident channels (any mix of orders),
  * each block carrying one channel through all its steps; tile_variant 1
  * keeps the fields in registers with an LDS exchange (real runs: grids of up
@@ -399,12 +403,20 @@ const char* cf_last_error(void);
  * (one problem + options each, the whole Sec. II force computation) are
  * queued in arrival order; a request enters as soon as its memory fits the
  * budget (a later request may pass an earlier one that does not fit yet) and
- * leaves when all its time steps have run, returning its memory.  Every
- * scheduler tick advances all resident requests by the same number of steps;
- * 2D requests whose stress surface fits a fused tile share fused launches.
+ * leaves when all its time steps have run, returning its memory.  In every
+ * scheduler tick the 2D requests whose stress surface fits a fused tile
+ * share fused launches and advance steps_per_tick steps; every other
+ * resident request (3D, wider 2D) advances the steps that an equal share of
+ * the tick's device time buys it, from its measured time per step.
+ * Cylindrical and k_z requests (Sec. III B, III C: one launch runs every
+ * step of a channel) run their whole solve as cf_solve in one tick, on
+ * their region of the budget; the convergence stop is not available for
+ * them.  Problems with dispersive materials are not served
+ * (CF_E_UNSUPPORTED).
  * A request's arithmetic does not depend on what else is resident: a result
  * is bitwise the same alone and in any mix, and equals cf_solve with the
- * same options and tile_variant (fused 2D) or CF_FLAG_SPLIT (others).
+ * same options and tile_variant (fused 2D and 3D) or CF_FLAG_SPLIT (wider
+ * 2D).
  *
  * Ownership: cf_server_submit copies the problem into the request, so the
  * caller may destroy its handle as soon as the call returns.  A request that
@@ -450,7 +462,10 @@ cf_status cf_server_submit(cf_server* s, cf_problem* p, const cf_opts* opts, uin
 
 /* State of a request (CF_REQ_*); when done, *out (may be NULL) receives its
  * result as from cf_solve (device_ms = wall time from admission to
- * completion).  Returns the request's error for failed / cancelled ones. */
+ * completion, except for cylindrical and k_z requests, whose device_ms is
+ * their cf_solve's).  gamma and trace are not kept (CF_E_ARG when asked);
+ * short per_* arrays give CF_E_ARG.  Returns the request's error for failed
+ * / cancelled ones. */
 cf_status cf_server_poll(cf_server* s, uint64_t ticket, int* state, cf_result* out);
 
 /* As cf_server_poll after waiting up to timeout_s seconds (< 0: no limit)

@@ -17,6 +17,12 @@ Cartesian line element ds along S in the (r, z) plane (the Jacobian r
 cancels, as the Appendix shows).  Every order m runs with its own step
 dt_m = cylindrical_courant(courant, m) dx over the same physical time.
 
+Partial force.  The orders advance on different steps, so F(T') is read on
+the axis of the n_steps base steps: after d of them order m has run
+floor(d T_m / n_steps) of its own T_m steps (all of them at d = n_steps),
+the same physical time to within one step of that order, and trace[d - 1]
+sums every order's partial channel integrals there.
+
 Surface.  S is a box in the (z, r) plane: z from s_lo[0] to s_hi[0] (cells),
 r from s_lo[1] to s_hi[1] (cells); r = 0 (s_lo[1] = 0) means S reaches the
 axis (no inner face), s_hi[1] = nr means S reaches the tube wall at
@@ -144,6 +150,7 @@ class CylResult:
     chans: list
     faces: list
     n_steps_m: list
+    trace: np.ndarray = None   # F after d = 1..n_steps base steps (see the module docstring)
 
 
 def setup(wl):
@@ -215,13 +222,21 @@ def solve(wl, m_max: int):
     sign = np.array([ch["sign"] for ch in chans])
     acc = np.zeros((m_max + 1, len(chans)))
     per_m, n_steps_m = {}, []
+    base = wl.n_steps
+    trace = np.zeros(base)
+    d = np.arange(1, base + 1)
     for m in range(m_max + 1):
         cm = cylindrical_courant(wl.courant, m)
         T = int(round(t_end / (cm * dx)))
         gam, dt = run_order(wl, m, faces, bases, eps_s, mu_s, chans, T, cm)
         K = kernel_table(wl.kernel, wl.sigma, dt, T)
-        acc[m] = (dt * K[:, None] * gam).sum(axis=0)
+        terms = dt * K[:, None] * gam
+        acc[m] = terms.sum(axis=0)
         wm = 1.0 if m == 0 else 2.0
         per_m[m] = wm * float(np.sum(sign * acc[m])) / np.pi
         n_steps_m.append(T)
-    return CylResult(sum(per_m.values()), per_m, acc, sign, chans, faces, n_steps_m)
+        # partial sums of this order after floor(d T / base) of its steps
+        part = np.concatenate([[0.0], np.cumsum(terms @ sign)])
+        s = np.where(d >= base, T, (d * T) // base)
+        trace += wm * part[s] / np.pi
+    return CylResult(sum(per_m.values()), per_m, acc, sign, chans, faces, n_steps_m, trace)

@@ -130,6 +130,7 @@ class KzResult:
     sign: np.ndarray
     chans: list
     faces: list
+    trace: np.ndarray = None    # trace[m] = sum_q w_q F_q after m + 1 steps (every k shares dt)
 
 
 def solve(wl, ks: Sequence[float], weights: Sequence[float]) -> KzResult:
@@ -142,9 +143,12 @@ def solve(wl, ks: Sequence[float], weights: Sequence[float]) -> KzResult:
     sign = np.array([c.sign for c in chans])
     acc = np.zeros((len(ks), len(chans)))
     per_k = []
+    trace = np.zeros(wl.n_steps)
     for q, k in enumerate(ks):
         gam = kz_gammas(wl, k, chans, faces, bases, eps_s, mu_s, wl.n_steps)
-        acc[q] = (dt * K[:, None] * gam).sum(axis=0)
+        terms = dt * K[:, None] * gam
+        acc[q] = terms.sum(axis=0)
         per_k.append(float(np.sum(sign * acc[q]) / np.pi))
+        trace += weights[q] * np.cumsum(terms @ sign) / np.pi
     force = float(sum(w * f for w, f in zip(weights, per_k)))
-    return KzResult(force, per_k, acc, sign, chans, faces)
+    return KzResult(force, per_k, acc, sign, chans, faces, trace)

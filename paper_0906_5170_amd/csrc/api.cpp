@@ -24,6 +24,7 @@
 #include "device.hpp"
 #include "plan.hpp"
 #include "solver.hpp"
+#include "red_span.hpp"
 
 struct cf_problem {
     cf::Problem p;
@@ -854,6 +855,7 @@ cf_status run_reduced(const cf::Problem& p, const cf_opts& o, const Staged& st, 
     }
     ord.axis = p.cyl ? 1 : 0;
     ord.cplx = p.bloch ? 1 : 0;
+
     CF_HIP(up(L.lut, luts.data(), luts.size() * sizeof(T)));
     CF_HIP(up(L.ktab, ktabs.data(), ktabs.size() * 8));
     // row factors in the field precision (A, B, C, D, P, Q per row):
@@ -908,6 +910,15 @@ cf_status run_reduced(const cf::Problem& p, const cf_opts& o, const Staged& st, 
     }
     hipError_t err = hipSuccess;
     timing->variant = -1;     // resident variant - 1 (-1: split path)
+    // time-convergence stop (resident kernels, one wave): the run goes in
+    // parts of stop_every steps on the base axis (each order its share of
+    // its own steps, red_step_at); F(T') is checked after each part
+    cfi::ConvergenceStop conv;
+    conv.on = o.stop_tol > 0 && st.waves.size() == 1 && st.red_res && o.path != CF_PATH_PLAIN;
+    conv.tol = o.stop_tol;
+    conv.every = conv.next = o.stop_every > 0 ? o.stop_every : 500;
+    int steps_run = o.n_steps;
+    std::vector<double> acc_probe;
 #define STEP_OK(expr)                     \
     do {                                  \
         err = (expr);                     \
@@ -917,18 +928,33 @@ cf_status run_reduced(const cf::Problem& p, const cf_opts& o, const Staged& st, 
     for (const Wave& w : st.waves) {
         const int* sl = dslots + w.all_off;
         if (st.red_res) {
-            // one launch: every channel of the wave, any mix of orders
-            double cu = 0;
-            for (int k = 0; k < w.n_all; ++k) {
-                const int c = st.slot_lists[w.all_off + k];
-                cu += (double)p.ncell * ord.steps[st.chans[c].order];
+            // one launch per part: every channel of the wave, any mix of orders
+            for (int d0 = 0; d0 < o.n_steps;) {
+                const int d1 = conv.on ? std::min(o.n_steps, d0 + conv.every) : o.n_steps;
+                const cf::RedSpan span = cf::red_span(ord, n_ord, d0, d1, o.n_steps);
+                double cu = 0;
+                for (int k = 0; k < w.n_all; ++k) {
+                    const int m = st.chans[st.slot_lists[w.all_off + k]].order;
+                    cu += (double)p.ncell * (span.s1[m] - span.s0[m]);
+                }
+                const bool take = smp.begin(s);
+                int used = 0;
+                STEP_OK(cf::launch_red_resident_span<T>(o.tile_variant, fields, dch, sl, w.n_all, g, ord, span, tabs,
+                                                        dA, dacc, dgam, (int)C, s, &used));
+                smp.end(take, s, cu, cu * state_bytes);
+                timing->variant = std::max(timing->variant, used - 1);
+                d0 = d1;
+                if (conv.on && d1 < o.n_steps) {
+                    conv.next += conv.every;
+                    acc_probe.assign(C * 2, 0.0);
+                    STEP_OK(hipMemcpyAsync(acc_probe.data(), dacc, C * 2 * 8, hipMemcpyDeviceToHost, s));
+                    STEP_OK(hipStreamSynchronize(s));
+                    if (conv.update(acc_probe, st.chans)) {
+                        steps_run = d1;
+                        break;
+                    }
+                }
             }
-            const bool take = smp.begin(s);
-            int used = 0;
-            STEP_OK(cf::launch_red_resident<T>(o.tile_variant, fields, dch, sl, w.n_all, g, ord, tabs, dA, dacc, dgam,
-                                               (int)C, s, &used));
-            smp.end(take, s, cu, cu * state_bytes);
-            timing->variant = std::max(timing->variant, used - 1);
             continue;
         }
         const int m = w.order;
@@ -973,7 +999,7 @@ cf_status run_reduced(const cf::Problem& p, const cf_opts& o, const Staged& st, 
         timing->cu_total = smp.cu;
         timing->launches = smp.seen;
     }
-    timing->steps_run = o.n_steps;
+    timing->steps_run = steps_run;
     acc_out.assign(C * 2, 0.0);
     // copies on the solve's own stream: a non-blocking caller stream is not
     // ordered with the null stream
@@ -1498,8 +1524,14 @@ bool fill_result(const cf::Problem& p, const std::vector<cf::Channel>& chans, co
     out->n_steps_run = steps;
     out->cell_updates = (double)C * (double)p.ncell * (double)steps;
     if (p.reduced()) {
+        // each order runs its share of its own steps (all of them unless the
+        // convergence stop ended the run after `steps` base steps)
         out->cell_updates = 0;
-        for (size_t c = 0; c < C; ++c) out->cell_updates += (double)p.ncell * cf::order_steps(p, o, chans[c].order);
+        for (size_t c = 0; c < C; ++c) {
+            const int64_t tm = cf::order_steps(p, o, chans[c].order);
+            const int64_t run = steps >= o.n_steps ? tm : (int64_t)steps * tm / o.n_steps;
+            out->cell_updates += (double)p.ncell * (double)run;
+        }
     }
     out->device_ms = ms;
     out->stencil_samples = tim.samples;

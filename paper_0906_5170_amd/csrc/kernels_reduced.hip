@@ -47,6 +47,7 @@
 
 #include "../../include/casimir_fdtd.h"
 #include "device.hpp"
+#include "red_span.hpp"
 #include "yee_common.hpp"
 
 namespace cf {
@@ -470,7 +471,7 @@ __device__ __forceinline__ void e_phase(T* __restrict__ F0, const Grid2D& g, con
 template <typename T, bool CYL, bool CPLX>
 __global__ __launch_bounds__(kResThreads) void k_red_resident(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                               const int* __restrict__ slots, Grid2D g, RedOrders ord,
-                                                              SurfTables t, double dA, double* __restrict__ acc,
+                                                              RedSpan sp, SurfTables t, double dA, double* __restrict__ acc,
                                                               double* __restrict__ gamma, int gamma_stride) {
     __shared__ double red[yee::kSurfThreads / 64];
     __shared__ T Lc[6 * 256 * 2];
@@ -479,25 +480,27 @@ __global__ __launch_bounds__(kResThreads) void k_red_resident(T* __restrict__ fi
     const int m = d.order;
     const T* lut = static_cast<const T*>(ord.lut) + m * ord.lut_stride;
     const double* ktab = ord.ktab + m * ord.ktab_stride;
-    const int nsteps = ord.steps[m];
+    const int s0 = sp.s0[m], s1 = sp.s1[m];
     const double dt = ord.dt[m];
     T* F = fields + d.field_off;
     const T* lk = lut + d.kind * 6 * 256 * 2;
     for (int k = threadIdx.x; k < 6 * 256 * 2; k += kResThreads) Lc[k] = lk[k];
-    const int64_t nval = (CPLX ? 12 : 6) * g.ncell;
-    for (int64_t k = threadIdx.x; k < nval; k += kResThreads) F[k] = T(0);
-    __syncthreads();
-    // kick: the source component's surface deposit (one writer per point)
-    for (int u = threadIdx.x; u < d.n_uniq; u += kResThreads) {
-        const int k0 = t.uoff[d.u_off + u], k1 = t.uoff[d.u_off + u + 1];
-        double s = 0.0;
-        for (int k = k0; k < k1; ++k) s += t.uw[k] * t.basis[d.basis_off + t.usamp[k]];
-        fields[d.src_off + t.uidx[d.u_off + u]] = T(d.kick_scale * s);
-    }
-    __syncthreads();
     const RedRun<T> rr{T(ord.coup[m]), static_cast<const T*>(ord.rows), T(ord.ph_c[m]), T(ord.ph_s[m])};
-    if (d.kind == 0) h_phase<T, 1, CYL, kResThreads, CPLX>(F, g, Lc, rr);
-    else e_phase<T, 1, CYL, kResThreads, CPLX>(F, g, Lc, rr);
+    if (s0 == 0) {   // first part of the run: clear, kick and start
+        const int64_t nval = (CPLX ? 12 : 6) * g.ncell;
+        for (int64_t k = threadIdx.x; k < nval; k += kResThreads) F[k] = T(0);
+        __syncthreads();
+        // kick: the source component's surface deposit (one writer per point)
+        for (int u = threadIdx.x; u < d.n_uniq; u += kResThreads) {
+            const int k0 = t.uoff[d.u_off + u], k1 = t.uoff[d.u_off + u + 1];
+            double s = 0.0;
+            for (int k = k0; k < k1; ++k) s += t.uw[k] * t.basis[d.basis_off + t.usamp[k]];
+            fields[d.src_off + t.uidx[d.u_off + u]] = T(d.kick_scale * s);
+        }
+        __syncthreads();
+        if (d.kind == 0) h_phase<T, 1, CYL, kResThreads, CPLX>(F, g, Lc, rr);
+        else e_phase<T, 1, CYL, kResThreads, CPLX>(F, g, Lc, rr);
+    }
     __syncthreads();
     const T* X = fields + d.meas_off;
     double sum = 0.0, comp = 0.0;
@@ -505,7 +508,7 @@ __global__ __launch_bounds__(kResThreads) void k_red_resident(T* __restrict__ fi
         sum = acc[2 * slot];
         comp = acc[2 * slot + 1];
     }
-    for (int step = 0; step < nsteps; ++step) {
+    for (int step = s0; step < s1; ++step) {
         h_phase<T, 0, CYL, kResThreads, CPLX>(F, g, Lc, rr);
         __syncthreads();
         e_phase<T, 0, CYL, kResThreads, CPLX>(F, g, Lc, rr);
@@ -551,7 +554,7 @@ __host__ __device__ constexpr int regs_x_len(int n, int np) {
 template <typename T, int K, int NTH, bool CYL, bool CPLX>
 __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const ChanDev* __restrict__ ch,
                                                   const int* __restrict__ slots, Grid2D g, RedOrders ord,
-                                                  SurfTables t, double dA, double* __restrict__ acc,
+                                                  RedSpan sp, SurfTables t, double dA, double* __restrict__ acc,
                                                   double* __restrict__ gamma, int gamma_stride) {
     constexpr int NP = CPLX ? 2 : 1;               // parts: real (and imaginary)
     extern __shared__ double lds_dyn[];
@@ -567,30 +570,34 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
     const int m = d.order;
     const T* lut = static_cast<const T*>(ord.lut) + m * ord.lut_stride;
     const double* ktab = ord.ktab + m * ord.ktab_stride;
-    const int nsteps = ord.steps[m];
+    const int s0 = sp.s0[m], s1 = sp.s1[m];
+    const bool resume_later = s1 < ord.steps[m];
     const double dt = ord.dt[m];
     T* F = fields + d.field_off;
     const T* lk = lut + d.kind * 6 * 256 * 2;
-    for (int k = threadIdx.x; k < 6 * 256 * 2; k += NTH) Lg[k] = lk[k];
+    if (s0 == 0)
+        for (int k = threadIdx.x; k < 6 * 256 * 2; k += NTH) Lg[k] = lk[k];
     for (int k = threadIdx.x; k < 6 * 16 * 2; k += NTH) {
         const int cmp = k / 32, q = (k / 2) % 16;
         Lc[k] = lk[((cmp << 8) + (q == 15 ? 255 : q)) * 2 + (k & 1)];
     }
     for (int k = threadIdx.x; k < n; k += NTH) W[k] = ord.idw[k];
     for (int k = threadIdx.x; k < kRowFactors * g.ny; k += NTH) R[k] = static_cast<const T*>(ord.rows)[k];
-    for (int64_t k = threadIdx.x; k < NP * 6 * g.ncell; k += NTH) F[k] = T(0);
-    __syncthreads();
-    // (the exchange array takes over Lg's space after the start)
-    for (int u = threadIdx.x; u < d.n_uniq; u += NTH) {
-        const int k0 = t.uoff[d.u_off + u], k1 = t.uoff[d.u_off + u + 1];
-        double s = 0.0;
-        for (int k = k0; k < k1; ++k) s += t.uw[k] * t.basis[d.basis_off + t.usamp[k]];
-        fields[d.src_off + t.uidx[d.u_off + u]] = T(d.kick_scale * s);
-    }
-    __syncthreads();
     const RedRun<T> rr{T(ord.coup[m]), R, CPLX ? T(ord.ph_c[m]) : T(1), CPLX ? T(ord.ph_s[m]) : T(0)};
-    if (d.kind == 0) h_phase<T, 1, CYL, NTH, CPLX>(F, g, Lg, rr);
-    else e_phase<T, 1, CYL, NTH, CPLX>(F, g, Lg, rr);
+    if (s0 == 0) {   // first part of the run: clear, kick and start
+        for (int64_t k = threadIdx.x; k < NP * 6 * g.ncell; k += NTH) F[k] = T(0);
+        __syncthreads();
+        // (the exchange array takes over Lg's space after the start)
+        for (int u = threadIdx.x; u < d.n_uniq; u += NTH) {
+            const int k0 = t.uoff[d.u_off + u], k1 = t.uoff[d.u_off + u + 1];
+            double s = 0.0;
+            for (int k = k0; k < k1; ++k) s += t.uw[k] * t.basis[d.basis_off + t.usamp[k]];
+            fields[d.src_off + t.uidx[d.u_off + u]] = T(d.kick_scale * s);
+        }
+        __syncthreads();
+        if (d.kind == 0) h_phase<T, 1, CYL, NTH, CPLX>(F, g, Lg, rr);
+        else e_phase<T, 1, CYL, NTH, CPLX>(F, g, Lg, rr);
+    }
     __syncthreads();
     T e0[NP][K], e1[NP][K], e2[NP][K], h0[NP][K], h1[NP][K], h2[NP][K];
 #pragma unroll
@@ -644,7 +651,7 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
         }
         pending = -1;
     };
-    for (int step = 0; step < nsteps; ++step) {
+    for (int step = s0; step < s1; ++step) {
         asm volatile("" : "+v"(i0), "+v"(j0));
         {
             int i = i0, j = j0;
@@ -760,6 +767,29 @@ __global__ __launch_bounds__(NTH) void k_red_regs(T* __restrict__ fields, const 
         acc[2 * slot] = sum;
         acc[2 * slot + 1] = comp;
     }
+    if (resume_later) {   // a later launch resumes from memory
+        // the thread index and the block's field pointer are formed again
+        // here (through an empty asm statement) rather than kept live
+        // through the step loop
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        T* Fe = fields + ch[slots[blockIdx.x]].field_off;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int c = tid + k * NTH;
+                T* Fp = Fe + p * 6 * n;
+                if (c < n) {
+                    Fp[c] = e0[p][k];
+                    Fp[n + c] = e1[p][k];
+                    Fp[2 * n + c] = e2[p][k];
+                    Fp[3 * n + c] = h0[p][k];
+                    Fp[4 * n + c] = h1[p][k];
+                    Fp[5 * n + c] = h2[p][k];
+                }
+            }
+    }
 }
 
 template <typename T>
@@ -823,8 +853,8 @@ constexpr int kCplxRegVariants<double> = 3;
 // Launch register variant v if the grid fits it: *launched tells whether it did.
 template <typename T, int V, bool CYL, bool CPLX>
 hipError_t regs_try(int64_t ncell, size_t lds, bool* launched, T* fields, const ChanDev* ch, const int* slots,
-                    int nslots, const Grid2D& g, const RedOrders& ord, const SurfTables& t, double dA, double* acc,
-                    double* gamma, int gamma_stride, hipStream_t s) {
+                    int nslots, const Grid2D& g, const RedOrders& ord, const RedSpan& sp, const SurfTables& t,
+                    double dA, double* acc, double* gamma, int gamma_stride, hipStream_t s) {
     *launched = false;
     if constexpr (CPLX && V >= kCplxRegVariants<T>) {
         return hipSuccess;
@@ -833,7 +863,7 @@ hipError_t regs_try(int64_t ncell, size_t lds, bool* launched, T* fields, const 
         if (ncell > (int64_t)K * NTH || !regs_lds_ok<T, K, NTH, CYL, CPLX>(lds)) return hipSuccess;
         *launched = true;
         hipLaunchKernelGGL((k_red_regs<T, K, NTH, CYL, CPLX>), dim3(nslots), dim3(NTH), lds, s, fields, ch, slots, g,
-                           ord, t, dA, acc, gamma, gamma_stride);
+                           ord, sp, t, dA, acc, gamma, gamma_stride);
         return hipGetLastError();
     }
 }
@@ -886,8 +916,8 @@ hipError_t launch_ered(int mode, double coupling, int axis, T* fields, const Cha
 
 template <typename T, bool CYL, bool CPLX>
 hipError_t resident_launch(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
-                           const Grid2D& g, const RedOrders& ord, const SurfTables& t, double dA, double* acc,
-                           double* gamma, int gamma_stride, hipStream_t s, int* used) {
+                           const Grid2D& g, const RedOrders& ord, const RedSpan& sp, const SurfTables& t, double dA,
+                           double* acc, double* gamma, int gamma_stride, hipStream_t s, int* used) {
     *used = 0;
     if (nslots <= 0) return hipSuccess;
     const size_t dyn = regs_lds_bytes<T>(g, CPLX ? 2 : 1);
@@ -897,7 +927,7 @@ hipError_t resident_launch(int variant, T* fields, const ChanDev* ch, const int*
         auto attempt = [&](auto v) {
             if (!launched && e == hipSuccess)
                 e = regs_try<T, decltype(v)::value, CYL, CPLX>(g.ncell, dyn, &launched, fields, ch, slots, nslots, g,
-                                                               ord, t, dA, acc, gamma, gamma_stride, s);
+                                                               ord, sp, t, dA, acc, gamma, gamma_stride, s);
         };
         attempt(std::integral_constant<int, 0>{});
         attempt(std::integral_constant<int, 1>{});
@@ -913,23 +943,34 @@ hipError_t resident_launch(int variant, T* fields, const ChanDev* ch, const int*
         }
     }
     *used = 2;
-    hipLaunchKernelGGL((k_red_resident<T, CYL, CPLX>), dim3(nslots), dim3(kResThreads), 0, s, fields, ch, slots, g, ord, t, dA,
-                       acc, gamma, gamma_stride);
+    hipLaunchKernelGGL((k_red_resident<T, CYL, CPLX>), dim3(nslots), dim3(kResThreads), 0, s, fields, ch, slots, g, ord, sp,
+                       t, dA, acc, gamma, gamma_stride);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_red_resident_span(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
+                                    const Grid2D& g, const RedOrders& ord, const RedSpan& sp, const SurfTables& t,
+                                    double dA, double* acc, double* gamma, int gamma_stride, hipStream_t s,
+                                    int* used) {
+    if (ord.axis)
+        return resident_launch<T, true, false>(variant, fields, ch, slots, nslots, g, ord, sp, t, dA, acc, gamma,
+                                               gamma_stride, s, used);
+    if (ord.cplx)
+        return resident_launch<T, false, true>(variant, fields, ch, slots, nslots, g, ord, sp, t, dA, acc, gamma,
+                                               gamma_stride, s, used);
+    return resident_launch<T, false, false>(variant, fields, ch, slots, nslots, g, ord, sp, t, dA, acc, gamma,
+                                            gamma_stride, s, used);
 }
 
 template <typename T>
 hipError_t launch_red_resident(int variant, T* fields, const ChanDev* ch, const int* slots, int nslots,
                                const Grid2D& g, const RedOrders& ord, const SurfTables& t, double dA, double* acc,
                                double* gamma, int gamma_stride, hipStream_t s, int* used) {
-    if (ord.axis)
-        return resident_launch<T, true, false>(variant, fields, ch, slots, nslots, g, ord, t, dA, acc, gamma,
-                                               gamma_stride, s, used);
-    if (ord.cplx)
-        return resident_launch<T, false, true>(variant, fields, ch, slots, nslots, g, ord, t, dA, acc, gamma,
-                                               gamma_stride, s, used);
-    return resident_launch<T, false, false>(variant, fields, ch, slots, nslots, g, ord, t, dA, acc, gamma,
-                                            gamma_stride, s, used);
+    RedSpan sp{};
+    for (int m = 0; m < kMaxOrders; ++m) sp.s1[m] = ord.steps[m];
+    return launch_red_resident_span<T>(variant, fields, ch, slots, nslots, g, ord, sp, t, dA, acc, gamma,
+                                       gamma_stride, s, used);
 }
 
 #define CF_RED_INSTANTIATE(T)                                                                                   \
@@ -939,7 +980,10 @@ hipError_t launch_red_resident(int variant, T* fields, const ChanDev* ch, const 
                                        const T*, const T*, double, double, int, hipStream_t);                  \
     template hipError_t launch_red_resident<T>(int, T*, const ChanDev*, const int*, int, const Grid2D&,       \
                                                const RedOrders&, const SurfTables&, double, double*, double*, \
-                                               int, hipStream_t, int*);
+                                               int, hipStream_t, int*);                                         \
+    template hipError_t launch_red_resident_span<T>(int, T*, const ChanDev*, const int*, int, const Grid2D&,  \
+                                                    const RedOrders&, const RedSpan&, const SurfTables&, double, \
+                                                    double*, double*, int, hipStream_t, int*);
 CF_RED_INSTANTIATE(float)
 CF_RED_INSTANTIATE(double)
 #undef CF_RED_INSTANTIATE

@@ -650,10 +650,6 @@ std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
     if (o.kernel != CF_KERNEL_GENERAL && o.kernel != CF_KERNEL_ZINV2D) return "unknown kernel";
     if (p.reduced()) {
         if (o.pol != CF_POL_3D) return "cylindrical and k_z runs take CF_POL_3D (all six components)";
-        if (o.stop_tol > 0) {
-            *code = CF_E_UNSUPPORTED;
-            return "the convergence stop is not available for cylindrical and k_z problems";
-        }
     } else if (p.grid.ndim == 2) {
         if (o.pol < 1 || o.pol > 3) return "2D runs take CF_POL_TM and/or CF_POL_TE";
         if (o.kernel == CF_KERNEL_ZINV2D && !p.vacuum_conductors) {

@@ -15,7 +15,10 @@
 //     gets an equal share of the tick's device time, the share of one
 //     fused request, as steps from its measured time per step.  A cheap 2D
 //     request is thus not held to the pace of a 3D cell many times its
-//     size (processor sharing in time rather than in steps).
+//     size (processor sharing in time rather than in steps);
+//   - cylindrical and k_z requests (whose kernels run every step of a
+//     channel in one launch) run their whole solve in one tick, on their
+//     arena region and the server's stream.
 // When a request has run all its steps its accumulators are copied back,
 // its memory returns to the arena and waiting requests can enter.  Every
 // request's arithmetic is independent of its co-residents, so a result is
@@ -85,6 +88,13 @@ struct Req {
     int tick_steps = 0;           // steps in the coming tick
     double credit = 0;            // step credit carried between ticks
     double sps = 0;               // measured device seconds per step
+    // cylindrical and k_z requests run as one cf_solve on their arena region
+    // (their kernels take every step of a channel in one launch)
+    bool whole = false;
+    bool ran = false;
+    std::unique_ptr<cf_problem> handle;
+    std::vector<double> w_ph, w_pf, w_pc;
+    cf_result w_res{};
     int state = ST_QUEUED;
     cf_status status = CF_OK;
     std::string err;
@@ -382,6 +392,7 @@ hipError_t start_wave(cf_server* S, Req& r, T* f) {
 
 template <typename T>
 hipError_t admit(cf_server* S, Req& r) {
+    if (r.whole) return hipSuccess;   // cf_solve stages its own tables at run time
     char* b = S->arena_base + r.off;
     hipStream_t s = S->stream;
     const cfi::Staged& st = r.st;
@@ -536,7 +547,7 @@ hipError_t tick(cf_server* S) {
     if ((e = mark()) != hipSuccess) return e;
     for (auto& rp : S->active) {
         Req& r = *rp;
-        if (r.fused) continue;
+        if (r.fused || r.whole) continue;
         char* b = S->arena_base + r.off;
         const cf::Problem& p = *r.prob;
         const cfi::Wave& w = r.st.waves[r.wave];
@@ -602,6 +613,27 @@ hipError_t tick(cf_server* S) {
         }
         if ((e = mark()) != hipSuccess) return e;
     }
+    // whole-solve requests: one blocking cf_solve each (a failure fails only
+    // that request)
+    for (auto& rp : S->active) {
+        Req& r = *rp;
+        if (!r.whole || r.ran || r.cancel) continue;
+        cf_opts o = r.opts;
+        o.stream = s;
+        r.w_res = cf_result{};
+        r.w_res.per_harmonic = r.w_ph.data();
+        r.w_res.per_harmonic_len = (int)r.w_ph.size();
+        r.w_res.per_face = r.w_pf.data();
+        r.w_res.per_face_len = (int)r.w_pf.size();
+        r.w_res.per_channel = r.w_pc.data();
+        r.w_res.per_channel_len = (int)r.w_pc.size();
+        const cf_status st = cf_solve(r.handle.get(), &o, S->arena_base + r.off, r.bytes, &r.w_res);
+        r.ran = true;
+        if (st != CF_OK) {
+            r.status = st;
+            r.err = cf_last_error();
+        }
+    }
     return hipSuccess;
 }
 
@@ -619,12 +651,12 @@ void plan_steps(cf_server* S) {
     double min_sps = 0;
     for (auto& rp : S->active) {
         if (rp->fused) ++nf;
-        else if (rp->sps > 0 && (min_sps == 0 || rp->sps < min_sps)) min_sps = rp->sps;
+        else if (!rp->whole && rp->sps > 0 && (min_sps == 0 || rp->sps < min_sps)) min_sps = rp->sps;
     }
     const double share = nf > 0 ? (S->group_s > 0 ? S->group_s / nf : 0.0) : S->kh * min_sps;
     for (auto& rp : S->active) {
         Req& r = *rp;
-        if (r.fused) continue;
+        if (r.fused || r.whole) continue;
         const long long left = r.opts.n_steps - r.done;
         long long n = S->kh;
         if (r.sps > 0 && share > 0) {
@@ -657,7 +689,7 @@ void read_times(cf_server* S) {
     size_t k = 1;
     for (auto& rp : S->active) {
         Req& r = *rp;
-        if (r.fused) continue;
+        if (r.fused || r.whole) continue;
         if (k + 1 >= S->n_marks) break;
         const double t = span(k++);
         if (r.tick_steps > 0 && t > 0) {
@@ -763,7 +795,7 @@ void loop(cf_server* S) {
         S->clock += S->kh;
         S->parity ^= 1;
         for (auto& rp : S->active)
-            if (!rp->fused) rp->done += rp->tick_steps;
+            if (!rp->fused && !rp->whole) rp->done += rp->tick_steps;
         // the stream has drained: staged group tables are no longer read
         S->keep_ch.clear();
         S->keep_inst.clear();
@@ -771,7 +803,7 @@ void loop(cf_server* S) {
         // ---- retire finished requests / start next channel waves ----
         for (auto it = S->active.begin(); it != S->active.end();) {
             Req& r = **it;
-            const long long ran = r.fused ? S->clock - r.start : r.done;
+            const long long ran = r.fused ? S->clock - r.start : r.whole ? (r.ran ? r.opts.n_steps : 0) : r.done;
             bool wave_done = ran >= r.opts.n_steps;
             const long long done = std::min<long long>(ran, r.opts.n_steps);
             if (!wave_done && r.conv.on && done >= r.conv.next) {
@@ -807,6 +839,9 @@ void loop(cf_server* S) {
                 r.status = CF_E_CANCELLED;
                 r.err = "request cancelled";
                 ++S->n_cancelled;
+            } else if (r.whole) {
+                r.state = r.status == CF_OK ? ST_DONE : ST_FAILED;
+                (r.status == CF_OK ? S->n_completed : S->n_failed)++;
             } else if (r.status == CF_OK) {
                 r.acc.assign((size_t)r.C * 2, 0.0);
                 hipError_t e3 = hipMemcpyAsync(r.acc.data(), S->arena_base + r.off + r.o_acc, r.acc.size() * 8,
@@ -907,20 +942,34 @@ static cf_status cf_server_submit_impl(cf_server* S, cf_problem* prob, const cf_
     if (o->precision != S->precision) return fail(CF_E_ARG, "request precision differs from the server's");
     if (o->path != CF_PATH_BATCHED) return fail(CF_E_ARG, "served requests use the batched path");
     if (o->n_subset > 0) return fail(CF_E_ARG, "served requests run every channel");
-    if (prob->p.reduced())
-        return fail(CF_E_UNSUPPORTED, "cylindrical and k_z problems are solved with cf_solve, not served");
     if (prob->p.dispersive)
         return fail(CF_E_UNSUPPORTED, "problems with dispersive materials are solved with cf_solve, not served");
     cf_status st = cf_validate(prob, o);
     if (st != CF_OK) return st;
     auto r = std::make_shared<Req>();
-    r->own = prob->p;                 // the caller may destroy its problem after submitting
-    r->prob = &r->own;
     r->opts = *o;
     r->t_submit = now_s();
-    // staging reads only settings fixed at creation: no lock needed
-    std::string err = prepare(S, *r);
-    if (!err.empty()) return fail(CF_E_BUDGET, err);
+    if (prob->p.reduced()) {
+        // the caller may destroy its problem after submitting: keep a copy
+        r->handle.reset(new cf_problem{prob->p});
+        r->prob = &r->handle->p;
+        r->whole = true;
+        cf_info info;
+        if ((st = cf_problem_info(r->handle.get(), o, &info)) != CF_OK) return st;
+        r->C = info.n_channels;
+        r->w_ph.assign(info.per_harmonic_len, 0.0);
+        r->w_pf.assign(2 * r->prob->grid.ndim, 0.0);
+        r->w_pc.assign(info.n_channels, 0.0);
+        r->bytes = cfi::align_up(info.workspace_bytes, 256);
+        if (r->bytes > S->arena.size())
+            return fail(CF_E_BUDGET, "request does not fit the server's memory budget");
+    } else {
+        r->own = prob->p;             // the caller may destroy its problem after submitting
+        r->prob = &r->own;
+        // staging reads only settings fixed at creation: no lock needed
+        std::string err = prepare(S, *r);
+        if (!err.empty()) return fail(CF_E_BUDGET, err);
+    }
     {
         std::lock_guard<std::mutex> lk(S->mu);
         r->ticket = S->next_ticket++;
@@ -936,6 +985,35 @@ static cf_status cf_server_submit_impl(cf_server* S, cf_problem* prob, const cf_
 static cf_status report(cf_server* S, const std::shared_ptr<Req>& r, int* state, cf_result* out) {
     if (state) *state = r->state;
     if (r->state == ST_DONE && out) {
+        const int lab = cf::harmonic_len(*r->prob);
+        if (out->per_harmonic && out->per_harmonic_len < lab) return fail(CF_E_ARG, "per_harmonic too short");
+        if (out->per_face && out->per_face_len < 2 * r->prob->grid.ndim) return fail(CF_E_ARG, "per_face too short");
+        if (out->per_channel && out->per_channel_len < r->C) return fail(CF_E_ARG, "per_channel too short");
+        if (out->gamma || out->trace) return fail(CF_E_ARG, "served requests keep no gamma or trace");
+    }
+    if (r->state == ST_DONE && out && r->whole) {
+        const cf_result& w = r->w_res;
+        auto put = [](double* dst, int len, const std::vector<double>& v) {
+            if (dst) std::copy(v.begin(), v.begin() + std::min<size_t>(v.size(), (size_t)len), dst);
+        };
+        put(out->per_harmonic, out->per_harmonic_len, r->w_ph);
+        put(out->per_face, out->per_face_len, r->w_pf);
+        put(out->per_channel, out->per_channel_len, r->w_pc);
+        out->force = w.force;
+        out->n_channels_run = w.n_channels_run;
+        out->cell_updates = w.cell_updates;
+        out->device_ms = w.device_ms;
+        out->stencil_ms_avg = w.stencil_ms_avg;
+        out->stencil_samples = w.stencil_samples;
+        out->stencil_launches = w.stencil_launches;
+        out->stencil_alg_bytes = w.stencil_alg_bytes;
+        out->stencil_cell_updates = w.stencil_cell_updates;
+        out->fused = w.fused;
+        out->tile_variant = w.tile_variant;
+        out->tile_halo = w.tile_halo;
+        out->n_steps_run = w.n_steps_run;
+        out->advanced_cell_updates = w.advanced_cell_updates;
+    } else if (r->state == ST_DONE && out) {
         cfi::StencilTiming tim;
         tim.steps_run = r->steps_run;
         tim.variant = r->variant >= 0 ? r->variant : r->v3;   // fused 2D tile or fused 3D band shape

@@ -11,11 +11,14 @@ casimir_inputs; no value comes from the HIP library.
     python tests/golden/make_golden.py cyl     # cylindrical piston res 40, n, m in {0, 1, 2}, full T
     python tests/golden/make_golden.py kz      # k_z dielectric piston, 8 k points, full T
     python tests/golden/make_golden.py stop    # partial-force traces of the convergence-stop workloads
+    python tests/golden/make_golden.py stop_reduced  # the same for a cylindrical and a k_z workload
 """
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
@@ -137,6 +140,32 @@ def stop_traces(workers=8):
         json.dump(out, f, indent=1)
 
 
+def stop_traces_reduced():
+    """Partial-force traces of the cylindrical and k_z convergence-stop
+    workloads (the cylindrical trace on the axis of the base steps: order m
+    at floor(d T_m / n_steps) of its own steps)."""
+    from casimir_inputs.configs import stop_cyl, stop_kz
+    from oracle import cylforce, kz
+    out = {"source": "oracle.cylforce.solve / oracle.kz.solve (FP64 NumPy), written by tests/golden/make_golden.py"}
+    t0 = time.time()
+    wl = stop_cyl()
+    r = cylforce.solve(wl, m_max=wl.m_max)
+    terms = sum(float(np.sum(np.abs(r.sign * r.acc[m]))) * (1.0 if m == 0 else 2.0)
+                for m in range(wl.m_max + 1)) / np.pi
+    out["cyl"] = dict(workload=wl.name, shape=list(wl.shape), n_steps=wl.n_steps, n_steps_m=list(r.n_steps_m),
+                      force=r.force, terms=terms, trace=[float(v) for v in r.trace], oracle_seconds=time.time() - t0)
+    print("cyl", r.force, f"{time.time() - t0:.1f}s")
+    t0 = time.time()
+    wl = stop_kz()
+    r = kz.solve(wl, wl.kz, wl.kz_weight)
+    terms = sum(abs(w) * float(np.sum(np.abs(r.sign * r.acc[q]))) for q, w in enumerate(wl.kz_weight)) / np.pi
+    out["kz"] = dict(workload=wl.name, shape=list(wl.shape), n_steps=wl.n_steps, force=r.force, terms=terms,
+                     trace=[float(v) for v in r.trace], oracle_seconds=time.time() - t0)
+    print("kz", r.force, f"{time.time() - t0:.1f}s")
+    with open(os.path.join(HERE, "stop_traces_reduced_oracle.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 def main(which, workers=8):
     fname, make = CASES[which]
     wl = make()
@@ -172,5 +201,7 @@ if __name__ == "__main__":
         kz_golden()
     elif sys.argv[1] == "stop":
         stop_traces()
+    elif sys.argv[1] == "stop_reduced":
+        stop_traces_reduced()
     else:
         main(sys.argv[1])

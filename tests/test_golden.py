@@ -44,3 +44,20 @@ def test_stop_traces_are_current():
     s3 = ref["sphere3d"]
     assert s3["workload"] == stop_sphere3d().name and len(s3["trace"]) == s3["n_steps"]
     assert s3["trace"][-1] == pytest.approx(s3["force"], rel=1e-12)
+
+
+def test_reduced_stop_traces_are_current():
+    """The cylindrical trace is recomputed (13 s) and must match to rounding;
+    both traces end at their force."""
+    from casimir_inputs.configs import stop_cyl, stop_kz
+    from oracle import cylforce
+    path = os.path.join(HERE, "golden", "stop_traces_reduced_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("stop_traces_reduced_oracle.json not generated")
+    ref = json.load(open(path))
+    wl = stop_cyl()
+    r = cylforce.solve(wl, m_max=wl.m_max)
+    np.testing.assert_allclose(r.trace, ref["cyl"]["trace"], rtol=1e-12, atol=1e-18)
+    assert ref["kz"]["workload"] == stop_kz().name
+    for key in ("cyl", "kz"):
+        assert ref[key]["trace"][-1] == pytest.approx(ref[key]["force"], rel=1e-9)

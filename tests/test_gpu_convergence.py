@@ -191,3 +191,73 @@ def test_stop_3d_matches_the_oracle_rule(cf, variant):
     assert r["fused"]
     assert r["n_steps_run"] == T_ref
     assert abs(r["force"] - ref["trace"][T_ref - 1]) <= 1e-9 * ref["terms"]
+
+
+GOLD_RED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "stop_traces_reduced_oracle.json")
+
+
+def gold_red(key):
+    if not os.path.exists(GOLD_RED):
+        pytest.skip("stop_traces_reduced_oracle.json not generated")
+    return json.load(open(GOLD_RED))[key]
+
+
+def reduced_case(key):
+    from casimir_inputs.configs import stop_cyl, stop_kz
+    return stop_cyl() if key == "cyl" else stop_kz()
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("key", ["cyl", "kz"])
+def test_stop_reduced_matches_the_oracle_rule(cf, key, variant):
+    """Cylindrical and k_z problems on the resident kernels (1: fields in
+    registers, 2: in global memory): the run goes in parts of stop_every base
+    steps, and the stop step and force follow the oracle's trace (for the
+    cylinder, every order at floor(d T_m / n_steps) of its own steps)."""
+    announce(f"convergence stop vs oracle rule, {key}, resident variant {variant}")
+    ref = gold_red(key)
+    wl = reduced_case(key)
+    assert ref["workload"] == wl.name
+    every, tol = 50, 1e-6
+    T_ref, margin = oracle_stop_step(np.array(ref["trace"]), tol, every)
+    assert T_ref < wl.n_steps and margin > 0.05, (T_ref, margin)
+    p = cf.Problem.from_workload(wl)
+    o = opts_of(wl, pol="3D", stop_tol=tol, stop_every=every, tile_variant=variant)
+    r = p.solve(**o)
+    print(f"[stop] {key} variant {r['tile_variant']}: oracle rule {T_ref}, GPU {r['n_steps_run']}", flush=True)
+    assert r["tile_variant"] == variant
+    assert r["n_steps_run"] == T_ref
+    assert abs(r["force"] - ref["trace"][T_ref - 1]) <= 1e-9 * ref["terms"]
+    full = p.solve(**opts_of(wl, pol="3D", tile_variant=variant))
+    assert r["cell_updates"] < full["cell_updates"]
+
+
+def _bloch_grating(n_steps):
+    from casimir_inputs import kz_workload
+    BIGV = 1e30
+    nx, ny = 24, 30
+    ids = rasterize((nx, ny, 1), [Box((-BIGV, -BIGV, -BIGV), (BIGV, 4, BIGV), 1), Box((8, 12, -BIGV), (16, 18, BIGV), 2)])
+    wl = Workload(name="grating1", ndim=2, shape=(nx, ny, 1), res=10.0, bc=("periodic", "pec", "periodic"),
+                  pml_cells=(0, 0, 0), eps=[1.0, float("-inf"), 4.0], mu=[1.0, 1.0, 1.0], comp_ids=ids,
+                  s_lo=(6, 10, 0), s_hi=(18, 20, 1), n_harm=4, force_axis=1, pol="3D", kernel="general",
+                  n_steps=n_steps, sigma=1.0, courant=0.5, precision="fp64")
+    return kz_workload(wl, [0.0, 0.9], [1.0, 1.0], kx=[0.4, 0.4])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("key", ["cyl", "kz", "bloch"])
+def test_reduced_parts_resume_bitwise(cf, key, variant, precision):
+    """A run cut into parts (a stop that never fires: checks every 37 base
+    steps while the force still moves) equals the one-launch run bit for
+    bit, per channel and per step of Gamma."""
+    announce(f"reduced run in parts vs one launch, {key}, variant {variant}, {precision}")
+    wl = _bloch_grating(300) if key == "bloch" else reduced_case(key).replace(n_steps=300)
+    p = cf.Problem.from_workload(wl)
+    o = opts_of(wl, pol="3D", precision=precision, tile_variant=variant, keep_gamma=True)
+    one = p.solve(**o)
+    parts = p.solve(**dict(o, stop_tol=1e-15, stop_every=37))
+    assert parts["n_steps_run"] == wl.n_steps and parts["tile_variant"] == variant
+    np.testing.assert_array_equal(parts["per_channel"], one["per_channel"])
+    np.testing.assert_array_equal(parts["gamma"], one["gamma"])
+    assert parts["force"] == one["force"]

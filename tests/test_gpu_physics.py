@@ -1,8 +1,7 @@
 """Physics of the piston with sidewalls (Sec. III A, Fig. 3) on the GPU path.
 
-The paper computes the force between the two blocks as a function of the
-sidewall separation h for metallic and for perfect-magnetic-conductor (PMC)
-sidewalls. It reports three qualitative facts, explained by image currents
+Sec. III A sweeps the sidewall separation h and plots the block-block
+force for metallic and for perfect-magnetic-conductor (PMC) sidewalls. It reports three qualitative facts, explained by image currents
 that change sign between the two kinds of wall:
 * metallic sidewalls suppress the TM force and enhance the TE force at
   small h, so the total force is nonmonotonic in h;

@@ -246,3 +246,34 @@ def test_server_time_share_lets_small_requests_pass(cf):
     np.testing.assert_array_equal(r3["per_channel"], one3["per_channel"])
     np.testing.assert_array_equal(r2["per_channel"], one2["per_channel"])
     assert r3["force"] == one3["force"] and r2["force"] == one2["force"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_server_runs_cylindrical_and_kz_requests_whole(cf, precision):
+    """Cylindrical and k_z requests (their kernels take every step of a
+    channel in one launch) run as one whole solve inside a tick, beside a
+    fused piston; each result equals its one-shot cf_solve bit for bit."""
+    from casimir_inputs import cyl_piston, dielectric_piston2d, kz_workload
+    announce(f"server: cylindrical and k_z requests beside a piston ({precision})")
+    wls = [cyl_piston(res=10, h_u=0.8, length_u=15.0, n_harm=3, m_max=2, n_steps=400, precision=precision),
+           kz_workload(dielectric_piston2d(40, 31, 4, 10, 5, 10, 13, 10.0, n_steps=300, n_harm=6,
+                                           precision=precision), [0.0, 0.8, 2.5], [0.3, 0.5, 0.25]),
+           piston2d(40, 31, 4, 10, 5, 10, 13, 10.0, pol="TM+TE", n_steps=300, n_harm=8)]
+    probs = [cf.Problem.from_workload(w) for w in wls]
+    opts = [opts_of(w, precision=precision) for w in wls]
+    stop = dict(opts[0], stop_tol=1e-2, stop_every=50)     # the stop runs the resident kernels in parts
+    with cf.Server(256 * MiB, precision=precision) as srv:
+        tickets = [srv.submit(p, **o) for p, o in zip(probs, opts)]
+        t_stop = srv.submit(probs[0], **stop)
+        served = [srv.wait(t, timeout=120) for t in tickets]
+        stopped = srv.wait(t_stop, timeout=120)
+        st = srv.stats()
+    assert st["completed"] == 4 and st["failed"] == 0
+    one = probs[0].solve(**stop)
+    assert stopped["n_steps_run"] == one["n_steps_run"] < wls[0].n_steps
+    np.testing.assert_array_equal(stopped["per_channel"], one["per_channel"])
+    for p, o, s in zip(probs, opts, served):
+        one = p.solve(**dict(o, tile_variant=s["tile_variant"]) if s["fused"] else o)
+        np.testing.assert_array_equal(s["per_channel"], one["per_channel"])
+        np.testing.assert_array_equal(s["per_harmonic"], one["per_harmonic"])
+        assert s["force"] == one["force"] and s["n_steps_run"] == one["n_steps_run"]

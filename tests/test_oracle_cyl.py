@@ -18,6 +18,11 @@
   error): the error falls by > 3.5x from 20 to 40 cells per unit (second
   order: 4x) and is below 15 % at 40 (measured: m = 0 58 % -> 12 %,
   m = 1 27 % -> 6 %).
+* The tube's ends are immaterial: the piston's force with PEC end caps 3.5
+  units beyond each cylinder equals the force with caps 5.5 units beyond to
+  a relative 1e-6 (the tube is a waveguide below cutoff on the imaginary
+  frequency contour, so the fields decay exponentially along the axis; the
+  paper terminates its tube with PML for the same purpose, Sec. III C).
 """
 import numpy as np
 import pytest
@@ -221,3 +226,16 @@ def test_piston_converges_to_mode_sum():
     for m in (0, 1):
         assert abs(errs[m][1]) < 0.15
         assert abs(errs[m][0]) / abs(errs[m][1]) > 3.5
+
+
+def test_tube_end_caps_are_immaterial():
+    """cyl_piston at res 10, T = 2500: tube lengths 10 (the benchmark's
+    3.5 units of tube beyond each cylinder) and 14 give the same force to
+    1e-6 relative, and length 8 (2.5 units) already to 1e-3."""
+    from casimir_inputs import cyl_piston
+    with threadpool_limits(limits=1):
+        f = {L: cylforce.solve(w, m_max=w.m_max).force
+             for L, w in ((L, cyl_piston(res=10, h_u=0.5, length_u=L, n_harm=3, m_max=2, n_steps=2500,
+                                         precision="fp64")) for L in (8.0, 10.0, 14.0))}
+    assert abs(f[10.0] / f[14.0] - 1) < 1e-6
+    assert 1e-6 < abs(f[8.0] / f[14.0] - 1) < 1e-3
