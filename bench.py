@@ -138,6 +138,21 @@ def measured_serving_mixed():
     return rec
 
 
+C4_FULL_RECORD = os.path.join(ROOT, "profiles", "c4_full_solve_sphere_plate_192_fp32.json")
+
+
+def measured_c4_full():
+    """The committed record of the whole 3D force solve (bench.py --c4-full:
+    about 4.5 minutes, too long for the default run), with whether the 3D
+    kernel sources are still the ones it was measured on."""
+    if not os.path.exists(C4_FULL_RECORD):
+        return None
+    rec = json.load(open(C4_FULL_RECORD))
+    rec["source_current"] = rec.get("source_sha256") == kernel3d_source_hash()
+    rec["measured_in_this_run"] = False
+    return rec
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -242,7 +257,8 @@ def bench_3d(cf, torch, n_chan=64, n_steps=200, variant=0):
             "traffic_bytes_per_advanced_cell_update": traffic / adv if traffic else None,
             "real_hbm_GBps": traffic / (r["stencil_ms_avg"] * 1e-3) / 1e9 if traffic and r["stencil_ms_avg"] else None,
             "variant_sweep": sweep,
-            "projected_full_solve_s": 1280 * wl.n_cells * wl.n_steps / rate}
+            "projected_full_solve_s": 1280 * wl.n_cells * wl.n_steps / rate,
+            "full_solve_record": measured_c4_full()}
 
 
 def bench_3d_full(cf, torch, waves=3, precision="fp32", run=None):

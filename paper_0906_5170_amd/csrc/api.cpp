@@ -539,6 +539,8 @@ TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, c
                   const ELive* el) {
     TBPlan t;
     if (p.grid.ndim != 2 || p.reduced() || chans.empty()) return t;
+    // the fused kernel forms the surface sum with its first four waves
+    if ((sh.ty + 2 * sh.kh) / sh.b < 4) return t;
     int xmin = p.nx, xmax = -1, ymin = p.ny, ymax = -1;
     bool pol_used[2] = {false, false};
     for (const auto& ch : chans) {

@@ -138,6 +138,7 @@ def test_every_tile_variant_bitwise_equals_split(cf, precision, nvar):
     wl = SMALL["ragged_61x37"]().replace(n_steps=53)
     ref = run(cf, wl, precision=precision, split=True)
     for v in range(1, nvar + 1):
+        print(f"[variant] {v}", flush=True)
         r = run(cf, wl, precision=precision, tile_variant=v)
         assert r["fused"] and r["tile_variant"] == v
         np.testing.assert_array_equal(r["per_channel"], ref["per_channel"])
@@ -299,6 +300,7 @@ def test_fused_skips_conductor_rows_bitwise(cf, name, precision, nvar):
     ref = run(cf, wl, precision=precision, split=True)
     assert ref["advanced_cell_updates"] == ref["cell_updates"]
     for v in range(1, nvar + 1):
+        print(f"[variant] {v}", flush=True)
         r = run(cf, wl, precision=precision, tile_variant=v)
         assert r["fused"] and r["tile_variant"] == v
         np.testing.assert_array_equal(r["per_channel"], ref["per_channel"])
