@@ -735,6 +735,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--stencil-only", action="store_true",
+                    help="only the sampled-timing solve of the headline workload (its launches run one at a "
+                         "time on one stream): the command for kernel traces of the dominant kernel")
     ap.add_argument("--main-only", action="store_true",
                     help="only the headline solve and its stencil timing (for counter runs)")
     ap.add_argument("--tile-variant", type=int, default=0,
@@ -837,6 +840,12 @@ def main():
     log(f"[bench] {wl.name}: {info['n_channels']} channels, {wl.n_cells} cells, T={wl.n_steps}, "
         f"workspace {info['workspace_bytes'] / 2**20:.1f} MiB")
 
+    if args.stencil_only:
+        rt = prob.solve(workspace=ws, time_stencil=True, **opts)
+        print(json.dumps({"workload": wl.name, "tile_variant": rt["tile_variant"],
+                          "avg_launch_ms": rt["stencil_ms_avg"], "launches_timed": rt["stencil_samples"],
+                          "launches": rt["stencil_launches"], "device_ms": rt["device_ms"]}), flush=True)
+        return
     for w in range(args.warmup):
         r = prob.solve(workspace=ws, **opts)
         log(f"[bench] warmup {w}: force {r['force']:.10e} device {r['device_ms']:.1f} ms")
@@ -884,7 +893,15 @@ def main():
                 "kernel": "k_rb2d: fused register-blocked 2D update of all TM (or TE) channels, "
                           "steps_per_launch time steps per launch",
                 "avg_launch_ms": rt["stencil_ms_avg"], "launches_timed": rt["stencil_samples"],
-                "tile_variant": rt["tile_variant"], "steps_per_launch": rt["tile_halo"]}
+                "tile_variant": rt["tile_variant"], "steps_per_launch": rt["tile_halo"],
+                "launches_per_solve": rt["stencil_launches"],
+                # the timed solves run the TM and the TE launches on two streams, so that
+                # each polarization's launch tail overlaps the other's; over a whole solve
+                # the VALU issue rate is (instructions per launch x launches) / device time
+                "solve_valu_frac": (valu * rt["stencil_launches"] / (r["device_ms"] * 1e-3) / VALU_PEAK_WAVE_INSTR
+                                    if valu and r["device_ms"] > 0 else None),
+                "solve_valu_note": "per-launch figures (frac, traffic) come from a solve whose launches run "
+                                   "one at a time (launch sampling turns the two streams off)"}
 
     out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
