@@ -786,9 +786,9 @@ struct SideStreams {
     std::vector<hipStream_t> s;
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> join;
-    hipError_t open(hipStream_t main, int n) {
+    // n streams and their events (before any graph capture begins)
+    hipError_t create(int n) {
         hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventRecord(fork, main);
         for (int k = 0; k < n && e == hipSuccess; ++k) {
             hipStream_t x = nullptr;
             hipEvent_t j = nullptr;
@@ -798,8 +798,14 @@ struct SideStreams {
             e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
             if (e != hipSuccess) break;
             join.push_back(j);
-            e = hipStreamWaitEvent(x, fork, 0);
         }
+        return e;
+    }
+    // the streams start after everything issued on main so far (inside a
+    // capture this makes them branches of the graph)
+    hipError_t open(hipStream_t main) {
+        hipError_t e = hipEventRecord(fork, main);
+        for (size_t k = 0; k < s.size() && e == hipSuccess; ++k) e = hipStreamWaitEvent(s[k], fork, 0);
         return e;
     }
     hipError_t close(hipStream_t main) {
@@ -1415,11 +1421,12 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             int nw_tm = 0, nw_te = 0;
             STEP_OK(upload_inst(make_inst(pl, true)));
             // TM and TE channels, and channels among themselves, are
-            // independent runs: without graph capture, launch sampling or the
-            // convergence stop each polarization's channels go in kPolGroups
-            // groups, each with its own work list and stream, so that the tail
-            // of one group's launch overlaps the other groups' launches
-            const bool split_pol = !graph.on && !smp.on && !conv.on && w.n_tm > 0 && w.n_te > 0;
+            // independent runs: without launch sampling or the convergence
+            // stop each polarization's channels go in kPolGroups groups, each
+            // with its own work list and stream (a parallel branch of the graph
+            // when captured), so that the tail of one group's launch overlaps
+            // the other groups' launches
+            const bool split_pol = !smp.on && !conv.on && w.n_tm > 0 && w.n_te > 0;
             const int G = split_pol ? kPolGroups : 1;
             int gn[2][kPolGroups] = {}, gw[2][kPolGroups] = {};
             size_t goff[2][kPolGroups] = {};
@@ -1443,11 +1450,12 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
             // cells the fused kernel skips are never written: both ping-pong
             // arrays start at zero there
             STEP_OK(hipMemsetAsync(ws + L.fields2, 0, field_bytes, s));
+            SideStreams side;
+            if (split_pol) STEP_OK(side.create(2 * G - 1));
             STEP_OK(graph.begin());
             const hipStream_t ls = graph.launch_stream(s);
-            SideStreams side;
-            if (split_pol) STEP_OK(side.open(s, 2 * G - 1));
-            const hipError_t body = [&]() -> hipError_t {
+            hipError_t fork_err = split_pol ? side.open(ls) : hipSuccess;
+            const hipError_t body0 = fork_err != hipSuccess ? fork_err : [&]() -> hipError_t {
                 int parity = 0;
                 for (int m = 0; m < o.n_steps; m += kh) {
                     const int ks = std::min(kh, o.n_steps - m);
@@ -1470,8 +1478,12 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
                 }
                 return hipSuccess;
             }();
+            hipError_t body = body0;
+            if (split_pol && !side.s.empty()) {
+                const hipError_t ec = side.close(ls);   // joins the branches before a capture ends
+                if (body == hipSuccess) body = ec;
+            }
             STEP_OK(graph.end(s, body));
-            if (split_pol) STEP_OK(side.close(s));
         } else if (three && st.f3d) {
             // fused 3D: one launch per step, ping-pong between the two field
             // (and psi) arrays; the surface is read from the array just written
@@ -1988,23 +2000,37 @@ cf_status run_batch(const BatchPlan& B, const BatchLayout& L, const cf_opts& o, 
             BSTEP(cf::launch_e2d<T>(CF_POL_TE, 1, A, dch, te, B.inst_te_n[i], g, lut, s));
         }
         int launches = 0;
+        // the TE launches on a second stream (a parallel branch of the graph
+        // when captured), so that each polarization's launch tail overlaps
+        // the other's
+        SideStreams side;
+        const bool split_pol = n_tm > 0 && n_te > 0 && !(o.flags & CF_FLAG_TIME_STENCIL);
+        if (split_pol) BSTEP(side.create(1));
         BSTEP(graph.begin());
         {
             const hipStream_t ls = graph.launch_stream(s);
-            const hipError_t body = [&]() -> hipError_t {
-                int parity = 0;
-                for (int m = 0; m < o.n_steps; m += kh) {
-                    hipError_t e = hipSuccess;
-                    if (n_tm) e = cf::launch_tb2d<T>(variant, CF_POL_TM, dch, dwork, nw_tm, dinst, kh, m, parity, ls);
-                    if (e == hipSuccess && n_te)
-                        e = cf::launch_tb2d<T>(variant, CF_POL_TE, dch, dwork + B.work_items, nw_te, dinst, kh, m,
-                                               parity, ls);
-                    if (e != hipSuccess) return e;
-                    launches += (n_tm > 0) + (n_te > 0);
-                    parity ^= 1;
-                }
-                return hipSuccess;
-            }();
+            hipError_t body = split_pol ? side.open(ls) : hipSuccess;
+            if (body == hipSuccess)
+                body = [&]() -> hipError_t {
+                    const hipStream_t ts = split_pol ? side.s[0] : ls;
+                    int parity = 0;
+                    for (int m = 0; m < o.n_steps; m += kh) {
+                        hipError_t e = hipSuccess;
+                        if (n_tm)
+                            e = cf::launch_tb2d<T>(variant, CF_POL_TM, dch, dwork, nw_tm, dinst, kh, m, parity, ls);
+                        if (e == hipSuccess && n_te)
+                            e = cf::launch_tb2d<T>(variant, CF_POL_TE, dch, dwork + B.work_items, nw_te, dinst, kh, m,
+                                                   parity, ts);
+                        if (e != hipSuccess) return e;
+                        launches += (n_tm > 0) + (n_te > 0);
+                        parity ^= 1;
+                    }
+                    return hipSuccess;
+                }();
+            if (split_pol && !side.s.empty()) {
+                const hipError_t ec = side.close(ls);   // joins the branch before the capture ends
+                if (body == hipSuccess) body = ec;
+            }
             BSTEP(graph.end(s, body));
         }
         timing->launches = launches;
