@@ -163,6 +163,10 @@ struct cf_server {
     std::vector<hipEvent_t> ev;
     size_t n_marks = 0;
     double group_s = 0;
+    // second stream for the TE launches of the fused group (forked from and
+    // joined back to the server's stream every tick); default priority
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     std::deque<std::vector<cf::ChanDev>> keep_ch;
     std::deque<std::vector<cf::InstDev>> keep_inst;
     std::deque<std::vector<cf::WorkItem>> keep_work;
@@ -539,10 +543,23 @@ hipError_t tick(cf_server* S) {
         const cf::ChanDev* gch = reinterpret_cast<const cf::ChanDev*>(S->group + S->g_ch);
         const cf::InstDev* gin = reinterpret_cast<const cf::InstDev*>(S->group + S->g_inst);
         const cf::WorkItem* gw = reinterpret_cast<const cf::WorkItem*>(S->group + S->g_work);
+        // TM and TE launches on two streams: each polarization's launch tail
+        // overlaps the other's (the requests' channels are independent runs)
+        bool any_te = false, any_tm = false;
+        for (const auto& l : S->launches) (l.pol == CF_POL_TE ? any_te : any_tm) = true;
+        const bool split = any_te && any_tm && S->side;
+        if (split) {
+            if ((e = hipEventRecord(S->fork, s)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(S->side, S->fork, 0)) != hipSuccess) return e;
+        }
         for (const auto& l : S->launches)
             if ((e = cf::launch_tb2d<T>(l.variant, l.pol, gch, gw + l.off, l.n, gin, S->kh, (int)S->clock,
-                                        S->parity, s)) != hipSuccess)
+                                        S->parity, split && l.pol == CF_POL_TE ? S->side : s)) != hipSuccess)
                 return e;
+        if (split) {
+            if ((e = hipEventRecord(S->join, S->side)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s, S->join, 0)) != hipSuccess) return e;
+        }
     }
     if ((e = mark()) != hipSuccess) return e;
     for (auto& rp : S->active) {
@@ -930,6 +947,10 @@ static cf_status cf_server_create_impl(size_t hbm_budget_bytes, int precision, i
         if (hipStreamCreate(&S->stream) != hipSuccess) return fail(CF_E_DEVICE, "hipStreamCreate failed");
         S->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&S->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&S->join, hipEventDisableTiming) != hipSuccess)
+        return fail(CF_E_DEVICE, "server stream setup failed");
     cf_server* raw = S.get();
     if (precision == CF_FP64) S->worker = std::thread([raw] { loop<double>(raw); });
     else S->worker = std::thread([raw] { loop<float>(raw); });
@@ -1097,6 +1118,12 @@ static cf_status cf_server_destroy_impl(cf_server* S) {
     if (S->worker.joinable()) S->worker.join();
     (void)hipStreamSynchronize(S->stream);
     for (hipEvent_t x : S->ev) (void)hipEventDestroy(x);
+    if (S->side) {
+        (void)hipStreamSynchronize(S->side);
+        (void)hipStreamDestroy(S->side);
+    }
+    if (S->fork) (void)hipEventDestroy(S->fork);
+    if (S->join) (void)hipEventDestroy(S->join);
     if (S->own_stream) (void)hipStreamDestroy(S->stream);
     if (S->own_arena) (void)hipFree(S->group);
     delete S;
