@@ -32,6 +32,8 @@ from .configs import (
     cyl_piston,
     c_cyl_piston,
     dielectric_piston2d,
+    slabs_open_1d,
+    waveguides_open_2d,
     kz_workload,
     kz_gauss,
     small_cases,
@@ -56,6 +58,8 @@ __all__ = [
     "cyl_piston",
     "c_cyl_piston",
     "dielectric_piston2d",
+    "slabs_open_1d",
+    "waveguides_open_2d",
     "kz_workload",
     "kz_gauss",
     "small_cases",

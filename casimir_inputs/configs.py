@@ -305,6 +305,74 @@ def dielectric_piston2d(nx: int, ny: int, slab_px: int, block_w: int, block_h: i
                       meta=dict(wl.meta, eps_block=float(eps_block)))
 
 
+def slabs_open_1d(res: int, a_u: float, d_u: float, pad_u: float, pml_u: float, eps_inf: float,
+                  poles=(), margin: int = 2, ny: int = 1, **opts) -> Workload:
+    """Two identical dielectric slabs (thickness d_u, permittivity eps_inf
+    plus the Lorentz terms ``poles`` = ((d_eps, omega_0), ...)) a vacuum gap
+    a_u apart in open space: pad_u of vacuum on either side, then a CPML of
+    pml_u along x; translation invariant along y (periodic, ny cells).  S is
+    two full-width lines around the right slab, in the vacuum.  The geometry
+    of Sec. III B's dispersive example reduced to one dimension (slabs in
+    place of the two waveguides)."""
+    P = int(round(pml_u * res))
+    pad = int(round(pad_u * res))
+    d = int(round(d_u * res))
+    a = int(round(a_u * res))
+    if margin >= a or margin >= pad:
+        raise ValueError("the stress surface needs vacuum on both sides of the slab")
+    x1 = P + pad                 # left slab [x1, x1 + d)
+    x2 = x1 + d + a              # right slab [x2, x2 + d)
+    nx = x2 + d + pad + P
+    prims = [Box((x1, -BIG, -BIG), (x1 + d, BIG, BIG), 1), Box((x2, -BIG, -BIG), (x2 + d, BIG, BIG), 1)]
+    ids = rasterize((nx, ny, 1), prims)
+    lor = {1: tuple((float(de), float(w0)) for de, w0 in poles)} if poles else {}
+    kw = dict(sigma=1.0, courant=0.5, n_steps=2000, pol="3D", kernel="general", precision="fp64")
+    kw.update(opts)
+    return Workload(
+        name=kw.pop("name", f"slabs_open_{nx}x{ny}"), ndim=2, shape=(nx, ny, 1), res=float(res),
+        bc=("pml", "periodic", "periodic"), pml_cells=(P, 0, 0), eps=[1.0, float(eps_inf)], mu=[1.0, 1.0],
+        comp_ids=ids, s_lo=(x2 - margin, 0, 0), s_hi=(x2 + d + margin, ny, 1), n_harm=max(1, ny),
+        force_axis=0, lorentz=lor, meta=dict(a_px=a, d_px=d, pad_px=pad, pml_px=P, slabs=((x1, x1 + d), (x2, x2 + d))),
+        **kw,
+    )
+
+
+def waveguides_open_2d(res: int, w_u: float, t_u: float, gap_u: float, pad_u: float, pml_u: float,
+                       eps_inf: float, poles=(), n_harm: int = 8, margin: int = 2, **opts) -> Workload:
+    """Sec. III B's dispersive example: two identical dielectric waveguides
+    of rectangular cross-section (w_u along x, t_u along y) side by side, a
+    vacuum gap gap_u apart along x, in open space (pad_u of vacuum around
+    them, then a CPML of pml_u on all four sides).  Permittivity eps_inf plus
+    the Lorentz terms ``poles``.  S is the right waveguide grown by
+    ``margin`` cells; the force is along x.  Solved as a k_z problem (the
+    dielectrics hybridize the two polarizations)."""
+    P = int(round(pml_u * res))
+    pad = int(round(pad_u * res))
+    w = int(round(w_u * res))
+    t = int(round(t_u * res))
+    gap = int(round(gap_u * res))
+    if 2 * margin >= gap or margin >= pad:
+        raise ValueError("the stress surface needs vacuum around the waveguide")
+    x1 = P + pad
+    x2 = x1 + w + gap
+    nx = x2 + w + pad + P
+    y0 = P + pad
+    ny = y0 + t + pad + P
+    prims = [Box((x1, y0, -BIG), (x1 + w, y0 + t, BIG), 1), Box((x2, y0, -BIG), (x2 + w, y0 + t, BIG), 1)]
+    ids = rasterize((nx, ny, 1), prims)
+    lor = {1: tuple((float(de), float(w0)) for de, w0 in poles)} if poles else {}
+    kw = dict(sigma=1.0, courant=0.5, n_steps=2000, pol="3D", kernel="general", precision="fp64")
+    kw.update(opts)
+    return Workload(
+        name=kw.pop("name", f"waveguides_open_{nx}x{ny}"), ndim=2, shape=(nx, ny, 1), res=float(res),
+        bc=("pml", "pml", "periodic"), pml_cells=(P, P, 0), eps=[1.0, float(eps_inf)], mu=[1.0, 1.0],
+        comp_ids=ids, s_lo=(x2 - margin, y0 - margin, 0), s_hi=(x2 + w + margin, y0 + t + margin, 1),
+        n_harm=int(n_harm), force_axis=0, lorentz=lor,
+        meta=dict(guides=((x1, x1 + w), (x2, x2 + w)), guide_y=(y0, y0 + t), pml_px=P),
+        **kw,
+    )
+
+
 def small_cases():
     """Small workloads the oracle finishes in seconds (parity test sizes)."""
     return {

@@ -31,6 +31,16 @@ includes the 1/pi).
 
 Stability: the k terms raise the scheme's largest frequency; the Courant
 number must stay below 2 / sqrt(8 + (k dx)^2) / v_max (kz_courant_limit).
+
+Open space and dispersion (Sec. III B's waveguides): KzSim inherits the
+CPML of YeeSim on any in-plane axis whose boundary is "pml" (the k terms
+are not differences and take no stretching) and the Lorentz polarizations
+of dispersive materials on all three E components (the ADE is local and
+linear, so the factor i carried by e_z carries over to its polarization).
+
+Parity: pinned (tests/test_oracle_kz.py; tests/test_oracle_kz_open.py:
+dispersive slabs in open space against the Lifshitz force at each k, and
+the in-plane CPML against a large PEC box).
 """
 from __future__ import annotations
 
@@ -57,9 +67,13 @@ class KzSim(YeeSim):
     """YeeSim on a 2D grid with all six components and the k couplings."""
 
     def __init__(self, wl, kind: str, n_channels: int, k: float, sigma: float = None, courant: float = None):
+        self.k = float(k)                   # before the base class checks the Lorentz stability
         super().__init__(wl, kind, n_channels, ("x", "y", "z"), ("x", "y", "z"), sigma, courant)
-        self.k = float(k)
         self.kd = self.k * self.dx          # k in the undivided form of the curls
+
+    def curl_bound(self) -> float:
+        """(K dx)^2 bound: the in-plane 8 plus (k dx)^2."""
+        return 8.0 + (self.k / self.wl.res) ** 2
 
     def curl_e(self, a: str) -> np.ndarray:
         out = super().curl_e(a)

@@ -60,8 +60,10 @@ lossless.  Discretized with centred differences at the E time levels,
 
 i.e. E^{m+1} = a E^m + b curl H - (sum P^{m+1} - a sum P^m) / eps_inf with
 the non-dispersive a, b of eps_inf.  P starts at zero: the kicks sit on S,
-which must lie in a non-dispersive medium.  Stable for w0 dt < 2 (with the
-Yee limit taken at eps_inf).
+which must lie in a non-dispersive medium.  Stable when w0 dt < 2 for every
+term and the coupled field-polarization frequency of the fastest grid mode
+stays below 2 / dt (lorentz_stable; a strong term such as silicon's raises
+that frequency well above the plain Yee limit at eps_inf).
 
 CPML (Roden-Gedney, kappa = 1, alpha = 0) along any axis whose boundary is
 "pml": every difference along that axis inside the layer becomes D + psi with
@@ -126,6 +128,26 @@ def pml_profile(n: int, P: int, dx: float, dt: float, half: bool):
     sig = smax * (depth / P) ** PML_ORDER
     b = np.exp(-sig * dt)
     return b, b - 1.0
+
+
+def lorentz_stable(eps_inf: float, mu: float, terms, courant: float, dx: float, curl_bound: float) -> bool:
+    """Stability of the centred Lorentz scheme in a uniform medium.  A plane
+    wave z^m with Omega^2 = (4 / dt^2) sin^2(omega dt / 2) and spatial
+    curl-curl eigenvalue K^2 / mu satisfies
+        Omega^2 (eps_inf + sum d_eps w0^2 / (w0^2 - Omega^2)) = K^2 / mu;
+    it is stable when every root Omega^2 stays at or below X = 4 / dt^2.
+    Above the largest w0^2 the left side minus the right increases with
+    Omega^2, so the condition is w0 dt < 2 for every term and
+        f(X) = eps_inf X - K_max^2 / mu + sum d_eps w0^2 X / (w0^2 - X) > 0,
+    with K_max^2 = curl_bound / dx^2 (evaluated here in units of dx^2)."""
+    X = 4.0 / (courant * courant)
+    f = eps_inf * X - curl_bound / mu
+    for de, w0 in terms:
+        w2 = (w0 * dx) ** 2
+        if w2 * courant * courant >= 4.0:
+            return False
+        f += de * w2 * X / (w2 - X)
+    return f > 0.0
 
 
 class YeeSim:
@@ -224,6 +246,18 @@ class YeeSim:
             e_inf = np.where(live, eps[ids], 1.0)
             self.poles[a] = (terms, e_inf)
             self.P[a] = [[np.zeros(self.E[a].shape), np.zeros(self.E[a].shape)] for _ in terms]
+        mu = np.asarray(wl.mu, dtype=np.float64)
+        for k, v in lor.items():
+            if not np.isfinite(eps[k]) or not np.isfinite(mu[k]):
+                continue
+            if not lorentz_stable(eps[k], mu[k], v, self.courant, self.dx, self.curl_bound()):
+                raise ValueError("Lorentz medium unstable at this time step: the coupled field and "
+                                 "polarization frequency exceeds 2 / dt (lower the Courant number)")
+
+    def curl_bound(self) -> float:
+        """Upper bound of the undivided curl-curl eigenvalue, (K dx)^2, of the
+        grid: 4 per axis along which the fields vary."""
+        return 4.0 * self.wl.ndim
 
     def _pml_setup(self):
         wl = self.wl

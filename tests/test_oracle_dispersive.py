@@ -260,3 +260,61 @@ def test_unstable_term_and_dispersive_surface_refused():
     # the medium around S made dispersive
     with pytest.raises(ValueError):
         oracle.solve(wl.replace(lorentz={0: ((1.0, 2.0),)}))
+
+
+def _uniform_lorentz_box(courant, eps_inf, terms, n=16, res=20.0, pol="TM"):
+    from casimir_inputs.geometry import Workload, rasterize
+    ids = rasterize((n, n, 1), [])
+    return Workload(name="medium", ndim=2, shape=(n, n, 1), res=res, bc=("periodic", "periodic", "periodic"),
+                    pml_cells=(0, 0, 0), eps=[eps_inf], mu=[1.0], comp_ids=ids, s_lo=(4, 4, 0), s_hi=(8, 8, 1),
+                    n_harm=1, force_axis=0, sigma=0.0, courant=courant, pol=pol, kernel="general",
+                    lorentz={0: tuple(terms)})
+
+
+@pytest.mark.parametrize("k", [None, 15.0], ids=["2d", "kz"])
+def test_coupled_lorentz_stability_limit(monkeypatch, k):
+    """A strong term (silicon's d_eps = 10.835 on eps_inf = 1.035, w0 dx =
+    1.1) is unstable well inside the plain Yee limit at eps_inf and far
+    below w0 dt = 2: the field-polarization coupling raises the fastest
+    grid mode's frequency.  The criterion oracle.yee.lorentz_stable (with
+    the curl-curl bound 8 + (k dx)^2 of the grid) separates growth from
+    boundedness of random fields in a uniform periodic medium to 2 %, and
+    the oracle refuses a step above it."""
+    import oracle.yee as Y
+    from oracle import kz
+    eps_inf, terms, res = 1.035, ((10.835, 22.0),), 20.0
+    bound = 8.0 + ((k or 0.0) / res) ** 2
+    lo, hi = 0.01, 0.7
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if Y.lorentz_stable(eps_inf, 1.0, terms, mid, 1.0 / res, bound) else (lo, mid)
+    c_star = lo
+    yee_limit = np.sqrt(eps_inf / 2.0)                    # courant * sqrt(2) / sqrt(eps_inf) < 1
+    assert c_star < 0.65 * yee_limit                       # well inside the Yee limit at eps_inf
+    assert c_star * 22.0 / res < 0.5                                      # and far below w0 dt = 2
+
+    def make(c):
+        wl = _uniform_lorentz_box(c, eps_inf, terms, res=res, pol="TM" if k is None else "3D")
+        if k is None:
+            return YeeSim(wl, "E", 1, ("z",), ("x", "y"))
+        return kz.KzSim(wl, "E", 1, k)
+
+    with pytest.raises(ValueError):
+        make(1.02 * c_star)
+    make(0.98 * c_star)                                    # accepted
+    monkeypatch.setattr(Y, "lorentz_stable", lambda *a: True)
+
+    def peak(c):
+        S = make(c)
+        rng = np.random.default_rng(3)
+        for f in (S.E, S.H):
+            for a in f:
+                f[a] = rng.standard_normal(f[a].shape)
+        with np.errstate(all="ignore"):
+            for _ in range(3000):
+                S.step()
+        v = max(np.abs(S.E[a]).max() for a in S.E)
+        return v if np.isfinite(v) else np.inf
+
+    assert peak(0.98 * c_star) < 20.0
+    assert peak(1.02 * c_star) > 1e6
