@@ -57,7 +57,14 @@ typedef enum {
     CF_E_UNSUPPORTED = 8  /* option combination not implemented                  */
 } cf_status;
 
-/* Boundary per axis (both ends of the axis). */
+/* Boundary per axis (both ends of the axis).  CF_BC_PML: a CPML
+ * (Roden-Gedney, polynomial order 3, R0 = 1e-8, kappa = 1, alpha = 0) of
+ * pml_cells cells inside the grid at both ends, backed by a PEC wall
+ * (Sec. III B: open space around the bodies).  3D grids take it along z;
+ * Cartesian 2D and k_z problems along x and/or y (split half-step kernels:
+ * the fused and resident kernels carry no CPML); cylindrical problems not
+ * at all (CF_E_ARG at creation).  The kick and the consistent start stretch
+ * their differences inside a layer as every later step does. */
 enum { CF_BC_PEC = 0, CF_BC_PERIODIC = 1, CF_BC_PML = 2 };
 /* Polarizations: 2D runs take CF_POL_TM, CF_POL_TE or both OR-ed; 3D runs CF_POL_3D. */
 enum { CF_POL_TM = 1, CF_POL_TE = 2, CF_POL_3D = 4 };
@@ -160,11 +167,18 @@ typedef struct cf_materials {
      * polarization P with P'' + sigma P' + w0^2 P = d_eps w0^2 E, and
      * D = eps[id] E + sum P carries the conductivity of E-current runs.
      * n_lorentz = 0 (or NULL arrays): no dispersion.  Limits: Cartesian 2D
-     * problems only (else CF_E_UNSUPPORTED at validation); S must lie in a
-     * non-dispersive medium (CF_E_SURFACE); w0 dt < 2 for every term
-     * (CF_E_CFL); at most 4 terms per material.  Dispersive problems run on
-     * the split half-step kernels (the fused kernel does not take them) and
-     * are not served (CF_E_UNSUPPORTED). */
+     * and k_z problems only (3D and cylindrical: CF_E_UNSUPPORTED at
+     * validation); S must lie in a non-dispersive medium (CF_E_SURFACE); at
+     * most 4 terms per material.  Stability (CF_E_CFL otherwise): w0 dt < 2
+     * for every term, and the fastest grid mode of the coupled field and
+     * polarizations stays below 2 / dt:
+     *   eps X - K^2 / mu + sum_j d_eps_j w0_j^2 X / (w0_j^2 - X) > 0,
+     * X = 4 / dt^2, K^2 = (8 + (k_max dx)^2) / dx^2 in 2D (k_max: the largest
+     * |k_z| of a k_z problem), for each dispersive material (eps, mu); a
+     * strong term lowers the stable Courant number well below the Yee limit
+     * at eps.  Dispersive problems run on the split half-step kernels (the
+     * fused and resident kernels do not take them) and are not served
+     * (CF_E_UNSUPPORTED). */
     int n_lorentz;
     const double* lorentz_deps;
     const double* lorentz_w0;
@@ -411,8 +425,8 @@ const char* cf_last_error(void);
  * Cylindrical and k_z requests (Sec. III B, III C: one launch runs every
  * step of a channel) run their whole solve as cf_solve in one tick, on
  * their region of the budget; the convergence stop is not available for
- * them.  Problems with dispersive materials are not served
- * (CF_E_UNSUPPORTED).
+ * them.  Problems with dispersive materials, and Cartesian 2D problems
+ * with in-plane PML layers, are not served (CF_E_UNSUPPORTED).
  * A request's arithmetic does not depend on what else is resident: a result
  * is bitwise the same alone and in any mix, and equals cf_solve with the
  * same options and tile_variant (fused 2D and 3D) or CF_FLAG_SPLIT (wider

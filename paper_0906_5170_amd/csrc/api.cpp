@@ -66,7 +66,7 @@ bool g_tune_loaded = false;
 // Device workspace layout of one solve.
 struct Layout {
     size_t ids, lut, ktab, pml, chans, slots, gidx, gw, uidx, uoff, usamp, uw, basis, acc, gamma,
-        fields, fields2, psi, psi2, idp, shadow, rinv, inst, work, aux, lor, zr, total;
+        fields, fields2, psi, psi2, pml2, idp, shadow, rinv, inst, work, aux, lor, zr, total;
     size_t work_items;    // capacity of one work list
 };
 
@@ -278,6 +278,15 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
     st.resident = std::max(st.resident, 1);
     const int P = p.grid.ndim == 3 && p.grid.bc[2] == CF_BC_PML ? p.grid.pml_cells[2] : 0;
     st.psi_comp = (int64_t)2 * P * p.nx * p.ny;
+    st.psi_block = 4 * st.psi_comp;
+    if (p.grid.ndim == 2) {
+        // in-plane CPML (split kernels): an x and a y layer array per field slot
+        const int px = p.grid.bc[0] == CF_BC_PML ? p.grid.pml_cells[0] : 0;
+        const int py = p.grid.bc[1] == CF_BC_PML ? p.grid.pml_cells[1] : 0;
+        st.pml2d = px > 0 || py > 0;
+        st.psi2d_slot = (int64_t)p.ny * 2 * px + (int64_t)2 * py * p.nx;
+        st.psi_block = st.pml2d ? (int64_t)st.ncomp * st.psi2d_slot : 0;
+    }
     // concatenated gather / scatter tables for every (face, comp) pair used
     std::vector<int> g_goff(p.gathers.size(), -1), g_uoff(p.gathers.size(), -1);
     auto add_gather = [&](int gi) {
@@ -304,7 +313,8 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
     // waves: consecutive runs of `resident` channels; the split cylindrical
     // path groups the channels by azimuthal order first (one order per wave),
     // the resident cylindrical kernel takes any mix of orders
-    st.red_res = p.reduced() && !plain && !(o.flags & CF_FLAG_SPLIT);
+    // the resident reduced kernels carry no CPML and no polarizations
+    st.red_res = p.reduced() && !plain && !(o.flags & CF_FLAG_SPLIT) && !p.dispersive && !st.pml2d;
     std::vector<std::vector<int>> wave_lists;
     std::vector<int> wave_order;
     {
@@ -326,8 +336,10 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
     std::vector<int> block_of(C, 0);
     for (const auto& wl : wave_lists)
         for (size_t k = 0; k < wl.size(); ++k) block_of[wl[k]] = (int)k;
-    // dispersive media: (P^m, P^{m-1}) per E slot (two, the TE count) and term
-    st.aux_block = p.dispersive ? (int64_t)2 * p.n_lor * 2 * p.ncell : 0;
+    // dispersive media: (P^m, P^{m-1}) per E slot (Cartesian: two, the TE
+    // count; k_z runs: three per part) and term
+    const int e_slots = p.reduced() ? 3 * (p.bloch ? 2 : 1) : 2;
+    st.aux_block = p.dispersive ? (int64_t)e_slots * p.n_lor * 2 * p.ncell : 0;
     const double res = p.grid.res;
     for (int c = 0; c < C; ++c) {
         const cf::Channel& ch = chans[c];
@@ -338,7 +350,7 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         const int blk = block_of[c];
         cf::ChanDev d{};
         d.field_off = (int64_t)blk * st.ncomp * p.ncell;
-        d.psi_off = (int64_t)blk * 4 * st.psi_comp;
+        d.psi_off = (int64_t)blk * st.psi_block;
         d.aux_off = (int64_t)blk * st.aux_block;
         d.src_off = d.field_off + (int64_t)cf::comp_slot(ch.pol, ch.src) * p.ncell;
         d.meas_off = d.field_off + (int64_t)cf::comp_slot(ch.pol, ch.meas) * p.ncell;
@@ -414,9 +426,9 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
         if (st.v3d >= 0 && cf::f3d_steps(st.v3d) == 2 && st.sbox.vol <= 0) st.v3d = cf::f3d_single(st.v3d);
         if (st.f3d) stage_zranges(p, st);
     }
-    // the fused kernel carries no polarizations: dispersive problems take the
-    // split half-step kernels
-    if (!plain && p.grid.ndim == 2 && !(o.flags & CF_FLAG_SPLIT) && !p.dispersive) {
+    // the fused kernel carries no polarizations and no CPML: dispersive
+    // problems and problems with in-plane layers take the split kernels
+    if (!plain && p.grid.ndim == 2 && !(o.flags & CF_FLAG_SPLIT) && !p.dispersive && !st.pml2d) {
         cf::TBShape sh[cf::kMaxVariants];
         const int nv = o.precision == CF_FP64 ? cf::tb_variants<double>(sh, cf::kMaxVariants)
                                               : cf::tb_variants<float>(sh, cf::kMaxVariants);
@@ -672,7 +684,8 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.gamma = (o.flags & CF_FLAG_KEEP_GAMMA) ? take((size_t)t_max * C * 8) : off;
     L.fields = take(block);
     L.fields2 = st.variant >= 0 || st.f3d ? take(block) : off;
-    L.psi = st.psi_comp > 0 ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
+    L.psi = st.psi_block > 0 ? take((size_t)st.resident * st.psi_block * fsz) : off;
+    L.pml2 = st.pml2d ? take((size_t)4 * (p.nx + p.ny) * 8) : off;
     L.psi2 = st.psi_comp > 0 && st.f3d ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
     L.idp = st.f3d ? take((size_t)p.ncell * 8) : st.red_res ? take((size_t)p.ncell * 4) : off;
     L.shadow = st.f3d && st.sbox.vol > 0 ? take((size_t)st.resident * st.sbox.vol * fsz) : off;
@@ -836,6 +849,23 @@ struct SideStreams {
 // steps.  Split path (CF_FLAG_SPLIT, plain): waves of one order each; per
 // wave clear, kick, consistent start, then per step the H and E half steps
 // and the surface projection with the g-weighted accumulation.
+// In-plane CPML of a 2D problem (split kernels): uploads the x and y
+// profiles for the run's time step and points the grid at them and at the
+// psi blocks.  tab holds the host copy until the solve has synchronized.
+hipError_t set_pml2d(const cf::Problem& p, const cf_opts& o, const Staged& st, const Layout& L, char* ws,
+                     hipStream_t s, cf::Grid2D& g, std::vector<double>& tab) {
+    tab.clear();
+    for (int a = 0; a < 2; ++a) {
+        const size_t at = tab.size();
+        cf::pml_axis_tables(p, a, o.courant, tab);
+        g.pml[a] = tab.size() > at ? p.grid.pml_cells[a] : 0;
+        g.pml_tab[a] = reinterpret_cast<const double*>(ws + L.pml2) + at;
+    }
+    g.psi = ws + L.psi;
+    g.psi_slot = st.psi2d_slot;
+    return hipMemcpyAsync(ws + L.pml2, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s);
+}
+
 template <typename T>
 cf_status run_reduced(const cf::Problem& p, const cf_opts& o, const Staged& st, const Layout& L, char* ws,
                   hipStream_t s, std::vector<double>& acc_out, std::vector<double>& gamma_out, double* device_ms,
@@ -886,6 +916,18 @@ cf_status run_reduced(const cf::Problem& p, const cf_opts& o, const Staged& st, 
     g.perx = p.grid.bc[0] == CF_BC_PERIODIC;
     g.pery = p.grid.bc[1] == CF_BC_PERIODIC;   // k_z problems only (the tube wall is PEC)
     for (int c = 0; c < cf::kNumComp; ++c) g.ids[c] = dids + (size_t)c * p.ncell;
+    std::vector<double> lor;
+    if (p.dispersive) {   // k_z runs (split kernels); every order shares the Courant number
+        lor = lorentz_table(p, o.sigma, o.courant);
+        CF_HIP(up(L.lor, lor.data(), lor.size() * 8));
+        g.n_lor = p.n_lor;
+        g.lor = reinterpret_cast<const double*>(ws + L.lor);
+        g.aux = ws + L.aux;
+    }
+    std::vector<double> pml2_host;
+    if (st.pml2d) CF_HIP(set_pml2d(p, o, st, L, ws, s, g, pml2_host));
+    const size_t aux_bytes = (size_t)st.resident * st.aux_block * sizeof(T);
+    const size_t psi_bytes = (size_t)st.resident * st.psi_block * sizeof(T);
     const double dA = 1.0 / p.grid.res;       // line element of the two-dimensional plane
     const size_t field_bytes = (size_t)st.resident * st.ncomp * p.ncell * sizeof(T);
     const double state_bytes = 2.0 * st.ncomp * sizeof(T);
@@ -1021,6 +1063,8 @@ cf_status run_reduced(const cf::Problem& p, const cf_opts& o, const Staged& st, 
         const T* lut_m = dlut + m * lut_len;
         const double* k_m = dk + (size_t)m * t_max;
         STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));
+        if (psi_bytes) STEP_OK(hipMemsetAsync(ws + L.psi, 0, psi_bytes, s));
+        if (aux_bytes) STEP_OK(hipMemsetAsync(ws + L.aux, 0, aux_bytes, s));
         STEP_OK(cf::launch_kick<T>(fields, dch, sl, w.n_all, st.max_uniq, tabs, s));
         STEP_OK(cf::launch_hred<T>(1, ord.coup[m], ord.axis, fields, dch, sl, w.n_all, g, lut_m, drows, ord.ph_c[m],
                                    ord.ph_s[m], ord.cplx, s));
@@ -1137,7 +1181,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     }
 
     T* fields = reinterpret_cast<T*>(ws + L.fields);
-    T* psi = st.psi_comp > 0 ? reinterpret_cast<T*>(ws + L.psi) : nullptr;
+    T* psi = st.psi_block > 0 ? reinterpret_cast<T*>(ws + L.psi) : nullptr;
     const cf::ChanDev* dch = reinterpret_cast<const cf::ChanDev*>(ws + L.chans);
     const int* dslots = reinterpret_cast<const int*>(ws + L.slots);
     const T* dlut = reinterpret_cast<const T*>(ws + L.lut);
@@ -1166,6 +1210,8 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
         g.lor = reinterpret_cast<const double*>(ws + L.lor);
         g.aux = ws + L.aux;
     }
+    std::vector<double> pml2_host;
+    if (st.pml2d) CF_HIP(set_pml2d(p, o, st, L, ws, s, g, pml2_host));
     const size_t aux_bytes = (size_t)st.resident * st.aux_block * sizeof(T);
     cf::Grid3D g3{};
     g3.nx = p.nx;
@@ -1186,7 +1232,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     const double dt = o.courant / p.grid.res;
     const double dA = std::pow(1.0 / p.grid.res, p.grid.ndim - 1);
     const size_t field_bytes = (size_t)st.resident * st.ncomp * p.ncell * sizeof(T);
-    const size_t psi_bytes = (size_t)st.resident * 4 * st.psi_comp * sizeof(T);
+    const size_t psi_bytes = (size_t)st.resident * st.psi_block * sizeof(T);
     const double state_bytes = 2.0 * st.ncomp * sizeof(T);   // read + write of a cell's state
     const bool three = p.grid.ndim == 3;
 
@@ -2209,7 +2255,7 @@ static cf_status cf_batch_workspace_size_impl(cf_problem* const* probs, int n, c
     for (int i = 0; i < n; ++i) {
         cf_status st = cf_validate(probs[i], o);
         if (st != CF_OK) return st;
-        if (probs[i]->p.grid.ndim == 2 && !probs[i]->p.reduced() && !probs[i]->p.dispersive) fused.push_back(probs[i]);
+        if (probs[i]->p.fusable2d()) fused.push_back(probs[i]);
         size_t b = 0;
         cf_opts oo = *o;
         oo.n_subset = 0;
@@ -2320,7 +2366,7 @@ static cf_status cf_batch_solve_impl(cf_problem* const* probs, int n, const cf_o
     std::vector<int> fused_idx;
     if (!(o->flags & CF_FLAG_SPLIT))
         for (int i = 0; i < n; ++i)
-            if (probs[i]->p.grid.ndim == 2 && !probs[i]->p.reduced() && !probs[i]->p.dispersive)
+            if (probs[i]->p.fusable2d())
                 fused_idx.push_back(i);
     BatchPlan B;
     if (fused_idx.size() >= 1) {

@@ -13,7 +13,7 @@ namespace cf {
 // (uidx/uoff) and the basis table.
 struct ChanDev {
     int64_t field_off;   // first element of the channel's field block
-    int64_t psi_off;     // first element of the channel's CPML block (3D)
+    int64_t psi_off;     // first element of the channel's CPML block (3D; 2D split kernels)
     int32_t inst;        // instance of a fused launch
     int32_t pol;         // CF_POL_TM / CF_POL_TE / CF_POL_3D
     int32_t local;       // channel index within its instance (accumulator, Gamma column)
@@ -50,6 +50,17 @@ struct Grid2D {
     int n_lor;
     const double* lor;
     void* aux;
+    // CPML along x (axis 0) and y (axis 1), split kernels only: pml[a]
+    // layers at each end of axis a (0: none).  pml_tab[a] holds 4 rows of
+    // n_a values: b and c at the half-cell positions (H components), then b
+    // and c at the integer positions (E components).  psi (field precision,
+    // the channel's block at ChanDev.psi_off) holds per part (complex runs:
+    // real, imaginary) and per field slot s an x array of ny * 2 pml[0]
+    // values and a y array of 2 pml[1] * nx values; psi_slot is their sum.
+    int pml[2];
+    const double* pml_tab[2];
+    void* psi;
+    int64_t psi_slot;
 };
 constexpr int kLorStride(int n_lor) { return 2 + 3 * n_lor; }
 

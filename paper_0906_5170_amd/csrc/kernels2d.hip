@@ -40,6 +40,8 @@ __device__ __forceinline__ T yee_half(T b, T d) { return yee::half(b, d); }
 
 using yee::neumaier;
 using yee::block_surface_sum;
+using yee::lorentz_step;
+using yee::pml_d2;
 
 // ---------------------------------------------------------------------------
 // split half-step kernels (one launch per half step for a batch of channels)
@@ -66,12 +68,16 @@ __global__ __launch_bounds__(BX* BY) void k_h2d(T* __restrict__ fields, const Ch
         const T ezu = in_u ? Ez[c + g.nx] : (g.pery ? Ez[i] : T(0));
         const T* lx = lut_ab(lut, d.kind, CF_HX, g.ids[CF_HX][c]);
         const T* ly = lut_ab(lut, d.kind, CF_HY, g.ids[CF_HY][c]);
+        // the consistent start (MODE 1) stretches its curl in the CPML too
+        T* psi = g.psi ? static_cast<T*>(g.psi) + d.psi_off : nullptr;
+        const T dy = pml_d2(ezu - ez, g, psi, 1, 1, true, i, j);
+        const T dx = pml_d2(ezr - ez, g, psi, 2, 0, true, i, j);
         if (MODE == 0) {
-            Hx[c] = yee_sub(lx[0], Hx[c], lx[1], ezu - ez);
-            Hy[c] = yee_sub(ly[0], Hy[c], ly[1], ez - ezr);
+            Hx[c] = yee_sub(lx[0], Hx[c], lx[1], dy);
+            Hy[c] = yee_sub(ly[0], Hy[c], ly[1], -dx);
         } else {
-            Hx[c] = yee_half(lx[1], ezu - ez);
-            Hy[c] = yee_half(ly[1], ez - ezr);
+            Hx[c] = yee_half(lx[1], dy);
+            Hy[c] = yee_half(ly[1], -dx);
         }
     } else {
         const T* Ex = base;
@@ -80,36 +86,16 @@ __global__ __launch_bounds__(BX* BY) void k_h2d(T* __restrict__ fields, const Ch
         const T ex = Ex[c], ey = Ey[c];
         const T eyr = in_r ? Ey[c + 1] : (g.perx ? Ey[c + 1 - g.nx] : T(0));
         const T exu = in_u ? Ex[c + g.nx] : (g.pery ? Ex[i] : T(0));
-        const T curl = (eyr - ey) - (exu - ex);
         const T* lz = lut_ab(lut, d.kind, CF_HZ, g.ids[CF_HZ][c]);
+        T* psi = g.psi ? static_cast<T*>(g.psi) + d.psi_off : nullptr;
+        const T dx = pml_d2(eyr - ey, g, psi, 2, 0, true, i, j);
+        const T dy = pml_d2(exu - ex, g, psi, 2, 1, true, i, j);
         if (MODE == 0) {
-            Hz[c] = yee_sub(lz[0], Hz[c], lz[1], curl);
+            Hz[c] = yee_sub(lz[0], Hz[c], lz[1], dx - dy);
         } else {
-            Hz[c] = yee_half(lz[1], curl);
+            Hz[c] = yee_half(lz[1], dx - dy);
         }
     }
-}
-
-// Dispersive media: advances the Lorentz polarizations of one E component at
-// cell c (every term's pair P^m, P^{m-1} -> P^{m+1}, P^m, from E^m = e_old)
-// and returns (sum P^{m+1} - a sum P^m) / eps_inf, the amount the E update
-// of D = eps_inf E + sum P subtracts.  Zero for an id without terms.
-template <typename T>
-__device__ __forceinline__ T lorentz_step(const Grid2D& g, T* aux, int e_slot, int64_t c, int id, T a, T e_old) {
-    const double* row = g.lor + (size_t)id * kLorStride(g.n_lor);
-    if (row[0] == 0.0) return T(0);
-    T sum_now = T(0), sum_next = T(0);
-    for (int j = 0; j < g.n_lor; ++j) {
-        T* pc = aux + (int64_t)((e_slot * g.n_lor + j) * 2) * g.ncell + c;
-        T* pp = pc + g.ncell;
-        const T cur = *pc, prev = *pp;
-        const T nxt = fma(T(row[2 + 3 * j]), cur, fma(-T(row[3 + 3 * j]), prev, T(row[4 + 3 * j]) * e_old));
-        sum_now += cur;
-        sum_next += nxt;
-        *pp = cur;
-        *pc = nxt;
-    }
-    return (sum_next - a * sum_now) * T(row[1]);
 }
 
 template <typename T, int POL, int MODE>
@@ -131,16 +117,18 @@ __global__ __launch_bounds__(BX* BY) void k_e2d(T* __restrict__ fields, const Ch
         const T hx = Hx[c], hy = Hy[c];
         const T hyl = i > 0 ? Hy[c - 1] : (g.perx ? Hy[c - 1 + g.nx] : T(0));
         const T hxd = j > 0 ? Hx[c - g.nx] : (g.pery ? Hx[c + (int64_t)(g.ny - 1) * g.nx] : T(0));
-        const T curl = (hy - hyl) - (hx - hxd);
         const T* lz = lut_ab(lut, d.kind, CF_EZ, g.ids[CF_EZ][c]);
+        T* psi = g.psi ? static_cast<T*>(g.psi) + d.psi_off : nullptr;
+        const T dx = pml_d2(hy - hyl, g, psi, 0, 0, false, i, j);
+        const T dy = pml_d2(hx - hxd, g, psi, 0, 1, false, i, j);
         if (MODE == 0) {
             const T ez = Ez[c];
-            T e_new = yee_add(lz[0], ez, lz[1], curl);
+            T e_new = yee_add(lz[0], ez, lz[1], dx - dy);
             if (g.n_lor > 0)
                 e_new -= lorentz_step(g, static_cast<T*>(g.aux) + d.aux_off, 0, c, g.ids[CF_EZ][c], lz[0], ez);
             Ez[c] = e_new;
         } else {
-            Ez[c] = yee_half(lz[1], curl);
+            Ez[c] = yee_half(lz[1], dx - dy);
         }
     } else {
         T* Ex = base;
@@ -151,10 +139,13 @@ __global__ __launch_bounds__(BX* BY) void k_e2d(T* __restrict__ fields, const Ch
         const T hzl = i > 0 ? Hz[c - 1] : (g.perx ? Hz[c - 1 + g.nx] : T(0));
         const T* lx = lut_ab(lut, d.kind, CF_EX, g.ids[CF_EX][c]);
         const T* ly = lut_ab(lut, d.kind, CF_EY, g.ids[CF_EY][c]);
+        T* psi = g.psi ? static_cast<T*>(g.psi) + d.psi_off : nullptr;
+        const T dy = pml_d2(hz - hzd, g, psi, 0, 1, false, i, j);
+        const T dx = pml_d2(hz - hzl, g, psi, 1, 0, false, i, j);
         if (MODE == 0) {
             const T ex = Ex[c], ey = Ey[c];
-            T ex_new = yee_add(lx[0], ex, lx[1], hz - hzd);
-            T ey_new = yee_sub(ly[0], ey, ly[1], hz - hzl);
+            T ex_new = yee_add(lx[0], ex, lx[1], dy);
+            T ey_new = yee_sub(ly[0], ey, ly[1], dx);
             if (g.n_lor > 0) {
                 T* aux = static_cast<T*>(g.aux) + d.aux_off;
                 ex_new -= lorentz_step(g, aux, 0, c, g.ids[CF_EX][c], lx[0], ex);
@@ -163,8 +154,8 @@ __global__ __launch_bounds__(BX* BY) void k_e2d(T* __restrict__ fields, const Ch
             Ex[c] = ex_new;
             Ey[c] = ey_new;
         } else {
-            Ex[c] = yee_half(lx[1], hz - hzd);
-            Ey[c] = -yee_half(ly[1], hz - hzl);
+            Ex[c] = yee_half(lx[1], dy);
+            Ey[c] = -yee_half(ly[1], dx);
         }
     }
 }

@@ -45,10 +45,11 @@ __device__ __forceinline__ int pml_plane(int k, int nz, int P) {
 }
 
 // z difference with the CPML update: psi <- b psi + c D, returns D + psi.
-// In start mode (mode 1) psi is not advanced: the layers hold zero fields.
+// The consistent start (mode 1) advances psi too: its partner field is set
+// from the stretched curl, and the first step stretches it again.
 template <typename T, int MODE>
 __device__ __forceinline__ T zdiff(T D, T* psi, int64_t at, T b, T c) {
-    if (MODE == 1 || psi == nullptr) return D;
+    if (psi == nullptr) return D;
     const T p = fma(b, psi[at], c * D);
     psi[at] = p;
     return D + p;

@@ -149,6 +149,39 @@ __device__ __forceinline__ void e_values(T& ex, T& ey, T& ez, T hx, T hy, T hz, 
     }
 }
 
+// The k_z forms (no cylindrical weights) with the in-plane differences
+// passed in, as the CPML stretches them (split kernels only): the same
+// operations as h_values / e_values with CYL = false (MODE 0 the step,
+// MODE 1 the consistent start).
+template <typename T, int MODE>
+__device__ __forceinline__ void h_values_kz(T& hx, T& hy, T& hz, T ex, T ey, T dy_ez, T dx_ez, T dx_ey, T dy_ex,
+                                            const T* lx, const T* ly, const T* lz, T M) {
+    const T cz = dy_ez - M * ey, cr = M * ex - dx_ez, cp = dx_ey - dy_ex;
+    if (MODE == 0) {
+        hx = yee::sub(lx[0], hx, lx[1], cz);
+        hy = yee::sub(ly[0], hy, ly[1], cr);
+        hz = yee::sub(lz[0], hz, lz[1], cp);
+    } else {
+        hx = yee::half(lx[1], cz);
+        hy = yee::half(ly[1], cr);
+        hz = yee::half(lz[1], cp);
+    }
+}
+template <typename T, int MODE>
+__device__ __forceinline__ void e_values_kz(T& ex, T& ey, T& ez, T hx, T hy, T dy_hz, T dx_hz, T dx_hy, T dy_hx,
+                                            const T* lx, const T* ly, const T* lz, T M) {
+    const T cz = dy_hz + M * hy, cr = -(M * hx) - dx_hz, cp = dx_hy - dy_hx;
+    if (MODE == 0) {
+        ex = yee::add(lx[0], ex, lx[1], cz);
+        ey = yee::add(ly[0], ey, ly[1], cr);
+        ez = yee::add(lz[0], ez, lz[1], cp);
+    } else {
+        ex = yee::half(lx[1], cz);
+        ey = yee::half(ly[1], cr);
+        ez = yee::half(lz[1], cp);
+    }
+}
+
 // Reduced-update parameters of one run: coupling M, the row factors and,
 // for complex (Bloch-periodic x) runs, the phase p = pc + i ps that a field
 // gains across the periodic x edge.
@@ -174,9 +207,10 @@ __device__ __forceinline__ T bloch_bwd(T a, T b, int part, T pc, T ps) {
 }
 
 // H update of cell (i, j), part `part`, of the channel block F in global memory.
+// psi: the channel's CPML block (k_z runs with in-plane layers), or nullptr.
 template <typename T, int MODE, bool CYL, bool CPLX = false>
 __device__ __forceinline__ void hred_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
-                                          const RedRun<T>& rr, int i, int j, int part = 0) {
+                                          const RedRun<T>& rr, int i, int j, int part = 0, T* psi = nullptr) {
     T* const Fo = F + (CPLX ? (1 - part) * 6 * g.ncell : 0);    // the other part (complex runs)
     F += CPLX ? part * 6 * g.ncell : 0;
     const T* Ex = F;
@@ -206,18 +240,31 @@ __device__ __forceinline__ void hred_cell(T* __restrict__ F, const Grid2D& g, co
         eyr = Ey[c + 1 - g.nx];
     }
     T hx = Hx[c], hy = Hy[c], hz = Hz[c];
-    h_values<T, MODE, CYL>(hx, hy, hz, Ex[c], Ey[c], Ez[c], ezu, exu, ezr, eyr,
-                      lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]), lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]),
-                      lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]), rr.M, j, rr.rows + kRowFactors * j);
+    if (!CYL && psi != nullptr) {
+        // CPML: slots Hx 3, Hy 4, Hz 5; H components at half-cell positions
+        T* pp = psi + (CPLX ? part * 6 * g.psi_slot : 0);
+        const T ex = Ex[c], ey = Ey[c], ez = Ez[c];
+        h_values_kz<T, MODE>(hx, hy, hz, ex, ey, yee::pml_d2(ezu - ez, g, pp, 3, 1, true, i, j),
+                       yee::pml_d2(ezr - ez, g, pp, 4, 0, true, i, j), yee::pml_d2(eyr - ey, g, pp, 5, 0, true, i, j),
+                       yee::pml_d2(exu - ex, g, pp, 5, 1, true, i, j), lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]),
+                       lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]), lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]), rr.M);
+    } else {
+        h_values<T, MODE, CYL>(hx, hy, hz, Ex[c], Ey[c], Ez[c], ezu, exu, ezr, eyr,
+                          lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]), lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]),
+                          lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]), rr.M, j, rr.rows + kRowFactors * j);
+    }
     Hx[c] = hx;
     Hy[c] = hy;
     Hz[c] = hz;
 }
 
 // E update of cell (i, j), part `part`, of the channel block F in global memory.
+// psi: as in hred_cell; aux: the channel's polarization block (dispersive
+// k_z runs), or nullptr.
 template <typename T, int MODE, bool CYL, bool CPLX = false>
 __device__ __forceinline__ void ered_cell(T* __restrict__ F, const Grid2D& g, const T* __restrict__ lut, int kind,
-                                          const RedRun<T>& rr, int i, int j, int part = 0) {
+                                          const RedRun<T>& rr, int i, int j, int part = 0, T* psi = nullptr,
+                                          T* aux = nullptr) {
     T* const Fo = F + (CPLX ? (1 - part) * 6 * g.ncell : 0);
     F += CPLX ? part * 6 * g.ncell : 0;
     T* Ex = F;
@@ -247,9 +294,27 @@ __device__ __forceinline__ void ered_cell(T* __restrict__ F, const Grid2D& g, co
         hzl = Hz[c - 1 + g.nx];
     }
     T ex = Ex[c], ey = Ey[c], ez = Ez[c];
-    e_values<T, MODE, CYL>(ex, ey, ez, Hx[c], Hy[c], Hz[c], hxd, hzd, hyl, hzl,
-                      lut_ab(lut, kind, CF_EX, g.ids[CF_EX][c]), lut_ab(lut, kind, CF_EY, g.ids[CF_EY][c]),
-                      lut_ab(lut, kind, CF_EZ, g.ids[CF_EZ][c]), rr.M, j, rr.rows + kRowFactors * j);
+    const T* lx = lut_ab(lut, kind, CF_EX, g.ids[CF_EX][c]);
+    const T* ly = lut_ab(lut, kind, CF_EY, g.ids[CF_EY][c]);
+    const T* lz = lut_ab(lut, kind, CF_EZ, g.ids[CF_EZ][c]);
+    if (!CYL && psi != nullptr) {
+        // CPML: slots Ex 0, Ey 1, Ez 2; E components at integer positions
+        T* pp = psi + (CPLX ? part * 6 * g.psi_slot : 0);
+        const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
+        e_values_kz<T, MODE>(ex, ey, ez, hx, hy, yee::pml_d2(hz - hzd, g, pp, 0, 1, false, i, j),
+                       yee::pml_d2(hz - hzl, g, pp, 1, 0, false, i, j), yee::pml_d2(hy - hyl, g, pp, 2, 0, false, i, j),
+                       yee::pml_d2(hx - hxd, g, pp, 2, 1, false, i, j), lx, ly, lz, rr.M);
+    } else {
+        e_values<T, MODE, CYL>(ex, ey, ez, Hx[c], Hy[c], Hz[c], hxd, hzd, hyl, hzl, lx, ly, lz, rr.M, j,
+                               rr.rows + kRowFactors * j);
+    }
+    if (!CYL && MODE == 0 && aux != nullptr) {
+        // Lorentz polarizations of D = eps_inf E + sum P (E slots 0, 1, 2)
+        T* ap = aux + (CPLX ? (int64_t)part * 3 * g.n_lor * 2 * g.ncell : 0);
+        ex -= yee::lorentz_step(g, ap, 0, c, g.ids[CF_EX][c], lx[0], Ex[c]);
+        ey -= yee::lorentz_step(g, ap, 1, c, g.ids[CF_EY][c], ly[0], Ey[c]);
+        ez -= yee::lorentz_step(g, ap, 2, c, g.ids[CF_EZ][c], lz[0], Ez[c]);
+    }
     Ex[c] = ex;
     Ey[c] = ey;
     Ez[c] = ez;
@@ -265,8 +330,9 @@ __global__ __launch_bounds__(BX* BY) void k_hred(T* __restrict__ fields, const C
     const int i = (blockIdx.x % tiles_x) * BX + threadIdx.x;
     const int j = (blockIdx.x / tiles_x) * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
+    T* psi = g.psi ? static_cast<T*>(g.psi) + d.psi_off : nullptr;
     for (int part = 0; part < (CPLX ? 2 : 1); ++part)
-        hred_cell<T, MODE, CYL, CPLX>(fields + d.field_off, g, lut, d.kind, rr, i, j, part);
+        hred_cell<T, MODE, CYL, CPLX>(fields + d.field_off, g, lut, d.kind, rr, i, j, part, psi);
 }
 
 template <typename T, int MODE, bool CYL, bool CPLX>
@@ -279,8 +345,10 @@ __global__ __launch_bounds__(BX* BY) void k_ered(T* __restrict__ fields, const C
     const int i = (blockIdx.x % tiles_x) * BX + threadIdx.x;
     const int j = (blockIdx.x / tiles_x) * BY + threadIdx.y;
     if (i >= g.nx || j >= g.ny) return;
+    T* psi = g.psi ? static_cast<T*>(g.psi) + d.psi_off : nullptr;
+    T* aux = g.n_lor > 0 ? static_cast<T*>(g.aux) + d.aux_off : nullptr;
     for (int part = 0; part < (CPLX ? 2 : 1); ++part)
-        ered_cell<T, MODE, CYL, CPLX>(fields + d.field_off, g, lut, d.kind, rr, i, j, part);
+        ered_cell<T, MODE, CYL, CPLX>(fields + d.field_off, g, lut, d.kind, rr, i, j, part, psi, aux);
 }
 
 // Every cell of the grid once, block-strided: thread t takes flat cells

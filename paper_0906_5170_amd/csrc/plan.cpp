@@ -380,7 +380,6 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
         return "unknown coordinate system";
     if (g.coord == CF_COORD_KZ) {
         if (g.ndim != 2) return "k_z problems are 2D grids";
-        if (g.bc[0] == CF_BC_PML || g.bc[1] == CF_BC_PML) return "PML is implemented for 3D grids";
         if (s.n_kz < 1 || s.n_kz > 33 || !s.kz || !s.kz_weight) return "k_z problems need 1..33 wavevectors";
         for (int q = 0; q < s.n_kz; ++q)
             if (!std::isfinite(s.kz[q]) || !std::isfinite(s.kz_weight[q])) return "k_z points must be finite";
@@ -388,7 +387,7 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
     if (g.coord == CF_COORD_CYLINDRICAL) {
         if (g.ndim != 2) return "cylindrical problems are 2D (r, z) grids";
         if (g.bc[1] != CF_BC_PEC) return "cylindrical problems need a PEC tube wall (bc[1])";
-        if (g.bc[0] == CF_BC_PML) return "PML is implemented for 3D grids";
+        if (g.bc[0] == CF_BC_PML) return "PML is not implemented for cylindrical problems";
         if (s.m_max < 0 || s.m_max > 32) return "m_max must be in 0..32";
     }
     if (m.n_materials < 1 || m.n_materials > 254 || !m.eps || !m.mu) return "bad material table";
@@ -640,6 +639,28 @@ static std::string finish_cyl_surface(Problem& p, const cf_surface& s) {
     return surface_medium(p);
 }
 
+// Stability of the centred Lorentz scheme in a uniform medium (eps_inf, mu,
+// terms).  A plane wave with Omega^2 = (4 / dt^2) sin^2(omega dt / 2) and
+// curl-curl eigenvalue K^2 / mu obeys
+//     Omega^2 (eps_inf + sum d_eps w0^2 / (w0^2 - Omega^2)) = K^2 / mu,
+// and is stable when every root Omega^2 <= X = 4 / dt^2.  Above the largest
+// w0^2 the left side minus the right increases with Omega^2, so the scheme
+// is stable when w0 dt < 2 for every term and
+//     eps_inf X - K_max^2 / mu + sum d_eps w0^2 X / (w0^2 - X) > 0,
+// K_max^2 = bound / dx^2 (all in units of dx^2 here).
+bool lorentz_stable(double eps_inf, double mu, const double* de, const double* w0, int n, double courant,
+                    double dx, double bound) {
+    const double X = 4.0 / (courant * courant);
+    double f = eps_inf * X - bound / mu;
+    for (int j = 0; j < n; ++j) {
+        if (de[j] == 0.0) continue;
+        const double w2 = (w0[j] * dx) * (w0[j] * dx);
+        if (w2 * courant * courant >= 4.0) return false;
+        f += de[j] * w2 * X / (w2 - X);
+    }
+    return f > 0.0;
+}
+
 std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
     *code = CF_E_ARG;
     if (!(o.sigma >= 0) || !std::isfinite(o.sigma)) return "sigma must be >= 0";
@@ -665,15 +686,15 @@ std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
             return "the z-invariant kernel applies to 2D runs only";
         }
     }
-    if (p.dispersive && (p.grid.ndim == 3 || p.reduced())) {
+    if (p.dispersive && (p.grid.ndim == 3 || p.cyl)) {
         *code = CF_E_UNSUPPORTED;
-        return "dispersive materials are implemented for Cartesian 2D problems";
+        return "dispersive materials are implemented for Cartesian 2D and k_z problems";
     }
     if (p.grid.ndim == 2) {
         for (int a = 0; a < 2; ++a)
-            if (p.grid.bc[a] == CF_BC_PML) {
+            if (p.grid.bc[a] == CF_BC_PML && p.cyl) {
                 *code = CF_E_UNSUPPORTED;
-                return "PML is implemented for 3D grids";
+                return "PML is not implemented for cylindrical problems";
             }
     } else {
         if (p.grid.bc[0] == CF_BC_PML || p.grid.bc[1] == CF_BC_PML) {
@@ -695,13 +716,25 @@ std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
         return "courant number above the Yee stability limit";
     }
     if (p.dispersive) {
-        // centred Lorentz update: stable for w0 dt < 2
-        const double dt = o.courant / p.grid.res;
-        for (size_t k = 0; k < p.lor_w0.size(); ++k)
-            if (p.lor_de[k] != 0.0 && p.lor_w0[k] * dt >= 2.0) {
+        // centred Lorentz update: every term needs w0 dt < 2, and the coupled
+        // field-polarization frequency of the fastest grid mode must stay
+        // below 2 / dt (lorentz_stable)
+        double bound = 4.0 * p.grid.ndim;
+        if (p.kz) {
+            double kmax = 0;
+            for (double k : p.kzs) kmax = std::max(kmax, std::abs(k) / p.grid.res);
+            bound = 8.0 + kmax * kmax;
+        }
+        const double dx = 1.0 / p.grid.res;
+        for (int i = 0; i < p.nmat; ++i) {
+            if (!p.has_terms(i) || !std::isfinite(p.eps[i]) || !std::isfinite(p.mu[i])) continue;
+            if (!lorentz_stable(p.eps[i], p.mu[i], &p.lor_de[(size_t)i * p.n_lor], &p.lor_w0[(size_t)i * p.n_lor],
+                                p.n_lor, o.courant, dx, bound)) {
                 *code = CF_E_CFL;
-                return "a Lorentz term has w0 dt >= 2 (unstable)";
+                return "a Lorentz medium is unstable at this time step (the coupled field and polarization "
+                       "frequency exceeds 2 / dt): lower the Courant number";
             }
+        }
     }
     if (p.cyl && o.courant * vmax > 0.5) {
         *code = CF_E_CFL;
@@ -868,6 +901,27 @@ void pml_tables(const Problem& p, double courant, std::vector<double>& bh, std::
                 be[k] = b;
                 ce[k] = b - 1.0;
             }
+        }
+}
+
+// The same profile along in-plane axis `axis` of a 2D problem: appends
+// b, c at the half-cell positions, then b, c at the integer positions (n
+// values each); nothing when the axis has no layers.
+void pml_axis_tables(const Problem& p, int axis, double courant, std::vector<double>& out) {
+    if (p.grid.bc[axis] != CF_BC_PML) return;
+    const int n = axis == 0 ? p.nx : p.ny, P = p.grid.pml_cells[axis];
+    const double dx = 1.0 / p.grid.res, dt = courant * dx;
+    const double smax = -(3.0 + 1.0) * std::log(1e-8) / (2.0 * P * dx);
+    const size_t o = out.size();
+    out.resize(o + 4 * (size_t)n);
+    for (int half = 1; half >= 0; --half)
+        for (int q = 0; q < n; ++q) {
+            const double x = q + 0.5 * half;
+            const double depth = std::max(std::max(P - x, x - (n - P)), 0.0);
+            const double b = std::exp(-smax * std::pow(depth / P, 3) * dt);
+            const size_t row = o + (half ? 0 : 2 * (size_t)n);
+            out[row + q] = b;
+            out[row + n + q] = b - 1.0;
         }
 }
 

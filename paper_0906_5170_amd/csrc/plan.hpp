@@ -103,6 +103,10 @@ struct Problem {
     // reduced two-dimensional problems: six components, one run per order
     // (azimuthal order m, or k_z point q)
     bool reduced() const { return cyl || kz; }
+    // a 2D problem with CPML layers on an in-plane axis (split kernels only)
+    bool pml2d() const { return grid.ndim == 2 && (grid.bc[0] == CF_BC_PML || grid.bc[1] == CF_BC_PML); }
+    // a Cartesian 2D problem the fused kernel can take (no polarizations, no CPML)
+    bool fusable2d() const { return grid.ndim == 2 && !reduced() && !dispersive && !pml2d(); }
     int n_orders() const { return cyl ? m_max + 1 : kz ? (int)kzs.size() : 1; }
     double order_weight(int q) const { return cyl ? (q == 0 ? 1.0 : 2.0) : kz ? kz_w[q] : 1.0; }
     // coupling of order q in the undivided curls: m, or k dx
@@ -142,6 +146,7 @@ std::vector<double> coefficient_lut(const Problem& p, double sigma, double coura
 void kernel_table(int kernel, double sigma, double dt, int n, double* out);
 
 // CPML along z: b, c at the z positions of H_x/H_y (k + 1/2) and E_x/E_y (k).
+void pml_axis_tables(const Problem& p, int axis, double courant, std::vector<double>& out);
 void pml_tables(const Problem& p, double courant, std::vector<double>& bh, std::vector<double>& ch,
                 std::vector<double>& be, std::vector<double>& ce);
 

@@ -965,6 +965,8 @@ static cf_status cf_server_submit_impl(cf_server* S, cf_problem* prob, const cf_
     if (o->n_subset > 0) return fail(CF_E_ARG, "served requests run every channel");
     if (prob->p.dispersive)
         return fail(CF_E_UNSUPPORTED, "problems with dispersive materials are solved with cf_solve, not served");
+    if (prob->p.pml2d() && !prob->p.reduced())
+        return fail(CF_E_UNSUPPORTED, "2D problems with PML layers are solved with cf_solve, not served");
     cf_status st = cf_validate(prob, o);
     if (st != CF_OK) return st;
     auto r = std::make_shared<Req>();

@@ -77,6 +77,9 @@ struct Staged {
     int resident = 0;                      // field blocks on the device
     int ncomp = 3;
     int64_t psi_comp = 0;                  // values per psi component (3D CPML)
+    int64_t psi_block = 0;                 // CPML values per resident channel (3D, or 2D split kernels)
+    int64_t psi2d_slot = 0;                // 2D CPML: values per field slot (x and y layer arrays)
+    bool pml2d = false;                    // 2D problem with in-plane CPML layers (split kernels)
     bool red_res = false;                  // cylindrical waves on the resident solve kernel
     bool f3d = false;                      // 3D steps on the fused z-streaming kernel
     int v3d = -1;                          // its variant when fixed by the options (-1: autotune)

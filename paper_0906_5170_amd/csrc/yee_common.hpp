@@ -61,6 +61,53 @@ __device__ __forceinline__ double lane_value(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
+// Undivided difference D along in-plane axis `axis` for the component in
+// field slot `slot` at cell (i, j) of a 2D grid, stretched inside the CPML
+// layers (Roden-Gedney with kappa = 1, alpha = 0): psi <- b psi + c D,
+// returns D + psi.  Outside the layers b = 1 and c = 0, so psi stays 0 and
+// the difference is returned as it is.  half: the updated component sits at
+// a half-cell position along the axis.  psi: the channel's CPML block
+// (part already applied), or nullptr.
+template <typename T>
+__device__ __forceinline__ T pml_d2(T D, const Grid2D& g, T* psi, int slot, int axis, bool half, int i, int j) {
+    const int P = g.pml[axis];
+    if (P == 0 || psi == nullptr) return D;
+    const int n = axis == 0 ? g.nx : g.ny;
+    const int q = axis == 0 ? i : j;
+    if (q >= P && q < n - P) return D;
+    const int qq = q < P ? q : q - (n - 2 * P);
+    T* arr = psi + slot * g.psi_slot + (axis == 0 ? 0 : (int64_t)g.ny * 2 * g.pml[0]);
+    const int64_t at = axis == 0 ? (int64_t)j * (2 * P) + qq : (int64_t)qq * g.nx + i;
+    const double* tab = g.pml_tab[axis] + (half ? 0 : 2 * n);
+    const T p = fma(T(tab[q]), arr[at], T(tab[n + q]) * D);
+    arr[at] = p;
+    return D + p;
+}
+
+// Dispersive media: advances the Lorentz polarizations of one E component at
+// cell c (every term's pair P^m, P^{m-1} -> P^{m+1}, P^m, from E^m = e_old)
+// and returns (sum P^{m+1} - a sum P^m) / eps_inf, the amount the E update
+// of D = eps_inf E + sum P subtracts.  Zero for an id without terms.  aux:
+// the channel's polarization block (part already applied); e_slot: the E
+// component's slot in it.
+template <typename T>
+__device__ __forceinline__ T lorentz_step(const Grid2D& g, T* aux, int e_slot, int64_t c, int id, T a, T e_old) {
+    const double* row = g.lor + (size_t)id * kLorStride(g.n_lor);
+    if (row[0] == 0.0) return T(0);
+    T sum_now = T(0), sum_next = T(0);
+    for (int j = 0; j < g.n_lor; ++j) {
+        T* pc = aux + (int64_t)((e_slot * g.n_lor + j) * 2) * g.ncell + c;
+        T* pp = pc + g.ncell;
+        const T cur = *pc, prev = *pp;
+        const T nxt = fma(T(row[2 + 3 * j]), cur, fma(-T(row[3 + 3 * j]), prev, T(row[4 + 3 * j]) * e_old));
+        sum_now += cur;
+        sum_next += nxt;
+        *pp = cur;
+        *pc = nxt;
+    }
+    return (sum_next - a * sum_now) * T(row[1]);
+}
+
 // Threads that take part in a surface sum (the first kSurfThreads of the block).
 constexpr int kSurfThreads = 256;
 

@@ -46,6 +46,9 @@ CASES = {
     "pec_z": lambda: sphere_case(12, 11, 18),
     "pml_z_fluid": lambda: sphere_case(12, 12, 26, bc_z="pml", pml=4, eps_bg=1.8, n_steps=60),
     "pml_z_force_x": lambda: sphere_case(13, 12, 26, bc_z="pml", pml=4, n_steps=30).replace(force_axis=0),
+    # S's top face on the first plane of the upper layer: the kick and the
+    # consistent start reach into the CPML and stretch there as every step does
+    "pml_z_touching": lambda: sphere_case(12, 12, 19, bc_z="pml", pml=4, n_steps=40),
 }
 
 

@@ -342,3 +342,51 @@ def test_dispersive_validation(cf):
     with pytest.raises(cf.CfError) as e:
         fast.validate(kernel="general", **opts)
     assert e.value.status == "CF_E_CFL"
+
+
+def test_open_space_kz_and_cartesian_validation(cf):
+    """In-plane CPML (Sec. III B: waveguides in open space) is accepted for
+    Cartesian 2D and k_z problems, dispersive media for k_z problems too;
+    a cylindrical CPML is refused at creation."""
+    from casimir_inputs import slabs_open_1d, waveguides_open_2d
+    si = ((10.835, 22.0),)
+    wg = waveguides_open_2d(20, 0.5, 0.25, 0.25, 0.5, 0.5, 1.035, si, n_harm=3, n_steps=50, courant=0.35)
+    opts = dict(sigma=1.0, courant=0.35, n_steps=50, kernel="general", precision="fp32")
+    kzp = cf.Problem.from_workload(kz_workload(wg, [0.0, 2.0, 6.0], [1.0, 1.0, 1.0]))
+    kzp.validate(pol="3D", **opts)
+    assert kzp.info(pol="3D", **opts)["workspace_bytes"] > 0
+    cart = cf.Problem.from_workload(wg.replace(pol="TM+TE"))
+    cart.validate(pol="TM+TE", **opts)
+    with pytest.raises(cf.CfError) as e:
+        cf.Problem.from_workload(cyl_piston(res=10, n_harm=2, m_max=1).replace(bc=("pml", "pec", "periodic"),
+                                                                              pml_cells=(3, 0, 0)))
+    assert e.value.status == "CF_E_ARG"
+    # a stress surface next to a layer is accepted (its kick and start stretch
+    # like every later step, as in the oracle)
+    cf.Problem.from_workload(slabs_open_1d(20, 0.5, 0.25, 0.15, 0.5, 1.5, (), n_steps=50))
+
+
+def test_coupled_lorentz_stability_matches_oracle(cf):
+    """The library's coupled Lorentz stability rule (CF_E_CFL) makes the
+    oracle's decision (oracle.yee.lorentz_stable) on a sweep of Courant
+    numbers, for Cartesian 2D and k_z problems: silicon's strong term is
+    refused at 0.5 on a 20-cell grid although w0 dt = 0.55."""
+    from casimir_inputs import waveguides_open_2d
+    from oracle.yee import lorentz_stable
+    si = ((10.835, 22.0),)
+    wg = waveguides_open_2d(20, 0.5, 0.25, 0.25, 0.5, 0.5, 1.035, si, n_harm=2, n_steps=20)
+    for coord, ks in (("cartesian", None), ("kz", [0.0, 9.0])):
+        wl = wg if ks is None else kz_workload(wg, ks, [1.0] * len(ks))
+        p = cf.Problem.from_workload(wl)
+        bound = 8.0 if ks is None else 8.0 + (max(ks) / 20.0) ** 2
+        pol = "TM+TE" if ks is None else "3D"
+        for c in np.linspace(0.30, 0.50, 21):
+            ok = lorentz_stable(1.035, 1.0, si, c, 1.0 / 20.0, bound)
+            try:
+                p.validate(pol=pol, sigma=1.0, courant=float(c), n_steps=20, kernel="general", precision="fp64")
+                got = True
+            except cf.CfError as e:
+                assert e.status == "CF_E_CFL"
+                got = False
+            assert got == ok, (coord, c)
+        assert not lorentz_stable(1.035, 1.0, si, 0.5, 1.0 / 20.0, bound)
