@@ -337,8 +337,8 @@ class YeeSim:
             if a in self.poles:
                 terms, e_inf = self.poles[a]
                 dt, r = self.dt, 0.5 * self.sigma * self.dt
-                p_now = np.zeros(new.shape)
-                p_next = np.zeros(new.shape)
+                p_now = np.zeros_like(new)          # complex in Bloch runs
+                p_next = np.zeros_like(new)
                 for (de, w0), st in zip(terms, self.P[a]):
                     cur, prev = st
                     nxt = ((2.0 - (w0 * dt) ** 2) * cur - (1.0 - r) * prev
