@@ -400,8 +400,8 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
                     const T ezr = j + 1 < CX ? f0[(j + 1) % CX][r] : from_next(f0[0][r]);
                     const T ezu = r + 1 < B ? f0[j][(r + 1) % B] : e_above[j];
                     const Pair<T> cx = CF_K(1, j, r), cy = CF_K(2, j, r);
-                    f1[j][r] = yee_sub(cx.a, f1[j][r], cx.b, ezu - ez);
-                    f2[j][r] = yee_sub(cy.a, f2[j][r], cy.b, ez - ezr);
+                    yee::sub_into(f1[j][r], cx.a, cx.b, ezu - ez);
+                    yee::sub_into(f2[j][r], cy.a, cy.b, ez - ezr);
                 }
         } else {
 #pragma unroll
@@ -412,7 +412,7 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
                     const T eyr = j + 1 < CX ? f1[(j + 1) % CX][r] : from_next(f1[0][r]);
                     const T exu = r + 1 < B ? f0[j][(r + 1) % B] : e_above[j];
                     const Pair<T> cz = CF_K(2, j, r);
-                    f2[j][r] = yee_sub(cz.a, f2[j][r], cz.b, (eyr - ey) - (exu - ex));
+                    yee::sub_into(f2[j][r], cz.a, cz.b, (eyr - ey) - (exu - ex));
                 }
         }
         // ---- E half: needs the H row below the wave's band ----
@@ -434,7 +434,7 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
                     const T hxd = r > 0 ? f1[j][(r + B - 1) % B] : h_below[j];
                     const T curl = (hy - hyl) - (hx - hxd);
                     const Pair<T> cz = CF_K(0, j, r);
-                    f0[j][r] = yee_add(cz.a, f0[j][r], cz.b, curl);
+                    yee::add_into(f0[j][r], cz.a, cz.b, curl);
                 }
         } else {
 #pragma unroll
@@ -445,8 +445,8 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
                     const T hzl = j > 0 ? f2[(j + CX - 1) % CX][r] : from_prev(f2[CX - 1][r]);
                     const T hzd = r > 0 ? f2[j][(r + B - 1) % B] : h_below[j];
                     const Pair<T> cx = CF_K(0, j, r), cy = CF_K(1, j, r);
-                    f0[j][r] = yee_add(cx.a, f0[j][r], cx.b, hz - hzd);
-                    f1[j][r] = yee_sub(cy.a, f1[j][r], cy.b, hz - hzl);
+                    yee::add_into(f0[j][r], cx.a, cx.b, hz - hzd);
+                    yee::sub_into(f1[j][r], cy.a, cy.b, hz - hzl);
                 }
         }
         if (stile) {

@@ -17,6 +17,21 @@ template <typename T>
 __device__ __forceinline__ T sub(T a, T x, T b, T d) { return fma(a, x, -(b * d)); }
 template <typename T>
 __device__ __forceinline__ T add(T a, T x, T b, T d) { return fma(a, x, b * d); }
+// The same two updates computed into x's own register: the final fused
+// multiply-add is written as the three-source form with x as both a source
+// and the destination, so a field updated under a branch (the fused kernel
+// skips waves that hold only conductor) needs no copy back into its home
+// register.  Bitwise the same as sub / add.
+__device__ __forceinline__ void fma_into(float& x, float a, float t) {
+    asm("v_fma_f32 %0, %1, %0, %2" : "+v"(x) : "v"(a), "v"(t));
+}
+__device__ __forceinline__ void fma_into(double& x, double a, double t) {
+    asm("v_fma_f64 %0, %1, %0, %2" : "+v"(x) : "v"(a), "v"(t));
+}
+template <typename T>
+__device__ __forceinline__ void sub_into(T& x, T a, T b, T d) { fma_into(x, a, -(b * d)); }
+template <typename T>
+__device__ __forceinline__ void add_into(T& x, T a, T b, T d) { fma_into(x, a, b * d); }
 // partner field of the consistent start: (b / 2) d
 template <typename T>
 __device__ __forceinline__ T half(T b, T d) { return (T(0.5) * b) * d; }
