@@ -273,7 +273,9 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
     const int tx = tile % g.ntx, ty = tile / g.ntx;
     const int rx0 = g.base_x + tx * TX - KH, ry0 = g.base_y + ty * TY - KH;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, w = tid >> 6;
+    // the wave index is uniform across a wave: taken as a scalar, every row
+    // index and row bound below is scalar arithmetic
+    const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     for (int i = tid; i < 3 * 256; i += NTB) {
         const int s = i >> 8, id = i & 255;
@@ -283,18 +285,26 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
         L[s][id].b = p[1];
     }
 
-    // cell (j, r) of this lane: grid index, or -1 beyond a non-periodic edge
-    auto cell_of = [&](int j, int r) -> int64_t {
-        int gx = rx0 + lane * CX + j, gy = ry0 + w * B + r;
-        if (gx < 0 || gx >= g.nx) {
-            if (!g.perx) return -1;
-            gx = ((gx % g.nx) + g.nx) % g.nx;
-        }
-        if (gy < 0 || gy >= g.ny) {
-            if (!g.pery) return -1;
-            gy = ((gy % g.ny) + g.ny) % g.ny;
-        }
-        return (int64_t)gy * g.nx + gx;
+    // Column of the lane's cell j and row r of the wave's band in the grid
+    // (wrapped on a periodic axis), or -1 beyond a non-periodic edge: the x
+    // index is per lane and column, the y index uniform across the wave, so
+    // each is formed once here instead of once per cell.  Cell indices fit
+    // 32 bits: the library refuses larger grids.
+    int col[CX], row[B];
+#pragma unroll
+    for (int j = 0; j < CX; ++j) {
+        int gx = rx0 + lane * CX + j;
+        if (gx < 0 || gx >= g.nx) gx = g.perx ? ((gx % g.nx) + g.nx) % g.nx : -1;
+        col[j] = gx;
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+        int gy = ry0 + w * B + r;
+        if (gy < 0 || gy >= g.ny) gy = g.pery ? ((gy % g.ny) + g.ny) % g.ny : -1;
+        row[r] = __builtin_amdgcn_readfirstlane(gy);
+    }
+    auto cell_of = [&](int j, int r) -> int {
+        return col[j] < 0 || row[r] < 0 ? -1 : row[r] * g.nx + col[j];
     };
     uint32_t m0p[CX][NP], m1p[CX][NP], m2p[CX][NP];
 #pragma unroll
@@ -305,7 +315,7 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
     for (int j = 0; j < CX; ++j)
 #pragma unroll
         for (int r = 0; r < B; ++r) {
-            const int64_t gi = cell_of(j, r);
+            const int gi = cell_of(j, r);
             const uint32_t i0 = gi >= 0 ? g.ids[C0][gi] : kNullId;
             const uint32_t i1 = gi >= 0 ? g.ids[C1][gi] : kNullId;
             const uint32_t i2 = gi >= 0 ? g.ids[C2][gi] : kNullId;
@@ -351,15 +361,17 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
 
     T f0[CX][B], f1[CX][B], f2[CX][B];
     {
-        const T* S = src + d.field_off;
+        const T* S0 = src + d.field_off;
+        const T* S1 = S0 + g.ncell;
+        const T* S2 = S1 + g.ncell;
 #pragma unroll
         for (int j = 0; j < CX; ++j)
 #pragma unroll
             for (int r = 0; r < B; ++r) {
-                const int64_t gi = live ? cell_of(j, r) : -1;
-                f0[j][r] = gi >= 0 ? S[gi] : T(0);
-                f1[j][r] = gi >= 0 ? S[g.ncell + gi] : T(0);
-                f2[j][r] = gi >= 0 ? S[2 * g.ncell + gi] : T(0);
+                const int gi = live ? cell_of(j, r) : -1;
+                f0[j][r] = gi >= 0 ? S0[gi] : T(0);
+                f1[j][r] = gi >= 0 ? S1[gi] : T(0);
+                f2[j][r] = gi >= 0 ? S2[gi] : T(0);
             }
     }
     // CREG: each cell's (a, b) pairs are constant over the launch and can be
@@ -481,7 +493,9 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
         acc[1] = acc_c;
     }
     if (!live) return;   // its cells are 0 in both arrays already
-    T* D = dst + d.field_off;
+    T* D0 = dst + d.field_off;
+    T* D1 = D0 + g.ncell;
+    T* D2 = D1 + g.ncell;
 #pragma unroll
     for (int j = 0; j < CX; ++j) {
         const int cx = lane * CX + j;
@@ -492,10 +506,10 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
             const int ry = w * B + r;
             const int gy = ry0 + ry;
             if (ry < KH || ry >= KH + TY || gy < 0 || gy >= g.ny) continue;
-            const int64_t gi = (int64_t)gy * g.nx + gx;
-            D[gi] = f0[j][r];
-            D[g.ncell + gi] = f1[j][r];
-            D[2 * g.ncell + gi] = f2[j][r];
+            const int gi = gy * g.nx + gx;
+            D0[gi] = f0[j][r];
+            D1[gi] = f1[j][r];
+            D2[gi] = f2[j][r];
         }
     }
 }
