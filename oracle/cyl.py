@@ -44,10 +44,21 @@ checks.
 Stability.  The m/r couplings of co-located pairs raise the largest
 frequency of the scheme near the axis; the stable Courant number falls with
 m (cylindrical_courant gives the value used).
+
+Open tube ends (bc "pml" along the axis; Sec. III C's piston ends in PML):
+the CPML of the Cartesian scheme (oracle.yee, same profile) stretches the
+four axial differences, d_z e_phi (h_r), d_z e_r (h_phi), d_z h_phi (e_r)
+and d_z h_r (e_phi), inside the layers, at the updated component's axial
+position; the layers are backed by a PEC end (e_r and e_phi held at 0 on
+the first plane).  The radial differences and the m/r couplings are not
+stretched.  Pinned by a pulse in a short tube with layers against the same
+pulse in a tube three times as long with PEC ends (tests/test_oracle_cyl.py).
 """
 from __future__ import annotations
 
 import numpy as np
+
+from .yee import pml_profile
 
 COMP = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")   # e_z, e_r, e_phi, h_z, h_r, h_phi
 
@@ -83,6 +94,15 @@ class CylSim:
         self.r0 = np.arange(self.nr) - 0.5
         self.r1 = np.arange(self.nr) * 1.0
         self._coefficients()
+        # CPML along the axis: (b, c) per axial position of each stretched
+        # target (h_r, h_phi at half cells; e_r, e_phi at whole cells) and psi
+        self.pml, self.psi = {}, {}
+        if self.bc_z == "pml":
+            P = int(wl.pml_cells[0])
+            for c, half in (("Hy", True), ("Hz", True), ("Ey", False), ("Ez", False)):
+                b, cc = pml_profile(self.nz, P, self.dx, self.dt, half)
+                self.pml[c] = (b[None, None, :], cc[None, None, :])
+                self.psi[c] = np.zeros(shape)
 
     # -- coefficients -----------------------------------------------------
     def _coefficients(self):
@@ -111,8 +131,9 @@ class CylSim:
             if c in ("Ex", "Ez", "Hy"):
                 a[0, :] = 0.0
                 b[0, :] = 0.0
-            # PEC end wall at z = 0: e_r and e_phi (axial offset 0) lie on it
-            if self.bc_z == "pec" and c in ("Ey", "Ez"):
+            # PEC end wall at z = 0 (also behind a CPML): e_r and e_phi
+            # (axial offset 0) lie on it
+            if self.bc_z in ("pec", "pml") and c in ("Ey", "Ez"):
                 a[:, 0] = 0.0
                 b[:, 0] = 0.0
             self.a[c] = a
@@ -134,6 +155,15 @@ class CylSim:
         out = F.copy()
         out[:, :, 1:] -= F[:, :, :-1]
         return out
+
+    def _stretch(self, target, D):
+        """An axial difference D of the update of `target`, stretched inside
+        the CPML: psi <- b psi + c D, D + psi (unchanged without layers)."""
+        if target not in self.pml:
+            return D
+        b, c = self.pml[target]
+        self.psi[target] = b * self.psi[target] + c * D
+        return D + self.psi[target]
 
     @staticmethod
     def _shift_up(F):
@@ -162,10 +192,10 @@ class CylSim:
         cz[:, 0, :] = 4.0 * ez[:, 1, :] if m == 0 else 0.0
         # h_r at offset-0 rows (r = j - 1/2): (m/r) e_z - d_z e_phi
         with np.errstate(divide="ignore", invalid="ignore"):
-            cr = m * ex / r0 - self._dz_fwd(ez)
+            cr = m * ex / r0 - self._stretch("Hy", self._dz_fwd(ez))
         cr[:, 0, :] = 0.0
         # h_phi at (1,1): d_z e_r - d_r e_z
-        cp = self._dz_fwd(ey) - (self._shift_up(ex) - ex)
+        cp = self._stretch("Hz", self._dz_fwd(ey)) - (self._shift_up(ex) - ex)
         return {"Hx": cz, "Hy": cr, "Hz": cp}
 
     def curl_h(self):
@@ -180,10 +210,10 @@ class CylSim:
         cz[:, 0, :] = 0.0
         # e_r at offset-1 rows: -(m/r) h_z - d_z h_phi
         with np.errstate(divide="ignore", invalid="ignore"):
-            cr = -m * hx / r1 - self._dz_bwd(hz)
+            cr = -m * hx / r1 - self._stretch("Ey", self._dz_bwd(hz))
         cr[:, 0, :] = 0.0
         # e_phi at (0,0): d_z h_r - d_r h_z
-        cp = self._dz_bwd(hy) - (hx - self._shift_down(hx))
+        cp = self._stretch("Ez", self._dz_bwd(hy)) - (hx - self._shift_down(hx))
         cp[:, 0, :] = 0.0
         return {"Ex": cz, "Ey": cr, "Ez": cp}
 
