@@ -60,10 +60,13 @@ typedef enum {
 /* Boundary per axis (both ends of the axis).  CF_BC_PML: a CPML
  * (Roden-Gedney, polynomial order 3, R0 = 1e-8, kappa = 1, alpha = 0) of
  * pml_cells cells inside the grid at both ends, backed by a PEC wall
- * (Sec. III B: open space around the bodies).  3D grids take it along z;
- * Cartesian 2D and k_z problems along x and/or y (split half-step kernels:
- * the fused and resident kernels carry no CPML); cylindrical problems not
- * at all (CF_E_ARG at creation).  The kick and the consistent start stretch
+ * (Sec. III B: open space around the bodies; Sec. III C: open tube ends).
+ * 3D grids take it along z; Cartesian 2D and k_z problems along x and/or
+ * y; cylindrical problems along the tube axis (x) only, the tube wall
+ * staying PEC (CF_E_ARG at creation otherwise).  In 2D, k_z and
+ * cylindrical problems the split half-step kernels carry the layers (the
+ * fused and resident kernels do not); each cylindrical order uses the
+ * profile of its own time step.  The kick and the consistent start stretch
  * their differences inside a layer as every later step does. */
 enum { CF_BC_PEC = 0, CF_BC_PERIODIC = 1, CF_BC_PML = 2 };
 /* Polarizations: 2D runs take CF_POL_TM, CF_POL_TE or both OR-ed; 3D runs CF_POL_3D. */

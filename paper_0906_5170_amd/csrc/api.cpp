@@ -685,7 +685,7 @@ Layout layout_for(const cf::Problem& p, const cf_opts& o, const Staged& st) {
     L.fields = take(block);
     L.fields2 = st.variant >= 0 || st.f3d ? take(block) : off;
     L.psi = st.psi_block > 0 ? take((size_t)st.resident * st.psi_block * fsz) : off;
-    L.pml2 = st.pml2d ? take((size_t)4 * (p.nx + p.ny) * 8) : off;
+    L.pml2 = st.pml2d ? take((size_t)p.n_orders() * 4 * (p.nx + p.ny) * 8) : off;   // per order: its time step
     L.psi2 = st.psi_comp > 0 && st.f3d ? take((size_t)st.resident * 4 * st.psi_comp * fsz) : off;
     L.idp = st.f3d ? take((size_t)p.ncell * 8) : st.red_res ? take((size_t)p.ncell * 4) : off;
     L.shadow = st.f3d && st.sbox.vol > 0 ? take((size_t)st.resident * st.sbox.vol * fsz) : off;
@@ -849,21 +849,34 @@ struct SideStreams {
 // steps.  Split path (CF_FLAG_SPLIT, plain): waves of one order each; per
 // wave clear, kick, consistent start, then per step the H and E half steps
 // and the surface projection with the g-weighted accumulation.
+void pml_order(const cf::Problem& p, const Layout& L, char* ws, cf::Grid2D& g, int m);
+
 // In-plane CPML of a 2D problem (split kernels): uploads the x and y
-// profiles for the run's time step and points the grid at them and at the
-// psi blocks.  tab holds the host copy until the solve has synchronized.
+// profiles for the time step of every order (cylindrical orders m >= 2 step
+// with a smaller Courant number; the other problems have one order or one
+// time step) and points the grid at order 0's and at the psi blocks
+// (pml_order moves it to another order's).  tab holds the host copy until
+// the solve has synchronized.
 hipError_t set_pml2d(const cf::Problem& p, const cf_opts& o, const Staged& st, const Layout& L, char* ws,
                      hipStream_t s, cf::Grid2D& g, std::vector<double>& tab) {
     tab.clear();
-    for (int a = 0; a < 2; ++a) {
-        const size_t at = tab.size();
-        cf::pml_axis_tables(p, a, o.courant, tab);
-        g.pml[a] = tab.size() > at ? p.grid.pml_cells[a] : 0;
-        g.pml_tab[a] = reinterpret_cast<const double*>(ws + L.pml2) + at;
-    }
+    for (int m = 0; m < p.n_orders(); ++m)
+        for (int a = 0; a < 2; ++a) cf::pml_axis_tables(p, a, cf::order_courant(p, o.courant, m), tab);
     g.psi = ws + L.psi;
     g.psi_slot = st.psi2d_slot;
+    pml_order(p, L, ws, g, 0);
     return hipMemcpyAsync(ws + L.pml2, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s);
+}
+
+// Points the grid's CPML profiles at order m's (the layout of set_pml2d).
+void pml_order(const cf::Problem& p, const Layout& L, char* ws, cf::Grid2D& g, int m) {
+    const size_t per_axis[2] = {p.grid.bc[0] == CF_BC_PML ? 4 * (size_t)p.nx : 0,
+                                p.grid.bc[1] == CF_BC_PML ? 4 * (size_t)p.ny : 0};
+    const double* base = reinterpret_cast<const double*>(ws + L.pml2) + (size_t)m * (per_axis[0] + per_axis[1]);
+    g.pml[0] = per_axis[0] ? p.grid.pml_cells[0] : 0;
+    g.pml[1] = per_axis[1] ? p.grid.pml_cells[1] : 0;
+    g.pml_tab[0] = base;
+    g.pml_tab[1] = base + per_axis[0];
 }
 
 template <typename T>
@@ -1060,6 +1073,7 @@ cf_status run_reduced(const cf::Problem& p, const cf_opts& o, const Staged& st, 
         const int m = w.order;
         const int tm = ord.steps[m];
         const double dt = ord.dt[m];
+        if (st.pml2d) pml_order(p, L, ws, g, m);
         const T* lut_m = dlut + m * lut_len;
         const double* k_m = dk + (size_t)m * t_max;
         STEP_OK(hipMemsetAsync(fields, 0, field_bytes, s));

@@ -248,6 +248,28 @@ __device__ __forceinline__ void hred_cell(T* __restrict__ F, const Grid2D& g, co
                        yee::pml_d2(ezr - ez, g, pp, 4, 0, true, i, j), yee::pml_d2(eyr - ey, g, pp, 5, 0, true, i, j),
                        yee::pml_d2(exu - ex, g, pp, 5, 1, true, i, j), lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]),
                        lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]), lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]), rr.M);
+    } else if (CYL && psi != nullptr && j > 0) {
+        // CPML at the tube ends (along the axis, the grid's x): the axial
+        // differences of h_r (slot 4) and h_phi (slot 5) are stretched; the
+        // rest is h_values' cylindrical form (the axis row takes h_values)
+        const T ex = Ex[c], ey = Ey[c], ez = Ez[c];
+        const T* rw = rr.rows + kRowFactors * j;
+        const T r = T(j);
+        const T cz = (((r + T(0.5)) * ezu - (r - T(0.5)) * ez) - rr.M * ey) * rw[RC];
+        const T cr = (rr.M * ex) * rw[RD] - yee::pml_d2(ezr - ez, g, psi, 4, 0, true, i, j);
+        const T cp = yee::pml_d2(eyr - ey, g, psi, 5, 0, true, i, j) - (exu - ex);
+        const T* lx = lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]);
+        const T* ly = lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]);
+        const T* lz = lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]);
+        if (MODE == 0) {
+            hx = yee::sub(lx[0], hx, lx[1], cz);
+            hy = yee::sub(ly[0], hy, ly[1], cr);
+            hz = yee::sub(lz[0], hz, lz[1], cp);
+        } else {
+            hx = yee::half(lx[1], cz);
+            hy = yee::half(ly[1], cr);
+            hz = yee::half(lz[1], cp);
+        }
     } else {
         h_values<T, MODE, CYL>(hx, hy, hz, Ex[c], Ey[c], Ez[c], ezu, exu, ezr, eyr,
                           lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]), lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]),
@@ -304,6 +326,24 @@ __device__ __forceinline__ void ered_cell(T* __restrict__ F, const Grid2D& g, co
         e_values_kz<T, MODE>(ex, ey, ez, hx, hy, yee::pml_d2(hz - hzd, g, pp, 0, 1, false, i, j),
                        yee::pml_d2(hz - hzl, g, pp, 1, 0, false, i, j), yee::pml_d2(hy - hyl, g, pp, 2, 0, false, i, j),
                        yee::pml_d2(hx - hxd, g, pp, 2, 1, false, i, j), lx, ly, lz, rr.M);
+    } else if (CYL && psi != nullptr && j > 0) {
+        // CPML at the tube ends: the axial differences of e_r (slot 1) and
+        // e_phi (slot 2) are stretched; the rest is e_values' cylindrical form
+        const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
+        const T* rw = rr.rows + kRowFactors * j;
+        const T r = T(j);
+        const T cz = ((r * hz - (r - T(1)) * hzd) + rr.M * hy) * rw[RD];
+        const T cr = -((rr.M * hx) * rw[RC]) - yee::pml_d2(hz - hzl, g, psi, 1, 0, false, i, j);
+        const T cp = yee::pml_d2(hy - hyl, g, psi, 2, 0, false, i, j) - (hx - hxd);
+        if (MODE == 0) {
+            ex = yee::add(lx[0], ex, lx[1], cz);
+            ey = yee::add(ly[0], ey, ly[1], cr);
+            ez = yee::add(lz[0], ez, lz[1], cp);
+        } else {
+            ex = yee::half(lx[1], cz);
+            ey = yee::half(ly[1], cr);
+            ez = yee::half(lz[1], cp);
+        }
     } else {
         e_values<T, MODE, CYL>(ex, ey, ez, Hx[c], Hy[c], Hz[c], hxd, hzd, hyl, hzl, lx, ly, lz, rr.M, j,
                                rr.rows + kRowFactors * j);

@@ -387,7 +387,6 @@ std::string build_problem(const cf_grid& g, const cf_materials& m, const cf_surf
     if (g.coord == CF_COORD_CYLINDRICAL) {
         if (g.ndim != 2) return "cylindrical problems are 2D (r, z) grids";
         if (g.bc[1] != CF_BC_PEC) return "cylindrical problems need a PEC tube wall (bc[1])";
-        if (g.bc[0] == CF_BC_PML) return "PML is not implemented for cylindrical problems";
         if (s.m_max < 0 || s.m_max > 32) return "m_max must be in 0..32";
     }
     if (m.n_materials < 1 || m.n_materials > 254 || !m.eps || !m.mu) return "bad material table";
@@ -690,13 +689,7 @@ std::string validate_opts(const Problem& p, const cf_opts& o, cf_status* code) {
         *code = CF_E_UNSUPPORTED;
         return "dispersive materials are implemented for Cartesian 2D and k_z problems";
     }
-    if (p.grid.ndim == 2) {
-        for (int a = 0; a < 2; ++a)
-            if (p.grid.bc[a] == CF_BC_PML && p.cyl) {
-                *code = CF_E_UNSUPPORTED;
-                return "PML is not implemented for cylindrical problems";
-            }
-    } else {
+    if (p.grid.ndim == 3) {
         if (p.grid.bc[0] == CF_BC_PML || p.grid.bc[1] == CF_BC_PML) {
             *code = CF_E_UNSUPPORTED;
             return "3D PML is implemented along z only";

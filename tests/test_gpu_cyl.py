@@ -10,7 +10,10 @@ Cases (each printed before it runs):
   smaller time steps);
 * ``ring``: a PEC ring off the axis with periodic ends, S with an inner and
   an outer radial face, orders 0..2;
-* ``pmc``: the piston with a PMC-lined tube at resolution 20, orders 0..3.
+* ``pmc``: the piston with a PMC-lined tube at resolution 20, orders 0..3;
+* ``pml_ends``: the piston in a tube that ends in 10-cell CPML layers (Sec.
+  III C), orders 0..2 (order 2 with its own layer profile for its smaller
+  time step), on the split kernels, which carry the layers.
 
 Tolerances: FP64 fields follow the oracle up to rounding order (the
 coefficients and the 1/r factors are formed differently): 1e-9 of the
@@ -66,6 +69,8 @@ CASES = {
     "ring": ring_periodic,
     "pmc": lambda: cyl_piston(res=20, h_u=0.5, length_u=6.0, n_harm=5, m_max=3, sidewall="pmc", n_steps=300,
                               precision="fp64"),
+    "pml_ends": lambda: cyl_piston(res=10, h_u=0.8, length_u=8.0, n_harm=3, m_max=2, n_steps=400,
+                                   precision="fp64").replace(bc=("pml", "pec", "periodic"), pml_cells=(10, 0, 0)),
 }
 _ORACLE = {}
 
@@ -111,7 +116,7 @@ def test_fp64_matches_oracle(cf, name):
     print(f"[cyl] {name}: max channel error {rel:.2e} of the largest, F = {res['force']:.6e}", flush=True)
 
 
-@pytest.mark.parametrize("name", ["closed", "wall", "ring"])
+@pytest.mark.parametrize("name", ["closed", "wall", "ring", "pml_ends"])
 def test_fp32_matches_oracle(cf, name):
     announce(f"cylindrical fp32 vs oracle: {name}")
     wl, ref = oracle_result(name)
