@@ -525,9 +525,11 @@ static long live_waves(const cf::Problem& p, TBPlan& t, const cf::TBShape& sh, c
         const int ry0 = t.base_y + (tile / t.ntx) * sh.ty - sh.kh;
         for (int w = 0; w < W; ++w) zero[w] = el.count(rx0, rx0 + RW, ry0 + w * sh.b, ry0 + (w + 1) * sh.b) == 0;
         bool any = false;
+        uint32_t mask = 0;
         for (int w = 0; w < W; ++w) {
             if (zero[w] && (w + 1 == W || zero[w + 1])) continue;   // advances nothing
             any = true;
+            mask |= 1u << w;
             ++n;
             if (!fill) continue;
             // tile-interior cells of the wave inside the grid
@@ -537,7 +539,7 @@ static long live_waves(const cf::Problem& p, TBPlan& t, const cf::TBShape& sh, c
             if (y1 > y0 && x1 > x0) t.live_cells[k] += (double)(y1 - y0) * (x1 - x0);
         }
         if (!any && tile == t.stile) ++n;
-        if (fill && (any || tile == t.stile)) t.live[k].push_back(tile);
+        if (fill && (any || tile == t.stile)) t.live[k].push_back({tile, mask});
     }
     return n;
 }
@@ -623,22 +625,24 @@ TBPlan plan_tiles(const cf::Problem& p, const std::vector<cf::Channel>& chans, c
 // tiles.  Each channel is assigned whole to the XCD queue with the fewest
 // tiles so far; block b = 8 i + x takes item i of queue x, so every tile of
 // a channel runs on XCD x (blocks are dispatched to XCDs round-robin).
-std::vector<cf::WorkItem> make_work(const std::vector<int>& slots, const std::vector<const std::vector<int>*>& tiles,
+std::vector<cf::WorkItem> make_work(const std::vector<int>& slots, const std::vector<const std::vector<LiveTile>*>& tiles,
                                     const std::vector<int>& stile) {
     std::vector<std::vector<cf::WorkItem>> q(8);
     std::vector<long> load(8, 0);
     for (size_t k = 0; k < slots.size(); ++k) {
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        const std::vector<int>& tl = *tiles[k];
-        const bool has_s = std::find(tl.begin(), tl.end(), stile[k]) != tl.end();
-        if (has_s) q[x].push_back({slots[k], stile[k]});
-        for (int t : tl)
-            if (!has_s || t != stile[k]) q[x].push_back({slots[k], t});
+        const std::vector<LiveTile>& tl = *tiles[k];
+        const LiveTile* s = nullptr;
+        for (const LiveTile& t : tl)
+            if (t.tile == stile[k]) s = &t;
+        if (s) q[x].push_back({slots[k], s->tile, s->waves});
+        for (const LiveTile& t : tl)
+            if (t.tile != stile[k]) q[x].push_back({slots[k], t.tile, t.waves});
         load[x] += (long)tl.size();
     }
     size_t len = 0;
     for (auto& v : q) len = std::max(len, v.size());
-    std::vector<cf::WorkItem> out(8 * len, cf::WorkItem{-1, 0});
+    std::vector<cf::WorkItem> out(8 * len, cf::WorkItem{-1, 0, 0u});
     for (int x = 0; x < 8; ++x)
         for (size_t i = 0; i < q[x].size(); ++i) out[8 * i + x] = q[x][i];
     return out;
@@ -1300,7 +1304,7 @@ cf_status run_solve(const cf::Problem& p, const cf_opts& o, const Staged& st, co
     auto upload_work = [&](const int* list, int n, const TBPlan& pl, int pol, size_t slot_off,
                            size_t region_end, int* nwork) -> hipError_t {
         std::vector<int> sl(list, list + n), st(n, pl.stile);
-        std::vector<const std::vector<int>*> tl(n, &live_tiles(pl, pol));
+        std::vector<const std::vector<LiveTile>*> tl(n, &live_tiles(pl, pol));
         host_work.push_back(make_work(sl, tl, st));
         *nwork = (int)host_work.back().size();
         if (slot_off + (size_t)*nwork > region_end) return hipErrorInvalidValue;
@@ -1972,7 +1976,7 @@ cf_status run_batch(const BatchPlan& B, const BatchLayout& L, const cf_opts& o, 
         return I;
     };
     auto work_for = [&](int v, const std::vector<int>& slots) {
-        std::vector<const std::vector<int>*> tl;
+        std::vector<const std::vector<LiveTile>*> tl;
         std::vector<int> st;
         for (int sl : slots) {
             const int i = B.dev[sl].inst;

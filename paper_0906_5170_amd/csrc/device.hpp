@@ -100,9 +100,10 @@ struct InstDev {
 };
 
 // Work item of a fused launch: channel descriptor `slot`, tile `tile` of its
-// instance.  slot < 0 is padding.
+// instance, and the tile's live waves.  slot < 0 is padding.
 struct WorkItem {
     int slot, tile;
+    uint32_t waves;   // bit w: wave w of the tile has a cell that can change (the host's plan)
 };
 
 // Tile interior (tx x ty cells), halo / maximum steps per launch and rows

@@ -259,6 +259,15 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
 
     const WorkItem wi = work[blockIdx.x];
     if (wi.slot < 0) return;
+    // A wave whose band, and the band of the wave above, hold no E component
+    // with a nonzero coefficient advances nothing: E is held at 0 there and H,
+    // whose curl reads only those rows, keeps its value, which is 0 from the
+    // start (every field there starts at 0 and the cells are never written).
+    // Such a wave skips its loads, arithmetic and write-back; it still takes
+    // part in the barriers and writes its (zero) exchange rows.  Above the top
+    // wave lie only stale rim rows, so its own band decides.  The host's plan
+    // applies this test to the material ids (live_waves) and hands the tile's
+    // live waves over in the work item.
     const int slot = wi.slot, tile = wi.tile;
     const ChanDev d = ch[slot];
     const InstDev g = insts[d.inst];
@@ -276,6 +285,7 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
     // the wave index is uniform across a wave: taken as a scalar, every row
     // index and row bound below is scalar arithmetic
     const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool live = ((wi.waves >> w) & 1u) != 0;
 
     for (int i = tid; i < 3 * 256; i += NTB) {
         const int s = i >> 8, id = i & 255;
@@ -315,7 +325,7 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
     for (int j = 0; j < CX; ++j)
 #pragma unroll
         for (int r = 0; r < B; ++r) {
-            const int gi = cell_of(j, r);
+            const int gi = live ? cell_of(j, r) : -1;   // a skipped wave reads no coefficient
             const uint32_t i0 = gi >= 0 ? g.ids[C0][gi] : kNullId;
             const uint32_t i1 = gi >= 0 ? g.ids[C1][gi] : kNullId;
             const uint32_t i2 = gi >= 0 ? g.ids[C2][gi] : kNullId;
@@ -323,42 +333,6 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
             m1p[j][r >> 2] |= i1 << (8 * (r & 3));
             m2p[j][r >> 2] |= i2 << (8 * (r & 3));
         }
-    const bool stile = tile == g.stile;
-    double acc_s = 0.0, acc_c = 0.0;
-    if (stile && tid == 0) {
-        acc_s = acc[0];
-        acc_c = acc[1];
-    }
-    __syncthreads();
-
-#define CF_ID(p, j, r) ((p[j][(r) >> 2] >> (8 * ((r) & 3))) & 255u)
-    // A wave whose band, and the band of the wave above, hold no E component
-    // with a nonzero coefficient advances nothing: E is held at 0 there and H,
-    // whose curl reads only those rows, keeps its value, which is 0 from the
-    // start (every field there starts at 0 and the cells are never written).
-    // Such a wave skips its loads, arithmetic and write-back; it still takes
-    // part in the barriers and writes its (zero) exchange rows.  Above the top
-    // wave lie only stale rim rows, so its own band decides.
-    __shared__ int band_e[RBW];
-    {
-        bool e_any = false;
-#pragma unroll
-        for (int j = 0; j < CX; ++j)
-#pragma unroll
-            for (int r = 0; r < B; ++r) {
-                const Pair<T> c0 = L[0][CF_ID(m0p, j, r)];
-                e_any = e_any || c0.a != T(0) || c0.b != T(0);
-                if (POL == CF_POL_TE) {
-                    const Pair<T> c1 = L[1][CF_ID(m1p, j, r)];
-                    e_any = e_any || c1.a != T(0) || c1.b != T(0);
-                }
-            }
-        const int wave_any = __any(e_any) ? 1 : 0;
-        if (lane == 0) band_e[w] = wave_any;
-    }
-    __syncthreads();
-    const bool live = __builtin_amdgcn_readfirstlane((band_e[w] || (w + 1 < RBW && band_e[w + 1])) ? 1 : 0) != 0;
-
     T f0[CX][B], f1[CX][B], f2[CX][B];
     {
         const T* S0 = src + d.field_off;
@@ -374,6 +348,15 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
                 f2[j][r] = gi >= 0 ? S2[gi] : T(0);
             }
     }
+    const bool stile = tile == g.stile;
+    double acc_s = 0.0, acc_c = 0.0;
+    if (stile && tid == 0) {
+        acc_s = acc[0];
+        acc_c = acc[1];
+    }
+    __syncthreads();
+
+#define CF_ID(p, j, r) ((p[j][(r) >> 2] >> (8 * ((r) & 3))) & 255u)
     // CREG: each cell's (a, b) pairs are constant over the launch and can be
     // held in registers instead of being looked up in LDS every step.
     constexpr int KJ = CREG ? CX : 1, KB = CREG ? B : 1;

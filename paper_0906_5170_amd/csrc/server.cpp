@@ -442,7 +442,7 @@ hipError_t rebuild_group(cf_server* S) {
     std::vector<cf::InstDev> inst;
     struct SlotTiles {
         std::vector<int> first;                          // slots
-        std::vector<const std::vector<int>*> second;     // live tiles per slot
+        std::vector<const std::vector<cfi::LiveTile>*> second;   // live tiles per slot
         std::vector<int> third;                          // surface tile per slot
     };
     std::map<std::pair<int, int>, SlotTiles> lists;   // (v, pol) -> slots, tiles, surface tiles

@@ -45,13 +45,19 @@ cf_status guarded(F&& body) noexcept {
 // hold only E components with a = b = 0 (perfect conductor, wall, outside
 // the grid) advances nothing: E stays 0 there, so does H (its curl reads only
 // those rows), and the kernel skips it.  live[k] lists the tiles of
-// polarization k (0 TM, 1 TE) with at least one other wave; the rest are not
-// launched.  live_cells[k] counts the tile-interior cells of those waves
-// inside the grid (cells the kernel advances per channel and step).
+// polarization k (0 TM, 1 TE) with at least one other wave, each with the
+// bit mask of its live waves (the kernel reads it from its work item); the
+// rest are not launched.  live_cells[k] counts the tile-interior cells of
+// those waves inside the grid (cells the kernel advances per channel and
+// step).
+struct LiveTile {
+    int tile;
+    uint32_t waves;   // bit w: wave w of the tile advances
+};
 struct TBPlan {
     bool ok = false;
     int base_x = 0, base_y = 0, ntx = 0, nty = 0, stile = -1;
-    std::vector<int> live[2];
+    std::vector<LiveTile> live[2];
     double live_cells[2] = {0, 0};
 };
 
@@ -130,10 +136,10 @@ void stage(const cf::Problem& p, const cf_opts& o, const std::vector<cf::Channel
 // it should not be left for the tail of the launch).
 // tiles[k] lists the tiles slot k runs (its plan's live tiles of the slot's
 // polarization).
-std::vector<cf::WorkItem> make_work(const std::vector<int>& slots, const std::vector<const std::vector<int>*>& tiles,
+std::vector<cf::WorkItem> make_work(const std::vector<int>& slots, const std::vector<const std::vector<LiveTile>*>& tiles,
                                     const std::vector<int>& stile);
 // the live tile list of polarization pol (CF_POL_TM / CF_POL_TE) in plan pl
-inline const std::vector<int>& live_tiles(const TBPlan& pl, int pol) { return pl.live[pol == CF_POL_TE ? 1 : 0]; }
+inline const std::vector<LiveTile>& live_tiles(const TBPlan& pl, int pol) { return pl.live[pol == CF_POL_TE ? 1 : 0]; }
 // Host reduction of accumulators into a cf_result; false if not finite.
 bool fill_result(const cf::Problem& p, const std::vector<cf::Channel>& chans, const std::vector<double>& acc,
                  const std::vector<double>& gam, const cf_opts& o, double ms, const StencilTiming& tim,
