@@ -42,6 +42,7 @@ using yee::neumaier;
 using yee::block_surface_sum;
 using yee::lorentz_step;
 using yee::pml_d2;
+using yee::as_global;
 
 // ---------------------------------------------------------------------------
 // split half-step kernels (one launch per half step for a batch of channels)
@@ -275,10 +276,10 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
     const int m0 = mclock - g.start;                      // instance's own step
     const int ksteps = min(kmax, g.nsteps - m0);
     if (m0 < 0 || ksteps <= 0) return;                    // not started / finished
-    const T* __restrict__ lut = static_cast<const T*>(g.lut);
-    const T* __restrict__ src = static_cast<const T*>(parity ? g.fb : g.fa);
-    T* __restrict__ dst = static_cast<T*>(parity ? g.fa : g.fb);
-    double* __restrict__ acc = g.acc + 2 * d.local;
+    const auto lut = as_global(static_cast<const T*>(g.lut));
+    const auto src = as_global(static_cast<const T*>(parity ? g.fb : g.fa));
+    const auto dst = as_global(static_cast<T*>(parity ? g.fa : g.fb));
+    const auto acc = as_global(g.acc + 2 * d.local);
     const int tx = tile % g.ntx, ty = tile / g.ntx;
     const int rx0 = g.base_x + tx * TX - KH, ry0 = g.base_y + ty * TY - KH;
     const int tid = threadIdx.x;
@@ -286,14 +287,6 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
     // index and row bound below is scalar arithmetic
     const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const bool live = ((wi.waves >> w) & 1u) != 0;
-
-    for (int i = tid; i < 3 * 256; i += NTB) {
-        const int s = i >> 8, id = i & 255;
-        const int comp = s == 0 ? C0 : (s == 1 ? C1 : C2);
-        const T* p = lut_ab(lut, d.kind, comp, id);
-        L[s][id].a = p[0];
-        L[s][id].b = p[1];
-    }
 
     // Column of the lane's cell j and row r of the wave's band in the grid
     // (wrapped on a periodic axis), or -1 beyond a non-periodic edge: the x
@@ -313,40 +306,79 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
         if (gy < 0 || gy >= g.ny) gy = g.pery ? ((gy % g.ny) + g.ny) % g.ny : -1;
         row[r] = __builtin_amdgcn_readfirstlane(gy);
     }
-    auto cell_of = [&](int j, int r) -> int {
-        return col[j] < 0 || row[r] < 0 ? -1 : row[r] * g.nx + col[j];
-    };
+    // The channel kind's coefficient pairs of the three components, staged in
+    // LDS once the cell loads below are issued too.  Every load of the
+    // prologue is unconditional (a clamped index where a thread has no
+    // entry), so that all of them are in flight at once.
+    constexpr int NL = (3 * 256 + NTB - 1) / NTB;
+    Pair<T> lv[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = min(tid + k * NTB, 3 * 256 - 1);
+        const int s = i >> 8, id = i & 255;
+        const int comp = s == 0 ? C0 : (s == 1 ? C1 : C2);
+        const auto p = lut + (((d.kind * 6 + comp) << 8) + id) * 2;   // (a, b) of (kind, comp, id)
+        lv[k].a = p[0];
+        lv[k].b = p[1];
+    }
+
+    // A cell is read when its wave is live and its row and column lie in the
+    // grid.  The loads of a live wave are unconditional, from the clamped
+    // cell (0 for an index beyond the grid), and the null id or zero field
+    // is selected after them, so that all of them are in flight at once (a
+    // load under a lane mask whose byte is then shifted makes the compiler
+    // wait for it inside the mask, one load after another).  The row offset
+    // row[r] nx is uniform: each load takes a scalar row base and the lane's
+    // column as its offset.  A skipped wave reads nothing.
     uint32_t m0p[CX][NP], m1p[CX][NP], m2p[CX][NP];
-#pragma unroll
-    for (int j = 0; j < CX; ++j)
-#pragma unroll
-        for (int r = 0; r < NP; ++r) m0p[j][r] = m1p[j][r] = m2p[j][r] = 0;
-#pragma unroll
-    for (int j = 0; j < CX; ++j)
-#pragma unroll
-        for (int r = 0; r < B; ++r) {
-            const int gi = live ? cell_of(j, r) : -1;   // a skipped wave reads no coefficient
-            const uint32_t i0 = gi >= 0 ? g.ids[C0][gi] : kNullId;
-            const uint32_t i1 = gi >= 0 ? g.ids[C1][gi] : kNullId;
-            const uint32_t i2 = gi >= 0 ? g.ids[C2][gi] : kNullId;
-            m0p[j][r >> 2] |= i0 << (8 * (r & 3));
-            m1p[j][r >> 2] |= i1 << (8 * (r & 3));
-            m2p[j][r >> 2] |= i2 << (8 * (r & 3));
-        }
     T f0[CX][B], f1[CX][B], f2[CX][B];
     {
-        const T* S0 = src + d.field_off;
-        const T* S1 = S0 + g.ncell;
-        const T* S2 = S1 + g.ncell;
+        constexpr uint32_t kNull4 = kNullId * 0x01010101u;
 #pragma unroll
         for (int j = 0; j < CX; ++j)
 #pragma unroll
+            for (int q = 0; q < NP; ++q) m0p[j][q] = m1p[j][q] = m2p[j][q] = live ? 0u : kNull4;
+        uint32_t b0[CX][B], b1[CX][B], b2[CX][B];
+        if (live) {
+            const auto I0 = as_global(g.ids[C0]), I1 = as_global(g.ids[C1]), I2 = as_global(g.ids[C2]);
+            const auto S0 = src + d.field_off;
+            const auto S1 = S0 + g.ncell;
+            const auto S2 = S1 + g.ncell;
+#pragma unroll
             for (int r = 0; r < B; ++r) {
-                const int gi = live ? cell_of(j, r) : -1;
-                f0[j][r] = gi >= 0 ? S0[gi] : T(0);
-                f1[j][r] = gi >= 0 ? S1[gi] : T(0);
-                f2[j][r] = gi >= 0 ? S2[gi] : T(0);
+                const int64_t ro = (int64_t)max(row[r], 0) * g.nx;
+#pragma unroll
+                for (int j = 0; j < CX; ++j) {
+                    const uint32_t cj = (uint32_t)max(col[j], 0);
+                    b0[j][r] = (I0 + ro)[cj];
+                    b1[j][r] = (I1 + ro)[cj];
+                    b2[j][r] = (I2 + ro)[cj];
+                    f0[j][r] = (S0 + ro)[cj];
+                    f1[j][r] = (S1 + ro)[cj];
+                    f2[j][r] = (S2 + ro)[cj];
+                }
             }
+#pragma unroll
+            for (int r = 0; r < B; ++r)
+#pragma unroll
+                for (int j = 0; j < CX; ++j) {
+                    const bool in = row[r] >= 0 && col[j] >= 0;
+                    m0p[j][r >> 2] |= (in ? b0[j][r] : kNullId) << (8 * (r & 3));
+                    m1p[j][r >> 2] |= (in ? b1[j][r] : kNullId) << (8 * (r & 3));
+                    m2p[j][r >> 2] |= (in ? b2[j][r] : kNullId) << (8 * (r & 3));
+                    if (!in) f0[j][r] = f1[j][r] = f2[j][r] = T(0);
+                }
+        } else {
+#pragma unroll
+            for (int r = 0; r < B; ++r)
+#pragma unroll
+                for (int j = 0; j < CX; ++j) f0[j][r] = f1[j][r] = f2[j][r] = T(0);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = tid + k * NTB;
+        if (i < 3 * 256) L[i >> 8][i & 255] = lv[k];
     }
     const bool stile = tile == g.stile;
     double acc_s = 0.0, acc_c = 0.0;
@@ -463,8 +495,8 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
             if (tid == 0) {
                 const double G = g.dA * s;
                 const int m = m0 + step;
-                neumaier(acc_s, acc_c, (g.dt * g.ktab[m]) * G);
-                if (g.gamma) g.gamma[(int64_t)m * g.gamma_stride + d.local] = G;
+                neumaier(acc_s, acc_c, (g.dt * as_global(g.ktab)[m]) * G);
+                if (g.gamma) as_global(g.gamma)[(int64_t)m * g.gamma_stride + d.local] = G;
             }
             __syncthreads();
         }
@@ -476,23 +508,23 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
         acc[1] = acc_c;
     }
     if (!live) return;   // its cells are 0 in both arrays already
-    T* D0 = dst + d.field_off;
-    T* D1 = D0 + g.ncell;
-    T* D2 = D1 + g.ncell;
+    const auto D0 = dst + d.field_off;
+    const auto D1 = D0 + g.ncell;
+    const auto D2 = D1 + g.ncell;
 #pragma unroll
-    for (int j = 0; j < CX; ++j) {
-        const int cx = lane * CX + j;
-        const int gx = rx0 + cx;
-        if (cx < KH || cx >= KH + TX || gx < 0 || gx >= g.nx) continue;
+    for (int r = 0; r < B; ++r) {
+        const int ry = w * B + r;   // uniform: the row test is a scalar branch
+        const int gy = ry0 + ry;
+        if (ry < KH || ry >= KH + TY || gy < 0 || gy >= g.ny) continue;
+        const int64_t ro = (int64_t)gy * g.nx;
 #pragma unroll
-        for (int r = 0; r < B; ++r) {
-            const int ry = w * B + r;
-            const int gy = ry0 + ry;
-            if (ry < KH || ry >= KH + TY || gy < 0 || gy >= g.ny) continue;
-            const int gi = gy * g.nx + gx;
-            D0[gi] = f0[j][r];
-            D1[gi] = f1[j][r];
-            D2[gi] = f2[j][r];
+        for (int j = 0; j < CX; ++j) {
+            const int cx = lane * CX + j;
+            const int gx = rx0 + cx;
+            if (cx < KH || cx >= KH + TX || gx < 0 || gx >= g.nx) continue;
+            (D0 + ro)[(uint32_t)gx] = f0[j][r];
+            (D1 + ro)[(uint32_t)gx] = f1[j][r];
+            (D2 + ro)[(uint32_t)gx] = f2[j][r];
         }
     }
 }

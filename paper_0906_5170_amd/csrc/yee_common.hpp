@@ -42,6 +42,20 @@ __device__ __forceinline__ const T* lut_ab(const T* lut, int kind, int comp, int
     return lut + (((kind * 6 + comp) << 8) + id) * 2;
 }
 
+// A device pointer that reaches a kernel inside a struct read from memory is
+// a generic pointer to the compiler, which then addresses it with FLAT
+// instructions: those also count on the LDS/scalar counter, so every wait
+// for an LDS exchange waits for them too, and each needs a 64-bit address
+// in vector registers.  Every buffer the library hands its kernels is global
+// device memory; the global view of such a pointer gets global instructions
+// (an SGPR base with a 32-bit lane offset where the base is uniform).
+template <typename T>
+using gmem = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gmem<T> as_global(T* p) {
+    return (gmem<T>)p;
+}
+
 template <typename T>
 struct Pair {
     T a, b;
@@ -150,11 +164,11 @@ __device__ __forceinline__ void wave_surface_partials(const ChanDev& d, const Su
     double s = 0.0;
     const int n = threadIdx.x < kSurfThreads ? d.nsamp : 0;
     for (int i = threadIdx.x; i < n; i += kSurfThreads) {
-        const int32_t* gi = t.gidx + d.g_off + (int64_t)i * d.P;
-        const double* gw = t.gw + d.g_off + (int64_t)i * d.P;
+        const auto gi = as_global(t.gidx) + d.g_off + (int64_t)i * d.P;
+        const auto gw = as_global(t.gw) + d.g_off + (int64_t)i * d.P;
         double v = 0.0;
         for (int p = 0; p < d.P; ++p) v += gw[p] * fetch(gi[p]);
-        s += t.basis[d.basis_off + i] * v;
+        s += as_global(t.basis)[d.basis_off + i] * v;
     }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if ((threadIdx.x & 63) == 0 && threadIdx.x < kSurfThreads) red[threadIdx.x >> 6] = s;
