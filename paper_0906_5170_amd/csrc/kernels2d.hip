@@ -229,6 +229,15 @@ __global__ __launch_bounds__(NT) void k_surface(const T* __restrict__ fields, co
 // for every tile of a channel (halo re-reads hit that XCD's L2).  Instances
 // (problems) of one launch have their own grids, tables and time origin.
 
+// Largest channel surface (samples, stencil points per sample) whose tables
+// the surface tile keeps in LDS over a launch; larger ones are read from the
+// global tables after every step.  A block of a shape whose other LDS arrays
+// are large keeps fewer samples, so that two blocks still fit in a CU's LDS.
+constexpr int kSurfP = 4;
+constexpr int surf_cap(int other_lds_bytes) {
+    return other_lds_bytes + 512 * (kSurfP * (2 + 8) + 8) <= 80 * 1024 ? 512 : 128;
+}
+
 // Register-blocked fused kernel.  A block holds a (64 CX) x (RBW B) region
 // of one channel: lane l of wave w owns columns CX l .. CX l + CX - 1 and rows
 // w B .. w B + B - 1, with every field value in registers.  x neighbours come
@@ -257,6 +266,13 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
     __shared__ T xh[RBW][CX][64];
     __shared__ T stage[RH * RW];     // measured component (surface tile only), [row][col j][lane]
     __shared__ double red[RBW];
+    // launch-resident surface tables of the surface tile (see `staged`)
+    constexpr int kSurfCap =
+        surf_cap((int)(sizeof(L) + sizeof(xe) + sizeof(xh) + sizeof(stage) + sizeof(red)) + 8 * KH);
+    __shared__ uint16_t s_off[kSurfCap * kSurfP];
+    __shared__ double s_w[kSurfCap * kSurfP];
+    __shared__ double s_b[kSurfCap];
+    __shared__ double s_k[KH];
 
     const WorkItem wi = work[blockIdx.x];
     if (wi.slot < 0) return;
@@ -381,6 +397,26 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
         if (i < 3 * 256) L[i >> 8][i & 255] = lv[k];
     }
     const bool stile = tile == g.stile;
+    // The surface tile keeps its channel's surface tables in LDS for the
+    // launch when they fit: the stage offset of every stencil point (its
+    // grid index converted once), the weights, the basis row and K(t_m) of
+    // the launch's steps.  The sum after each step then reads no global
+    // memory, in the same order as the table path.
+    const bool staged = stile && d.nsamp <= kSurfCap && d.P <= kSurfP;
+    if (staged) {
+        const int ne = d.nsamp * d.P;
+        const auto gi = as_global(t.gidx) + d.g_off;
+        const auto gw = as_global(t.gw) + d.g_off;
+        for (int e = tid; e < ne; e += NTB) {
+            const int32_t idx = gi[e];
+            const int gx = idx % g.nx, gy = idx / g.nx;
+            const int cx = gx - rx0;
+            s_off[e] = (uint16_t)((gy - ry0) * RW + (cx % CX) * 64 + cx / CX);
+            s_w[e] = gw[e];
+        }
+        for (int i = tid; i < d.nsamp; i += NTB) s_b[i] = as_global(t.basis)[d.basis_off + i];
+        if (tid < ksteps) s_k[tid] = as_global(g.ktab)[m0 + tid];
+    }
     double acc_s = 0.0, acc_c = 0.0;
     if (stile && tid == 0) {
         acc_s = acc[0];
@@ -484,18 +520,27 @@ void k_rb2d(const ChanDev* __restrict__ ch, const WorkItem* __restrict__ work,
                 for (int j = 0; j < CX; ++j)
                     stage[(w * B + r) * RW + j * 64 + lane] = ms == 0 ? f0[j][r] : (ms == 1 ? f1[j][r] : f2[j][r]);
             __syncthreads();
-            const double s = block_surface_sum(
-                d, t,
-                [&](int32_t idx) {
-                    const int gx = idx % g.nx, gy = idx / g.nx;
-                    const int cx = gx - rx0;
-                    return (double)stage[(gy - ry0) * RW + (cx % CX) * 64 + cx / CX];
-                },
-                red);
+            double s;
+            if (staged) {
+                yee::wave_surface_partials_staged(
+                    d.nsamp, d.P, s_off, s_w, s_b, [&](uint16_t o) { return (double)stage[o]; }, red);
+                __syncthreads();
+                s = tid == 0 ? yee::wave_partials_total(red) : 0.0;
+            } else {
+                s = block_surface_sum(
+                    d, t,
+                    [&](int32_t idx) {
+                        const int gx = idx % g.nx, gy = idx / g.nx;
+                        const int cx = gx - rx0;
+                        return (double)stage[(gy - ry0) * RW + (cx % CX) * 64 + cx / CX];
+                    },
+                    red);
+            }
             if (tid == 0) {
                 const double G = g.dA * s;
                 const int m = m0 + step;
-                neumaier(acc_s, acc_c, (g.dt * as_global(g.ktab)[m]) * G);
+                const double kt = staged ? s_k[step] : as_global(g.ktab)[m];
+                neumaier(acc_s, acc_c, (g.dt * kt) * G);
                 if (g.gamma) as_global(g.gamma)[(int64_t)m * g.gamma_stride + d.local] = G;
             }
             __syncthreads();

@@ -150,6 +150,13 @@ __device__ __forceinline__ void neumaier(double& sum, double& comp, double term)
     sum = nt;
 }
 
+// Fixed-order sum of s over a wave; lane 0 of each of the first
+// kSurfThreads / 64 waves stores its wave's sum in red[wave].
+__device__ __forceinline__ void wave_partial_store(double s, double* red) {
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0 && threadIdx.x < kSurfThreads) red[threadIdx.x >> 6] = s;
+}
+
 // Gamma sum of one channel by the first kSurfThreads threads of a block:
 // thread t takes samples t, t + kSurfThreads, ...; sum_p w X in FP64 per
 // sample, weighted by the basis row; then a fixed-order reduction over the
@@ -170,8 +177,25 @@ __device__ __forceinline__ void wave_surface_partials(const ChanDev& d, const Su
         for (int p = 0; p < d.P; ++p) v += gw[p] * fetch(gi[p]);
         s += as_global(t.basis)[d.basis_off + i] * v;
     }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0 && threadIdx.x < kSurfThreads) red[threadIdx.x >> 6] = s;
+    wave_partial_store(s, red);
+}
+
+// The same partial sums from a launch-resident copy of the channel's tables:
+// off[i P + p] is where fetch finds point p of sample i, w the weights in
+// the table's order and b the basis row, so the result is bitwise that of
+// wave_surface_partials.
+template <typename Fetch>
+__device__ __forceinline__ void wave_surface_partials_staged(int nsamp, int P, const uint16_t* off,
+                                                             const double* w, const double* b, Fetch fetch,
+                                                             double* red) {
+    double s = 0.0;
+    const int n = threadIdx.x < kSurfThreads ? nsamp : 0;
+    for (int i = threadIdx.x; i < n; i += kSurfThreads) {
+        double v = 0.0;
+        for (int p = 0; p < P; ++p) v += w[i * P + p] * fetch(off[i * P + p]);
+        s += b[i] * v;
+    }
+    wave_partial_store(s, red);
 }
 
 // The fixed-order total of the wave partials (after a barrier that follows
