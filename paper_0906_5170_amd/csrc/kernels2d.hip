@@ -233,6 +233,8 @@ __global__ __launch_bounds__(NT) void k_surface(const T* __restrict__ fields, co
 // the surface tile keeps in LDS over a launch; larger ones are read from the
 // global tables after every step.  A block of a shape whose other LDS arrays
 // are large keeps fewer samples, so that two blocks still fit in a CU's LDS.
+// With the present shapes every fused surface fits: it lies inside one tile,
+// so a face has at most 120 samples, with 2 x 2 points each.
 constexpr int kSurfP = 4;
 constexpr int surf_cap(int other_lds_bytes) {
     return other_lds_bytes + 512 * (kSurfP * (2 + 8) + 8) <= 80 * 1024 ? 512 : 128;
