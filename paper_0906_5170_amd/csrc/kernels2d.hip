@@ -672,9 +672,10 @@ hipError_t launch_surface(const T* fields, const ChanDev* ch, const int* slots, 
 
 // waves per SIMD the register budget is sized for: the field state per lane
 // is 3 B CX values of sizeof(T) bytes (plus as many coefficient pairs with
-// creg)
+// creg).  An FP32 shape that reads its coefficients from LDS fits 6 waves
+// (76 VGPRs, no spills), three 8-wave blocks per CU.
 constexpr int rb_wpe(int B, bool creg, int CX, int tsize) {
-    return B * CX * (tsize / 4) >= 16 ? 2 : (creg ? 3 : 4);
+    return B * CX * (tsize / 4) >= 16 ? 2 : (creg ? 3 : (tsize == 4 ? 6 : 4));
 }
 
 template <typename T, int W, int B, int KH, bool CREG, int CX>
