@@ -149,6 +149,54 @@ __device__ __forceinline__ void e_values(T& ex, T& ey, T& ez, T hx, T hy, T hz, 
     }
 }
 
+// The CPML-stretched difference of yee::pml_d2 in two phases, for a cell
+// that stretches several differences: pml_fetch issues the loads of one
+// difference's (b, c) and psi (none outside the layers), pml_apply forms
+// psi <- b psi + c D, stores it and returns D + psi, the same arithmetic.
+// Fetching every difference of a cell before applying any keeps all their
+// loads in flight together; a psi store between them would hold the next
+// difference's loads back (the compiler cannot tell that the psi entries
+// are distinct, which they are: each difference has its own slot and axis).
+template <typename T>
+struct PmlTerm {
+    T* at;   // nullptr: outside the layers
+    double b, c;
+    T psi;
+};
+// The loads are unconditional for every lane, with or without layers on the
+// axis (a lane outside the layers reads the first table entry and the first
+// psi entry of the channel's block and discards them), so that no load sits
+// under a branch: the compiler would wait for it before the branches merge.
+// psi must be the channel's CPML block (not null).  Every read stays inside
+// the CPML profile region, which holds 4 (nx + ny) values per order for both
+// axes whatever their layers (the host's layout).
+template <typename T>
+__device__ __forceinline__ PmlTerm<T> pml_fetch(const Grid2D& g, T* psi, int slot, int axis, bool half, int i,
+                                                int j) {
+    PmlTerm<T> t;
+    const int P = g.pml[axis];
+    const int n = axis == 0 ? g.nx : g.ny;
+    const int q = axis == 0 ? i : j;
+    const bool in = P > 0 && (q < P || q >= n - P);
+    const int qc = in ? q : 0;
+    const int qq = in ? (q < P ? q : q - (n - 2 * P)) : 0;
+    T* arr = psi + slot * g.psi_slot + (axis == 0 ? 0 : (int64_t)g.ny * 2 * g.pml[0]);
+    const double* tab = g.pml_tab[axis] + (half ? 0 : 2 * n);
+    T* at = in ? arr + (axis == 0 ? (int64_t)j * (2 * P) + qq : (int64_t)qq * g.nx + i) : psi;
+    t.b = tab[qc];
+    t.c = tab[n + qc];
+    t.psi = *at;
+    t.at = in ? at : nullptr;
+    return t;
+}
+template <typename T>
+__device__ __forceinline__ T pml_apply(const PmlTerm<T>& t, T D) {
+    if (t.at == nullptr) return D;
+    const T p = fma(T(t.b), t.psi, T(t.c) * D);
+    *t.at = p;
+    return D + p;
+}
+
 // The k_z forms (no cylindrical weights) with the in-plane differences
 // passed in, as the CPML stretches them (split kernels only): the same
 // operations as h_values / e_values with CYL = false (MODE 0 the step,
@@ -244,10 +292,14 @@ __device__ __forceinline__ void hred_cell(T* __restrict__ F, const Grid2D& g, co
         // CPML: slots Hx 3, Hy 4, Hz 5; H components at half-cell positions
         T* pp = psi + (CPLX ? part * 6 * g.psi_slot : 0);
         const T ex = Ex[c], ey = Ey[c], ez = Ez[c];
-        h_values_kz<T, MODE>(hx, hy, hz, ex, ey, yee::pml_d2(ezu - ez, g, pp, 3, 1, true, i, j),
-                       yee::pml_d2(ezr - ez, g, pp, 4, 0, true, i, j), yee::pml_d2(eyr - ey, g, pp, 5, 0, true, i, j),
-                       yee::pml_d2(exu - ex, g, pp, 5, 1, true, i, j), lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]),
-                       lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]), lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]), rr.M);
+        const PmlTerm<T> t0 = pml_fetch(g, pp, 3, 1, true, i, j), t1 = pml_fetch(g, pp, 4, 0, true, i, j);
+        const PmlTerm<T> t2 = pml_fetch(g, pp, 5, 0, true, i, j), t3 = pml_fetch(g, pp, 5, 1, true, i, j);
+        const T* lx = lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]);
+        const T* ly = lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]);
+        const T* lz = lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]);
+        const T d0 = pml_apply(t0, ezu - ez), d1 = pml_apply(t1, ezr - ez);
+        const T d2 = pml_apply(t2, eyr - ey), d3 = pml_apply(t3, exu - ex);
+        h_values_kz<T, MODE>(hx, hy, hz, ex, ey, d0, d1, d2, d3, lx, ly, lz, rr.M);
     } else if (CYL && psi != nullptr && j > 0) {
         // CPML at the tube ends (along the axis, the grid's x): the axial
         // differences of h_r (slot 4) and h_phi (slot 5) are stretched; the
@@ -256,11 +308,12 @@ __device__ __forceinline__ void hred_cell(T* __restrict__ F, const Grid2D& g, co
         const T* rw = rr.rows + kRowFactors * j;
         const T r = T(j);
         const T cz = (((r + T(0.5)) * ezu - (r - T(0.5)) * ez) - rr.M * ey) * rw[RC];
-        const T cr = (rr.M * ex) * rw[RD] - yee::pml_d2(ezr - ez, g, psi, 4, 0, true, i, j);
-        const T cp = yee::pml_d2(eyr - ey, g, psi, 5, 0, true, i, j) - (exu - ex);
+        const PmlTerm<T> t1 = pml_fetch(g, psi, 4, 0, true, i, j), t2 = pml_fetch(g, psi, 5, 0, true, i, j);
         const T* lx = lut_ab(lut, kind, CF_HX, g.ids[CF_HX][c]);
         const T* ly = lut_ab(lut, kind, CF_HY, g.ids[CF_HY][c]);
         const T* lz = lut_ab(lut, kind, CF_HZ, g.ids[CF_HZ][c]);
+        const T cr = (rr.M * ex) * rw[RD] - pml_apply(t1, ezr - ez);
+        const T cp = pml_apply(t2, eyr - ey) - (exu - ex);
         if (MODE == 0) {
             hx = yee::sub(lx[0], hx, lx[1], cz);
             hy = yee::sub(ly[0], hy, ly[1], cr);
@@ -316,16 +369,21 @@ __device__ __forceinline__ void ered_cell(T* __restrict__ F, const Grid2D& g, co
         hzl = Hz[c - 1 + g.nx];
     }
     T ex = Ex[c], ey = Ey[c], ez = Ez[c];
-    const T* lx = lut_ab(lut, kind, CF_EX, g.ids[CF_EX][c]);
-    const T* ly = lut_ab(lut, kind, CF_EY, g.ids[CF_EY][c]);
-    const T* lz = lut_ab(lut, kind, CF_EZ, g.ids[CF_EZ][c]);
+    // the material ids are read once: a byte load after a field store would
+    // have to be repeated (bytes may alias anything)
+    const int id_x = g.ids[CF_EX][c], id_y = g.ids[CF_EY][c], id_z = g.ids[CF_EZ][c];
+    const T* lx = lut_ab(lut, kind, CF_EX, id_x);
+    const T* ly = lut_ab(lut, kind, CF_EY, id_y);
+    const T* lz = lut_ab(lut, kind, CF_EZ, id_z);
     if (!CYL && psi != nullptr) {
         // CPML: slots Ex 0, Ey 1, Ez 2; E components at integer positions
         T* pp = psi + (CPLX ? part * 6 * g.psi_slot : 0);
         const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
-        e_values_kz<T, MODE>(ex, ey, ez, hx, hy, yee::pml_d2(hz - hzd, g, pp, 0, 1, false, i, j),
-                       yee::pml_d2(hz - hzl, g, pp, 1, 0, false, i, j), yee::pml_d2(hy - hyl, g, pp, 2, 0, false, i, j),
-                       yee::pml_d2(hx - hxd, g, pp, 2, 1, false, i, j), lx, ly, lz, rr.M);
+        const PmlTerm<T> t0 = pml_fetch(g, pp, 0, 1, false, i, j), t1 = pml_fetch(g, pp, 1, 0, false, i, j);
+        const PmlTerm<T> t2 = pml_fetch(g, pp, 2, 0, false, i, j), t3 = pml_fetch(g, pp, 2, 1, false, i, j);
+        const T d0 = pml_apply(t0, hz - hzd), d1 = pml_apply(t1, hz - hzl);
+        const T d2 = pml_apply(t2, hy - hyl), d3 = pml_apply(t3, hx - hxd);
+        e_values_kz<T, MODE>(ex, ey, ez, hx, hy, d0, d1, d2, d3, lx, ly, lz, rr.M);
     } else if (CYL && psi != nullptr && j > 0) {
         // CPML at the tube ends: the axial differences of e_r (slot 1) and
         // e_phi (slot 2) are stretched; the rest is e_values' cylindrical form
@@ -333,8 +391,9 @@ __device__ __forceinline__ void ered_cell(T* __restrict__ F, const Grid2D& g, co
         const T* rw = rr.rows + kRowFactors * j;
         const T r = T(j);
         const T cz = ((r * hz - (r - T(1)) * hzd) + rr.M * hy) * rw[RD];
-        const T cr = -((rr.M * hx) * rw[RC]) - yee::pml_d2(hz - hzl, g, psi, 1, 0, false, i, j);
-        const T cp = yee::pml_d2(hy - hyl, g, psi, 2, 0, false, i, j) - (hx - hxd);
+        const PmlTerm<T> t1 = pml_fetch(g, psi, 1, 0, false, i, j), t2 = pml_fetch(g, psi, 2, 0, false, i, j);
+        const T cr = -((rr.M * hx) * rw[RC]) - pml_apply(t1, hz - hzl);
+        const T cp = pml_apply(t2, hy - hyl) - (hx - hxd);
         if (MODE == 0) {
             ex = yee::add(lx[0], ex, lx[1], cz);
             ey = yee::add(ly[0], ey, ly[1], cr);
@@ -351,9 +410,9 @@ __device__ __forceinline__ void ered_cell(T* __restrict__ F, const Grid2D& g, co
     if (!CYL && MODE == 0 && aux != nullptr) {
         // Lorentz polarizations of D = eps_inf E + sum P (E slots 0, 1, 2)
         T* ap = aux + (CPLX ? (int64_t)part * 3 * g.n_lor * 2 * g.ncell : 0);
-        ex -= yee::lorentz_step(g, ap, 0, c, g.ids[CF_EX][c], lx[0], Ex[c]);
-        ey -= yee::lorentz_step(g, ap, 1, c, g.ids[CF_EY][c], ly[0], Ey[c]);
-        ez -= yee::lorentz_step(g, ap, 2, c, g.ids[CF_EZ][c], lz[0], Ez[c]);
+        ex -= yee::lorentz_step(g, ap, 0, c, id_x, lx[0], Ex[c]);
+        ey -= yee::lorentz_step(g, ap, 1, c, id_y, ly[0], Ey[c]);
+        ez -= yee::lorentz_step(g, ap, 2, c, id_z, lz[0], Ez[c]);
     }
     Ex[c] = ex;
     Ey[c] = ey;
