@@ -799,6 +799,8 @@ def main():
                     help="only the cylindrical piston section (for profiling); prints its record")
     ap.add_argument("--cyl-quick", action="store_true",
                     help="with --cyl-only: the register-resident FP32 solve only (no split / FP64 / oracle)")
+    ap.add_argument("--open-only", action="store_true",
+                    help="only the open-space waveguide pair (for profiling); prints its record")
     ap.add_argument("--serve-n", type=int, default=24, help="requests in the served piston stream")
     ap.add_argument("--serve-mixed", type=int, default=0,
                     help="only serve this many requests of the mixed 2D/3D stream at their drawn sizes "
@@ -818,7 +820,7 @@ def main():
         args.no_precision = True
         if args.with_3d:
             args.no_3d = False
-    if args.cyl_only or args.serve_mixed:
+    if args.cyl_only or args.serve_mixed or args.open_only:
         args.no_cpu = True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding the channels over "
@@ -861,6 +863,9 @@ def main():
         return
     if args.serve_mixed:
         print(json.dumps(bench_serving_mixed(cf, torch, args)), flush=True)
+        return
+    if args.open_only:
+        print(json.dumps(bench_open_space(cf, torch)), flush=True)
         return
     if args.cyl_only:
         rec = bench_cyl(cf, torch, quick=args.cyl_quick)
